@@ -1,0 +1,481 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Each test checks the oracle against a closed form, an identity of the double
+integral (paper Sec. 2.1), exhaustive search, a quadrature of the definition,
+an invariant of the optimiser steps (paper Sec. 2.2), or an independent
+Philox implementation -- chosen so that a dropped term, a wrong sign, a
+swapped operand or a wrong index in the oracle fails at least one of them.
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2511_01255_amd import inputs
+
+DK1 = inputs.DK1
+DK2 = inputs.DK2
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rel(a, b):
+    return np.max(np.abs(np.asarray(a) - np.asarray(b)) / np.maximum(np.abs(np.asarray(b)), 1e-300))
+
+
+# ---------------------------------------------------------------- Philox
+
+def _kat():
+    rows = []
+    with open(os.path.join(GOLD, "philox4x32_10_kat.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = [int(t, 16) for t in line.split()]
+            rows.append((v[0:4], v[4:6], v[6:10]))
+    return rows
+
+
+def test_philox_known_answers(orc):
+    for ctr, key, want in _kat():
+        assert orc.philox(ctr, key).tolist() == want
+
+
+def _random_queries(n=200, seed=7):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 2**32, size=(n, 6), dtype=np.uint64).astype(np.uint32)
+
+
+def _run_helper(exe, q):
+    txt = "\n".join(" ".join("%08x" % v for v in row) for row in q) + "\n"
+    out = subprocess.run([exe], input=txt, capture_output=True, text=True, check=True).stdout
+    return np.array([[int(t, 16) for t in line.split()] for line in out.strip().splitlines()], dtype=np.uint64)
+
+
+def test_philox_vs_aten_header(orc, tmp_path):
+    import torch
+    inc = os.path.join(os.path.dirname(torch.__file__), "include")
+    exe = str(tmp_path / "px_aten")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-I" + inc,
+                    os.path.join(GOLD, "philox_aten_xcheck.cpp"), "-o", exe], check=True)
+    q = _random_queries()
+    ref = _run_helper(exe, q)
+    mine = np.array([orc.philox(r[:4], r[4:]) for r in q], dtype=np.uint64)
+    assert np.array_equal(ref, mine)
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not available")
+def test_philox_vs_rocrand_header(orc, tmp_path):
+    exe = str(tmp_path / "px_roc")
+    subprocess.run(["hipcc", "-O1", "--offload-arch=gfx950",
+                    os.path.join(GOLD, "philox_rocrand_xcheck.cpp"), "-o", exe], check=True,
+                   capture_output=True)
+    q = _random_queries(seed=11)
+    ref = _run_helper(exe, q)
+    mine = np.array([orc.philox(r[:4], r[4:]) for r in q], dtype=np.uint64)
+    assert np.array_equal(ref, mine)
+
+
+# ---------------------------------------------------------------- quadrature rule
+
+def test_gauss_legendre_exact_for_polynomials(orc):
+    x, w = orc.gl_rule(16)
+    for k in range(32):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs(np.sum(w * x ** k) - exact) < 1e-14
+
+
+# ---------------------------------------------------------------- fitness
+
+@pytest.mark.parametrize("case", ["uniform", "jitter", "offset", "dk1_zero", "dk2_zero", "equal_dk", "neg_dk"])
+def test_prefix_form_matches_nested_quadrature(orc, case):
+    n = 12 if case != "jitter" else 20
+    z = inputs.uniform_boundaries(n, 2.0)
+    k1, k2 = DK1, DK2
+    if case == "jitter":
+        z = inputs.jittered_boundaries(n, 2.0, 0.3, seed=5)
+    elif case == "offset":
+        z = z + 1234.5
+    elif case == "dk1_zero":
+        k1 = 0.0
+    elif case == "dk2_zero":
+        k2 = 0.0
+    elif case == "equal_dk":
+        k2 = k1
+    elif case == "neg_dk":
+        k1, k2 = -0.7, 0.45
+    D = orc.Design(z, k1, k2)
+    d = inputs.random_signs(4, n, seed=3)
+    S, _ = D.fitness(d)
+    Sq = np.array([orc.fitness_quad(z, k1, k2, dd) for dd in d])
+    assert rel(S, Sq) < 1e-13
+
+
+def test_prefix_form_matches_quadrature_n64(orc):
+    n = 64
+    z = inputs.jittered_boundaries(n, 2.0, 0.2, seed=9)
+    D = orc.Design(z, DK1, DK2)
+    d = inputs.random_signs(2, n, seed=4)
+    S, _ = D.fitness(d)
+    Sq = np.array([orc.fitness_quad(z, DK1, DK2, dd) for dd in d])
+    assert rel(S, Sq) < 1e-13
+
+
+def test_prefix_form_matches_pair_sum(orc):
+    n = 300
+    z = inputs.jittered_boundaries(n, 2.0, 0.3, seed=2)
+    D = orc.Design(z, DK1, DK2)
+    d = inputs.random_signs(8, n, seed=6)
+    S, f = D.fitness(d)
+    Sp, fp = D.fitness_pairs(d.astype(np.float64))
+    assert rel(S, Sp) < 1e-14
+    assert rel(f, fp) < 1e-14
+
+
+def _E(k, w):
+    return (1 - np.exp(-1j * k * w)) / (1j * k)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 40, 400])
+def test_periodic_first_order_qpm_closed_form(orc, n):
+    # w = pi / dk1, d_n = (-1)^(n-1): d_n a_n = -2i/dk1 for every n, so
+    # P_{n-1} = -2i (n-1)/dk1; with r = -exp(-i dk2 w) the outer sum is
+    # geometric: S = (-2i E2/dk1) sum_{k<N} k r^k + G (1 - r^N)/(1 - r).
+    w = math.pi / DK1
+    z = np.arange(n + 1) * w
+    D = orc.Design(z, DK1, DK2)
+    d = np.array([(-1) ** k for k in range(n)], dtype=np.int8)
+    S, _ = D.fitness(d[None])
+    r = -np.exp(-1j * DK2 * w)
+    G = (_E(DK2, w) - _E(DK1 + DK2, w)) / (1j * DK1)
+    ksum = r * (1 - n * r ** (n - 1) + (n - 1) * r ** n) / (1 - r) ** 2
+    Sc = (-2j * _E(DK2, w) / DK1) * ksum + G * (1 - r ** n) / (1 - r)
+    # w is pi/dk1 rounded to double: the n-th boundary phase is off by ~n eps,
+    # which moves S by up to ~n^2 eps relative.
+    tol = 1e-14 + 4 * n * n * np.finfo(float).eps
+    assert abs(S[0] - Sc) / abs(Sc) < tol
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 400])
+def test_first_and_third_order_identity(orc, n):
+    # dk2 = 3 dk1, w = pi/dk1, alternating d: S = -2 L^2 / (3 pi^2) exactly.
+    w = math.pi / DK1
+    z = np.arange(n + 1) * w
+    D = orc.Design(z, DK1, 3 * DK1)
+    d = np.array([(-1) ** k for k in range(n)], dtype=np.int8)
+    S, _ = D.fitness(d[None])
+    L = n * w
+    want = -2 * L * L / (3 * math.pi ** 2)
+    tol = 1e-14 + 4 * n * n * np.finfo(float).eps
+    assert abs(S[0] - want) / abs(want) < tol
+
+
+def test_uniform_poling_equals_single_domain(orc):
+    # d = +1 everywhere: the double integral over [z0, zN] does not care how
+    # the crystal is cut into domains.
+    z = inputs.jittered_boundaries(50, 2.0, 0.3, seed=8, z0=5.0)
+    D = orc.Design(z, DK1, DK2)
+    S, _ = D.fitness(np.ones((1, 50), np.int8))
+    L = z[-1] - z[0]
+    want = orc.G(DK1, DK2, L) * np.exp(-1j * (DK1 + DK2) * z[0])
+    assert abs(S[0] - want) / abs(want) < 1e-13
+
+
+def test_single_domain_is_its_diagonal_term(orc):
+    z = np.array([3.0, 5.5])
+    D = orc.Design(z, DK1, DK2)
+    S, _ = D.fitness(np.array([[-1]], np.int8))
+    _, _, c, C = D.phases()
+    assert S[0] == c[0] == C
+
+
+def test_negation_is_bitwise_invariant(orc):
+    n = 1000
+    D = orc.Design(inputs.uniform_boundaries(n), DK1, DK2)
+    d = inputs.random_signs(16, n, seed=12)
+    _, f1 = D.fitness(d)
+    _, f2 = D.fitness(-d)
+    assert np.array_equal(f1, f2)
+
+
+def test_shift_conjugation_and_scaling(orc):
+    n = 200
+    z = inputs.jittered_boundaries(n, 2.0, 0.3, seed=13)
+    d = inputs.random_signs(6, n, seed=14)
+    _, f = orc.Design(z, DK1, DK2).fitness(d)
+    # a shift of the crystal multiplies S by a unit phase
+    _, fs = orc.Design(z + 777.25, DK1, DK2).fitness(d)
+    assert rel(fs, f) < 1e-12
+    # dk -> -dk conjugates S
+    S1, _ = orc.Design(z, DK1, DK2).fitness(d)
+    S2, _ = orc.Design(z, -DK1, -DK2).fitness(d)
+    assert rel(S2, np.conj(S1)) < 1e-13
+    # (z, dk) -> (z / s, s dk) scales S by 1 / s^2 (S has units of length^2)
+    s = 4.0
+    Ss, _ = orc.Design(z / s, s * DK1, s * DK2).fitness(d)
+    assert rel(Ss * s * s, S1) < 1e-13
+
+
+@pytest.mark.parametrize("k1,k2,w", [(0.3, 0.9, 2.0), (2e-3, 0.9, 2.0), (0.5, 0.0, 3.0),
+                                      (0.3, -0.3, 2.0), (5.0, 7.0, 3.0), (-1.1, 2.2, 1.7)])
+def test_diagonal_term_closed_form_vs_quadrature(orc, k1, k2, w):
+    a = orc.G(k1, k2, w)
+    b = orc.G(k1, k2, w, quad=True)
+    assert abs(a - b) / abs(b) < 1e-14
+
+
+def test_diagonal_term_limits(orc):
+    # k1 = k2 = 0: int_0^w t dt = w^2/2; k1 = 0: int_0^w t e^{-i k2 t} dt.
+    w = 2.5
+    assert abs(orc.G(0.0, 0.0, w) - w * w / 2) < 1e-15
+    k2 = 0.8
+    J = (np.exp(-1j * k2 * w) * (1 + 1j * k2 * w) - 1) / (k2 * k2)
+    assert abs(orc.G(0.0, k2, w) - J) / abs(J) < 1e-14
+
+
+@pytest.mark.parametrize("n", [10, 14])
+def test_bruteforce_optimum(orc, n):
+    D = orc.Design(inputs.uniform_boundaries(n), DK1, DK2)
+    d, fb, fs = D.bruteforce()
+    # the optimum is the maximum over every pattern, and its value matches
+    # a quadrature of the definition
+    _, f_all = D.fitness(inputs.random_signs(512, n, seed=n))
+    assert fb >= f_all.max() and fs <= fb
+    Sq = orc.fitness_quad(inputs.uniform_boundaries(n), DK1, DK2, d)
+    assert abs(abs(Sq) ** 2 - fb) / fb < 1e-13
+
+
+# ---------------------------------------------------------------- relaxation
+
+def test_relaxation_matches_pair_sum_and_corners(orc):
+    n = 120
+    z = inputs.jittered_boundaries(n, 2.0, 0.3, seed=21)
+    D = orc.Design(z, DK1, DK2)
+    th = np.random.default_rng(3).standard_normal((3, n))
+    S, f, _ = D.relax(th)
+    Sp, fp = D.fitness_pairs(np.tanh(th))
+    assert rel(S, Sp) < 1e-13
+    # at the corners (|theta| large, tanh = +-1 exactly) the relaxed value is
+    # the +-1 fitness and the gradient vanishes
+    dpm = inputs.random_signs(3, n, seed=22)
+    S2, f2, g2 = D.relax(40.0 * dpm)
+    _, fpm = D.fitness(dpm)
+    assert rel(f2, fpm) < 1e-14
+    assert np.all(g2 == 0.0)
+
+
+def test_relaxation_gradient_vs_finite_differences(orc):
+    n = 400
+    z = inputs.uniform_boundaries(n)
+    D = orc.Design(z, DK1, DK2)
+    rng = np.random.default_rng(5)
+    th = rng.standard_normal((2, n))
+    _, f, g = D.relax(th)
+    h = 1e-6
+    idx = rng.integers(0, n, size=24)
+    for b in range(2):
+        for k in idx:
+            tp = th[b].copy()
+            tm = th[b].copy()
+            tp[k] += h
+            tm[k] -= h
+            _, fp, _ = D.relax(tp[None], grad=False)
+            _, fm, _ = D.relax(tm[None], grad=False)
+            fd = (fp[0] - fm[0]) / (2 * h)
+            assert abs(fd - g[b, k]) <= 1e-6 * np.max(np.abs(g[b])) + 1e-9 * abs(f[b])
+
+
+def test_relaxation_gradient_vs_pair_sum_derivative(orc):
+    # dS/dd_k of the quadratic form, written out as O(N^2) sums
+    n = 60
+    D = orc.Design(inputs.jittered_boundaries(n, 2.0, 0.3, seed=31), DK1, DK2)
+    a, b, c, _ = D.phases()
+    th = np.random.default_rng(8).standard_normal((1, n))
+    S, _, g = D.relax(th)
+    d = np.tanh(th[0])
+    for k in range(n):
+        dS = sum(d[m] * a[m] for m in range(k)) * b[k] + a[k] * sum(d[m] * b[m] for m in range(k + 1, n)) \
+            + 2 * c[k] * d[k]
+        want = 2 * np.real(np.conj(S[0]) * dS) * (1 - d[k] ** 2)
+        assert abs(want - g[0, k]) <= 1e-12 * np.max(np.abs(g))
+
+
+# ---------------------------------------------------------------- DE
+
+def test_init_population_range_and_signs(orc):
+    x = orc.init_pop(64, 300, seed=0)
+    assert x.min() >= -1.0 and x.max() < 1.0
+    d = orc.sign_map(x)
+    assert abs((d < 0).mean() - 0.5) < 0.02
+    # -0.0 and +0.0 map to +1
+    assert orc.sign_map(np.array([-0.0, 0.0, -1e-45, 1e-45], np.float32)).tolist() == [1, 1, -1, 1]
+
+
+def test_de_donors_distinct_and_uniform(orc):
+    np_, D = 16, 8
+    x = orc.init_pop(np_, D, seed=1)
+    counts = np.zeros((np_, np_))
+    for g in range(400):
+        _, idx = orc.de_step(x, 0.5, 0.9, seed=3, g=g)
+        r = idx[:, :3]
+        for i in range(np_):
+            assert len(set(r[i].tolist() + [i])) == 4
+            for v in r[i]:
+                counts[i, v] += 1
+        assert np.all((idx[:, 3] >= 0) & (idx[:, 3] < D))
+    # every donor slot j != i equally likely: 3 * 400 / 15 = 80 expected
+    off = counts[~np.eye(np_, dtype=bool)]
+    chi2 = np.sum((off - 80.0) ** 2 / 80.0)
+    assert chi2 < 330  # 240 dof; p ~ 1e-4 threshold
+
+
+def test_de_special_cases(orc):
+    np_, D = 12, 50
+    x = orc.init_pop(np_, D, seed=2)
+    # F = 0, CR = 1: the trial is exactly donor r1
+    u, idx = orc.de_step(x, 0.0, 1.0, seed=5, g=0)
+    assert np.array_equal(u, x[idx[:, 0]])
+    # CR = 0: gene jrand, and only it, comes from the mutant
+    u, idx = orc.de_step(x, 0.5, 0.0, seed=5, g=1)
+    for i in range(np_):
+        diff = np.nonzero(u[i] != x[i])[0]
+        assert diff.tolist() == [int(idx[i, 3])]
+    # constant rows x_k = k/64: with CR = 1 every gene of trial i is
+    # (r1 + F (r2 - r3)) / 64 (clamped), F = 1 keeps it exact
+    xc = np.repeat((np.arange(np_, dtype=np.float32) / 64.0)[:, None], D, axis=1)
+    u, idx = orc.de_step(xc, 1.0, 1.0, seed=6, g=0)
+    want = np.clip((idx[:, 0] + idx[:, 1] - idx[:, 2]) / 64.0, -1, 1).astype(np.float32)
+    assert np.array_equal(u, np.repeat(want[:, None], D, axis=1))
+    # crossover rate: fraction of mutant genes ~ CR
+    x = orc.init_pop(64, 400, seed=3)
+    u, _ = orc.de_step(x, 0.5, 0.3, seed=7, g=0)
+    frac = np.mean(u != x)
+    assert abs(frac - 0.3) < 0.02
+    # identical rows: any trial equals the row (mutant = x when donors agree)
+    xs = np.repeat(x[:1], 8, axis=0)
+    u, _ = orc.de_step(xs, 0.7, 0.9, seed=8, g=2)
+    assert np.array_equal(u, xs)
+    assert np.all(np.abs(orc.de_step(x, 2.0, 1.0, seed=9, g=0)[0]) <= 1.0)
+
+
+# ---------------------------------------------------------------- GWO
+
+def test_gwo_a_zero_closed_form(orc):
+    np_, D = 10, 64
+    x = orc.init_pop(np_, D, seed=4)
+    L = np.array([3, 7, 1], np.int32)
+    y = orc.gwo_step(x, L, 0.0, seed=1, g=0, variant=0)
+    X = x[L].astype(np.float64)
+    s = np.abs(X).sum(axis=0)
+    want = (np.abs(X) * X).sum(axis=0) / s / 3.0
+    for i in range(np_):
+        if i in L:
+            assert np.array_equal(y[i], x[i])
+        else:
+            assert np.max(np.abs(y[i] - want)) < 2e-7
+    ym = orc.gwo_step(x, L, 0.0, seed=1, g=0, variant=1)
+    for i in set(range(np_)) - set(L.tolist()):
+        assert np.max(np.abs(ym[i] - X.mean(axis=0))) < 2e-7
+
+
+def test_gwo_distance_uses_scaled_leader(orc):
+    # wolf at x = 0, leaders all X > 0: D_k = |C X - 0| = C X, so
+    # Y_k = X (1 - A C) with A C in (-2a, 2a): y / X spans (1 -+ 2a) / 3.
+    # (A distance |X - C x| would confine y / X to (1 -+ a) / 3.)
+    np_, D = 8, 4000
+    x = np.zeros((np_, D), np.float32)
+    x[:3] = 0.3
+    L = np.array([0, 1, 2], np.int32)
+    a = 0.5
+    y = orc.gwo_step(x, L, a, seed=9, g=0)[3:] / 0.3
+    assert y.min() >= (1 - 2 * a) / 3 - 1e-6 and y.max() <= (1 + 2 * a) / 3 + 1e-6
+    assert y.max() > (1 + a) / 3 + 0.02 and y.min() < (1 - a) / 3 - 0.02
+    assert np.all(np.abs(orc.gwo_step(orc.init_pop(20, 100, seed=5), L, 2.0, seed=3, g=4)) <= 1.0)
+
+
+def test_gwo_zero_leaders_give_zero(orc):
+    x = orc.init_pop(6, 40, seed=6)
+    x[[0, 1, 2]] = 0.0
+    y = orc.gwo_step(x, np.array([0, 1, 2], np.int32), 0.0, seed=2, g=0)
+    assert np.all(y[3:] == 0.0)
+
+
+def test_gwo_coefficient_ranges(orc):
+    # a wolf sitting on leaders that all equal X > 0 with a > 0:
+    # Y_k = X - A_k |C_k - 1| X with A in [-a, a), C in [0, 2) -> Y_k in
+    # X (1 - a, 1 + a], so y = weighted mean / 3 lies in X (1 -+ a) / 3.
+    np_, D = 8, 2000
+    x = np.full((np_, D), 0.6, np.float32)
+    L = np.array([0, 1, 2], np.int32)
+    a = 0.5
+    y = orc.gwo_step(x, L, a, seed=7, g=0)[3:]
+    assert y.min() >= 0.6 * (1 - a) / 3 - 1e-6 and y.max() <= 0.6 * (1 + a) / 3 + 1e-6
+    # the spread uses the whole range: A C-coupling is random per gene
+    assert y.std() > 0.01
+
+
+# ---------------------------------------------------------------- leaders / loop
+
+def test_top3_order_and_ties(orc):
+    f = np.array([1.0, 5.0, 5.0, 3.0, 5.0, 0.0])
+    assert orc.top3(f).tolist() == [1, 2, 4]
+    rng = np.random.default_rng(1)
+    g = rng.standard_normal(1000)
+    assert orc.top3(g).tolist() == np.argsort(-g, kind="stable")[:3].tolist()
+
+
+def test_a_schedule(orc):
+    G = 200
+    a = np.array([orc.a_schedule(g, G) for g in range(G)])
+    assert a[0] == 2.0 and abs(a[-1] - 0.01) < 1e-7
+    assert np.all(np.diff(a) < 0)
+
+
+@pytest.mark.slow
+def test_hwsda_reaches_bruteforce_optimum(orc):
+    n = 12
+    D = orc.Design(inputs.uniform_boundaries(n), DK1, DK2)
+    _, fb, _ = D.bruteforce()
+    hits = 0
+    for seed in range(6):
+        x, f, tr = D.hwsda_run(32, 60, 0.5, 0.9, seed)
+        assert np.all(np.diff(tr) >= 0)  # best-so-far never decreases
+        hits += abs(f.max() - fb) <= 1e-12 * fb
+    assert hits >= 5
+
+
+@pytest.mark.parametrize("F,CR", [(0.5, 0.9), (0.0, 0.0)])
+def test_hwsda_run_consistent_with_steps(orc, F, CR):
+    # one generation of the loop equals the individual steps chained by hand;
+    # with F = CR = 0 half of the trials tie their target (same signs), and a
+    # trial replaces its target only when strictly better
+    n, np_ = 40, 8
+    D = orc.Design(inputs.uniform_boundaries(n), DK1, DK2)
+    x1, f1, _ = D.hwsda_run(np_, 1, F, CR, seed=3)
+    x = orc.init_pop(np_, n, seed=3)
+    _, f = D.fitness(orc.sign_map(x))
+    u, _ = orc.de_step(x, F, CR, seed=3, g=0)
+    _, fu = D.fitness(orc.sign_map(u))
+    acc = fu > f
+    x[acc] = u[acc]
+    f[acc] = fu[acc]
+    L = orc.top3(f)
+    y = orc.gwo_step(x, L, orc.a_schedule(0, 1), seed=3, g=0)
+    _, fy = D.fitness(orc.sign_map(y))
+    acc = fy > f
+    acc[L] = False
+    x[acc] = y[acc]
+    f[acc] = fy[acc]
+    assert np.array_equal(x, x1) and np.array_equal(f, f1)
+
+
+def test_hwsda_ties_keep_the_target(orc):
+    # with a single domain every genome has the same f (d^2 = 1), so every
+    # trial and candidate ties its target; strict selection keeps the
+    # initial population unchanged
+    D = orc.Design(np.array([0.0, 2.0]), DK1, DK2)
+    x, f, _ = D.hwsda_run(6, 5, 0.5, 0.9, seed=4)
+    assert np.array_equal(x, orc.init_pop(6, 1, seed=4))
+    assert np.all(f == f[0])
