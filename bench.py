@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Benchmark of the HWSDA hot path on one MI355X.
+
+Workload (the fitness-throughput population): N = 10,000 domains of 2.0 um
+(L = 20 mm), dk1 = 2 pi / 19.5 um^-1, dk2 = 2 pi / 6.6 um^-1, NP = 4096
+genomes = 4064 iid +-1 (p = 1/2) + 32 first-order periodic seeds
+(period 19.5 um, random phase). Genes carry those signs with magnitudes
+uniform on (0, 1). All inputs are synthetic and seeded, resident in HBM
+before timing starts.
+
+One step = one HWSDA generation over that population, every kernel of the
+hot path: DE rand/1 trials (F = 0.5, CR = 0.9), evaluation of the 4096
+trials, selection, top-3 leaders, grey-wolf candidates, evaluation,
+selection, generation advance -- replayed as one captured HIP graph.
+
+value = domain evaluations per second over whole generations:
+(2 NP - 3) N per generation / measured seconds. Also reported: generations/s
+with FP32 and FP64 fitness and with the per-individual FP64 kernel; the
+fitness kernels alone; per-kernel times from HIP events on the run's own
+stream; the roofline of the dominant kernel; the CPU oracle on a bounded
+sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("domain-evaluations/sec (NP×N per s) of |d_eff|^2; HWSDA generations/s vs FP64 plain")
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, GB/s
+PEAK_FP32_TFLOPS = 157.3     # vector FP32 (packed), TFLOP/s
+PEAK_FP64_TFLOPS = 78.6      # vector FP64, TFLOP/s
+PEAK_VALU_TOPS = 39.3        # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, lane-instructions/s (x1e12)
+
+N_DOMAINS, NP, WIDTH = 10000, 4096, 2.0
+F, CR, SEED = 0.5, 0.9, 0
+
+
+def algorithmic_work(step, npop, n):
+    """(bound, work per launch, unit) of one generation step; work is the
+    algorithmic bytes or operations of one launch."""
+    genes = npop * n
+    bits = genes / 8.0
+    if step == "de":          # target + 3 donors read, trial written, trial bits
+        return "hbm", 20.0 * genes + bits, "B"
+    if step == "gwo":         # Philox words: 3 calls per 4 genes (integer VALU)
+        return "alu", 0.75 * genes, "philox"
+    if step.startswith("fitness"):  # 10 flops per domain evaluation, bits read
+        return "alu", 10.0 * genes, "flop"
+    return "latency", 0.0, ""
+
+
+def philox_issue_slots():
+    """VALU issue slots of one Philox4x32-10 call on gfx950: 10 rounds of two
+    32x32->64 multiplies (v_mad_u64_u32, quarter rate = 4 slots each) and
+    four 32-bit xors."""
+    return 10 * (2 * 4 + 4)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--prec", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--cpu-generations", type=int, default=6,
+                    help="generations of the CPU oracle sample (0 = skip)")
+    ap.add_argument("--no-extras", action="store_true", help="only the timed generations")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2511_01255_amd import inputs
+    from paper_2511_01255_amd import qpm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+
+    z = inputs.uniform_boundaries(N_DOMAINS, WIDTH)
+    d = inputs.fitness_population(NP, N_DOMAINS, WIDTH, 32, seed=1)
+    mag = np.random.default_rng(2).uniform(1e-3, 1.0, size=d.shape).astype(np.float32)
+    genes = torch.from_numpy(np.ascontiguousarray(mag * d.astype(np.float32))).cuda()
+    bits = torch.from_numpy(inputs.pack_bits(d).view(np.int32)).cuda()
+    design = qpm.precompute_phases(z, inputs.DK1, inputs.DK2)
+    prec = qpm.PREC_F64 if args.prec == "f64" else qpm.PREC_F32
+    evals_per_gen = (2 * NP - 3) * N_DOMAINS
+
+    def timed_run(prec_, fit_kernel, steps, warmup):
+        R = qpm.Run(design, NP, warmup + steps + 32, F=F, CR=CR, seed=SEED, prec=prec_, fit_kernel=fit_kernel)
+        R.load(genes)
+        R.advance(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R.advance(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return R, dt
+
+    log("[bench] main timed run: %d warmup + %d steps, prec %s" % (args.warmup, args.steps, args.prec))
+    R, dt = timed_run(prec, qpm.FIT_AUTO, args.steps, args.warmup)
+    value = evals_per_gen * args.steps / dt
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "domain-evaluations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {
+            "workload": "fitness-throughput population: N=10000 domains x 2.0 um (L=20 mm), dk1=2pi/19.5, "
+                        "dk2=2pi/6.6 um^-1, NP=4096 (4064 iid +-1 + 32 periodic seeds); one HWSDA generation "
+                        "per step (DE rand/1 F=0.5 CR=0.9, GWO a: 2->0), %s fitness" % args.prec.upper(),
+            "N": N_DOMAINS, "NP": NP, "generation_evals": 2 * NP - 3,
+        },
+        "generations_per_s": args.steps / dt,
+    }
+
+    # per-kernel times from HIP events on the run's stream
+    tsteps = 20
+    R.set_timing(True)
+    R.timing(reset=True)
+    R.advance(tsteps)
+    ms, ng = R.timing()
+    R.set_timing(False)
+    R.destroy()
+    per = {k: v / ng for k, v in ms.items()}
+    out["kernel_ms"] = per
+    dom = max(per, key=per.get)
+    bound, work, wunit = algorithmic_work(dom, NP, N_DOMAINS)
+    t_dom = per[dom] * 1e-3
+    if bound == "hbm":
+        roof = {"bound": "hbm", "achieved": work / t_dom / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    elif wunit == "philox":
+        # integer VALU: Philox words per launch x issue slots per word
+        slots = work * philox_issue_slots()
+        roof = {"bound": "alu", "achieved": slots / t_dom / 1e12, "peak": PEAK_VALU_TOPS,
+                "unit": "T VALU lane-slots/s (Philox)"}
+    else:
+        peak = PEAK_FP64_TFLOPS if prec == qpm.PREC_F64 else PEAK_FP32_TFLOPS
+        roof = {"bound": "alu", "achieved": work / t_dom / 1e12, "peak": peak, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["kernel_ms"] = per[dom]
+    out["roofline"] = roof
+
+    if not args.no_extras:
+        # generations/s with FP64 fitness, segmented and per-individual
+        alt = {}
+        for name, p_, k_ in (("f64_segmented", qpm.PREC_F64, qpm.FIT_AUTO),
+                             ("f64_per_genome", qpm.PREC_F64, qpm.FIT_PER_GENOME),
+                             ("f32_segmented", qpm.PREC_F32, qpm.FIT_AUTO)):
+            st = 40 if k_ != qpm.FIT_PER_GENOME else 10
+            R2, dt2 = timed_run(p_, k_, st, 3)
+            R2.destroy()
+            alt[name] = st / dt2
+            log("[bench] %s: %.1f generations/s" % (name, st / dt2))
+        out["generations_per_s_by_fitness"] = alt
+
+        # fitness kernels alone on the same bits
+        fit = {}
+        stream = torch.cuda.current_stream()
+        for name, p_, k_, reps in (("f32_segmented", qpm.PREC_F32, qpm.FIT_AUTO, 100),
+                                   ("f64_segmented", qpm.PREC_F64, qpm.FIT_AUTO, 100),
+                                   ("f64_per_genome", qpm.PREC_F64, qpm.FIT_PER_GENOME, 5)):
+            o = qpm.eval_fitness(design, bits, NP, prec=p_, kernel=k_)
+            for _ in range(3):
+                qpm.eval_fitness(design, bits, NP, prec=p_, kernel=k_, out=o)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                qpm.eval_fitness(design, bits, NP, prec=p_, kernel=k_, out=o)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) * 1e-3 / reps
+            rate = NP * N_DOMAINS / t
+            peak = PEAK_FP64_TFLOPS if p_ == qpm.PREC_F64 else PEAK_FP32_TFLOPS
+            fit[name] = {"domain_evals_per_s": rate, "us_per_pass": t * 1e6,
+                         "alg_tflops": 10 * rate / 1e12, "frac_of_peak": 10 * rate / 1e12 / peak}
+            log("[bench] fitness %s: %.3g domain-evals/s (%.1f us)" % (name, rate, t * 1e6))
+        out["fitness_only"] = fit
+
+    if args.cpu_generations > 0:
+        import oracle as orc
+        log("[bench] CPU oracle: %d generations" % args.cpu_generations)
+        O = orc.Design(z, inputs.DK1, inputs.DK2)
+        x = (mag * d.astype(np.float32)).astype(np.float32)
+        t0 = time.perf_counter()
+        _, f = O.fitness(orc.sign_map(x))
+        G = args.cpu_generations
+        for g in range(G):
+            u, _ = orc.de_step(x, F, CR, SEED, g)
+            _, fu = O.fitness(orc.sign_map(u))
+            acc = fu > f
+            x[acc] = u[acc]
+            f[acc] = fu[acc]
+            L = orc.top3(f)
+            y = orc.gwo_step(x, L, orc.a_schedule(g, G), SEED, g)
+            _, fy = O.fitness(orc.sign_map(y))
+            acc = fy > f
+            acc[L] = False
+            x[acc] = y[acc]
+            f[acc] = fy[acc]
+        tc = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": evals_per_gen * G / tc,
+            "unit": "domain-evaluations/s",
+            "cores": orc.num_threads(),
+            "kind": "oracle",
+            "sample": "%d HWSDA generations of the same workload (plus the initial evaluation) with the "
+                      "long-double CPU oracle, %.1f s" % (G, tc),
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,267 @@
+/*
+ * qpm.h -- C ABI of the MI355X (gfx950) hot path of HWSDA, the hybrid
+ * differential-evolution / grey-wolf optimiser for aperiodically poled
+ * quasi-phase-matching crystals (He Chen, Zihua Zheng, Jinghua Sun, "Design
+ * of quasi phase matching crystal based on differential gray wolf
+ * algorithm").
+ *
+ * Objective (paper Sec. 2.1, the d_eff double integral): for a crystal cut
+ * into N domains [z_{n-1}, z_n) with polarity d_n = +1 or -1,
+ *   d_eff = int d(z) e^{-i dk2 z} ( int_{z_0}^{z} d(x) e^{-i dk1 x} dx ) dz,
+ * and the fitness is f = |d_eff|^2 (maximised; the undepleted-pump
+ * prefactor is dropped, as in the paper). Units: z in um, dk in 1/um,
+ * d_eff in um^2, f in um^4.
+ *
+ * Conventions shared by every entry point
+ *   - Device pointers are HIP device memory of the current device; host
+ *     pointers are ordinary process memory. The caller owns every buffer it
+ *     passes and the library keeps no caller pointer after a call returns.
+ *   - qpm_stream is a hipStream_t (NULL = the null stream). Entry points
+ *     validate their arguments on the host, enqueue work on the stream and
+ *     return without synchronising unless stated otherwise; device faults
+ *     surface at the next synchronisation.
+ *   - A failing call returns a negative qpm_status, launches nothing and
+ *     writes no output; qpm_last_error() then holds a message (per thread).
+ *     Nothing aborts and no C++ exception crosses the ABI.
+ *   - Bit layout of a population of +-1 sequences ("population-major"):
+ *     uint32 words bits[w * ld + i], w < W = ceil(N / 32), i < ld; bit k of
+ *     word w of genome i is set exactly when d_{32 w + k} = -1 (0-based
+ *     domains). ld >= np and ld is a multiple of 64. Padding bits (domains
+ *     >= N) must be 0; padding columns (i >= np) are read but ignored.
+ *   - Genes (the optimiser's continuous positions): float rows x[i * ldx + j],
+ *     j < D = N, ldx >= D rounded up to a multiple of 4, rows 16-byte
+ *     aligned. Gene j maps to d_j = -1 exactly when x_ij < 0.0f (so -0.0
+ *     maps to +1).
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the
+ *     64-bit seed; the counter is (c0, individual, generation,
+ *     instance << 8 | stream tag), so every draw depends only on its
+ *     coordinates, never on launch shape.
+ */
+#ifndef QPM_H
+#define QPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qpm_status;
+enum {
+    QPM_OK = 0,
+    QPM_EINVAL = -1,  /* an argument is invalid (see each entry point) */
+    QPM_ERANGE = -2,  /* a size overflows the supported range */
+    QPM_ENOMEM = -3,  /* a device allocation failed */
+    QPM_EHIP = -4,    /* a HIP runtime call failed (text in qpm_last_error) */
+    QPM_ENOTSUP = -5  /* the current device is not gfx950 */
+};
+
+typedef enum {
+    QPM_PREC_F32 = 0, /* FP32 within blocks of domains, FP64 across blocks */
+    QPM_PREC_F64 = 1  /* FP64 throughout */
+} qpm_prec;
+
+/* Which fitness kernel evaluates a population. */
+typedef enum {
+    QPM_FIT_AUTO = 0,       /* segmented, launch shape from the tuner */
+    QPM_FIT_SEGMENTED = 1,  /* domain axis split over waves and workgroups */
+    QPM_FIT_PER_GENOME = 2  /* one lane per genome over all N (FP64 only) */
+} qpm_fit_kernel;
+
+typedef void *qpm_stream;               /* a hipStream_t */
+typedef struct qpm_design_s *qpm_design; /* owns the device phase tables */
+typedef struct qpm_run_s *qpm_run_handle;
+
+/* Status text for a code, and the calling thread's last error message. */
+const char *qpm_status_string(qpm_status s);
+const char *qpm_last_error(void);
+
+/*
+ * qpm_precompute_phases -- build a design: the per-domain integrals of the
+ * d_eff double integral (paper Sec. 2.1), evaluated on the GPU in FP64.
+ *   a_n = int_{z_{n-1}}^{z_n} e^{-i dk1 x} dx,
+ *   b_n = int_{z_{n-1}}^{z_n} e^{-i dk2 z} dz,
+ *   c_n = int_{z_{n-1}}^{z_n} e^{-i dk2 z} int_{z_{n-1}}^{z} e^{-i dk1 x} dx dz,
+ *   C = sum_n c_n, so that d_eff = sum_n d_n b_n P_{n-1} + C with
+ *   P_n = sum_{m<=n} d_m a_m.
+ * z: host, n_domains + 1 finite, strictly increasing boundaries (um); z[0]
+ * may be non-zero. dk1, dk2: finite (1/um), zero allowed. n_domains >= 1
+ * and <= 2^27. The call synchronises s before it returns (the design is
+ * ready to use on any stream). *out receives the design; free it with
+ * qpm_design_free. Errors: QPM_EINVAL (bad z or dk, NULL pointer),
+ * QPM_ERANGE (n too large), QPM_ENOMEM, QPM_EHIP, QPM_ENOTSUP.
+ */
+qpm_status qpm_precompute_phases(const double *z, int64_t n_domains, double dk1, double dk2,
+                                 qpm_stream s, qpm_design *out);
+
+/* Release a design (NULL is accepted). Synchronises the device first. */
+qpm_status qpm_design_free(qpm_design d);
+
+/* n_domains and C = sum_n c_n (re, im) of a design (host outputs; either
+ * may be NULL). */
+qpm_status qpm_design_info(qpm_design d, int64_t *n_domains, double *C);
+
+/* Copy the FP64 per-domain integrals to host arrays of 2 * n_domains
+ * doubles (re, im interleaved); any pointer may be NULL. Synchronous. */
+qpm_status qpm_design_read_phases(qpm_design d, double *a, double *b, double *c);
+
+/*
+ * qpm_eval_fitness -- f_i = |d_eff(d_i)|^2 for np genomes (paper Sec. 2.1;
+ * evaluation step of Sec. 3.2).
+ * bits: device, population-major words (layout above), W x ld uint32.
+ * fitness: device, np floats (QPM_PREC_F32) or doubles (QPM_PREC_F64).
+ * kernel: a qpm_fit_kernel; QPM_FIT_PER_GENOME needs QPM_PREC_F64.
+ * Temporary device memory is taken from the stream-ordered allocator of s.
+ * Errors: QPM_EINVAL (np < 1, ld < np or not a multiple of 64, NULL
+ * pointer, unknown precision or kernel), QPM_ENOMEM, QPM_EHIP.
+ */
+qpm_status qpm_eval_fitness(qpm_design d, qpm_prec p, const uint32_t *bits, int64_t np,
+                            int64_t ld, void *fitness, int32_t kernel, qpm_stream s);
+
+/*
+ * qpm_init_population -- DE step 1 (paper Sec. 2.2.1): x_ij uniform on
+ * [-1, 1) (Philox stream INIT, counter (j / 4, i, 0, inst << 8 | 1), word
+ * j % 4, value (u >> 8) 2^-23 - 1), and the +-1 bits of every row.
+ * x: device np x ldx floats; bits: device W x ld words.
+ */
+qpm_status qpm_init_population(int64_t np, int64_t D, int64_t ldx, uint64_t seed, uint32_t inst,
+                               float *x, uint32_t *bits, int64_t ld, qpm_stream s);
+
+/*
+ * qpm_de_step -- DE rand/1 mutation and binomial crossover (paper Sec.
+ * 2.2.1 steps 2-3), synchronous over the population x of generation g:
+ *   r1, r2, r3 distinct and != i (np >= 4), drawn without replacement from
+ *   one Philox call (counter (0, i, g, inst << 8 | 2): words 0..2 give
+ *   k_m = floor(u np_m / 2^32) with np_m = np-1, np-2, np-3 and r_m the k_m-th
+ *   index not yet excluded; word 3 gives jrand = floor(u D / 2^32));
+ *   v_j = fmaf(F, x_r2j - x_r3j, x_r1j) clamped to [-1, 1];
+ *   u_ij = v_j if ((u >> 8) 2^-24 <= CR) or j == jrand, else x_ij, with u
+ *   from counter (j / 4, i, g, inst << 8 | 3), word j % 4.
+ * x: device np x ldx; u: device np x ldx (trial vectors); u_bits: device
+ * W x ld words of the trials. F in [0, 2], CR in [0, 1].
+ * Errors: QPM_EINVAL (np < 4, D < 1, ldx, ld, F, CR out of range, NULL or
+ * misaligned pointer).
+ */
+qpm_status qpm_de_step(const float *x, int64_t np, int64_t D, int64_t ldx, float F, float CR,
+                       uint64_t seed, uint32_t generation, uint32_t inst, float *u,
+                       uint32_t *u_bits, int64_t ld, qpm_stream s);
+
+/*
+ * qpm_gwo_step -- grey-wolf update of the omega wolves (paper Sec. 2.2.2):
+ * per gene j of a non-leader i and leader k in (alpha, beta, delta), with
+ * r1 = lo16(u) 2^-16 and r2 = hi16(u) 2^-16 of one Philox word,
+ *   A = fmaf(2a, r1, -a), C = 2 r2, D_k = |fmaf(C, X_kj, -x_ij)|,
+ *   Y_k = fmaf(-A, D_k, X_kj);
+ * variant 0 (as printed): y = (sum_k |Y_k| Y_k / sum_k |Y_k|) / 3 (0 if the
+ * sum is 0); variant 1: y = (Y_1 + Y_2 + Y_3) / 3; clamped to [-1, 1].
+ * Philox words: for gene quad q = j / 4 and t = 3 (j % 4) + k, counter
+ * (3 q + t / 4, i, g, inst << 8 | 4), word t % 4.
+ * leaders: device int32[3] (alpha, beta, delta), distinct, in [0, np); the
+ * call copies them to the host to validate them, so it synchronises s.
+ * Leader rows of y and y_bits are left untouched. a >= 0.
+ */
+qpm_status qpm_gwo_step(const float *x, int64_t np, int64_t D, int64_t ldx,
+                        const int32_t *leaders, float a, uint64_t seed, uint32_t generation,
+                        uint32_t inst, int32_t variant, float *y, uint32_t *y_bits, int64_t ld,
+                        qpm_stream s);
+
+/* Configuration of a whole optimisation (paper Sec. 3.2, steps 1-7). */
+typedef struct {
+    int64_t np;          /* population size, >= 4 */
+    int64_t generations; /* G >= 1 */
+    float F;             /* DE scale factor in [0, 2] */
+    float CR;            /* crossover rate in [0, 1] */
+    uint64_t seed;       /* Philox key */
+    uint32_t inst;       /* instance number in the Philox counter */
+    int32_t prec;        /* qpm_prec of the fitness kernel */
+    int32_t gwo_variant; /* 0 = weighted as printed, 1 = plain mean */
+    int32_t use_graph;   /* 1 = replay one captured generation */
+    int32_t fit_kernel;  /* qpm_fit_kernel of the evaluations */
+} qpm_run_config;
+
+typedef struct {
+    double best_fitness;  /* f of the best individual */
+    int64_t best_index;   /* its slot (lowest slot among ties) */
+    int64_t generations;  /* generations completed */
+    int64_t fitness_evals; /* genomes evaluated */
+    double domain_evals;  /* fitness_evals * N */
+} qpm_run_stats;
+
+/*
+ * qpm_run_create -- allocate a run and perform step 1 (initialise, evaluate,
+ * pick leaders). One generation g (steps 2-6 of paper Sec. 3.2) is then:
+ * DE trials (qpm_de_step), evaluation, greedy one-to-one selection (a
+ * trial replaces its target only when strictly better), leaders alpha,
+ * beta, delta = the three best by (f descending, slot ascending), GWO
+ * candidates for every other wolf with a_g = (float)(2 (1 - g / G)),
+ * evaluation, greedy selection again (leaders excluded). The run owns its
+ * own stream; s is the stream the caller's later reads are ordered with.
+ */
+qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_stream s,
+                          qpm_run_handle *out);
+
+/* Advance a run by `generations` (asynchronous on the run's stream; the
+ * total may not exceed cfg->generations). */
+qpm_status qpm_run_advance(qpm_run_handle r, int64_t generations);
+
+/*
+ * Copy the current state: x (device, np x ldx floats, may be NULL),
+ * fitness (device, np floats or doubles per cfg->prec, may be NULL),
+ * leaders (host int32[3], may be NULL: the leaders chosen in the last
+ * completed generation, or at initialisation), *generation (host, may be
+ * NULL). Synchronous.
+ */
+qpm_status qpm_run_read(qpm_run_handle r, float *x, int64_t ldx, void *fitness, int32_t *leaders,
+                        int64_t *generation);
+
+/* Best individual of the current population: best_x (device, D floats, may
+ * be NULL), best_bits (device, W words, may be NULL), stats (host, may be
+ * NULL). Synchronous. */
+qpm_status qpm_run_best(qpm_run_handle r, float *best_x, uint32_t *best_bits, qpm_run_stats *stats);
+
+/*
+ * qpm_run_load -- replace the current population with caller genes x
+ * (device, np x ldx floats, ldx >= D), then evaluate it and pick the
+ * leaders again (a warm start from chosen designs, e.g. periodic poling).
+ * The generation count is unchanged. Asynchronous on the run's stream.
+ */
+qpm_status qpm_run_load(qpm_run_handle r, const float *x, int64_t ldx);
+
+/* Kernels of one generation, in launch order (timing slots). */
+enum {
+    QPM_K_DE = 0,
+    QPM_K_FIT_DE = 1,
+    QPM_K_SELECT_DE = 2,
+    QPM_K_TOP3 = 3,
+    QPM_K_GWO = 4,
+    QPM_K_FIT_GWO = 5,
+    QPM_K_SELECT_GWO = 6,
+    QPM_K_ADVANCE = 7,
+    QPM_K_COUNT = 8
+};
+
+/*
+ * qpm_run_set_timing -- with enable != 0, qpm_run_advance launches each
+ * generation kernel by kernel (no graph) on the run's stream with a HIP
+ * event after every step, synchronises at the end of the call and adds the
+ * measured durations to per-step totals; enable == 0 returns to the normal
+ * mode. qpm_run_timing copies the totals (ms, host double[QPM_K_COUNT]) and
+ * the number of timed generations, and with reset != 0 clears them.
+ */
+qpm_status qpm_run_set_timing(qpm_run_handle r, int32_t enable);
+qpm_status qpm_run_timing(qpm_run_handle r, double *ms, int64_t *generations, int32_t reset);
+
+/* Release a run (NULL accepted). */
+qpm_status qpm_run_destroy(qpm_run_handle r);
+
+/* qpm_run -- create, advance cfg->generations, report the best, destroy.
+ * Synchronous. */
+qpm_status qpm_run(qpm_design d, const qpm_run_config *cfg, float *best_x, uint32_t *best_bits,
+                   qpm_run_stats *stats, qpm_stream s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QPM_H */

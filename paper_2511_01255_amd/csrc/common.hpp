@@ -1,0 +1,110 @@
+// common.hpp -- shared host/device pieces of libqpm (HIP, gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+
+#include "qpm.h"
+
+#define QPM_API extern "C" __attribute__((visibility("default")))
+
+namespace qpm {
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
+void clear_error();
+
+#define QPM_TRY_HIP(expr)                                                              \
+    do {                                                                               \
+        hipError_t qpm_e_ = (expr);                                                    \
+        if (qpm_e_ != hipSuccess) {                                                    \
+            ::qpm::set_error("%s failed: %s", #expr, hipGetErrorString(qpm_e_));     \
+            return (qpm_e_ == hipErrorOutOfMemory) ? QPM_ENOMEM : QPM_EHIP;            \
+        }                                                                              \
+    } while (0)
+
+#define QPM_REQUIRE(cond, code, ...)     \
+    do {                                 \
+        if (!(cond)) {                   \
+            ::qpm::set_error(__VA_ARGS__); \
+            return (code);               \
+        }                                \
+    } while (0)
+
+// checks that the current device is gfx950
+qpm_status check_device();
+
+inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+inline int64_t words_for(int64_t n) { return (n + 31) / 32; }
+
+// ---------------------------------------------------------------- design
+
+struct Design {
+    int64_t n = 0;       // domains
+    int64_t words = 0;   // W = ceil(n / 32)
+    double dk1 = 0, dk2 = 0;
+    double C[2] = {0, 0};
+    double4 *ph64 = nullptr;  // [32 W] {a.re, a.im, b.re, b.im}, zero padded
+    float4 *ph32 = nullptr;   // [32 W] the same rounded to float
+    double2 *c64 = nullptr;   // [n] diagonal terms c_n
+    double *Cdev = nullptr;   // [2] C on the device
+    int device = 0;
+};
+
+// ---------------------------------------------------------------- fitness
+
+struct FitPlan {
+    int kind = QPM_FIT_SEGMENTED;  // qpm_fit_kernel (never AUTO here)
+    int waves = 16;                // waves per workgroup (segmented)
+    int wpw = 2;                   // bit words per wave (segmented)
+    int gy = 1;                    // workgroup segments along the domain axis
+};
+
+FitPlan plan_fitness(const Design &d, qpm_prec p, int64_t np, int kernel);
+size_t fitness_workspace_bytes(const FitPlan &plan, int64_t ld);
+qpm_status launch_fitness(const Design &d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                          void *fitness, const FitPlan &plan, double *workspace, hipStream_t s);
+
+// ---------------------------------------------------------------- evolution kernels
+
+// Rows of the current population live in one of two buffers; flags[i]
+// (nullable = all 0) selects buf1 for row i. Trials / candidates of row i
+// are written to the other buffer (out1 when flags is null).
+struct PopView {
+    const float *x0;
+    const float *x1;
+    const uint32_t *flags;
+    float *out0;  // target of row i when flags[i] == 1
+    float *out1;  // target of row i when flags[i] == 0 (or flags null)
+    int64_t np, D, ldx;
+};
+
+qpm_status launch_init(int64_t np, int64_t D, int64_t ldx, uint64_t seed, uint32_t inst, float *x,
+                       uint32_t *bits, int64_t ld, hipStream_t s);
+qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const uint32_t *gen_dev,
+                     uint32_t gen, uint32_t inst, uint32_t *bits, int64_t ld, hipStream_t s);
+qpm_status launch_gwo(const PopView &pv, const int32_t *leaders, const float *a_tab, float a,
+                      uint64_t seed, const uint32_t *gen_dev, uint32_t gen, uint32_t inst,
+                      int variant, uint32_t *bits, int64_t ld, hipStream_t s);
+// f[i] <- fnew[i] and flags[i] ^= 1 where fnew[i] > f[i] (leaders skipped
+// when non-null); T = float or double by `f64`
+qpm_status launch_select(void *f, const void *fnew, uint32_t *flags, int64_t np, const int32_t *leaders,
+                         bool f64, hipStream_t s);
+// the three best slots by (f descending, slot ascending)
+qpm_status launch_top3(const void *f, int64_t np, bool f64, int32_t *out3, hipStream_t s);
+// rows of the current population (through flags) -> dense out[np][ldo]
+qpm_status launch_gather(const PopView &pv, const int32_t *rows, int64_t nrows, float *out, int64_t ldo,
+                         hipStream_t s);
+// sign bits of every row of a dense population x[np][ldx] -> W x ld words
+qpm_status launch_pack_pop(const float *x, int64_t np, int64_t D, int64_t ldx, uint32_t *bits, int64_t ld,
+                           hipStream_t s);
+// sign bits of one gene row (D genes) -> W words
+qpm_status launch_pack_row(const float *x, int64_t D, uint32_t *bits, hipStream_t s);
+
+}  // namespace qpm
+
+// The opaque handle types of the ABI are the library's structures.
+struct qpm_design_s : public qpm::Design {};

@@ -1,0 +1,316 @@
+// fitness.hip -- f = |d_eff|^2 over bit-packed +-1 genomes (paper Sec. 2.1).
+//
+// Per genome the double integral splits domain by domain into
+//   d_eff = sum_n d_n b_n P_{n-1} + C,   P_n = sum_{m<=n} d_m a_m,
+// and a stretch of domains reduces to the triple (A, B, Q) =
+// (sum d a, sum d b, sum d_n b_n (A before n)). Triples combine
+// associatively: (A1,B1,Q1) + (A2,B2,Q2) = (A1+A2, B1+B2, Q1+Q2+A1 B2).
+//
+// Mapping on gfx950: one lane per genome (a wave = 64 consecutive genomes,
+// so each bit word load is one 256-byte coalesced row of the
+// population-major layout). The domain axis is cut into segments of `wpw`
+// words; each wave scans one segment, reading the per-domain coefficients
+// with scalar loads (they are the same for every lane), the waves of a
+// workgroup combine their triples in LDS in segment order, and a second
+// small pass combines workgroup segments in order. No float atomics: the
+// result depends only on the launch plan, never on timing.
+#include "common.hpp"
+
+namespace qpm {
+
+// +-1.0 from bit k of w (bit set -> -1), as a double and as a float
+__device__ __forceinline__ double sign64(uint32_t w, int k)
+{
+    const uint32_t hi = ((w << (31 - k)) & 0x80000000u) | 0x3ff00000u;
+    return __hiloint2double(static_cast<int>(hi), 0);
+}
+__device__ __forceinline__ float sign32(uint32_t w, int k)
+{
+    return __uint_as_float(((w << (31 - k)) & 0x80000000u) | 0x3f800000u);
+}
+
+struct Tri {
+    double ar, ai, br, bi, qr, qi;
+};
+
+// t <- t (+) u   (t covers the domains before u)
+__device__ __forceinline__ void tri_append(Tri &t, const Tri &u)
+{
+    t.qr = fma(t.ar, u.br, fma(-t.ai, u.bi, t.qr + u.qr));
+    t.qi = fma(t.ar, u.bi, fma(t.ai, u.br, t.qi + u.qi));
+    t.ar += u.ar;
+    t.ai += u.ai;
+    t.br += u.br;
+    t.bi += u.bi;
+}
+
+__device__ __forceinline__ void store_fitness(void *fit, int out_f64, int64_t i, const Tri &t,
+                                              const double *__restrict__ C)
+{
+    const double sr = t.qr + C[0], si = t.qi + C[1];
+    const double f = fma(sr, sr, si * si);
+    if (out_f64)
+        static_cast<double *>(fit)[i] = f;
+    else
+        static_cast<float *>(fit)[i] = static_cast<float>(f);
+}
+
+// One word (32 domains) in FP64.
+__device__ __forceinline__ void scan_word_f64(Tri &t, uint32_t word, const double4 *__restrict__ p)
+{
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        const double4 c = p[k];  // {a.re, a.im, b.re, b.im}, wave-uniform
+        const double s = sign64(word, k);
+        const double tr = fma(c.z, t.ar, -(c.w * t.ai));
+        const double ti = fma(c.z, t.ai, c.w * t.ar);
+        t.qr = fma(s, tr, t.qr);
+        t.qi = fma(s, ti, t.qi);
+        t.ar = fma(s, c.x, t.ar);
+        t.ai = fma(s, c.y, t.ai);
+        t.br = fma(s, c.z, t.br);
+        t.bi = fma(s, c.w, t.bi);
+    }
+}
+
+// One word in FP32 blocks of BLK domains, each block folded into FP64.
+template <int BLK>
+__device__ __forceinline__ void scan_word_f32(Tri &t, uint32_t word, const float4 *__restrict__ p)
+{
+#pragma unroll
+    for (int h = 0; h < 32 / BLK; ++h) {
+        float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f, qr = 0.f, qi = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < BLK; ++kk) {
+            const int k = h * BLK + kk;
+            const float4 c = p[k];
+            const float s = sign32(word, k);
+            const float tr = fmaf(c.z, ar, -(c.w * ai));
+            const float ti = fmaf(c.z, ai, c.w * ar);
+            qr = fmaf(s, tr, qr);
+            qi = fmaf(s, ti, qi);
+            ar = fmaf(s, c.x, ar);
+            ai = fmaf(s, c.y, ai);
+            br = fmaf(s, c.z, br);
+            bi = fmaf(s, c.w, bi);
+        }
+        const Tri u{ar, ai, br, bi, qr, qi};
+        tri_append(t, u);
+    }
+}
+
+template <bool F32, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void fit_seg_kernel(const uint32_t *__restrict__ bits, int64_t ld, int W,
+                                                             const double4 *__restrict__ ph64,
+                                                             const float4 *__restrict__ ph32, int wpw, int64_t np,
+                                                             double *__restrict__ part,
+                                                             const double *__restrict__ C, void *__restrict__ fit,
+                                                             int direct, int out_f64)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+    const int seg = static_cast<int>(blockIdx.y) * WAVES + wave;
+    const int w0 = seg * wpw;
+    const int w1 = min(W, w0 + wpw);
+    Tri t{0, 0, 0, 0, 0, 0};
+    const uint32_t *bp = bits + i;
+    if (w0 < w1) {
+        uint32_t next = bp[static_cast<int64_t>(w0) * ld];
+        for (int wd = w0; wd < w1; ++wd) {
+            const uint32_t word = next;
+            if (wd + 1 < w1) next = bp[static_cast<int64_t>(wd + 1) * ld];
+            if constexpr (F32)
+                scan_word_f32<32>(t, word, ph32 + static_cast<int64_t>(wd) * 32);
+            else
+                scan_word_f64(t, word, ph64 + static_cast<int64_t>(wd) * 32);
+        }
+    }
+    if constexpr (WAVES > 1) {
+        __shared__ double sh[6][WAVES][64];
+        sh[0][wave][lane] = t.ar;
+        sh[1][wave][lane] = t.ai;
+        sh[2][wave][lane] = t.br;
+        sh[3][wave][lane] = t.bi;
+        sh[4][wave][lane] = t.qr;
+        sh[5][wave][lane] = t.qi;
+        __syncthreads();
+        if (wave != 0) return;
+#pragma unroll 1
+        for (int w = 1; w < WAVES; ++w) {
+            const Tri u{sh[0][w][lane], sh[1][w][lane], sh[2][w][lane],
+                        sh[3][w][lane], sh[4][w][lane], sh[5][w][lane]};
+            tri_append(t, u);
+        }
+    }
+    if (direct) {
+        if (i < np) store_fitness(fit, out_f64, i, t, C);
+    } else {
+        double *o = part + static_cast<int64_t>(blockIdx.y) * 6 * ld + i;
+        o[0 * ld] = t.ar;
+        o[1 * ld] = t.ai;
+        o[2 * ld] = t.br;
+        o[3 * ld] = t.bi;
+        o[4 * ld] = t.qr;
+        o[5 * ld] = t.qi;
+    }
+}
+
+__global__ __launch_bounds__(256) void fit_combine_kernel(const double *__restrict__ part, int gy, int64_t ld,
+                                                          int64_t np, const double *__restrict__ C,
+                                                          void *__restrict__ fit, int out_f64)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= np) return;
+    const double *p = part + i;
+    Tri t{p[0], p[ld], p[2 * ld], p[3 * ld], p[4 * ld], p[5 * ld]};
+    for (int s = 1; s < gy; ++s) {
+        const double *q = part + static_cast<int64_t>(s) * 6 * ld + i;
+        const Tri u{q[0], q[ld], q[2 * ld], q[3 * ld], q[4 * ld], q[5 * ld]};
+        tri_append(t, u);
+    }
+    store_fitness(fit, out_f64, i, t, C);
+}
+
+// The per-individual scheme: one lane walks its whole genome; no segment
+// triples, so B is not tracked.
+__global__ __launch_bounds__(128) void fit_per_genome_kernel(const uint32_t *__restrict__ bits, int64_t ld, int W,
+                                                             const double4 *__restrict__ ph64, int64_t np,
+                                                             const double *__restrict__ C, double *__restrict__ fit)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 128 + threadIdx.x;
+    if (i >= np) return;
+    double ar = 0, ai = 0, qr = 0, qi = 0;
+    for (int wd = 0; wd < W; ++wd) {
+        const uint32_t word = bits[static_cast<int64_t>(wd) * ld + i];
+        const double4 *p = ph64 + static_cast<int64_t>(wd) * 32;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            const double4 c = p[k];
+            const double s = sign64(word, k);
+            const double tr = fma(c.z, ar, -(c.w * ai));
+            const double ti = fma(c.z, ai, c.w * ar);
+            qr = fma(s, tr, qr);
+            qi = fma(s, ti, qi);
+            ar = fma(s, c.x, ar);
+            ai = fma(s, c.y, ai);
+        }
+    }
+    const double sr = qr + C[0], si = qi + C[1];
+    fit[i] = fma(sr, sr, si * si);
+}
+
+template <bool F32>
+static void launch_seg(const Design &d, const FitPlan &pl, const uint32_t *bits, int64_t np, int64_t ld,
+                       double *part, void *fit, int out_f64, hipStream_t s)
+{
+    const dim3 grid(static_cast<unsigned>((np + 63) / 64), static_cast<unsigned>(pl.gy));
+    const int direct = pl.gy == 1;
+    const int W = static_cast<int>(d.words);
+#define QPM_SEG_CASE(NW)                                                                                       \
+    case NW:                                                                                                   \
+        fit_seg_kernel<F32, NW><<<grid, dim3(NW * 64), 0, s>>>(bits, ld, W, d.ph64, d.ph32, pl.wpw, np, part, \
+                                                              d.Cdev, fit, direct, out_f64);                  \
+        break;
+    switch (pl.waves) {
+        QPM_SEG_CASE(1)
+        QPM_SEG_CASE(2)
+        QPM_SEG_CASE(4)
+        QPM_SEG_CASE(8)
+        QPM_SEG_CASE(16)
+    default: break;
+    }
+#undef QPM_SEG_CASE
+}
+
+FitPlan plan_fitness(const Design &d, qpm_prec p, int64_t np, int kernel)
+{
+    (void)p;
+    FitPlan pl;
+    if (kernel == QPM_FIT_PER_GENOME) {
+        pl.kind = QPM_FIT_PER_GENOME;
+        pl.gy = 1;
+        return pl;
+    }
+    pl.kind = QPM_FIT_SEGMENTED;
+    const int64_t groups = (np + 63) / 64;
+    const int64_t W = d.words;
+    // aim for ~8 waves per SIMD on 256 CUs x 4 SIMDs
+    const int64_t target_waves = 8192;
+    int64_t segs = (target_waves + groups - 1) / groups;
+    if (segs < 1) segs = 1;
+    int64_t wpw = (W + segs - 1) / segs;
+    if (wpw < 1) wpw = 1;
+    const int64_t nseg = (W + wpw - 1) / wpw;
+    int waves = 1;
+    while (waves < 16 && waves < nseg) waves *= 2;
+    pl.waves = waves;
+    pl.wpw = static_cast<int>(wpw);
+    pl.gy = static_cast<int>((nseg + waves - 1) / waves);
+    return pl;
+}
+
+size_t fitness_workspace_bytes(const FitPlan &pl, int64_t ld)
+{
+    if (pl.kind != QPM_FIT_SEGMENTED || pl.gy <= 1) return 0;
+    return sizeof(double) * 6 * static_cast<size_t>(pl.gy) * static_cast<size_t>(ld);
+}
+
+qpm_status launch_fitness(const Design &d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld, void *fit,
+                          const FitPlan &pl, double *part, hipStream_t s)
+{
+    const int out_f64 = (p == QPM_PREC_F64);
+    if (pl.kind == QPM_FIT_PER_GENOME) {
+        const unsigned blocks = static_cast<unsigned>((np + 127) / 128);
+        fit_per_genome_kernel<<<blocks, 128, 0, s>>>(bits, ld, static_cast<int>(d.words), d.ph64, np, d.Cdev,
+                                                     static_cast<double *>(fit));
+    } else {
+        if (p == QPM_PREC_F32)
+            launch_seg<true>(d, pl, bits, np, ld, part, fit, out_f64, s);
+        else
+            launch_seg<false>(d, pl, bits, np, ld, part, fit, out_f64, s);
+        if (pl.gy > 1) {
+            const unsigned blocks = static_cast<unsigned>((np + 255) / 256);
+            fit_combine_kernel<<<blocks, 256, 0, s>>>(part, pl.gy, ld, np, d.Cdev, fit, out_f64);
+        }
+    }
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
+}
+
+}  // namespace qpm
+
+using namespace qpm;
+
+QPM_API qpm_status qpm_eval_fitness(qpm_design d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                                    void *fitness, int32_t kernel, qpm_stream sv)
+{
+    clear_error();
+    QPM_REQUIRE(d && bits && fitness, QPM_EINVAL, "design, bits and fitness must not be NULL");
+    QPM_REQUIRE(p == QPM_PREC_F32 || p == QPM_PREC_F64, QPM_EINVAL, "unknown precision %d", (int)p);
+    QPM_REQUIRE(kernel == QPM_FIT_AUTO || kernel == QPM_FIT_SEGMENTED || kernel == QPM_FIT_PER_GENOME, QPM_EINVAL,
+                "unknown fitness kernel %d", (int)kernel);
+    QPM_REQUIRE(!(kernel == QPM_FIT_PER_GENOME && p != QPM_PREC_F64), QPM_EINVAL,
+                "the per-genome kernel computes in FP64 only");
+    QPM_REQUIRE(np >= 1, QPM_EINVAL, "np must be >= 1 (got %lld)", (long long)np);
+    QPM_REQUIRE(ld >= np && ld % 64 == 0, QPM_EINVAL, "ld (%lld) must be >= np (%lld) and a multiple of 64",
+                (long long)ld, (long long)np);
+    QPM_REQUIRE(np <= (int64_t(1) << 31) && d->words * ld <= (int64_t(1) << 40), QPM_ERANGE,
+                "population too large");
+    QPM_REQUIRE(aligned16(bits) || (reinterpret_cast<uintptr_t>(bits) & 3u) == 0, QPM_EINVAL,
+                "bits must be 4-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(sv);
+    const FitPlan pl = plan_fitness(*d, p, np, kernel);
+    const size_t wsb = fitness_workspace_bytes(pl, ld);
+    double *ws = nullptr;
+    if (wsb) QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&ws), wsb, s));
+    qpm_status st = launch_fitness(*d, p, bits, np, ld, fitness, pl, ws, s);
+    if (ws) {
+        hipError_t e = hipFreeAsync(ws, s);
+        if (st == QPM_OK && e != hipSuccess) {
+            set_error("hipFreeAsync failed: %s", hipGetErrorString(e));
+            st = QPM_EHIP;
+        }
+    }
+    return st;
+}

@@ -1,0 +1,362 @@
+// run.hip -- the HWSDA loop on the device (paper Sec. 3.2, steps 1-7).
+//
+// State: genes in two buffers with a per-individual flag naming the buffer
+// that holds the current row (selection flips a flag instead of copying a
+// row); fitness of the current rows; one bit buffer reused for the DE
+// trials and the GWO candidates; the leaders; a device generation counter
+// and a table of a_g. One generation is a fixed sequence of launches that
+// reads g from the counter, so it is captured once into a HIP graph and
+// replayed G times with no host work or synchronisation in between.
+#include <vector>
+
+#include "common.hpp"
+
+namespace qpm {
+
+__global__ void advance_kernel(uint32_t *gen) { gen[0] += 1u; }
+
+}  // namespace qpm
+
+using namespace qpm;
+
+struct qpm_run_s {
+    const Design *d = nullptr;
+    qpm_run_config cfg{};
+    hipStream_t st = nullptr;
+    int64_t D = 0, ldx = 0, ld = 0, W = 0;
+    float *buf[2] = {nullptr, nullptr};
+    uint32_t *flags = nullptr;
+    void *f_cur = nullptr;
+    void *f_new = nullptr;
+    uint32_t *tbits = nullptr;
+    int32_t *leaders = nullptr;
+    int32_t *best = nullptr;
+    uint32_t *gen = nullptr;
+    float *a_tab = nullptr;
+    double *fws = nullptr;
+    FitPlan plan;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t done = 0;
+    // per-step timing (qpm_run_set_timing)
+    bool timing = false;
+    hipEvent_t ev[QPM_K_COUNT + 1] = {};
+    double ms[QPM_K_COUNT] = {};
+    int64_t timed = 0;
+
+    bool f64() const { return cfg.prec == QPM_PREC_F64; }
+    PopView view() const { return PopView{buf[0], buf[1], flags, buf[0], buf[1], cfg.np, D, ldx}; }
+};
+
+static void release(qpm_run_s *r)
+{
+    if (!r) return;
+    if (r->st) (void)hipStreamSynchronize(r->st);
+    if (r->exec) (void)hipGraphExecDestroy(r->exec);
+    if (r->graph) (void)hipGraphDestroy(r->graph);
+    (void)hipFree(r->buf[0]);
+    (void)hipFree(r->buf[1]);
+    (void)hipFree(r->flags);
+    (void)hipFree(r->f_cur);
+    (void)hipFree(r->f_new);
+    (void)hipFree(r->tbits);
+    (void)hipFree(r->leaders);
+    (void)hipFree(r->best);
+    (void)hipFree(r->gen);
+    (void)hipFree(r->a_tab);
+    (void)hipFree(r->fws);
+    for (auto &e : r->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (r->st) (void)hipStreamDestroy(r->st);
+    delete r;
+}
+
+// steps 2-6 for the generation held in the device counter; with `ev`, an
+// event is recorded before each step and after the last
+static qpm_status enqueue_generation(qpm_run_s *r, hipEvent_t *ev = nullptr)
+{
+    const qpm_run_config &c = r->cfg;
+    const PopView pv = r->view();
+    const qpm_prec p = static_cast<qpm_prec>(c.prec);
+    auto mark = [&](int k) -> qpm_status {
+        if (ev) QPM_TRY_HIP(hipEventRecord(ev[k], r->st));
+        return QPM_OK;
+    };
+    qpm_status st;
+#define QPM_STEP(k, call)                         \
+    if ((st = mark(k)) != QPM_OK) return st;      \
+    if ((st = (call)) != QPM_OK) return st;
+    QPM_STEP(QPM_K_DE, launch_de(pv, c.F, c.CR, c.seed, r->gen, 0u, c.inst, r->tbits, r->ld, r->st))
+    QPM_STEP(QPM_K_FIT_DE, launch_fitness(*r->d, p, r->tbits, c.np, r->ld, r->f_new, r->plan, r->fws, r->st))
+    QPM_STEP(QPM_K_SELECT_DE, launch_select(r->f_cur, r->f_new, r->flags, c.np, nullptr, r->f64(), r->st))
+    QPM_STEP(QPM_K_TOP3, launch_top3(r->f_cur, c.np, r->f64(), r->leaders, r->st))
+    QPM_STEP(QPM_K_GWO, launch_gwo(pv, r->leaders, r->a_tab, 0.0f, c.seed, r->gen, 0u, c.inst, c.gwo_variant,
+                                   r->tbits, r->ld, r->st))
+    QPM_STEP(QPM_K_FIT_GWO, launch_fitness(*r->d, p, r->tbits, c.np, r->ld, r->f_new, r->plan, r->fws, r->st))
+    QPM_STEP(QPM_K_SELECT_GWO, launch_select(r->f_cur, r->f_new, r->flags, c.np, r->leaders, r->f64(), r->st))
+#undef QPM_STEP
+    if ((st = mark(QPM_K_ADVANCE)) != QPM_OK) return st;
+    advance_kernel<<<1, 1, 0, r->st>>>(r->gen);
+    QPM_TRY_HIP(hipGetLastError());
+    return mark(QPM_K_COUNT);
+}
+
+QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_stream sv, qpm_run_handle *out)
+{
+    clear_error();
+    QPM_REQUIRE(d && cfg && out, QPM_EINVAL, "design, cfg and out must not be NULL");
+    const qpm_run_config c = *cfg;
+    QPM_REQUIRE(c.np >= 4 && c.np <= (int64_t(1) << 24), QPM_EINVAL, "np must be in [4, 2^24] (got %lld)",
+                (long long)c.np);
+    QPM_REQUIRE(c.generations >= 1 && c.generations <= (int64_t(1) << 31) - 2, QPM_EINVAL,
+                "generations must be in [1, 2^31 - 2]");
+    QPM_REQUIRE(c.F >= 0.0f && c.F <= 2.0f, QPM_EINVAL, "F must be in [0, 2] (got %g)", (double)c.F);
+    QPM_REQUIRE(c.CR >= 0.0f && c.CR <= 1.0f, QPM_EINVAL, "CR must be in [0, 1] (got %g)", (double)c.CR);
+    QPM_REQUIRE(c.prec == QPM_PREC_F32 || c.prec == QPM_PREC_F64, QPM_EINVAL, "unknown precision %d", c.prec);
+    QPM_REQUIRE(c.gwo_variant == 0 || c.gwo_variant == 1, QPM_EINVAL, "gwo_variant must be 0 or 1");
+    QPM_REQUIRE(c.inst < (1u << 24), QPM_EINVAL, "inst must be < 2^24");
+    QPM_REQUIRE(c.fit_kernel == QPM_FIT_AUTO || c.fit_kernel == QPM_FIT_SEGMENTED ||
+                    c.fit_kernel == QPM_FIT_PER_GENOME,
+                QPM_EINVAL, "unknown fitness kernel %d", c.fit_kernel);
+    QPM_REQUIRE(!(c.fit_kernel == QPM_FIT_PER_GENOME && c.prec != QPM_PREC_F64), QPM_EINVAL,
+                "the per-genome kernel computes in FP64 only");
+    qpm_status st = check_device();
+    if (st != QPM_OK) return st;
+
+    auto *r = new qpm_run_s();
+    r->d = d;
+    r->cfg = c;
+    r->D = d->n;
+    r->ldx = ((r->D + 63) / 64) * 64;
+    r->ld = ((c.np + 63) / 64) * 64;
+    r->W = d->words;
+    r->plan = plan_fitness(*d, static_cast<qpm_prec>(c.prec), c.np, c.fit_kernel);
+    const size_t es = r->f64() ? sizeof(double) : sizeof(float);
+    const size_t gene_bytes = sizeof(float) * static_cast<size_t>(c.np) * static_cast<size_t>(r->ldx);
+    hipError_t e = hipStreamCreateWithFlags(&r->st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&r->buf[0], gene_bytes);
+    if (e == hipSuccess) e = hipMalloc(&r->buf[1], gene_bytes);
+    if (e == hipSuccess) e = hipMalloc(&r->flags, sizeof(uint32_t) * c.np);
+    if (e == hipSuccess) e = hipMalloc(&r->f_cur, es * c.np);
+    if (e == hipSuccess) e = hipMalloc(&r->f_new, es * c.np);
+    if (e == hipSuccess) e = hipMalloc(&r->tbits, sizeof(uint32_t) * r->W * r->ld);
+    if (e == hipSuccess) e = hipMalloc(&r->leaders, sizeof(int32_t) * 3);
+    if (e == hipSuccess) e = hipMalloc(&r->best, sizeof(int32_t) * 3);
+    if (e == hipSuccess) e = hipMalloc(&r->gen, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&r->a_tab, sizeof(float) * c.generations);
+    const size_t wsb = fitness_workspace_bytes(r->plan, r->ld);
+    if (e == hipSuccess && wsb) e = hipMalloc(&r->fws, wsb);
+    if (e != hipSuccess) {
+        set_error("run allocation failed: %s", hipGetErrorString(e));
+        release(r);
+        return e == hipErrorOutOfMemory ? QPM_ENOMEM : QPM_EHIP;
+    }
+    // a_g = 2 (1 - g / G): linear from 2 towards 0, evaluated in double
+    std::vector<float> a(c.generations);
+    for (int64_t g = 0; g < c.generations; ++g)
+        a[g] = static_cast<float>(2.0 * (1.0 - static_cast<double>(g) / static_cast<double>(c.generations)));
+
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, static_cast<hipStream_t>(sv));
+    if (e == hipSuccess) e = hipStreamWaitEvent(r->st, ev, 0);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->a_tab, a.data(), sizeof(float) * c.generations, hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess) e = hipMemsetAsync(r->flags, 0, sizeof(uint32_t) * c.np, r->st);
+    if (e == hipSuccess) e = hipMemsetAsync(r->gen, 0, sizeof(uint32_t), r->st);
+    if (e == hipSuccess) e = hipMemsetAsync(r->tbits, 0, sizeof(uint32_t) * r->W * r->ld, r->st);
+    if (e == hipSuccess) e = hipMemsetAsync(r->buf[1], 0, gene_bytes, r->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(r->st);  // a.data() must outlive the copy
+    if (ev) (void)hipEventDestroy(ev);
+    if (e != hipSuccess) {
+        set_error("run set-up failed: %s", hipGetErrorString(e));
+        release(r);
+        return QPM_EHIP;
+    }
+    // step 1: initialise, evaluate, leaders
+    const qpm_prec p = static_cast<qpm_prec>(c.prec);
+    st = launch_init(c.np, r->D, r->ldx, c.seed, c.inst, r->buf[0], r->tbits, r->ld, r->st);
+    if (st == QPM_OK) st = launch_fitness(*d, p, r->tbits, c.np, r->ld, r->f_cur, r->plan, r->fws, r->st);
+    if (st == QPM_OK) st = launch_top3(r->f_cur, c.np, r->f64(), r->leaders, r->st);
+    if (st == QPM_OK && c.use_graph) {
+        e = hipStreamBeginCapture(r->st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            set_error("hipStreamBeginCapture failed: %s", hipGetErrorString(e));
+            st = QPM_EHIP;
+        } else {
+            st = enqueue_generation(r);
+            hipError_t e2 = hipStreamEndCapture(r->st, &r->graph);
+            if (st == QPM_OK && e2 != hipSuccess) {
+                set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e2));
+                st = QPM_EHIP;
+            }
+            if (st == QPM_OK) {
+                e2 = hipGraphInstantiate(&r->exec, r->graph, nullptr, nullptr, 0);
+                if (e2 != hipSuccess) {
+                    set_error("hipGraphInstantiate failed: %s", hipGetErrorString(e2));
+                    st = QPM_EHIP;
+                }
+            }
+        }
+    }
+    if (st != QPM_OK) {
+        release(r);
+        return st;
+    }
+    *out = r;
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_run_advance(qpm_run_handle r, int64_t generations)
+{
+    clear_error();
+    QPM_REQUIRE(r != nullptr, QPM_EINVAL, "run is NULL");
+    QPM_REQUIRE(generations >= 0 && r->done + generations <= r->cfg.generations, QPM_EINVAL,
+                "advancing %lld generations would pass the configured %lld (done %lld)", (long long)generations,
+                (long long)r->cfg.generations, (long long)r->done);
+    for (int64_t g = 0; g < generations; ++g) {
+        if (r->timing) {
+            qpm_status st = enqueue_generation(r, r->ev);
+            if (st != QPM_OK) return st;
+            QPM_TRY_HIP(hipEventSynchronize(r->ev[QPM_K_COUNT]));
+            for (int k = 0; k < QPM_K_COUNT; ++k) {
+                float t = 0.0f;
+                QPM_TRY_HIP(hipEventElapsedTime(&t, r->ev[k], r->ev[k + 1]));
+                r->ms[k] += t;
+            }
+            ++r->timed;
+        } else if (r->exec) {
+            QPM_TRY_HIP(hipGraphLaunch(r->exec, r->st));
+        } else {
+            qpm_status st = enqueue_generation(r);
+            if (st != QPM_OK) return st;
+        }
+        ++r->done;
+    }
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_run_set_timing(qpm_run_handle r, int32_t enable)
+{
+    clear_error();
+    QPM_REQUIRE(r != nullptr, QPM_EINVAL, "run is NULL");
+    if (enable && !r->ev[0])
+        for (auto &e : r->ev) QPM_TRY_HIP(hipEventCreate(&e));
+    r->timing = enable != 0;
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_run_timing(qpm_run_handle r, double *ms, int64_t *generations, int32_t reset)
+{
+    clear_error();
+    QPM_REQUIRE(r != nullptr, QPM_EINVAL, "run is NULL");
+    if (ms)
+        for (int k = 0; k < QPM_K_COUNT; ++k) ms[k] = r->ms[k];
+    if (generations) *generations = r->timed;
+    if (reset) {
+        for (double &v : r->ms) v = 0.0;
+        r->timed = 0;
+    }
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_run_load(qpm_run_handle r, const float *x, int64_t ldx)
+{
+    clear_error();
+    QPM_REQUIRE(r != nullptr && x != nullptr, QPM_EINVAL, "run and x must not be NULL");
+    QPM_REQUIRE(ldx >= r->D, QPM_EINVAL, "ldx (%lld) must be >= D (%lld)", (long long)ldx, (long long)r->D);
+    const qpm_run_config &c = r->cfg;
+    QPM_TRY_HIP(hipMemcpy2DAsync(r->buf[0], sizeof(float) * r->ldx, x, sizeof(float) * ldx, sizeof(float) * r->D,
+                                 c.np, hipMemcpyDeviceToDevice, r->st));
+    QPM_TRY_HIP(hipMemsetAsync(r->flags, 0, sizeof(uint32_t) * c.np, r->st));
+    qpm_status st = launch_pack_pop(r->buf[0], c.np, r->D, r->ldx, r->tbits, r->ld, r->st);
+    if (st == QPM_OK)
+        st = launch_fitness(*r->d, static_cast<qpm_prec>(c.prec), r->tbits, c.np, r->ld, r->f_cur, r->plan, r->fws,
+                            r->st);
+    if (st == QPM_OK) st = launch_top3(r->f_cur, c.np, r->f64(), r->leaders, r->st);
+    return st;
+}
+
+QPM_API qpm_status qpm_run_read(qpm_run_handle r, float *x, int64_t ldx, void *fitness, int32_t *leaders,
+                                int64_t *generation)
+{
+    clear_error();
+    QPM_REQUIRE(r != nullptr, QPM_EINVAL, "run is NULL");
+    if (x) QPM_REQUIRE(ldx >= r->D, QPM_EINVAL, "ldx (%lld) must be >= D (%lld)", (long long)ldx, (long long)r->D);
+    const PopView pv = r->view();
+    if (x) {
+        qpm_status st = launch_gather(pv, nullptr, r->cfg.np, x, ldx, r->st);
+        if (st != QPM_OK) return st;
+    }
+    const size_t es = r->f64() ? sizeof(double) : sizeof(float);
+    if (fitness) QPM_TRY_HIP(hipMemcpyAsync(fitness, r->f_cur, es * r->cfg.np, hipMemcpyDeviceToDevice, r->st));
+    if (leaders) QPM_TRY_HIP(hipMemcpyAsync(leaders, r->leaders, sizeof(int32_t) * 3, hipMemcpyDeviceToHost, r->st));
+    QPM_TRY_HIP(hipStreamSynchronize(r->st));
+    if (generation) *generation = r->done;
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_run_best(qpm_run_handle r, float *best_x, uint32_t *best_bits, qpm_run_stats *stats)
+{
+    clear_error();
+    QPM_REQUIRE(r != nullptr, QPM_EINVAL, "run is NULL");
+    qpm_status st = launch_top3(r->f_cur, r->cfg.np, r->f64(), r->best, r->st);
+    if (st != QPM_OK) return st;
+    const PopView pv = r->view();
+    if (best_x) {
+        if ((st = launch_gather(pv, r->best, 1, best_x, r->D, r->st)) != QPM_OK) return st;
+        if (best_bits && (st = launch_pack_row(best_x, r->D, best_bits, r->st)) != QPM_OK) return st;
+    } else if (best_bits) {
+        float *tmp = nullptr;
+        QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&tmp), sizeof(float) * r->D, r->st));
+        st = launch_gather(pv, r->best, 1, tmp, r->D, r->st);
+        if (st == QPM_OK) st = launch_pack_row(tmp, r->D, best_bits, r->st);
+        (void)hipFreeAsync(tmp, r->st);
+        if (st != QPM_OK) return st;
+    }
+    int32_t bi[3] = {0, 0, 0};
+    QPM_TRY_HIP(hipMemcpyAsync(bi, r->best, sizeof(bi), hipMemcpyDeviceToHost, r->st));
+    QPM_TRY_HIP(hipStreamSynchronize(r->st));
+    if (stats) {
+        double bf = 0.0;
+        if (r->f64()) {
+            QPM_TRY_HIP(hipMemcpy(&bf, static_cast<double *>(r->f_cur) + bi[0], sizeof(double), hipMemcpyDeviceToHost));
+        } else {
+            float v = 0.0f;
+            QPM_TRY_HIP(hipMemcpy(&v, static_cast<float *>(r->f_cur) + bi[0], sizeof(float), hipMemcpyDeviceToHost));
+            bf = v;
+        }
+        stats->best_fitness = bf;
+        stats->best_index = bi[0];
+        stats->generations = r->done;
+        stats->fitness_evals = r->cfg.np + r->done * (2 * r->cfg.np - 3);
+        stats->domain_evals = static_cast<double>(stats->fitness_evals) * static_cast<double>(r->D);
+    }
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_run_destroy(qpm_run_handle r)
+{
+    clear_error();
+    release(r);
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_run(qpm_design d, const qpm_run_config *cfg, float *best_x, uint32_t *best_bits,
+                           qpm_run_stats *stats, qpm_stream s)
+{
+    qpm_run_handle r = nullptr;
+    qpm_status st = qpm_run_create(d, cfg, s, &r);
+    if (st != QPM_OK) return st;
+    st = qpm_run_advance(r, cfg->generations);
+    if (st == QPM_OK) st = qpm_run_best(r, best_x, best_bits, stats);
+    if (st == QPM_OK) {
+        // the caller's stream sees the outputs
+        hipError_t e = hipStreamSynchronize(r->st);
+        if (e != hipSuccess) {
+            set_error("run failed: %s", hipGetErrorString(e));
+            st = QPM_EHIP;
+        }
+    }
+    release(r);
+    return st;
+}

@@ -1,0 +1,280 @@
+"""Python binding of libqpm (include/qpm.h): the same entry points without the
+`qpm_` prefix. Argument marshalling only -- every step runs in the HIP
+library; there is no fallback path. Device buffers are torch CUDA tensors
+(PyTorch provides device memory and streams), host buffers numpy arrays.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqpm.so")
+
+PREC_F32 = 0
+PREC_F64 = 1
+FIT_AUTO = 0
+FIT_SEGMENTED = 1
+FIT_PER_GENOME = 2
+# timing slots of one generation (QPM_K_*)
+STEP_NAMES = ["de", "fitness_de", "select_de", "top3", "gwo", "fitness_gwo", "select_gwo", "advance"]
+
+_P = C.c_void_p
+_I64 = C.c_int64
+_I32 = C.c_int32
+_U32 = C.c_uint32
+_U64 = C.c_uint64
+_F = C.c_float
+_D = C.c_double
+
+
+class QpmError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("qpm error %d: %s" % (status, message))
+        self.status = status
+
+
+class RunConfig(C.Structure):
+    _fields_ = [("np", _I64), ("generations", _I64), ("F", _F), ("CR", _F), ("seed", _U64),
+                ("inst", _U32), ("prec", _I32), ("gwo_variant", _I32), ("use_graph", _I32),
+                ("fit_kernel", _I32)]
+
+
+class RunStats(C.Structure):
+    _fields_ = [("best_fitness", _D), ("best_index", _I64), ("generations", _I64),
+                ("fitness_evals", _I64), ("domain_evals", _D)]
+
+
+_lib = None
+
+_SIGS = {
+    "qpm_status_string": (C.c_char_p, [_I32]),
+    "qpm_last_error": (C.c_char_p, []),
+    "qpm_precompute_phases": (_I32, [_P, _I64, _D, _D, _P, C.POINTER(_P)]),
+    "qpm_design_free": (_I32, [_P]),
+    "qpm_design_info": (_I32, [_P, _P, _P]),
+    "qpm_design_read_phases": (_I32, [_P, _P, _P, _P]),
+    "qpm_eval_fitness": (_I32, [_P, _I32, _P, _I64, _I64, _P, _I32, _P]),
+    "qpm_init_population": (_I32, [_I64, _I64, _I64, _U64, _U32, _P, _P, _I64, _P]),
+    "qpm_de_step": (_I32, [_P, _I64, _I64, _I64, _F, _F, _U64, _U32, _U32, _P, _P, _I64, _P]),
+    "qpm_gwo_step": (_I32, [_P, _I64, _I64, _I64, _P, _F, _U64, _U32, _U32, _I32, _P, _P, _I64, _P]),
+    "qpm_run_create": (_I32, [_P, C.POINTER(RunConfig), _P, C.POINTER(_P)]),
+    "qpm_run_advance": (_I32, [_P, _I64]),
+    "qpm_run_read": (_I32, [_P, _P, _I64, _P, _P, _P]),
+    "qpm_run_best": (_I32, [_P, _P, _P, C.POINTER(RunStats)]),
+    "qpm_run_destroy": (_I32, [_P]),
+    "qpm_run_load": (_I32, [_P, _P, _I64]),
+    "qpm_run_set_timing": (_I32, [_P, _I32]),
+    "qpm_run_timing": (_I32, [_P, _P, _P, _I32]),
+    "qpm_run": (_I32, [_P, C.POINTER(RunConfig), _P, _P, C.POINTER(RunStats), _P]),
+}
+
+
+def lib():
+    """Load libqpm.so. Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libqpm.so is not built (expected at %s); run __graft_entry__.build()" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise QpmError(status, lib().qpm_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def words(n):
+    return (n + 31) // 32
+
+
+def ld_for(np_):
+    return max(64, ((np_ + 63) // 64) * 64)
+
+
+def ldx_for(D):
+    return ((D + 63) // 64) * 64
+
+
+class Design:
+    """A design: device tables of the per-domain integrals."""
+
+    def __init__(self, handle, n):
+        self._h = handle
+        self.n = n
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        n = C.c_int64()
+        Cc = (C.c_double * 2)()
+        _check(lib().qpm_design_info(self._h, C.byref(n), Cc))
+        return int(n.value), complex(Cc[0], Cc[1])
+
+    def read_phases(self):
+        a = np.zeros(2 * self.n)
+        b = np.zeros(2 * self.n)
+        c = np.zeros(2 * self.n)
+        _check(lib().qpm_design_read_phases(self._h, a.ctypes.data, b.ctypes.data, c.ctypes.data))
+        v = lambda t: t[0::2] + 1j * t[1::2]
+        return v(a), v(b), v(c)
+
+    def free(self):
+        if self._h is not None and _lib is not None:
+            _lib.qpm_design_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def precompute_phases(z, dk1, dk2, stream=None):
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    h = C.c_void_p()
+    _check(lib().qpm_precompute_phases(z.ctypes.data, len(z) - 1, float(dk1), float(dk2), _stream(stream),
+                                       C.byref(h)))
+    return Design(h, len(z) - 1)
+
+
+def eval_fitness(design, bits, np_, prec=PREC_F32, kernel=FIT_AUTO, out=None, stream=None):
+    """bits: int32 CUDA tensor (W, ld) -> fitness tensor (np_,) float32 / float64."""
+    import torch
+    if out is None:
+        out = torch.empty(np_, dtype=torch.float64 if prec == PREC_F64 else torch.float32, device=bits.device)
+    _check(lib().qpm_eval_fitness(design.handle, prec, _ptr(bits), np_, bits.shape[1], _ptr(out), kernel,
+                                  _stream(stream)))
+    return out
+
+
+def init_population(np_, D, seed, inst=0, ldx=None, device="cuda", stream=None):
+    import torch
+    ldx = ldx_for(D) if ldx is None else ldx
+    ld = ld_for(np_)
+    x = torch.zeros((np_, ldx), dtype=torch.float32, device=device)
+    bits = torch.zeros((words(D), ld), dtype=torch.int32, device=device)
+    _check(lib().qpm_init_population(np_, D, ldx, seed, inst, _ptr(x), _ptr(bits), ld, _stream(stream)))
+    return x, bits
+
+
+def de_step(x, D, F, CR, seed, generation, inst=0, stream=None):
+    """x: float32 CUDA tensor (np, ldx) -> (u, u_bits)."""
+    import torch
+    np_, ldx = x.shape
+    ld = ld_for(np_)
+    u = torch.zeros_like(x)
+    ub = torch.zeros((words(D), ld), dtype=torch.int32, device=x.device)
+    _check(lib().qpm_de_step(_ptr(x), np_, D, ldx, F, CR, seed, generation, inst, _ptr(u), _ptr(ub), ld,
+                             _stream(stream)))
+    return u, ub
+
+
+def gwo_step(x, D, leaders, a, seed, generation, inst=0, variant=0, stream=None):
+    """x: float32 CUDA tensor (np, ldx); leaders: int32 CUDA tensor (3,).
+    Returns (y, y_bits); leader rows of y are a copy of x, their bit
+    columns are left 0."""
+    import torch
+    np_, ldx = x.shape
+    ld = ld_for(np_)
+    y = x.clone()
+    yb = torch.zeros((words(D), ld), dtype=torch.int32, device=x.device)
+    _check(lib().qpm_gwo_step(_ptr(x), np_, D, ldx, _ptr(leaders), a, seed, generation, inst, variant, _ptr(y),
+                              _ptr(yb), ld, _stream(stream)))
+    return y, yb
+
+
+def _config(np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0, use_graph=1,
+            fit_kernel=FIT_AUTO):
+    return RunConfig(np=np_, generations=generations, F=F, CR=CR, seed=seed, inst=inst, prec=prec,
+                     gwo_variant=gwo_variant, use_graph=use_graph, fit_kernel=fit_kernel)
+
+
+class Run:
+    """A whole optimisation on the device (run_create / advance / read / best)."""
+
+    def __init__(self, design, np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0,
+                 use_graph=1, fit_kernel=FIT_AUTO, stream=None):
+        self.design = design
+        self.cfg = _config(np_, generations, F, CR, seed, inst, prec, gwo_variant, use_graph, fit_kernel)
+        self.D = design.n
+        h = C.c_void_p()
+        _check(lib().qpm_run_create(design.handle, C.byref(self.cfg), _stream(stream), C.byref(h)))
+        self._h = h
+
+    def advance(self, generations=1):
+        _check(lib().qpm_run_advance(self._h, generations))
+
+    def read(self, device="cuda"):
+        import torch
+        np_ = self.cfg.np
+        x = torch.empty((np_, self.D), dtype=torch.float32, device=device)
+        f = torch.empty(np_, dtype=torch.float64 if self.cfg.prec == PREC_F64 else torch.float32, device=device)
+        L = (C.c_int32 * 3)()
+        g = C.c_int64()
+        _check(lib().qpm_run_read(self._h, _ptr(x), self.D, _ptr(f), L, C.byref(g)))
+        return x, f, [L[0], L[1], L[2]], int(g.value)
+
+    def best(self, device="cuda"):
+        import torch
+        bx = torch.empty(self.D, dtype=torch.float32, device=device)
+        bb = torch.empty(words(self.D), dtype=torch.int32, device=device)
+        st = RunStats()
+        _check(lib().qpm_run_best(self._h, _ptr(bx), _ptr(bb), C.byref(st)))
+        return bx, bb, st
+
+    def load(self, x):
+        """x: float32 CUDA tensor (np, >= D) -> becomes the population."""
+        _check(lib().qpm_run_load(self._h, _ptr(x), x.shape[1]))
+
+    def set_timing(self, enable=True):
+        _check(lib().qpm_run_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self, reset=False):
+        """-> ({step name: total ms}, timed generations)."""
+        ms = (C.c_double * len(STEP_NAMES))()
+        g = C.c_int64()
+        _check(lib().qpm_run_timing(self._h, ms, C.byref(g), 1 if reset else 0))
+        return dict(zip(STEP_NAMES, list(ms))), int(g.value)
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.qpm_run_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def run(design, np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0, use_graph=1,
+        fit_kernel=FIT_AUTO, stream=None, device="cuda"):
+    import torch
+    cfg = _config(np_, generations, F, CR, seed, inst, prec, gwo_variant, use_graph, fit_kernel)
+    bx = torch.empty(design.n, dtype=torch.float32, device=device)
+    bb = torch.empty(words(design.n), dtype=torch.int32, device=device)
+    st = RunStats()
+    _check(lib().qpm_run(design.handle, C.byref(cfg), _ptr(bx), _ptr(bb), C.byref(st), _stream(stream)))
+    return bx, bb, st

@@ -1,0 +1,117 @@
+"""The C-ABI library loads, exports every entry point include/qpm.h declares,
+and rejects invalid arguments on the host before touching a device (these
+tests run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(inc, fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(qpm_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2511_01255_amd import qpm
+    return qpm.lib()
+
+
+def test_header_declares_the_core_entry_points():
+    names = _declared()
+    for n in ["qpm_precompute_phases", "qpm_eval_fitness", "qpm_de_step", "qpm_gwo_step", "qpm_run"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    for n in _declared():
+        assert hasattr(L, n), n
+
+
+def test_status_strings(L):
+    for code in range(0, -6, -1):
+        assert L.qpm_status_string(code)
+    assert L.qpm_status_string(-99) == b"unknown status"
+
+
+def _err(L):
+    return L.qpm_last_error().decode()
+
+
+def test_precompute_rejects_bad_boundaries(L):
+    h = C.c_void_p()
+    assert L.qpm_precompute_phases(None, 4, 0.1, 0.2, None, C.byref(h)) == -1
+    z = np.array([0.0, 1.0, 1.0, 2.0])
+    assert L.qpm_precompute_phases(z.ctypes.data, 3, 0.1, 0.2, None, C.byref(h)) == -1
+    assert "strictly increasing" in _err(L)
+    z = np.array([0.0, 1.0, np.nan])
+    assert L.qpm_precompute_phases(z.ctypes.data, 2, 0.1, 0.2, None, C.byref(h)) == -1
+    z = np.array([0.0, 1.0])
+    assert L.qpm_precompute_phases(z.ctypes.data, 1, float("inf"), 0.2, None, C.byref(h)) == -1
+    assert L.qpm_precompute_phases(z.ctypes.data, 0, 0.1, 0.2, None, C.byref(h)) == -1
+    assert L.qpm_precompute_phases(z.ctypes.data, 1 << 28, 0.1, 0.2, None, C.byref(h)) == -2
+    assert h.value is None  # nothing written on error
+
+
+def test_fitness_rejects_bad_arguments(L):
+    fake = C.c_void_p(0x10000)  # never dereferenced: validation fails first
+    assert L.qpm_eval_fitness(None, 0, fake, 4, 64, fake, 0, None) == -1
+    assert L.qpm_eval_fitness(fake, 7, fake, 4, 64, fake, 0, None) == -1
+    assert "precision" in _err(L)
+    assert L.qpm_eval_fitness(fake, 0, fake, 4, 64, fake, 2, None) == -1  # per-genome is FP64 only
+    assert L.qpm_eval_fitness(fake, 1, fake, 0, 64, fake, 0, None) == -1
+    assert L.qpm_eval_fitness(fake, 1, fake, 65, 64, fake, 0, None) == -1
+    assert L.qpm_eval_fitness(fake, 1, fake, 10, 96, fake, 0, None) == -1
+    assert "multiple of 64" in _err(L)
+    assert L.qpm_eval_fitness(fake, 1, fake, 10, 64, fake, 9, None) == -1
+
+
+def test_de_and_gwo_reject_bad_arguments(L):
+    x = C.c_void_p(0x10000)
+    u = C.c_void_p(0x20000000)
+    b = C.c_void_p(0x30000000)
+
+    def de(np_=8, D=10, ldx=12, F=0.5, CR=0.9, xx=x, uu=u, bb=b, ld=64):
+        return L.qpm_de_step(xx, np_, D, ldx, C.c_float(F), C.c_float(CR), 0, 0, 0, uu, bb, ld, None)
+
+    # every call below fails validation before any device work
+    assert de(np_=3) == -1 and "np >= 4" in _err(L)
+    assert de(F=2.5) == -1 and "F must be" in _err(L)
+    assert de(CR=-0.1) == -1
+    assert de(ldx=10) == -1 and "ldx" in _err(L)
+    assert de(ld=32) == -1
+    assert de(xx=C.c_void_p(0x10004)) == -1 and "aligned" in _err(L)
+    assert de(uu=x) == -1 and "overlap" in _err(L)
+    assert de(bb=None) == -1
+
+    def gwo(np_=8, D=10, ldx=12, a=1.0, variant=0, leaders=C.c_void_p(0x40000000)):
+        return L.qpm_gwo_step(x, np_, D, ldx, leaders, C.c_float(a), 0, 0, 0, variant, u, b, 64, None)
+
+    assert gwo(np_=3) == -1
+    assert gwo(a=-1.0) == -1
+    assert gwo(variant=2) == -1
+    assert gwo(leaders=None) == -1
+
+
+def test_run_rejects_bad_config(L):
+    from paper_2511_01255_amd import qpm
+    fake = C.c_void_p(0x10000)
+    h = C.c_void_p()
+    for kw in [dict(np_=3, generations=10), dict(np_=8, generations=0), dict(np_=8, generations=5, F=3.0),
+               dict(np_=8, generations=5, CR=2.0), dict(np_=8, generations=5, prec=5),
+               dict(np_=8, generations=5, gwo_variant=3)]:
+        cfg = qpm._config(**kw)
+        assert L.qpm_run_create(fake, C.byref(cfg), None, C.byref(h)) == -1
+    assert h.value is None
+    assert L.qpm_run_advance(None, 1) == -1
