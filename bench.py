@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--cpu-generations", type=int, default=6,
                     help="generations of the CPU oracle sample (0 = skip)")
     ap.add_argument("--no-extras", action="store_true", help="only the timed generations")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first copy a 512 MiB buffer three times (byte calibration of memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -86,6 +88,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
+
+    if args.calib_copy:
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     z = inputs.uniform_boundaries(N_DOMAINS, WIDTH)
     d = inputs.fitness_population(NP, N_DOMAINS, WIDTH, 32, seed=1)

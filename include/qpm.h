@@ -120,6 +120,17 @@ qpm_status qpm_eval_fitness(qpm_design d, qpm_prec p, const uint32_t *bits, int6
                             int64_t ld, void *fitness, int32_t kernel, qpm_stream s);
 
 /*
+ * qpm_eval_fitness_shape -- qpm_eval_fitness with the segmented kernel's
+ * launch shape given explicitly (for tuning): waves_per_group in
+ * {1, 2, 4, 8, 16} waves of 64 genomes share one workgroup and scan
+ * consecutive segments of words_per_wave >= 1 bit words each. The result
+ * equals qpm_eval_fitness up to the summation order of the segments.
+ */
+qpm_status qpm_eval_fitness_shape(qpm_design d, qpm_prec p, const uint32_t *bits, int64_t np,
+                                  int64_t ld, void *fitness, int32_t waves_per_group,
+                                  int32_t words_per_wave, qpm_stream s);
+
+/*
  * qpm_init_population -- DE step 1 (paper Sec. 2.2.1): x_ij uniform on
  * [-1, 1) (Philox stream INIT, counter (j / 4, i, 0, inst << 8 | 1), word
  * j % 4, value (u >> 8) 2^-23 - 1), and the +-1 bits of every row.
@@ -165,6 +176,32 @@ qpm_status qpm_gwo_step(const float *x, int64_t np, int64_t D, int64_t ldx,
                         const int32_t *leaders, float a, uint64_t seed, uint32_t generation,
                         uint32_t inst, int32_t variant, float *y, uint32_t *y_bits, int64_t ld,
                         qpm_stream s);
+
+/*
+ * qpm_relax_forward -- the relaxation d = tanh(theta) of a design (not in
+ * the paper; it extends the d_eff double integral of Sec. 2.1 to real d):
+ *   S = sum_{m<n} d_m d_n a_m b_n + sum_n d_n^2 c_n,  f = |S|^2,
+ * which equals the +-1 fitness where |theta| is large. theta: device,
+ * B x ldt floats (row b holds theta_{b,0..N-1}); f: device B floats and/or
+ * S: device B x 2 doubles (re, im); either may be NULL, not both.
+ * prec selects FP32 (per-segment scans in FP32, segments combined in FP64)
+ * or FP64. Temporary device memory comes from the stream-ordered
+ * allocator of s.
+ */
+qpm_status qpm_relax_forward(qpm_design d, qpm_prec p, const float *theta, int64_t B, int64_t ldt,
+                             float *f, double *S, qpm_stream s);
+
+/*
+ * qpm_relax_backward -- the adjoint of qpm_relax_forward:
+ *   grad_theta_{b,k} = grad_f_b 2 Re(conj(S_b) dS_b/dd_k) (1 - d_k^2),
+ *   dS/dd_k = b_k P_{k-1} + a_k R_{k+1} + 2 c_k d_k,
+ * with P_{k-1} = sum_{m<k} d_m a_m and R_{k+1} = sum_{n>k} d_n b_n.
+ * S: device B x 2 doubles saved from the forward call; grad_f: device B
+ * floats; grad_theta: device B x ldg floats.
+ */
+qpm_status qpm_relax_backward(qpm_design d, qpm_prec p, const float *theta, int64_t B, int64_t ldt,
+                              const double *S, const float *grad_f, float *grad_theta, int64_t ldg,
+                              qpm_stream s);
 
 /* Configuration of a whole optimisation (paper Sec. 3.2, steps 1-7). */
 typedef struct {
@@ -228,17 +265,18 @@ qpm_status qpm_run_best(qpm_run_handle r, float *best_x, uint32_t *best_bits, qp
  */
 qpm_status qpm_run_load(qpm_run_handle r, const float *x, int64_t ldx);
 
-/* Kernels of one generation, in launch order (timing slots). */
+/* Steps of one generation, in launch order (timing slots): the DE trials,
+ * their evaluation, its finish (segment combine + selection + leaders),
+ * the grey-wolf candidates, their evaluation, its finish (combine +
+ * selection + next generation's DE draws + generation advance). */
 enum {
     QPM_K_DE = 0,
     QPM_K_FIT_DE = 1,
-    QPM_K_SELECT_DE = 2,
-    QPM_K_TOP3 = 3,
-    QPM_K_GWO = 4,
-    QPM_K_FIT_GWO = 5,
-    QPM_K_SELECT_GWO = 6,
-    QPM_K_ADVANCE = 7,
-    QPM_K_COUNT = 8
+    QPM_K_FINISH_DE = 2,
+    QPM_K_GWO = 3,
+    QPM_K_FIT_GWO = 4,
+    QPM_K_FINISH_GWO = 5,
+    QPM_K_COUNT = 6
 };
 
 /*

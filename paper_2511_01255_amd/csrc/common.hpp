@@ -67,6 +67,18 @@ FitPlan plan_fitness(const Design &d, qpm_prec p, int64_t np, int kernel);
 size_t fitness_workspace_bytes(const FitPlan &plan, int64_t ld);
 qpm_status launch_fitness(const Design &d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
                           void *fitness, const FitPlan &plan, double *workspace, hipStream_t s);
+// the segment triples only (6 x max(gy, 1) x ld doubles), for the fused
+// finish step of a run
+size_t fitness_partials_bytes(const FitPlan &plan, int64_t ld);
+qpm_status launch_fitness_partials(const Design &d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                                   const FitPlan &plan, double *part, hipStream_t s);
+// Finish one evaluation of a run: combine the triples of genome i into f,
+// select (f > f_cur[i] replaces, leaders in skip3 excluded), then in the
+// last workgroup: top3_out <- leaders (when non-null); with draws_next the
+// DE draws of generation gen + 1 are written and gen is advanced.
+qpm_status launch_finish(const double *part, int gy, int64_t ld, int64_t np, const double *C, void *f_cur,
+                         bool f64, uint32_t *flags, const int32_t *skip3, int32_t *top3_out, int4 *draws_next,
+                         uint32_t *gen, int64_t D, uint64_t seed, uint32_t inst, uint32_t *ticket, hipStream_t s);
 
 // ---------------------------------------------------------------- evolution kernels
 
@@ -84,8 +96,13 @@ struct PopView {
 
 qpm_status launch_init(int64_t np, int64_t D, int64_t ldx, uint64_t seed, uint32_t inst, float *x,
                        uint32_t *bits, int64_t ld, hipStream_t s);
+// draws: device scratch of np int4 (donors r1, r2, r3 and jrand)
 qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const uint32_t *gen_dev,
-                     uint32_t gen, uint32_t inst, uint32_t *bits, int64_t ld, hipStream_t s);
+                     uint32_t gen, uint32_t inst, uint32_t *bits, int64_t ld, int4 *draws, bool compute_draws,
+                     hipStream_t s);
+// DE draws of generation *gen_dev for every individual
+qpm_status launch_draws(int64_t np, int64_t D, uint64_t seed, const uint32_t *gen_dev, uint32_t inst, int4 *draws,
+                        hipStream_t s);
 qpm_status launch_gwo(const PopView &pv, const int32_t *leaders, const float *a_tab, float a,
                       uint64_t seed, const uint32_t *gen_dev, uint32_t gen, uint32_t inst,
                       int variant, uint32_t *bits, int64_t ld, hipStream_t s);

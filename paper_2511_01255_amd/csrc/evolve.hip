@@ -19,7 +19,7 @@
 #include <vector>
 
 #include "common.hpp"
-#include "philox.hpp"
+#include "device_common.hpp"
 
 namespace qpm {
 
@@ -36,6 +36,18 @@ __device__ __forceinline__ float *out_row_of(const PopView &pv, int64_t r)
 }
 
 __device__ __forceinline__ float clamp1(float v) { return fminf(fmaxf(v, -1.0f), 1.0f); }
+
+// x / 3 correctly rounded, without a division: q0 = x RN(1/3), the exact
+// remainder r = x - 3 q0 by FMA, one FMA correction, and the sign of x
+// restored (only -0 would otherwise come out as +0). Checked against IEEE
+// division for every finite binary32 input.
+__device__ __forceinline__ float div3(float x)
+{
+    const float c = 0x1.555556p-2f;  // RN(1/3)
+    const float q0 = x * c;
+    const float r = fmaf(-q0, 3.0f, x);
+    return copysignf(fmaf(r, c, q0), x);
+}
 
 __device__ __forceinline__ void store_quad(float *dst, int64_t j0, int64_t D, float4 v)
 {
@@ -76,8 +88,8 @@ __device__ __forceinline__ void store_word(uint32_t nib, int64_t q, bool valid, 
 __global__ __launch_bounds__(256) void init_kernel(int64_t D, int64_t ldx, uint32_t k0, uint32_t k1, uint32_t inst,
                                                    float *__restrict__ x, uint32_t *__restrict__ bits, int64_t ld)
 {
-    const int64_t i = blockIdx.y;
-    const int64_t q = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t i = blockIdx.x;
+    const int64_t q = static_cast<int64_t>(blockIdx.y) * 256 + threadIdx.x;
     const int64_t j0 = 4 * q;
     const bool valid = j0 < D;
     uint32_t nib = 0;
@@ -92,57 +104,68 @@ __global__ __launch_bounds__(256) void init_kernel(int64_t D, int64_t ldx, uint3
 
 // ------------------------------------------------------------ DE rand/1 + binomial crossover
 
-__global__ __launch_bounds__(256) void de_kernel(PopView pv, float F, float CR, uint32_t k0, uint32_t k1,
-                                                 const uint32_t *__restrict__ gen_dev, uint32_t gen_c, uint32_t inst,
-                                                 uint32_t *__restrict__ bits, int64_t ld)
+// One draw per individual and generation, shared by every gene chunk.
+__global__ __launch_bounds__(256) void de_draws_kernel(int64_t np, int64_t D, uint32_t k0, uint32_t k1,
+                                                       const uint32_t *__restrict__ gen_dev, uint32_t gen_c,
+                                                       uint32_t inst, int4 *__restrict__ draws)
 {
-    const int64_t i = blockIdx.y;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= np) return;
     const uint32_t g = gen_dev ? gen_dev[0] : gen_c;
-    const uint32_t c3 = inst << 8;
-    const int64_t np = pv.np, D = pv.D;
+    draws[i] = de_draw(i, np, D, g, inst, k0, k1);
+}
 
-    // donors: three distinct indices != i, each the k-th index not yet
-    // excluded (exclusions applied in ascending order), and jrand
-    const U4 o = philox10(0u, static_cast<uint32_t>(i), g, c3 | kTagDeIdx, k0, k1);
-    int64_t r1 = bounded(o.x, static_cast<uint32_t>(np - 1));
-    if (r1 >= i) ++r1;
-    int64_t r2 = bounded(o.y, static_cast<uint32_t>(np - 2));
-    {
-        const int64_t lo = i < r1 ? i : r1, hi = i < r1 ? r1 : i;
-        if (r2 >= lo) ++r2;
-        if (r2 >= hi) ++r2;
-    }
-    int64_t r3 = bounded(o.z, static_cast<uint32_t>(np - 3));
-    {
-        int64_t e0 = i, e1 = r1, e2 = r2, t;
-        if (e0 > e1) { t = e0; e0 = e1; e1 = t; }
-        if (e1 > e2) { t = e1; e1 = e2; e2 = t; }
-        if (e0 > e1) { t = e0; e0 = e1; e1 = t; }
-        if (r3 >= e0) ++r3;
-        if (r3 >= e1) ++r3;
-        if (r3 >= e2) ++r3;
-    }
-    const int64_t jrand = bounded(o.w, static_cast<uint32_t>(D));
-
-    const int64_t q = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    const int64_t j0 = 4 * q;
-    const bool valid = j0 < D;
+// Work split: a lane moves one gene quad (float4). A chunk is CW = 256 /
+// IPW genes; one wave covers IPW individuals of a chunk (64 / IPW lanes
+// each) and a 256-lane workgroup covers 4 IPW consecutive individuals.
+// Chunks are dealt to the eight XCDs round-robin (workgroup id mod 8 =
+// XCD) and every XCD walks its chunks in order over all individuals, so
+// while it works on a chunk that slice of the whole population
+// (np x CW x 4 bytes, chosen <= 2 MB) stays in the XCD's L2 and the random
+// donor rows hit it.
+template <int IPW>
+__global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restrict__ draws, float F, float CR,
+                                                 uint32_t k0, uint32_t k1, const uint32_t *__restrict__ gen_dev,
+                                                 uint32_t gen_c, uint32_t inst, uint32_t *__restrict__ bits,
+                                                 int64_t ld, int groups, int chunks)
+{
+    constexpr int LPI = 64 / IPW;  // lanes per individual
+    constexpr int CW = 4 * LPI;    // genes per chunk
+    constexpr int WPC = CW / 32;   // bit words per chunk and individual
+    constexpr int IPG = 4 * IPW;   // individuals per workgroup
+    const uint32_t b = blockIdx.x;
+    const int xcd = static_cast<int>(b & 7u);
+    const int k = static_cast<int>(b >> 3);
+    const int gi = k % groups;
+    const int c = xcd + 8 * (k / groups);
+    if (c >= chunks) return;
+    const int t = threadIdx.x;
+    const int local = t / LPI;  // individual within the workgroup
+    const int li = t % LPI;     // lane within the individual
+    const int64_t D = pv.D, np = pv.np;
+    const int64_t i = static_cast<int64_t>(gi) * IPG + local;
+    const int64_t j0 = static_cast<int64_t>(c) * CW + 4 * li;
+    const bool active = i < np && j0 < D;
+    const uint32_t g = gen_dev ? gen_dev[0] : gen_c;
+    __shared__ uint32_t wsh[IPG][WPC];
     uint32_t nib = 0;
-    if (valid) {
+    if (active) {
+        const int4 dr = draws[i];
         const float4 xv = *reinterpret_cast<const float4 *>(row_of(pv, i) + j0);
-        const float4 a = *reinterpret_cast<const float4 *>(row_of(pv, r1) + j0);
-        const float4 b = *reinterpret_cast<const float4 *>(row_of(pv, r2) + j0);
-        const float4 c = *reinterpret_cast<const float4 *>(row_of(pv, r3) + j0);
-        const U4 r = philox10(static_cast<uint32_t>(q), static_cast<uint32_t>(i), g, c3 | kTagDeCr, k0, k1);
+        const float4 a = *reinterpret_cast<const float4 *>(row_of(pv, dr.x) + j0);
+        const float4 bq = *reinterpret_cast<const float4 *>(row_of(pv, dr.y) + j0);
+        const float4 cq = *reinterpret_cast<const float4 *>(row_of(pv, dr.z) + j0);
+        const U4 r = philox10(static_cast<uint32_t>(j0 >> 2), static_cast<uint32_t>(i), g, (inst << 8) | kTagDeCr,
+                              k0, k1);
         const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
         const float as[4] = {a.x, a.y, a.z, a.w};
-        const float bs[4] = {b.x, b.y, b.z, b.w};
-        const float cs[4] = {c.x, c.y, c.z, c.w};
-        const uint32_t rs[4] = {r.x, r.y, r.z, r.w};
+        const float bs[4] = {bq.x, bq.y, bq.z, bq.w};
+        const float cs[4] = {cq.x, cq.y, cq.z, cq.w};
+        const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
         float us[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const bool take = (unit24(rs[e]) <= CR) || (j0 + e == jrand);
+            const bool take = (unit24(rw[e]) <= CR) || (j0 + e == dr.w);
             const float v = clamp1(fmaf(F, bs[e] - cs[e], as[e]));
             us[e] = take ? v : xs[e];
         }
@@ -150,7 +173,21 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, float F, float CR, 
         store_quad(out_row_of(pv, i), j0, D, uv);
         nib = quad_nibble(uv, j0, D);
     }
-    store_word(nib, q, valid, bits, ld, i);
+    // merge the nibbles of 8 neighbouring lanes (32 genes) into one word
+    uint32_t w = nib << (4 * (t & 7));
+    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 1));
+    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 2));
+    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 4));
+    if ((t & 7) == 0) wsh[local][li >> 3] = w;
+    __syncthreads();
+    // the IPG consecutive individuals of this workgroup share each bit row:
+    // one contiguous store of IPG words per chunk word
+    if (t < IPG * WPC) {
+        const int wd = t / IPG, ii = t % IPG;
+        const int64_t row = static_cast<int64_t>(gi) * IPG + ii;
+        const int64_t wg = static_cast<int64_t>(c) * WPC + wd;
+        if (row < np && wg * 32 < D) bits[wg * ld + row] = wsh[ii][wd];
+    }
 }
 
 // ------------------------------------------------------------ grey-wolf update
@@ -160,7 +197,7 @@ __global__ __launch_bounds__(256) void gwo_kernel(PopView pv, const int32_t *__r
                                                   const uint32_t *__restrict__ gen_dev, uint32_t gen_c, uint32_t inst,
                                                   int variant, uint32_t *__restrict__ bits, int64_t ld)
 {
-    const int64_t i = blockIdx.y;
+    const int64_t i = blockIdx.x;
     const int64_t L0 = leaders[0], L1 = leaders[1], L2 = leaders[2];
     const int64_t np = pv.np, D = pv.D;
     // leaders keep their positions; indices outside the population make
@@ -172,7 +209,7 @@ __global__ __launch_bounds__(256) void gwo_kernel(PopView pv, const int32_t *__r
     const float two_a = 2.0f * a;
     const uint32_t c3 = (inst << 8) | kTagGwo;
 
-    const int64_t q = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t q = static_cast<int64_t>(blockIdx.y) * 256 + threadIdx.x;
     const int64_t j0 = 4 * q;
     const bool valid = j0 < D;
     uint32_t nib = 0;
@@ -197,19 +234,21 @@ __global__ __launch_bounds__(256) void gwo_kernel(PopView pv, const int32_t *__r
             for (int k = 0; k < 3; ++k) {
                 const uint32_t o = wrd[3 * e + k];
                 const float r1 = static_cast<float>(o & 0xFFFFu) * 0x1p-16f;
-                const float r2 = static_cast<float>(o >> 16) * 0x1p-16f;
                 const float A = fmaf(two_a, r1, -a);
-                const float Cc = 2.0f * r2;
+                const float Cc = static_cast<float>(o >> 16) * 0x1p-15f;  // = 2 r2, exactly
                 const float Dk = fabsf(fmaf(Cc, Xs[k][e], -xs[e]));
                 Y[k] = fmaf(-A, Dk, Xs[k][e]);
             }
             float yv;
             if (variant == 1) {
-                yv = ((Y[0] + Y[1]) + Y[2]) / 3.0f;
+                yv = div3((Y[0] + Y[1]) + Y[2]);
             } else {
                 const float s = (fabsf(Y[0]) + fabsf(Y[1])) + fabsf(Y[2]);
                 const float num = fmaf(fabsf(Y[2]), Y[2], fmaf(fabsf(Y[1]), Y[1], fabsf(Y[0]) * Y[0]));
-                yv = (s == 0.0f) ? 0.0f : (num / s) / 3.0f;
+                // evaluated unconditionally (no divergent branch); the 0/0 of
+                // s == 0 is selected away
+                const float qv = div3(num / s);
+                yv = (s == 0.0f) ? 0.0f : qv;
             }
             ys[e] = clamp1(yv);
         }
@@ -240,74 +279,9 @@ __global__ __launch_bounds__(256) void select_kernel(T *__restrict__ f, const T 
 // ------------------------------------------------------------ top-3
 
 template <typename T>
-struct Top3 {
-    T v[3];
-    int i[3];
-};
-
-template <typename T>
-__device__ __forceinline__ bool ahead(T va, int ia, T vb, int ib)
-{
-    return va > vb || (va == vb && ia < ib);
-}
-
-template <typename T>
-__device__ __forceinline__ void top3_insert(Top3<T> &t, T v, int idx)
-{
-    if (ahead(v, idx, t.v[0], t.i[0])) {
-        t.v[2] = t.v[1]; t.i[2] = t.i[1];
-        t.v[1] = t.v[0]; t.i[1] = t.i[0];
-        t.v[0] = v; t.i[0] = idx;
-    } else if (ahead(v, idx, t.v[1], t.i[1])) {
-        t.v[2] = t.v[1]; t.i[2] = t.i[1];
-        t.v[1] = v; t.i[1] = idx;
-    } else if (ahead(v, idx, t.v[2], t.i[2])) {
-        t.v[2] = v; t.i[2] = idx;
-    }
-}
-
-// One workgroup of 1024 lanes. (f descending, slot ascending) is a strict
-// total order, so the three best are unique whatever the merge order.
-template <typename T>
 __global__ __launch_bounds__(1024) void top3_kernel(const T *__restrict__ f, int64_t np, int32_t *__restrict__ out)
 {
-    Top3<T> t;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        t.v[k] = -INFINITY;
-        t.i[k] = INT_MAX;
-    }
-    for (int64_t i = threadIdx.x; i < np; i += 1024) top3_insert(t, f[i], static_cast<int>(i));
-    for (int off = 32; off >= 1; off >>= 1) {
-        T ov[3];
-        int oi[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            ov[k] = __shfl_xor(t.v[k], off);
-            oi[k] = __shfl_xor(t.i[k], off);
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) top3_insert(t, ov[k], oi[k]);
-    }
-    __shared__ T sv[16][3];
-    __shared__ int si[16][3];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            sv[wave][k] = t.v[k];
-            si[wave][k] = t.i[k];
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        Top3<T> r = t;
-        for (int w = 1; w < 16; ++w)
-            for (int k = 0; k < 3; ++k) top3_insert(r, sv[w][k], si[w][k]);
-        out[0] = r.i[0];
-        out[1] = r.i[1];
-        out[2] = r.i[2];
-    }
+    block_top3<T, 1024>(f, np, out);
 }
 
 // ------------------------------------------------------------ gather / pack
@@ -325,8 +299,8 @@ __global__ __launch_bounds__(256) void gather_kernel(PopView pv, const int32_t *
 __global__ __launch_bounds__(256) void pack_pop_kernel(const float *__restrict__ x, int64_t D, int64_t ldx,
                                                        uint32_t *__restrict__ bits, int64_t ld)
 {
-    const int64_t i = blockIdx.y;
-    const int64_t q = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t i = blockIdx.x;
+    const int64_t q = static_cast<int64_t>(blockIdx.y) * 256 + threadIdx.x;
     const int64_t j0 = 4 * q;
     const bool valid = j0 < D;
     uint32_t nib = 0;
@@ -349,10 +323,14 @@ __global__ __launch_bounds__(256) void pack_row_kernel(const float *__restrict__
 
 // ------------------------------------------------------------ launchers
 
+// x = individual (fastest in dispatch order), y = 1024-gene chunk: all
+// individuals of one chunk run before the next chunk, so the random donor
+// rows of DE hit the caches (one chunk of the whole population is
+// np x 4 KB) instead of streaming the population from HBM three times.
 static dim3 quad_grid(int64_t D, int64_t rows)
 {
     const int64_t quads = (D + 3) / 4;
-    return dim3(static_cast<unsigned>((quads + 255) / 256), static_cast<unsigned>(rows));
+    return dim3(static_cast<unsigned>(rows), static_cast<unsigned>((quads + 255) / 256));
 }
 
 qpm_status launch_init(int64_t np, int64_t D, int64_t ldx, uint64_t seed, uint32_t inst, float *x, uint32_t *bits,
@@ -365,10 +343,28 @@ qpm_status launch_init(int64_t np, int64_t D, int64_t ldx, uint64_t seed, uint32
 }
 
 qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const uint32_t *gen_dev, uint32_t gen,
-                     uint32_t inst, uint32_t *bits, int64_t ld, hipStream_t s)
+                     uint32_t inst, uint32_t *bits, int64_t ld, int4 *draws, bool compute_draws, hipStream_t s)
 {
-    de_kernel<<<quad_grid(pv.D, pv.np), 256, 0, s>>>(pv, F, CR, static_cast<uint32_t>(seed),
-                                                     static_cast<uint32_t>(seed >> 32), gen_dev, gen, inst, bits, ld);
+    const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
+    if (compute_draws)
+        de_draws_kernel<<<static_cast<unsigned>((pv.np + 255) / 256), 256, 0, s>>>(pv.np, pv.D, k0, k1, gen_dev,
+                                                                                   gen, inst, draws);
+    // individuals per wave so that one chunk of the population fits in 2 MB
+    const int64_t row_bytes = 2 * 1024 * 1024 / pv.np;
+    const int ipw = row_bytes >= 1024 ? 1 : (row_bytes >= 512 ? 2 : 4);
+    const int64_t cw = 256 / ipw;
+    const int64_t chunks = (pv.D + cw - 1) / cw;
+    const int64_t groups = (pv.np + 4 * ipw - 1) / (4 * ipw);
+    const int64_t blocks = 8 * ((chunks + 7) / 8) * groups;
+    QPM_REQUIRE(blocks < (int64_t(1) << 31), QPM_ERANGE, "population too large for one DE launch");
+    const int gr = static_cast<int>(groups), ch = static_cast<int>(chunks);
+    const unsigned nb = static_cast<unsigned>(blocks);
+    if (ipw == 1)
+        de_kernel<1><<<nb, 256, 0, s>>>(pv, draws, F, CR, k0, k1, gen_dev, gen, inst, bits, ld, gr, ch);
+    else if (ipw == 2)
+        de_kernel<2><<<nb, 256, 0, s>>>(pv, draws, F, CR, k0, k1, gen_dev, gen, inst, bits, ld, gr, ch);
+    else
+        de_kernel<4><<<nb, 256, 0, s>>>(pv, draws, F, CR, k0, k1, gen_dev, gen, inst, bits, ld, gr, ch);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }
@@ -422,6 +418,15 @@ qpm_status launch_pack_pop(const float *x, int64_t np, int64_t D, int64_t ldx, u
                            hipStream_t s)
 {
     pack_pop_kernel<<<quad_grid(D, np), 256, 0, s>>>(x, D, ldx, bits, ld);
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
+}
+
+qpm_status launch_draws(int64_t np, int64_t D, uint64_t seed, const uint32_t *gen_dev, uint32_t inst, int4 *draws,
+                        hipStream_t s)
+{
+    de_draws_kernel<<<static_cast<unsigned>((np + 255) / 256), 256, 0, s>>>(
+        np, D, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), gen_dev, 0u, inst, draws);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }
@@ -493,7 +498,12 @@ QPM_API qpm_status qpm_de_step(const float *x, int64_t np, int64_t D, int64_t ld
     const size_t bytes = sizeof(float) * static_cast<size_t>(np) * static_cast<size_t>(ldx);
     QPM_REQUIRE(!overlaps(x, bytes, u, bytes), QPM_EINVAL, "x and u must not overlap");
     const PopView pv{x, x, nullptr, u, u, np, D, ldx};
-    return launch_de(pv, F, CR, seed, nullptr, generation, inst, u_bits, ld, static_cast<hipStream_t>(sv));
+    hipStream_t s = static_cast<hipStream_t>(sv);
+    int4 *draws = nullptr;
+    QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&draws), sizeof(int4) * np, s));
+    qpm_status st2 = launch_de(pv, F, CR, seed, nullptr, generation, inst, u_bits, ld, draws, true, s);
+    (void)hipFreeAsync(draws, s);
+    return st2;
 }
 
 QPM_API qpm_status qpm_gwo_step(const float *x, int64_t np, int64_t D, int64_t ldx, const int32_t *leaders, float a,

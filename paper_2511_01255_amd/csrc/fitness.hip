@@ -173,10 +173,12 @@ __global__ __launch_bounds__(256) void fit_combine_kernel(const double *__restri
 }
 
 // The per-individual scheme: one lane walks its whole genome; no segment
-// triples, so B is not tracked.
+// triples, so B is not tracked. With `part` the result is written as the
+// single segment triple (A, 0, Q) instead of a fitness value.
 __global__ __launch_bounds__(128) void fit_per_genome_kernel(const uint32_t *__restrict__ bits, int64_t ld, int W,
                                                              const double4 *__restrict__ ph64, int64_t np,
-                                                             const double *__restrict__ C, double *__restrict__ fit)
+                                                             const double *__restrict__ C, double *__restrict__ fit,
+                                                             double *__restrict__ part)
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * 128 + threadIdx.x;
     if (i >= np) return;
@@ -196,16 +198,26 @@ __global__ __launch_bounds__(128) void fit_per_genome_kernel(const uint32_t *__r
             ai = fma(s, c.y, ai);
         }
     }
+    if (part) {
+        double *o = part + i;
+        o[0] = ar;
+        o[ld] = ai;
+        o[2 * ld] = 0.0;
+        o[3 * ld] = 0.0;
+        o[4 * ld] = qr;
+        o[5 * ld] = qi;
+        return;
+    }
     const double sr = qr + C[0], si = qi + C[1];
     fit[i] = fma(sr, sr, si * si);
 }
 
 template <bool F32>
 static void launch_seg(const Design &d, const FitPlan &pl, const uint32_t *bits, int64_t np, int64_t ld,
-                       double *part, void *fit, int out_f64, hipStream_t s)
+                       double *part, void *fit, int out_f64, bool direct_ok, hipStream_t s)
 {
     const dim3 grid(static_cast<unsigned>((np + 63) / 64), static_cast<unsigned>(pl.gy));
-    const int direct = pl.gy == 1;
+    const int direct = direct_ok && pl.gy == 1;
     const int W = static_cast<int>(d.words);
 #define QPM_SEG_CASE(NW)                                                                                       \
     case NW:                                                                                                   \
@@ -256,6 +268,12 @@ size_t fitness_workspace_bytes(const FitPlan &pl, int64_t ld)
     return sizeof(double) * 6 * static_cast<size_t>(pl.gy) * static_cast<size_t>(ld);
 }
 
+size_t fitness_partials_bytes(const FitPlan &pl, int64_t ld)
+{
+    const size_t gy = pl.kind == QPM_FIT_SEGMENTED ? static_cast<size_t>(pl.gy) : 1;
+    return sizeof(double) * 6 * gy * static_cast<size_t>(ld);
+}
+
 qpm_status launch_fitness(const Design &d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld, void *fit,
                           const FitPlan &pl, double *part, hipStream_t s)
 {
@@ -263,12 +281,12 @@ qpm_status launch_fitness(const Design &d, qpm_prec p, const uint32_t *bits, int
     if (pl.kind == QPM_FIT_PER_GENOME) {
         const unsigned blocks = static_cast<unsigned>((np + 127) / 128);
         fit_per_genome_kernel<<<blocks, 128, 0, s>>>(bits, ld, static_cast<int>(d.words), d.ph64, np, d.Cdev,
-                                                     static_cast<double *>(fit));
+                                                     static_cast<double *>(fit), nullptr);
     } else {
         if (p == QPM_PREC_F32)
-            launch_seg<true>(d, pl, bits, np, ld, part, fit, out_f64, s);
+            launch_seg<true>(d, pl, bits, np, ld, part, fit, out_f64, true, s);
         else
-            launch_seg<false>(d, pl, bits, np, ld, part, fit, out_f64, s);
+            launch_seg<false>(d, pl, bits, np, ld, part, fit, out_f64, true, s);
         if (pl.gy > 1) {
             const unsigned blocks = static_cast<unsigned>((np + 255) / 256);
             fit_combine_kernel<<<blocks, 256, 0, s>>>(part, pl.gy, ld, np, d.Cdev, fit, out_f64);
@@ -278,29 +296,43 @@ qpm_status launch_fitness(const Design &d, qpm_prec p, const uint32_t *bits, int
     return QPM_OK;
 }
 
+qpm_status launch_fitness_partials(const Design &d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                                   const FitPlan &pl, double *part, hipStream_t s)
+{
+    if (pl.kind == QPM_FIT_PER_GENOME) {
+        const unsigned blocks = static_cast<unsigned>((np + 127) / 128);
+        fit_per_genome_kernel<<<blocks, 128, 0, s>>>(bits, ld, static_cast<int>(d.words), d.ph64, np, d.Cdev,
+                                                     nullptr, part);
+    } else if (p == QPM_PREC_F32) {
+        launch_seg<true>(d, pl, bits, np, ld, part, nullptr, 0, false, s);
+    } else {
+        launch_seg<false>(d, pl, bits, np, ld, part, nullptr, 1, false, s);
+    }
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
+}
+
 }  // namespace qpm
 
 using namespace qpm;
 
-QPM_API qpm_status qpm_eval_fitness(qpm_design d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
-                                    void *fitness, int32_t kernel, qpm_stream sv)
+static qpm_status check_fitness_args(qpm_design d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                                     void *fitness)
 {
-    clear_error();
     QPM_REQUIRE(d && bits && fitness, QPM_EINVAL, "design, bits and fitness must not be NULL");
     QPM_REQUIRE(p == QPM_PREC_F32 || p == QPM_PREC_F64, QPM_EINVAL, "unknown precision %d", (int)p);
-    QPM_REQUIRE(kernel == QPM_FIT_AUTO || kernel == QPM_FIT_SEGMENTED || kernel == QPM_FIT_PER_GENOME, QPM_EINVAL,
-                "unknown fitness kernel %d", (int)kernel);
-    QPM_REQUIRE(!(kernel == QPM_FIT_PER_GENOME && p != QPM_PREC_F64), QPM_EINVAL,
-                "the per-genome kernel computes in FP64 only");
     QPM_REQUIRE(np >= 1, QPM_EINVAL, "np must be >= 1 (got %lld)", (long long)np);
     QPM_REQUIRE(ld >= np && ld % 64 == 0, QPM_EINVAL, "ld (%lld) must be >= np (%lld) and a multiple of 64",
                 (long long)ld, (long long)np);
+    QPM_REQUIRE((reinterpret_cast<uintptr_t>(bits) & 3u) == 0, QPM_EINVAL, "bits must be 4-byte aligned");
     QPM_REQUIRE(np <= (int64_t(1) << 31) && d->words * ld <= (int64_t(1) << 40), QPM_ERANGE,
                 "population too large");
-    QPM_REQUIRE(aligned16(bits) || (reinterpret_cast<uintptr_t>(bits) & 3u) == 0, QPM_EINVAL,
-                "bits must be 4-byte aligned");
-    hipStream_t s = static_cast<hipStream_t>(sv);
-    const FitPlan pl = plan_fitness(*d, p, np, kernel);
+    return QPM_OK;
+}
+
+static qpm_status run_plan(qpm_design d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld, void *fitness,
+                           const FitPlan &pl, hipStream_t s)
+{
     const size_t wsb = fitness_workspace_bytes(pl, ld);
     double *ws = nullptr;
     if (wsb) QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&ws), wsb, s));
@@ -313,4 +345,36 @@ QPM_API qpm_status qpm_eval_fitness(qpm_design d, qpm_prec p, const uint32_t *bi
         }
     }
     return st;
+}
+
+QPM_API qpm_status qpm_eval_fitness(qpm_design d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                                    void *fitness, int32_t kernel, qpm_stream sv)
+{
+    clear_error();
+    QPM_REQUIRE(kernel == QPM_FIT_AUTO || kernel == QPM_FIT_SEGMENTED || kernel == QPM_FIT_PER_GENOME, QPM_EINVAL,
+                "unknown fitness kernel %d", (int)kernel);
+    QPM_REQUIRE(!(kernel == QPM_FIT_PER_GENOME && p != QPM_PREC_F64), QPM_EINVAL,
+                "the per-genome kernel computes in FP64 only");
+    qpm_status st = check_fitness_args(d, p, bits, np, ld, fitness);
+    if (st != QPM_OK) return st;
+    return run_plan(d, p, bits, np, ld, fitness, plan_fitness(*d, p, np, kernel), static_cast<hipStream_t>(sv));
+}
+
+QPM_API qpm_status qpm_eval_fitness_shape(qpm_design d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                                          void *fitness, int32_t waves, int32_t wpw, qpm_stream sv)
+{
+    clear_error();
+    QPM_REQUIRE(waves == 1 || waves == 2 || waves == 4 || waves == 8 || waves == 16, QPM_EINVAL,
+                "waves_per_group must be 1, 2, 4, 8 or 16 (got %d)", (int)waves);
+    QPM_REQUIRE(wpw >= 1, QPM_EINVAL, "words_per_wave must be >= 1 (got %d)", (int)wpw);
+    qpm_status st = check_fitness_args(d, p, bits, np, ld, fitness);
+    if (st != QPM_OK) return st;
+    FitPlan pl;
+    pl.kind = QPM_FIT_SEGMENTED;
+    pl.waves = waves;
+    pl.wpw = wpw;
+    const int64_t nseg = (d->words + wpw - 1) / wpw;
+    pl.gy = static_cast<int>((nseg + waves - 1) / waves);
+    QPM_REQUIRE(pl.gy <= 65535, QPM_ERANGE, "too many workgroup segments (%d)", pl.gy);
+    return run_plan(d, p, bits, np, ld, fitness, pl, static_cast<hipStream_t>(sv));
 }

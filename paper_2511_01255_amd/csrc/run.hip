@@ -13,8 +13,6 @@
 
 namespace qpm {
 
-__global__ void advance_kernel(uint32_t *gen) { gen[0] += 1u; }
-
 }  // namespace qpm
 
 using namespace qpm;
@@ -33,6 +31,8 @@ struct qpm_run_s {
     int32_t *best = nullptr;
     uint32_t *gen = nullptr;
     float *a_tab = nullptr;
+    int4 *draws = nullptr;
+    uint32_t *ticket = nullptr;
     double *fws = nullptr;
     FitPlan plan;
     hipGraph_t graph = nullptr;
@@ -65,6 +65,8 @@ static void release(qpm_run_s *r)
     (void)hipFree(r->gen);
     (void)hipFree(r->a_tab);
     (void)hipFree(r->fws);
+    (void)hipFree(r->draws);
+    (void)hipFree(r->ticket);
     for (auto &e : r->ev)
         if (e) (void)hipEventDestroy(e);
     if (r->st) (void)hipStreamDestroy(r->st);
@@ -86,18 +88,18 @@ static qpm_status enqueue_generation(qpm_run_s *r, hipEvent_t *ev = nullptr)
 #define QPM_STEP(k, call)                         \
     if ((st = mark(k)) != QPM_OK) return st;      \
     if ((st = (call)) != QPM_OK) return st;
-    QPM_STEP(QPM_K_DE, launch_de(pv, c.F, c.CR, c.seed, r->gen, 0u, c.inst, r->tbits, r->ld, r->st))
-    QPM_STEP(QPM_K_FIT_DE, launch_fitness(*r->d, p, r->tbits, c.np, r->ld, r->f_new, r->plan, r->fws, r->st))
-    QPM_STEP(QPM_K_SELECT_DE, launch_select(r->f_cur, r->f_new, r->flags, c.np, nullptr, r->f64(), r->st))
-    QPM_STEP(QPM_K_TOP3, launch_top3(r->f_cur, c.np, r->f64(), r->leaders, r->st))
+    const int gy = r->plan.kind == QPM_FIT_SEGMENTED ? r->plan.gy : 1;
+    const double *C = r->d->Cdev;
+    QPM_STEP(QPM_K_DE, launch_de(pv, c.F, c.CR, c.seed, r->gen, 0u, c.inst, r->tbits, r->ld, r->draws, false, r->st))
+    QPM_STEP(QPM_K_FIT_DE, launch_fitness_partials(*r->d, p, r->tbits, c.np, r->ld, r->plan, r->fws, r->st))
+    QPM_STEP(QPM_K_FINISH_DE, launch_finish(r->fws, gy, r->ld, c.np, C, r->f_cur, r->f64(), r->flags, nullptr,
+                                            r->leaders, nullptr, r->gen, r->D, c.seed, c.inst, r->ticket, r->st))
     QPM_STEP(QPM_K_GWO, launch_gwo(pv, r->leaders, r->a_tab, 0.0f, c.seed, r->gen, 0u, c.inst, c.gwo_variant,
                                    r->tbits, r->ld, r->st))
-    QPM_STEP(QPM_K_FIT_GWO, launch_fitness(*r->d, p, r->tbits, c.np, r->ld, r->f_new, r->plan, r->fws, r->st))
-    QPM_STEP(QPM_K_SELECT_GWO, launch_select(r->f_cur, r->f_new, r->flags, c.np, r->leaders, r->f64(), r->st))
+    QPM_STEP(QPM_K_FIT_GWO, launch_fitness_partials(*r->d, p, r->tbits, c.np, r->ld, r->plan, r->fws, r->st))
+    QPM_STEP(QPM_K_FINISH_GWO, launch_finish(r->fws, gy, r->ld, c.np, C, r->f_cur, r->f64(), r->flags, r->leaders,
+                                             nullptr, r->draws, r->gen, r->D, c.seed, c.inst, r->ticket, r->st))
 #undef QPM_STEP
-    if ((st = mark(QPM_K_ADVANCE)) != QPM_OK) return st;
-    advance_kernel<<<1, 1, 0, r->st>>>(r->gen);
-    QPM_TRY_HIP(hipGetLastError());
     return mark(QPM_K_COUNT);
 }
 
@@ -144,8 +146,9 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     if (e == hipSuccess) e = hipMalloc(&r->best, sizeof(int32_t) * 3);
     if (e == hipSuccess) e = hipMalloc(&r->gen, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&r->a_tab, sizeof(float) * c.generations);
-    const size_t wsb = fitness_workspace_bytes(r->plan, r->ld);
-    if (e == hipSuccess && wsb) e = hipMalloc(&r->fws, wsb);
+    if (e == hipSuccess) e = hipMalloc(&r->draws, sizeof(int4) * c.np);
+    if (e == hipSuccess) e = hipMalloc(&r->ticket, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&r->fws, fitness_partials_bytes(r->plan, r->ld));
     if (e != hipSuccess) {
         set_error("run allocation failed: %s", hipGetErrorString(e));
         release(r);
@@ -163,6 +166,7 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     if (e == hipSuccess) e = hipMemcpyAsync(r->a_tab, a.data(), sizeof(float) * c.generations, hipMemcpyHostToDevice, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->flags, 0, sizeof(uint32_t) * c.np, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->gen, 0, sizeof(uint32_t), r->st);
+    if (e == hipSuccess) e = hipMemsetAsync(r->ticket, 0, sizeof(uint32_t), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->tbits, 0, sizeof(uint32_t) * r->W * r->ld, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->buf[1], 0, gene_bytes, r->st);
     if (e == hipSuccess) e = hipStreamSynchronize(r->st);  // a.data() must outlive the copy
@@ -177,6 +181,7 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     st = launch_init(c.np, r->D, r->ldx, c.seed, c.inst, r->buf[0], r->tbits, r->ld, r->st);
     if (st == QPM_OK) st = launch_fitness(*d, p, r->tbits, c.np, r->ld, r->f_cur, r->plan, r->fws, r->st);
     if (st == QPM_OK) st = launch_top3(r->f_cur, c.np, r->f64(), r->leaders, r->st);
+    if (st == QPM_OK) st = launch_draws(c.np, r->D, c.seed, r->gen, c.inst, r->draws, r->st);
     if (st == QPM_OK && c.use_graph) {
         e = hipStreamBeginCapture(r->st, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) {
@@ -273,6 +278,7 @@ QPM_API qpm_status qpm_run_load(qpm_run_handle r, const float *x, int64_t ldx)
         st = launch_fitness(*r->d, static_cast<qpm_prec>(c.prec), r->tbits, c.np, r->ld, r->f_cur, r->plan, r->fws,
                             r->st);
     if (st == QPM_OK) st = launch_top3(r->f_cur, c.np, r->f64(), r->leaders, r->st);
+    if (st == QPM_OK) st = launch_draws(c.np, r->D, c.seed, r->gen, c.inst, r->draws, r->st);
     return st;
 }
 

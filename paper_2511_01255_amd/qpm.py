@@ -17,7 +17,7 @@ FIT_AUTO = 0
 FIT_SEGMENTED = 1
 FIT_PER_GENOME = 2
 # timing slots of one generation (QPM_K_*)
-STEP_NAMES = ["de", "fitness_de", "select_de", "top3", "gwo", "fitness_gwo", "select_gwo", "advance"]
+STEP_NAMES = ["de", "fitness_de", "finish_de", "gwo", "fitness_gwo", "finish_gwo"]
 
 _P = C.c_void_p
 _I64 = C.c_int64
@@ -55,9 +55,12 @@ _SIGS = {
     "qpm_design_info": (_I32, [_P, _P, _P]),
     "qpm_design_read_phases": (_I32, [_P, _P, _P, _P]),
     "qpm_eval_fitness": (_I32, [_P, _I32, _P, _I64, _I64, _P, _I32, _P]),
+    "qpm_eval_fitness_shape": (_I32, [_P, _I32, _P, _I64, _I64, _P, _I32, _I32, _P]),
     "qpm_init_population": (_I32, [_I64, _I64, _I64, _U64, _U32, _P, _P, _I64, _P]),
     "qpm_de_step": (_I32, [_P, _I64, _I64, _I64, _F, _F, _U64, _U32, _U32, _P, _P, _I64, _P]),
     "qpm_gwo_step": (_I32, [_P, _I64, _I64, _I64, _P, _F, _U64, _U32, _U32, _I32, _P, _P, _I64, _P]),
+    "qpm_relax_forward": (_I32, [_P, _I32, _P, _I64, _I64, _P, _P, _P]),
+    "qpm_relax_backward": (_I32, [_P, _I32, _P, _I64, _I64, _P, _P, _P, _I64, _P]),
     "qpm_run_create": (_I32, [_P, C.POINTER(RunConfig), _P, C.POINTER(_P)]),
     "qpm_run_advance": (_I32, [_P, _I64]),
     "qpm_run_read": (_I32, [_P, _P, _I64, _P, _P, _P]),
@@ -168,6 +171,16 @@ def eval_fitness(design, bits, np_, prec=PREC_F32, kernel=FIT_AUTO, out=None, st
     return out
 
 
+def eval_fitness_shape(design, bits, np_, prec, waves_per_group, words_per_wave, out=None, stream=None):
+    """eval_fitness with an explicit segmented launch shape (tuning)."""
+    import torch
+    if out is None:
+        out = torch.empty(np_, dtype=torch.float64 if prec == PREC_F64 else torch.float32, device=bits.device)
+    _check(lib().qpm_eval_fitness_shape(design.handle, prec, _ptr(bits), np_, bits.shape[1], _ptr(out),
+                                        waves_per_group, words_per_wave, _stream(stream)))
+    return out
+
+
 def init_population(np_, D, seed, inst=0, ldx=None, device="cuda", stream=None):
     import torch
     ldx = ldx_for(D) if ldx is None else ldx
@@ -202,6 +215,62 @@ def gwo_step(x, D, leaders, a, seed, generation, inst=0, variant=0, stream=None)
     _check(lib().qpm_gwo_step(_ptr(x), np_, D, ldx, _ptr(leaders), a, seed, generation, inst, variant, _ptr(y),
                               _ptr(yb), ld, _stream(stream)))
     return y, yb
+
+
+def relax_forward(design, theta, prec=PREC_F32, stream=None):
+    """theta: float32 CUDA tensor (B, >= N) -> (f float32 (B,), S float64 (B, 2))."""
+    import torch
+    B, ldt = theta.shape
+    f = torch.empty(B, dtype=torch.float32, device=theta.device)
+    S = torch.empty((B, 2), dtype=torch.float64, device=theta.device)
+    _check(lib().qpm_relax_forward(design.handle, prec, _ptr(theta), B, ldt, _ptr(f), _ptr(S), _stream(stream)))
+    return f, S
+
+
+def relax_backward(design, theta, S, grad_f, prec=PREC_F32, stream=None):
+    """-> grad_theta float32 (B, ldt) (entries past N are left 0)."""
+    import torch
+    B, ldt = theta.shape
+    g = torch.zeros_like(theta)
+    gf = grad_f.to(torch.float32).contiguous()
+    _check(lib().qpm_relax_backward(design.handle, prec, _ptr(theta), B, ldt, _ptr(S), _ptr(gf), _ptr(g), ldt,
+                                    _stream(stream)))
+    return g
+
+
+def _relax_function():
+    import torch
+
+    class QpmRelax(torch.autograd.Function):
+        """f = |d_eff(tanh theta)|^2 per row, with the hand-written adjoint."""
+
+        @staticmethod
+        def forward(ctx, theta, design, prec=PREC_F32):
+            theta = theta.contiguous()
+            f, S = relax_forward(design, theta, prec)
+            ctx.save_for_backward(theta, S)
+            ctx.design = design
+            ctx.prec = prec
+            return f
+
+        @staticmethod
+        def backward(ctx, grad_f):
+            theta, S = ctx.saved_tensors
+            g = relax_backward(ctx.design, theta, S, grad_f, ctx.prec)
+            return g, None, None
+
+    return QpmRelax
+
+
+_QpmRelax = None
+
+
+def relax(theta, design, prec=PREC_F32):
+    """Differentiable f(theta) = |d_eff(tanh theta)|^2 (torch autograd)."""
+    global _QpmRelax
+    if _QpmRelax is None:
+        _QpmRelax = _relax_function()
+    return _QpmRelax.apply(theta, design, prec)
 
 
 def _config(np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0, use_graph=1,

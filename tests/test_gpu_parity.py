@@ -303,3 +303,18 @@ def test_run_fp32_lockstep(q, orc):
             assert ok, "generation %d row %d matches no admissible outcome" % (g, i)
     print("FP32 lockstep: %d generations, %d adopted near-tie decisions" % (G, adoptions))
     R.destroy()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_fitness_every_launch_shape_matches_oracle(q, orc, prec):
+    # the tuner may pick any shape: all of them must meet the tolerance
+    npop, n = 130, 3001
+    z, d = _fit_case(npop, n, "periodic", seed=4)
+    D = q.precompute_phases(z, DK1, DK2)
+    bits = _bits(d)
+    _, fo = orc.Design(z, DK1, DK2).fitness(d)
+    for waves in (1, 2, 4, 8, 16):
+        for wpw in (1, 2, 3, 7, 94, 200):
+            f = q.eval_fitness_shape(D, bits, npop, prec, waves, wpw).double().cpu().numpy()
+            err = _rel_err(f, fo)
+            assert err.max() <= TOL[prec], (waves, wpw, err.max())
