@@ -72,6 +72,8 @@ typedef enum {
 typedef void *qpm_stream;               /* a hipStream_t */
 typedef struct qpm_design_s *qpm_design; /* owns the device phase tables */
 typedef struct qpm_run_s *qpm_run_handle;
+typedef struct qpm_batch_s *qpm_batch;   /* many designs, concatenated tables */
+typedef struct qpm_batch_run_s *qpm_batch_run_handle;
 
 /* Status text for a code, and the calling thread's last error message. */
 const char *qpm_status_string(qpm_status s);
@@ -297,6 +299,55 @@ qpm_status qpm_run_destroy(qpm_run_handle r);
  * Synchronous. */
 qpm_status qpm_run(qpm_design d, const qpm_run_config *cfg, float *best_x, uint32_t *best_bits,
                    qpm_run_stats *stats, qpm_stream s);
+
+/*
+ * Batches of independent designs (not in the paper, which optimises one
+ * crystal per run): each step of a generation is one launch over all
+ * instances. Instance b has N_b = offsets[b+1] - offsets[b] - 1 domains with
+ * boundaries z[offsets[b] .. offsets[b+1]) (host, concatenated, offsets[0] =
+ * 0) and mismatches dk1[b], dk2[b] (host). Its tables are those of
+ * qpm_precompute_phases. Synchronises s. 1 <= n_inst <= 65535.
+ */
+qpm_status qpm_precompute_phases_batched(const double *z, const int64_t *offsets, int32_t n_inst,
+                                         const double *dk1, const double *dk2, qpm_stream s,
+                                         qpm_batch *out);
+qpm_status qpm_batch_free(qpm_batch b);
+/* n_inst, N_b (host int64[n_inst]) and C_b (host double[2 n_inst]); outputs
+ * may be NULL. */
+qpm_status qpm_batch_info(qpm_batch b, int32_t *n_inst, int64_t *n_domains, double *C);
+
+/*
+ * qpm_batch_eval_fitness -- f for np genomes of every instance. bits:
+ * device, the population-major words of all instances stacked by instance
+ * (sum_b W_b rows of ld words); fitness: device, n_inst x np floats / doubles
+ * (instance-major). waves_per_group in {0 (default), 4, 8, 16} and
+ * words_per_wave >= 0 (0 = default) choose the launch shape.
+ */
+qpm_status qpm_batch_eval_fitness(qpm_batch b, qpm_prec p, const uint32_t *bits, int64_t np,
+                                  int64_t ld, void *fitness, int32_t waves_per_group,
+                                  int32_t words_per_wave, qpm_stream s);
+
+/*
+ * qpm_batch_run_create -- one HWSDA run per instance, all advanced together
+ * (every instance follows the single-design generation of qpm_run_create
+ * with Philox instance number cfg->inst + b). 4 <= cfg->np <= 4096; the
+ * fitness kernel is the segmented one (cfg->fit_kernel is ignored). With
+ * tune != 0 the fitness launch shape is chosen by timing candidates on the
+ * initial population (kept per problem size for the process, and appended
+ * to the file named by the QPM_TUNE_CACHE environment variable if set).
+ */
+qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, int32_t tune, qpm_stream s,
+                                qpm_batch_run_handle *out);
+qpm_status qpm_batch_run_advance(qpm_batch_run_handle r, int64_t generations);
+qpm_status qpm_batch_run_set_timing(qpm_batch_run_handle r, int32_t enable);
+qpm_status qpm_batch_run_timing(qpm_batch_run_handle r, double *ms, int64_t *generations,
+                                int32_t reset);
+/* State of instance inst: x (device np x ldx, ldx >= N_inst), fitness
+ * (device np values), leaders (host int32[3]), fit_shape (host int32[2]:
+ * waves per group, words per wave in use); any may be NULL. Synchronous. */
+qpm_status qpm_batch_run_read(qpm_batch_run_handle r, int32_t inst, float *x, int64_t ldx,
+                              void *fitness, int32_t *leaders, int32_t *fit_shape);
+qpm_status qpm_batch_run_destroy(qpm_batch_run_handle r);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,1050 @@
+// batch.hip -- many independent designs of uneven length and phase
+// mismatch optimised together: every step of a generation is one launch over
+// all instances (an addition to the paper, whose runs optimise one crystal
+// at a time).
+//
+// Layout: the per-domain tables of all instances are concatenated by whole
+// 32-domain words (instance b starts at word row wofs_b), and so are the
+// population-major bit rows; gene rows of instance b start at float offset
+// xofs_b (row stride ldx_b). Per-individual arrays (fitness, flags, DE
+// draws) are instance-major, np per instance. Small device tables map a
+// workgroup to its (instance, segment) for the fitness and (instance,
+// chunk) for DE, GWO and initialisation. Every instance uses the Philox
+// instance number inst0 + b, so its random streams are those of a
+// single-design run with that instance number.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "device_common.hpp"
+#include "genes.hpp"
+#include "scan.hpp"
+
+namespace qpm {
+
+struct InstDesc {
+    int64_t n;     // domains (= genes)
+    int64_t words; // W
+    int64_t wofs;  // first word row of the instance
+    int64_t xofs;  // float offset of row 0 in a gene buffer
+    int64_t ldx;   // gene row stride
+    double C[2];
+};
+
+struct FitSeg {
+    int inst;  // instance
+    int w0;    // first word (within the instance) of the workgroup
+    int slot;  // partial slot
+    int pad;
+};
+
+struct Tile {
+    int inst;
+    int chunk;
+};
+
+// ---------------------------------------------------------------- fitness
+
+template <bool F32, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void batch_fit_kernel(const uint32_t *__restrict__ bits, int64_t ld,
+                                                               const double4 *__restrict__ ph64,
+                                                               const float4 *__restrict__ ph32, int wpw,
+                                                               const InstDesc *__restrict__ inst,
+                                                               const FitSeg *__restrict__ tab,
+                                                               double *__restrict__ part)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const FitSeg fs = tab[blockIdx.y];
+    const InstDesc id = inst[fs.inst];
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+    const int w0 = fs.w0 + wave * wpw;
+    const int w1 = min(static_cast<int>(id.words), w0 + wpw);
+    Tri t{0, 0, 0, 0, 0, 0};
+    const uint32_t *bp = bits + id.wofs * ld + i;
+    if (w0 < w1) {
+        uint32_t next = bp[static_cast<int64_t>(w0) * ld];
+        for (int wd = w0; wd < w1; ++wd) {
+            const uint32_t word = next;
+            if (wd + 1 < w1) next = bp[static_cast<int64_t>(wd + 1) * ld];
+            const int64_t dom = (id.wofs + wd) * 32;
+            if constexpr (F32)
+                scan_word_f32<32>(t, word, ph32 + dom);
+            else
+                scan_word_f64(t, word, ph64 + dom);
+        }
+    }
+    if constexpr (WAVES > 1) {
+        __shared__ double sh[6][WAVES][64];
+        sh[0][wave][lane] = t.ar;
+        sh[1][wave][lane] = t.ai;
+        sh[2][wave][lane] = t.br;
+        sh[3][wave][lane] = t.bi;
+        sh[4][wave][lane] = t.qr;
+        sh[5][wave][lane] = t.qi;
+        __syncthreads();
+        if (wave != 0) return;
+#pragma unroll 1
+        for (int w = 1; w < WAVES; ++w) {
+            const Tri u{sh[0][w][lane], sh[1][w][lane], sh[2][w][lane],
+                        sh[3][w][lane], sh[4][w][lane], sh[5][w][lane]};
+            tri_append(t, u);
+        }
+    }
+    double *o = part + static_cast<int64_t>(fs.slot) * 6 * ld + i;
+    o[0] = t.ar;
+    o[ld] = t.ai;
+    o[2 * ld] = t.br;
+    o[3 * ld] = t.bi;
+    o[4 * ld] = t.qr;
+    o[5 * ld] = t.qi;
+}
+
+// One workgroup per instance: combine the instance's slots into f, then
+//   mode 0 (evaluation only): f_out[b][i] = f;
+//   mode 1 (initial): f_cur = f, leaders, DE draws of generation gen;
+//   mode 2 (after DE): select, leaders;
+//   mode 3 (after GWO): select with the leaders excluded, DE draws of
+//     generation gen + 1; the last workgroup advances gen.
+template <typename T>
+__global__ __launch_bounds__(256) void batch_finish_kernel(int mode, const double *__restrict__ part,
+                                                           const int *__restrict__ slot_ofs, int64_t ld, int64_t np,
+                                                           const InstDesc *__restrict__ inst, T *__restrict__ f_cur,
+                                                           uint32_t *__restrict__ flags, int32_t *__restrict__ leaders,
+                                                           int4 *__restrict__ draws, uint32_t *__restrict__ gen,
+                                                           uint32_t k0, uint32_t k1, uint32_t inst0,
+                                                           uint32_t *__restrict__ ticket)
+{
+    const int b = blockIdx.x;
+    const InstDesc id = inst[b];
+    const int s0 = slot_ofs[b], s1 = slot_ofs[b + 1];
+    T *fb = f_cur + static_cast<int64_t>(b) * np;
+    uint32_t *flb = flags ? flags + static_cast<int64_t>(b) * np : nullptr;
+    int32_t *Lb = leaders ? leaders + 3 * b : nullptr;
+    const uint32_t g = gen ? gen[0] : 0u;
+    int32_t L0 = -1, L1 = -1, L2 = -1;
+    if (mode == 3) {
+        L0 = Lb[0];
+        L1 = Lb[1];
+        L2 = Lb[2];
+    }
+    for (int64_t i = threadIdx.x; i < np; i += 256) {
+        const double *p = part + static_cast<int64_t>(s0) * 6 * ld + i;
+        double ar = p[0], ai = p[ld], qr = p[4 * ld], qi = p[5 * ld];
+        for (int sg = s0 + 1; sg < s1; ++sg) {
+            const double *q = part + static_cast<int64_t>(sg) * 6 * ld + i;
+            const double vr = q[2 * ld], vi = q[3 * ld];
+            qr = fma(ar, vr, fma(-ai, vi, qr + q[4 * ld]));
+            qi = fma(ar, vi, fma(ai, vr, qi + q[5 * ld]));
+            ar += q[0];
+            ai += q[ld];
+        }
+        const double sr = qr + id.C[0], si = qi + id.C[1];
+        const T v = static_cast<T>(fma(sr, sr, si * si));
+        if (mode <= 1) {
+            fb[i] = v;
+        } else {
+            const bool skip = (mode == 3) && (i == L0 || i == L1 || i == L2);
+            if (!skip && v > fb[i]) {
+                fb[i] = v;
+                flb[i] ^= 1u;
+            }
+        }
+        if (mode == 1 || mode == 3)
+            draws[static_cast<int64_t>(b) * np + i] =
+                de_draw(i, np, id.n, mode == 3 ? g + 1u : g, inst0 + static_cast<uint32_t>(b), k0, k1);
+    }
+    if (mode == 1 || mode == 2) {
+        __syncthreads();
+        block_top3<T, 256>(fb, np, Lb);
+    }
+    if (mode == 3) {
+        __shared__ int s_last;
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) s_last = (atomicAdd(ticket, 1u) == gridDim.x - 1) ? 1 : 0;
+        __syncthreads();
+        if (s_last && threadIdx.x == 0) {
+            gen[0] += 1u;
+            *ticket = 0u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- evolution
+
+struct BatchPop {
+    const float *x0, *x1;
+    float *out0, *out1;
+    const uint32_t *flags;  // instance-major, np per instance
+    int64_t np;
+};
+
+__device__ __forceinline__ PopView view_of(const BatchPop &bp, const InstDesc &id, int b)
+{
+    return PopView{bp.x0 + id.xofs, bp.x1 + id.xofs, bp.flags + static_cast<int64_t>(b) * bp.np,
+                   bp.out0 + id.xofs, bp.out1 + id.xofs, bp.np, id.n, id.ldx};
+}
+
+// initialisation: grid x = individual, y = tile (instance, 1024-gene chunk)
+__global__ __launch_bounds__(256) void batch_init_kernel(int64_t np, const InstDesc *__restrict__ inst,
+                                                         const Tile *__restrict__ tiles, uint32_t k0, uint32_t k1,
+                                                         uint32_t inst0, float *__restrict__ x,
+                                                         uint32_t *__restrict__ bits, int64_t ld)
+{
+    const Tile tl = tiles[blockIdx.y];
+    const InstDesc id = inst[tl.inst];
+    const int64_t i = blockIdx.x;
+    const int64_t q = static_cast<int64_t>(tl.chunk) * 256 + threadIdx.x;
+    const int64_t j0 = 4 * q;
+    const bool valid = j0 < id.n;
+    uint32_t nib = 0;
+    if (valid) {
+        const U4 r = philox10(static_cast<uint32_t>(q), static_cast<uint32_t>(i), 0u,
+                              ((inst0 + static_cast<uint32_t>(tl.inst)) << 8) | kTagInit, k0, k1);
+        const float4 v = make_float4(sym24(r.x), sym24(r.y), sym24(r.z), sym24(r.w));
+        store_quad(x + id.xofs + i * id.ldx, j0, id.n, v);
+        nib = quad_nibble(v, j0, id.n);
+    }
+    store_word(nib, q, valid, bits + id.wofs * ld, ld, i);
+}
+
+// DE: tiles (instance, chunk of CW = 256 / IPW genes) dealt round-robin to
+// the XCDs (workgroup id mod 8); a workgroup covers 4 IPW consecutive
+// individuals of one tile.
+template <int IPW>
+__global__ __launch_bounds__(256) void batch_de_kernel(BatchPop bp, const InstDesc *__restrict__ inst,
+                                                       const Tile *__restrict__ tiles, int ntiles, int groups,
+                                                       const int4 *__restrict__ draws, float F, float CR, uint32_t k0,
+                                                       uint32_t k1, const uint32_t *__restrict__ gen, uint32_t inst0,
+                                                       uint32_t *__restrict__ bits, int64_t ld)
+{
+    constexpr int LPI = 64 / IPW;
+    constexpr int CW = 4 * LPI;
+    constexpr int WPC = CW / 32;
+    constexpr int IPG = 4 * IPW;
+    const uint32_t blk = blockIdx.x;
+    const int xcd = static_cast<int>(blk & 7u);
+    const int k = static_cast<int>(blk >> 3);
+    const int gi = k % groups;
+    const int ti = xcd + 8 * (k / groups);
+    if (ti >= ntiles) return;
+    const Tile tl = tiles[ti];
+    const InstDesc id = inst[tl.inst];
+    const PopView pv = view_of(bp, id, tl.inst);
+    const int t = threadIdx.x;
+    const int local = t / LPI, li = t % LPI;
+    const int64_t np = bp.np, D = id.n;
+    const int64_t i = static_cast<int64_t>(gi) * IPG + local;
+    const int64_t j0 = static_cast<int64_t>(tl.chunk) * CW + 4 * li;
+    const bool active = i < np && j0 < D;
+    const uint32_t g = gen[0];
+    const uint32_t instb = inst0 + static_cast<uint32_t>(tl.inst);
+    __shared__ uint32_t wsh[IPG][WPC];
+    uint32_t nib = 0;
+    if (active) {
+        const int4 dr = draws[static_cast<int64_t>(tl.inst) * np + i];
+        const float4 xv = *reinterpret_cast<const float4 *>(row_of(pv, i) + j0);
+        const float4 a = *reinterpret_cast<const float4 *>(row_of(pv, dr.x) + j0);
+        const float4 bq = *reinterpret_cast<const float4 *>(row_of(pv, dr.y) + j0);
+        const float4 cq = *reinterpret_cast<const float4 *>(row_of(pv, dr.z) + j0);
+        const float4 uv = de_quad(xv, a, bq, cq, j0, dr.w, static_cast<uint32_t>(i), g, instb, k0, k1, F, CR);
+        store_quad(out_row_of(pv, i), j0, D, uv);
+        nib = quad_nibble(uv, j0, D);
+    }
+    uint32_t w = nib << (4 * (t & 7));
+    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 1));
+    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 2));
+    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 4));
+    if ((t & 7) == 0) wsh[local][li >> 3] = w;
+    __syncthreads();
+    if (t < IPG * WPC) {
+        const int wd = t / IPG, ii = t % IPG;
+        const int64_t row = static_cast<int64_t>(gi) * IPG + ii;
+        const int64_t wg = static_cast<int64_t>(tl.chunk) * WPC + wd;
+        if (row < np && wg * 32 < D) bits[(id.wofs + wg) * ld + row] = wsh[ii][wd];
+    }
+}
+
+// GWO: grid x = individual, y = tile (instance, 1024-gene chunk)
+__global__ __launch_bounds__(256) void batch_gwo_kernel(BatchPop bp, const InstDesc *__restrict__ inst,
+                                                        const Tile *__restrict__ tiles,
+                                                        const int32_t *__restrict__ leaders,
+                                                        const float *__restrict__ a_tab, uint32_t k0, uint32_t k1,
+                                                        const uint32_t *__restrict__ gen, uint32_t inst0, int variant,
+                                                        uint32_t *__restrict__ bits, int64_t ld)
+{
+    const Tile tl = tiles[blockIdx.y];
+    const InstDesc id = inst[tl.inst];
+    const int64_t i = blockIdx.x;
+    const int64_t np = bp.np, D = id.n;
+    const int64_t L0 = leaders[3 * tl.inst], L1 = leaders[3 * tl.inst + 1], L2 = leaders[3 * tl.inst + 2];
+    if (i == L0 || i == L1 || i == L2) return;
+    if (L0 < 0 || L0 >= np || L1 < 0 || L1 >= np || L2 < 0 || L2 >= np) return;
+    const PopView pv = view_of(bp, id, tl.inst);
+    const uint32_t g = gen[0];
+    const float a = a_tab[g];
+    const float two_a = 2.0f * a;
+    const int64_t q = static_cast<int64_t>(tl.chunk) * 256 + threadIdx.x;
+    const int64_t j0 = 4 * q;
+    const bool valid = j0 < D;
+    uint32_t nib = 0;
+    if (valid) {
+        const float4 xv = *reinterpret_cast<const float4 *>(row_of(pv, i) + j0);
+        const float4 X0 = *reinterpret_cast<const float4 *>(row_of(pv, L0) + j0);
+        const float4 X1 = *reinterpret_cast<const float4 *>(row_of(pv, L1) + j0);
+        const float4 X2 = *reinterpret_cast<const float4 *>(row_of(pv, L2) + j0);
+        const float4 yv = gwo_quad(xv, X0, X1, X2, static_cast<uint32_t>(q), static_cast<uint32_t>(i), g,
+                                   inst0 + static_cast<uint32_t>(tl.inst), k0, k1, a, two_a, variant);
+        store_quad(out_row_of(pv, i), j0, D, yv);
+        nib = quad_nibble(yv, j0, D);
+    }
+    store_word(nib, q, valid, bits + id.wofs * ld, ld, i);
+}
+
+// rows of instance b's current population -> dense out[np][ldo]
+__global__ __launch_bounds__(256) void batch_gather_kernel(BatchPop bp, const InstDesc *__restrict__ inst, int b,
+                                                           float *__restrict__ out, int64_t ldo)
+{
+    const InstDesc id = inst[b];
+    const PopView pv = view_of(bp, id, b);
+    const int64_t r = blockIdx.y;
+    const float *x = row_of(pv, r);
+    for (int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; j < id.n; j += 256 * gridDim.x)
+        out[r * ldo + j] = x[j];
+}
+
+// ---------------------------------------------------------------- plans
+
+struct BatchFitPlan {
+    int waves = 16;
+    int wpw = 8;
+    std::vector<FitSeg> segs;
+    std::vector<int> slot_ofs;  // n_inst + 1
+};
+
+static BatchFitPlan make_fit_plan(const std::vector<InstDesc> &h, int waves, int wpw)
+{
+    BatchFitPlan p;
+    p.waves = waves;
+    p.wpw = wpw;
+    p.slot_ofs.push_back(0);
+    int slot = 0;
+    const int per_wg = waves * wpw;
+    for (size_t b = 0; b < h.size(); ++b) {
+        for (int w0 = 0; w0 < h[b].words; w0 += per_wg) p.segs.push_back(FitSeg{static_cast<int>(b), w0, slot++, 0});
+        p.slot_ofs.push_back(slot);
+    }
+    return p;
+}
+
+static void default_fit_shape(const std::vector<InstDesc> &h, int64_t np, int *waves, int *wpw)
+{
+    int64_t words = 0;
+    for (const auto &d : h) words += d.words;
+    const int64_t groups = (np + 63) / 64;
+    // aim for ~8 waves per SIMD (8192 waves) over 256 CUs x 4 SIMDs
+    int64_t w = (groups * words + 8191) / 8192;
+    if (w < 1) w = 1;
+    *waves = 16;
+    *wpw = static_cast<int>(w);
+}
+
+// Launch-shape tuner: a process-wide cache keyed by the problem, optionally
+// persisted in the file named by QPM_TUNE_CACHE ("key waves wpw" lines).
+static std::mutex g_tune_mu;
+static std::map<std::string, std::pair<int, int>> g_tune;
+static bool g_tune_loaded = false;
+
+static std::string tune_key(const char *kind, int64_t words, int64_t np, int prec, int64_t n_inst)
+{
+    // bucket the totals to powers of two so similar problems share a shape
+    auto bucket = [](int64_t v) {
+        int b = 0;
+        while ((int64_t(1) << b) < v) ++b;
+        return b;
+    };
+    char buf[128];
+    std::snprintf(buf, sizeof(buf), "gfx950/%s/w%d/np%d/p%d/i%d", kind, bucket(words), bucket(np), prec,
+                  bucket(n_inst));
+    return buf;
+}
+
+static void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("QPM_TUNE_CACHE");
+    if (!path) return;
+    FILE *fh = std::fopen(path, "r");
+    if (!fh) return;
+    char key[128];
+    int a, b;
+    while (std::fscanf(fh, "%127s %d %d", key, &a, &b) == 3) g_tune[key] = {a, b};
+    std::fclose(fh);
+}
+
+static void tune_store_locked(const std::string &key, int waves, int wpw)
+{
+    g_tune[key] = {waves, wpw};
+    const char *path = std::getenv("QPM_TUNE_CACHE");
+    if (!path) return;
+    FILE *fh = std::fopen(path, "a");
+    if (!fh) return;
+    std::fprintf(fh, "%s %d %d\n", key.c_str(), waves, wpw);
+    std::fclose(fh);
+}
+
+}  // namespace qpm
+
+using namespace qpm;
+
+// ---------------------------------------------------------------- the batch design
+
+struct qpm_batch_s {
+    int32_t n_inst = 0;
+    int64_t total_words = 0;
+    int64_t total_genes_stride = 0;  // sum over instances of ldx
+    std::vector<InstDesc> host;
+    InstDesc *dev = nullptr;
+    double4 *ph64 = nullptr;
+    float4 *ph32 = nullptr;
+    double2 *c64 = nullptr;
+    double *Cdev = nullptr;
+};
+
+static void free_batch(qpm_batch_s *b)
+{
+    if (!b) return;
+    (void)hipFree(b->dev);
+    (void)hipFree(b->ph64);
+    (void)hipFree(b->ph32);
+    (void)hipFree(b->c64);
+    (void)hipFree(b->Cdev);
+    delete b;
+}
+
+QPM_API qpm_status qpm_precompute_phases_batched(const double *z, const int64_t *offsets, int32_t n_inst,
+                                                 const double *dk1, const double *dk2, qpm_stream sv,
+                                                 qpm_batch *out)
+{
+    clear_error();
+    QPM_REQUIRE(z && offsets && dk1 && dk2 && out, QPM_EINVAL, "z, offsets, dk1, dk2 and out must not be NULL");
+    QPM_REQUIRE(n_inst >= 1 && n_inst <= 65535, QPM_EINVAL, "n_inst must be in [1, 65535] (got %d)", (int)n_inst);
+    QPM_REQUIRE(offsets[0] == 0, QPM_EINVAL, "offsets[0] must be 0");
+    int64_t words = 0, genes = 0;
+    for (int32_t b = 0; b < n_inst; ++b) {
+        const int64_t n = offsets[b + 1] - offsets[b] - 1;
+        QPM_REQUIRE(n >= 1 && n <= (int64_t(1) << 27), QPM_EINVAL,
+                    "instance %d: needs 2 .. 2^27 + 1 boundaries (offsets must increase by >= 2)", (int)b);
+        QPM_REQUIRE(std::isfinite(dk1[b]) && std::isfinite(dk2[b]), QPM_EINVAL, "instance %d: dk not finite",
+                    (int)b);
+        for (int64_t k = offsets[b]; k < offsets[b + 1]; ++k)
+            QPM_REQUIRE(std::isfinite(z[k]), QPM_EINVAL, "instance %d: z[%lld] not finite", (int)b, (long long)k);
+        for (int64_t k = offsets[b]; k + 1 < offsets[b + 1]; ++k)
+            QPM_REQUIRE(z[k + 1] > z[k], QPM_EINVAL, "instance %d: z must be strictly increasing", (int)b);
+        words += words_for(n);
+        genes += ((n + 63) / 64) * 64;
+    }
+    QPM_REQUIRE(words <= (int64_t(1) << 28), QPM_ERANGE, "batch too large (%lld words)", (long long)words);
+    qpm_status st = check_device();
+    if (st != QPM_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(sv);
+    auto *bt = new qpm_batch_s();
+    bt->n_inst = n_inst;
+    bt->total_words = words;
+    bt->total_genes_stride = genes;
+    int64_t wofs = 0, xofs = 0;
+    for (int32_t b = 0; b < n_inst; ++b) {
+        InstDesc d{};
+        d.n = offsets[b + 1] - offsets[b] - 1;
+        d.words = words_for(d.n);
+        d.wofs = wofs;
+        d.ldx = ((d.n + 63) / 64) * 64;
+        d.xofs = xofs;  // in units of rows x ldx: scaled by np at run creation
+        wofs += d.words;
+        xofs += d.ldx;
+        bt->host.push_back(d);
+    }
+    double *zdev = nullptr;
+    hipError_t e = hipMalloc(&bt->ph64, sizeof(double4) * 32 * words);
+    if (e == hipSuccess) e = hipMalloc(&bt->ph32, sizeof(float4) * 32 * words);
+    if (e == hipSuccess) e = hipMalloc(&bt->c64, sizeof(double2) * 32 * words);
+    if (e == hipSuccess) e = hipMalloc(&bt->Cdev, sizeof(double) * 2 * n_inst);
+    if (e == hipSuccess) e = hipMalloc(&bt->dev, sizeof(InstDesc) * n_inst);
+    if (e == hipSuccess) e = hipMalloc(&zdev, sizeof(double) * offsets[n_inst]);
+    if (e == hipSuccess) e = hipMemcpyAsync(zdev, z, sizeof(double) * offsets[n_inst], hipMemcpyHostToDevice, s);
+    for (int32_t b = 0; b < n_inst && e == hipSuccess; ++b) {
+        const InstDesc &d = bt->host[b];
+        if (launch_phases(zdev + offsets[b], d.n, dk1[b], dk2[b], bt->ph64 + 32 * d.wofs, bt->ph32 + 32 * d.wofs,
+                          bt->c64 + 32 * d.wofs, bt->Cdev + 2 * b, s) != QPM_OK)
+            e = hipErrorLaunchFailure;
+    }
+    std::vector<double> C(2 * n_inst);
+    if (e == hipSuccess) e = hipMemcpyAsync(C.data(), bt->Cdev, sizeof(double) * 2 * n_inst, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(zdev);
+    if (e == hipSuccess) {
+        for (int32_t b = 0; b < n_inst; ++b) {
+            bt->host[b].C[0] = C[2 * b];
+            bt->host[b].C[1] = C[2 * b + 1];
+        }
+        e = hipMemcpy(bt->dev, bt->host.data(), sizeof(InstDesc) * n_inst, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        set_error("batched phase precompute failed: %s", hipGetErrorString(e));
+        free_batch(bt);
+        return e == hipErrorOutOfMemory ? QPM_ENOMEM : QPM_EHIP;
+    }
+    *out = bt;
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_batch_free(qpm_batch b)
+{
+    clear_error();
+    if (!b) return QPM_OK;
+    (void)hipDeviceSynchronize();
+    free_batch(b);
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_batch_info(qpm_batch b, int32_t *n_inst, int64_t *n_domains, double *C)
+{
+    clear_error();
+    QPM_REQUIRE(b != nullptr, QPM_EINVAL, "batch is NULL");
+    if (n_inst) *n_inst = b->n_inst;
+    for (int32_t i = 0; i < b->n_inst; ++i) {
+        if (n_domains) n_domains[i] = b->host[i].n;
+        if (C) {
+            C[2 * i] = b->host[i].C[0];
+            C[2 * i + 1] = b->host[i].C[1];
+        }
+    }
+    return QPM_OK;
+}
+
+// ---------------------------------------------------------------- batched fitness
+
+static qpm_status launch_batch_fit(const qpm_batch_s &bt, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                                   const BatchFitPlan &pl, const FitSeg *segs_dev, double *part, hipStream_t s)
+{
+    const dim3 grid(static_cast<unsigned>((np + 63) / 64), static_cast<unsigned>(pl.segs.size()));
+#define QPM_BF_CASE(NW)                                                                                           \
+    case NW:                                                                                                      \
+        if (p == QPM_PREC_F32)                                                                                    \
+            batch_fit_kernel<true, NW><<<grid, NW * 64, 0, s>>>(bits, ld, bt.ph64, bt.ph32, pl.wpw, bt.dev,       \
+                                                                segs_dev, part);                                  \
+        else                                                                                                      \
+            batch_fit_kernel<false, NW><<<grid, NW * 64, 0, s>>>(bits, ld, bt.ph64, bt.ph32, pl.wpw, bt.dev,      \
+                                                                 segs_dev, part);                                 \
+        break;
+    switch (pl.waves) {
+        QPM_BF_CASE(4)
+        QPM_BF_CASE(8)
+        QPM_BF_CASE(16)
+    default: QPM_REQUIRE(false, QPM_EINVAL, "unsupported waves per group %d", pl.waves);
+    }
+#undef QPM_BF_CASE
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
+}
+
+// device copies of a fitness plan's tables
+struct FitPlanDev {
+    FitSeg *segs = nullptr;
+    int *slot_ofs = nullptr;
+    double *part = nullptr;
+};
+
+static qpm_status upload_fit_plan(const BatchFitPlan &pl, int64_t ld, hipStream_t s, FitPlanDev *out)
+{
+    FitPlanDev d;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&d.segs), sizeof(FitSeg) * pl.segs.size(), s);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void **>(&d.slot_ofs), sizeof(int) * pl.slot_ofs.size(), s);
+    if (e == hipSuccess)
+        e = hipMallocAsync(reinterpret_cast<void **>(&d.part), sizeof(double) * 6 * pl.segs.size() * ld, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d.segs, pl.segs.data(), sizeof(FitSeg) * pl.segs.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d.slot_ofs, pl.slot_ofs.data(), sizeof(int) * pl.slot_ofs.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host vectors must outlive the copies
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(d.segs, s);
+        (void)hipFreeAsync(d.slot_ofs, s);
+        (void)hipFreeAsync(d.part, s);
+        set_error("fitness plan upload failed: %s", hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? QPM_ENOMEM : QPM_EHIP;
+    }
+    *out = d;
+    return QPM_OK;
+}
+
+static void free_fit_plan(FitPlanDev &d, hipStream_t s)
+{
+    (void)hipFreeAsync(d.segs, s);
+    (void)hipFreeAsync(d.slot_ofs, s);
+    (void)hipFreeAsync(d.part, s);
+    d = FitPlanDev{};
+}
+
+static qpm_status launch_batch_finish(int mode, const qpm_batch_s &bt, qpm_prec p, const FitPlanDev &fp, int64_t ld,
+                                      int64_t np, void *f, uint32_t *flags, int32_t *leaders, int4 *draws,
+                                      uint32_t *gen, uint64_t seed, uint32_t inst0, uint32_t *ticket, hipStream_t s)
+{
+    const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
+    if (p == QPM_PREC_F64)
+        batch_finish_kernel<double><<<bt.n_inst, 256, 0, s>>>(mode, fp.part, fp.slot_ofs, ld, np, bt.dev,
+                                                             static_cast<double *>(f), flags, leaders, draws, gen, k0,
+                                                             k1, inst0, ticket);
+    else
+        batch_finish_kernel<float><<<bt.n_inst, 256, 0, s>>>(mode, fp.part, fp.slot_ofs, ld, np, bt.dev,
+                                                            static_cast<float *>(f), flags, leaders, draws, gen, k0,
+                                                            k1, inst0, ticket);
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_batch_eval_fitness(qpm_batch b, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                                          void *fitness, int32_t waves_per_group, int32_t words_per_wave,
+                                          qpm_stream sv)
+{
+    clear_error();
+    QPM_REQUIRE(b && bits && fitness, QPM_EINVAL, "batch, bits and fitness must not be NULL");
+    QPM_REQUIRE(p == QPM_PREC_F32 || p == QPM_PREC_F64, QPM_EINVAL, "unknown precision %d", (int)p);
+    QPM_REQUIRE(np >= 1 && np <= (int64_t(1) << 24), QPM_EINVAL, "np out of range (%lld)", (long long)np);
+    QPM_REQUIRE(ld >= np && ld % 64 == 0, QPM_EINVAL, "ld (%lld) must be >= np and a multiple of 64", (long long)ld);
+    QPM_REQUIRE(waves_per_group == 0 || waves_per_group == 4 || waves_per_group == 8 || waves_per_group == 16,
+                QPM_EINVAL, "waves_per_group must be 0 (default), 4, 8 or 16");
+    QPM_REQUIRE(words_per_wave >= 0, QPM_EINVAL, "words_per_wave must be >= 0");
+    hipStream_t s = static_cast<hipStream_t>(sv);
+    int waves, wpw;
+    default_fit_shape(b->host, np, &waves, &wpw);
+    if (waves_per_group) waves = waves_per_group;
+    if (words_per_wave) wpw = words_per_wave;
+    const BatchFitPlan pl = make_fit_plan(b->host, waves, wpw);
+    QPM_REQUIRE(pl.segs.size() <= 65535, QPM_ERANGE, "too many fitness segments (%zu)", pl.segs.size());
+    FitPlanDev fp;
+    qpm_status st = upload_fit_plan(pl, ld, s, &fp);
+    if (st != QPM_OK) return st;
+    st = launch_batch_fit(*b, p, bits, np, ld, pl, fp.segs, fp.part, s);
+    if (st == QPM_OK)
+        st = launch_batch_finish(0, *b, p, fp, ld, np, fitness, nullptr, nullptr, nullptr, nullptr, 0, 0, nullptr, s);
+    free_fit_plan(fp, s);
+    return st;
+}
+
+// ---------------------------------------------------------------- the batched run
+
+struct qpm_batch_run_s {
+    const qpm_batch_s *bt = nullptr;
+    qpm_run_config cfg{};
+    hipStream_t st = nullptr;
+    int64_t ld = 0;
+    float *buf[2] = {nullptr, nullptr};
+    uint32_t *flags = nullptr;
+    void *f_cur = nullptr;
+    uint32_t *bits = nullptr;
+    int32_t *leaders = nullptr;
+    int4 *draws = nullptr;
+    uint32_t *gen = nullptr;
+    uint32_t *ticket = nullptr;
+    float *a_tab = nullptr;
+    InstDesc *inst = nullptr;  // instance table with xofs scaled by np
+    Tile *gtiles = nullptr;    // (instance, 1024-gene chunk)
+    int n_gtiles = 0;
+    Tile *dtiles = nullptr;    // (instance, DE chunk)
+    int n_dtiles = 0, de_ipw = 1, de_groups = 1;
+    BatchFitPlan fplan;
+    FitPlanDev fdev;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t done = 0;
+    bool timing = false;
+    hipEvent_t ev[QPM_K_COUNT + 1] = {};
+    double ms[QPM_K_COUNT] = {};
+    int64_t timed = 0;
+    double tune_us = 0.0;
+
+    bool f64() const { return cfg.prec == QPM_PREC_F64; }
+    BatchPop pop() const { return BatchPop{buf[0], buf[1], buf[0], buf[1], flags, cfg.np}; }
+};
+
+static void release_batch_run(qpm_batch_run_s *r)
+{
+    if (!r) return;
+    if (r->st) (void)hipStreamSynchronize(r->st);
+    if (r->exec) (void)hipGraphExecDestroy(r->exec);
+    if (r->graph) (void)hipGraphDestroy(r->graph);
+    (void)hipFree(r->buf[0]);
+    (void)hipFree(r->buf[1]);
+    (void)hipFree(r->flags);
+    (void)hipFree(r->f_cur);
+    (void)hipFree(r->bits);
+    (void)hipFree(r->leaders);
+    (void)hipFree(r->draws);
+    (void)hipFree(r->gen);
+    (void)hipFree(r->ticket);
+    (void)hipFree(r->a_tab);
+    (void)hipFree(r->inst);
+    (void)hipFree(r->gtiles);
+    (void)hipFree(r->dtiles);
+    if (r->st && r->fdev.segs) {
+        free_fit_plan(r->fdev, r->st);
+        (void)hipStreamSynchronize(r->st);
+    }
+    for (auto &e : r->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (r->st) (void)hipStreamDestroy(r->st);
+    delete r;
+}
+
+static qpm_status launch_batch_de(qpm_batch_run_s *r)
+{
+    const qpm_run_config &c = r->cfg;
+    const uint32_t k0 = static_cast<uint32_t>(c.seed), k1 = static_cast<uint32_t>(c.seed >> 32);
+    const int64_t blocks = 8 * ((r->n_dtiles + 7) / 8) * static_cast<int64_t>(r->de_groups);
+    const unsigned nb = static_cast<unsigned>(blocks);
+    const BatchPop bp = r->pop();
+#define QPM_BDE(IPW)                                                                                          \
+    batch_de_kernel<IPW><<<nb, 256, 0, r->st>>>(bp, r->inst, r->dtiles, r->n_dtiles, r->de_groups, r->draws, \
+                                                c.F, c.CR, k0, k1, r->gen, c.inst, r->bits, r->ld)
+    if (r->de_ipw == 1)
+        QPM_BDE(1);
+    else if (r->de_ipw == 2)
+        QPM_BDE(2);
+    else
+        QPM_BDE(4);
+#undef QPM_BDE
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
+}
+
+static qpm_status launch_batch_gwo(qpm_batch_run_s *r)
+{
+    const qpm_run_config &c = r->cfg;
+    const dim3 grid(static_cast<unsigned>(c.np), static_cast<unsigned>(r->n_gtiles));
+    batch_gwo_kernel<<<grid, 256, 0, r->st>>>(r->pop(), r->inst, r->gtiles, r->leaders, r->a_tab,
+                                             static_cast<uint32_t>(c.seed), static_cast<uint32_t>(c.seed >> 32),
+                                             r->gen, c.inst, c.gwo_variant, r->bits, r->ld);
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
+}
+
+static qpm_status batch_generation(qpm_batch_run_s *r, hipEvent_t *ev = nullptr)
+{
+    const qpm_run_config &c = r->cfg;
+    const qpm_prec p = static_cast<qpm_prec>(c.prec);
+    auto mark = [&](int k) -> qpm_status {
+        if (ev) QPM_TRY_HIP(hipEventRecord(ev[k], r->st));
+        return QPM_OK;
+    };
+    qpm_status st;
+#define QPM_STEP(k, call)                    \
+    if ((st = mark(k)) != QPM_OK) return st; \
+    if ((st = (call)) != QPM_OK) return st;
+    QPM_STEP(QPM_K_DE, launch_batch_de(r))
+    QPM_STEP(QPM_K_FIT_DE, launch_batch_fit(*r->bt, p, r->bits, c.np, r->ld, r->fplan, r->fdev.segs, r->fdev.part,
+                                            r->st))
+    QPM_STEP(QPM_K_FINISH_DE, launch_batch_finish(2, *r->bt, p, r->fdev, r->ld, c.np, r->f_cur, r->flags, r->leaders,
+                                                  r->draws, r->gen, c.seed, c.inst, r->ticket, r->st))
+    QPM_STEP(QPM_K_GWO, launch_batch_gwo(r))
+    QPM_STEP(QPM_K_FIT_GWO, launch_batch_fit(*r->bt, p, r->bits, c.np, r->ld, r->fplan, r->fdev.segs, r->fdev.part,
+                                             r->st))
+    QPM_STEP(QPM_K_FINISH_GWO, launch_batch_finish(3, *r->bt, p, r->fdev, r->ld, c.np, r->f_cur, r->flags,
+                                                   r->leaders, r->draws, r->gen, c.seed, c.inst, r->ticket, r->st))
+#undef QPM_STEP
+    return mark(QPM_K_COUNT);
+}
+
+// time the batched fitness for a few launch shapes on the current bits and
+// keep the fastest (results are equal up to the summation order)
+static qpm_status tune_fitness(qpm_batch_run_s *r)
+{
+    const qpm_run_config &c = r->cfg;
+    const std::string key = tune_key("batchfit", r->bt->total_words, c.np, c.prec, r->bt->n_inst);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            r->fplan = make_fit_plan(r->bt->host, it->second.first, it->second.second);
+            return QPM_OK;
+        }
+    }
+    int dw, dwpw;
+    default_fit_shape(r->bt->host, c.np, &dw, &dwpw);
+    std::vector<std::pair<int, int>> cands;
+    for (int waves : {4, 8, 16})
+        for (int f : {1, 2, 4, 8}) cands.push_back({waves, std::max(1, dwpw * f / 2)});
+    hipEvent_t e0, e1;
+    QPM_TRY_HIP(hipEventCreate(&e0));
+    QPM_TRY_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    std::pair<int, int> pick{dw, dwpw};
+    const qpm_prec p = static_cast<qpm_prec>(c.prec);
+    for (auto cand : cands) {
+        BatchFitPlan pl = make_fit_plan(r->bt->host, cand.first, cand.second);
+        if (pl.segs.size() > 65535) continue;
+        FitPlanDev fp;
+        qpm_status st = upload_fit_plan(pl, r->ld, r->st, &fp);
+        if (st != QPM_OK) return st;
+        st = launch_batch_fit(*r->bt, p, r->bits, c.np, r->ld, pl, fp.segs, fp.part, r->st);  // warm-up
+        QPM_TRY_HIP(hipEventRecord(e0, r->st));
+        for (int rep = 0; rep < 3 && st == QPM_OK; ++rep)
+            st = launch_batch_fit(*r->bt, p, r->bits, c.np, r->ld, pl, fp.segs, fp.part, r->st);
+        QPM_TRY_HIP(hipEventRecord(e1, r->st));
+        QPM_TRY_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        QPM_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+        free_fit_plan(fp, r->st);
+        if (st != QPM_OK) return st;
+        if (ms < best) {
+            best = ms;
+            pick = cand;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    QPM_TRY_HIP(hipStreamSynchronize(r->st));
+    r->tune_us = best * 1000.0 / 3.0;
+    r->fplan = make_fit_plan(r->bt->host, pick.first, pick.second);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_store_locked(key, pick.first, pick.second);
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, int32_t tune, qpm_stream sv,
+                                        qpm_batch_run_handle *out)
+{
+    clear_error();
+    QPM_REQUIRE(b && cfg && out, QPM_EINVAL, "batch, cfg and out must not be NULL");
+    const qpm_run_config c = *cfg;
+    QPM_REQUIRE(c.np >= 4 && c.np <= 4096, QPM_EINVAL, "batched runs need 4 <= np <= 4096 (got %lld)",
+                (long long)c.np);
+    QPM_REQUIRE(c.generations >= 1 && c.generations <= (int64_t(1) << 31) - 2, QPM_EINVAL, "generations out of range");
+    QPM_REQUIRE(c.F >= 0.0f && c.F <= 2.0f, QPM_EINVAL, "F must be in [0, 2]");
+    QPM_REQUIRE(c.CR >= 0.0f && c.CR <= 1.0f, QPM_EINVAL, "CR must be in [0, 1]");
+    QPM_REQUIRE(c.prec == QPM_PREC_F32 || c.prec == QPM_PREC_F64, QPM_EINVAL, "unknown precision %d", c.prec);
+    QPM_REQUIRE(c.gwo_variant == 0 || c.gwo_variant == 1, QPM_EINVAL, "gwo_variant must be 0 or 1");
+    QPM_REQUIRE(static_cast<int64_t>(c.inst) + b->n_inst <= (int64_t(1) << 24), QPM_EINVAL,
+                "inst + n_inst must be <= 2^24");
+    qpm_status st = check_device();
+    if (st != QPM_OK) return st;
+    auto *r = new qpm_batch_run_s();
+    r->bt = b;
+    r->cfg = c;
+    r->ld = ((c.np + 63) / 64) * 64;
+    const int64_t n_inst = b->n_inst;
+    // instance table with gene offsets for np rows per instance
+    std::vector<InstDesc> h = b->host;
+    int64_t xofs = 0;
+    for (auto &d : h) {
+        d.xofs = xofs;
+        xofs += c.np * d.ldx;
+    }
+    const size_t gene_bytes = sizeof(float) * static_cast<size_t>(xofs);
+    // tiles
+    std::vector<Tile> gt, dt;
+    const int64_t row_bytes = 2 * 1024 * 1024 / c.np;
+    r->de_ipw = row_bytes >= 1024 ? 1 : (row_bytes >= 512 ? 2 : 4);
+    const int64_t cw = 256 / r->de_ipw;
+    r->de_groups = static_cast<int>((c.np + 4 * r->de_ipw - 1) / (4 * r->de_ipw));
+    for (int32_t i = 0; i < b->n_inst; ++i) {
+        for (int64_t ch = 0; ch * 1024 < h[i].n; ++ch) gt.push_back(Tile{i, static_cast<int>(ch)});
+        for (int64_t ch = 0; ch * cw < h[i].n; ++ch) dt.push_back(Tile{i, static_cast<int>(ch)});
+    }
+    r->n_gtiles = static_cast<int>(gt.size());
+    r->n_dtiles = static_cast<int>(dt.size());
+    hipError_t e = hipStreamCreateWithFlags(&r->st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&r->buf[0], gene_bytes);
+    if (e == hipSuccess) e = hipMalloc(&r->buf[1], gene_bytes);
+    if (e == hipSuccess) e = hipMalloc(&r->flags, sizeof(uint32_t) * n_inst * c.np);
+    if (e == hipSuccess) e = hipMalloc(&r->f_cur, (r->f64() ? 8 : 4) * n_inst * c.np);
+    if (e == hipSuccess) e = hipMalloc(&r->bits, sizeof(uint32_t) * b->total_words * r->ld);
+    if (e == hipSuccess) e = hipMalloc(&r->leaders, sizeof(int32_t) * 3 * n_inst);
+    if (e == hipSuccess) e = hipMalloc(&r->draws, sizeof(int4) * n_inst * c.np);
+    if (e == hipSuccess) e = hipMalloc(&r->gen, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&r->ticket, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&r->a_tab, sizeof(float) * c.generations);
+    if (e == hipSuccess) e = hipMalloc(&r->inst, sizeof(InstDesc) * n_inst);
+    if (e == hipSuccess) e = hipMalloc(&r->gtiles, sizeof(Tile) * gt.size());
+    if (e == hipSuccess) e = hipMalloc(&r->dtiles, sizeof(Tile) * dt.size());
+    if (e != hipSuccess) {
+        set_error("batched run allocation failed: %s", hipGetErrorString(e));
+        release_batch_run(r);
+        return e == hipErrorOutOfMemory ? QPM_ENOMEM : QPM_EHIP;
+    }
+    std::vector<float> a(c.generations);
+    for (int64_t g = 0; g < c.generations; ++g)
+        a[g] = static_cast<float>(2.0 * (1.0 - static_cast<double>(g) / static_cast<double>(c.generations)));
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, static_cast<hipStream_t>(sv));
+    if (e == hipSuccess) e = hipStreamWaitEvent(r->st, ev, 0);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->a_tab, a.data(), sizeof(float) * c.generations, hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->inst, h.data(), sizeof(InstDesc) * n_inst, hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->gtiles, gt.data(), sizeof(Tile) * gt.size(), hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->dtiles, dt.data(), sizeof(Tile) * dt.size(), hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess) e = hipMemsetAsync(r->flags, 0, sizeof(uint32_t) * n_inst * c.np, r->st);
+    if (e == hipSuccess) e = hipMemsetAsync(r->gen, 0, sizeof(uint32_t), r->st);
+    if (e == hipSuccess) e = hipMemsetAsync(r->ticket, 0, sizeof(uint32_t), r->st);
+    if (e == hipSuccess) e = hipMemsetAsync(r->bits, 0, sizeof(uint32_t) * b->total_words * r->ld, r->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(r->st);
+    if (ev) (void)hipEventDestroy(ev);
+    if (e != hipSuccess) {
+        set_error("batched run set-up failed: %s", hipGetErrorString(e));
+        release_batch_run(r);
+        return QPM_EHIP;
+    }
+    // step 1: initialise every instance
+    {
+        const dim3 grid(static_cast<unsigned>(c.np), static_cast<unsigned>(r->n_gtiles));
+        batch_init_kernel<<<grid, 256, 0, r->st>>>(c.np, r->inst, r->gtiles, static_cast<uint32_t>(c.seed),
+                                                  static_cast<uint32_t>(c.seed >> 32), c.inst, r->buf[0], r->bits,
+                                                  r->ld);
+        e = hipGetLastError();
+        if (e != hipSuccess) {
+            set_error("batched init launch failed: %s", hipGetErrorString(e));
+            release_batch_run(r);
+            return QPM_EHIP;
+        }
+    }
+    if (tune) {
+        st = tune_fitness(r);
+    } else {
+        int dw, dwpw;
+        default_fit_shape(b->host, c.np, &dw, &dwpw);
+        r->fplan = make_fit_plan(b->host, dw, dwpw);
+    }
+    if (st == QPM_OK && r->fplan.segs.size() > 65535) {
+        set_error("too many fitness segments (%zu)", r->fplan.segs.size());
+        st = QPM_ERANGE;
+    }
+    if (st == QPM_OK) st = upload_fit_plan(r->fplan, r->ld, r->st, &r->fdev);
+    const qpm_prec p = static_cast<qpm_prec>(c.prec);
+    if (st == QPM_OK) st = launch_batch_fit(*b, p, r->bits, c.np, r->ld, r->fplan, r->fdev.segs, r->fdev.part, r->st);
+    if (st == QPM_OK)
+        st = launch_batch_finish(1, *b, p, r->fdev, r->ld, c.np, r->f_cur, r->flags, r->leaders, r->draws, r->gen,
+                                 c.seed, c.inst, r->ticket, r->st);
+    if (st == QPM_OK && c.use_graph) {
+        e = hipStreamBeginCapture(r->st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            set_error("hipStreamBeginCapture failed: %s", hipGetErrorString(e));
+            st = QPM_EHIP;
+        } else {
+            st = batch_generation(r);
+            hipError_t e2 = hipStreamEndCapture(r->st, &r->graph);
+            if (st == QPM_OK && e2 != hipSuccess) {
+                set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e2));
+                st = QPM_EHIP;
+            }
+            if (st == QPM_OK && hipGraphInstantiate(&r->exec, r->graph, nullptr, nullptr, 0) != hipSuccess) {
+                set_error("hipGraphInstantiate failed");
+                st = QPM_EHIP;
+            }
+        }
+    }
+    if (st != QPM_OK) {
+        release_batch_run(r);
+        return st;
+    }
+    *out = r;
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_batch_run_advance(qpm_batch_run_handle r, int64_t generations)
+{
+    clear_error();
+    QPM_REQUIRE(r != nullptr, QPM_EINVAL, "run is NULL");
+    QPM_REQUIRE(generations >= 0 && r->done + generations <= r->cfg.generations, QPM_EINVAL,
+                "advancing %lld generations would pass the configured %lld (done %lld)", (long long)generations,
+                (long long)r->cfg.generations, (long long)r->done);
+    for (int64_t g = 0; g < generations; ++g) {
+        if (r->timing) {
+            qpm_status st = batch_generation(r, r->ev);
+            if (st != QPM_OK) return st;
+            QPM_TRY_HIP(hipEventSynchronize(r->ev[QPM_K_COUNT]));
+            for (int k = 0; k < QPM_K_COUNT; ++k) {
+                float t = 0.0f;
+                QPM_TRY_HIP(hipEventElapsedTime(&t, r->ev[k], r->ev[k + 1]));
+                r->ms[k] += t;
+            }
+            ++r->timed;
+        } else if (r->exec) {
+            QPM_TRY_HIP(hipGraphLaunch(r->exec, r->st));
+        } else {
+            qpm_status st = batch_generation(r);
+            if (st != QPM_OK) return st;
+        }
+        ++r->done;
+    }
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_batch_run_set_timing(qpm_batch_run_handle r, int32_t enable)
+{
+    clear_error();
+    QPM_REQUIRE(r != nullptr, QPM_EINVAL, "run is NULL");
+    if (enable && !r->ev[0])
+        for (auto &e : r->ev) QPM_TRY_HIP(hipEventCreate(&e));
+    r->timing = enable != 0;
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_batch_run_timing(qpm_batch_run_handle r, double *ms, int64_t *generations, int32_t reset)
+{
+    clear_error();
+    QPM_REQUIRE(r != nullptr, QPM_EINVAL, "run is NULL");
+    if (ms)
+        for (int k = 0; k < QPM_K_COUNT; ++k) ms[k] = r->ms[k];
+    if (generations) *generations = r->timed;
+    if (reset) {
+        for (double &v : r->ms) v = 0.0;
+        r->timed = 0;
+    }
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_batch_run_read(qpm_batch_run_handle r, int32_t inst, float *x, int64_t ldx, void *fitness,
+                                      int32_t *leaders, int32_t *fit_shape)
+{
+    clear_error();
+    QPM_REQUIRE(r != nullptr, QPM_EINVAL, "run is NULL");
+    QPM_REQUIRE(inst >= 0 && inst < r->bt->n_inst, QPM_EINVAL, "instance %d out of range", (int)inst);
+    const InstDesc &d = r->bt->host[inst];
+    if (x) {
+        QPM_REQUIRE(ldx >= d.n, QPM_EINVAL, "ldx (%lld) must be >= the instance's N (%lld)", (long long)ldx,
+                    (long long)d.n);
+        const int64_t blocks = (d.n + 255) / 256;
+        batch_gather_kernel<<<dim3(static_cast<unsigned>(blocks < 64 ? blocks : 64),
+                                   static_cast<unsigned>(r->cfg.np)),
+                              256, 0, r->st>>>(r->pop(), r->inst, inst, x, ldx);
+        QPM_TRY_HIP(hipGetLastError());
+    }
+    const size_t es = r->f64() ? sizeof(double) : sizeof(float);
+    if (fitness)
+        QPM_TRY_HIP(hipMemcpyAsync(fitness, static_cast<char *>(r->f_cur) + es * r->cfg.np * inst, es * r->cfg.np,
+                                   hipMemcpyDeviceToDevice, r->st));
+    if (leaders)
+        QPM_TRY_HIP(hipMemcpyAsync(leaders, r->leaders + 3 * inst, sizeof(int32_t) * 3, hipMemcpyDeviceToHost, r->st));
+    QPM_TRY_HIP(hipStreamSynchronize(r->st));
+    if (fit_shape) {
+        fit_shape[0] = r->fplan.waves;
+        fit_shape[1] = r->fplan.wpw;
+    }
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_batch_run_destroy(qpm_batch_run_handle r)
+{
+    clear_error();
+    release_batch_run(r);
+    return QPM_OK;
+}

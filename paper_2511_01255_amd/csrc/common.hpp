@@ -54,6 +54,11 @@ struct Design {
     int device = 0;
 };
 
+// per-domain tables of one design into caller buffers (npad = 32 W
+// entries of ph64 / ph32, n of c64) and C = sum c_n into Cdev[2]
+qpm_status launch_phases(const double *zdev, int64_t n, double dk1, double dk2, double4 *ph64, float4 *ph32,
+                         double2 *c64, double *Cdev, hipStream_t s);
+
 // ---------------------------------------------------------------- fitness
 
 struct FitPlan {

@@ -20,68 +20,9 @@
 
 #include "common.hpp"
 #include "device_common.hpp"
+#include "genes.hpp"
 
 namespace qpm {
-
-__device__ __forceinline__ const float *row_of(const PopView &pv, int64_t r)
-{
-    const bool second = pv.flags != nullptr && pv.flags[r] != 0u;
-    return (second ? pv.x1 : pv.x0) + r * pv.ldx;
-}
-
-__device__ __forceinline__ float *out_row_of(const PopView &pv, int64_t r)
-{
-    const bool second = pv.flags != nullptr && pv.flags[r] != 0u;
-    return (second ? pv.out0 : pv.out1) + r * pv.ldx;
-}
-
-__device__ __forceinline__ float clamp1(float v) { return fminf(fmaxf(v, -1.0f), 1.0f); }
-
-// x / 3 correctly rounded, without a division: q0 = x RN(1/3), the exact
-// remainder r = x - 3 q0 by FMA, one FMA correction, and the sign of x
-// restored (only -0 would otherwise come out as +0). Checked against IEEE
-// division for every finite binary32 input.
-__device__ __forceinline__ float div3(float x)
-{
-    const float c = 0x1.555556p-2f;  // RN(1/3)
-    const float q0 = x * c;
-    const float r = fmaf(-q0, 3.0f, x);
-    return copysignf(fmaf(r, c, q0), x);
-}
-
-__device__ __forceinline__ void store_quad(float *dst, int64_t j0, int64_t D, float4 v)
-{
-    if (j0 + 3 < D) {
-        *reinterpret_cast<float4 *>(dst + j0) = v;
-    } else {
-        dst[j0] = v.x;
-        if (j0 + 1 < D) dst[j0 + 1] = v.y;
-        if (j0 + 2 < D) dst[j0 + 2] = v.z;
-    }
-}
-
-__device__ __forceinline__ uint32_t quad_nibble(float4 v, int64_t j0, int64_t D)
-{
-    uint32_t n = 0;
-    n |= (v.x < 0.0f) ? 1u : 0u;
-    n |= (j0 + 1 < D && v.y < 0.0f) ? 2u : 0u;
-    n |= (j0 + 2 < D && v.z < 0.0f) ? 4u : 0u;
-    n |= (j0 + 3 < D && v.w < 0.0f) ? 8u : 0u;
-    return n;
-}
-
-// Merge the nibbles of 8 neighbouring lanes (gene quads 8w .. 8w+7) into
-// word w and store it from the first lane of the group. Every lane of the
-// wave must call this (it shuffles).
-__device__ __forceinline__ void store_word(uint32_t nib, int64_t q, bool valid, uint32_t *bits, int64_t ld,
-                                           int64_t i)
-{
-    uint32_t w = nib << (4 * (threadIdx.x & 7));
-    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 1));
-    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 2));
-    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 4));
-    if (valid && (threadIdx.x & 7) == 0) bits[(q >> 3) * ld + i] = w;
-}
 
 // ------------------------------------------------------------ initialisation
 
@@ -155,21 +96,7 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
         const float4 a = *reinterpret_cast<const float4 *>(row_of(pv, dr.x) + j0);
         const float4 bq = *reinterpret_cast<const float4 *>(row_of(pv, dr.y) + j0);
         const float4 cq = *reinterpret_cast<const float4 *>(row_of(pv, dr.z) + j0);
-        const U4 r = philox10(static_cast<uint32_t>(j0 >> 2), static_cast<uint32_t>(i), g, (inst << 8) | kTagDeCr,
-                              k0, k1);
-        const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
-        const float as[4] = {a.x, a.y, a.z, a.w};
-        const float bs[4] = {bq.x, bq.y, bq.z, bq.w};
-        const float cs[4] = {cq.x, cq.y, cq.z, cq.w};
-        const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
-        float us[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const bool take = (unit24(rw[e]) <= CR) || (j0 + e == dr.w);
-            const float v = clamp1(fmaf(F, bs[e] - cs[e], as[e]));
-            us[e] = take ? v : xs[e];
-        }
-        const float4 uv = make_float4(us[0], us[1], us[2], us[3]);
+        const float4 uv = de_quad(xv, a, bq, cq, j0, dr.w, static_cast<uint32_t>(i), g, inst, k0, k1, F, CR);
         store_quad(out_row_of(pv, i), j0, D, uv);
         nib = quad_nibble(uv, j0, D);
     }
@@ -207,7 +134,6 @@ __global__ __launch_bounds__(256) void gwo_kernel(PopView pv, const int32_t *__r
     const uint32_t g = gen_dev ? gen_dev[0] : gen_c;
     const float a = a_tab ? a_tab[g] : a_c;
     const float two_a = 2.0f * a;
-    const uint32_t c3 = (inst << 8) | kTagGwo;
 
     const int64_t q = static_cast<int64_t>(blockIdx.y) * 256 + threadIdx.x;
     const int64_t j0 = 4 * q;
@@ -218,41 +144,8 @@ __global__ __launch_bounds__(256) void gwo_kernel(PopView pv, const int32_t *__r
         const float4 X0 = *reinterpret_cast<const float4 *>(row_of(pv, L0) + j0);
         const float4 X1 = *reinterpret_cast<const float4 *>(row_of(pv, L1) + j0);
         const float4 X2 = *reinterpret_cast<const float4 *>(row_of(pv, L2) + j0);
-        const uint32_t cq = static_cast<uint32_t>(3 * q);
-        const U4 wa = philox10(cq, static_cast<uint32_t>(i), g, c3, k0, k1);
-        const U4 wb = philox10(cq + 1u, static_cast<uint32_t>(i), g, c3, k0, k1);
-        const U4 wc = philox10(cq + 2u, static_cast<uint32_t>(i), g, c3, k0, k1);
-        // word t of the quad: gene e = t / 3, leader k = t % 3
-        const uint32_t wrd[12] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w, wc.x, wc.y, wc.z, wc.w};
-        const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
-        const float Xs[3][4] = {{X0.x, X0.y, X0.z, X0.w}, {X1.x, X1.y, X1.z, X1.w}, {X2.x, X2.y, X2.z, X2.w}};
-        float ys[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            float Y[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const uint32_t o = wrd[3 * e + k];
-                const float r1 = static_cast<float>(o & 0xFFFFu) * 0x1p-16f;
-                const float A = fmaf(two_a, r1, -a);
-                const float Cc = static_cast<float>(o >> 16) * 0x1p-15f;  // = 2 r2, exactly
-                const float Dk = fabsf(fmaf(Cc, Xs[k][e], -xs[e]));
-                Y[k] = fmaf(-A, Dk, Xs[k][e]);
-            }
-            float yv;
-            if (variant == 1) {
-                yv = div3((Y[0] + Y[1]) + Y[2]);
-            } else {
-                const float s = (fabsf(Y[0]) + fabsf(Y[1])) + fabsf(Y[2]);
-                const float num = fmaf(fabsf(Y[2]), Y[2], fmaf(fabsf(Y[1]), Y[1], fabsf(Y[0]) * Y[0]));
-                // evaluated unconditionally (no divergent branch); the 0/0 of
-                // s == 0 is selected away
-                const float qv = div3(num / s);
-                yv = (s == 0.0f) ? 0.0f : qv;
-            }
-            ys[e] = clamp1(yv);
-        }
-        const float4 yv4 = make_float4(ys[0], ys[1], ys[2], ys[3]);
+        const float4 yv4 = gwo_quad(xv, X0, X1, X2, static_cast<uint32_t>(q), static_cast<uint32_t>(i), g, inst, k0,
+                                    k1, a, two_a, variant);
         store_quad(out_row_of(pv, i), j0, D, yv4);
         nib = quad_nibble(yv4, j0, D);
     }

@@ -15,89 +15,9 @@
 // small pass combines workgroup segments in order. No float atomics: the
 // result depends only on the launch plan, never on timing.
 #include "common.hpp"
+#include "scan.hpp"
 
 namespace qpm {
-
-// +-1.0 from bit k of w (bit set -> -1), as a double and as a float
-__device__ __forceinline__ double sign64(uint32_t w, int k)
-{
-    const uint32_t hi = ((w << (31 - k)) & 0x80000000u) | 0x3ff00000u;
-    return __hiloint2double(static_cast<int>(hi), 0);
-}
-__device__ __forceinline__ float sign32(uint32_t w, int k)
-{
-    return __uint_as_float(((w << (31 - k)) & 0x80000000u) | 0x3f800000u);
-}
-
-struct Tri {
-    double ar, ai, br, bi, qr, qi;
-};
-
-// t <- t (+) u   (t covers the domains before u)
-__device__ __forceinline__ void tri_append(Tri &t, const Tri &u)
-{
-    t.qr = fma(t.ar, u.br, fma(-t.ai, u.bi, t.qr + u.qr));
-    t.qi = fma(t.ar, u.bi, fma(t.ai, u.br, t.qi + u.qi));
-    t.ar += u.ar;
-    t.ai += u.ai;
-    t.br += u.br;
-    t.bi += u.bi;
-}
-
-__device__ __forceinline__ void store_fitness(void *fit, int out_f64, int64_t i, const Tri &t,
-                                              const double *__restrict__ C)
-{
-    const double sr = t.qr + C[0], si = t.qi + C[1];
-    const double f = fma(sr, sr, si * si);
-    if (out_f64)
-        static_cast<double *>(fit)[i] = f;
-    else
-        static_cast<float *>(fit)[i] = static_cast<float>(f);
-}
-
-// One word (32 domains) in FP64.
-__device__ __forceinline__ void scan_word_f64(Tri &t, uint32_t word, const double4 *__restrict__ p)
-{
-#pragma unroll
-    for (int k = 0; k < 32; ++k) {
-        const double4 c = p[k];  // {a.re, a.im, b.re, b.im}, wave-uniform
-        const double s = sign64(word, k);
-        const double tr = fma(c.z, t.ar, -(c.w * t.ai));
-        const double ti = fma(c.z, t.ai, c.w * t.ar);
-        t.qr = fma(s, tr, t.qr);
-        t.qi = fma(s, ti, t.qi);
-        t.ar = fma(s, c.x, t.ar);
-        t.ai = fma(s, c.y, t.ai);
-        t.br = fma(s, c.z, t.br);
-        t.bi = fma(s, c.w, t.bi);
-    }
-}
-
-// One word in FP32 blocks of BLK domains, each block folded into FP64.
-template <int BLK>
-__device__ __forceinline__ void scan_word_f32(Tri &t, uint32_t word, const float4 *__restrict__ p)
-{
-#pragma unroll
-    for (int h = 0; h < 32 / BLK; ++h) {
-        float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f, qr = 0.f, qi = 0.f;
-#pragma unroll
-        for (int kk = 0; kk < BLK; ++kk) {
-            const int k = h * BLK + kk;
-            const float4 c = p[k];
-            const float s = sign32(word, k);
-            const float tr = fmaf(c.z, ar, -(c.w * ai));
-            const float ti = fmaf(c.z, ai, c.w * ar);
-            qr = fmaf(s, tr, qr);
-            qi = fmaf(s, ti, qi);
-            ar = fmaf(s, c.x, ar);
-            ai = fmaf(s, c.y, ai);
-            br = fmaf(s, c.z, br);
-            bi = fmaf(s, c.w, bi);
-        }
-        const Tri u{ar, ai, br, bi, qr, qi};
-        tri_append(t, u);
-    }
-}
 
 template <bool F32, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void fit_seg_kernel(const uint32_t *__restrict__ bits, int64_t ld, int W,

@@ -1,0 +1,146 @@
+// genes.hpp -- per-gene-quad arithmetic of the optimiser steps (paper Sec.
+// 2.2.1 DE rand/1 + binomial crossover, Sec. 2.2.2 grey-wolf update), and
+// the row / bit-word helpers, shared by the single-design and batched
+// kernels. Binary32 arithmetic is spelled out with explicit fmaf and the
+// library is built with -ffp-contract=off, so trial and candidate genes are
+// bit-for-bit what these formulas state.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.hpp"
+#include "philox.hpp"
+
+namespace qpm {
+
+__device__ __forceinline__ const float *row_of(const PopView &pv, int64_t r)
+{
+    const bool second = pv.flags != nullptr && pv.flags[r] != 0u;
+    return (second ? pv.x1 : pv.x0) + r * pv.ldx;
+}
+
+__device__ __forceinline__ float *out_row_of(const PopView &pv, int64_t r)
+{
+    const bool second = pv.flags != nullptr && pv.flags[r] != 0u;
+    return (second ? pv.out0 : pv.out1) + r * pv.ldx;
+}
+
+__device__ __forceinline__ float clamp1(float v) { return fminf(fmaxf(v, -1.0f), 1.0f); }
+
+// x / 3 correctly rounded, without a division: q0 = x RN(1/3), the exact
+// remainder r = x - 3 q0 by FMA, one FMA correction, and the sign of x
+// restored (only -0 would otherwise come out as +0). Checked against IEEE
+// division for every finite binary32 input.
+__device__ __forceinline__ float div3(float x)
+{
+    const float c = 0x1.555556p-2f;  // RN(1/3)
+    const float q0 = x * c;
+    const float r = fmaf(-q0, 3.0f, x);
+    return copysignf(fmaf(r, c, q0), x);
+}
+
+__device__ __forceinline__ void store_quad(float *dst, int64_t j0, int64_t D, float4 v)
+{
+    if (j0 + 3 < D) {
+        *reinterpret_cast<float4 *>(dst + j0) = v;
+    } else {
+        dst[j0] = v.x;
+        if (j0 + 1 < D) dst[j0 + 1] = v.y;
+        if (j0 + 2 < D) dst[j0 + 2] = v.z;
+    }
+}
+
+__device__ __forceinline__ uint32_t quad_nibble(float4 v, int64_t j0, int64_t D)
+{
+    uint32_t n = 0;
+    n |= (v.x < 0.0f) ? 1u : 0u;
+    n |= (j0 + 1 < D && v.y < 0.0f) ? 2u : 0u;
+    n |= (j0 + 2 < D && v.z < 0.0f) ? 4u : 0u;
+    n |= (j0 + 3 < D && v.w < 0.0f) ? 8u : 0u;
+    return n;
+}
+
+// Merge the nibbles of 8 neighbouring lanes (gene quads 8w .. 8w+7) into
+// word w and store it from the first lane of the group. Every lane of the
+// wave must call this (it shuffles).
+__device__ __forceinline__ void store_word(uint32_t nib, int64_t q, bool valid, uint32_t *bits, int64_t ld,
+                                           int64_t i)
+{
+    uint32_t w = nib << (4 * (threadIdx.x & 7));
+    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 1));
+    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 2));
+    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 4));
+    if (valid && (threadIdx.x & 7) == 0) bits[(q >> 3) * ld + i] = w;
+}
+
+// DE for genes j0..j0+3 of individual i: v = clamp(fmaf(F, b - c, a)),
+// u_j = v_j where ((w_j >> 8) 2^-24 <= CR) or j == jrand, else x_j, with
+// the words w of Philox counter (j0 / 4, i, g, inst << 8 | DE_CR).
+__device__ __forceinline__ float4 de_quad(float4 xv, float4 a, float4 b, float4 c, int64_t j0, int jrand, uint32_t i,
+                                          uint32_t g, uint32_t inst, uint32_t k0, uint32_t k1, float F, float CR)
+{
+    const U4 r = philox10(static_cast<uint32_t>(j0 >> 2), i, g, (inst << 8) | kTagDeCr, k0, k1);
+    const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+    const float as[4] = {a.x, a.y, a.z, a.w};
+    const float bs[4] = {b.x, b.y, b.z, b.w};
+    const float cs[4] = {c.x, c.y, c.z, c.w};
+    const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+    float us[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const bool take = (unit24(rw[e]) <= CR) || (j0 + e == jrand);
+        const float v = clamp1(fmaf(F, bs[e] - cs[e], as[e]));
+        us[e] = take ? v : xs[e];
+    }
+    return make_float4(us[0], us[1], us[2], us[3]);
+}
+
+// Grey-wolf update of gene quad q of a non-leader: per gene e and leader k,
+// word t = 3e + k of the counters (3q + t / 4, i, g, inst << 8 | GWO) gives
+// r1 = lo16 2^-16 and C = 2 r2 = hi16 2^-15; A = fmaf(2a, r1, -a),
+// D_k = |fmaf(C, X_k, -x)|, Y_k = fmaf(-A, D_k, X_k); then the weighted
+// combination (variant 0) or the mean (variant 1), divided by 3, clamped.
+__device__ __forceinline__ float4 gwo_quad(float4 xv, float4 X0, float4 X1, float4 X2, uint32_t q, uint32_t i,
+                                           uint32_t g, uint32_t inst, uint32_t k0, uint32_t k1, float a, float two_a,
+                                           int variant)
+{
+    const uint32_t c3 = (inst << 8) | kTagGwo;
+    const uint32_t cq = 3u * q;
+    const U4 wa = philox10(cq, i, g, c3, k0, k1);
+    const U4 wb = philox10(cq + 1u, i, g, c3, k0, k1);
+    const U4 wc = philox10(cq + 2u, i, g, c3, k0, k1);
+    const uint32_t wrd[12] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w, wc.x, wc.y, wc.z, wc.w};
+    const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+    const float Xs[3][4] = {{X0.x, X0.y, X0.z, X0.w}, {X1.x, X1.y, X1.z, X1.w}, {X2.x, X2.y, X2.z, X2.w}};
+    float ys[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        float Y[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const uint32_t o = wrd[3 * e + k];
+            const float r1 = static_cast<float>(o & 0xFFFFu) * 0x1p-16f;
+            const float A = fmaf(two_a, r1, -a);
+            const float Cc = static_cast<float>(o >> 16) * 0x1p-15f;  // = 2 r2, exactly
+            const float Dk = fabsf(fmaf(Cc, Xs[k][e], -xs[e]));
+            Y[k] = fmaf(-A, Dk, Xs[k][e]);
+        }
+        float yv;
+        if (variant == 1) {
+            yv = div3((Y[0] + Y[1]) + Y[2]);
+        } else {
+            const float s = (fabsf(Y[0]) + fabsf(Y[1])) + fabsf(Y[2]);
+            const float num = fmaf(fabsf(Y[2]), Y[2], fmaf(fabsf(Y[1]), Y[1], fabsf(Y[0]) * Y[0]));
+            // evaluated unconditionally (no divergent branch); the 0/0 of
+            // s == 0 is selected away
+            const float qv = div3(num / s);
+            yv = (s == 0.0f) ? 0.0f : qv;
+        }
+        ys[e] = clamp1(yv);
+    }
+    return make_float4(ys[0], ys[1], ys[2], ys[3]);
+}
+
+}  // namespace qpm

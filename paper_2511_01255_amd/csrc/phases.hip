@@ -172,6 +172,20 @@ __global__ __launch_bounds__(256) void sum_c_kernel(const double2 *__restrict__ 
     }
 }
 
+qpm_status launch_phases(const double *zdev, int64_t n, double dk1, double dk2, double4 *ph64, float4 *ph32,
+                         double2 *c64, double *Cdev, hipStream_t s)
+{
+    static const GLRule16 gl = make_gl16();
+    const int64_t npad = words_for(n) * 32;
+    const int64_t blocks = (npad + 255) / 256;
+    phases_kernel<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(zdev, n, npad, dk1, dk2, gl, ph64, ph32,
+                                                                           c64);
+    QPM_TRY_HIP(hipGetLastError());
+    sum_c_kernel<<<1, 256, 0, s>>>(c64, n, Cdev);
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
+}
+
 static void free_design(Design *d)
 {
     if (!d) return;
@@ -223,18 +237,9 @@ QPM_API qpm_status qpm_precompute_phases(const double *z, int64_t n, double dk1,
         set_error("device allocation for a design of %lld domains failed: %s", (long long)n, hipGetErrorString(e));
         return QPM_ENOMEM;
     }
-    const GLRule16 gl = make_gl16();
     e = hipMemcpyAsync(zdev, z, sizeof(double) * (n + 1), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) {
-        const int64_t blocks = (npad + 255) / 256;
-        phases_kernel<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(zdev, n, npad, dk1, dk2, gl, d->ph64,
-                                                                               d->ph32, d->c64);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) {
-        sum_c_kernel<<<1, 256, 0, s>>>(d->c64, n, d->Cdev);
-        e = hipGetLastError();
-    }
+    if (e == hipSuccess && launch_phases(zdev, n, dk1, dk2, d->ph64, d->ph32, d->c64, d->Cdev, s) != QPM_OK)
+        e = hipErrorLaunchFailure;
     if (e == hipSuccess) e = hipMemcpyAsync(d->C, d->Cdev, sizeof(double) * 2, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(zdev);

@@ -70,6 +70,16 @@ _SIGS = {
     "qpm_run_set_timing": (_I32, [_P, _I32]),
     "qpm_run_timing": (_I32, [_P, _P, _P, _I32]),
     "qpm_run": (_I32, [_P, C.POINTER(RunConfig), _P, _P, C.POINTER(RunStats), _P]),
+    "qpm_precompute_phases_batched": (_I32, [_P, _P, _I32, _P, _P, _P, C.POINTER(_P)]),
+    "qpm_batch_free": (_I32, [_P]),
+    "qpm_batch_info": (_I32, [_P, _P, _P, _P]),
+    "qpm_batch_eval_fitness": (_I32, [_P, _I32, _P, _I64, _I64, _P, _I32, _I32, _P]),
+    "qpm_batch_run_create": (_I32, [_P, C.POINTER(RunConfig), _I32, _P, C.POINTER(_P)]),
+    "qpm_batch_run_advance": (_I32, [_P, _I64]),
+    "qpm_batch_run_set_timing": (_I32, [_P, _I32]),
+    "qpm_batch_run_timing": (_I32, [_P, _P, _P, _I32]),
+    "qpm_batch_run_read": (_I32, [_P, _I32, _P, _I64, _P, _P, _P]),
+    "qpm_batch_run_destroy": (_I32, [_P]),
 }
 
 
@@ -347,3 +357,108 @@ def run(design, np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, 
     st = RunStats()
     _check(lib().qpm_run(design.handle, C.byref(cfg), _ptr(bx), _ptr(bb), C.byref(st), _stream(stream)))
     return bx, bb, st
+
+
+class Batch:
+    """Many independent designs with concatenated device tables."""
+
+    def __init__(self, handle, ns):
+        self._h = handle
+        self.ns = list(ns)
+        self.n_inst = len(ns)
+        self.words = [words(n) for n in ns]
+        self.word_ofs = np.concatenate([[0], np.cumsum(self.words)]).astype(np.int64)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        n = C.c_int32()
+        ns = np.zeros(self.n_inst, dtype=np.int64)
+        Cc = np.zeros(2 * self.n_inst)
+        _check(lib().qpm_batch_info(self._h, C.byref(n), ns.ctypes.data, Cc.ctypes.data))
+        return ns, Cc[0::2] + 1j * Cc[1::2]
+
+    def free(self):
+        if self._h is not None and _lib is not None:
+            _lib.qpm_batch_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def precompute_phases_batched(zs, dk1s, dk2s, stream=None):
+    """zs: list of boundary arrays (N_b + 1 each); dk1s, dk2s: per instance."""
+    zs = [np.ascontiguousarray(z, dtype=np.float64) for z in zs]
+    offsets = np.concatenate([[0], np.cumsum([len(z) for z in zs])]).astype(np.int64)
+    zc = np.ascontiguousarray(np.concatenate(zs))
+    d1 = np.ascontiguousarray(dk1s, dtype=np.float64)
+    d2 = np.ascontiguousarray(dk2s, dtype=np.float64)
+    h = C.c_void_p()
+    _check(lib().qpm_precompute_phases_batched(zc.ctypes.data, offsets.ctypes.data, len(zs), d1.ctypes.data,
+                                               d2.ctypes.data, _stream(stream), C.byref(h)))
+    return Batch(h, [len(z) - 1 for z in zs])
+
+
+def batch_eval_fitness(batch, bits, np_, prec=PREC_F32, waves_per_group=0, words_per_wave=0, out=None,
+                       stream=None):
+    """bits: int32 CUDA tensor (sum W_b, ld) -> fitness (n_inst, np_)."""
+    import torch
+    if out is None:
+        out = torch.empty((batch.n_inst, np_), dtype=torch.float64 if prec == PREC_F64 else torch.float32,
+                          device=bits.device)
+    _check(lib().qpm_batch_eval_fitness(batch.handle, prec, _ptr(bits), np_, bits.shape[1], _ptr(out),
+                                        waves_per_group, words_per_wave, _stream(stream)))
+    return out
+
+
+class BatchRun:
+    """One HWSDA run per instance of a Batch, advanced together."""
+
+    def __init__(self, batch, np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0,
+                 use_graph=1, tune=1, stream=None):
+        self.batch = batch
+        self.cfg = _config(np_, generations, F, CR, seed, inst, prec, gwo_variant, use_graph, FIT_AUTO)
+        h = C.c_void_p()
+        _check(lib().qpm_batch_run_create(batch.handle, C.byref(self.cfg), 1 if tune else 0, _stream(stream),
+                                          C.byref(h)))
+        self._h = h
+
+    def advance(self, generations=1):
+        _check(lib().qpm_batch_run_advance(self._h, generations))
+
+    def read(self, inst, device="cuda"):
+        import torch
+        n = self.batch.ns[inst]
+        np_ = self.cfg.np
+        x = torch.empty((np_, n), dtype=torch.float32, device=device)
+        f = torch.empty(np_, dtype=torch.float64 if self.cfg.prec == PREC_F64 else torch.float32, device=device)
+        L = (C.c_int32 * 3)()
+        shape = (C.c_int32 * 2)()
+        _check(lib().qpm_batch_run_read(self._h, inst, _ptr(x), n, _ptr(f), L, shape))
+        return x, f, [L[0], L[1], L[2]], (shape[0], shape[1])
+
+    def set_timing(self, enable=True):
+        _check(lib().qpm_batch_run_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self, reset=False):
+        ms = (C.c_double * len(STEP_NAMES))()
+        g = C.c_int64()
+        _check(lib().qpm_batch_run_timing(self._h, ms, C.byref(g), 1 if reset else 0))
+        return dict(zip(STEP_NAMES, list(ms))), int(g.value)
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.qpm_batch_run_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
