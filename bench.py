@@ -55,6 +55,45 @@ def algorithmic_work(step, npop, n):
     return "latency", 0.0, ""
 
 
+KERNEL_SOURCES = {  # the files a kernel's code comes from (traffic records are tied to them)
+    "de": ["evolve.hip", "genes.hpp", "device_common.hpp", "philox.hpp", "common.hpp"],
+    "gwo": ["evolve.hip", "genes.hpp", "device_common.hpp", "philox.hpp", "common.hpp"],
+    "fitness_de": ["fitness.hip", "scan.hpp", "common.hpp"],
+    "fitness_gwo": ["fitness.hip", "scan.hpp", "common.hpp"],
+}
+
+
+def source_digest(step):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(step, []):
+        with open(os.path.join(ROOT, "paper_2511_01255_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(step):
+    """HBM bytes per launch from the committed counter summary of this step
+    (profiles/traffic_<step>.txt: FETCH_SIZE and WRITE_SIZE scaled by a
+    plain copy), or None when absent or when the kernel's sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % step)
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("source_digest") != source_digest(step):
+        return None
+    try:
+        return float(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def philox_issue_slots():
     """VALU issue slots of one Philox4x32-10 call on gfx950: 10 rounds of two
     32x32->64 multiplies (v_mad_u64_u32, quarter rate = 4 slots each) and
@@ -107,7 +146,8 @@ def main():
     evals_per_gen = (2 * NP - 3) * N_DOMAINS
 
     def timed_run(prec_, fit_kernel, steps, warmup):
-        R = qpm.Run(design, NP, warmup + steps + 32, F=F, CR=CR, seed=SEED, prec=prec_, fit_kernel=fit_kernel)
+        R = qpm.Run(design, NP, warmup + steps + 32, F=F, CR=CR, seed=SEED, prec=prec_, fit_kernel=fit_kernel,
+                    tune=1)
         R.load(genes)
         R.advance(warmup)
         torch.cuda.synchronize()
@@ -166,7 +206,7 @@ def main():
         peak = PEAK_FP64_TFLOPS if prec == qpm.PREC_F64 else PEAK_FP32_TFLOPS
         roof = {"bound": "alu", "achieved": work / t_dom / 1e12, "peak": peak, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom)
     roof["kernel"] = dom
     roof["kernel_ms"] = per[dom]
     out["roofline"] = roof
@@ -206,6 +246,73 @@ def main():
                          "alg_tflops": 10 * rate / 1e12, "frac_of_peak": 10 * rate / 1e12 / peak}
             log("[bench] fitness %s: %.3g domain-evals/s (%.1f us)" % (name, rate, t * 1e6))
         out["fitness_only"] = fit
+
+    if not args.no_extras:
+        # full HWSDA at NP = 1024 on the same design (G = 5000 schedule,
+        # seed 0, FP32 fitness): generations/s and the per-kernel split
+        R3 = qpm.Run(design, 1024, 5000, F=F, CR=CR, seed=0, prec=qpm.PREC_F32, tune=1)
+        R3.advance(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R3.advance(400)
+        torch.cuda.synchronize()
+        t3 = (time.perf_counter() - t0) / 400
+        R3.set_timing(True)
+        R3.advance(20)
+        ms3, ng3 = R3.timing()
+        R3.destroy()
+        out["hwsda_np1024"] = {
+            "generations_per_s": 1.0 / t3, "ms_per_generation": t3 * 1e3,
+            "domain_evals_per_s": (2 * 1024 - 3) * N_DOMAINS / t3,
+            "kernel_ms": {k: v / ng3 for k, v in ms3.items()},
+        }
+        log("[bench] NP=1024 run: %.1f generations/s" % (1.0 / t3))
+
+        # batched uneven designs: 64 instances, N ~ U[1000, 50000], width
+        # U[1.5, 3] um, dk1 = 2 pi / U[18, 21], dk2 = 2 pi / U[6.2, 7], NP = 256
+        specs = inputs.batched_designs(64, seed=1)
+        total_n = sum(len(z) - 1 for z, _, _ in specs)
+        B = qpm.precompute_phases_batched([t[0] for t in specs], [t[1] for t in specs], [t[2] for t in specs])
+        BR = qpm.BatchRun(B, 256, 40, F=F, CR=CR, seed=SEED, prec=prec, tune=1)
+        BR.advance(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        BR.advance(10)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / 10
+        BR.set_timing(True)
+        BR.advance(3)
+        bms, bng = BR.timing()
+        BR.destroy()
+        del B
+        out["batched_designs"] = {
+            "instances": 64, "np": 256, "total_domains": total_n,
+            "ms_per_generation": tb * 1e3, "generations_per_s": 1.0 / tb,
+            "domain_evals_per_s": (2 * 256 - 3) * total_n / tb,
+            "kernel_ms": {k: v / bng for k, v in bms.items()},
+        }
+        log("[bench] batched designs: %.2f ms/generation" % (tb * 1e3))
+        # relaxation forward + adjoint: batch 256, N = 50,000 x 2 um
+        zr = inputs.uniform_boundaries(50000, 2.0)
+        Dr = qpm.precompute_phases(zr, inputs.DK1, inputs.DK2)
+        th = torch.from_numpy(inputs.relax_theta(256, 50000, seed=1)).cuda()
+        ones = torch.ones(256, device="cuda")
+        rel = {}
+        for name, p_ in (("f32", qpm.PREC_F32), ("f64", qpm.PREC_F64)):
+            f_, S_ = qpm.relax_forward(Dr, th, p_)
+            qpm.relax_backward(Dr, th, S_, ones, p_)
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(10):
+                f_, S_ = qpm.relax_forward(Dr, th, p_)
+                qpm.relax_backward(Dr, th, S_, ones, p_)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) * 1e-3 / 10
+            rel[name] = {"ms_forward_adjoint": t * 1e3, "domain_evals_per_s": 256 * 50000 / t}
+        out["relaxation"] = rel
+        log("[bench] relaxation fwd+adjoint: %s" % rel)
 
     if args.cpu_generations > 0:
         import oracle as orc

@@ -159,6 +159,18 @@ qpm_status qpm_init_population(int64_t np, int64_t D, int64_t ldx, uint64_t seed
 qpm_status qpm_de_step(const float *x, int64_t np, int64_t D, int64_t ldx, float F, float CR,
                        uint64_t seed, uint32_t generation, uint32_t inst, float *u,
                        uint32_t *u_bits, int64_t ld, qpm_stream s);
+/*
+ * qpm_de_step_shape -- qpm_de_step with an explicit launch shape: each wave
+ * covers individuals_per_wave individuals (1, 2 or 4; 0 = chosen from np)
+ * of a gene chunk of 256 / individuals_per_wave genes, and each workgroup
+ * makes `passes` (1, 2 or 4) passes over consecutive groups of
+ * individuals. The shape changes the speed only, never the result.
+ * Errors: as qpm_de_step, and QPM_EINVAL for a shape outside these sets.
+ */
+qpm_status qpm_de_step_shape(const float *x, int64_t np, int64_t D, int64_t ldx, float F, float CR,
+                             uint64_t seed, uint32_t generation, uint32_t inst, float *u,
+                             uint32_t *u_bits, int64_t ld, int32_t individuals_per_wave,
+                             int32_t passes, qpm_stream s);
 
 /*
  * qpm_gwo_step -- grey-wolf update of the omega wolves (paper Sec. 2.2.2):
@@ -172,7 +184,8 @@ qpm_status qpm_de_step(const float *x, int64_t np, int64_t D, int64_t ldx, float
  * (3 q + t / 4, i, g, inst << 8 | 4), word t % 4.
  * leaders: device int32[3] (alpha, beta, delta), distinct, in [0, np); the
  * call copies them to the host to validate them, so it synchronises s.
- * Leader rows of y and y_bits are left untouched. a >= 0.
+ * Leader rows of y and y_bits are left untouched. a = 0 or
+ * 2^-100 <= a <= 1e30 (the parameter runs from 2 down to 0).
  */
 qpm_status qpm_gwo_step(const float *x, int64_t np, int64_t D, int64_t ldx,
                         const int32_t *leaders, float a, uint64_t seed, uint32_t generation,
@@ -217,6 +230,9 @@ typedef struct {
     int32_t gwo_variant; /* 0 = weighted as printed, 1 = plain mean */
     int32_t use_graph;   /* 1 = replay one captured generation */
     int32_t fit_kernel;  /* qpm_fit_kernel of the evaluations */
+    int32_t tune;        /* 1 = time candidate launch shapes of the fitness
+                            and DE kernels at creation and keep the fastest
+                            (cached per problem size; QPM_TUNE_CACHE file) */
 } qpm_run_config;
 
 typedef struct {
@@ -292,6 +308,17 @@ enum {
 qpm_status qpm_run_set_timing(qpm_run_handle r, int32_t enable);
 qpm_status qpm_run_timing(qpm_run_handle r, double *ms, int64_t *generations, int32_t reset);
 
+/*
+ * qpm_run_polish -- gradient polish of the three current leaders through the
+ * relaxation (not in the paper): theta = the leader's genes, `steps` steps of
+ * theta += eta g / max|g| with g = df/dtheta of qpm_relax_backward, then the
+ * +-1 projection y = clamp(theta, -1, 1) (same signs) is scored by the exact
+ * +-1 fitness and replaces the leader only if it is strictly better.
+ * *accepted (host, may be NULL) receives how many of the three were
+ * replaced. Synchronous; not captured in the generation graph.
+ */
+qpm_status qpm_run_polish(qpm_run_handle r, int32_t steps, float eta, int32_t *accepted);
+
 /* Release a run (NULL accepted). */
 qpm_status qpm_run_destroy(qpm_run_handle r);
 
@@ -335,6 +362,9 @@ qpm_status qpm_batch_eval_fitness(qpm_batch b, qpm_prec p, const uint32_t *bits,
  * tune != 0 the fitness launch shape is chosen by timing candidates on the
  * initial population (kept per problem size for the process, and appended
  * to the file named by the QPM_TUNE_CACHE environment variable if set).
+ * Errors: QPM_EINVAL (NULL arguments, parameters out of range),
+ * QPM_ERANGE (more than 65535 fitness segments or 1024-gene chunks over
+ * the batch), QPM_ENOMEM, QPM_EHIP, QPM_ENOTSUP (not a gfx950 device).
  */
 qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, int32_t tune, qpm_stream s,
                                 qpm_batch_run_handle *out);

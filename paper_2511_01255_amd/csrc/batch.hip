@@ -356,51 +356,6 @@ static void default_fit_shape(const std::vector<InstDesc> &h, int64_t np, int *w
     *wpw = static_cast<int>(w);
 }
 
-// Launch-shape tuner: a process-wide cache keyed by the problem, optionally
-// persisted in the file named by QPM_TUNE_CACHE ("key waves wpw" lines).
-static std::mutex g_tune_mu;
-static std::map<std::string, std::pair<int, int>> g_tune;
-static bool g_tune_loaded = false;
-
-static std::string tune_key(const char *kind, int64_t words, int64_t np, int prec, int64_t n_inst)
-{
-    // bucket the totals to powers of two so similar problems share a shape
-    auto bucket = [](int64_t v) {
-        int b = 0;
-        while ((int64_t(1) << b) < v) ++b;
-        return b;
-    };
-    char buf[128];
-    std::snprintf(buf, sizeof(buf), "gfx950/%s/w%d/np%d/p%d/i%d", kind, bucket(words), bucket(np), prec,
-                  bucket(n_inst));
-    return buf;
-}
-
-static void tune_load_locked()
-{
-    if (g_tune_loaded) return;
-    g_tune_loaded = true;
-    const char *path = std::getenv("QPM_TUNE_CACHE");
-    if (!path) return;
-    FILE *fh = std::fopen(path, "r");
-    if (!fh) return;
-    char key[128];
-    int a, b;
-    while (std::fscanf(fh, "%127s %d %d", key, &a, &b) == 3) g_tune[key] = {a, b};
-    std::fclose(fh);
-}
-
-static void tune_store_locked(const std::string &key, int waves, int wpw)
-{
-    g_tune[key] = {waves, wpw};
-    const char *path = std::getenv("QPM_TUNE_CACHE");
-    if (!path) return;
-    FILE *fh = std::fopen(path, "a");
-    if (!fh) return;
-    std::fprintf(fh, "%s %d %d\n", key.c_str(), waves, wpw);
-    std::fclose(fh);
-}
-
 }  // namespace qpm
 
 using namespace qpm;
@@ -770,11 +725,9 @@ static qpm_status tune_fitness(qpm_batch_run_s *r)
     const qpm_run_config &c = r->cfg;
     const std::string key = tune_key("batchfit", r->bt->total_words, c.np, c.prec, r->bt->n_inst);
     {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_load_locked();
-        auto it = g_tune.find(key);
-        if (it != g_tune.end()) {
-            r->fplan = make_fit_plan(r->bt->host, it->second.first, it->second.second);
+        int v0, v1;
+        if (tune_lookup(key, &v0, &v1)) {
+            r->fplan = make_fit_plan(r->bt->host, v0, v1);
             return QPM_OK;
         }
     }
@@ -815,8 +768,7 @@ static qpm_status tune_fitness(qpm_batch_run_s *r)
     QPM_TRY_HIP(hipStreamSynchronize(r->st));
     r->tune_us = best * 1000.0 / 3.0;
     r->fplan = make_fit_plan(r->bt->host, pick.first, pick.second);
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    tune_store_locked(key, pick.first, pick.second);
+    tune_store(key, pick.first, pick.second);
     return QPM_OK;
 }
 
@@ -859,6 +811,11 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
     for (int32_t i = 0; i < b->n_inst; ++i) {
         for (int64_t ch = 0; ch * 1024 < h[i].n; ++ch) gt.push_back(Tile{i, static_cast<int>(ch)});
         for (int64_t ch = 0; ch * cw < h[i].n; ++ch) dt.push_back(Tile{i, static_cast<int>(ch)});
+    }
+    if (gt.size() > 65535) {  // the GWO and init grids put these chunks on gridDim.y
+        set_error("too many 1024-gene chunks over the batch (%zu > 65535)", gt.size());
+        release_batch_run(r);
+        return QPM_ERANGE;
     }
     r->n_gtiles = static_cast<int>(gt.size());
     r->n_dtiles = static_cast<int>(dt.size());

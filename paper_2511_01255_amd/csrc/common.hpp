@@ -5,6 +5,7 @@
 
 #include <cstdarg>
 #include <cstdint>
+#include <string>
 
 #include "qpm.h"
 
@@ -81,9 +82,11 @@ qpm_status launch_fitness_partials(const Design &d, qpm_prec p, const uint32_t *
 // select (f > f_cur[i] replaces, leaders in skip3 excluded), then in the
 // last workgroup: top3_out <- leaders (when non-null); with draws_next the
 // DE draws of generation gen + 1 are written and gen is advanced.
+// fbits (optional): packed copy of flags, 2 ceil(np / 64) words
 qpm_status launch_finish(const double *part, int gy, int64_t ld, int64_t np, const double *C, void *f_cur,
-                         bool f64, uint32_t *flags, const int32_t *skip3, int32_t *top3_out, int4 *draws_next,
-                         uint32_t *gen, int64_t D, uint64_t seed, uint32_t inst, uint32_t *ticket, hipStream_t s);
+                         bool f64, uint32_t *flags, uint32_t *fbits, const int32_t *skip3, int32_t *top3_out,
+                         int4 *draws_next, uint32_t *gen, int64_t D, uint64_t seed, uint32_t inst, uint32_t *ticket,
+                         hipStream_t s);
 
 // ---------------------------------------------------------------- evolution kernels
 
@@ -102,20 +105,22 @@ struct PopView {
 qpm_status launch_init(int64_t np, int64_t D, int64_t ldx, uint64_t seed, uint32_t inst, float *x,
                        uint32_t *bits, int64_t ld, hipStream_t s);
 // draws: device scratch of np int4 (donors r1, r2, r3 and jrand)
+// ipw: individuals per wave of the DE kernel (1, 2 or 4; 0 = chosen from np);
+// passes: groups of individuals per workgroup (1, 2 or 4); fbits: optional
+// packed copy of pv.flags (bit i % 32 of word i / 32)
 qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const uint32_t *gen_dev,
                      uint32_t gen, uint32_t inst, uint32_t *bits, int64_t ld, int4 *draws, bool compute_draws,
-                     hipStream_t s);
+                     hipStream_t s, int ipw = 0, int passes = 1, const uint32_t *fbits = nullptr);
+// segmented plan with an explicit shape
+FitPlan plan_fitness_shape(const Design &d, int waves, int wpw);
 // DE draws of generation *gen_dev for every individual
 qpm_status launch_draws(int64_t np, int64_t D, uint64_t seed, const uint32_t *gen_dev, uint32_t inst, int4 *draws,
                         hipStream_t s);
 qpm_status launch_gwo(const PopView &pv, const int32_t *leaders, const float *a_tab, float a,
                       uint64_t seed, const uint32_t *gen_dev, uint32_t gen, uint32_t inst,
                       int variant, uint32_t *bits, int64_t ld, hipStream_t s);
-// f[i] <- fnew[i] and flags[i] ^= 1 where fnew[i] > f[i] (leaders skipped
-// when non-null); T = float or double by `f64`
-qpm_status launch_select(void *f, const void *fnew, uint32_t *flags, int64_t np, const int32_t *leaders,
-                         bool f64, hipStream_t s);
-// the three best slots by (f descending, slot ascending)
+// the three best of f[0..np) (f descending, slot ascending) into out3;
+// T = float or double by `f64`
 qpm_status launch_top3(const void *f, int64_t np, bool f64, int32_t *out3, hipStream_t s);
 // rows of the current population (through flags) -> dense out[np][ldo]
 qpm_status launch_gather(const PopView &pv, const int32_t *rows, int64_t nrows, float *out, int64_t ldo,
@@ -125,6 +130,20 @@ qpm_status launch_pack_pop(const float *x, int64_t np, int64_t D, int64_t ldx, u
                            hipStream_t s);
 // sign bits of one gene row (D genes) -> W words
 qpm_status launch_pack_row(const float *x, int64_t D, uint32_t *bits, hipStream_t s);
+
+// ---------------------------------------------------------------- polish
+
+qpm_status launch_polish_step(float *theta, const float *grad, int64_t rows, int64_t n, int64_t ld, float eta,
+                              hipStream_t s);
+qpm_status launch_polish_project(const float *theta, float *y, int64_t rows, int64_t n, int64_t ld, hipStream_t s);
+qpm_status launch_polish_accept(const float *y, int64_t n, int64_t ldy, const void *fcand, bool f64, const int32_t *L,
+                                const PopView &pv, void *f_cur, uint32_t *accepted, hipStream_t s);
+
+// ---------------------------------------------------------------- tuner cache
+
+std::string tune_key(const char *kind, int64_t a, int64_t b, int prec, int64_t c);
+bool tune_lookup(const std::string &key, int *v0, int *v1);
+void tune_store(const std::string &key, int v0, int v1);
 
 }  // namespace qpm
 

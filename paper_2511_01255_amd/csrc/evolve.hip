@@ -58,22 +58,32 @@ __global__ __launch_bounds__(256) void de_draws_kernel(int64_t np, int64_t D, ui
 
 // Work split: a lane moves one gene quad (float4). A chunk is CW = 256 /
 // IPW genes; one wave covers IPW individuals of a chunk (64 / IPW lanes
-// each) and a 256-lane workgroup covers 4 IPW consecutive individuals.
-// Chunks are dealt to the eight XCDs round-robin (workgroup id mod 8 =
-// XCD) and every XCD walks its chunks in order over all individuals, so
-// while it works on a chunk that slice of the whole population
-// (np x CW x 4 bytes, chosen <= 2 MB) stays in the XCD's L2 and the random
-// donor rows hit it.
-template <int IPW>
-__global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restrict__ draws, float F, float CR,
-                                                 uint32_t k0, uint32_t k1, const uint32_t *__restrict__ gen_dev,
-                                                 uint32_t gen_c, uint32_t inst, uint32_t *__restrict__ bits,
-                                                 int64_t ld, int groups, int chunks)
+// each) and a 256-lane workgroup covers IPG = 4 IPW consecutive
+// individuals per pass, R passes over R IPG consecutive individuals. The
+// rows of pass r + 1 are loaded before the trials of pass r are stored, so
+// two passes' reads are in flight per wave. Chunks are dealt to the eight
+// XCDs round-robin (workgroup id mod 8 = XCD) and every XCD walks its
+// chunks in order over all individuals, so while it works on a chunk that
+// slice of the whole population (np x CW x 4 bytes, chosen <= 2 MB) stays in
+// the XCD's L2 and the random donor rows hit it.
+//
+// Each row's buffer is named by its flag. With `fbits` (the flags packed one
+// bit per individual) the workgroup first copies the packed flags to LDS,
+// so a donor row's address costs an LDS read instead of a second dependent
+// global load after the draw.
+template <int IPW, int R>
+__global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restrict__ draws,
+                                                 const uint32_t *__restrict__ fbits, float F, float CR, uint32_t k0,
+                                                 uint32_t k1, const uint32_t *__restrict__ gen_dev, uint32_t gen_c,
+                                                 uint32_t inst, uint32_t *__restrict__ bits, int64_t ld, int groups,
+                                                 int chunks)
 {
     constexpr int LPI = 64 / IPW;  // lanes per individual
     constexpr int CW = 4 * LPI;    // genes per chunk
     constexpr int WPC = CW / 32;   // bit words per chunk and individual
-    constexpr int IPG = 4 * IPW;   // individuals per workgroup
+    constexpr int IPG = 4 * IPW;   // individuals per workgroup pass
+    constexpr int IPB = R * IPG;   // individuals per workgroup
+    static_assert(IPB * WPC <= 256, "one bit word per thread at the end");
     const uint32_t b = blockIdx.x;
     const int xcd = static_cast<int>(b & 7u);
     const int k = static_cast<int>(b >> 3);
@@ -81,37 +91,69 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
     const int c = xcd + 8 * (k / groups);
     if (c >= chunks) return;
     const int t = threadIdx.x;
-    const int local = t / LPI;  // individual within the workgroup
+    const int local = t / LPI;  // individual within a pass
     const int li = t % LPI;     // lane within the individual
     const int64_t D = pv.D, np = pv.np;
-    const int64_t i = static_cast<int64_t>(gi) * IPG + local;
+    const int64_t i0 = static_cast<int64_t>(gi) * IPB + local;
     const int64_t j0 = static_cast<int64_t>(c) * CW + 4 * li;
-    const bool active = i < np && j0 < D;
     const uint32_t g = gen_dev ? gen_dev[0] : gen_c;
-    __shared__ uint32_t wsh[IPG][WPC];
-    uint32_t nib = 0;
-    if (active) {
-        const int4 dr = draws[i];
-        const float4 xv = *reinterpret_cast<const float4 *>(row_of(pv, i) + j0);
-        const float4 a = *reinterpret_cast<const float4 *>(row_of(pv, dr.x) + j0);
-        const float4 bq = *reinterpret_cast<const float4 *>(row_of(pv, dr.y) + j0);
-        const float4 cq = *reinterpret_cast<const float4 *>(row_of(pv, dr.z) + j0);
-        const float4 uv = de_quad(xv, a, bq, cq, j0, dr.w, static_cast<uint32_t>(i), g, inst, k0, k1, F, CR);
-        store_quad(out_row_of(pv, i), j0, D, uv);
-        nib = quad_nibble(uv, j0, D);
+    __shared__ uint32_t wsh[IPB][WPC];
+    extern __shared__ uint32_t sfb[];  // (np + 31) / 32 packed flags when fbits != nullptr
+    const bool packed = fbits != nullptr;
+    if (packed)
+        for (int64_t k = t; k < (np + 31) / 32; k += 256) sfb[k] = fbits[k];
+    int4 dr[R];
+    bool act[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = i0 + r * IPG;
+        act[r] = i < np && j0 < D;
+        dr[r] = act[r] ? draws[i] : make_int4(0, 0, 0, 0);
     }
-    // merge the nibbles of 8 neighbouring lanes (32 genes) into one word
-    uint32_t w = nib << (4 * (t & 7));
-    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 1));
-    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 2));
-    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 4));
-    if ((t & 7) == 0) wsh[local][li >> 3] = w;
+    if (packed) __syncthreads();
+    auto second = [&](int64_t r) -> bool {
+        return packed ? ((sfb[r >> 5] >> (r & 31)) & 1u) != 0u : (pv.flags != nullptr && pv.flags[r] != 0u);
+    };
+    auto src = [&](int64_t r) -> const float * { return (second(r) ? pv.x1 : pv.x0) + r * pv.ldx; };
+    float4 cur[4], nxt[4];
+    auto load = [&](int r, float4 *v) {
+        if (act[r]) {
+            const int64_t i = i0 + r * IPG;
+            v[0] = *reinterpret_cast<const float4 *>(src(i) + j0);
+            v[1] = *reinterpret_cast<const float4 *>(src(dr[r].x) + j0);
+            v[2] = *reinterpret_cast<const float4 *>(src(dr[r].y) + j0);
+            v[3] = *reinterpret_cast<const float4 *>(src(dr[r].z) + j0);
+        }
+    };
+    load(0, cur);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (r + 1 < R) load(r + 1, nxt);
+        uint32_t nib = 0;
+        if (act[r]) {
+            const int64_t i = i0 + r * IPG;
+            const float4 uv = de_quad(cur[0], cur[1], cur[2], cur[3], j0, dr[r].w, static_cast<uint32_t>(i), g, inst,
+                                      k0, k1, F, CR);
+            store_quad((second(i) ? pv.out0 : pv.out1) + i * pv.ldx, j0, D, uv);
+            nib = quad_nibble(uv, j0, D);
+        }
+        // merge the nibbles of 8 neighbouring lanes (32 genes) into one word
+        uint32_t w = nib << (4 * (t & 7));
+        w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 1));
+        w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 2));
+        w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 4));
+        if ((t & 7) == 0) wsh[r * IPG + local][li >> 3] = w;
+        if (r + 1 < R) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) cur[m] = nxt[m];
+        }
+    }
     __syncthreads();
-    // the IPG consecutive individuals of this workgroup share each bit row:
-    // one contiguous store of IPG words per chunk word
-    if (t < IPG * WPC) {
-        const int wd = t / IPG, ii = t % IPG;
-        const int64_t row = static_cast<int64_t>(gi) * IPG + ii;
+    // the IPB consecutive individuals of this workgroup share each bit row:
+    // one contiguous store of IPB words per chunk word
+    if (t < IPB * WPC) {
+        const int wd = t / IPB, ii = t % IPB;
+        const int64_t row = static_cast<int64_t>(gi) * IPB + ii;
         const int64_t wg = static_cast<int64_t>(c) * WPC + wd;
         if (row < np && wg * 32 < D) bits[wg * ld + row] = wsh[ii][wd];
     }
@@ -150,23 +192,6 @@ __global__ __launch_bounds__(256) void gwo_kernel(PopView pv, const int32_t *__r
         nib = quad_nibble(yv4, j0, D);
     }
     store_word(nib, q, valid, bits, ld, i);
-}
-
-// ------------------------------------------------------------ selection
-
-template <typename T>
-__global__ __launch_bounds__(256) void select_kernel(T *__restrict__ f, const T *__restrict__ fnew,
-                                                     uint32_t *__restrict__ flags, int64_t np,
-                                                     const int32_t *__restrict__ leaders)
-{
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= np) return;
-    if (leaders && (i == leaders[0] || i == leaders[1] || i == leaders[2])) return;
-    const T v = fnew[i];
-    if (v > f[i]) {
-        f[i] = v;
-        flags[i] ^= 1u;
-    }
 }
 
 // ------------------------------------------------------------ top-3
@@ -236,28 +261,38 @@ qpm_status launch_init(int64_t np, int64_t D, int64_t ldx, uint64_t seed, uint32
 }
 
 qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const uint32_t *gen_dev, uint32_t gen,
-                     uint32_t inst, uint32_t *bits, int64_t ld, int4 *draws, bool compute_draws, hipStream_t s)
+                     uint32_t inst, uint32_t *bits, int64_t ld, int4 *draws, bool compute_draws, hipStream_t s,
+                     int ipw_req, int passes, const uint32_t *fbits)
 {
+    // the packed flags are staged in LDS up to 65536 individuals (8 KB)
+    if (pv.np > 65536) fbits = nullptr;
+    const size_t lds = fbits ? sizeof(uint32_t) * static_cast<size_t>((pv.np + 31) / 32) : 0;
     const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
     if (compute_draws)
         de_draws_kernel<<<static_cast<unsigned>((pv.np + 255) / 256), 256, 0, s>>>(pv.np, pv.D, k0, k1, gen_dev,
                                                                                    gen, inst, draws);
     // individuals per wave so that one chunk of the population fits in 2 MB
     const int64_t row_bytes = 2 * 1024 * 1024 / pv.np;
-    const int ipw = row_bytes >= 1024 ? 1 : (row_bytes >= 512 ? 2 : 4);
+    const int ipw = (ipw_req == 1 || ipw_req == 2 || ipw_req == 4) ? ipw_req
+                                                                   : (row_bytes >= 1024 ? 1 : (row_bytes >= 512 ? 2 : 4));
+    const int R = (passes == 2 || passes == 4) ? passes : 1;
     const int64_t cw = 256 / ipw;
     const int64_t chunks = (pv.D + cw - 1) / cw;
-    const int64_t groups = (pv.np + 4 * ipw - 1) / (4 * ipw);
+    const int64_t groups = (pv.np + 4 * ipw * R - 1) / (4 * ipw * R);
     const int64_t blocks = 8 * ((chunks + 7) / 8) * groups;
     QPM_REQUIRE(blocks < (int64_t(1) << 31), QPM_ERANGE, "population too large for one DE launch");
     const int gr = static_cast<int>(groups), ch = static_cast<int>(chunks);
     const unsigned nb = static_cast<unsigned>(blocks);
-    if (ipw == 1)
-        de_kernel<1><<<nb, 256, 0, s>>>(pv, draws, F, CR, k0, k1, gen_dev, gen, inst, bits, ld, gr, ch);
-    else if (ipw == 2)
-        de_kernel<2><<<nb, 256, 0, s>>>(pv, draws, F, CR, k0, k1, gen_dev, gen, inst, bits, ld, gr, ch);
-    else
-        de_kernel<4><<<nb, 256, 0, s>>>(pv, draws, F, CR, k0, k1, gen_dev, gen, inst, bits, ld, gr, ch);
+#define QPM_DE(I, P) \
+    de_kernel<I, P><<<nb, 256, lds, s>>>(pv, draws, fbits, F, CR, k0, k1, gen_dev, gen, inst, bits, ld, gr, ch)
+    if (ipw == 1) {
+        if (R == 1) QPM_DE(1, 1); else if (R == 2) QPM_DE(1, 2); else QPM_DE(1, 4);
+    } else if (ipw == 2) {
+        if (R == 1) QPM_DE(2, 1); else if (R == 2) QPM_DE(2, 2); else QPM_DE(2, 4);
+    } else {
+        if (R == 1) QPM_DE(4, 1); else if (R == 2) QPM_DE(4, 2); else QPM_DE(4, 4);
+    }
+#undef QPM_DE
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }
@@ -269,20 +304,6 @@ qpm_status launch_gwo(const PopView &pv, const int32_t *leaders, const float *a_
     gwo_kernel<<<quad_grid(pv.D, pv.np), 256, 0, s>>>(pv, leaders, a_tab, a, static_cast<uint32_t>(seed),
                                                       static_cast<uint32_t>(seed >> 32), gen_dev, gen, inst, variant,
                                                       bits, ld);
-    QPM_TRY_HIP(hipGetLastError());
-    return QPM_OK;
-}
-
-qpm_status launch_select(void *f, const void *fnew, uint32_t *flags, int64_t np, const int32_t *leaders, bool f64,
-                         hipStream_t s)
-{
-    const unsigned blocks = static_cast<unsigned>((np + 255) / 256);
-    if (f64)
-        select_kernel<double><<<blocks, 256, 0, s>>>(static_cast<double *>(f), static_cast<const double *>(fnew),
-                                                     flags, np, leaders);
-    else
-        select_kernel<float><<<blocks, 256, 0, s>>>(static_cast<float *>(f), static_cast<const float *>(fnew), flags,
-                                                    np, leaders);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }
@@ -373,11 +394,10 @@ QPM_API qpm_status qpm_init_population(int64_t np, int64_t D, int64_t ldx, uint6
     return launch_init(np, D, ldx, seed, inst, x, bits, ld, static_cast<hipStream_t>(sv));
 }
 
-QPM_API qpm_status qpm_de_step(const float *x, int64_t np, int64_t D, int64_t ldx, float F, float CR,
-                               uint64_t seed, uint32_t generation, uint32_t inst, float *u, uint32_t *u_bits,
-                               int64_t ld, qpm_stream sv)
+static qpm_status de_step(const float *x, int64_t np, int64_t D, int64_t ldx, float F, float CR, uint64_t seed,
+                          uint32_t generation, uint32_t inst, float *u, uint32_t *u_bits, int64_t ld, int ipw,
+                          int passes, qpm_stream sv)
 {
-    clear_error();
     qpm_status st = check_rows(x, np, D, ldx, "x");
     if (st != QPM_OK) return st;
     st = check_rows(u, np, D, ldx, "u");
@@ -394,9 +414,30 @@ QPM_API qpm_status qpm_de_step(const float *x, int64_t np, int64_t D, int64_t ld
     hipStream_t s = static_cast<hipStream_t>(sv);
     int4 *draws = nullptr;
     QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&draws), sizeof(int4) * np, s));
-    qpm_status st2 = launch_de(pv, F, CR, seed, nullptr, generation, inst, u_bits, ld, draws, true, s);
+    qpm_status st2 = launch_de(pv, F, CR, seed, nullptr, generation, inst, u_bits, ld, draws, true, s, ipw, passes);
     (void)hipFreeAsync(draws, s);
     return st2;
+}
+
+QPM_API qpm_status qpm_de_step(const float *x, int64_t np, int64_t D, int64_t ldx, float F, float CR,
+                               uint64_t seed, uint32_t generation, uint32_t inst, float *u, uint32_t *u_bits,
+                               int64_t ld, qpm_stream sv)
+{
+    clear_error();
+    return de_step(x, np, D, ldx, F, CR, seed, generation, inst, u, u_bits, ld, 0, 1, sv);
+}
+
+QPM_API qpm_status qpm_de_step_shape(const float *x, int64_t np, int64_t D, int64_t ldx, float F, float CR,
+                                     uint64_t seed, uint32_t generation, uint32_t inst, float *u, uint32_t *u_bits,
+                                     int64_t ld, int32_t individuals_per_wave, int32_t passes, qpm_stream sv)
+{
+    clear_error();
+    QPM_REQUIRE(individuals_per_wave == 0 || individuals_per_wave == 1 || individuals_per_wave == 2 ||
+                    individuals_per_wave == 4,
+                QPM_EINVAL, "individuals_per_wave must be 0, 1, 2 or 4 (got %d)", (int)individuals_per_wave);
+    QPM_REQUIRE(passes == 1 || passes == 2 || passes == 4, QPM_EINVAL, "passes must be 1, 2 or 4 (got %d)",
+                (int)passes);
+    return de_step(x, np, D, ldx, F, CR, seed, generation, inst, u, u_bits, ld, individuals_per_wave, passes, sv);
 }
 
 QPM_API qpm_status qpm_gwo_step(const float *x, int64_t np, int64_t D, int64_t ldx, const int32_t *leaders, float a,
@@ -412,7 +453,8 @@ QPM_API qpm_status qpm_gwo_step(const float *x, int64_t np, int64_t D, int64_t l
     if (st != QPM_OK) return st;
     QPM_REQUIRE(leaders != nullptr, QPM_EINVAL, "leaders must not be NULL");
     QPM_REQUIRE(np >= 4, QPM_EINVAL, "the grey-wolf step needs np >= 4 (got %lld)", (long long)np);
-    QPM_REQUIRE(a >= 0.0f && a <= 1e30f, QPM_EINVAL, "a must be finite and >= 0 (got %g)", (double)a);
+    QPM_REQUIRE(a == 0.0f || (a >= 0x1p-100f && a <= 1e30f), QPM_EINVAL,
+                "a must be 0 or in [2^-100, 1e30] (got %g)", (double)a);
     QPM_REQUIRE(variant == 0 || variant == 1, QPM_EINVAL, "variant must be 0 or 1");
     QPM_REQUIRE(inst < (1u << 24), QPM_EINVAL, "inst must be < 2^24");
     const size_t bytes = sizeof(float) * static_cast<size_t>(np) * static_cast<size_t>(ldx);

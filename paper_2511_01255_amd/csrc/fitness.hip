@@ -76,20 +76,14 @@ __global__ __launch_bounds__(WAVES * 64) void fit_seg_kernel(const uint32_t *__r
     }
 }
 
+// 64 genomes per workgroup of 4 waves (see combine_segments)
 __global__ __launch_bounds__(256) void fit_combine_kernel(const double *__restrict__ part, int gy, int64_t ld,
                                                           int64_t np, const double *__restrict__ C,
                                                           void *__restrict__ fit, int out_f64)
 {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= np) return;
-    const double *p = part + i;
-    Tri t{p[0], p[ld], p[2 * ld], p[3 * ld], p[4 * ld], p[5 * ld]};
-    for (int s = 1; s < gy; ++s) {
-        const double *q = part + static_cast<int64_t>(s) * 6 * ld + i;
-        const Tri u{q[0], q[ld], q[2 * ld], q[3 * ld], q[4 * ld], q[5 * ld]};
-        tri_append(t, u);
-    }
-    store_fitness(fit, out_f64, i, t, C);
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + (threadIdx.x & 63);
+    const Tri t = combine_segments<4>(part, gy, ld, i, i < np);
+    if (threadIdx.x < 64 && i < np) store_fitness(fit, out_f64, i, t, C);
 }
 
 // The per-individual scheme: one lane walks its whole genome; no segment
@@ -182,6 +176,17 @@ FitPlan plan_fitness(const Design &d, qpm_prec p, int64_t np, int kernel)
     return pl;
 }
 
+FitPlan plan_fitness_shape(const Design &d, int waves, int wpw)
+{
+    FitPlan pl;
+    pl.kind = QPM_FIT_SEGMENTED;
+    pl.waves = waves;
+    pl.wpw = wpw;
+    const int64_t nseg = (d.words + wpw - 1) / wpw;
+    pl.gy = static_cast<int>((nseg + waves - 1) / waves);
+    return pl;
+}
+
 size_t fitness_workspace_bytes(const FitPlan &pl, int64_t ld)
 {
     if (pl.kind != QPM_FIT_SEGMENTED || pl.gy <= 1) return 0;
@@ -208,7 +213,7 @@ qpm_status launch_fitness(const Design &d, qpm_prec p, const uint32_t *bits, int
         else
             launch_seg<false>(d, pl, bits, np, ld, part, fit, out_f64, true, s);
         if (pl.gy > 1) {
-            const unsigned blocks = static_cast<unsigned>((np + 255) / 256);
+            const unsigned blocks = static_cast<unsigned>((np + 63) / 64);
             fit_combine_kernel<<<blocks, 256, 0, s>>>(part, pl.gy, ld, np, d.Cdev, fit, out_f64);
         }
     }
@@ -289,12 +294,7 @@ QPM_API qpm_status qpm_eval_fitness_shape(qpm_design d, qpm_prec p, const uint32
     QPM_REQUIRE(wpw >= 1, QPM_EINVAL, "words_per_wave must be >= 1 (got %d)", (int)wpw);
     qpm_status st = check_fitness_args(d, p, bits, np, ld, fitness);
     if (st != QPM_OK) return st;
-    FitPlan pl;
-    pl.kind = QPM_FIT_SEGMENTED;
-    pl.waves = waves;
-    pl.wpw = wpw;
-    const int64_t nseg = (d->words + wpw - 1) / wpw;
-    pl.gy = static_cast<int>((nseg + waves - 1) / waves);
+    const FitPlan pl = plan_fitness_shape(*d, waves, wpw);
     QPM_REQUIRE(pl.gy <= 65535, QPM_ERANGE, "too many workgroup segments (%d)", pl.gy);
     return run_plan(d, p, bits, np, ld, fitness, pl, static_cast<hipStream_t>(sv));
 }

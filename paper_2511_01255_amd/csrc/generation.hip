@@ -7,39 +7,46 @@
 // so the kernel can be replayed from a graph.
 #include "common.hpp"
 #include "device_common.hpp"
+#include "scan.hpp"
 
 namespace qpm {
 
+// Workgroup = 4 waves over 64 consecutive individuals (lane = individual):
+// the waves fold the segment triples (combine_segments), wave 0 selects,
+// and keeps the packed copy of the buffer flags (bit i % 32 of word i / 32;
+// the wave owns words 2b and 2b + 1) that the DE kernel stages in LDS.
 template <typename T>
 __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ part, int gy, int64_t ld, int64_t np,
                                                      const double *__restrict__ C, T *__restrict__ f_cur,
-                                                     uint32_t *__restrict__ flags, const int32_t *__restrict__ skip3,
+                                                     uint32_t *__restrict__ flags, uint32_t *__restrict__ fbits,
+                                                     const int32_t *__restrict__ skip3,
                                                      int32_t *__restrict__ top3_out, int4 *__restrict__ draws_next,
                                                      uint32_t *__restrict__ gen, int64_t D, uint32_t k0, uint32_t k1,
                                                      uint32_t inst, uint32_t *__restrict__ ticket)
 {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (i < np) {
-        const double *p = part + i;
-        double ar = p[0], ai = p[ld], br = p[2 * ld], bi = p[3 * ld], qr = p[4 * ld], qi = p[5 * ld];
-        for (int sgm = 1; sgm < gy; ++sgm) {
-            const double *q = part + static_cast<int64_t>(sgm) * 6 * ld + i;
-            const double ur = q[0], ui = q[ld], vr = q[2 * ld], vi = q[3 * ld];
-            qr = fma(ar, vr, fma(-ai, vi, qr + q[4 * ld]));
-            qi = fma(ar, vi, fma(ai, vr, qi + q[5 * ld]));
-            ar += ur;
-            ai += ui;
-            br += vr;
-            bi += vi;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+    const bool valid = i < np;
+    const Tri t = combine_segments<4>(part, gy, ld, i, valid);
+    if (threadIdx.x < 64) {
+        uint32_t fl = 0;
+        if (valid) {
+            const double sr = t.qr + C[0], si = t.qi + C[1];
+            const T v = static_cast<T>(fma(sr, sr, si * si));
+            const bool skip = skip3 != nullptr && (i == skip3[0] || i == skip3[1] || i == skip3[2]);
+            fl = flags[i];
+            if (!skip && v > f_cur[i]) {
+                f_cur[i] = v;
+                fl ^= 1u;
+                flags[i] = fl;
+            }
+            if (draws_next) draws_next[i] = de_draw(i, np, D, gen[0] + 1u, inst, k0, k1);
         }
-        const double sr = qr + C[0], si = qi + C[1];
-        const T v = static_cast<T>(fma(sr, sr, si * si));
-        const bool skip = skip3 != nullptr && (i == skip3[0] || i == skip3[1] || i == skip3[2]);
-        if (!skip && v > f_cur[i]) {
-            f_cur[i] = v;
-            flags[i] ^= 1u;
+        const uint64_t m = __ballot(fl != 0u);
+        if (fbits != nullptr && lane == 0) {
+            fbits[2 * blockIdx.x] = static_cast<uint32_t>(m);
+            fbits[2 * blockIdx.x + 1] = static_cast<uint32_t>(m >> 32);
         }
-        if (draws_next) draws_next[i] = de_draw(i, np, D, gen[0] + 1u, inst, k0, k1);
     }
     __shared__ int s_last;
     __threadfence();
@@ -56,17 +63,18 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ 
 }
 
 qpm_status launch_finish(const double *part, int gy, int64_t ld, int64_t np, const double *C, void *f_cur, bool f64,
-                         uint32_t *flags, const int32_t *skip3, int32_t *top3_out, int4 *draws_next, uint32_t *gen,
-                         int64_t D, uint64_t seed, uint32_t inst, uint32_t *ticket, hipStream_t s)
+                         uint32_t *flags, uint32_t *fbits, const int32_t *skip3, int32_t *top3_out,
+                         int4 *draws_next, uint32_t *gen, int64_t D, uint64_t seed, uint32_t inst, uint32_t *ticket,
+                         hipStream_t s)
 {
-    const unsigned blocks = static_cast<unsigned>((np + 255) / 256);
+    const unsigned blocks = static_cast<unsigned>((np + 63) / 64);
     const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
     if (f64)
-        finish_kernel<double><<<blocks, 256, 0, s>>>(part, gy, ld, np, C, static_cast<double *>(f_cur), flags, skip3,
-                                                     top3_out, draws_next, gen, D, k0, k1, inst, ticket);
+        finish_kernel<double><<<blocks, 256, 0, s>>>(part, gy, ld, np, C, static_cast<double *>(f_cur), flags, fbits,
+                                                     skip3, top3_out, draws_next, gen, D, k0, k1, inst, ticket);
     else
-        finish_kernel<float><<<blocks, 256, 0, s>>>(part, gy, ld, np, C, static_cast<float *>(f_cur), flags, skip3,
-                                                    top3_out, draws_next, gen, D, k0, k1, inst, ticket);
+        finish_kernel<float><<<blocks, 256, 0, s>>>(part, gy, ld, np, C, static_cast<float *>(f_cur), flags, fbits,
+                                                    skip3, top3_out, draws_next, gen, D, k0, k1, inst, ticket);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }

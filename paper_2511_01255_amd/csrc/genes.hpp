@@ -108,6 +108,7 @@ __device__ __forceinline__ float4 gwo_quad(float4 xv, float4 X0, float4 X1, floa
 {
     const uint32_t c3 = (inst << 8) | kTagGwo;
     const uint32_t cq = 3u * q;
+    const float two_a_s = two_a * 0x1p-16f;
     const U4 wa = philox10(cq, i, g, c3, k0, k1);
     const U4 wb = philox10(cq + 1u, i, g, c3, k0, k1);
     const U4 wc = philox10(cq + 2u, i, g, c3, k0, k1);
@@ -121,8 +122,10 @@ __device__ __forceinline__ float4 gwo_quad(float4 xv, float4 X0, float4 X1, floa
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const uint32_t o = wrd[3 * e + k];
-            const float r1 = static_cast<float>(o & 0xFFFFu) * 0x1p-16f;
-            const float A = fmaf(two_a, r1, -a);
+            // A = fmaf(2a, lo16 2^-16, -a) with the power of two moved onto
+            // 2a: the product is the same real number (both scalings are
+            // exact for a = 0 or a >= 2^-100), so A is the same float
+            const float A = fmaf(two_a_s, static_cast<float>(o & 0xFFFFu), -a);
             const float Cc = static_cast<float>(o >> 16) * 0x1p-15f;  // = 2 r2, exactly
             const float Dk = fabsf(fmaf(Cc, Xs[k][e], -xs[e]));
             Y[k] = fmaf(-A, Dk, Xs[k][e]);

@@ -20,8 +20,16 @@ struct U4 {
     uint32_t x, y, z, w;
 };
 
-__host__ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                                uint32_t k0, uint32_t k1)
+// three-input exclusive or in one VALU instruction (truth table 0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// One round is two 32 x 32 -> 64-bit multiplies (v_mad_u64_u32) and two
+// three-input xors; the round keys are wave-uniform (scalar registers).
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                       uint32_t k1)
 {
     constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
     constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
@@ -29,8 +37,8 @@ __host__ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa = static_cast<uint64_t>(kMulA) * c0;
         const uint64_t pb = static_cast<uint64_t>(kMulB) * c2;
-        const uint32_t n0 = static_cast<uint32_t>(pb >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = static_cast<uint32_t>(pa >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3(static_cast<uint32_t>(pb >> 32), c1, k0);
+        const uint32_t n2 = xor3(static_cast<uint32_t>(pa >> 32), c3, k1);
         c1 = static_cast<uint32_t>(pb);
         c3 = static_cast<uint32_t>(pa);
         c0 = n0;

@@ -223,6 +223,90 @@ static qpm_status relax_partials(const Design &d, qpm_prec p, const float *theta
     return QPM_OK;
 }
 
+// ---------------------------------------------------------------- polish
+
+// theta_r += eta g_r / max_k |g_rk| for each row r (one workgroup per row)
+__global__ __launch_bounds__(256) void polish_step_kernel(float *__restrict__ theta, const float *__restrict__ grad,
+                                                          int64_t n, int64_t ld, float eta)
+{
+    const int64_t r = blockIdx.x;
+    float *th = theta + r * ld;
+    const float *g = grad + r * ld;
+    float m = 0.0f;
+    for (int64_t k = threadIdx.x; k < n; k += 256) m = fmaxf(m, fabsf(g[k]));
+    for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    __shared__ float sm[4];
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = fmaxf(fmaxf(sm[0], sm[1]), fmaxf(sm[2], sm[3]));
+    if (m == 0.0f) return;
+    const float sc = eta / m;
+    for (int64_t k = threadIdx.x; k < n; k += 256) th[k] = fmaf(sc, g[k], th[k]);
+}
+
+// y = clamp(theta, -1, 1): the +-1 projection keeps the sign of theta and
+// is a valid gene row
+__global__ __launch_bounds__(256) void polish_project_kernel(const float *__restrict__ theta, float *__restrict__ y,
+                                                             int64_t n, int64_t ld)
+{
+    const int64_t r = blockIdx.y;
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; k < n; k += 256 * gridDim.x)
+        y[r * ld + k] = fminf(fmaxf(theta[r * ld + k], -1.0f), 1.0f);
+}
+
+// For each of the three leaders: keep the projected row when its exact +-1
+// fitness beats the leader's. One workgroup per leader.
+template <typename T>
+__global__ __launch_bounds__(256) void polish_accept_kernel(const float *__restrict__ y, int64_t n, int64_t ldy,
+                                                            const T *__restrict__ fcand, const int32_t *__restrict__ L,
+                                                            float *__restrict__ x0, float *__restrict__ x1,
+                                                            const uint32_t *__restrict__ flags, int64_t ldx,
+                                                            T *__restrict__ f_cur, uint32_t *__restrict__ accepted)
+{
+    const int k = blockIdx.x;
+    const int64_t row = L[k];
+    const T fc = fcand[k];
+    if (!(fc > f_cur[row])) return;
+    float *dst = (flags[row] ? x1 : x0) + row * ldx;
+    for (int64_t j = threadIdx.x; j < n; j += 256) dst[j] = y[k * ldy + j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        f_cur[row] = fc;
+        atomicAdd(accepted, 1u);
+    }
+}
+
+qpm_status launch_polish_step(float *theta, const float *grad, int64_t rows, int64_t n, int64_t ld, float eta,
+                              hipStream_t s)
+{
+    polish_step_kernel<<<static_cast<unsigned>(rows), 256, 0, s>>>(theta, grad, n, ld, eta);
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
+}
+
+qpm_status launch_polish_project(const float *theta, float *y, int64_t rows, int64_t n, int64_t ld, hipStream_t s)
+{
+    const int64_t bx = (n + 255) / 256;
+    polish_project_kernel<<<dim3(static_cast<unsigned>(bx < 64 ? bx : 64), static_cast<unsigned>(rows)), 256, 0, s>>>(
+        theta, y, n, ld);
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
+}
+
+qpm_status launch_polish_accept(const float *y, int64_t n, int64_t ldy, const void *fcand, bool f64, const int32_t *L,
+                                const PopView &pv, void *f_cur, uint32_t *accepted, hipStream_t s)
+{
+    float *x0 = const_cast<float *>(pv.x0), *x1 = const_cast<float *>(pv.x1);
+    if (f64)
+        polish_accept_kernel<double><<<3, 256, 0, s>>>(y, n, ldy, static_cast<const double *>(fcand), L, x0, x1,
+                                                       pv.flags, pv.ldx, static_cast<double *>(f_cur), accepted);
+    else
+        polish_accept_kernel<float><<<3, 256, 0, s>>>(y, n, ldy, static_cast<const float *>(fcand), L, x0, x1,
+                                                      pv.flags, pv.ldx, static_cast<float *>(f_cur), accepted);
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
+}
+
 }  // namespace qpm
 
 using namespace qpm;

@@ -7,6 +7,8 @@
 // and a table of a_g. One generation is a fixed sequence of launches that
 // reads g from the counter, so it is captured once into a HIP graph and
 // replayed G times with no host work or synchronisation in between.
+#include <algorithm>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -24,6 +26,7 @@ struct qpm_run_s {
     int64_t D = 0, ldx = 0, ld = 0, W = 0;
     float *buf[2] = {nullptr, nullptr};
     uint32_t *flags = nullptr;
+    uint32_t *fbits = nullptr;  // flags packed one bit per individual (2 ceil(np / 64) words)
     void *f_cur = nullptr;
     void *f_new = nullptr;
     uint32_t *tbits = nullptr;
@@ -35,6 +38,8 @@ struct qpm_run_s {
     uint32_t *ticket = nullptr;
     double *fws = nullptr;
     FitPlan plan;
+    int de_ipw = 0;     // 0 = chosen from np
+    int de_passes = 1;  // groups of individuals per DE workgroup
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int64_t done = 0;
@@ -43,6 +48,14 @@ struct qpm_run_s {
     hipEvent_t ev[QPM_K_COUNT + 1] = {};
     double ms[QPM_K_COUNT] = {};
     int64_t timed = 0;
+    // gradient polish of the leaders (qpm_run_polish), allocated on first use
+    float *pol = nullptr;       // theta, grad, y: 3 rows of ldx each
+    double *pol_S = nullptr;   // 3 x 2
+    float *pol_f = nullptr;    // 3 relaxed values, then 3 ones (grad_f)
+    void *pol_fc = nullptr;    // 3 exact fitness values
+    uint32_t *pol_bits = nullptr;  // W x 64
+    uint32_t *pol_acc = nullptr;
+    double *pol_ws = nullptr;
 
     bool f64() const { return cfg.prec == QPM_PREC_F64; }
     PopView view() const { return PopView{buf[0], buf[1], flags, buf[0], buf[1], cfg.np, D, ldx}; }
@@ -57,6 +70,7 @@ static void release(qpm_run_s *r)
     (void)hipFree(r->buf[0]);
     (void)hipFree(r->buf[1]);
     (void)hipFree(r->flags);
+    (void)hipFree(r->fbits);
     (void)hipFree(r->f_cur);
     (void)hipFree(r->f_new);
     (void)hipFree(r->tbits);
@@ -67,6 +81,13 @@ static void release(qpm_run_s *r)
     (void)hipFree(r->fws);
     (void)hipFree(r->draws);
     (void)hipFree(r->ticket);
+    (void)hipFree(r->pol);
+    (void)hipFree(r->pol_S);
+    (void)hipFree(r->pol_f);
+    (void)hipFree(r->pol_fc);
+    (void)hipFree(r->pol_bits);
+    (void)hipFree(r->pol_acc);
+    (void)hipFree(r->pol_ws);
     for (auto &e : r->ev)
         if (e) (void)hipEventDestroy(e);
     if (r->st) (void)hipStreamDestroy(r->st);
@@ -90,17 +111,107 @@ static qpm_status enqueue_generation(qpm_run_s *r, hipEvent_t *ev = nullptr)
     if ((st = (call)) != QPM_OK) return st;
     const int gy = r->plan.kind == QPM_FIT_SEGMENTED ? r->plan.gy : 1;
     const double *C = r->d->Cdev;
-    QPM_STEP(QPM_K_DE, launch_de(pv, c.F, c.CR, c.seed, r->gen, 0u, c.inst, r->tbits, r->ld, r->draws, false, r->st))
+    QPM_STEP(QPM_K_DE, launch_de(pv, c.F, c.CR, c.seed, r->gen, 0u, c.inst, r->tbits, r->ld, r->draws, false, r->st,
+                                 r->de_ipw, r->de_passes, r->fbits))
     QPM_STEP(QPM_K_FIT_DE, launch_fitness_partials(*r->d, p, r->tbits, c.np, r->ld, r->plan, r->fws, r->st))
-    QPM_STEP(QPM_K_FINISH_DE, launch_finish(r->fws, gy, r->ld, c.np, C, r->f_cur, r->f64(), r->flags, nullptr,
-                                            r->leaders, nullptr, r->gen, r->D, c.seed, c.inst, r->ticket, r->st))
+    QPM_STEP(QPM_K_FINISH_DE, launch_finish(r->fws, gy, r->ld, c.np, C, r->f_cur, r->f64(), r->flags, r->fbits,
+                                            nullptr, r->leaders, nullptr, r->gen, r->D, c.seed, c.inst, r->ticket, r->st))
     QPM_STEP(QPM_K_GWO, launch_gwo(pv, r->leaders, r->a_tab, 0.0f, c.seed, r->gen, 0u, c.inst, c.gwo_variant,
                                    r->tbits, r->ld, r->st))
     QPM_STEP(QPM_K_FIT_GWO, launch_fitness_partials(*r->d, p, r->tbits, c.np, r->ld, r->plan, r->fws, r->st))
-    QPM_STEP(QPM_K_FINISH_GWO, launch_finish(r->fws, gy, r->ld, c.np, C, r->f_cur, r->f64(), r->flags, r->leaders,
-                                             nullptr, r->draws, r->gen, r->D, c.seed, c.inst, r->ticket, r->st))
+    QPM_STEP(QPM_K_FINISH_GWO, launch_finish(r->fws, gy, r->ld, c.np, C, r->f_cur, r->f64(), r->flags, r->fbits,
+                                             r->leaders, nullptr, r->draws, r->gen, r->D, c.seed, c.inst, r->ticket, r->st))
 #undef QPM_STEP
     return mark(QPM_K_COUNT);
+}
+
+// Time candidate launch shapes on the initial population (bits in tbits,
+// genes in buf[0]) and keep the fastest: the segmented fitness shape
+// (waves per workgroup, words per wave) and the DE chunk width (individuals
+// per wave). Every candidate computes the same values (the fitness up to the
+// summation order). Leaves buf[1], tbits and draws overwritten.
+static qpm_status tune_run(qpm_run_s *r)
+{
+    const qpm_run_config &c = r->cfg;
+    const qpm_prec p = static_cast<qpm_prec>(c.prec);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    QPM_TRY_HIP(hipEventCreate(&e0));
+    QPM_TRY_HIP(hipEventCreate(&e1));
+    auto time3 = [&](auto &&launch, float *ms) -> qpm_status {
+        qpm_status st = launch();  // warm-up
+        if (st != QPM_OK) return st;
+        QPM_TRY_HIP(hipEventRecord(e0, r->st));
+        for (int rep = 0; rep < 3 && st == QPM_OK; ++rep) st = launch();
+        QPM_TRY_HIP(hipEventRecord(e1, r->st));
+        QPM_TRY_HIP(hipEventSynchronize(e1));
+        QPM_TRY_HIP(hipEventElapsedTime(ms, e0, e1));
+        return st;
+    };
+    qpm_status st = QPM_OK;
+    if (r->plan.kind == QPM_FIT_SEGMENTED) {
+        const std::string key = tune_key("fit", r->d->words, c.np, c.prec, 1);
+        int waves = 0, wpw = 0;
+        if (!tune_lookup(key, &waves, &wpw)) {
+            const int w0 = r->plan.wpw;
+            std::vector<FitPlan> cands;
+            for (int wv : {4, 8, 16})
+                for (int f : {1, 2, 4, 8}) {
+                    FitPlan pl = plan_fitness_shape(*r->d, wv, std::max(1, w0 * f / 2));
+                    if (pl.gy <= 65535) cands.push_back(pl);
+                }
+            size_t maxb = 0;
+            for (const auto &pl : cands) maxb = std::max(maxb, fitness_partials_bytes(pl, r->ld));
+            double *part = nullptr;
+            QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&part), maxb, r->st));
+            float best = 1e30f;
+            for (const auto &pl : cands) {
+                float ms = 0.0f;
+                st = time3([&]() { return launch_fitness_partials(*r->d, p, r->tbits, c.np, r->ld, pl, part, r->st); },
+                           &ms);
+                if (st != QPM_OK) break;
+                if (ms < best) {
+                    best = ms;
+                    waves = pl.waves;
+                    wpw = pl.wpw;
+                }
+            }
+            (void)hipFreeAsync(part, r->st);
+            if (st != QPM_OK) return st;
+            tune_store(key, waves, wpw);
+        }
+        r->plan = plan_fitness_shape(*r->d, waves, wpw);
+    }
+    {
+        const std::string key = tune_key("de2", r->D, c.np, 0, 1);
+        int ipw = 0, passes = 0;
+        if (!tune_lookup(key, &ipw, &passes)) {
+            st = launch_draws(c.np, r->D, c.seed, r->gen, c.inst, r->draws, r->st);
+            if (st != QPM_OK) return st;
+            const PopView pv = r->view();
+            float best = 1e30f;
+            for (int cand : {1, 2, 4})
+                for (int np_ : {1, 2, 4}) {
+                    float ms = 0.0f;
+                    st = time3([&]() {
+                        return launch_de(pv, c.F, c.CR, c.seed, r->gen, 0u, c.inst, r->tbits, r->ld, r->draws, false,
+                                         r->st, cand, np_, r->fbits);
+                    },
+                               &ms);
+                    if (st != QPM_OK) return st;
+                    if (ms < best) {
+                        best = ms;
+                        ipw = cand;
+                        passes = np_;
+                    }
+                }
+            tune_store(key, ipw, passes);
+        }
+        r->de_ipw = ipw;
+        r->de_passes = passes >= 1 ? passes : 1;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return QPM_OK;
 }
 
 QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_stream sv, qpm_run_handle *out)
@@ -139,6 +250,7 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     if (e == hipSuccess) e = hipMalloc(&r->buf[0], gene_bytes);
     if (e == hipSuccess) e = hipMalloc(&r->buf[1], gene_bytes);
     if (e == hipSuccess) e = hipMalloc(&r->flags, sizeof(uint32_t) * c.np);
+    if (e == hipSuccess) e = hipMalloc(&r->fbits, sizeof(uint32_t) * 2 * ((c.np + 63) / 64));
     if (e == hipSuccess) e = hipMalloc(&r->f_cur, es * c.np);
     if (e == hipSuccess) e = hipMalloc(&r->f_new, es * c.np);
     if (e == hipSuccess) e = hipMalloc(&r->tbits, sizeof(uint32_t) * r->W * r->ld);
@@ -148,7 +260,6 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     if (e == hipSuccess) e = hipMalloc(&r->a_tab, sizeof(float) * c.generations);
     if (e == hipSuccess) e = hipMalloc(&r->draws, sizeof(int4) * c.np);
     if (e == hipSuccess) e = hipMalloc(&r->ticket, sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc(&r->fws, fitness_partials_bytes(r->plan, r->ld));
     if (e != hipSuccess) {
         set_error("run allocation failed: %s", hipGetErrorString(e));
         release(r);
@@ -165,6 +276,7 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     if (e == hipSuccess) e = hipStreamWaitEvent(r->st, ev, 0);
     if (e == hipSuccess) e = hipMemcpyAsync(r->a_tab, a.data(), sizeof(float) * c.generations, hipMemcpyHostToDevice, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->flags, 0, sizeof(uint32_t) * c.np, r->st);
+    if (e == hipSuccess) e = hipMemsetAsync(r->fbits, 0, sizeof(uint32_t) * 2 * ((c.np + 63) / 64), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->gen, 0, sizeof(uint32_t), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->ticket, 0, sizeof(uint32_t), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->tbits, 0, sizeof(uint32_t) * r->W * r->ld, r->st);
@@ -176,9 +288,21 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
         release(r);
         return QPM_EHIP;
     }
-    // step 1: initialise, evaluate, leaders
+    // step 1: initialise, evaluate, leaders (after tuning on the initial
+    // population, which the tuner's trial launches overwrite)
     const qpm_prec p = static_cast<qpm_prec>(c.prec);
     st = launch_init(c.np, r->D, r->ldx, c.seed, c.inst, r->buf[0], r->tbits, r->ld, r->st);
+    if (st == QPM_OK && c.tune) {
+        st = tune_run(r);
+        if (st == QPM_OK) st = launch_init(c.np, r->D, r->ldx, c.seed, c.inst, r->buf[0], r->tbits, r->ld, r->st);
+    }
+    if (st == QPM_OK) {
+        e = hipMalloc(&r->fws, fitness_partials_bytes(r->plan, r->ld));
+        if (e != hipSuccess) {
+            set_error("run allocation failed: %s", hipGetErrorString(e));
+            st = e == hipErrorOutOfMemory ? QPM_ENOMEM : QPM_EHIP;
+        }
+    }
     if (st == QPM_OK) st = launch_fitness(*d, p, r->tbits, c.np, r->ld, r->f_cur, r->plan, r->fws, r->st);
     if (st == QPM_OK) st = launch_top3(r->f_cur, c.np, r->f64(), r->leaders, r->st);
     if (st == QPM_OK) st = launch_draws(c.np, r->D, c.seed, r->gen, c.inst, r->draws, r->st);
@@ -273,6 +397,7 @@ QPM_API qpm_status qpm_run_load(qpm_run_handle r, const float *x, int64_t ldx)
     QPM_TRY_HIP(hipMemcpy2DAsync(r->buf[0], sizeof(float) * r->ldx, x, sizeof(float) * ldx, sizeof(float) * r->D,
                                  c.np, hipMemcpyDeviceToDevice, r->st));
     QPM_TRY_HIP(hipMemsetAsync(r->flags, 0, sizeof(uint32_t) * c.np, r->st));
+    QPM_TRY_HIP(hipMemsetAsync(r->fbits, 0, sizeof(uint32_t) * 2 * ((c.np + 63) / 64), r->st));
     qpm_status st = launch_pack_pop(r->buf[0], c.np, r->D, r->ldx, r->tbits, r->ld, r->st);
     if (st == QPM_OK)
         st = launch_fitness(*r->d, static_cast<qpm_prec>(c.prec), r->tbits, c.np, r->ld, r->f_cur, r->plan, r->fws,
@@ -337,6 +462,58 @@ QPM_API qpm_status qpm_run_best(qpm_run_handle r, float *best_x, uint32_t *best_
         stats->fitness_evals = r->cfg.np + r->done * (2 * r->cfg.np - 3);
         stats->domain_evals = static_cast<double>(stats->fitness_evals) * static_cast<double>(r->D);
     }
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_run_polish(qpm_run_handle r, int32_t steps, float eta, int32_t *accepted)
+{
+    clear_error();
+    QPM_REQUIRE(r != nullptr, QPM_EINVAL, "run is NULL");
+    QPM_REQUIRE(steps >= 0 && steps <= 100000, QPM_EINVAL, "steps must be in [0, 1e5] (got %d)", (int)steps);
+    QPM_REQUIRE(eta >= 0.0f && eta <= 1e6f, QPM_EINVAL, "eta must be finite and >= 0");
+    const qpm_run_config &c = r->cfg;
+    const qpm_prec p = static_cast<qpm_prec>(c.prec);
+    const int64_t ldx = r->ldx, D = r->D;
+    const FitPlan pl3 = plan_fitness(*r->d, p, 3, QPM_FIT_AUTO);
+    if (!r->pol) {
+        hipError_t e = hipMalloc(&r->pol, sizeof(float) * 9 * ldx);
+        if (e == hipSuccess) e = hipMalloc(&r->pol_S, sizeof(double) * 6);
+        if (e == hipSuccess) e = hipMalloc(&r->pol_f, sizeof(float) * 6);
+        if (e == hipSuccess) e = hipMalloc(&r->pol_fc, sizeof(double) * 3);
+        if (e == hipSuccess) e = hipMalloc(&r->pol_bits, sizeof(uint32_t) * r->W * 64);
+        if (e == hipSuccess) e = hipMalloc(&r->pol_acc, sizeof(uint32_t));
+        const size_t wsb = fitness_workspace_bytes(pl3, 64);
+        if (e == hipSuccess && wsb) e = hipMalloc(&r->pol_ws, wsb);
+        if (e == hipSuccess) e = hipMemsetAsync(r->pol, 0, sizeof(float) * 9 * ldx, r->st);
+        static const float ones[3] = {1.0f, 1.0f, 1.0f};
+        if (e == hipSuccess) e = hipMemcpyAsync(r->pol_f + 3, ones, sizeof(ones), hipMemcpyHostToDevice, r->st);
+        if (e == hipSuccess) e = hipMemsetAsync(r->pol_bits, 0, sizeof(uint32_t) * r->W * 64, r->st);
+        if (e != hipSuccess) {
+            set_error("polish allocation failed: %s", hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? QPM_ENOMEM : QPM_EHIP;
+        }
+    }
+    float *theta = r->pol, *grad = r->pol + 3 * ldx, *y = r->pol + 6 * ldx;
+    auto *dh = const_cast<qpm_design_s *>(static_cast<const qpm_design_s *>(r->d));
+    const PopView pv = r->view();
+    qpm_status st = launch_gather(pv, r->leaders, 3, theta, ldx, r->st);
+    for (int32_t k = 0; k < steps && st == QPM_OK; ++k) {
+        st = qpm_relax_forward(dh, p, theta, 3, ldx, r->pol_f, r->pol_S, r->st);
+        if (st == QPM_OK) st = qpm_relax_backward(dh, p, theta, 3, ldx, r->pol_S, r->pol_f + 3, grad, ldx, r->st);
+        if (st == QPM_OK) st = launch_polish_step(theta, grad, 3, D, ldx, eta, r->st);
+    }
+    if (st == QPM_OK) st = launch_polish_project(theta, y, 3, D, ldx, r->st);
+    if (st == QPM_OK) st = launch_pack_pop(y, 3, D, ldx, r->pol_bits, 64, r->st);
+    if (st == QPM_OK) st = launch_fitness(*r->d, p, r->pol_bits, 3, 64, r->pol_fc, pl3, r->pol_ws, r->st);
+    if (st == QPM_OK) {
+        QPM_TRY_HIP(hipMemsetAsync(r->pol_acc, 0, sizeof(uint32_t), r->st));
+        st = launch_polish_accept(y, D, ldx, r->pol_fc, r->f64(), r->leaders, pv, r->f_cur, r->pol_acc, r->st);
+    }
+    if (st != QPM_OK) return st;
+    uint32_t acc = 0;
+    QPM_TRY_HIP(hipMemcpyAsync(&acc, r->pol_acc, sizeof(acc), hipMemcpyDeviceToHost, r->st));
+    QPM_TRY_HIP(hipStreamSynchronize(r->st));
+    if (accepted) *accepted = static_cast<int32_t>(acc);
     return QPM_OK;
 }
 

@@ -40,6 +40,52 @@ __device__ __forceinline__ void tri_append(Tri &t, const Tri &u)
     t.bi += u.bi;
 }
 
+// Segment triples of genome i are stored as part[s][6][ld] (A, B, Q real
+// and imaginary parts). The gy segments are split into NW contiguous
+// ranges, range w = [gy w / NW, gy (w+1) / NW) folded in order by wave w of
+// the workgroup (lane = genome); wave 0 then folds the NW range triples in
+// order. Every caller uses this one association, so a genome's fitness has
+// the same bits whichever kernel combines it. Call from every lane (the
+// workgroup synchronises); the result is valid in wave 0.
+template <int NW>
+__device__ __forceinline__ Tri combine_segments(const double *__restrict__ part, int gy, int64_t ld, int64_t i,
+                                                bool valid)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int s0 = static_cast<int>((static_cast<int64_t>(gy) * wave) / NW);
+    const int s1 = static_cast<int>((static_cast<int64_t>(gy) * (wave + 1)) / NW);
+    Tri t{0, 0, 0, 0, 0, 0};
+    if (valid && s0 < s1) {
+        const double *p = part + static_cast<int64_t>(s0) * 6 * ld + i;
+        t = Tri{p[0], p[ld], p[2 * ld], p[3 * ld], p[4 * ld], p[5 * ld]};
+#pragma unroll 4
+        for (int sg = s0 + 1; sg < s1; ++sg) {
+            const double *q = part + static_cast<int64_t>(sg) * 6 * ld + i;
+            tri_append(t, Tri{q[0], q[ld], q[2 * ld], q[3 * ld], q[4 * ld], q[5 * ld]});
+        }
+    }
+    if constexpr (NW > 1) {
+        __shared__ double sh[6][NW][64];
+        sh[0][wave][lane] = t.ar;
+        sh[1][wave][lane] = t.ai;
+        sh[2][wave][lane] = t.br;
+        sh[3][wave][lane] = t.bi;
+        sh[4][wave][lane] = t.qr;
+        sh[5][wave][lane] = t.qi;
+        __syncthreads();
+        if (wave == 0) {
+            for (int w = 1; w < NW; ++w) {
+                const int a = static_cast<int>((static_cast<int64_t>(gy) * w) / NW);
+                const int b = static_cast<int>((static_cast<int64_t>(gy) * (w + 1)) / NW);
+                if (a < b)
+                    tri_append(t, Tri{sh[0][w][lane], sh[1][w][lane], sh[2][w][lane], sh[3][w][lane],
+                                      sh[4][w][lane], sh[5][w][lane]});
+            }
+        }
+    }
+    return t;
+}
+
 __device__ __forceinline__ void store_fitness(void *fit, int out_f64, int64_t i, const Tri &t,
                                               const double *__restrict__ C)
 {

@@ -37,7 +37,7 @@ class QpmError(RuntimeError):
 class RunConfig(C.Structure):
     _fields_ = [("np", _I64), ("generations", _I64), ("F", _F), ("CR", _F), ("seed", _U64),
                 ("inst", _U32), ("prec", _I32), ("gwo_variant", _I32), ("use_graph", _I32),
-                ("fit_kernel", _I32)]
+                ("fit_kernel", _I32), ("tune", _I32)]
 
 
 class RunStats(C.Structure):
@@ -58,6 +58,7 @@ _SIGS = {
     "qpm_eval_fitness_shape": (_I32, [_P, _I32, _P, _I64, _I64, _P, _I32, _I32, _P]),
     "qpm_init_population": (_I32, [_I64, _I64, _I64, _U64, _U32, _P, _P, _I64, _P]),
     "qpm_de_step": (_I32, [_P, _I64, _I64, _I64, _F, _F, _U64, _U32, _U32, _P, _P, _I64, _P]),
+    "qpm_de_step_shape": (_I32, [_P, _I64, _I64, _I64, _F, _F, _U64, _U32, _U32, _P, _P, _I64, _I32, _I32, _P]),
     "qpm_gwo_step": (_I32, [_P, _I64, _I64, _I64, _P, _F, _U64, _U32, _U32, _I32, _P, _P, _I64, _P]),
     "qpm_relax_forward": (_I32, [_P, _I32, _P, _I64, _I64, _P, _P, _P]),
     "qpm_relax_backward": (_I32, [_P, _I32, _P, _I64, _I64, _P, _P, _P, _I64, _P]),
@@ -67,6 +68,7 @@ _SIGS = {
     "qpm_run_best": (_I32, [_P, _P, _P, C.POINTER(RunStats)]),
     "qpm_run_destroy": (_I32, [_P]),
     "qpm_run_load": (_I32, [_P, _P, _I64]),
+    "qpm_run_polish": (_I32, [_P, _I32, _F, _P]),
     "qpm_run_set_timing": (_I32, [_P, _I32]),
     "qpm_run_timing": (_I32, [_P, _P, _P, _I32]),
     "qpm_run": (_I32, [_P, C.POINTER(RunConfig), _P, _P, C.POINTER(RunStats), _P]),
@@ -201,15 +203,20 @@ def init_population(np_, D, seed, inst=0, ldx=None, device="cuda", stream=None):
     return x, bits
 
 
-def de_step(x, D, F, CR, seed, generation, inst=0, stream=None):
-    """x: float32 CUDA tensor (np, ldx) -> (u, u_bits)."""
+def de_step(x, D, F, CR, seed, generation, inst=0, stream=None, shape=None):
+    """x: float32 CUDA tensor (np, ldx) -> (u, u_bits). shape: optional
+    (individuals_per_wave, passes) launch shape."""
     import torch
     np_, ldx = x.shape
     ld = ld_for(np_)
     u = torch.zeros_like(x)
     ub = torch.zeros((words(D), ld), dtype=torch.int32, device=x.device)
-    _check(lib().qpm_de_step(_ptr(x), np_, D, ldx, F, CR, seed, generation, inst, _ptr(u), _ptr(ub), ld,
-                             _stream(stream)))
+    if shape is None:
+        _check(lib().qpm_de_step(_ptr(x), np_, D, ldx, F, CR, seed, generation, inst, _ptr(u), _ptr(ub), ld,
+                                 _stream(stream)))
+    else:
+        _check(lib().qpm_de_step_shape(_ptr(x), np_, D, ldx, F, CR, seed, generation, inst, _ptr(u), _ptr(ub), ld,
+                                       shape[0], shape[1], _stream(stream)))
     return u, ub
 
 
@@ -284,18 +291,18 @@ def relax(theta, design, prec=PREC_F32):
 
 
 def _config(np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0, use_graph=1,
-            fit_kernel=FIT_AUTO):
+            fit_kernel=FIT_AUTO, tune=0):
     return RunConfig(np=np_, generations=generations, F=F, CR=CR, seed=seed, inst=inst, prec=prec,
-                     gwo_variant=gwo_variant, use_graph=use_graph, fit_kernel=fit_kernel)
+                     gwo_variant=gwo_variant, use_graph=use_graph, fit_kernel=fit_kernel, tune=tune)
 
 
 class Run:
     """A whole optimisation on the device (run_create / advance / read / best)."""
 
     def __init__(self, design, np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0,
-                 use_graph=1, fit_kernel=FIT_AUTO, stream=None):
+                 use_graph=1, fit_kernel=FIT_AUTO, tune=0, stream=None):
         self.design = design
-        self.cfg = _config(np_, generations, F, CR, seed, inst, prec, gwo_variant, use_graph, fit_kernel)
+        self.cfg = _config(np_, generations, F, CR, seed, inst, prec, gwo_variant, use_graph, fit_kernel, tune)
         self.D = design.n
         h = C.c_void_p()
         _check(lib().qpm_run_create(design.handle, C.byref(self.cfg), _stream(stream), C.byref(h)))
@@ -325,6 +332,12 @@ class Run:
     def load(self, x):
         """x: float32 CUDA tensor (np, >= D) -> becomes the population."""
         _check(lib().qpm_run_load(self._h, _ptr(x), x.shape[1]))
+
+    def polish(self, steps=20, eta=0.05):
+        """Gradient polish of the three leaders; returns how many improved."""
+        acc = C.c_int32()
+        _check(lib().qpm_run_polish(self._h, steps, eta, C.byref(acc)))
+        return int(acc.value)
 
     def set_timing(self, enable=True):
         _check(lib().qpm_run_set_timing(self._h, 1 if enable else 0))

@@ -95,11 +95,20 @@ def test_de_and_gwo_reject_bad_arguments(L):
     assert de(uu=x) == -1 and "overlap" in _err(L)
     assert de(bb=None) == -1
 
+    def de_shape(ipw, passes, np_=3):
+        return L.qpm_de_step_shape(x, np_, 10, 12, C.c_float(0.5), C.c_float(0.9), 0, 0, 0, u, b, 64, ipw, passes,
+                                   None)
+
+    assert de_shape(3, 1) == -1 and "individuals_per_wave" in _err(L)
+    assert de_shape(1, 3) == -1 and "passes" in _err(L)
+    assert de_shape(2, 2) == -1 and "np >= 4" in _err(L)  # a valid shape goes on to the usual checks
+
     def gwo(np_=8, D=10, ldx=12, a=1.0, variant=0, leaders=C.c_void_p(0x40000000)):
         return L.qpm_gwo_step(x, np_, D, ldx, leaders, C.c_float(a), 0, 0, 0, variant, u, b, 64, None)
 
     assert gwo(np_=3) == -1
     assert gwo(a=-1.0) == -1
+    assert gwo(a=1e-35) == -1 and "2^-100" in _err(L)
     assert gwo(variant=2) == -1
     assert gwo(leaders=None) == -1
 

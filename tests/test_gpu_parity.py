@@ -174,6 +174,18 @@ def test_de_step_matches_oracle(q, orc, np_, D, F, CR):
         assert np.array_equal(inputs.unpack_bits(ub.cpu().numpy(), np_, D), orc.sign_map(uo))
 
 
+@pytest.mark.parametrize("shape", [(w, p) for w in (1, 2, 4) for p in (1, 2, 4)], ids=lambda s: "ipw%d_p%d" % s)
+def test_de_every_launch_shape_matches_oracle(q, orc, shape):
+    # ragged in both axes: np not a multiple of any workgroup's individuals,
+    # D not a multiple of any chunk width
+    for np_, D in ((70, 1007), (517, 3001)):
+        x, _ = q.init_population(np_, D, seed=9)
+        u, ub = q.de_step(x, D, 0.5, 0.9, seed=4, generation=2, inst=3, shape=shape)
+        uo, _ = orc.de_step(_host(x, D), 0.5, 0.9, seed=4, g=2, inst=3)
+        assert np.array_equal(_host(u, D), uo)
+        assert np.array_equal(inputs.unpack_bits(ub.cpu().numpy(), np_, D), orc.sign_map(uo))
+
+
 @pytest.mark.parametrize("np_,D", [(37, 203), (4, 5), (300, 1001), (1024, 10000)])
 @pytest.mark.parametrize("variant", [0, 1])
 def test_gwo_step_matches_oracle(q, orc, np_, D, variant):
@@ -318,3 +330,20 @@ def test_fitness_every_launch_shape_matches_oracle(q, orc, prec):
             f = q.eval_fitness_shape(D, bits, npop, prec, waves, wpw).double().cpu().numpy()
             err = _rel_err(f, fo)
             assert err.max() <= TOL[prec], (waves, wpw, err.max())
+
+
+def test_run_tuned_equals_untuned_fp64(q):
+    # the tuner only changes launch shapes: DE chunk widths give identical
+    # trials, fitness shapes change the FP64 summation order (~1e-16), far
+    # below the gaps between distinct genomes
+    n, npop, G = 3001, 200, 8
+    D = q.precompute_phases(inputs.uniform_boundaries(n, 2.0), DK1, DK2)
+    outs = []
+    for tune in (0, 1):
+        R = q.Run(D, npop, G, seed=9, prec=1, tune=tune)
+        R.advance(G)
+        x, f, L, _ = R.read()
+        outs.append((x.cpu().numpy(), f.cpu().numpy(), L))
+        R.destroy()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.max(np.abs(outs[0][1] - outs[1][1]) / outs[0][1]) <= 1e-13

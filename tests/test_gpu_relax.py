@@ -115,3 +115,36 @@ def test_relax_corners_equal_pm1_fitness(q):
     bits = torch.from_numpy(inputs.pack_bits(d).view(np.int32)).cuda()
     fp = q.eval_fitness(D, bits, B, prec=q.PREC_F64).cpu().numpy()
     assert np.max(np.abs(f.double().cpu().numpy() - fp) / fp) <= 1e-6  # f is returned in float32
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_run_polish_of_leaders(q, prec):
+    # polish never lowers a leader, touches nothing else, replaces a leader
+    # only by genes whose exact +-1 fitness is higher, and is deterministic
+    n, npop = 2000, 64
+    D = q.precompute_phases(inputs.uniform_boundaries(n, 2.0), DK1, DK2)
+    results = []
+    for rep in range(2):
+        R = q.Run(D, npop, 10, seed=2, prec=prec)
+        R.advance(3)
+        x0, f0, L, _ = R.read()
+        acc = R.polish(20, 0.05)
+        x1, f1, L1, _ = R.read()
+        x0, f0, x1, f1 = (t.cpu().numpy() for t in (x0, f0, x1, f1))
+        others = np.setdiff1d(np.arange(npop), L)
+        assert np.array_equal(x1[others], x0[others]) and np.array_equal(f1[others], f0[others])
+        changed = [k for k in L if not np.array_equal(x1[k], x0[k])]
+        assert len(changed) == acc and 0 <= acc <= 3
+        for k in L:
+            assert f1[k] >= f0[k]
+        for k in changed:
+            assert f1[k] > f0[k] and np.all(np.abs(x1[k]) <= 1.0)
+            import torch
+            bits = torch.from_numpy(inputs.pack_bits(np.where(x1[k] < 0, -1, 1)[None].astype(np.int8))
+                                    .view(np.int32)).cuda()
+            fe = q.eval_fitness(D, bits, 1, prec=prec).double().cpu().numpy()[0]
+            assert abs(fe - f1[k]) <= (1e-12 if prec == 1 else 1e-6) * fe
+        R.advance(2)  # the run continues after a polish
+        results.append((x1, f1, acc))
+        R.destroy()
+    assert np.array_equal(results[0][0], results[1][0]) and results[0][2] == results[1][2]
