@@ -39,6 +39,13 @@ PEAK_VALU_TOPS = 39.3        # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, lane-instru
 
 N_DOMAINS, NP, WIDTH = 10000, 4096, 2.0
 F, CR, SEED = 0.5, 0.9, 0
+# The grey-wolf update's minimal VALU work per gene, in lane-instructions:
+# Philox4x32-10 at 0.75 calls per gene x 10 rounds x (2 v_mad_u64_u32 +
+# 2 three-input xors) = 30; per leader two 16-bit conversions, A (1 FMA),
+# C X_k (multiply + FMA), Y_k (1 FMA) = 6, x 3 = 18; the combination: |Y|
+# sum (2), numerator (3), the IEEE division sequence (9), x / 3 (4), zero
+# test (2), clamp (1), sign bit (1) = 22.
+GWO_INSTR_PER_GENE = 30 + 18 + 22
 
 
 def algorithmic_work(step, npop, n):
@@ -48,8 +55,8 @@ def algorithmic_work(step, npop, n):
     bits = genes / 8.0
     if step == "de":          # target + 3 donors read, trial written, trial bits
         return "hbm", 20.0 * genes + bits, "B"
-    if step == "gwo":         # Philox words: 3 calls per 4 genes (integer VALU)
-        return "alu", 0.75 * genes, "philox"
+    if step == "gwo":         # VALU lane-instructions of the non-leader genes
+        return "alu", GWO_INSTR_PER_GENE * (npop - 3) * n, "instr"
     if step.startswith("fitness"):  # 10 flops per domain evaluation, bits read
         return "alu", 10.0 * genes, "flop"
     return "latency", 0.0, ""
@@ -93,12 +100,6 @@ def measured_traffic(step):
     except (KeyError, ValueError):
         return None
 
-
-def philox_issue_slots():
-    """VALU issue slots of one Philox4x32-10 call on gfx950: 10 rounds of two
-    32x32->64 multiplies (v_mad_u64_u32, quarter rate = 4 slots each) and
-    four 32-bit xors."""
-    return 10 * (2 * 4 + 4)
 
 
 def main():
@@ -197,11 +198,9 @@ def main():
     t_dom = per[dom] * 1e-3
     if bound == "hbm":
         roof = {"bound": "hbm", "achieved": work / t_dom / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
-    elif wunit == "philox":
-        # integer VALU: Philox words per launch x issue slots per word
-        slots = work * philox_issue_slots()
-        roof = {"bound": "alu", "achieved": slots / t_dom / 1e12, "peak": PEAK_VALU_TOPS,
-                "unit": "T VALU lane-slots/s (Philox)"}
+    elif wunit == "instr":
+        roof = {"bound": "alu", "achieved": work / t_dom / 1e12, "peak": PEAK_VALU_TOPS,
+                "unit": "T VALU lane-instructions/s"}
     else:
         peak = PEAK_FP64_TFLOPS if prec == qpm.PREC_F64 else PEAK_FP32_TFLOPS
         roof = {"bound": "alu", "achieved": work / t_dom / 1e12, "peak": peak, "unit": "TFLOP/s"}

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void batch_init_kernel(int64_t np, const InstD
 template <int IPW>
 __global__ __launch_bounds__(256) void batch_de_kernel(BatchPop bp, const InstDesc *__restrict__ inst,
                                                        const Tile *__restrict__ tiles, int ntiles, int groups,
-                                                       const int4 *__restrict__ draws, float F, float CR, uint32_t k0,
+                                                       const int4 *__restrict__ draws, float F, uint32_t cr_max, uint32_t k0,
                                                        uint32_t k1, const uint32_t *__restrict__ gen, uint32_t inst0,
                                                        uint32_t *__restrict__ bits, int64_t ld)
 {
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void batch_de_kernel(BatchPop bp, const InstDe
         const float4 a = *reinterpret_cast<const float4 *>(row_of(pv, dr.x) + j0);
         const float4 bq = *reinterpret_cast<const float4 *>(row_of(pv, dr.y) + j0);
         const float4 cq = *reinterpret_cast<const float4 *>(row_of(pv, dr.z) + j0);
-        const float4 uv = de_quad(xv, a, bq, cq, j0, dr.w, static_cast<uint32_t>(i), g, instb, k0, k1, F, CR);
+        const float4 uv = de_quad(xv, a, bq, cq, j0, dr.w, static_cast<uint32_t>(i), g, instb, k0, k1, F, cr_max);
         store_quad(out_row_of(pv, i), j0, D, uv);
         nib = quad_nibble(uv, j0, D);
     }
@@ -669,7 +669,7 @@ static qpm_status launch_batch_de(qpm_batch_run_s *r)
     const BatchPop bp = r->pop();
 #define QPM_BDE(IPW)                                                                                          \
     batch_de_kernel<IPW><<<nb, 256, 0, r->st>>>(bp, r->inst, r->dtiles, r->n_dtiles, r->de_groups, r->draws, \
-                                                c.F, c.CR, k0, k1, r->gen, c.inst, r->bits, r->ld)
+                                                c.F, cr_threshold(c.CR), k0, k1, r->gen, c.inst, r->bits, r->ld)
     if (r->de_ipw == 1)
         QPM_BDE(1);
     else if (r->de_ipw == 2)

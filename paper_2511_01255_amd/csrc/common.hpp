@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <cmath>
 #include <cstdint>
 #include <string>
 
@@ -82,11 +83,17 @@ qpm_status launch_fitness_partials(const Design &d, qpm_prec p, const uint32_t *
 // select (f > f_cur[i] replaces, leaders in skip3 excluded), then in the
 // last workgroup: top3_out <- leaders (when non-null); with draws_next the
 // DE draws of generation gen + 1 are written and gen is advanced.
-// fbits (optional): packed copy of flags, 2 ceil(np / 64) words
+// fbits (optional): packed copy of flags, 2 ceil(np / 64) words; cand:
+// scratch of finish_cand_bytes(np) for the leader candidates (needed with
+// top3_out)
 qpm_status launch_finish(const double *part, int gy, int64_t ld, int64_t np, const double *C, void *f_cur,
                          bool f64, uint32_t *flags, uint32_t *fbits, const int32_t *skip3, int32_t *top3_out,
-                         int4 *draws_next, uint32_t *gen, int64_t D, uint64_t seed, uint32_t inst, uint32_t *ticket,
-                         hipStream_t s);
+                         void *cand, int4 *draws_next, uint32_t *gen, int64_t D, uint64_t seed, uint32_t inst,
+                         uint32_t *ticket, hipStream_t s);
+inline size_t finish_cand_bytes(int64_t np)
+{
+    return static_cast<size_t>((np + 63) / 64) * 3 * (sizeof(double) + sizeof(int32_t));
+}
 
 // ---------------------------------------------------------------- evolution kernels
 
@@ -105,6 +112,16 @@ struct PopView {
 qpm_status launch_init(int64_t np, int64_t D, int64_t ldx, uint64_t seed, uint32_t inst, float *x,
                        uint32_t *bits, int64_t ld, hipStream_t s);
 // draws: device scratch of np int4 (donors r1, r2, r3 and jrand)
+// Crossover threshold on a raw Philox word w: (w >> 8) 2^-24 <= CR holds
+// exactly when (w >> 8) <= T = floor(CR 2^24) (CR 2^24 is exact), that is
+// when w <= 256 T + 255.
+inline uint32_t cr_threshold(float CR)
+{
+    const float t = std::floor(CR * 16777216.0f);
+    if (t >= 16777215.0f) return 0xFFFFFFFFu;
+    return static_cast<uint32_t>(t) * 256u + 255u;
+}
+
 // ipw: individuals per wave of the DE kernel (1, 2 or 4; 0 = chosen from np);
 // passes: groups of individuals per workgroup (1, 2 or 4); fbits: optional
 // packed copy of pv.flags (bit i % 32 of word i / 32)

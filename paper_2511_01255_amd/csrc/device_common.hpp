@@ -68,11 +68,8 @@ __device__ __forceinline__ void top3_insert(Top3<T> &t, T v, int idx)
     }
 }
 
-// The three best of f[0..np) over one workgroup of NT lanes (NT a multiple
-// of 64, <= 1024). (f descending, slot ascending) is a strict total order,
-// so the result is unique whatever the merge order. Written by lane 0.
-template <typename T, int NT>
-__device__ void block_top3(const T *__restrict__ f, int64_t np, int32_t *__restrict__ out)
+template <typename T>
+__device__ __forceinline__ Top3<T> top3_empty()
 {
     Top3<T> t;
 #pragma unroll
@@ -80,7 +77,14 @@ __device__ void block_top3(const T *__restrict__ f, int64_t np, int32_t *__restr
         t.v[k] = -INFINITY;
         t.i[k] = INT_MAX;
     }
-    for (int64_t i = threadIdx.x; i < np; i += NT) top3_insert(t, f[i], static_cast<int>(i));
+    return t;
+}
+
+// merge the lists of the 64 lanes of a wave (every lane ends with the
+// wave's three best)
+template <typename T>
+__device__ __forceinline__ void wave_top3(Top3<T> &t)
+{
     for (int off = 32; off >= 1; off >>= 1) {
         T ov[3];
         int oi[3];
@@ -92,6 +96,34 @@ __device__ void block_top3(const T *__restrict__ f, int64_t np, int32_t *__restr
 #pragma unroll
         for (int k = 0; k < 3; ++k) top3_insert(t, ov[k], oi[k]);
     }
+}
+
+// The three best of the n candidates (f[j], idx ? idx[j] : j) over one
+// workgroup of NT lanes (NT a multiple of 64, <= 1024). (f descending,
+// slot ascending) is a strict total order, so the result is unique
+// whatever the merge order. Loads are issued four at a time. Written by
+// lane 0.
+template <typename T, int NT>
+__device__ void block_top3(const T *__restrict__ f, int64_t n, int32_t *__restrict__ out,
+                           const int32_t *__restrict__ idx = nullptr)
+{
+    Top3<T> t = top3_empty<T>();
+    for (int64_t base = threadIdx.x; base < n; base += 4 * NT) {
+        T v[4];
+        int ix[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t j = base + static_cast<int64_t>(u) * NT;
+            const int64_t jj = j < n ? j : 0;
+            const T fv = f[jj];
+            const int iv = idx ? idx[jj] : static_cast<int>(jj);
+            v[u] = j < n ? fv : static_cast<T>(-INFINITY);
+            ix[u] = j < n ? iv : INT_MAX;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) top3_insert(t, v[u], ix[u]);
+    }
+    wave_top3(t);
     __shared__ T sv[NT / 64][3];
     __shared__ int si[NT / 64][3];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;

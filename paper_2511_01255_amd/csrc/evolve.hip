@@ -67,16 +67,19 @@ __global__ __launch_bounds__(256) void de_draws_kernel(int64_t np, int64_t D, ui
 // slice of the whole population (np x CW x 4 bytes, chosen <= 2 MB) stays in
 // the XCD's L2 and the random donor rows hit it.
 //
-// Each row's buffer is named by its flag. With `fbits` (the flags packed one
-// bit per individual) the workgroup first copies the packed flags to LDS,
-// so a donor row's address costs an LDS read instead of a second dependent
-// global load after the draw.
-template <int IPW, int R>
+// Each row's buffer is named by its flag. PACKED (a run's population: the
+// two buffers are one allocation, x1 = x0 + np ldx, out0 = x0, out1 = x1,
+// np <= 65536, ldx < 2^24): the workgroup first copies the flags, packed one
+// bit per individual, to LDS; row r of buffer b is then row r + b np of one
+// array, addressed with 24-bit multiplies, so a donor address costs an LDS
+// read and a few ALU operations instead of a second dependent global load.
+// Otherwise the flags (if any) are read from global memory.
+template <int IPW, int R, bool PACKED>
 __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restrict__ draws,
-                                                 const uint32_t *__restrict__ fbits, float F, float CR, uint32_t k0,
-                                                 uint32_t k1, const uint32_t *__restrict__ gen_dev, uint32_t gen_c,
-                                                 uint32_t inst, uint32_t *__restrict__ bits, int64_t ld, int groups,
-                                                 int chunks)
+                                                 const uint32_t *__restrict__ fbits, float F, uint32_t cr_max,
+                                                 uint32_t k0, uint32_t k1, const uint32_t *__restrict__ gen_dev,
+                                                 uint32_t gen_c, uint32_t inst, uint32_t *__restrict__ bits,
+                                                 int64_t ld, int groups, int chunks)
 {
     constexpr int LPI = 64 / IPW;  // lanes per individual
     constexpr int CW = 4 * LPI;    // genes per chunk
@@ -98,23 +101,37 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
     const int64_t j0 = static_cast<int64_t>(c) * CW + 4 * li;
     const uint32_t g = gen_dev ? gen_dev[0] : gen_c;
     __shared__ uint32_t wsh[IPB][WPC];
-    extern __shared__ uint32_t sfb[];  // (np + 31) / 32 packed flags when fbits != nullptr
-    const bool packed = fbits != nullptr;
-    if (packed)
-        for (int64_t k = t; k < (np + 31) / 32; k += 256) sfb[k] = fbits[k];
+    extern __shared__ uint32_t sfb[];  // PACKED: (np + 31) / 32 flag words
     int4 dr[R];
     bool act[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = i0 + r * IPG;
         act[r] = i < np && j0 < D;
-        dr[r] = act[r] ? draws[i] : make_int4(0, 0, 0, 0);
+        // unconditional (clamped) load: no branch, so no wait before the
+        // flag staging below
+        dr[r] = draws[i < np ? i : np - 1];
     }
-    if (packed) __syncthreads();
-    auto second = [&](int64_t r) -> bool {
-        return packed ? ((sfb[r >> 5] >> (r & 31)) & 1u) != 0u : (pv.flags != nullptr && pv.flags[r] != 0u);
+    // the draws' loads are in flight while the flags are staged
+    if constexpr (PACKED) {
+        for (int k = t; k < static_cast<int>((np + 31) / 32); k += 256) sfb[k] = fbits[k];
+        __syncthreads();
+    }
+    const uint32_t np32 = static_cast<uint32_t>(np), ldx24 = static_cast<uint32_t>(pv.ldx) & 0xFFFFFFu;
+    // PACKED: float offset of row r of buffer (flag of r) ^ flip from x0
+    auto packed_row = [&](int64_t r, uint32_t flip) -> uint64_t {
+        const uint32_t rr = static_cast<uint32_t>(r);
+        const uint32_t b = ((sfb[rr >> 5] >> (rr & 31u)) & 1u) ^ flip;
+        const uint32_t row = (rr + b * np32) & 0xFFFFFFu;
+        return static_cast<uint64_t>(row) * ldx24;
     };
-    auto src = [&](int64_t r) -> const float * { return (second(r) ? pv.x1 : pv.x0) + r * pv.ldx; };
+    auto second = [&](int64_t r) -> bool { return pv.flags != nullptr && pv.flags[r] != 0u; };
+    auto src = [&](int64_t r) -> const float * {
+        if constexpr (PACKED)
+            return pv.x0 + packed_row(r, 0u);
+        else
+            return (second(r) ? pv.x1 : pv.x0) + r * pv.ldx;
+    };
     float4 cur[4], nxt[4];
     auto load = [&](int r, float4 *v) {
         if (act[r]) {
@@ -133,8 +150,13 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
         if (act[r]) {
             const int64_t i = i0 + r * IPG;
             const float4 uv = de_quad(cur[0], cur[1], cur[2], cur[3], j0, dr[r].w, static_cast<uint32_t>(i), g, inst,
-                                      k0, k1, F, CR);
-            store_quad((second(i) ? pv.out0 : pv.out1) + i * pv.ldx, j0, D, uv);
+                                      k0, k1, F, cr_max);
+            float *dst;
+            if constexpr (PACKED)
+                dst = pv.out0 + packed_row(i, 1u);
+            else
+                dst = (second(i) ? pv.out0 : pv.out1) + i * pv.ldx;
+            store_quad(dst, j0, D, uv);
             nib = quad_nibble(uv, j0, D);
         }
         // merge the nibbles of 8 neighbouring lanes (32 genes) into one word
@@ -161,14 +183,21 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
 
 // ------------------------------------------------------------ grey-wolf update
 
+// Grid x = 8 ceil(np / 8): workgroup x runs on XCD x mod 8 (gridDim.x is a
+// multiple of 8, so this holds for every y) and takes individual
+// (x mod 8) ceil(np / 8) + x / 8. Each XCD thus owns a contiguous range of
+// individuals and the 32-bit bit words of neighbouring individuals, which
+// share cache lines, are written from one L2 instead of eight.
 __global__ __launch_bounds__(256) void gwo_kernel(PopView pv, const int32_t *__restrict__ leaders,
                                                   const float *__restrict__ a_tab, float a_c, uint32_t k0, uint32_t k1,
                                                   const uint32_t *__restrict__ gen_dev, uint32_t gen_c, uint32_t inst,
-                                                  int variant, uint32_t *__restrict__ bits, int64_t ld)
+                                                  int variant, uint32_t *__restrict__ bits, int64_t ld,
+                                                  int64_t per_xcd)
 {
-    const int64_t i = blockIdx.x;
-    const int64_t L0 = leaders[0], L1 = leaders[1], L2 = leaders[2];
     const int64_t np = pv.np, D = pv.D;
+    const int64_t i = static_cast<int64_t>(blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
+    if (i >= np) return;
+    const int64_t L0 = leaders[0], L1 = leaders[1], L2 = leaders[2];
     // leaders keep their positions; indices outside the population make
     // the launch a no-op instead of an out-of-bounds read
     if (i == L0 || i == L1 || i == L2) return;
@@ -251,9 +280,20 @@ static dim3 quad_grid(int64_t D, int64_t rows)
     return dim3(static_cast<unsigned>(rows), static_cast<unsigned>((quads + 255) / 256));
 }
 
+// grid.x holds rows (< 2^31) and grid.y the 1024-gene chunks (<= 65535)
+static qpm_status check_quad_grid(int64_t D, int64_t rows)
+{
+    QPM_REQUIRE(rows < (int64_t(1) << 31), QPM_ERANGE, "too many rows for one launch (%lld)", (long long)rows);
+    QPM_REQUIRE((D + 1023) / 1024 <= 65535, QPM_ERANGE, "D = %lld exceeds 65535 chunks of 1024 genes",
+                (long long)D);
+    return QPM_OK;
+}
+
 qpm_status launch_init(int64_t np, int64_t D, int64_t ldx, uint64_t seed, uint32_t inst, float *x, uint32_t *bits,
                        int64_t ld, hipStream_t s)
 {
+    const qpm_status st = check_quad_grid(D, np);
+    if (st != QPM_OK) return st;
     init_kernel<<<quad_grid(D, np), 256, 0, s>>>(D, ldx, static_cast<uint32_t>(seed),
                                                  static_cast<uint32_t>(seed >> 32), inst, x, bits, ld);
     QPM_TRY_HIP(hipGetLastError());
@@ -264,9 +304,12 @@ qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const 
                      uint32_t inst, uint32_t *bits, int64_t ld, int4 *draws, bool compute_draws, hipStream_t s,
                      int ipw_req, int passes, const uint32_t *fbits)
 {
-    // the packed flags are staged in LDS up to 65536 individuals (8 KB)
-    if (pv.np > 65536) fbits = nullptr;
-    const size_t lds = fbits ? sizeof(uint32_t) * static_cast<size_t>((pv.np + 31) / 32) : 0;
+    // the packed-flag path: one allocation for both buffers, flags staged
+    // in LDS (at most 65536 individuals, 8 KB), 24-bit row arithmetic
+    const bool packed = fbits != nullptr && pv.np <= 65536 && pv.ldx < (int64_t(1) << 24) &&
+                        pv.x1 == pv.x0 + pv.np * pv.ldx && pv.out0 == pv.x0 && pv.out1 == pv.x1;
+    const size_t lds = packed ? sizeof(uint32_t) * static_cast<size_t>((pv.np + 31) / 32) : 0;
+    const uint32_t cr_max = cr_threshold(CR);
     const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
     if (compute_draws)
         de_draws_kernel<<<static_cast<unsigned>((pv.np + 255) / 256), 256, 0, s>>>(pv.np, pv.D, k0, k1, gen_dev,
@@ -283,14 +326,19 @@ qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const 
     QPM_REQUIRE(blocks < (int64_t(1) << 31), QPM_ERANGE, "population too large for one DE launch");
     const int gr = static_cast<int>(groups), ch = static_cast<int>(chunks);
     const unsigned nb = static_cast<unsigned>(blocks);
-#define QPM_DE(I, P) \
-    de_kernel<I, P><<<nb, 256, lds, s>>>(pv, draws, fbits, F, CR, k0, k1, gen_dev, gen, inst, bits, ld, gr, ch)
+#define QPM_DE(I, P)                                                                                            \
+    if (packed)                                                                                                 \
+        de_kernel<I, P, true><<<nb, 256, lds, s>>>(pv, draws, fbits, F, cr_max, k0, k1, gen_dev, gen, inst, bits, \
+                                                   ld, gr, ch);                                                 \
+    else                                                                                                        \
+        de_kernel<I, P, false><<<nb, 256, 0, s>>>(pv, draws, nullptr, F, cr_max, k0, k1, gen_dev, gen, inst, bits, \
+                                                  ld, gr, ch);
     if (ipw == 1) {
-        if (R == 1) QPM_DE(1, 1); else if (R == 2) QPM_DE(1, 2); else QPM_DE(1, 4);
+        if (R == 1) { QPM_DE(1, 1) } else if (R == 2) { QPM_DE(1, 2) } else { QPM_DE(1, 4) }
     } else if (ipw == 2) {
-        if (R == 1) QPM_DE(2, 1); else if (R == 2) QPM_DE(2, 2); else QPM_DE(2, 4);
+        if (R == 1) { QPM_DE(2, 1) } else if (R == 2) { QPM_DE(2, 2) } else { QPM_DE(2, 4) }
     } else {
-        if (R == 1) QPM_DE(4, 1); else if (R == 2) QPM_DE(4, 2); else QPM_DE(4, 4);
+        if (R == 1) { QPM_DE(4, 1) } else if (R == 2) { QPM_DE(4, 2) } else { QPM_DE(4, 4) }
     }
 #undef QPM_DE
     QPM_TRY_HIP(hipGetLastError());
@@ -301,9 +349,12 @@ qpm_status launch_gwo(const PopView &pv, const int32_t *leaders, const float *a_
                       const uint32_t *gen_dev, uint32_t gen, uint32_t inst, int variant, uint32_t *bits, int64_t ld,
                       hipStream_t s)
 {
-    gwo_kernel<<<quad_grid(pv.D, pv.np), 256, 0, s>>>(pv, leaders, a_tab, a, static_cast<uint32_t>(seed),
-                                                      static_cast<uint32_t>(seed >> 32), gen_dev, gen, inst, variant,
-                                                      bits, ld);
+    const int64_t per_xcd = (pv.np + 7) / 8;
+    const qpm_status st = check_quad_grid(pv.D, 8 * per_xcd);
+    if (st != QPM_OK) return st;
+    const dim3 grid(static_cast<unsigned>(8 * per_xcd), quad_grid(pv.D, pv.np).y);
+    gwo_kernel<<<grid, 256, 0, s>>>(pv, leaders, a_tab, a, static_cast<uint32_t>(seed),
+                                    static_cast<uint32_t>(seed >> 32), gen_dev, gen, inst, variant, bits, ld, per_xcd);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }
@@ -331,6 +382,8 @@ qpm_status launch_gather(const PopView &pv, const int32_t *rows, int64_t nrows, 
 qpm_status launch_pack_pop(const float *x, int64_t np, int64_t D, int64_t ldx, uint32_t *bits, int64_t ld,
                            hipStream_t s)
 {
+    const qpm_status st = check_quad_grid(D, np);
+    if (st != QPM_OK) return st;
     pack_pop_kernel<<<quad_grid(D, np), 256, 0, s>>>(x, D, ldx, bits, ld);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;

@@ -13,14 +13,24 @@ namespace qpm {
 
 // Workgroup = 4 waves over 64 consecutive individuals (lane = individual):
 // the waves fold the segment triples (combine_segments), wave 0 selects,
-// and keeps the packed copy of the buffer flags (bit i % 32 of word i / 32;
-// the wave owns words 2b and 2b + 1) that the DE kernel stages in LDS.
+// keeps the packed copy of the buffer flags (bit i % 32 of word i / 32;
+// the wave owns words 2b and 2b + 1) that the DE kernel stages in LDS, and,
+// when leaders are wanted, leaves its own three best in cand (3 per
+// workgroup), so the last workgroup merges 3 candidates per workgroup
+// instead of rereading every fitness value.
+//
+// Cross-workgroup ordering: one wave per workgroup releases (agent-scope
+// fence, which writes back the XCD's L2) before taking a ticket; only the
+// last workgroup acquires (invalidates its L2) before reading the others'
+// results. The last workgroup resets the ticket, so the kernel can be
+// replayed from a graph.
 template <typename T>
 __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ part, int gy, int64_t ld, int64_t np,
                                                      const double *__restrict__ C, T *__restrict__ f_cur,
                                                      uint32_t *__restrict__ flags, uint32_t *__restrict__ fbits,
                                                      const int32_t *__restrict__ skip3,
-                                                     int32_t *__restrict__ top3_out, int4 *__restrict__ draws_next,
+                                                     int32_t *__restrict__ top3_out, T *__restrict__ cand_v,
+                                                     int32_t *__restrict__ cand_i, int4 *__restrict__ draws_next,
                                                      uint32_t *__restrict__ gen, int64_t D, uint32_t k0, uint32_t k1,
                                                      uint32_t inst, uint32_t *__restrict__ ticket)
 {
@@ -30,12 +40,15 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ 
     const Tri t = combine_segments<4>(part, gy, ld, i, valid);
     if (threadIdx.x < 64) {
         uint32_t fl = 0;
+        T fv = static_cast<T>(-INFINITY);
         if (valid) {
             const double sr = t.qr + C[0], si = t.qi + C[1];
             const T v = static_cast<T>(fma(sr, sr, si * si));
             const bool skip = skip3 != nullptr && (i == skip3[0] || i == skip3[1] || i == skip3[2]);
             fl = flags[i];
-            if (!skip && v > f_cur[i]) {
+            fv = f_cur[i];
+            if (!skip && v > fv) {
+                fv = v;
                 f_cur[i] = v;
                 fl ^= 1u;
                 flags[i] = fl;
@@ -47,15 +60,27 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ 
             fbits[2 * blockIdx.x] = static_cast<uint32_t>(m);
             fbits[2 * blockIdx.x + 1] = static_cast<uint32_t>(m >> 32);
         }
+        if (top3_out) {
+            Top3<T> tp = top3_empty<T>();
+            tp.v[0] = fv;
+            tp.i[0] = valid ? static_cast<int>(i) : INT_MAX;
+            wave_top3(tp);
+            if (lane < 3) {
+                cand_v[3 * blockIdx.x + lane] = lane == 0 ? tp.v[0] : (lane == 1 ? tp.v[1] : tp.v[2]);
+                cand_i[3 * blockIdx.x + lane] = lane == 0 ? tp.i[0] : (lane == 1 ? tp.i[1] : tp.i[2]);
+            }
+        }
     }
     __shared__ int s_last;
-    __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(ticket, 1u) == gridDim.x - 1) ? 1 : 0;
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        s_last = (atomicAdd(ticket, 1u) == gridDim.x - 1) ? 1 : 0;
+    }
     __syncthreads();
     if (!s_last) return;
-    __threadfence();
-    if (top3_out) block_top3<T, 256>(f_cur, np, top3_out);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (top3_out) block_top3<T, 256>(cand_v, 3 * static_cast<int64_t>(gridDim.x), top3_out, cand_i);
     if (threadIdx.x == 0) {
         if (draws_next) gen[0] += 1u;
         *ticket = 0u;
@@ -63,18 +88,27 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ 
 }
 
 qpm_status launch_finish(const double *part, int gy, int64_t ld, int64_t np, const double *C, void *f_cur, bool f64,
-                         uint32_t *flags, uint32_t *fbits, const int32_t *skip3, int32_t *top3_out,
+                         uint32_t *flags, uint32_t *fbits, const int32_t *skip3, int32_t *top3_out, void *cand,
                          int4 *draws_next, uint32_t *gen, int64_t D, uint64_t seed, uint32_t inst, uint32_t *ticket,
                          hipStream_t s)
 {
     const unsigned blocks = static_cast<unsigned>((np + 63) / 64);
+    QPM_REQUIRE(top3_out == nullptr || cand != nullptr, QPM_EINVAL, "leader candidates need a buffer");
     const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
-    if (f64)
+    // cand: 3 values per workgroup (T) followed by 3 slots per workgroup (int32)
+    if (f64) {
+        double *cv = static_cast<double *>(cand);
+        int32_t *ci = cv ? reinterpret_cast<int32_t *>(cv + 3 * static_cast<size_t>(blocks)) : nullptr;
         finish_kernel<double><<<blocks, 256, 0, s>>>(part, gy, ld, np, C, static_cast<double *>(f_cur), flags, fbits,
-                                                     skip3, top3_out, draws_next, gen, D, k0, k1, inst, ticket);
-    else
+                                                     skip3, top3_out, cv, ci, draws_next, gen, D, k0, k1, inst,
+                                                     ticket);
+    } else {
+        float *cv = static_cast<float *>(cand);
+        int32_t *ci = cv ? reinterpret_cast<int32_t *>(cv + 3 * static_cast<size_t>(blocks)) : nullptr;
         finish_kernel<float><<<blocks, 256, 0, s>>>(part, gy, ld, np, C, static_cast<float *>(f_cur), flags, fbits,
-                                                    skip3, top3_out, draws_next, gen, D, k0, k1, inst, ticket);
+                                                    skip3, top3_out, cv, ci, draws_next, gen, D, k0, k1, inst,
+                                                    ticket);
+    }
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }

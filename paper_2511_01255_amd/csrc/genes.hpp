@@ -77,11 +77,15 @@ __device__ __forceinline__ void store_word(uint32_t nib, int64_t q, bool valid, 
 
 // DE for genes j0..j0+3 of individual i: v = clamp(fmaf(F, b - c, a)),
 // u_j = v_j where ((w_j >> 8) 2^-24 <= CR) or j == jrand, else x_j, with
-// the words w of Philox counter (j0 / 4, i, g, inst << 8 | DE_CR).
+// the words w of Philox counter (j0 / 4, i, g, inst << 8 | DE_CR). The
+// crossover test is taken on the raw word: w <= cr_max = cr_threshold(CR)
+// holds exactly when (w >> 8) 2^-24 <= CR.
 __device__ __forceinline__ float4 de_quad(float4 xv, float4 a, float4 b, float4 c, int64_t j0, int jrand, uint32_t i,
-                                          uint32_t g, uint32_t inst, uint32_t k0, uint32_t k1, float F, float CR)
+                                          uint32_t g, uint32_t inst, uint32_t k0, uint32_t k1, float F,
+                                          uint32_t cr_max)
 {
     const U4 r = philox10(static_cast<uint32_t>(j0 >> 2), i, g, (inst << 8) | kTagDeCr, k0, k1);
+    const int rel = jrand - static_cast<int>(j0);  // D <= 2^30
     const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
     const float as[4] = {a.x, a.y, a.z, a.w};
     const float bs[4] = {b.x, b.y, b.z, b.w};
@@ -90,7 +94,7 @@ __device__ __forceinline__ float4 de_quad(float4 xv, float4 a, float4 b, float4 
     float us[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const bool take = (unit24(rw[e]) <= CR) || (j0 + e == jrand);
+        const bool take = (rw[e] <= cr_max) || (rel == e);
         const float v = clamp1(fmaf(F, bs[e] - cs[e], as[e]));
         us[e] = take ? v : xs[e];
     }

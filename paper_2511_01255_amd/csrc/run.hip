@@ -27,6 +27,7 @@ struct qpm_run_s {
     float *buf[2] = {nullptr, nullptr};
     uint32_t *flags = nullptr;
     uint32_t *fbits = nullptr;  // flags packed one bit per individual (2 ceil(np / 64) words)
+    void *cand = nullptr;       // leader candidates of the finish step (finish_cand_bytes)
     void *f_cur = nullptr;
     void *f_new = nullptr;
     uint32_t *tbits = nullptr;
@@ -40,8 +41,10 @@ struct qpm_run_s {
     FitPlan plan;
     int de_ipw = 0;     // 0 = chosen from np
     int de_passes = 1;  // groups of individuals per DE workgroup
-    hipGraph_t graph = nullptr;
+    hipGraph_t graph = nullptr;  // one generation
     hipGraphExec_t exec = nullptr;
+    hipGraph_t graph_k = nullptr;  // kGraphGens generations back to back
+    hipGraphExec_t exec_k = nullptr;
     int64_t done = 0;
     // per-step timing (qpm_run_set_timing)
     bool timing = false;
@@ -67,10 +70,12 @@ static void release(qpm_run_s *r)
     if (r->st) (void)hipStreamSynchronize(r->st);
     if (r->exec) (void)hipGraphExecDestroy(r->exec);
     if (r->graph) (void)hipGraphDestroy(r->graph);
-    (void)hipFree(r->buf[0]);
-    (void)hipFree(r->buf[1]);
+    if (r->exec_k) (void)hipGraphExecDestroy(r->exec_k);
+    if (r->graph_k) (void)hipGraphDestroy(r->graph_k);
+    (void)hipFree(r->buf[0]);  // buf[1] lives in the same allocation
     (void)hipFree(r->flags);
     (void)hipFree(r->fbits);
+    (void)hipFree(r->cand);
     (void)hipFree(r->f_cur);
     (void)hipFree(r->f_new);
     (void)hipFree(r->tbits);
@@ -115,14 +120,45 @@ static qpm_status enqueue_generation(qpm_run_s *r, hipEvent_t *ev = nullptr)
                                  r->de_ipw, r->de_passes, r->fbits))
     QPM_STEP(QPM_K_FIT_DE, launch_fitness_partials(*r->d, p, r->tbits, c.np, r->ld, r->plan, r->fws, r->st))
     QPM_STEP(QPM_K_FINISH_DE, launch_finish(r->fws, gy, r->ld, c.np, C, r->f_cur, r->f64(), r->flags, r->fbits,
-                                            nullptr, r->leaders, nullptr, r->gen, r->D, c.seed, c.inst, r->ticket, r->st))
+                                            nullptr, r->leaders, r->cand, nullptr, r->gen, r->D, c.seed, c.inst,
+                                            r->ticket, r->st))
     QPM_STEP(QPM_K_GWO, launch_gwo(pv, r->leaders, r->a_tab, 0.0f, c.seed, r->gen, 0u, c.inst, c.gwo_variant,
                                    r->tbits, r->ld, r->st))
     QPM_STEP(QPM_K_FIT_GWO, launch_fitness_partials(*r->d, p, r->tbits, c.np, r->ld, r->plan, r->fws, r->st))
     QPM_STEP(QPM_K_FINISH_GWO, launch_finish(r->fws, gy, r->ld, c.np, C, r->f_cur, r->f64(), r->flags, r->fbits,
-                                             r->leaders, nullptr, r->draws, r->gen, r->D, c.seed, c.inst, r->ticket, r->st))
+                                             r->leaders, nullptr, nullptr, r->draws, r->gen, r->D, c.seed, c.inst,
+                                             r->ticket, r->st))
 #undef QPM_STEP
     return mark(QPM_K_COUNT);
+}
+
+// Capture `gens` generations (each reads g from the device counter) into
+// one graph; advancing by whole multiples of kGraphGens replays the long
+// graph, which saves the gaps between graph launches.
+constexpr int64_t kGraphGens = 8;
+
+static qpm_status capture_generations(qpm_run_s *r, int64_t gens, hipGraph_t *graph, hipGraphExec_t *exec)
+{
+    hipError_t e = hipStreamBeginCapture(r->st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        set_error("hipStreamBeginCapture failed: %s", hipGetErrorString(e));
+        return QPM_EHIP;
+    }
+    qpm_status st = QPM_OK;
+    for (int64_t g = 0; g < gens && st == QPM_OK; ++g) st = enqueue_generation(r);
+    e = hipStreamEndCapture(r->st, graph);
+    if (st == QPM_OK && e != hipSuccess) {
+        set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        st = QPM_EHIP;
+    }
+    if (st == QPM_OK) {
+        e = hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            set_error("hipGraphInstantiate failed: %s", hipGetErrorString(e));
+            st = QPM_EHIP;
+        }
+    }
+    return st;
 }
 
 // Time candidate launch shapes on the initial population (bits in tbits,
@@ -137,14 +173,20 @@ static qpm_status tune_run(qpm_run_s *r)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     QPM_TRY_HIP(hipEventCreate(&e0));
     QPM_TRY_HIP(hipEventCreate(&e1));
-    auto time3 = [&](auto &&launch, float *ms) -> qpm_status {
-        qpm_status st = launch();  // warm-up
-        if (st != QPM_OK) return st;
-        QPM_TRY_HIP(hipEventRecord(e0, r->st));
-        for (int rep = 0; rep < 3 && st == QPM_OK; ++rep) st = launch();
-        QPM_TRY_HIP(hipEventRecord(e1, r->st));
-        QPM_TRY_HIP(hipEventSynchronize(e1));
-        QPM_TRY_HIP(hipEventElapsedTime(ms, e0, e1));
+    // the fastest of five single launches after a warm-up (the minimum is
+    // the estimate least disturbed by other work on the device)
+    auto time_min = [&](auto &&launch, float *ms) -> qpm_status {
+        qpm_status st = launch();
+        *ms = 1e30f;
+        for (int rep = 0; rep < 5 && st == QPM_OK; ++rep) {
+            QPM_TRY_HIP(hipEventRecord(e0, r->st));
+            st = launch();
+            QPM_TRY_HIP(hipEventRecord(e1, r->st));
+            QPM_TRY_HIP(hipEventSynchronize(e1));
+            float t = 0.0f;
+            QPM_TRY_HIP(hipEventElapsedTime(&t, e0, e1));
+            if (t < *ms) *ms = t;
+        }
         return st;
     };
     qpm_status st = QPM_OK;
@@ -163,11 +205,13 @@ static qpm_status tune_run(qpm_run_s *r)
             for (const auto &pl : cands) maxb = std::max(maxb, fitness_partials_bytes(pl, r->ld));
             double *part = nullptr;
             QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&part), maxb, r->st));
+            // a candidate is timed with its segment combine (the run's finish
+            // step does the same combine), so more segments are not free
             float best = 1e30f;
             for (const auto &pl : cands) {
                 float ms = 0.0f;
-                st = time3([&]() { return launch_fitness_partials(*r->d, p, r->tbits, c.np, r->ld, pl, part, r->st); },
-                           &ms);
+                st = time_min([&]() { return launch_fitness(*r->d, p, r->tbits, c.np, r->ld, r->f_new, pl, part, r->st); },
+                              &ms);
                 if (st != QPM_OK) break;
                 if (ms < best) {
                     best = ms;
@@ -192,7 +236,7 @@ static qpm_status tune_run(qpm_run_s *r)
             for (int cand : {1, 2, 4})
                 for (int np_ : {1, 2, 4}) {
                     float ms = 0.0f;
-                    st = time3([&]() {
+                    st = time_min([&]() {
                         return launch_de(pv, c.F, c.CR, c.seed, r->gen, 0u, c.inst, r->tbits, r->ld, r->draws, false,
                                          r->st, cand, np_, r->fbits);
                     },
@@ -247,10 +291,13 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     const size_t es = r->f64() ? sizeof(double) : sizeof(float);
     const size_t gene_bytes = sizeof(float) * static_cast<size_t>(c.np) * static_cast<size_t>(r->ldx);
     hipError_t e = hipStreamCreateWithFlags(&r->st, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipMalloc(&r->buf[0], gene_bytes);
-    if (e == hipSuccess) e = hipMalloc(&r->buf[1], gene_bytes);
+    // both gene buffers in one allocation (buf[1] = buf[0] + np ldx), so
+    // the DE kernel can address row r of either buffer as one array
+    if (e == hipSuccess) e = hipMalloc(&r->buf[0], 2 * gene_bytes);
+    if (e == hipSuccess) r->buf[1] = r->buf[0] + c.np * r->ldx;
     if (e == hipSuccess) e = hipMalloc(&r->flags, sizeof(uint32_t) * c.np);
     if (e == hipSuccess) e = hipMalloc(&r->fbits, sizeof(uint32_t) * 2 * ((c.np + 63) / 64));
+    if (e == hipSuccess) e = hipMalloc(&r->cand, finish_cand_bytes(c.np));
     if (e == hipSuccess) e = hipMalloc(&r->f_cur, es * c.np);
     if (e == hipSuccess) e = hipMalloc(&r->f_new, es * c.np);
     if (e == hipSuccess) e = hipMalloc(&r->tbits, sizeof(uint32_t) * r->W * r->ld);
@@ -307,25 +354,9 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     if (st == QPM_OK) st = launch_top3(r->f_cur, c.np, r->f64(), r->leaders, r->st);
     if (st == QPM_OK) st = launch_draws(c.np, r->D, c.seed, r->gen, c.inst, r->draws, r->st);
     if (st == QPM_OK && c.use_graph) {
-        e = hipStreamBeginCapture(r->st, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) {
-            set_error("hipStreamBeginCapture failed: %s", hipGetErrorString(e));
-            st = QPM_EHIP;
-        } else {
-            st = enqueue_generation(r);
-            hipError_t e2 = hipStreamEndCapture(r->st, &r->graph);
-            if (st == QPM_OK && e2 != hipSuccess) {
-                set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e2));
-                st = QPM_EHIP;
-            }
-            if (st == QPM_OK) {
-                e2 = hipGraphInstantiate(&r->exec, r->graph, nullptr, nullptr, 0);
-                if (e2 != hipSuccess) {
-                    set_error("hipGraphInstantiate failed: %s", hipGetErrorString(e2));
-                    st = QPM_EHIP;
-                }
-            }
-        }
+        st = capture_generations(r, 1, &r->graph, &r->exec);
+        if (st == QPM_OK && c.generations >= 2 * kGraphGens)
+            st = capture_generations(r, kGraphGens, &r->graph_k, &r->exec_k);
     }
     if (st != QPM_OK) {
         release(r);
@@ -342,7 +373,13 @@ QPM_API qpm_status qpm_run_advance(qpm_run_handle r, int64_t generations)
     QPM_REQUIRE(generations >= 0 && r->done + generations <= r->cfg.generations, QPM_EINVAL,
                 "advancing %lld generations would pass the configured %lld (done %lld)", (long long)generations,
                 (long long)r->cfg.generations, (long long)r->done);
-    for (int64_t g = 0; g < generations; ++g) {
+    int64_t g = 0;
+    if (!r->timing && r->exec_k)
+        for (; g + kGraphGens <= generations; g += kGraphGens) {
+            QPM_TRY_HIP(hipGraphLaunch(r->exec_k, r->st));
+            r->done += kGraphGens;
+        }
+    for (; g < generations; ++g) {
         if (r->timing) {
             qpm_status st = enqueue_generation(r, r->ev);
             if (st != QPM_OK) return st;
