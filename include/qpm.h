@@ -64,9 +64,11 @@ typedef enum {
 
 /* Which fitness kernel evaluates a population. */
 typedef enum {
-    QPM_FIT_AUTO = 0,       /* segmented, launch shape from the tuner */
-    QPM_FIT_SEGMENTED = 1,  /* domain axis split over waves and workgroups */
-    QPM_FIT_PER_GENOME = 2  /* one lane per genome over all N (FP64 only) */
+    QPM_FIT_AUTO = 0,       /* the table kernel, launch shape from the tuner in runs */
+    QPM_FIT_SEGMENTED = 1,  /* domain axis split over waves and workgroups, per-domain walk */
+    QPM_FIT_PER_GENOME = 2, /* one lane per genome over all N (FP64 only) */
+    QPM_FIT_TABLE = 3       /* segmented, each 4-domain block's triple looked up
+                               by its sign pattern in a per-design table (LDS) */
 } qpm_fit_kernel;
 
 typedef void *qpm_stream;               /* a hipStream_t */
@@ -131,6 +133,20 @@ qpm_status qpm_eval_fitness(qpm_design d, qpm_prec p, const uint32_t *bits, int6
 qpm_status qpm_eval_fitness_shape(qpm_design d, qpm_prec p, const uint32_t *bits, int64_t np,
                                   int64_t ld, void *fitness, int32_t waves_per_group,
                                   int32_t words_per_wave, qpm_stream s);
+
+/*
+ * qpm_eval_fitness_table_shape -- qpm_eval_fitness with the table kernel
+ * (QPM_FIT_TABLE) and its launch shape given explicitly: a workgroup holds
+ * groups_per_workgroup in {1, 2, 4} groups of 64 genomes x 4 waves, each
+ * wave scanning words_per_wave >= 1 bit words; the tables of the
+ * workgroup's 4 words_per_wave words are staged in LDS (3 KB per word in
+ * FP32, 6 KB in FP64), which must fit in 64 KB. The result equals
+ * qpm_eval_fitness with QPM_FIT_TABLE up to the summation order.
+ * Errors: as qpm_eval_fitness, QPM_EINVAL for a shape outside these limits.
+ */
+qpm_status qpm_eval_fitness_table_shape(qpm_design d, qpm_prec p, const uint32_t *bits, int64_t np,
+                                        int64_t ld, void *fitness, int32_t groups_per_workgroup,
+                                        int32_t words_per_wave, qpm_stream s);
 
 /*
  * qpm_init_population -- DE step 1 (paper Sec. 2.2.1): x_ij uniform on

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cmath>
 #include <cstdint>
@@ -53,8 +54,13 @@ struct Design {
     float4 *ph32 = nullptr;   // [32 W] the same rounded to float
     double2 *c64 = nullptr;   // [n] diagonal terms c_n
     double *Cdev = nullptr;   // [2] C on the device
+    double2 *tab64 = nullptr; // [8 W][A, B, Q][16 sign patterns] per 4-domain block
+    float2 *tab32 = nullptr;  // the same rounded to float
     int device = 0;
 };
+
+// sign-pattern tables of the 8 W blocks of 4 domains (from ph64)
+qpm_status launch_pattern_tables(const double4 *ph64, int64_t words, double2 *tab64, float2 *tab32, hipStream_t s);
 
 // per-domain tables of one design into caller buffers (npad = 32 W
 // entries of ph64 / ph32, n of c64) and C = sum c_n into Cdev[2]
@@ -65,8 +71,8 @@ qpm_status launch_phases(const double *zdev, int64_t n, double dk1, double dk2, 
 
 struct FitPlan {
     int kind = QPM_FIT_SEGMENTED;  // qpm_fit_kernel (never AUTO here)
-    int waves = 16;                // waves per workgroup (segmented)
-    int wpw = 2;                   // bit words per wave (segmented)
+    int waves = 16;                // waves per workgroup (segmented) or genome groups (table)
+    int wpw = 2;                   // bit words per wave
     int gy = 1;                    // workgroup segments along the domain axis
 };
 
@@ -130,6 +136,12 @@ qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const 
                      hipStream_t s, int ipw = 0, int passes = 1, const uint32_t *fbits = nullptr);
 // segmented plan with an explicit shape
 FitPlan plan_fitness_shape(const Design &d, int waves, int wpw);
+// table plan: gw genome groups of 64 per workgroup, wpw words per wave
+// (1 <= wpw <= table_max_wpw: 4 wpw words of tables fit in 64 KB of LDS)
+FitPlan plan_fitness_table(const Design &d, qpm_prec p, int gw, int wpw);
+__host__ __device__ constexpr int table_max_wpw(bool f32) { return f32 ? 5 : 2; }
+// LDS of one table-kernel workgroup (tables, reused for the combine)
+size_t table_lds_bytes(int64_t W, bool f32, int gw, int wpw);
 // DE draws of generation *gen_dev for every individual
 qpm_status launch_draws(int64_t np, int64_t D, uint64_t seed, const uint32_t *gen_dev, uint32_t inst, int4 *draws,
                         hipStream_t s);

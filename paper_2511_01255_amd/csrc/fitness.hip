@@ -126,6 +126,166 @@ __global__ __launch_bounds__(128) void fit_per_genome_kernel(const uint32_t *__r
     fit[i] = fma(sr, sr, si * si);
 }
 
+// The table kernel: each 4-domain block contributes the precomputed triple
+// of its sign pattern (16 patterns per block, Design::tab32 / tab64), so a
+// domain evaluation costs a quarter of a pattern lookup plus one triple
+// append, instead of a complex multiply-add per domain:
+//   Q += A Bp + Qp,  A += Ap,  B += Bp   (complex; p = 4 bits of the word).
+// Workgroup = GW genome groups x 4 segment waves (wave = 64 genomes, lane =
+// genome). The workgroup copies the tables of its 4 wpw words to LDS (one
+// component row of 16 patterns is 128 bytes in FP32, so a wave's lookups
+// of one component hit distinct banks), each wave walks wpw words of its
+// segment, and the 4 segment triples of each genome are combined in LDS in
+// order. FP32: the lookups and sums of one word in binary32, each word's
+// triple folded into FP64; FP64: binary64 throughout.
+template <bool F32, int GW>
+__global__ __launch_bounds__(GW * 256) void fit_tab_kernel(const uint32_t *__restrict__ bits, int64_t ld, int W,
+                                                           const double2 *__restrict__ tab64,
+                                                           const float2 *__restrict__ tab32, int wpw, int64_t np,
+                                                           double *__restrict__ part, const double *__restrict__ C,
+                                                           void *__restrict__ fit, int direct, int out_f64)
+{
+    constexpr int SW = 4;
+    constexpr int NT = GW * 256;
+    constexpr int MAXW = table_max_wpw(F32);
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int gsub = wave / SW, ssub = wave % SW;
+    const int64_t i = (static_cast<int64_t>(blockIdx.x) * GW + gsub) * 64 + lane;
+    const int wbase = static_cast<int>(blockIdx.y) * SW * wpw;
+    const int nw = min(W - wbase, SW * wpw);  // >= 1 by the grid
+    // the tables of words [wbase, wbase + nw) go straight to LDS (16 bytes
+    // per lane per load, no registers, no wait between loads)
+    {
+        const int n16 = nw * 8 * 48 * (F32 ? 8 : 16) / 16;
+        const uint4 *src = F32 ? reinterpret_cast<const uint4 *>(tab32 + static_cast<int64_t>(wbase) * 8 * 48)
+                               : reinterpret_cast<const uint4 *>(tab64 + static_cast<int64_t>(wbase) * 8 * 48);
+        for (int k = 0; k * NT < n16; ++k) {
+            const int idx = k * NT + static_cast<int>(threadIdx.x);
+            if (idx < n16)
+                __builtin_amdgcn_global_load_lds(
+                    src + idx, reinterpret_cast<__attribute__((address_space(3))) void *>(
+                                   reinterpret_cast<uintptr_t>(lds + static_cast<size_t>(k * NT + wave * 64) * 16)),
+                    16, 0, 0);
+        }
+    }
+    // this wave's bit words, loaded while the tables arrive (clamped
+    // addresses, so every load is in bounds and none is branched around)
+    const bool live = i < np;
+    const int w0 = ssub * wpw, w1 = min(nw, w0 + wpw);
+    const int64_t ic = i < ld ? i : ld - 1;
+    uint32_t wv[MAXW];
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) wv[k] = bits[static_cast<int64_t>(min(wbase + w0 + k, W - 1)) * ld + ic];
+    // keep the loads here, issued together with the table copies (the
+    // compiler would otherwise sink each one to its first use, one memory
+    // latency per word)
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) asm volatile("" ::"v"(wv[k]));
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    Tri t{0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) {
+        const int wr = w0 + k;
+        if (wr >= w1) break;
+        const uint32_t word = live ? wv[k] : 0u;
+        if constexpr (F32) {
+            const float2 *tb = reinterpret_cast<const float2 *>(lds) + wr * 8 * 48;
+            float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f, qr = 0.f, qi = 0.f;
+#pragma unroll
+            for (int h = 0; h < 8; ++h) {
+                const uint32_t pt = (word >> (4 * h)) & 15u;
+                const float2 A = tb[h * 48 + pt], B = tb[h * 48 + 16 + pt], Q = tb[h * 48 + 32 + pt];
+                qr = fmaf(-ai, B.y, fmaf(ar, B.x, qr + Q.x));
+                qi = fmaf(ai, B.x, fmaf(ar, B.y, qi + Q.y));
+                ar += A.x;
+                ai += A.y;
+                br += B.x;
+                bi += B.y;
+            }
+            tri_append(t, Tri{ar, ai, br, bi, qr, qi});
+        } else {
+            const double2 *tb = reinterpret_cast<const double2 *>(lds) + wr * 8 * 48;
+#pragma unroll
+            for (int h = 0; h < 8; ++h) {
+                const uint32_t pt = (word >> (4 * h)) & 15u;
+                const double2 A = tb[h * 48 + pt], B = tb[h * 48 + 16 + pt], Q = tb[h * 48 + 32 + pt];
+                t.qr = fma(-t.ai, B.y, fma(t.ar, B.x, t.qr + Q.x));
+                t.qi = fma(t.ai, B.x, fma(t.ar, B.y, t.qi + Q.y));
+                t.ar += A.x;
+                t.ai += A.y;
+                t.br += B.x;
+                t.bi += B.y;
+            }
+        }
+    }
+    // the 4 segment triples of each genome group, in order, through LDS
+    // (the tables are no longer read)
+    __syncthreads();
+    double *sh = reinterpret_cast<double *>(lds);  // [6][GW * SW][64]
+    constexpr int NWV = GW * SW;
+    sh[(0 * NWV + wave) * 64 + lane] = t.ar;
+    sh[(1 * NWV + wave) * 64 + lane] = t.ai;
+    sh[(2 * NWV + wave) * 64 + lane] = t.br;
+    sh[(3 * NWV + wave) * 64 + lane] = t.bi;
+    sh[(4 * NWV + wave) * 64 + lane] = t.qr;
+    sh[(5 * NWV + wave) * 64 + lane] = t.qi;
+    __syncthreads();
+    if (ssub != 0 || !live) return;
+#pragma unroll 1
+    for (int s2 = 1; s2 < SW; ++s2) {
+        if (s2 * wpw >= nw) break;
+        const int v = gsub * SW + s2;
+        tri_append(t, Tri{sh[(0 * NWV + v) * 64 + lane], sh[(1 * NWV + v) * 64 + lane], sh[(2 * NWV + v) * 64 + lane],
+                          sh[(3 * NWV + v) * 64 + lane], sh[(4 * NWV + v) * 64 + lane],
+                          sh[(5 * NWV + v) * 64 + lane]});
+    }
+    if (direct) {
+        store_fitness(fit, out_f64, i, t, C);
+    } else {
+        double *o = part + static_cast<int64_t>(blockIdx.y) * 6 * ld + i;
+        o[0 * ld] = t.ar;
+        o[1 * ld] = t.ai;
+        o[2 * ld] = t.br;
+        o[3 * ld] = t.bi;
+        o[4 * ld] = t.qr;
+        o[5 * ld] = t.qi;
+    }
+}
+
+size_t table_lds_bytes(int64_t W, bool f32, int gw, int wpw)
+{
+    const int64_t words = std::min<int64_t>(W, 4 * static_cast<int64_t>(wpw));
+    const size_t tab = static_cast<size_t>(words) * 8 * 48 * (f32 ? 8 : 16);
+    const size_t comb = static_cast<size_t>(gw) * 4 * 64 * 6 * 8;
+    return std::max(tab, comb);
+}
+
+template <bool F32>
+static void launch_tab(const Design &d, const FitPlan &pl, const uint32_t *bits, int64_t np, int64_t ld,
+                       double *part, void *fit, int out_f64, bool direct_ok, hipStream_t s)
+{
+    const int gw = pl.waves;
+    const dim3 grid(static_cast<unsigned>((np + 64 * gw - 1) / (64 * gw)), static_cast<unsigned>(pl.gy));
+    const int direct = direct_ok && pl.gy == 1;
+    const int W = static_cast<int>(d.words);
+    const size_t lds = table_lds_bytes(d.words, F32, gw, pl.wpw);
+#define QPM_TAB_CASE(G)                                                                                       \
+    case G:                                                                                                   \
+        fit_tab_kernel<F32, G><<<grid, dim3(G * 256), lds, s>>>(bits, ld, W, d.tab64, d.tab32, pl.wpw, np, part, \
+                                                                d.Cdev, fit, direct, out_f64);               \
+        break;
+    switch (gw) {
+        QPM_TAB_CASE(1)
+        QPM_TAB_CASE(2)
+        QPM_TAB_CASE(4)
+    default: break;
+    }
+#undef QPM_TAB_CASE
+}
+
 template <bool F32>
 static void launch_seg(const Design &d, const FitPlan &pl, const uint32_t *bits, int64_t np, int64_t ld,
                        double *part, void *fit, int out_f64, bool direct_ok, hipStream_t s)
@@ -149,14 +309,30 @@ static void launch_seg(const Design &d, const FitPlan &pl, const uint32_t *bits,
 #undef QPM_SEG_CASE
 }
 
-FitPlan plan_fitness(const Design &d, qpm_prec p, int64_t np, int kernel)
+FitPlan plan_fitness_table(const Design &d, qpm_prec p, int gw, int wpw)
 {
     (void)p;
+    FitPlan pl;
+    pl.kind = QPM_FIT_TABLE;
+    pl.waves = gw;
+    pl.wpw = wpw;
+    pl.gy = static_cast<int>((d.words + 4 * static_cast<int64_t>(wpw) - 1) / (4 * static_cast<int64_t>(wpw)));
+    return pl;
+}
+
+FitPlan plan_fitness(const Design &d, qpm_prec p, int64_t np, int kernel)
+{
     FitPlan pl;
     if (kernel == QPM_FIT_PER_GENOME) {
         pl.kind = QPM_FIT_PER_GENOME;
         pl.gy = 1;
         return pl;
+    }
+    if (kernel == QPM_FIT_AUTO || kernel == QPM_FIT_TABLE) {
+        // 48 KB of tables per workgroup: 4 wpw words of 3 KB (FP32) or 6 KB
+        const int wpw = p == QPM_PREC_F32 ? 4 : 2;
+        const int gw = np >= 1024 ? 4 : (np >= 256 ? 2 : 1);
+        return plan_fitness_table(d, p, gw, wpw);
     }
     pl.kind = QPM_FIT_SEGMENTED;
     const int64_t groups = (np + 63) / 64;
@@ -189,13 +365,13 @@ FitPlan plan_fitness_shape(const Design &d, int waves, int wpw)
 
 size_t fitness_workspace_bytes(const FitPlan &pl, int64_t ld)
 {
-    if (pl.kind != QPM_FIT_SEGMENTED || pl.gy <= 1) return 0;
+    if (pl.kind == QPM_FIT_PER_GENOME || pl.gy <= 1) return 0;
     return sizeof(double) * 6 * static_cast<size_t>(pl.gy) * static_cast<size_t>(ld);
 }
 
 size_t fitness_partials_bytes(const FitPlan &pl, int64_t ld)
 {
-    const size_t gy = pl.kind == QPM_FIT_SEGMENTED ? static_cast<size_t>(pl.gy) : 1;
+    const size_t gy = pl.kind == QPM_FIT_PER_GENOME ? 1 : static_cast<size_t>(pl.gy);
     return sizeof(double) * 6 * gy * static_cast<size_t>(ld);
 }
 
@@ -208,10 +384,16 @@ qpm_status launch_fitness(const Design &d, qpm_prec p, const uint32_t *bits, int
         fit_per_genome_kernel<<<blocks, 128, 0, s>>>(bits, ld, static_cast<int>(d.words), d.ph64, np, d.Cdev,
                                                      static_cast<double *>(fit), nullptr);
     } else {
-        if (p == QPM_PREC_F32)
+        if (pl.kind == QPM_FIT_TABLE) {
+            if (p == QPM_PREC_F32)
+                launch_tab<true>(d, pl, bits, np, ld, part, fit, out_f64, true, s);
+            else
+                launch_tab<false>(d, pl, bits, np, ld, part, fit, out_f64, true, s);
+        } else if (p == QPM_PREC_F32) {
             launch_seg<true>(d, pl, bits, np, ld, part, fit, out_f64, true, s);
-        else
+        } else {
             launch_seg<false>(d, pl, bits, np, ld, part, fit, out_f64, true, s);
+        }
         if (pl.gy > 1) {
             const unsigned blocks = static_cast<unsigned>((np + 63) / 64);
             fit_combine_kernel<<<blocks, 256, 0, s>>>(part, pl.gy, ld, np, d.Cdev, fit, out_f64);
@@ -228,6 +410,11 @@ qpm_status launch_fitness_partials(const Design &d, qpm_prec p, const uint32_t *
         const unsigned blocks = static_cast<unsigned>((np + 127) / 128);
         fit_per_genome_kernel<<<blocks, 128, 0, s>>>(bits, ld, static_cast<int>(d.words), d.ph64, np, d.Cdev,
                                                      nullptr, part);
+    } else if (pl.kind == QPM_FIT_TABLE) {
+        if (p == QPM_PREC_F32)
+            launch_tab<true>(d, pl, bits, np, ld, part, nullptr, 0, false, s);
+        else
+            launch_tab<false>(d, pl, bits, np, ld, part, nullptr, 1, false, s);
     } else if (p == QPM_PREC_F32) {
         launch_seg<true>(d, pl, bits, np, ld, part, nullptr, 0, false, s);
     } else {
@@ -276,8 +463,9 @@ QPM_API qpm_status qpm_eval_fitness(qpm_design d, qpm_prec p, const uint32_t *bi
                                     void *fitness, int32_t kernel, qpm_stream sv)
 {
     clear_error();
-    QPM_REQUIRE(kernel == QPM_FIT_AUTO || kernel == QPM_FIT_SEGMENTED || kernel == QPM_FIT_PER_GENOME, QPM_EINVAL,
-                "unknown fitness kernel %d", (int)kernel);
+    QPM_REQUIRE(kernel == QPM_FIT_AUTO || kernel == QPM_FIT_SEGMENTED || kernel == QPM_FIT_PER_GENOME ||
+                    kernel == QPM_FIT_TABLE,
+                QPM_EINVAL, "unknown fitness kernel %d", (int)kernel);
     QPM_REQUIRE(!(kernel == QPM_FIT_PER_GENOME && p != QPM_PREC_F64), QPM_EINVAL,
                 "the per-genome kernel computes in FP64 only");
     qpm_status st = check_fitness_args(d, p, bits, np, ld, fitness);
@@ -295,6 +483,24 @@ QPM_API qpm_status qpm_eval_fitness_shape(qpm_design d, qpm_prec p, const uint32
     qpm_status st = check_fitness_args(d, p, bits, np, ld, fitness);
     if (st != QPM_OK) return st;
     const FitPlan pl = plan_fitness_shape(*d, waves, wpw);
+    QPM_REQUIRE(pl.gy <= 65535, QPM_ERANGE, "too many workgroup segments (%d)", pl.gy);
+    return run_plan(d, p, bits, np, ld, fitness, pl, static_cast<hipStream_t>(sv));
+}
+
+QPM_API qpm_status qpm_eval_fitness_table_shape(qpm_design d, qpm_prec p, const uint32_t *bits, int64_t np,
+                                                int64_t ld, void *fitness, int32_t groups, int32_t wpw,
+                                                qpm_stream sv)
+{
+    clear_error();
+    QPM_REQUIRE(groups == 1 || groups == 2 || groups == 4, QPM_EINVAL,
+                "groups_per_workgroup must be 1, 2 or 4 (got %d)", (int)groups);
+    QPM_REQUIRE(wpw >= 1, QPM_EINVAL, "words_per_wave must be >= 1 (got %d)", (int)wpw);
+    qpm_status st = check_fitness_args(d, p, bits, np, ld, fitness);
+    if (st != QPM_OK) return st;
+    QPM_REQUIRE(wpw <= table_max_wpw(p == QPM_PREC_F32), QPM_EINVAL,
+                "words_per_wave %d exceeds %d (the tables of 4 words_per_wave words must fit in 64 KB of LDS)",
+                (int)wpw, table_max_wpw(p == QPM_PREC_F32));
+    const FitPlan pl = plan_fitness_table(*d, p, groups, wpw);
     QPM_REQUIRE(pl.gy <= 65535, QPM_ERANGE, "too many workgroup segments (%d)", pl.gy);
     return run_plan(d, p, bits, np, ld, fitness, pl, static_cast<hipStream_t>(sv));
 }

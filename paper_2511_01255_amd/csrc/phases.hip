@@ -172,6 +172,49 @@ __global__ __launch_bounds__(256) void sum_c_kernel(const double2 *__restrict__ 
     }
 }
 
+// The 16 sign patterns of each block of 4 domains, reduced to their triple:
+// for block q and pattern p (bit k set -> d = -1 for domain 4q + k),
+//   A = sum_k d_k a_k,  B = sum_k d_k b_k,  Q = sum_k d_k b_k sum_{m<k} d_m a_m,
+// in FP64 from the FP64 integrals (padding domains have a = b = 0). Layout
+// [q][A, B, Q][p], one complex value per entry, so the 16 patterns of one
+// component are one contiguous row.
+__global__ __launch_bounds__(256) void pattern_table_kernel(const double4 *__restrict__ ph64, int64_t nblocks,
+                                                            double2 *__restrict__ tab64, float2 *__restrict__ tab32)
+{
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (tid >= nblocks * 16) return;
+    const int64_t q = tid >> 4;
+    const int p = static_cast<int>(tid & 15);
+    double ar = 0, ai = 0, br = 0, bi = 0, qr = 0, qi = 0;
+    for (int k = 0; k < 4; ++k) {
+        const double4 c = ph64[4 * q + k];
+        const double sg = ((p >> k) & 1) ? -1.0 : 1.0;
+        qr = fma(sg, fma(c.z, ar, -(c.w * ai)), qr);
+        qi = fma(sg, fma(c.z, ai, c.w * ar), qi);
+        ar = fma(sg, c.x, ar);
+        ai = fma(sg, c.y, ai);
+        br = fma(sg, c.z, br);
+        bi = fma(sg, c.w, bi);
+    }
+    double2 *o = tab64 + q * 48 + p;
+    o[0] = make_double2(ar, ai);
+    o[16] = make_double2(br, bi);
+    o[32] = make_double2(qr, qi);
+    float2 *f = tab32 + q * 48 + p;
+    f[0] = make_float2(static_cast<float>(ar), static_cast<float>(ai));
+    f[16] = make_float2(static_cast<float>(br), static_cast<float>(bi));
+    f[32] = make_float2(static_cast<float>(qr), static_cast<float>(qi));
+}
+
+qpm_status launch_pattern_tables(const double4 *ph64, int64_t words, double2 *tab64, float2 *tab32, hipStream_t s)
+{
+    const int64_t nblocks = words * 8;
+    pattern_table_kernel<<<static_cast<unsigned>((nblocks * 16 + 255) / 256), 256, 0, s>>>(ph64, nblocks, tab64,
+                                                                                           tab32);
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
+}
+
 qpm_status launch_phases(const double *zdev, int64_t n, double dk1, double dk2, double4 *ph64, float4 *ph32,
                          double2 *c64, double *Cdev, hipStream_t s)
 {
@@ -193,6 +236,8 @@ static void free_design(Design *d)
     (void)hipFree(d->ph32);
     (void)hipFree(d->c64);
     (void)hipFree(d->Cdev);
+    (void)hipFree(d->tab64);
+    (void)hipFree(d->tab32);
     delete static_cast<qpm_design_s *>(d);
 }
 
@@ -230,6 +275,8 @@ QPM_API qpm_status qpm_precompute_phases(const double *z, int64_t n, double dk1,
     if (e == hipSuccess) e = hipMalloc(&d->ph32, sizeof(float4) * npad);
     if (e == hipSuccess) e = hipMalloc(&d->c64, sizeof(double2) * n);
     if (e == hipSuccess) e = hipMalloc(&d->Cdev, sizeof(double) * 2);
+    if (e == hipSuccess) e = hipMalloc(&d->tab64, sizeof(double2) * 48 * 8 * d->words);
+    if (e == hipSuccess) e = hipMalloc(&d->tab32, sizeof(float2) * 48 * 8 * d->words);
     if (e == hipSuccess) e = hipMalloc(&zdev, sizeof(double) * (n + 1));
     if (e != hipSuccess) {
         (void)hipFree(zdev);
@@ -239,6 +286,8 @@ QPM_API qpm_status qpm_precompute_phases(const double *z, int64_t n, double dk1,
     }
     e = hipMemcpyAsync(zdev, z, sizeof(double) * (n + 1), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && launch_phases(zdev, n, dk1, dk2, d->ph64, d->ph32, d->c64, d->Cdev, s) != QPM_OK)
+        e = hipErrorLaunchFailure;
+    if (e == hipSuccess && launch_pattern_tables(d->ph64, d->words, d->tab64, d->tab32, s) != QPM_OK)
         e = hipErrorLaunchFailure;
     if (e == hipSuccess) e = hipMemcpyAsync(d->C, d->Cdev, sizeof(double) * 2, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -114,7 +114,7 @@ static qpm_status enqueue_generation(qpm_run_s *r, hipEvent_t *ev = nullptr)
 #define QPM_STEP(k, call)                         \
     if ((st = mark(k)) != QPM_OK) return st;      \
     if ((st = (call)) != QPM_OK) return st;
-    const int gy = r->plan.kind == QPM_FIT_SEGMENTED ? r->plan.gy : 1;
+    const int gy = r->plan.kind == QPM_FIT_PER_GENOME ? 1 : r->plan.gy;
     const double *C = r->d->Cdev;
     QPM_STEP(QPM_K_DE, launch_de(pv, c.F, c.CR, c.seed, r->gen, 0u, c.inst, r->tbits, r->ld, r->draws, false, r->st,
                                  r->de_ipw, r->de_passes, r->fbits))
@@ -224,6 +224,37 @@ static qpm_status tune_run(qpm_run_s *r)
             tune_store(key, waves, wpw);
         }
         r->plan = plan_fitness_shape(*r->d, waves, wpw);
+    } else if (r->plan.kind == QPM_FIT_TABLE) {
+        const std::string key = tune_key("tab", r->d->words, c.np, c.prec, 1);
+        int gw = 0, wpw = 0;
+        if (!tune_lookup(key, &gw, &wpw)) {
+            std::vector<FitPlan> cands;
+            for (int g : {1, 2, 4})
+                for (int w = 1; w <= table_max_wpw(p == QPM_PREC_F32); ++w) {
+                    FitPlan pl = plan_fitness_table(*r->d, p, g, w);
+                    if (pl.gy <= 65535) cands.push_back(pl);
+                }
+            size_t maxb = 0;
+            for (const auto &pl : cands) maxb = std::max(maxb, fitness_partials_bytes(pl, r->ld));
+            double *part = nullptr;
+            QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&part), maxb, r->st));
+            float best = 1e30f;
+            for (const auto &pl : cands) {
+                float ms = 0.0f;
+                st = time_min([&]() { return launch_fitness(*r->d, p, r->tbits, c.np, r->ld, r->f_new, pl, part, r->st); },
+                              &ms);
+                if (st != QPM_OK) break;
+                if (ms < best) {
+                    best = ms;
+                    gw = pl.waves;
+                    wpw = pl.wpw;
+                }
+            }
+            (void)hipFreeAsync(part, r->st);
+            if (st != QPM_OK) return st;
+            tune_store(key, gw, wpw);
+        }
+        r->plan = plan_fitness_table(*r->d, p, gw, wpw);
     }
     {
         const std::string key = tune_key("de2", r->D, c.np, 0, 1);
@@ -273,7 +304,7 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     QPM_REQUIRE(c.gwo_variant == 0 || c.gwo_variant == 1, QPM_EINVAL, "gwo_variant must be 0 or 1");
     QPM_REQUIRE(c.inst < (1u << 24), QPM_EINVAL, "inst must be < 2^24");
     QPM_REQUIRE(c.fit_kernel == QPM_FIT_AUTO || c.fit_kernel == QPM_FIT_SEGMENTED ||
-                    c.fit_kernel == QPM_FIT_PER_GENOME,
+                    c.fit_kernel == QPM_FIT_PER_GENOME || c.fit_kernel == QPM_FIT_TABLE,
                 QPM_EINVAL, "unknown fitness kernel %d", c.fit_kernel);
     QPM_REQUIRE(!(c.fit_kernel == QPM_FIT_PER_GENOME && c.prec != QPM_PREC_F64), QPM_EINVAL,
                 "the per-genome kernel computes in FP64 only");

@@ -16,6 +16,7 @@ PREC_F64 = 1
 FIT_AUTO = 0
 FIT_SEGMENTED = 1
 FIT_PER_GENOME = 2
+FIT_TABLE = 3
 # timing slots of one generation (QPM_K_*)
 STEP_NAMES = ["de", "fitness_de", "finish_de", "gwo", "fitness_gwo", "finish_gwo"]
 
@@ -56,6 +57,7 @@ _SIGS = {
     "qpm_design_read_phases": (_I32, [_P, _P, _P, _P]),
     "qpm_eval_fitness": (_I32, [_P, _I32, _P, _I64, _I64, _P, _I32, _P]),
     "qpm_eval_fitness_shape": (_I32, [_P, _I32, _P, _I64, _I64, _P, _I32, _I32, _P]),
+    "qpm_eval_fitness_table_shape": (_I32, [_P, _I32, _P, _I64, _I64, _P, _I32, _I32, _P]),
     "qpm_init_population": (_I32, [_I64, _I64, _I64, _U64, _U32, _P, _P, _I64, _P]),
     "qpm_de_step": (_I32, [_P, _I64, _I64, _I64, _F, _F, _U64, _U32, _U32, _P, _P, _I64, _P]),
     "qpm_de_step_shape": (_I32, [_P, _I64, _I64, _I64, _F, _F, _U64, _U32, _U32, _P, _P, _I64, _I32, _I32, _P]),
@@ -190,6 +192,16 @@ def eval_fitness_shape(design, bits, np_, prec, waves_per_group, words_per_wave,
         out = torch.empty(np_, dtype=torch.float64 if prec == PREC_F64 else torch.float32, device=bits.device)
     _check(lib().qpm_eval_fitness_shape(design.handle, prec, _ptr(bits), np_, bits.shape[1], _ptr(out),
                                         waves_per_group, words_per_wave, _stream(stream)))
+    return out
+
+
+def eval_fitness_table_shape(design, bits, np_, prec, groups_per_workgroup, words_per_wave, out=None, stream=None):
+    """eval_fitness with the table kernel and an explicit launch shape."""
+    import torch
+    if out is None:
+        out = torch.empty(np_, dtype=torch.float64 if prec == PREC_F64 else torch.float32, device=bits.device)
+    _check(lib().qpm_eval_fitness_table_shape(design.handle, prec, _ptr(bits), np_, bits.shape[1], _ptr(out),
+                                              groups_per_workgroup, words_per_wave, _stream(stream)))
     return out
 
 

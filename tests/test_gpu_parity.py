@@ -100,7 +100,8 @@ def _fit_case(npop, n, kind, seed=3):
 
 
 @pytest.mark.parametrize("shape", FIT_SHAPES, ids=lambda s: "np%d_n%d_%s" % s)
-@pytest.mark.parametrize("mode", [(1, 0), (1, 1), (1, 2), (0, 0)], ids=["f64auto", "f64seg", "f64pergenome", "f32"])
+@pytest.mark.parametrize("mode", [(1, 0), (1, 1), (1, 2), (1, 3), (0, 0), (0, 1), (0, 3)],
+                         ids=["f64auto", "f64seg", "f64pergenome", "f64table", "f32auto", "f32seg", "f32table"])
 def test_fitness_matches_oracle(q, orc, shape, mode):
     prec, kernel = mode
     npop, n, kind = shape
@@ -110,6 +111,31 @@ def test_fitness_matches_oracle(q, orc, shape, mode):
     _, fo = orc.Design(z, DK1, DK2).fitness(d)
     err = _rel_err(f, fo)
     assert err.max() <= TOL[prec], "max rel err %.3g" % err.max()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("groups", [1, 2, 4])
+def test_fitness_every_table_shape(q, orc, prec, groups):
+    # every words-per-wave the LDS allows, on a ragged population and a
+    # ragged last word; W = 94 words so the segment count is ragged too
+    npop, n = 197, 3001
+    z, d = _fit_case(npop, n, "periodic", seed=5)
+    D = q.precompute_phases(z, DK1, DK2)
+    _, fo = orc.Design(z, DK1, DK2).fitness(d)
+    bits = _bits(d)
+    for wpw in range(1, 6 if prec == 0 else 3):
+        f = q.eval_fitness_table_shape(D, bits, npop, prec, groups, wpw).double().cpu().numpy()
+        err = _rel_err(f, fo)
+        assert err.max() <= TOL[prec], "wpw %d: max rel err %.3g" % (wpw, err.max())
+
+
+def test_fitness_table_shape_rejects_oversized_lds(q):
+    D = q.precompute_phases(inputs.uniform_boundaries(3001, 2.0), DK1, DK2)
+    bits = _bits(inputs.random_signs(8, 3001, seed=1))
+    with pytest.raises(q.QpmError):
+        q.eval_fitness_table_shape(D, bits, 8, 1, 1, 3)  # FP64: 4 x 3 words x 6 KB > 64 KB
+    with pytest.raises(q.QpmError):
+        q.eval_fitness_table_shape(D, bits, 8, 0, 3, 1)  # groups must be 1, 2 or 4
 
 
 @pytest.mark.parametrize("prec", [1, 0])
