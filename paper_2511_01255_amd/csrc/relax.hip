@@ -7,35 +7,36 @@
 //   P_{k-1} = sum_{m<k} d_m a_m,  R_{k+1} = sum_{n>k} d_n b_n,
 //   df/dtheta_k = 2 Re(conj(S) dS/dd_k) (1 - d_k^2).
 //
-// Mapping: one lane per batch row (64 rows per wave); the domain axis is cut
-// into segments, one per wave, scanned in order with the per-domain
-// coefficients in scalar registers. A segment reduces to (A, B, Q, Dg) =
-// (sum d a, sum d b, sum_n d_n b_n (A before n), sum c d^2); segments are
-// combined in order by a small per-row pass that also forms, for the
-// adjoint, the prefix A before and the suffix B after every segment. The
-// adjoint then re-walks each segment from those two values.
+// Mapping: a workgroup of 256 lanes covers one segment of L = 256 M
+// consecutive domains for R consecutive rows; lane t owns the M domains
+// [seg L + t M, seg L + (t + 1) M), so the loads of theta and the stores of
+// the gradient are coalesced along the row, and it keeps its M domains'
+// coefficients in registers while it walks the R rows. A lane's chunk
+// reduces to (A, B, Q, Dg) = (sum d a, sum d b, sum_n d_n b_n (A before n),
+// sum c d^2); the 256 chunk triples of a segment combine in order (a
+// shuffle tree in each wave, then the 4 waves through LDS, in FP64), and
+// the segments of a row combine in order in a small per-row pass that also
+// forms, for the adjoint, the prefix A before and the suffix B after every
+// segment. The adjoint takes a lane's prefix of A and suffix of B from
+// ordered scans over the lanes and walks its chunk from them.
 #include "common.hpp"
 
 namespace qpm {
 
 struct RelaxPlan {
-    int seg_len;  // domains per segment (multiple of 4)
-    int nseg;     // segments
-    int waves;    // waves per workgroup
+    int M;     // domains per lane
+    int R;     // rows per workgroup
+    int L;     // domains per segment (256 M)
+    int nseg;  // segments per row
 };
 
-static RelaxPlan plan_relax(int64_t n, int64_t B)
+static RelaxPlan plan_relax(int64_t n, int64_t B, bool f32)
 {
-    const int64_t groups = (B + 63) / 64;
-    const int64_t target = 4096;  // waves in flight
-    int64_t segs = (target + groups - 1) / groups;
-    int64_t len = (n + segs - 1) / segs;
-    len = ((len + 3) / 4) * 4;
-    if (len < 16) len = 16;
     RelaxPlan p;
-    p.seg_len = static_cast<int>(len);
-    p.nseg = static_cast<int>((n + len - 1) / len);
-    p.waves = 4;
+    p.M = f32 ? 8 : 4;
+    p.R = B >= 64 ? 4 : 1;
+    p.L = 256 * p.M;
+    p.nseg = static_cast<int>((n + p.L - 1) / p.L);
     return p;
 }
 
@@ -46,67 +47,145 @@ __device__ __forceinline__ float tanh_t<float>(float x) { return tanhf(x); }
 template <>
 __device__ __forceinline__ double tanh_t<double>(double x) { return tanh(x); }
 
+// the triple of a stretch of domains plus its diagonal sum
+struct RTri {
+    double ar, ai, br, bi, qr, qi, gr, gi;
+};
+
+// t <- t (+) u (t covers the domains before u)
+__device__ __forceinline__ void rtri_append(RTri &t, const RTri &u)
+{
+    t.qr = fma(t.ar, u.br, fma(-t.ai, u.bi, t.qr + u.qr));
+    t.qi = fma(t.ar, u.bi, fma(t.ai, u.br, t.qi + u.qi));
+    t.ar += u.ar;
+    t.ai += u.ai;
+    t.br += u.br;
+    t.bi += u.bi;
+    t.gr += u.gr;
+    t.gi += u.gi;
+}
+
+__device__ __forceinline__ RTri rtri_shfl_down(const RTri &t, int off)
+{
+    return RTri{__shfl_down(t.ar, off), __shfl_down(t.ai, off), __shfl_down(t.br, off), __shfl_down(t.bi, off),
+                __shfl_down(t.qr, off), __shfl_down(t.qi, off), __shfl_down(t.gr, off), __shfl_down(t.gi, off)};
+}
+
+// coefficients of lane-owned domains (0 past n)
+template <typename T, int M>
+struct Coef {
+    T ar[M], ai[M], br[M], bi[M], cr[M], ci[M];
+};
+
+template <typename T, int M>
+__device__ __forceinline__ void load_coef(Coef<T, M> &c, int64_t k0, int64_t n, const double4 *__restrict__ ph64,
+                                          const float4 *__restrict__ ph32, const double2 *__restrict__ c64)
+{
+#pragma unroll
+    for (int e = 0; e < M; ++e) {
+        const int64_t k = k0 + e;
+        const bool in = k < n;
+        const int64_t kc = in ? k : 0;
+        if constexpr (sizeof(T) == 4) {
+            const float4 v = ph32[kc];
+            c.ar[e] = in ? v.x : 0.f;
+            c.ai[e] = in ? v.y : 0.f;
+            c.br[e] = in ? v.z : 0.f;
+            c.bi[e] = in ? v.w : 0.f;
+        } else {
+            const double4 v = ph64[kc];
+            c.ar[e] = in ? v.x : 0.0;
+            c.ai[e] = in ? v.y : 0.0;
+            c.br[e] = in ? v.z : 0.0;
+            c.bi[e] = in ? v.w : 0.0;
+        }
+        const double2 cc = c64[kc];
+        c.cr[e] = in ? static_cast<T>(cc.x) : T(0);
+        c.ci[e] = in ? static_cast<T>(cc.y) : T(0);
+    }
+}
+
+// theta[row][k0 .. k0 + M) (0 past n); VEC: 16-byte aligned rows
+template <int M, bool VEC>
+__device__ __forceinline__ void load_theta(float (&th)[M], const float *__restrict__ rowp, int64_t k0, int64_t n)
+{
+    if (VEC && k0 + M <= n) {
+#pragma unroll
+        for (int e = 0; e < M; e += 4) {
+            const float4 v = *reinterpret_cast<const float4 *>(rowp + k0 + e);
+            th[e] = v.x;
+            th[e + 1] = v.y;
+            th[e + 2] = v.z;
+            th[e + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < M; ++e) th[e] = k0 + e < n ? rowp[k0 + e] : 0.f;
+    }
+}
+
 // Segment partials: part[(seg * 8 + c) * ldb + row], c = A.re, A.im,
 // B.re, B.im, Q.re, Q.im, Dg.re, Dg.im (doubles).
-template <typename T>
-__global__ __launch_bounds__(256) void relax_seg_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
+template <typename T, int M, int R, bool VEC>
+__global__ __launch_bounds__(256) void relax_fwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
                                                         int64_t n, const double4 *__restrict__ ph64,
                                                         const float4 *__restrict__ ph32,
-                                                        const double2 *__restrict__ c64, int seg_len, int nseg,
-                                                        int64_t ldb, double *__restrict__ part)
+                                                        const double2 *__restrict__ c64, int nseg, int64_t ldb,
+                                                        double *__restrict__ part)
 {
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int seg = static_cast<int>(blockIdx.y) * 4 + wave;
-    if (seg >= nseg) return;
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * 64 + lane;
-    const bool live = row < B;
-    const int64_t n0 = static_cast<int64_t>(seg) * seg_len;
-    const int64_t n1 = n0 + seg_len < n ? n0 + seg_len : n;
-    T ar = 0, ai = 0, br = 0, bi = 0, qr = 0, qi = 0, gr = 0, gi = 0;
-    const float *th = theta + (live ? row : 0) * ldt;
-    for (int64_t k = n0; k < n1; k += 4) {
-        float4 t4 = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (live) {
-            if (k + 3 < n1) {
-                t4 = make_float4(th[k], th[k + 1], th[k + 2], th[k + 3]);
-            } else {
-                t4.x = th[k];
-                if (k + 1 < n1) t4.y = th[k + 1];
-                if (k + 2 < n1) t4.z = th[k + 2];
-            }
-        }
-        const float tv[4] = {t4.x, t4.y, t4.z, t4.w};
+    __shared__ RTri sh[4];
+    const int seg = static_cast<int>(blockIdx.x % static_cast<unsigned>(nseg));
+    const int64_t row0 = static_cast<int64_t>(blockIdx.x / static_cast<unsigned>(nseg)) * R;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t k0 = static_cast<int64_t>(seg) * 256 * M + static_cast<int64_t>(t) * M;
+    Coef<T, M> c;
+    load_coef<T, M>(c, k0, n, ph64, ph32, c64);
+    for (int r = 0; r < R; ++r) {
+        const int64_t row = row0 + r;
+        if (row >= B) break;
+        float th[M];
+        load_theta<M, VEC>(th, theta + row * ldt, k0, n);
+        T ar = 0, ai = 0, br = 0, bi = 0, qr = 0, qi = 0, gr = 0, gi = 0;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            if (k + e >= n1) break;
-            T pa_r, pa_i, pb_r, pb_i;
-            if constexpr (sizeof(T) == 4) {
-                const float4 c = ph32[k + e];
-                pa_r = c.x; pa_i = c.y; pb_r = c.z; pb_i = c.w;
-            } else {
-                const double4 c = ph64[k + e];
-                pa_r = c.x; pa_i = c.y; pb_r = c.z; pb_i = c.w;
-            }
-            const double2 cc = c64[k + e];
-            const T d = tanh_t<T>(static_cast<T>(tv[e]));
-            const T yr = d * pb_r, yi = d * pb_i;
-            // Q += y * A (A before this domain)
+        for (int e = 0; e < M; ++e) {
+            const T d = tanh_t<T>(static_cast<T>(th[e]));
+            const T yr = d * c.br[e], yi = d * c.bi[e];
             qr = fma(yr, ar, fma(-yi, ai, qr));
             qi = fma(yr, ai, fma(yi, ar, qi));
-            ar = fma(d, pa_r, ar);
-            ai = fma(d, pa_i, ai);
+            ar = fma(d, c.ar[e], ar);
+            ai = fma(d, c.ai[e], ai);
             br += yr;
             bi += yi;
             const T d2 = d * d;
-            gr = fma(d2, static_cast<T>(cc.x), gr);
-            gi = fma(d2, static_cast<T>(cc.y), gi);
+            gr = fma(d2, c.cr[e], gr);
+            gi = fma(d2, c.ci[e], gi);
         }
+        RTri u{ar, ai, br, bi, qr, qi, gr, gi};
+        // ordered tree over the wave: lane l (l % 2 off == 0) appends lane l + off
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const RTri o = rtri_shfl_down(u, off);
+            if ((lane & (2 * off - 1)) == 0) rtri_append(u, o);
+        }
+        if (lane == 0) sh[wave] = u;
+        __syncthreads();
+        if (t == 0) {
+            RTri s0 = sh[0];
+            rtri_append(s0, sh[1]);
+            rtri_append(s0, sh[2]);
+            rtri_append(s0, sh[3]);
+            double *o = part + static_cast<int64_t>(seg) * 8 * ldb + row;
+            o[0] = s0.ar;
+            o[ldb] = s0.ai;
+            o[2 * ldb] = s0.br;
+            o[3 * ldb] = s0.bi;
+            o[4 * ldb] = s0.qr;
+            o[5 * ldb] = s0.qi;
+            o[6 * ldb] = s0.gr;
+            o[7 * ldb] = s0.gi;
+        }
+        __syncthreads();
     }
-    if (!live) return;
-    double *o = part + static_cast<int64_t>(seg) * 8 * ldb + row;
-    o[0] = ar; o[ldb] = ai; o[2 * ldb] = br; o[3 * ldb] = bi;
-    o[4 * ldb] = qr; o[5 * ldb] = qi; o[6 * ldb] = gr; o[7 * ldb] = gi;
 }
 
 // Per row: S = (combined Q) + sum Dg and f = |S|^2; with `edges`, also the
@@ -153,72 +232,152 @@ __global__ __launch_bounds__(256) void relax_combine_kernel(const double *__rest
     if (f) f[row] = static_cast<float>(fma(Sr, Sr, Si * Si));
 }
 
-// The adjoint walk of one segment.
-template <typename T>
-__global__ __launch_bounds__(256) void relax_grad_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
-                                                         int64_t n, const double4 *__restrict__ ph64,
-                                                         const float4 *__restrict__ ph32,
-                                                         const double2 *__restrict__ c64, int seg_len, int nseg,
-                                                         int64_t ldb, const double *__restrict__ part,
-                                                         const double *__restrict__ edges,
-                                                         const double *__restrict__ S,
-                                                         const float *__restrict__ grad_f,
-                                                         float *__restrict__ grad_theta, int64_t ldg)
+// The adjoint over one segment for R rows: lane prefix of A and suffix of
+// B by ordered scans (FP64), then each lane walks its chunk.
+template <typename T, int M, int R, bool VEC>
+__global__ __launch_bounds__(256) void relax_bwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
+                                                        int64_t n, const double4 *__restrict__ ph64,
+                                                        const float4 *__restrict__ ph32,
+                                                        const double2 *__restrict__ c64, int nseg, int64_t ldb,
+                                                        const double *__restrict__ edges,
+                                                        const double *__restrict__ S,
+                                                        const float *__restrict__ grad_f,
+                                                        float *__restrict__ grad_theta, int64_t ldg)
 {
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int seg = static_cast<int>(blockIdx.y) * 4 + wave;
-    if (seg >= nseg) return;
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * 64 + lane;
-    if (row >= B) return;
-    const int64_t n0 = static_cast<int64_t>(seg) * seg_len;
-    const int64_t n1 = n0 + seg_len < n ? n0 + seg_len : n;
-    const double *e = edges + static_cast<int64_t>(seg) * 4 * ldb + row;
-    const double *p = part + static_cast<int64_t>(seg) * 8 * ldb + row;
-    T pr = static_cast<T>(e[0]), pi = static_cast<T>(e[ldb]);  // P_{k-1}
-    // R_{k+1} = (suffix after the segment) + (segment B) - (B up to k)
-    const T rr0 = static_cast<T>(e[2 * ldb] + p[2 * ldb]), ri0 = static_cast<T>(e[3 * ldb] + p[3 * ldb]);
-    T cbr = 0, cbi = 0;
-    const T Sr = static_cast<T>(S[2 * row]), Si = static_cast<T>(S[2 * row + 1]);
-    const T gscale = static_cast<T>(2.0f * grad_f[row]);
-    const float *th = theta + row * ldt;
-    float *go = grad_theta + row * ldg;
-    for (int64_t k = n0; k < n1; ++k) {
-        T pa_r, pa_i, pb_r, pb_i;
-        if constexpr (sizeof(T) == 4) {
-            const float4 c = ph32[k];
-            pa_r = c.x; pa_i = c.y; pb_r = c.z; pb_i = c.w;
-        } else {
-            const double4 c = ph64[k];
-            pa_r = c.x; pa_i = c.y; pb_r = c.z; pb_i = c.w;
+    __shared__ double swa[4][2], swb[4][2];
+    const int seg = static_cast<int>(blockIdx.x % static_cast<unsigned>(nseg));
+    const int64_t row0 = static_cast<int64_t>(blockIdx.x / static_cast<unsigned>(nseg)) * R;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t k0 = static_cast<int64_t>(seg) * 256 * M + static_cast<int64_t>(t) * M;
+    Coef<T, M> c;
+    load_coef<T, M>(c, k0, n, ph64, ph32, c64);
+    for (int r = 0; r < R; ++r) {
+        const int64_t row = row0 + r;
+        if (row >= B) break;
+        float th[M];
+        load_theta<M, VEC>(th, theta + row * ldt, k0, n);
+        T d[M];
+        T alr = 0, ali = 0, blr = 0, bli = 0;
+#pragma unroll
+        for (int e = 0; e < M; ++e) {
+            d[e] = tanh_t<T>(static_cast<T>(th[e]));
+            alr = fma(d[e], c.ar[e], alr);
+            ali = fma(d[e], c.ai[e], ali);
+            blr = fma(d[e], c.br[e], blr);
+            bli = fma(d[e], c.bi[e], bli);
         }
-        const double2 cc = c64[k];
-        const T d = tanh_t<T>(static_cast<T>(th[k]));
-        const T yr = d * pb_r, yi = d * pb_i;
-        cbr += yr;
-        cbi += yi;
-        const T rr = rr0 - cbr, ri = ri0 - cbi;
-        // dS/dd = b P + a R + 2 c d
-        const T two_d = d + d;
-        const T dsr = fma(pb_r, pr, fma(-pb_i, pi, fma(pa_r, rr, fma(-pa_i, ri, two_d * static_cast<T>(cc.x)))));
-        const T dsi = fma(pb_r, pi, fma(pb_i, pr, fma(pa_r, ri, fma(pa_i, rr, two_d * static_cast<T>(cc.y)))));
-        const T re = fma(Sr, dsr, Si * dsi);
-        go[k] = static_cast<float>(gscale * re * (1 - d * d));
-        pr = fma(d, pa_r, pr);
-        pi = fma(d, pa_i, pi);
+        // inclusive scans over the wave: A forward, B backward
+        double par = alr, pai = ali, sbr = blr, sbi = bli;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double ur = __shfl_up(par, off), ui = __shfl_up(pai, off);
+            const double vr = __shfl_down(sbr, off), vi = __shfl_down(sbi, off);
+            if (lane >= off) {
+                par += ur;
+                pai += ui;
+            }
+            if (lane + off < 64) {
+                sbr += vr;
+                sbi += vi;
+            }
+        }
+        if (lane == 63) {
+            swa[wave][0] = par;
+            swa[wave][1] = pai;
+        }
+        if (lane == 0) {
+            swb[wave][0] = sbr;
+            swb[wave][1] = sbi;
+        }
+        __syncthreads();
+        const double *e = edges + static_cast<int64_t>(seg) * 4 * ldb + row;
+        // A before this lane's chunk, B after it
+        double Pr = e[0] + (par - alr), Pi = e[ldb] + (pai - ali);
+        double Rr = e[2 * ldb] + (sbr - blr), Ri = e[3 * ldb] + (sbi - bli);
+        for (int w = 0; w < wave; ++w) {
+            Pr += swa[w][0];
+            Pi += swa[w][1];
+        }
+        for (int w = 3; w > wave; --w) {
+            Rr += swb[w][0];
+            Ri += swb[w][1];
+        }
+        __syncthreads();
+        const T Sr = static_cast<T>(S[2 * row]), Si = static_cast<T>(S[2 * row + 1]);
+        const T gscale = static_cast<T>(2.0f * grad_f[row]);
+        // R_{k+1} = (B after the chunk) + (chunk B) - (chunk B up to k)
+        const T rr0 = static_cast<T>(Rr) + blr, ri0 = static_cast<T>(Ri) + bli;
+        T pr = static_cast<T>(Pr), pi = static_cast<T>(Pi), cbr = 0, cbi = 0;
+        float g[M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            const T dq = d[q];
+            cbr = fma(dq, c.br[q], cbr);
+            cbi = fma(dq, c.bi[q], cbi);
+            const T rr = rr0 - cbr, ri = ri0 - cbi;
+            // dS/dd = b P + a R + 2 c d
+            const T two_d = dq + dq;
+            const T dsr = fma(c.br[q], pr, fma(-c.bi[q], pi, fma(c.ar[q], rr, fma(-c.ai[q], ri, two_d * c.cr[q]))));
+            const T dsi = fma(c.br[q], pi, fma(c.bi[q], pr, fma(c.ar[q], ri, fma(c.ai[q], rr, two_d * c.ci[q]))));
+            const T re = fma(Sr, dsr, Si * dsi);
+            g[q] = static_cast<float>(gscale * re * (1 - dq * dq));
+            pr = fma(dq, c.ar[q], pr);
+            pi = fma(dq, c.ai[q], pi);
+        }
+        float *go = grad_theta + row * ldg;
+        if (VEC && k0 + M <= n) {
+#pragma unroll
+            for (int q = 0; q < M; q += 4)
+                *reinterpret_cast<float4 *>(go + k0 + q) = make_float4(g[q], g[q + 1], g[q + 2], g[q + 3]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < M; ++q)
+                if (k0 + q < n) go[k0 + q] = g[q];
+        }
     }
+}
+
+template <typename T, int M>
+static void launch_relax_fwd(const Design &d, const RelaxPlan &pl, bool vec, const float *theta, int64_t B,
+                             int64_t ldt, int64_t ldb, double *part, hipStream_t s)
+{
+    const unsigned blocks = static_cast<unsigned>(((B + pl.R - 1) / pl.R) * pl.nseg);
+#define QPM_RF(RR, V)                                                                                          \
+    relax_fwd_kernel<T, M, RR, V><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.ph32, d.c64, pl.nseg, ldb, \
+                                                         part)
+    if (pl.R == 4) {
+        if (vec) QPM_RF(4, true); else QPM_RF(4, false);
+    } else {
+        if (vec) QPM_RF(1, true); else QPM_RF(1, false);
+    }
+#undef QPM_RF
+}
+
+template <typename T, int M>
+static void launch_relax_bwd(const Design &d, const RelaxPlan &pl, bool vec, const float *theta, int64_t B,
+                             int64_t ldt, int64_t ldb, const double *edges, const double *S, const float *grad_f,
+                             float *grad_theta, int64_t ldg, hipStream_t s)
+{
+    const unsigned blocks = static_cast<unsigned>(((B + pl.R - 1) / pl.R) * pl.nseg);
+#define QPM_RB(RR, V)                                                                                              \
+    relax_bwd_kernel<T, M, RR, V><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.ph32, d.c64, pl.nseg, ldb,    \
+                                                         edges, S, grad_f, grad_theta, ldg)
+    if (pl.R == 4) {
+        if (vec) QPM_RB(4, true); else QPM_RB(4, false);
+    } else {
+        if (vec) QPM_RB(1, true); else QPM_RB(1, false);
+    }
+#undef QPM_RB
 }
 
 static qpm_status relax_partials(const Design &d, qpm_prec p, const float *theta, int64_t B, int64_t ldt,
                                  const RelaxPlan &pl, int64_t ldb, double *part, hipStream_t s)
 {
-    const dim3 grid(static_cast<unsigned>((B + 63) / 64), static_cast<unsigned>((pl.nseg + 3) / 4));
+    const bool vec = (reinterpret_cast<uintptr_t>(theta) & 15u) == 0 && ldt % 4 == 0;
     if (p == QPM_PREC_F32)
-        relax_seg_kernel<float><<<grid, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.ph32, d.c64, pl.seg_len, pl.nseg,
-                                                     ldb, part);
+        launch_relax_fwd<float, 8>(d, pl, vec, theta, B, ldt, ldb, part, s);
     else
-        relax_seg_kernel<double><<<grid, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.ph32, d.c64, pl.seg_len,
-                                                      pl.nseg, ldb, part);
+        launch_relax_fwd<double, 4>(d, pl, vec, theta, B, ldt, ldb, part, s);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }
@@ -330,7 +489,9 @@ QPM_API qpm_status qpm_relax_forward(qpm_design d, qpm_prec p, const float *thet
     if (st != QPM_OK) return st;
     QPM_REQUIRE(f != nullptr || S != nullptr, QPM_EINVAL, "at least one of f and S must be given");
     hipStream_t s = static_cast<hipStream_t>(sv);
-    const RelaxPlan pl = plan_relax(d->n, B);
+    const RelaxPlan pl = plan_relax(d->n, B, p == QPM_PREC_F32);
+    QPM_REQUIRE(((B + pl.R - 1) / pl.R) * pl.nseg < (int64_t(1) << 31), QPM_ERANGE,
+                "batch x segments too large for one launch");
     const int64_t ldb = ((B + 63) / 64) * 64;
     double *part = nullptr;
     QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&part), sizeof(double) * 8 * pl.nseg * ldb, s));
@@ -359,7 +520,9 @@ QPM_API qpm_status qpm_relax_backward(qpm_design d, qpm_prec p, const float *the
                 "S, grad_f and grad_theta must not be NULL");
     QPM_REQUIRE(ldg >= d->n, QPM_EINVAL, "ldg (%lld) must be >= n_domains", (long long)ldg);
     hipStream_t s = static_cast<hipStream_t>(sv);
-    const RelaxPlan pl = plan_relax(d->n, B);
+    const RelaxPlan pl = plan_relax(d->n, B, p == QPM_PREC_F32);
+    QPM_REQUIRE(((B + pl.R - 1) / pl.R) * pl.nseg < (int64_t(1) << 31), QPM_ERANGE,
+                "batch x segments too large for one launch");
     const int64_t ldb = ((B + 63) / 64) * 64;
     double *part = nullptr, *edges = nullptr;
     QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&part), sizeof(double) * 12 * pl.nseg * ldb, s));
@@ -368,14 +531,12 @@ QPM_API qpm_status qpm_relax_backward(qpm_design d, qpm_prec p, const float *the
     if (st == QPM_OK) {
         relax_combine_kernel<<<static_cast<unsigned>((B + 255) / 256), 256, 0, s>>>(part, pl.nseg, ldb, B, nullptr,
                                                                                     nullptr, edges);
-        const dim3 grid(static_cast<unsigned>((B + 63) / 64), static_cast<unsigned>((pl.nseg + 3) / 4));
+        const bool vec = (reinterpret_cast<uintptr_t>(theta) & 15u) == 0 && ldt % 4 == 0 &&
+                         (reinterpret_cast<uintptr_t>(grad_theta) & 15u) == 0 && ldg % 4 == 0;
         if (p == QPM_PREC_F32)
-            relax_grad_kernel<float><<<grid, 256, 0, s>>>(theta, ldt, B, d->n, d->ph64, d->ph32, d->c64, pl.seg_len,
-                                                          pl.nseg, ldb, part, edges, S, grad_f, grad_theta, ldg);
+            launch_relax_bwd<float, 8>(*d, pl, vec, theta, B, ldt, ldb, edges, S, grad_f, grad_theta, ldg, s);
         else
-            relax_grad_kernel<double><<<grid, 256, 0, s>>>(theta, ldt, B, d->n, d->ph64, d->ph32, d->c64,
-                                                           pl.seg_len, pl.nseg, ldb, part, edges, S, grad_f,
-                                                           grad_theta, ldg);
+            launch_relax_bwd<double, 4>(*d, pl, vec, theta, B, ldt, ldb, edges, S, grad_f, grad_theta, ldg, s);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
             set_error("relax adjoint launch failed: %s", hipGetErrorString(e));
