@@ -213,9 +213,11 @@ def main():
     if not args.no_extras:
         # generations/s with FP64 fitness, segmented and per-individual
         alt = {}
-        for name, p_, k_ in (("f64_segmented", qpm.PREC_F64, qpm.FIT_AUTO),
+        for name, p_, k_ in (("f64_table", qpm.PREC_F64, qpm.FIT_TABLE),
+                             ("f64_segmented", qpm.PREC_F64, qpm.FIT_SEGMENTED),
                              ("f64_per_genome", qpm.PREC_F64, qpm.FIT_PER_GENOME),
-                             ("f32_segmented", qpm.PREC_F32, qpm.FIT_AUTO)):
+                             ("f32_table", qpm.PREC_F32, qpm.FIT_TABLE),
+                             ("f32_segmented", qpm.PREC_F32, qpm.FIT_SEGMENTED)):
             st = 40 if k_ != qpm.FIT_PER_GENOME else 10
             R2, dt2 = timed_run(p_, k_, st, 3)
             R2.destroy()
@@ -226,8 +228,10 @@ def main():
         # fitness kernels alone on the same bits
         fit = {}
         stream = torch.cuda.current_stream()
-        for name, p_, k_, reps in (("f32_segmented", qpm.PREC_F32, qpm.FIT_AUTO, 100),
-                                   ("f64_segmented", qpm.PREC_F64, qpm.FIT_AUTO, 100),
+        for name, p_, k_, reps in (("f32_table", qpm.PREC_F32, qpm.FIT_TABLE, 100),
+                                   ("f64_table", qpm.PREC_F64, qpm.FIT_TABLE, 100),
+                                   ("f32_segmented", qpm.PREC_F32, qpm.FIT_SEGMENTED, 100),
+                                   ("f64_segmented", qpm.PREC_F64, qpm.FIT_SEGMENTED, 100),
                                    ("f64_per_genome", qpm.PREC_F64, qpm.FIT_PER_GENOME, 5)):
             o = qpm.eval_fitness(design, bits, NP, prec=p_, kernel=k_)
             for _ in range(3):

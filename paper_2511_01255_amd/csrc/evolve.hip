@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
                 dst = pv.out0 + packed_row(i, 1u);
             else
                 dst = (second(i) ? pv.out0 : pv.out1) + i * pv.ldx;
-            store_quad(dst, j0, D, uv);
+            store_quad_nt(dst, j0, D, uv);
             nib = quad_nibble(uv, j0, D);
         }
         // merge the nibbles of 8 neighbouring lanes (32 genes) into one word
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void gwo_kernel(PopView pv, const int32_t *__r
         const float4 X2 = *reinterpret_cast<const float4 *>(row_of(pv, L2) + j0);
         const float4 yv4 = gwo_quad(xv, X0, X1, X2, static_cast<uint32_t>(q), static_cast<uint32_t>(i), g, inst, k0,
                                     k1, a, two_a, variant);
-        store_quad(out_row_of(pv, i), j0, D, yv4);
+        store_quad_nt(out_row_of(pv, i), j0, D, yv4);
         nib = quad_nibble(yv4, j0, D);
     }
     store_word(nib, q, valid, bits, ld, i);

@@ -52,6 +52,22 @@ __device__ __forceinline__ void store_quad(float *dst, int64_t j0, int64_t D, fl
     }
 }
 
+// store_quad with non-temporal full-quad stores: trial and candidate rows
+// are not read again before the next step, so they should not displace the
+// rows the donor reads are served from
+__device__ __forceinline__ void store_quad_nt(float *dst, int64_t j0, int64_t D, float4 v)
+{
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    if (j0 + 3 < D) {
+        const v4f w = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(w, reinterpret_cast<v4f *>(dst + j0));
+    } else {
+        dst[j0] = v.x;
+        if (j0 + 1 < D) dst[j0 + 1] = v.y;
+        if (j0 + 2 < D) dst[j0 + 2] = v.z;
+    }
+}
+
 __device__ __forceinline__ uint32_t quad_nibble(float4 v, int64_t j0, int64_t D)
 {
     uint32_t n = 0;
