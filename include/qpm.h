@@ -363,12 +363,23 @@ qpm_status qpm_batch_info(qpm_batch b, int32_t *n_inst, int64_t *n_domains, doub
  * qpm_batch_eval_fitness -- f for np genomes of every instance. bits:
  * device, the population-major words of all instances stacked by instance
  * (sum_b W_b rows of ld words); fitness: device, n_inst x np floats / doubles
- * (instance-major). waves_per_group in {0 (default), 4, 8, 16} and
- * words_per_wave >= 0 (0 = default) choose the launch shape.
+ * (instance-major). With waves_per_group = words_per_wave = 0 the
+ * sign-pattern table kernel runs with its default shape; otherwise the
+ * per-domain kernel with waves_per_group in {0 (default), 4, 8, 16} and
+ * words_per_wave >= 0 (0 = default).
  */
 qpm_status qpm_batch_eval_fitness(qpm_batch b, qpm_prec p, const uint32_t *bits, int64_t np,
                                   int64_t ld, void *fitness, int32_t waves_per_group,
                                   int32_t words_per_wave, qpm_stream s);
+
+/*
+ * qpm_batch_eval_fitness_table -- qpm_batch_eval_fitness with the table
+ * kernel and an explicit shape: groups_per_workgroup in {1, 2, 4} groups of
+ * 64 genomes x 4 waves, words_per_wave in [1, 5] (FP32) or [1, 2] (FP64).
+ */
+qpm_status qpm_batch_eval_fitness_table(qpm_batch b, qpm_prec p, const uint32_t *bits, int64_t np,
+                                        int64_t ld, void *fitness, int32_t groups_per_workgroup,
+                                        int32_t words_per_wave, qpm_stream s);
 
 /*
  * qpm_batch_run_create -- one HWSDA run per instance, all advanced together

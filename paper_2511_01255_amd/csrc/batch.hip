@@ -106,6 +106,33 @@ __global__ __launch_bounds__(WAVES * 64) void batch_fit_kernel(const uint32_t *_
     o[5 * ld] = t.qi;
 }
 
+// The table kernel over (instance, segment) tiles: the sign-pattern tables
+// and bit rows of instance b start at its word row wofs_b.
+template <bool F32, int GW>
+__global__ __launch_bounds__(GW * 256) void batch_fit_tab_kernel(const uint32_t *__restrict__ bits, int64_t ld,
+                                                                 const double2 *__restrict__ tab64,
+                                                                 const float2 *__restrict__ tab32, int wpw,
+                                                                 int64_t np, const InstDesc *__restrict__ inst,
+                                                                 const FitSeg *__restrict__ tab,
+                                                                 double *__restrict__ part)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    const FitSeg fs = tab[blockIdx.y];
+    const InstDesc id = inst[fs.inst];
+    const int64_t i = (static_cast<int64_t>(blockIdx.x) * GW + (threadIdx.x >> 8)) * 64 + (threadIdx.x & 63);
+    Tri t;
+    if (!tab_segment<F32, GW>(t, bits + id.wofs * ld, ld, static_cast<int>(id.words), fs.w0,
+                              tab64 + id.wofs * 8 * 48, tab32 + id.wofs * 8 * 48, wpw, np, lds))
+        return;
+    double *o = part + static_cast<int64_t>(fs.slot) * 6 * ld + i;
+    o[0] = t.ar;
+    o[ld] = t.ai;
+    o[2 * ld] = t.br;
+    o[3 * ld] = t.bi;
+    o[4 * ld] = t.qr;
+    o[5 * ld] = t.qi;
+}
+
 // One workgroup per instance: combine the instance's slots into f, then
 //   mode 0 (evaluation only): f_out[b][i] = f;
 //   mode 1 (initial): f_cur = f, leaders, DE draws of generation gen;
@@ -255,7 +282,7 @@ __global__ __launch_bounds__(256) void batch_de_kernel(BatchPop bp, const InstDe
         const float4 bq = *reinterpret_cast<const float4 *>(row_of(pv, dr.y) + j0);
         const float4 cq = *reinterpret_cast<const float4 *>(row_of(pv, dr.z) + j0);
         const float4 uv = de_quad(xv, a, bq, cq, j0, dr.w, static_cast<uint32_t>(i), g, instb, k0, k1, F, cr_max);
-        store_quad(out_row_of(pv, i), j0, D, uv);
+        store_quad_nt(out_row_of(pv, i), j0, D, uv);
         nib = quad_nibble(uv, j0, D);
     }
     uint32_t w = nib << (4 * (t & 7));
@@ -272,18 +299,21 @@ __global__ __launch_bounds__(256) void batch_de_kernel(BatchPop bp, const InstDe
     }
 }
 
-// GWO: grid x = individual, y = tile (instance, 1024-gene chunk)
+// GWO: grid x = 8 ceil(np / 8) (individuals in contiguous ranges per XCD,
+// as in the single-design kernel), y = tile (instance, 1024-gene chunk)
 __global__ __launch_bounds__(256) void batch_gwo_kernel(BatchPop bp, const InstDesc *__restrict__ inst,
                                                         const Tile *__restrict__ tiles,
                                                         const int32_t *__restrict__ leaders,
                                                         const float *__restrict__ a_tab, uint32_t k0, uint32_t k1,
                                                         const uint32_t *__restrict__ gen, uint32_t inst0, int variant,
-                                                        uint32_t *__restrict__ bits, int64_t ld)
+                                                        uint32_t *__restrict__ bits, int64_t ld, int64_t per_xcd)
 {
+    const int64_t np = bp.np;
+    const int64_t i = static_cast<int64_t>(blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
+    if (i >= np) return;
     const Tile tl = tiles[blockIdx.y];
     const InstDesc id = inst[tl.inst];
-    const int64_t i = blockIdx.x;
-    const int64_t np = bp.np, D = id.n;
+    const int64_t D = id.n;
     const int64_t L0 = leaders[3 * tl.inst], L1 = leaders[3 * tl.inst + 1], L2 = leaders[3 * tl.inst + 2];
     if (i == L0 || i == L1 || i == L2) return;
     if (L0 < 0 || L0 >= np || L1 < 0 || L1 >= np || L2 < 0 || L2 >= np) return;
@@ -302,7 +332,7 @@ __global__ __launch_bounds__(256) void batch_gwo_kernel(BatchPop bp, const InstD
         const float4 X2 = *reinterpret_cast<const float4 *>(row_of(pv, L2) + j0);
         const float4 yv = gwo_quad(xv, X0, X1, X2, static_cast<uint32_t>(q), static_cast<uint32_t>(i), g,
                                    inst0 + static_cast<uint32_t>(tl.inst), k0, k1, a, two_a, variant);
-        store_quad(out_row_of(pv, i), j0, D, yv);
+        store_quad_nt(out_row_of(pv, i), j0, D, yv);
         nib = quad_nibble(yv, j0, D);
     }
     store_word(nib, q, valid, bits + id.wofs * ld, ld, i);
@@ -323,8 +353,9 @@ __global__ __launch_bounds__(256) void batch_gather_kernel(BatchPop bp, const In
 // ---------------------------------------------------------------- plans
 
 struct BatchFitPlan {
-    int waves = 16;
+    int waves = 16;  // per-domain kernel: waves per workgroup; table kernel: 4 segment waves
     int wpw = 8;
+    int gw = 0;      // table kernel: genome groups of 64 per workgroup (0 = per-domain kernel)
     std::vector<FitSeg> segs;
     std::vector<int> slot_ofs;  // n_inst + 1
 };
@@ -342,6 +373,20 @@ static BatchFitPlan make_fit_plan(const std::vector<InstDesc> &h, int waves, int
         p.slot_ofs.push_back(slot);
     }
     return p;
+}
+
+// the table plan: tiles of 4 wpw words, gw genome groups per workgroup
+static BatchFitPlan make_tab_plan(const std::vector<InstDesc> &h, int gw, int wpw)
+{
+    BatchFitPlan p = make_fit_plan(h, 4, wpw);
+    p.gw = gw;
+    return p;
+}
+
+static void default_tab_shape(int64_t np, bool f32, int *gw, int *wpw)
+{
+    *gw = np >= 256 ? 4 : (np >= 128 ? 2 : 1);
+    *wpw = f32 ? 4 : 2;
 }
 
 static void default_fit_shape(const std::vector<InstDesc> &h, int64_t np, int *waves, int *wpw)
@@ -372,6 +417,8 @@ struct qpm_batch_s {
     float4 *ph32 = nullptr;
     double2 *c64 = nullptr;
     double *Cdev = nullptr;
+    double2 *tab64 = nullptr;  // sign-pattern tables, [8 total_words][3][16]
+    float2 *tab32 = nullptr;
 };
 
 static void free_batch(qpm_batch_s *b)
@@ -382,6 +429,8 @@ static void free_batch(qpm_batch_s *b)
     (void)hipFree(b->ph32);
     (void)hipFree(b->c64);
     (void)hipFree(b->Cdev);
+    (void)hipFree(b->tab64);
+    (void)hipFree(b->tab32);
     delete b;
 }
 
@@ -432,6 +481,8 @@ QPM_API qpm_status qpm_precompute_phases_batched(const double *z, const int64_t 
     if (e == hipSuccess) e = hipMalloc(&bt->ph32, sizeof(float4) * 32 * words);
     if (e == hipSuccess) e = hipMalloc(&bt->c64, sizeof(double2) * 32 * words);
     if (e == hipSuccess) e = hipMalloc(&bt->Cdev, sizeof(double) * 2 * n_inst);
+    if (e == hipSuccess) e = hipMalloc(&bt->tab64, sizeof(double2) * 48 * 8 * words);
+    if (e == hipSuccess) e = hipMalloc(&bt->tab32, sizeof(float2) * 48 * 8 * words);
     if (e == hipSuccess) e = hipMalloc(&bt->dev, sizeof(InstDesc) * n_inst);
     if (e == hipSuccess) e = hipMalloc(&zdev, sizeof(double) * offsets[n_inst]);
     if (e == hipSuccess) e = hipMemcpyAsync(zdev, z, sizeof(double) * offsets[n_inst], hipMemcpyHostToDevice, s);
@@ -441,6 +492,8 @@ QPM_API qpm_status qpm_precompute_phases_batched(const double *z, const int64_t 
                           bt->c64 + 32 * d.wofs, bt->Cdev + 2 * b, s) != QPM_OK)
             e = hipErrorLaunchFailure;
     }
+    if (e == hipSuccess && launch_pattern_tables(bt->ph64, words, bt->tab64, bt->tab32, s) != QPM_OK)
+        e = hipErrorLaunchFailure;
     std::vector<double> C(2 * n_inst);
     if (e == hipSuccess) e = hipMemcpyAsync(C.data(), bt->Cdev, sizeof(double) * 2 * n_inst, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -490,6 +543,29 @@ QPM_API qpm_status qpm_batch_info(qpm_batch b, int32_t *n_inst, int64_t *n_domai
 static qpm_status launch_batch_fit(const qpm_batch_s &bt, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
                                    const BatchFitPlan &pl, const FitSeg *segs_dev, double *part, hipStream_t s)
 {
+    if (pl.gw > 0) {
+        const dim3 grid(static_cast<unsigned>((np + 64 * pl.gw - 1) / (64 * pl.gw)),
+                        static_cast<unsigned>(pl.segs.size()));
+        const size_t lds = table_lds_bytes(4 * pl.wpw, p == QPM_PREC_F32, pl.gw, pl.wpw);
+#define QPM_BT_CASE(G)                                                                                             \
+    case G:                                                                                                        \
+        if (p == QPM_PREC_F32)                                                                                     \
+            batch_fit_tab_kernel<true, G><<<grid, G * 256, lds, s>>>(bits, ld, bt.tab64, bt.tab32, pl.wpw, np, bt.dev, \
+                                                                    segs_dev, part);                               \
+        else                                                                                                       \
+            batch_fit_tab_kernel<false, G><<<grid, G * 256, lds, s>>>(bits, ld, bt.tab64, bt.tab32, pl.wpw, np,      \
+                                                                     bt.dev, segs_dev, part);                      \
+        break;
+        switch (pl.gw) {
+            QPM_BT_CASE(1)
+            QPM_BT_CASE(2)
+            QPM_BT_CASE(4)
+        default: QPM_REQUIRE(false, QPM_EINVAL, "unsupported genome groups per workgroup %d", pl.gw);
+        }
+#undef QPM_BT_CASE
+        QPM_TRY_HIP(hipGetLastError());
+        return QPM_OK;
+    }
     const dim3 grid(static_cast<unsigned>((np + 63) / 64), static_cast<unsigned>(pl.segs.size()));
 #define QPM_BF_CASE(NW)                                                                                           \
     case NW:                                                                                                      \
@@ -566,6 +642,9 @@ static qpm_status launch_batch_finish(int mode, const qpm_batch_s &bt, qpm_prec 
     return QPM_OK;
 }
 
+static qpm_status batch_eval_plan(qpm_batch b, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                                  void *fitness, const BatchFitPlan &pl, hipStream_t s);
+
 QPM_API qpm_status qpm_batch_eval_fitness(qpm_batch b, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
                                           void *fitness, int32_t waves_per_group, int32_t words_per_wave,
                                           qpm_stream sv)
@@ -579,11 +658,41 @@ QPM_API qpm_status qpm_batch_eval_fitness(qpm_batch b, qpm_prec p, const uint32_
                 QPM_EINVAL, "waves_per_group must be 0 (default), 4, 8 or 16");
     QPM_REQUIRE(words_per_wave >= 0, QPM_EINVAL, "words_per_wave must be >= 0");
     hipStream_t s = static_cast<hipStream_t>(sv);
-    int waves, wpw;
-    default_fit_shape(b->host, np, &waves, &wpw);
-    if (waves_per_group) waves = waves_per_group;
-    if (words_per_wave) wpw = words_per_wave;
-    const BatchFitPlan pl = make_fit_plan(b->host, waves, wpw);
+    BatchFitPlan pl;
+    if (waves_per_group == 0 && words_per_wave == 0) {
+        int gw, wpw;
+        default_tab_shape(np, p == QPM_PREC_F32, &gw, &wpw);
+        pl = make_tab_plan(b->host, gw, wpw);
+    } else {
+        int waves, wpw;
+        default_fit_shape(b->host, np, &waves, &wpw);
+        if (waves_per_group) waves = waves_per_group;
+        if (words_per_wave) wpw = words_per_wave;
+        pl = make_fit_plan(b->host, waves, wpw);
+    }
+    return batch_eval_plan(b, p, bits, np, ld, fitness, pl, s);
+}
+
+QPM_API qpm_status qpm_batch_eval_fitness_table(qpm_batch b, qpm_prec p, const uint32_t *bits, int64_t np,
+                                                int64_t ld, void *fitness, int32_t groups, int32_t wpw,
+                                                qpm_stream sv)
+{
+    clear_error();
+    QPM_REQUIRE(b && bits && fitness, QPM_EINVAL, "batch, bits and fitness must not be NULL");
+    QPM_REQUIRE(p == QPM_PREC_F32 || p == QPM_PREC_F64, QPM_EINVAL, "unknown precision %d", (int)p);
+    QPM_REQUIRE(np >= 1 && np <= (int64_t(1) << 24), QPM_EINVAL, "np out of range (%lld)", (long long)np);
+    QPM_REQUIRE(ld >= np && ld % 64 == 0, QPM_EINVAL, "ld (%lld) must be >= np and a multiple of 64", (long long)ld);
+    QPM_REQUIRE(groups == 1 || groups == 2 || groups == 4, QPM_EINVAL,
+                "groups_per_workgroup must be 1, 2 or 4 (got %d)", (int)groups);
+    QPM_REQUIRE(wpw >= 1 && wpw <= table_max_wpw(p == QPM_PREC_F32), QPM_EINVAL,
+                "words_per_wave must be in [1, %d] (got %d)", table_max_wpw(p == QPM_PREC_F32), (int)wpw);
+    return batch_eval_plan(b, p, bits, np, ld, fitness, make_tab_plan(b->host, groups, wpw),
+                           static_cast<hipStream_t>(sv));
+}
+
+static qpm_status batch_eval_plan(qpm_batch b, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                                  void *fitness, const BatchFitPlan &pl, hipStream_t s)
+{
     QPM_REQUIRE(pl.segs.size() <= 65535, QPM_ERANGE, "too many fitness segments (%zu)", pl.segs.size());
     FitPlanDev fp;
     qpm_status st = upload_fit_plan(pl, ld, s, &fp);
@@ -684,10 +793,11 @@ static qpm_status launch_batch_de(qpm_batch_run_s *r)
 static qpm_status launch_batch_gwo(qpm_batch_run_s *r)
 {
     const qpm_run_config &c = r->cfg;
-    const dim3 grid(static_cast<unsigned>(c.np), static_cast<unsigned>(r->n_gtiles));
+    const int64_t per_xcd = (c.np + 7) / 8;
+    const dim3 grid(static_cast<unsigned>(8 * per_xcd), static_cast<unsigned>(r->n_gtiles));
     batch_gwo_kernel<<<grid, 256, 0, r->st>>>(r->pop(), r->inst, r->gtiles, r->leaders, r->a_tab,
                                              static_cast<uint32_t>(c.seed), static_cast<uint32_t>(c.seed >> 32),
-                                             r->gen, c.inst, c.gwo_variant, r->bits, r->ld);
+                                             r->gen, c.inst, c.gwo_variant, r->bits, r->ld, per_xcd);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }
@@ -718,44 +828,46 @@ static qpm_status batch_generation(qpm_batch_run_s *r, hipEvent_t *ev = nullptr)
     return mark(QPM_K_COUNT);
 }
 
-// time the batched fitness for a few launch shapes on the current bits and
-// keep the fastest (results are equal up to the summation order)
+// time the batched table fitness for a few launch shapes on the current
+// bits and keep the fastest (results are equal up to the summation order)
 static qpm_status tune_fitness(qpm_batch_run_s *r)
 {
     const qpm_run_config &c = r->cfg;
-    const std::string key = tune_key("batchfit", r->bt->total_words, c.np, c.prec, r->bt->n_inst);
+    const qpm_prec p = static_cast<qpm_prec>(c.prec);
+    const std::string key = tune_key("batchtab", r->bt->total_words, c.np, c.prec, r->bt->n_inst);
     {
         int v0, v1;
         if (tune_lookup(key, &v0, &v1)) {
-            r->fplan = make_fit_plan(r->bt->host, v0, v1);
+            r->fplan = make_tab_plan(r->bt->host, v0, v1);
             return QPM_OK;
         }
     }
-    int dw, dwpw;
-    default_fit_shape(r->bt->host, c.np, &dw, &dwpw);
     std::vector<std::pair<int, int>> cands;
-    for (int waves : {4, 8, 16})
-        for (int f : {1, 2, 4, 8}) cands.push_back({waves, std::max(1, dwpw * f / 2)});
+    for (int g : {1, 2, 4})
+        for (int w = 1; w <= table_max_wpw(p == QPM_PREC_F32); ++w) cands.push_back({g, w});
     hipEvent_t e0, e1;
     QPM_TRY_HIP(hipEventCreate(&e0));
     QPM_TRY_HIP(hipEventCreate(&e1));
     float best = 1e30f;
-    std::pair<int, int> pick{dw, dwpw};
-    const qpm_prec p = static_cast<qpm_prec>(c.prec);
+    std::pair<int, int> pick{1, 1};
+    default_tab_shape(c.np, p == QPM_PREC_F32, &pick.first, &pick.second);
     for (auto cand : cands) {
-        BatchFitPlan pl = make_fit_plan(r->bt->host, cand.first, cand.second);
+        BatchFitPlan pl = make_tab_plan(r->bt->host, cand.first, cand.second);
         if (pl.segs.size() > 65535) continue;
         FitPlanDev fp;
         qpm_status st = upload_fit_plan(pl, r->ld, r->st, &fp);
         if (st != QPM_OK) return st;
         st = launch_batch_fit(*r->bt, p, r->bits, c.np, r->ld, pl, fp.segs, fp.part, r->st);  // warm-up
-        QPM_TRY_HIP(hipEventRecord(e0, r->st));
-        for (int rep = 0; rep < 3 && st == QPM_OK; ++rep)
+        float ms = 1e30f;
+        for (int rep = 0; rep < 3 && st == QPM_OK; ++rep) {
+            QPM_TRY_HIP(hipEventRecord(e0, r->st));
             st = launch_batch_fit(*r->bt, p, r->bits, c.np, r->ld, pl, fp.segs, fp.part, r->st);
-        QPM_TRY_HIP(hipEventRecord(e1, r->st));
-        QPM_TRY_HIP(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        QPM_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+            QPM_TRY_HIP(hipEventRecord(e1, r->st));
+            QPM_TRY_HIP(hipEventSynchronize(e1));
+            float t = 0.0f;
+            QPM_TRY_HIP(hipEventElapsedTime(&t, e0, e1));
+            ms = std::min(ms, t);
+        }
         free_fit_plan(fp, r->st);
         if (st != QPM_OK) return st;
         if (ms < best) {
@@ -766,8 +878,8 @@ static qpm_status tune_fitness(qpm_batch_run_s *r)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     QPM_TRY_HIP(hipStreamSynchronize(r->st));
-    r->tune_us = best * 1000.0 / 3.0;
-    r->fplan = make_fit_plan(r->bt->host, pick.first, pick.second);
+    r->tune_us = best * 1000.0;
+    r->fplan = make_tab_plan(r->bt->host, pick.first, pick.second);
     tune_store(key, pick.first, pick.second);
     return QPM_OK;
 }
@@ -876,9 +988,9 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
     if (tune) {
         st = tune_fitness(r);
     } else {
-        int dw, dwpw;
-        default_fit_shape(b->host, c.np, &dw, &dwpw);
-        r->fplan = make_fit_plan(b->host, dw, dwpw);
+        int gw, wpw;
+        default_tab_shape(c.np, c.prec == QPM_PREC_F32, &gw, &wpw);
+        r->fplan = make_tab_plan(b->host, gw, wpw);
     }
     if (st == QPM_OK && r->fplan.segs.size() > 65535) {
         set_error("too many fitness segments (%zu)", r->fplan.segs.size());

@@ -12,6 +12,8 @@
 
 #include <cstdint>
 
+#include "common.hpp"
+
 namespace qpm {
 
 // +-1.0 from bit k of w (bit set -> -1), as a double and as a float
@@ -139,6 +141,118 @@ __device__ __forceinline__ void scan_word_f32(Tri &t, uint32_t word, const float
         const Tri u{ar, ai, br, bi, qr, qi};
         tri_append(t, u);
     }
+}
+
+// One workgroup of the table kernels (GW genome groups of 64 x 4 segment
+// waves, lane = genome) over the words [wbase, wbase + 4 wpw) of a design
+// of W words: `bits` and the tables point at the design's word 0; the
+// workgroup copies the tables of its words to `lds` (table_lds_bytes), each
+// wave walks wpw words of its segment, and the 4 segment triples of each
+// genome are folded in order. Returns true (with the workgroup's triple in
+// t) in the first segment wave of each group for genomes i < np, where
+// i = (blockIdx.x GW + group) 64 + lane. Every lane of the workgroup must
+// call it (it synchronises the workgroup).
+template <bool F32, int GW>
+__device__ __forceinline__ bool tab_segment(Tri &t, const uint32_t *__restrict__ bits, int64_t ld, int W, int wbase,
+                                            const double2 *__restrict__ tab64, const float2 *__restrict__ tab32,
+                                            int wpw, int64_t np, unsigned char *lds)
+{
+    constexpr int SW = 4;
+    constexpr int NT = GW * 256;
+    constexpr int MAXW = table_max_wpw(F32);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int gsub = wave / SW, ssub = wave % SW;
+    const int64_t i = (static_cast<int64_t>(blockIdx.x) * GW + gsub) * 64 + lane;
+    const int nw = min(W - wbase, SW * wpw);  // >= 1 by the grid
+    // the tables of words [wbase, wbase + nw) go straight to LDS (16 bytes
+    // per lane per load, no registers, no wait between loads)
+    {
+        const int n16 = nw * 8 * 48 * (F32 ? 8 : 16) / 16;
+        const uint4 *src = F32 ? reinterpret_cast<const uint4 *>(tab32 + static_cast<int64_t>(wbase) * 8 * 48)
+                               : reinterpret_cast<const uint4 *>(tab64 + static_cast<int64_t>(wbase) * 8 * 48);
+        for (int k = 0; k * NT < n16; ++k) {
+            const int idx = k * NT + static_cast<int>(threadIdx.x);
+            if (idx < n16)
+                __builtin_amdgcn_global_load_lds(
+                    src + idx, reinterpret_cast<__attribute__((address_space(3))) void *>(
+                                   reinterpret_cast<uintptr_t>(lds + static_cast<size_t>(k * NT + wave * 64) * 16)),
+                    16, 0, 0);
+        }
+    }
+    // this wave's bit words, loaded while the tables arrive (clamped
+    // addresses, so every load is in bounds and none is branched around)
+    const bool live = i < np;
+    const int w0 = ssub * wpw, w1 = min(nw, w0 + wpw);
+    const int64_t ic = i < ld ? i : ld - 1;
+    uint32_t wv[MAXW];
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) wv[k] = bits[static_cast<int64_t>(min(wbase + w0 + k, W - 1)) * ld + ic];
+    // keep the loads here, issued together with the table copies (the
+    // compiler would otherwise sink each one to its first use, one memory
+    // latency per word)
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) asm volatile("" ::"v"(wv[k]));
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    t = Tri{0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) {
+        const int wr = w0 + k;
+        if (wr >= w1) break;
+        const uint32_t word = live ? wv[k] : 0u;
+        if constexpr (F32) {
+            const float2 *tb = reinterpret_cast<const float2 *>(lds) + wr * 8 * 48;
+            float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f, qr = 0.f, qi = 0.f;
+#pragma unroll
+            for (int h = 0; h < 8; ++h) {
+                const uint32_t pt = (word >> (4 * h)) & 15u;
+                const float2 A = tb[h * 48 + pt], B = tb[h * 48 + 16 + pt], Q = tb[h * 48 + 32 + pt];
+                qr = fmaf(-ai, B.y, fmaf(ar, B.x, qr + Q.x));
+                qi = fmaf(ai, B.x, fmaf(ar, B.y, qi + Q.y));
+                ar += A.x;
+                ai += A.y;
+                br += B.x;
+                bi += B.y;
+            }
+            tri_append(t, Tri{ar, ai, br, bi, qr, qi});
+        } else {
+            const double2 *tb = reinterpret_cast<const double2 *>(lds) + wr * 8 * 48;
+#pragma unroll
+            for (int h = 0; h < 8; ++h) {
+                const uint32_t pt = (word >> (4 * h)) & 15u;
+                const double2 A = tb[h * 48 + pt], B = tb[h * 48 + 16 + pt], Q = tb[h * 48 + 32 + pt];
+                t.qr = fma(-t.ai, B.y, fma(t.ar, B.x, t.qr + Q.x));
+                t.qi = fma(t.ai, B.x, fma(t.ar, B.y, t.qi + Q.y));
+                t.ar += A.x;
+                t.ai += A.y;
+                t.br += B.x;
+                t.bi += B.y;
+            }
+        }
+    }
+    // the 4 segment triples of each genome group, in order, through LDS
+    // (the tables are no longer read)
+    __syncthreads();
+    double *sh = reinterpret_cast<double *>(lds);  // [6][GW * SW][64]
+    constexpr int NWV = GW * SW;
+    sh[(0 * NWV + wave) * 64 + lane] = t.ar;
+    sh[(1 * NWV + wave) * 64 + lane] = t.ai;
+    sh[(2 * NWV + wave) * 64 + lane] = t.br;
+    sh[(3 * NWV + wave) * 64 + lane] = t.bi;
+    sh[(4 * NWV + wave) * 64 + lane] = t.qr;
+    sh[(5 * NWV + wave) * 64 + lane] = t.qi;
+    __syncthreads();
+    if (ssub != 0 || !live) return false;
+#pragma unroll 1
+    for (int s2 = 1; s2 < SW; ++s2) {
+        if (s2 * wpw >= nw) break;
+        const int v = gsub * SW + s2;
+        tri_append(t, Tri{sh[(0 * NWV + v) * 64 + lane], sh[(1 * NWV + v) * 64 + lane], sh[(2 * NWV + v) * 64 + lane],
+                          sh[(3 * NWV + v) * 64 + lane], sh[(4 * NWV + v) * 64 + lane],
+                          sh[(5 * NWV + v) * 64 + lane]});
+    }
+    return true;
 }
 
 }  // namespace qpm

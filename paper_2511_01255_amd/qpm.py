@@ -78,6 +78,7 @@ _SIGS = {
     "qpm_batch_free": (_I32, [_P]),
     "qpm_batch_info": (_I32, [_P, _P, _P, _P]),
     "qpm_batch_eval_fitness": (_I32, [_P, _I32, _P, _I64, _I64, _P, _I32, _I32, _P]),
+    "qpm_batch_eval_fitness_table": (_I32, [_P, _I32, _P, _I64, _I64, _P, _I32, _I32, _P]),
     "qpm_batch_run_create": (_I32, [_P, C.POINTER(RunConfig), _I32, _P, C.POINTER(_P)]),
     "qpm_batch_run_advance": (_I32, [_P, _I64]),
     "qpm_batch_run_set_timing": (_I32, [_P, _I32]),
@@ -439,6 +440,17 @@ def batch_eval_fitness(batch, bits, np_, prec=PREC_F32, waves_per_group=0, words
                           device=bits.device)
     _check(lib().qpm_batch_eval_fitness(batch.handle, prec, _ptr(bits), np_, bits.shape[1], _ptr(out),
                                         waves_per_group, words_per_wave, _stream(stream)))
+    return out
+
+
+def batch_eval_fitness_table(batch, bits, np_, prec, groups_per_workgroup, words_per_wave, out=None, stream=None):
+    """batch_eval_fitness with the table kernel and an explicit shape."""
+    import torch
+    if out is None:
+        out = torch.empty((batch.n_inst, np_), dtype=torch.float64 if prec == PREC_F64 else torch.float32,
+                          device=bits.device)
+    _check(lib().qpm_batch_eval_fitness_table(batch.handle, prec, _ptr(bits), np_, bits.shape[1], _ptr(out),
+                                              groups_per_workgroup, words_per_wave, _stream(stream)))
     return out
 
 

@@ -55,6 +55,26 @@ def test_batch_fitness_matches_oracle(q, orc, prec, shape):
         assert abs(Cs[k] - O.phases()[3]) <= 1e-12 * abs(O.phases()[3]) + 1e-300
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("groups", [1, 2, 4])
+def test_batch_table_fitness_every_shape(q, orc, prec, groups):
+    # the table kernel over uneven instances (N = 1 ... 2049), every words
+    # per wave the LDS allows, ragged population
+    import torch
+    specs = _small_batch()
+    npop = 197
+    B = q.precompute_phases_batched([s[0] for s in specs], [s[1] for s in specs], [s[2] for s in specs])
+    ds = [inputs.random_signs(npop, len(s[0]) - 1, seed=10 + k) for k, s in enumerate(specs)]
+    bits = torch.from_numpy(_stack_bits(ds, inputs.ld_for(npop)).view(np.int32)).cuda()
+    refs = [orc.Design(z, k1, k2).fitness(ds[k])[1] for k, (z, k1, k2) in enumerate(specs)]
+    for wpw in range(1, 6 if prec == 0 else 3):
+        f = q.batch_eval_fitness_table(B, bits, npop, prec, groups, wpw).double().cpu().numpy()
+        for k, fo in enumerate(refs):
+            floor = 1e-2 * np.median(fo)
+            err = np.max(np.abs(f[k] - fo) / np.maximum(fo, floor))
+            assert err <= (1e-12 if prec == 1 else 1e-5), (wpw, k, err)
+
+
 def test_batch_run_fp64_equals_oracle_runs(q, orc):
     # every instance follows the single-design run with instance number
     # inst0 + b: same trajectory as the oracle's run, bit for bit
