@@ -301,15 +301,17 @@ def main():
         th = torch.from_numpy(inputs.relax_theta(256, 50000, seed=1)).cuda()
         ones = torch.ones(256, device="cuda")
         rel = {}
+        # forward keeping the segment edges, then the adjoint from them (the
+        # autograd path)
         for name, p_ in (("f32", qpm.PREC_F32), ("f64", qpm.PREC_F64)):
-            f_, S_ = qpm.relax_forward(Dr, th, p_)
-            qpm.relax_backward(Dr, th, S_, ones, p_)
+            f_, S_, E_ = qpm.relax_forward(Dr, th, p_, keep_edges=True)
+            qpm.relax_backward(Dr, th, S_, ones, p_, edges=E_)
             stream = torch.cuda.current_stream()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             for _ in range(10):
-                f_, S_ = qpm.relax_forward(Dr, th, p_)
-                qpm.relax_backward(Dr, th, S_, ones, p_)
+                f_, S_, E_ = qpm.relax_forward(Dr, th, p_, keep_edges=True)
+                qpm.relax_backward(Dr, th, S_, ones, p_, edges=E_)
             e1.record(stream)
             torch.cuda.synchronize()
             t = e0.elapsed_time(e1) * 1e-3 / 10

@@ -215,24 +215,38 @@ qpm_status qpm_gwo_step(const float *x, int64_t np, int64_t D, int64_t ldx,
  * which equals the +-1 fitness where |theta| is large. theta: device,
  * B x ldt floats (row b holds theta_{b,0..N-1}); f: device B floats and/or
  * S: device B x 2 doubles (re, im); either may be NULL, not both.
- * prec selects FP32 (per-segment scans in FP32, segments combined in FP64)
- * or FP64. Temporary device memory comes from the stream-ordered
- * allocator of s.
+ * edges: NULL, or device doubles (qpm_relax_edges_size of them) that
+ * receive the per-segment prefix and suffix sums the adjoint needs, so that
+ * qpm_relax_backward given them skips recomputing the forward pass.
+ * prec selects FP32 (per-lane chunks in FP32, everything across lanes and
+ * segments in FP64) or FP64. Temporary device memory comes from the
+ * stream-ordered allocator of s.
+ * Errors: QPM_EINVAL (NULL design or theta, both outputs NULL, B outside
+ * [1, 2^24], ldt < N, unknown precision), QPM_ERANGE, QPM_EHIP.
  */
 qpm_status qpm_relax_forward(qpm_design d, qpm_prec p, const float *theta, int64_t B, int64_t ldt,
-                             float *f, double *S, qpm_stream s);
+                             float *f, double *S, double *edges, qpm_stream s);
+
+/* Number of doubles of the edges buffer of qpm_relax_forward for a batch of
+ * B rows in precision p (4 per row and segment of 2048 (FP32) or 1024
+ * (FP64) domains). */
+qpm_status qpm_relax_edges_size(qpm_design d, qpm_prec p, int64_t B, int64_t *count);
 
 /*
  * qpm_relax_backward -- the adjoint of qpm_relax_forward:
  *   grad_theta_{b,k} = grad_f_b 2 Re(conj(S_b) dS_b/dd_k) (1 - d_k^2),
  *   dS/dd_k = b_k P_{k-1} + a_k R_{k+1} + 2 c_k d_k,
  * with P_{k-1} = sum_{m<k} d_m a_m and R_{k+1} = sum_{n>k} d_n b_n.
- * S: device B x 2 doubles saved from the forward call; grad_f: device B
- * floats; grad_theta: device B x ldg floats.
+ * S: device B x 2 doubles saved from the forward call; edges: the edges of
+ * the same forward call (same theta and precision), or NULL to recompute
+ * them; grad_f: device B floats; grad_theta: device B x ldg floats (entries
+ * past N are not written).
+ * Errors: as qpm_relax_forward, and QPM_EINVAL for NULL S, grad_f or
+ * grad_theta or ldg < N.
  */
 qpm_status qpm_relax_backward(qpm_design d, qpm_prec p, const float *theta, int64_t B, int64_t ldt,
-                              const double *S, const float *grad_f, float *grad_theta, int64_t ldg,
-                              qpm_stream s);
+                              const double *S, const double *edges, const float *grad_f,
+                              float *grad_theta, int64_t ldg, qpm_stream s);
 
 /* Configuration of a whole optimisation (paper Sec. 3.2, steps 1-7). */
 typedef struct {

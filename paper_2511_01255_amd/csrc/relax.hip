@@ -188,43 +188,68 @@ __global__ __launch_bounds__(256) void relax_fwd_kernel(const float *__restrict_
     }
 }
 
-// Per row: S = (combined Q) + sum Dg and f = |S|^2; with `edges`, also the
-// prefix A before and the suffix B after every segment:
-// edges[(seg * 4 + c) * ldb + row], c = Apre.re, Apre.im, Bsuf.re, Bsuf.im.
+// Per row (one wave): S = (combined Q) + sum Dg and f = |S|^2; with `edges`,
+// also the prefix A before and the suffix B after every segment:
+// edges[(seg * 4 + c) * lde + row], c = Apre.re, Apre.im, Bsuf.re, Bsuf.im.
+// Lane l folds the segments [l m, (l + 1) m), m = ceil(nseg / 64), in
+// order; an ordered shuffle tree combines the lanes, and lane scans give
+// each lane's prefix of A and suffix of B for the edges.
 __global__ __launch_bounds__(256) void relax_combine_kernel(const double *__restrict__ part, int nseg, int64_t ldb,
                                                             int64_t B, double *__restrict__ S,
-                                                            float *__restrict__ f, double *__restrict__ edges)
+                                                            float *__restrict__ f, double *__restrict__ edges,
+                                                            int64_t lde)
 {
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (row >= B) return;
-    double ar = 0, ai = 0, qr = 0, qi = 0, gr = 0, gi = 0;
-    for (int s = 0; s < nseg; ++s) {
-        const double *p = part + static_cast<int64_t>(s) * 8 * ldb + row;
-        if (edges) {
-            double *e = edges + static_cast<int64_t>(s) * 4 * ldb + row;
-            e[0] = ar;
-            e[ldb] = ai;
-        }
-        const double vr = p[2 * ldb], vi = p[3 * ldb];
-        qr = fma(ar, vr, fma(-ai, vi, qr + p[4 * ldb]));
-        qi = fma(ar, vi, fma(ai, vr, qi + p[5 * ldb]));
-        ar += p[0];
-        ai += p[ldb];
-        gr += p[6 * ldb];
-        gi += p[7 * ldb];
+    const int lane = threadIdx.x & 63;
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (row >= B) return;  // a whole wave: no barriers below
+    const int m = (nseg + 63) / 64;
+    const int s0 = min(nseg, lane * m), s1 = min(nseg, s0 + m);
+    RTri t{0, 0, 0, 0, 0, 0, 0, 0};
+    for (int sg = s0; sg < s1; ++sg) {
+        const double *p = part + static_cast<int64_t>(sg) * 8 * ldb + row;
+        rtri_append(t, RTri{p[0], p[ldb], p[2 * ldb], p[3 * ldb], p[4 * ldb], p[5 * ldb], p[6 * ldb], p[7 * ldb]});
     }
     if (edges) {
-        double sr = 0, si = 0;
-        for (int s = nseg - 1; s >= 0; --s) {
-            double *e = edges + static_cast<int64_t>(s) * 4 * ldb + row;
-            e[2 * ldb] = sr;
-            e[3 * ldb] = si;
-            const double *p = part + static_cast<int64_t>(s) * 8 * ldb + row;
-            sr += p[2 * ldb];
-            si += p[3 * ldb];
+        double par = t.ar, pai = t.ai, sbr = t.br, sbi = t.bi;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double ur = __shfl_up(par, off), ui = __shfl_up(pai, off);
+            const double vr = __shfl_down(sbr, off), vi = __shfl_down(sbi, off);
+            if (lane >= off) {
+                par += ur;
+                pai += ui;
+            }
+            if (lane + off < 64) {
+                sbr += vr;
+                sbi += vi;
+            }
+        }
+        double ar = par - t.ar, ai = pai - t.ai;  // A before this lane's segments
+        for (int sg = s0; sg < s1; ++sg) {
+            const double *p = part + static_cast<int64_t>(sg) * 8 * ldb + row;
+            double *e = edges + static_cast<int64_t>(sg) * 4 * lde + row;
+            e[0] = ar;
+            e[lde] = ai;
+            ar += p[0];
+            ai += p[ldb];
+        }
+        double br = sbr - t.br, bi = sbi - t.bi;  // B after this lane's segments
+        for (int sg = s1 - 1; sg >= s0; --sg) {
+            const double *p = part + static_cast<int64_t>(sg) * 8 * ldb + row;
+            double *e = edges + static_cast<int64_t>(sg) * 4 * lde + row;
+            e[2 * lde] = br;
+            e[3 * lde] = bi;
+            br += p[2 * ldb];
+            bi += p[3 * ldb];
         }
     }
-    const double Sr = qr + gr, Si = qi + gi;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const RTri o = rtri_shfl_down(t, off);
+        if ((lane & (2 * off - 1)) == 0) rtri_append(t, o);
+    }
+    if (lane != 0) return;
+    const double Sr = t.qr + t.gr, Si = t.qi + t.gi;
     if (S) {
         S[2 * row] = Sr;
         S[2 * row + 1] = Si;
@@ -238,8 +263,8 @@ template <typename T, int M, int R, bool VEC>
 __global__ __launch_bounds__(256) void relax_bwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
                                                         int64_t n, const double4 *__restrict__ ph64,
                                                         const float4 *__restrict__ ph32,
-                                                        const double2 *__restrict__ c64, int nseg, int64_t ldb,
-                                                        const double *__restrict__ edges,
+                                                        const double2 *__restrict__ c64, int nseg,
+                                                        const double *__restrict__ edges, int64_t lde,
                                                         const double *__restrict__ S,
                                                         const float *__restrict__ grad_f,
                                                         float *__restrict__ grad_theta, int64_t ldg)
@@ -290,10 +315,10 @@ __global__ __launch_bounds__(256) void relax_bwd_kernel(const float *__restrict_
             swb[wave][1] = sbi;
         }
         __syncthreads();
-        const double *e = edges + static_cast<int64_t>(seg) * 4 * ldb + row;
+        const double *e = edges + static_cast<int64_t>(seg) * 4 * lde + row;
         // A before this lane's chunk, B after it
-        double Pr = e[0] + (par - alr), Pi = e[ldb] + (pai - ali);
-        double Rr = e[2 * ldb] + (sbr - blr), Ri = e[3 * ldb] + (sbi - bli);
+        double Pr = e[0] + (par - alr), Pi = e[lde] + (pai - ali);
+        double Rr = e[2 * lde] + (sbr - blr), Ri = e[3 * lde] + (sbi - bli);
         for (int w = 0; w < wave; ++w) {
             Pr += swa[w][0];
             Pi += swa[w][1];
@@ -355,13 +380,13 @@ static void launch_relax_fwd(const Design &d, const RelaxPlan &pl, bool vec, con
 
 template <typename T, int M>
 static void launch_relax_bwd(const Design &d, const RelaxPlan &pl, bool vec, const float *theta, int64_t B,
-                             int64_t ldt, int64_t ldb, const double *edges, const double *S, const float *grad_f,
+                             int64_t ldt, const double *edges, int64_t lde, const double *S, const float *grad_f,
                              float *grad_theta, int64_t ldg, hipStream_t s)
 {
     const unsigned blocks = static_cast<unsigned>(((B + pl.R - 1) / pl.R) * pl.nseg);
 #define QPM_RB(RR, V)                                                                                              \
-    relax_bwd_kernel<T, M, RR, V><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.ph32, d.c64, pl.nseg, ldb,    \
-                                                         edges, S, grad_f, grad_theta, ldg)
+    relax_bwd_kernel<T, M, RR, V><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.ph32, d.c64, pl.nseg, edges, \
+                                                         lde, S, grad_f, grad_theta, ldg)
     if (pl.R == 4) {
         if (vec) QPM_RB(4, true); else QPM_RB(4, false);
     } else {
@@ -481,8 +506,27 @@ static qpm_status check_relax(qpm_design d, qpm_prec p, const float *theta, int6
     return QPM_OK;
 }
 
+static qpm_status launch_combine(const double *part, int nseg, int64_t ldb, int64_t B, double *S, float *f,
+                                 double *edges, int64_t lde, hipStream_t s)
+{
+    relax_combine_kernel<<<static_cast<unsigned>((B + 3) / 4), 256, 0, s>>>(part, nseg, ldb, B, S, f, edges, lde);
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_relax_edges_size(qpm_design d, qpm_prec p, int64_t B, int64_t *count)
+{
+    clear_error();
+    QPM_REQUIRE(d != nullptr && count != nullptr, QPM_EINVAL, "design and count must not be NULL");
+    QPM_REQUIRE(p == QPM_PREC_F32 || p == QPM_PREC_F64, QPM_EINVAL, "unknown precision %d", (int)p);
+    QPM_REQUIRE(B >= 1 && B <= (int64_t(1) << 24), QPM_EINVAL, "batch must be in [1, 2^24] (got %lld)",
+                (long long)B);
+    *count = 4 * static_cast<int64_t>(plan_relax(d->n, B, p == QPM_PREC_F32).nseg) * B;
+    return QPM_OK;
+}
+
 QPM_API qpm_status qpm_relax_forward(qpm_design d, qpm_prec p, const float *theta, int64_t B, int64_t ldt,
-                                     float *f, double *S, qpm_stream sv)
+                                     float *f, double *S, double *edges, qpm_stream sv)
 {
     clear_error();
     qpm_status st = check_relax(d, p, theta, B, ldt);
@@ -496,22 +540,14 @@ QPM_API qpm_status qpm_relax_forward(qpm_design d, qpm_prec p, const float *thet
     double *part = nullptr;
     QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&part), sizeof(double) * 8 * pl.nseg * ldb, s));
     st = relax_partials(*d, p, theta, B, ldt, pl, ldb, part, s);
-    if (st == QPM_OK) {
-        relax_combine_kernel<<<static_cast<unsigned>((B + 255) / 256), 256, 0, s>>>(part, pl.nseg, ldb, B, S, f,
-                                                                                    nullptr);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) {
-            set_error("relax combine launch failed: %s", hipGetErrorString(e));
-            st = QPM_EHIP;
-        }
-    }
+    if (st == QPM_OK) st = launch_combine(part, pl.nseg, ldb, B, S, f, edges, B, s);
     (void)hipFreeAsync(part, s);
     return st;
 }
 
 QPM_API qpm_status qpm_relax_backward(qpm_design d, qpm_prec p, const float *theta, int64_t B, int64_t ldt,
-                                      const double *S, const float *grad_f, float *grad_theta, int64_t ldg,
-                                      qpm_stream sv)
+                                      const double *S, const double *edges, const float *grad_f, float *grad_theta,
+                                      int64_t ldg, qpm_stream sv)
 {
     clear_error();
     qpm_status st = check_relax(d, p, theta, B, ldt);
@@ -523,26 +559,32 @@ QPM_API qpm_status qpm_relax_backward(qpm_design d, qpm_prec p, const float *the
     const RelaxPlan pl = plan_relax(d->n, B, p == QPM_PREC_F32);
     QPM_REQUIRE(((B + pl.R - 1) / pl.R) * pl.nseg < (int64_t(1) << 31), QPM_ERANGE,
                 "batch x segments too large for one launch");
-    const int64_t ldb = ((B + 63) / 64) * 64;
-    double *part = nullptr, *edges = nullptr;
-    QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&part), sizeof(double) * 12 * pl.nseg * ldb, s));
-    edges = part + static_cast<int64_t>(8) * pl.nseg * ldb;
-    st = relax_partials(*d, p, theta, B, ldt, pl, ldb, part, s);
+    double *work = nullptr;
+    const double *e = edges;
+    int64_t lde = B;
+    if (!edges) {
+        // no saved edges: recompute the segment partials and their edges
+        const int64_t ldb = ((B + 63) / 64) * 64;
+        QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&work), sizeof(double) * 12 * pl.nseg * ldb, s));
+        double *ework = work + static_cast<int64_t>(8) * pl.nseg * ldb;
+        st = relax_partials(*d, p, theta, B, ldt, pl, ldb, work, s);
+        if (st == QPM_OK) st = launch_combine(work, pl.nseg, ldb, B, nullptr, nullptr, ework, ldb, s);
+        e = ework;
+        lde = ldb;
+    }
     if (st == QPM_OK) {
-        relax_combine_kernel<<<static_cast<unsigned>((B + 255) / 256), 256, 0, s>>>(part, pl.nseg, ldb, B, nullptr,
-                                                                                    nullptr, edges);
         const bool vec = (reinterpret_cast<uintptr_t>(theta) & 15u) == 0 && ldt % 4 == 0 &&
                          (reinterpret_cast<uintptr_t>(grad_theta) & 15u) == 0 && ldg % 4 == 0;
         if (p == QPM_PREC_F32)
-            launch_relax_bwd<float, 8>(*d, pl, vec, theta, B, ldt, ldb, edges, S, grad_f, grad_theta, ldg, s);
+            launch_relax_bwd<float, 8>(*d, pl, vec, theta, B, ldt, e, lde, S, grad_f, grad_theta, ldg, s);
         else
-            launch_relax_bwd<double, 4>(*d, pl, vec, theta, B, ldt, ldb, edges, S, grad_f, grad_theta, ldg, s);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) {
-            set_error("relax adjoint launch failed: %s", hipGetErrorString(e));
+            launch_relax_bwd<double, 4>(*d, pl, vec, theta, B, ldt, e, lde, S, grad_f, grad_theta, ldg, s);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) {
+            set_error("relax adjoint launch failed: %s", hipGetErrorString(err));
             st = QPM_EHIP;
         }
     }
-    (void)hipFreeAsync(part, s);
+    if (work) (void)hipFreeAsync(work, s);
     return st;
 }

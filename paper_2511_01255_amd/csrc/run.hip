@@ -59,6 +59,7 @@ struct qpm_run_s {
     uint32_t *pol_bits = nullptr;  // W x 64
     uint32_t *pol_acc = nullptr;
     double *pol_ws = nullptr;
+    double *pol_edges = nullptr;  // relaxation edges of the 3 rows (both precisions' sizes)
 
     bool f64() const { return cfg.prec == QPM_PREC_F64; }
     PopView view() const { return PopView{buf[0], buf[1], flags, buf[0], buf[1], cfg.np, D, ldx}; }
@@ -93,6 +94,7 @@ static void release(qpm_run_s *r)
     (void)hipFree(r->pol_bits);
     (void)hipFree(r->pol_acc);
     (void)hipFree(r->pol_ws);
+    (void)hipFree(r->pol_edges);
     for (auto &e : r->ev)
         if (e) (void)hipEventDestroy(e);
     if (r->st) (void)hipStreamDestroy(r->st);
@@ -552,6 +554,12 @@ QPM_API qpm_status qpm_run_polish(qpm_run_handle r, int32_t steps, float eta, in
         if (e == hipSuccess) e = hipMalloc(&r->pol_acc, sizeof(uint32_t));
         const size_t wsb = fitness_workspace_bytes(pl3, 64);
         if (e == hipSuccess && wsb) e = hipMalloc(&r->pol_ws, wsb);
+        int64_t ne = 0;
+        if (e == hipSuccess && qpm_relax_edges_size(static_cast<qpm_design>(const_cast<qpm_design_s *>(
+                                                        static_cast<const qpm_design_s *>(r->d))),
+                                                    p, 3, &ne) != QPM_OK)
+            e = hipErrorInvalidValue;
+        if (e == hipSuccess) e = hipMalloc(&r->pol_edges, sizeof(double) * ne);
         if (e == hipSuccess) e = hipMemsetAsync(r->pol, 0, sizeof(float) * 9 * ldx, r->st);
         static const float ones[3] = {1.0f, 1.0f, 1.0f};
         if (e == hipSuccess) e = hipMemcpyAsync(r->pol_f + 3, ones, sizeof(ones), hipMemcpyHostToDevice, r->st);
@@ -566,8 +574,9 @@ QPM_API qpm_status qpm_run_polish(qpm_run_handle r, int32_t steps, float eta, in
     const PopView pv = r->view();
     qpm_status st = launch_gather(pv, r->leaders, 3, theta, ldx, r->st);
     for (int32_t k = 0; k < steps && st == QPM_OK; ++k) {
-        st = qpm_relax_forward(dh, p, theta, 3, ldx, r->pol_f, r->pol_S, r->st);
-        if (st == QPM_OK) st = qpm_relax_backward(dh, p, theta, 3, ldx, r->pol_S, r->pol_f + 3, grad, ldx, r->st);
+        st = qpm_relax_forward(dh, p, theta, 3, ldx, r->pol_f, r->pol_S, r->pol_edges, r->st);
+        if (st == QPM_OK)
+            st = qpm_relax_backward(dh, p, theta, 3, ldx, r->pol_S, r->pol_edges, r->pol_f + 3, grad, ldx, r->st);
         if (st == QPM_OK) st = launch_polish_step(theta, grad, 3, D, ldx, eta, r->st);
     }
     if (st == QPM_OK) st = launch_polish_project(theta, y, 3, D, ldx, r->st);

@@ -62,8 +62,9 @@ _SIGS = {
     "qpm_de_step": (_I32, [_P, _I64, _I64, _I64, _F, _F, _U64, _U32, _U32, _P, _P, _I64, _P]),
     "qpm_de_step_shape": (_I32, [_P, _I64, _I64, _I64, _F, _F, _U64, _U32, _U32, _P, _P, _I64, _I32, _I32, _P]),
     "qpm_gwo_step": (_I32, [_P, _I64, _I64, _I64, _P, _F, _U64, _U32, _U32, _I32, _P, _P, _I64, _P]),
-    "qpm_relax_forward": (_I32, [_P, _I32, _P, _I64, _I64, _P, _P, _P]),
-    "qpm_relax_backward": (_I32, [_P, _I32, _P, _I64, _I64, _P, _P, _P, _I64, _P]),
+    "qpm_relax_forward": (_I32, [_P, _I32, _P, _I64, _I64, _P, _P, _P, _P]),
+    "qpm_relax_edges_size": (_I32, [_P, _I32, _I64, _P]),
+    "qpm_relax_backward": (_I32, [_P, _I32, _P, _I64, _I64, _P, _P, _P, _P, _I64, _P]),
     "qpm_run_create": (_I32, [_P, C.POINTER(RunConfig), _P, C.POINTER(_P)]),
     "qpm_run_advance": (_I32, [_P, _I64]),
     "qpm_run_read": (_I32, [_P, _P, _I64, _P, _P, _P]),
@@ -247,23 +248,32 @@ def gwo_step(x, D, leaders, a, seed, generation, inst=0, variant=0, stream=None)
     return y, yb
 
 
-def relax_forward(design, theta, prec=PREC_F32, stream=None):
-    """theta: float32 CUDA tensor (B, >= N) -> (f float32 (B,), S float64 (B, 2))."""
+def relax_forward(design, theta, prec=PREC_F32, stream=None, keep_edges=False):
+    """theta: float32 CUDA tensor (B, >= N) -> (f float32 (B,), S float64 (B, 2)),
+    and with keep_edges the segment edges for relax_backward as a third value."""
     import torch
     B, ldt = theta.shape
     f = torch.empty(B, dtype=torch.float32, device=theta.device)
     S = torch.empty((B, 2), dtype=torch.float64, device=theta.device)
-    _check(lib().qpm_relax_forward(design.handle, prec, _ptr(theta), B, ldt, _ptr(f), _ptr(S), _stream(stream)))
-    return f, S
+    E = None
+    if keep_edges:
+        n = C.c_int64()
+        _check(lib().qpm_relax_edges_size(design.handle, prec, B, C.byref(n)))
+        E = torch.empty(n.value, dtype=torch.float64, device=theta.device)
+    _check(lib().qpm_relax_forward(design.handle, prec, _ptr(theta), B, ldt, _ptr(f), _ptr(S),
+                                   _ptr(E) if E is not None else None, _stream(stream)))
+    return (f, S, E) if keep_edges else (f, S)
 
 
-def relax_backward(design, theta, S, grad_f, prec=PREC_F32, stream=None):
-    """-> grad_theta float32 (B, ldt) (entries past N are left 0)."""
+def relax_backward(design, theta, S, grad_f, prec=PREC_F32, stream=None, edges=None):
+    """-> grad_theta float32 (B, ldt) (entries past N are 0). edges: from
+    relax_forward(..., keep_edges=True) on the same theta, or None."""
     import torch
     B, ldt = theta.shape
-    g = torch.zeros_like(theta)
+    g = torch.empty_like(theta) if ldt == design.n else torch.zeros_like(theta)
     gf = grad_f.to(torch.float32).contiguous()
-    _check(lib().qpm_relax_backward(design.handle, prec, _ptr(theta), B, ldt, _ptr(S), _ptr(gf), _ptr(g), ldt,
+    _check(lib().qpm_relax_backward(design.handle, prec, _ptr(theta), B, ldt, _ptr(S),
+                                    _ptr(edges) if edges is not None else None, _ptr(gf), _ptr(g), ldt,
                                     _stream(stream)))
     return g
 
@@ -277,16 +287,16 @@ def _relax_function():
         @staticmethod
         def forward(ctx, theta, design, prec=PREC_F32):
             theta = theta.contiguous()
-            f, S = relax_forward(design, theta, prec)
-            ctx.save_for_backward(theta, S)
+            f, S, E = relax_forward(design, theta, prec, keep_edges=True)
+            ctx.save_for_backward(theta, S, E)
             ctx.design = design
             ctx.prec = prec
             return f
 
         @staticmethod
         def backward(ctx, grad_f):
-            theta, S = ctx.saved_tensors
-            g = relax_backward(ctx.design, theta, S, grad_f, ctx.prec)
+            theta, S, E = ctx.saved_tensors
+            g = relax_backward(ctx.design, theta, S, grad_f, ctx.prec, edges=E)
             return g, None, None
 
     return QpmRelax

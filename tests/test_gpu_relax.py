@@ -92,6 +92,23 @@ def test_relax_gradient_vs_finite_differences_full_size(q, orc, prec):
     assert np.max(np.abs(f[:8].double().cpu().numpy() - fo) / fo) <= (1e-6 if prec == 1 else 1e-5)
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+def test_relax_saved_edges_equal_recomputed(q, prec):
+    # the adjoint from the forward call's saved edges is bit-identical to
+    # the adjoint that recomputes them (ragged B and N, unaligned ldt)
+    for B, n, ldt in ((5, 4099, 4099), (67, 2048, 2052), (1, 3, 3)):
+        D = q.precompute_phases(inputs.jittered_boundaries(n, 2.0, 0.3, seed=n), DK1, DK2)
+        th = _t(np.pad(inputs.relax_theta(B, n, seed=B), ((0, 0), (0, ldt - n))))
+        f1, S1, E = q.relax_forward(D, th, prec, keep_edges=True)
+        f2, S2 = q.relax_forward(D, th, prec)
+        assert np.array_equal(f1.cpu().numpy(), f2.cpu().numpy()) and np.array_equal(S1.cpu().numpy(), S2.cpu().numpy())
+        gf = _t(np.linspace(0.5, 1.5, B))
+        g1 = q.relax_backward(D, th, S1, gf, prec, edges=E).cpu().numpy()
+        g2 = q.relax_backward(D, th, S1, gf, prec).cpu().numpy()
+        assert np.array_equal(g1, g2)
+        assert not np.any(g1[:, n:])
+
+
 def test_relax_autograd_function(q):
     import torch
     n, B = 777, 9
