@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(int mode, const doubl
                                                            uint32_t *__restrict__ flags, int32_t *__restrict__ leaders,
                                                            int4 *__restrict__ draws, uint32_t *__restrict__ gen,
                                                            uint32_t k0, uint32_t k1, uint32_t inst0,
-                                                           uint32_t *__restrict__ ticket)
+                                                           uint32_t *__restrict__ ticket, uint32_t *__restrict__ fbits)
 {
     const int b = blockIdx.x;
     const InstDesc id = inst[b];
@@ -161,7 +161,12 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(int mode, const doubl
         L1 = Lb[1];
         L2 = Lb[2];
     }
-    for (int64_t i = threadIdx.x; i < np; i += 256) {
+    const int64_t fw = (np + 31) / 32;  // packed flag words per instance
+    for (int64_t base = 0; base < np; base += 256) {
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < np;
+        uint32_t fl = 0;
+        if (valid) {
         const double *p = part + static_cast<int64_t>(s0) * 6 * ld + i;
         double ar = p[0], ai = p[ld], qr = p[4 * ld], qi = p[5 * ld];
         for (int sg = s0 + 1; sg < s1; ++sg) {
@@ -178,14 +183,26 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(int mode, const doubl
             fb[i] = v;
         } else {
             const bool skip = (mode == 3) && (i == L0 || i == L1 || i == L2);
+            fl = flb[i];
             if (!skip && v > fb[i]) {
                 fb[i] = v;
-                flb[i] ^= 1u;
+                fl ^= 1u;
+                flb[i] = fl;
             }
         }
         if (mode == 1 || mode == 3)
             draws[static_cast<int64_t>(b) * np + i] =
                 de_draw(i, np, id.n, mode == 3 ? g + 1u : g, inst0 + static_cast<uint32_t>(b), k0, k1);
+        }
+        // the packed copy of this wave's 64 flags (words (base + 64 w) / 32 and + 1)
+        if (mode >= 2 && fbits) {
+            const uint64_t m = __ballot(fl != 0u);
+            const int64_t w0 = (base + 64 * (threadIdx.x >> 6)) / 32;
+            if ((threadIdx.x & 63) == 0) {
+                if (w0 < fw) fbits[b * fw + w0] = static_cast<uint32_t>(m);
+                if (w0 + 1 < fw) fbits[b * fw + w0 + 1] = static_cast<uint32_t>(m >> 32);
+            }
+        }
     }
     if (mode == 1 || mode == 2) {
         __syncthreads();
@@ -245,12 +262,16 @@ __global__ __launch_bounds__(256) void batch_init_kernel(int64_t np, const InstD
 // DE: tiles (instance, chunk of CW = 256 / IPW genes) dealt round-robin to
 // the XCDs (workgroup id mod 8); a workgroup covers 4 IPW consecutive
 // individuals of one tile.
+// Each row's buffer flag comes from the instance's packed flags (np / 32
+// words, np <= 4096), copied to LDS first, instead of a dependent global
+// load after the draw.
 template <int IPW>
 __global__ __launch_bounds__(256) void batch_de_kernel(BatchPop bp, const InstDesc *__restrict__ inst,
                                                        const Tile *__restrict__ tiles, int ntiles, int groups,
-                                                       const int4 *__restrict__ draws, float F, uint32_t cr_max, uint32_t k0,
-                                                       uint32_t k1, const uint32_t *__restrict__ gen, uint32_t inst0,
-                                                       uint32_t *__restrict__ bits, int64_t ld)
+                                                       const int4 *__restrict__ draws, float F, uint32_t cr_max,
+                                                       uint32_t k0, uint32_t k1, const uint32_t *__restrict__ gen,
+                                                       uint32_t inst0, uint32_t *__restrict__ bits, int64_t ld,
+                                                       const uint32_t *__restrict__ fbits)
 {
     constexpr int LPI = 64 / IPW;
     constexpr int CW = 4 * LPI;
@@ -274,15 +295,24 @@ __global__ __launch_bounds__(256) void batch_de_kernel(BatchPop bp, const InstDe
     const uint32_t g = gen[0];
     const uint32_t instb = inst0 + static_cast<uint32_t>(tl.inst);
     __shared__ uint32_t wsh[IPG][WPC];
+    __shared__ uint32_t sfb[128];
+    const int4 dr = draws[static_cast<int64_t>(tl.inst) * np + (i < np ? i : np - 1)];
+    const int fw = static_cast<int>((np + 31) / 32);
+    if (t < fw) sfb[t] = fbits[static_cast<int64_t>(tl.inst) * fw + t];
+    __syncthreads();
+    auto src = [&](int64_t r) -> const float * {
+        const bool second = ((sfb[r >> 5] >> (r & 31)) & 1u) != 0u;
+        return (second ? pv.x1 : pv.x0) + r * pv.ldx;
+    };
     uint32_t nib = 0;
     if (active) {
-        const int4 dr = draws[static_cast<int64_t>(tl.inst) * np + i];
-        const float4 xv = *reinterpret_cast<const float4 *>(row_of(pv, i) + j0);
-        const float4 a = *reinterpret_cast<const float4 *>(row_of(pv, dr.x) + j0);
-        const float4 bq = *reinterpret_cast<const float4 *>(row_of(pv, dr.y) + j0);
-        const float4 cq = *reinterpret_cast<const float4 *>(row_of(pv, dr.z) + j0);
+        const float4 xv = *reinterpret_cast<const float4 *>(src(i) + j0);
+        const float4 a = *reinterpret_cast<const float4 *>(src(dr.x) + j0);
+        const float4 bq = *reinterpret_cast<const float4 *>(src(dr.y) + j0);
+        const float4 cq = *reinterpret_cast<const float4 *>(src(dr.z) + j0);
         const float4 uv = de_quad(xv, a, bq, cq, j0, dr.w, static_cast<uint32_t>(i), g, instb, k0, k1, F, cr_max);
-        store_quad_nt(out_row_of(pv, i), j0, D, uv);
+        const bool second = ((sfb[i >> 5] >> (i & 31)) & 1u) != 0u;
+        store_quad_nt((second ? pv.out0 : pv.out1) + i * pv.ldx, j0, D, uv);
         nib = quad_nibble(uv, j0, D);
     }
     uint32_t w = nib << (4 * (t & 7));
@@ -598,7 +628,8 @@ static qpm_status upload_fit_plan(const BatchFitPlan &pl, int64_t ld, hipStream_
 {
     FitPlanDev d;
     hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&d.segs), sizeof(FitSeg) * pl.segs.size(), s);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void **>(&d.slot_ofs), sizeof(int) * pl.slot_ofs.size(), s);
+    if (e == hipSuccess)
+        e = hipMallocAsync(reinterpret_cast<void **>(&d.slot_ofs), sizeof(int) * pl.slot_ofs.size(), s);
     if (e == hipSuccess)
         e = hipMallocAsync(reinterpret_cast<void **>(&d.part), sizeof(double) * 6 * pl.segs.size() * ld, s);
     if (e == hipSuccess)
@@ -627,17 +658,18 @@ static void free_fit_plan(FitPlanDev &d, hipStream_t s)
 
 static qpm_status launch_batch_finish(int mode, const qpm_batch_s &bt, qpm_prec p, const FitPlanDev &fp, int64_t ld,
                                       int64_t np, void *f, uint32_t *flags, int32_t *leaders, int4 *draws,
-                                      uint32_t *gen, uint64_t seed, uint32_t inst0, uint32_t *ticket, hipStream_t s)
+                                      uint32_t *gen, uint64_t seed, uint32_t inst0, uint32_t *ticket, hipStream_t s,
+                                      uint32_t *fbits = nullptr)
 {
     const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
     if (p == QPM_PREC_F64)
         batch_finish_kernel<double><<<bt.n_inst, 256, 0, s>>>(mode, fp.part, fp.slot_ofs, ld, np, bt.dev,
                                                              static_cast<double *>(f), flags, leaders, draws, gen, k0,
-                                                             k1, inst0, ticket);
+                                                             k1, inst0, ticket, fbits);
     else
         batch_finish_kernel<float><<<bt.n_inst, 256, 0, s>>>(mode, fp.part, fp.slot_ofs, ld, np, bt.dev,
                                                             static_cast<float *>(f), flags, leaders, draws, gen, k0,
-                                                            k1, inst0, ticket);
+                                                            k1, inst0, ticket, fbits);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }
@@ -713,6 +745,7 @@ struct qpm_batch_run_s {
     int64_t ld = 0;
     float *buf[2] = {nullptr, nullptr};
     uint32_t *flags = nullptr;
+    uint32_t *fbits = nullptr;  // flags packed one bit per individual, ceil(np / 32) words per instance
     void *f_cur = nullptr;
     uint32_t *bits = nullptr;
     int32_t *leaders = nullptr;
@@ -748,6 +781,7 @@ static void release_batch_run(qpm_batch_run_s *r)
     if (r->graph) (void)hipGraphDestroy(r->graph);
     (void)hipFree(r->buf[0]);
     (void)hipFree(r->buf[1]);
+    (void)hipFree(r->fbits);
     (void)hipFree(r->flags);
     (void)hipFree(r->f_cur);
     (void)hipFree(r->bits);
@@ -778,7 +812,8 @@ static qpm_status launch_batch_de(qpm_batch_run_s *r)
     const BatchPop bp = r->pop();
 #define QPM_BDE(IPW)                                                                                          \
     batch_de_kernel<IPW><<<nb, 256, 0, r->st>>>(bp, r->inst, r->dtiles, r->n_dtiles, r->de_groups, r->draws, \
-                                                c.F, cr_threshold(c.CR), k0, k1, r->gen, c.inst, r->bits, r->ld)
+                                                c.F, cr_threshold(c.CR), k0, k1, r->gen, c.inst, r->bits, r->ld,  \
+                                                r->fbits)
     if (r->de_ipw == 1)
         QPM_BDE(1);
     else if (r->de_ipw == 2)
@@ -818,12 +853,13 @@ static qpm_status batch_generation(qpm_batch_run_s *r, hipEvent_t *ev = nullptr)
     QPM_STEP(QPM_K_FIT_DE, launch_batch_fit(*r->bt, p, r->bits, c.np, r->ld, r->fplan, r->fdev.segs, r->fdev.part,
                                             r->st))
     QPM_STEP(QPM_K_FINISH_DE, launch_batch_finish(2, *r->bt, p, r->fdev, r->ld, c.np, r->f_cur, r->flags, r->leaders,
-                                                  r->draws, r->gen, c.seed, c.inst, r->ticket, r->st))
+                                                  r->draws, r->gen, c.seed, c.inst, r->ticket, r->st, r->fbits))
     QPM_STEP(QPM_K_GWO, launch_batch_gwo(r))
     QPM_STEP(QPM_K_FIT_GWO, launch_batch_fit(*r->bt, p, r->bits, c.np, r->ld, r->fplan, r->fdev.segs, r->fdev.part,
                                              r->st))
     QPM_STEP(QPM_K_FINISH_GWO, launch_batch_finish(3, *r->bt, p, r->fdev, r->ld, c.np, r->f_cur, r->flags,
-                                                   r->leaders, r->draws, r->gen, c.seed, c.inst, r->ticket, r->st))
+                                                   r->leaders, r->draws, r->gen, c.seed, c.inst, r->ticket, r->st,
+                                                   r->fbits))
 #undef QPM_STEP
     return mark(QPM_K_COUNT);
 }
@@ -935,6 +971,7 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
     if (e == hipSuccess) e = hipMalloc(&r->buf[0], gene_bytes);
     if (e == hipSuccess) e = hipMalloc(&r->buf[1], gene_bytes);
     if (e == hipSuccess) e = hipMalloc(&r->flags, sizeof(uint32_t) * n_inst * c.np);
+    if (e == hipSuccess) e = hipMalloc(&r->fbits, sizeof(uint32_t) * n_inst * ((c.np + 31) / 32));
     if (e == hipSuccess) e = hipMalloc(&r->f_cur, (r->f64() ? 8 : 4) * n_inst * c.np);
     if (e == hipSuccess) e = hipMalloc(&r->bits, sizeof(uint32_t) * b->total_words * r->ld);
     if (e == hipSuccess) e = hipMalloc(&r->leaders, sizeof(int32_t) * 3 * n_inst);
@@ -957,11 +994,15 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
     e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(ev, static_cast<hipStream_t>(sv));
     if (e == hipSuccess) e = hipStreamWaitEvent(r->st, ev, 0);
-    if (e == hipSuccess) e = hipMemcpyAsync(r->a_tab, a.data(), sizeof(float) * c.generations, hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r->a_tab, a.data(), sizeof(float) * c.generations, hipMemcpyHostToDevice, r->st);
     if (e == hipSuccess) e = hipMemcpyAsync(r->inst, h.data(), sizeof(InstDesc) * n_inst, hipMemcpyHostToDevice, r->st);
-    if (e == hipSuccess) e = hipMemcpyAsync(r->gtiles, gt.data(), sizeof(Tile) * gt.size(), hipMemcpyHostToDevice, r->st);
-    if (e == hipSuccess) e = hipMemcpyAsync(r->dtiles, dt.data(), sizeof(Tile) * dt.size(), hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r->gtiles, gt.data(), sizeof(Tile) * gt.size(), hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r->dtiles, dt.data(), sizeof(Tile) * dt.size(), hipMemcpyHostToDevice, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->flags, 0, sizeof(uint32_t) * n_inst * c.np, r->st);
+    if (e == hipSuccess) e = hipMemsetAsync(r->fbits, 0, sizeof(uint32_t) * n_inst * ((c.np + 31) / 32), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->gen, 0, sizeof(uint32_t), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->ticket, 0, sizeof(uint32_t), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->bits, 0, sizeof(uint32_t) * b->total_words * r->ld, r->st);

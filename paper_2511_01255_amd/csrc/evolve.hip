@@ -316,8 +316,8 @@ qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const 
                                                                                    gen, inst, draws);
     // individuals per wave so that one chunk of the population fits in 2 MB
     const int64_t row_bytes = 2 * 1024 * 1024 / pv.np;
-    const int ipw = (ipw_req == 1 || ipw_req == 2 || ipw_req == 4) ? ipw_req
-                                                                   : (row_bytes >= 1024 ? 1 : (row_bytes >= 512 ? 2 : 4));
+    const int ipw_auto = row_bytes >= 1024 ? 1 : (row_bytes >= 512 ? 2 : 4);
+    const int ipw = (ipw_req == 1 || ipw_req == 2 || ipw_req == 4) ? ipw_req : ipw_auto;
     const int R = (passes == 2 || passes == 4) ? passes : 1;
     const int64_t cw = 256 / ipw;
     const int64_t chunks = (pv.D + cw - 1) / cw;

@@ -212,8 +212,9 @@ static qpm_status tune_run(qpm_run_s *r)
             float best = 1e30f;
             for (const auto &pl : cands) {
                 float ms = 0.0f;
-                st = time_min([&]() { return launch_fitness(*r->d, p, r->tbits, c.np, r->ld, r->f_new, pl, part, r->st); },
-                              &ms);
+                st = time_min(
+                    [&]() { return launch_fitness(*r->d, p, r->tbits, c.np, r->ld, r->f_new, pl, part, r->st); },
+                    &ms);
                 if (st != QPM_OK) break;
                 if (ms < best) {
                     best = ms;
@@ -243,8 +244,9 @@ static qpm_status tune_run(qpm_run_s *r)
             float best = 1e30f;
             for (const auto &pl : cands) {
                 float ms = 0.0f;
-                st = time_min([&]() { return launch_fitness(*r->d, p, r->tbits, c.np, r->ld, r->f_new, pl, part, r->st); },
-                              &ms);
+                st = time_min(
+                    [&]() { return launch_fitness(*r->d, p, r->tbits, c.np, r->ld, r->f_new, pl, part, r->st); },
+                    &ms);
                 if (st != QPM_OK) break;
                 if (ms < best) {
                     best = ms;
@@ -354,7 +356,8 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(ev, static_cast<hipStream_t>(sv));
     if (e == hipSuccess) e = hipStreamWaitEvent(r->st, ev, 0);
-    if (e == hipSuccess) e = hipMemcpyAsync(r->a_tab, a.data(), sizeof(float) * c.generations, hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r->a_tab, a.data(), sizeof(float) * c.generations, hipMemcpyHostToDevice, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->flags, 0, sizeof(uint32_t) * c.np, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->fbits, 0, sizeof(uint32_t) * 2 * ((c.np + 63) / 64), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->gen, 0, sizeof(uint32_t), r->st);
