@@ -108,7 +108,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--prec", choices=["f32", "f64"], default="f32")
-    ap.add_argument("--cpu-generations", type=int, default=6,
+    ap.add_argument("--cpu-generations", type=int, default=30,
                     help="generations of the CPU oracle sample (0 = skip)")
     ap.add_argument("--no-extras", action="store_true", help="only the timed generations")
     ap.add_argument("--calib-copy", action="store_true",
