@@ -305,8 +305,41 @@ def main():
         out["relaxation"] = rel
         log("[bench] relaxation fwd+adjoint: %s" % rel)
 
+    if not args.no_extras:
+        # a run shaped like the paper's timing table (N = 6600 domains of
+        # 0.1 um, L = 660 um, NP = 5000, G = 1000), with this workload's dk:
+        # seconds for the whole run, next to the paper's RTX 4070 figure
+        # (22.5 s, a different GPU and dk; context only)
+        zp = inputs.uniform_boundaries(6600, 0.1)
+        Dp = qpm.precompute_phases(zp, inputs.DK1, inputs.DK2)
+        Rp = qpm.Run(Dp, 5000, 1000, F=F, CR=CR, seed=0, prec=prec, tune=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Rp.advance(1000)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        Rp.destroy()
+        out["paper_shaped_run"] = {"N": 6600, "NP": 5000, "generations": 1000, "seconds": tp,
+                                   "paper_rtx4070_seconds_context": 22.5}
+        log("[bench] paper-shaped run (N=6600, NP=5000, G=1000): %.3f s" % tp)
+
     if args.cpu_generations > 0:
         import oracle as orc
+        # fitness error of the GPU kernels against the oracle on the
+        # benchmark population (max relative error per genome class)
+        Of = orc.Design(z, inputs.DK1, inputs.DK2)
+        _, fo = Of.fitness(d)
+        floor = 1e-2 * np.median(fo)
+        errs = {}
+        for name, p_, k_ in (("f32_table", qpm.PREC_F32, qpm.FIT_TABLE),
+                             ("f32_segmented", qpm.PREC_F32, qpm.FIT_SEGMENTED),
+                             ("f64_table", qpm.PREC_F64, qpm.FIT_TABLE),
+                             ("f64_segmented", qpm.PREC_F64, qpm.FIT_SEGMENTED)):
+            fg = qpm.eval_fitness(design, bits, NP, prec=p_, kernel=k_).double().cpu().numpy()
+            rel = np.abs(fg - fo) / np.maximum(fo, floor)
+            errs[name] = {"random_max_rel": float(rel[:NP - 32].max()), "periodic_max_rel": float(rel[NP - 32:].max())}
+        out["fitness_error_vs_oracle"] = errs
+        log("[bench] fitness error vs oracle: %s" % errs)
         log("[bench] CPU oracle: %d generations" % args.cpu_generations)
         O = orc.Design(z, inputs.DK1, inputs.DK2)
         x = (mag * d.astype(np.float32)).astype(np.float32)
