@@ -259,6 +259,28 @@ def test_run_fp64_trajectory_is_exact(q, orc):
     R.destroy()
 
 
+@pytest.mark.parametrize("case", [
+    # (N, NP, G, GWO variant, instance, fitness kernel)
+    (1, 4, 12, 0, 0, 0),        # one domain: every genome ties, nothing is accepted
+    (33, 65, 30, 1, 3, 0),      # ragged words and population, mean GWO variant
+    (1007, 130, 20, 0, 7, 1),   # per-domain segmented fitness
+    (2049, 70, 12, 1, 0, 2),    # the per-individual FP64 kernel
+    (300, 4, 40, 0, 1, 3),      # the smallest population
+], ids=lambda c: "n%d_np%d_g%d_v%d_i%d_k%d" % c)
+def test_run_fp64_trajectory_edge_cases(q, orc, case):
+    n, npop, G, variant, inst, kernel = case
+    z = inputs.jittered_boundaries(n, 2.0, 0.25, seed=n)
+    D = q.precompute_phases(z, DK1, DK2)
+    R = q.Run(D, npop, G, F=0.5, CR=0.9, seed=11, inst=inst, prec=1, gwo_variant=variant, fit_kernel=kernel)
+    R.advance(G)
+    x, f, _, g = R.read()
+    xo, fo, _ = orc.Design(z, DK1, DK2).hwsda_run(npop, G, 0.5, 0.9, 11, inst=inst, variant=variant)
+    assert g == G
+    assert np.array_equal(x.cpu().numpy(), xo)
+    assert np.max(np.abs(f.cpu().numpy() - fo) / np.maximum(fo, 1e-300)) <= 1e-12
+    R.destroy()
+
+
 def test_run_graph_and_eager_agree(q):
     n, npop, G = 300, 20, 15
     D = q.precompute_phases(inputs.uniform_boundaries(n, 2.0), DK1, DK2)
