@@ -24,6 +24,67 @@ namespace qpm {
 // last workgroup acquires (invalidates its L2) before reading the others'
 // results. The last workgroup resets the ticket, so the kernel can be
 // replayed from a graph.
+// Selection for the 64 genomes of group grp (i = 64 grp + lane), from their
+// combined triple t; called by one whole wave. Writes f_cur, flags, the
+// group's two packed flag words, the DE draws of generation gen + 1 (with
+// draws_next) and the group's three best (with cand_v).
+template <typename T>
+__device__ __forceinline__ void select_group(const Tri &t, int64_t grp, int lane, int64_t np,
+                                             const double *__restrict__ C, T *__restrict__ f_cur,
+                                             uint32_t *__restrict__ flags, uint32_t *__restrict__ fbits,
+                                             const int32_t *__restrict__ skip3, T *__restrict__ cand_v,
+                                             int32_t *__restrict__ cand_i, int4 *__restrict__ draws_next,
+                                             const uint32_t *__restrict__ gen, int64_t D, uint32_t k0, uint32_t k1,
+                                             uint32_t inst)
+{
+    const int64_t i = grp * 64 + lane;
+    const bool valid = i < np;
+    uint32_t fl = 0;
+    T fv = static_cast<T>(-INFINITY);
+    if (valid) {
+        const double sr = t.qr + C[0], si = t.qi + C[1];
+        const T v = static_cast<T>(fma(sr, sr, si * si));
+        const bool skip = skip3 != nullptr && (i == skip3[0] || i == skip3[1] || i == skip3[2]);
+        fl = flags[i];
+        fv = f_cur[i];
+        if (!skip && v > fv) {
+            fv = v;
+            f_cur[i] = v;
+            fl ^= 1u;
+            flags[i] = fl;
+        }
+        if (draws_next) draws_next[i] = de_draw(i, np, D, gen[0] + 1u, inst, k0, k1);
+    }
+    const uint64_t m = __ballot(fl != 0u);
+    if (fbits != nullptr && lane == 0) {
+        fbits[2 * grp] = static_cast<uint32_t>(m);
+        fbits[2 * grp + 1] = static_cast<uint32_t>(m >> 32);
+    }
+    if (cand_v) {
+        Top3<T> tp = top3_empty<T>();
+        tp.v[0] = fv;
+        tp.i[0] = valid ? static_cast<int>(i) : INT_MAX;
+        wave_top3(tp);
+        if (lane < 3) {
+            cand_v[3 * grp + lane] = lane == 0 ? tp.v[0] : (lane == 1 ? tp.v[1] : tp.v[2]);
+            cand_i[3 * grp + lane] = lane == 0 ? tp.i[0] : (lane == 1 ? tp.i[1] : tp.i[2]);
+        }
+    }
+}
+
+// Workgroup = 4 waves over 64 consecutive individuals (lane = individual):
+// the waves fold the segment triples (combine_segments), wave 0 selects,
+// keeps the packed copy of the buffer flags (bit i % 32 of word i / 32)
+// that the DE kernel stages in LDS, and, when leaders are wanted, leaves
+// its own three best in cand (3 per workgroup), so the last workgroup
+// merges 3 candidates per workgroup instead of rereading every fitness
+// value.
+//
+// Cross-workgroup ordering: one wave per workgroup releases (agent-scope
+// fence, which writes back the XCD's L2) before taking a ticket; only the
+// last workgroup acquires (invalidates its L2) before reading the others'
+// results. The last workgroup resets the ticket, so the kernel can be
+// replayed from a graph.
 template <typename T>
 __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ part, int gy, int64_t ld, int64_t np,
                                                      const double *__restrict__ C, T *__restrict__ f_cur,
@@ -36,41 +97,10 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ 
 {
     const int lane = threadIdx.x & 63;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + lane;
-    const bool valid = i < np;
-    const Tri t = combine_segments<4>(part, gy, ld, i, valid);
-    if (threadIdx.x < 64) {
-        uint32_t fl = 0;
-        T fv = static_cast<T>(-INFINITY);
-        if (valid) {
-            const double sr = t.qr + C[0], si = t.qi + C[1];
-            const T v = static_cast<T>(fma(sr, sr, si * si));
-            const bool skip = skip3 != nullptr && (i == skip3[0] || i == skip3[1] || i == skip3[2]);
-            fl = flags[i];
-            fv = f_cur[i];
-            if (!skip && v > fv) {
-                fv = v;
-                f_cur[i] = v;
-                fl ^= 1u;
-                flags[i] = fl;
-            }
-            if (draws_next) draws_next[i] = de_draw(i, np, D, gen[0] + 1u, inst, k0, k1);
-        }
-        const uint64_t m = __ballot(fl != 0u);
-        if (fbits != nullptr && lane == 0) {
-            fbits[2 * blockIdx.x] = static_cast<uint32_t>(m);
-            fbits[2 * blockIdx.x + 1] = static_cast<uint32_t>(m >> 32);
-        }
-        if (top3_out) {
-            Top3<T> tp = top3_empty<T>();
-            tp.v[0] = fv;
-            tp.i[0] = valid ? static_cast<int>(i) : INT_MAX;
-            wave_top3(tp);
-            if (lane < 3) {
-                cand_v[3 * blockIdx.x + lane] = lane == 0 ? tp.v[0] : (lane == 1 ? tp.v[1] : tp.v[2]);
-                cand_i[3 * blockIdx.x + lane] = lane == 0 ? tp.i[0] : (lane == 1 ? tp.i[1] : tp.i[2]);
-            }
-        }
-    }
+    const Tri t = combine_segments<4>(part, gy, ld, i, i < np);
+    if (threadIdx.x < 64)
+        select_group<T>(t, blockIdx.x, lane, np, C, f_cur, flags, fbits, skip3, top3_out ? cand_v : nullptr,
+                        cand_i, draws_next, gen, D, k0, k1, inst);
     __shared__ int s_last;
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -50,10 +50,9 @@ __device__ __forceinline__ void tri_append(Tri &t, const Tri &u)
 // the same bits whichever kernel combines it. Call from every lane (the
 // workgroup synchronises); the result is valid in wave 0.
 template <int NW>
-__device__ __forceinline__ Tri combine_segments(const double *__restrict__ part, int gy, int64_t ld, int64_t i,
-                                                bool valid)
+__device__ __forceinline__ Tri combine_segments_in(const double *__restrict__ part, int gy, int64_t ld, int64_t i,
+                                                   bool valid, int wave, int lane, double *sh)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int s0 = static_cast<int>((static_cast<int64_t>(gy) * wave) / NW);
     const int s1 = static_cast<int>((static_cast<int64_t>(gy) * (wave + 1)) / NW);
     Tri t{0, 0, 0, 0, 0, 0};
@@ -67,25 +66,36 @@ __device__ __forceinline__ Tri combine_segments(const double *__restrict__ part,
         }
     }
     if constexpr (NW > 1) {
-        __shared__ double sh[6][NW][64];
-        sh[0][wave][lane] = t.ar;
-        sh[1][wave][lane] = t.ai;
-        sh[2][wave][lane] = t.br;
-        sh[3][wave][lane] = t.bi;
-        sh[4][wave][lane] = t.qr;
-        sh[5][wave][lane] = t.qi;
+        // sh: [6][NW][64] doubles of this group
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const double v = c == 0 ? t.ar : c == 1 ? t.ai : c == 2 ? t.br : c == 3 ? t.bi : c == 4 ? t.qr : t.qi;
+            sh[(c * NW + wave) * 64 + lane] = v;
+        }
         __syncthreads();
         if (wave == 0) {
             for (int w = 1; w < NW; ++w) {
                 const int a = static_cast<int>((static_cast<int64_t>(gy) * w) / NW);
                 const int b = static_cast<int>((static_cast<int64_t>(gy) * (w + 1)) / NW);
                 if (a < b)
-                    tri_append(t, Tri{sh[0][w][lane], sh[1][w][lane], sh[2][w][lane], sh[3][w][lane],
-                                      sh[4][w][lane], sh[5][w][lane]});
+                    tri_append(t, Tri{sh[(0 * NW + w) * 64 + lane], sh[(1 * NW + w) * 64 + lane],
+                                      sh[(2 * NW + w) * 64 + lane], sh[(3 * NW + w) * 64 + lane],
+                                      sh[(4 * NW + w) * 64 + lane], sh[(5 * NW + w) * 64 + lane]});
             }
         }
     }
     return t;
+}
+
+// combine_segments_in for a workgroup of NW waves over one group of 64
+// genomes (wave = threadIdx.x / 64)
+template <int NW>
+__device__ __forceinline__ Tri combine_segments(const double *__restrict__ part, int gy, int64_t ld, int64_t i,
+                                                bool valid)
+{
+    __shared__ double sh[6 * NW * 64];
+    return combine_segments_in<NW>(part, gy, ld, i, valid, static_cast<int>(threadIdx.x >> 6),
+                                   static_cast<int>(threadIdx.x & 63), sh);
 }
 
 __device__ __forceinline__ void store_fitness(void *fit, int out_f64, int64_t i, const Tri &t,
