@@ -95,7 +95,7 @@ qpm_status launch_fitness_partials(const Design &d, qpm_prec p, const uint32_t *
 qpm_status launch_finish(const double *part, int gy, int64_t ld, int64_t np, const double *C, void *f_cur,
                          bool f64, uint32_t *flags, uint32_t *fbits, const int32_t *skip3, int32_t *top3_out,
                          void *cand, int4 *draws_next, uint32_t *gen, int64_t D, uint64_t seed, uint32_t inst,
-                         uint32_t *ticket, hipStream_t s);
+                         hipStream_t s);
 inline size_t finish_cand_bytes(int64_t np)
 {
     return static_cast<size_t>((np + 63) / 64) * 3 * (sizeof(double) + sizeof(int32_t));

@@ -1,29 +1,15 @@
-// generation.hip -- the fused end of each evaluation in a run: combine the
+// generation.hip -- the end of each evaluation in a run: combine the
 // segment triples into f = |d_eff|^2, greedy one-to-one selection (paper
-// Sec. 2.2.1 step 4; Sec. 3.2 steps 2 and 5), and, in the last workgroup to
-// finish, the global steps: the three leaders after DE selection (Sec. 3.2
-// step 3) or the advance to the next generation together with its DE
-// draws. A ticket counter finds the last workgroup; it resets the ticket,
-// so the kernel can be replayed from a graph.
+// Sec. 2.2.1 step 4; Sec. 3.2 steps 2 and 5), then the global steps in a
+// one-workgroup kernel: the three leaders after DE selection (Sec. 3.2
+// step 3) or the advance to the next generation (whose DE draws the
+// selection kernel writes).
 #include "common.hpp"
 #include "device_common.hpp"
 #include "scan.hpp"
 
 namespace qpm {
 
-// Workgroup = 4 waves over 64 consecutive individuals (lane = individual):
-// the waves fold the segment triples (combine_segments), wave 0 selects,
-// keeps the packed copy of the buffer flags (bit i % 32 of word i / 32;
-// the wave owns words 2b and 2b + 1) that the DE kernel stages in LDS, and,
-// when leaders are wanted, leaves its own three best in cand (3 per
-// workgroup), so the last workgroup merges 3 candidates per workgroup
-// instead of rereading every fitness value.
-//
-// Cross-workgroup ordering: one wave per workgroup releases (agent-scope
-// fence, which writes back the XCD's L2) before taking a ticket; only the
-// last workgroup acquires (invalidates its L2) before reading the others'
-// results. The last workgroup resets the ticket, so the kernel can be
-// replayed from a graph.
 // Selection for the 64 genomes of group grp (i = 64 grp + lane), from their
 // combined triple t; called by one whole wave. Writes f_cur, flags, the
 // group's two packed flag words, the DE draws of generation gen + 1 (with
@@ -76,68 +62,61 @@ __device__ __forceinline__ void select_group(const Tri &t, int64_t grp, int lane
 // the waves fold the segment triples (combine_segments), wave 0 selects,
 // keeps the packed copy of the buffer flags (bit i % 32 of word i / 32)
 // that the DE kernel stages in LDS, and, when leaders are wanted, leaves
-// its own three best in cand (3 per workgroup), so the last workgroup
-// merges 3 candidates per workgroup instead of rereading every fitness
-// value.
-//
-// Cross-workgroup ordering: one wave per workgroup releases (agent-scope
-// fence, which writes back the XCD's L2) before taking a ticket; only the
-// last workgroup acquires (invalidates its L2) before reading the others'
-// results. The last workgroup resets the ticket, so the kernel can be
-// replayed from a graph.
+// its own three best in cand (3 per workgroup). The global steps (merging
+// the candidates into the leaders, advancing the generation) run in
+// finish_tail_kernel after it: a kernel boundary orders them, which costs
+// less here than an agent-scope release (an L2 write-back) in every
+// workgroup.
 template <typename T>
 __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ part, int gy, int64_t ld, int64_t np,
                                                      const double *__restrict__ C, T *__restrict__ f_cur,
                                                      uint32_t *__restrict__ flags, uint32_t *__restrict__ fbits,
-                                                     const int32_t *__restrict__ skip3,
-                                                     int32_t *__restrict__ top3_out, T *__restrict__ cand_v,
+                                                     const int32_t *__restrict__ skip3, T *__restrict__ cand_v,
                                                      int32_t *__restrict__ cand_i, int4 *__restrict__ draws_next,
-                                                     uint32_t *__restrict__ gen, int64_t D, uint32_t k0, uint32_t k1,
-                                                     uint32_t inst, uint32_t *__restrict__ ticket)
+                                                     const uint32_t *__restrict__ gen, int64_t D, uint32_t k0,
+                                                     uint32_t k1, uint32_t inst)
 {
     const int lane = threadIdx.x & 63;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + lane;
     const Tri t = combine_segments<4>(part, gy, ld, i, i < np);
     if (threadIdx.x < 64)
-        select_group<T>(t, blockIdx.x, lane, np, C, f_cur, flags, fbits, skip3, top3_out ? cand_v : nullptr,
-                        cand_i, draws_next, gen, D, k0, k1, inst);
-    __shared__ int s_last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        s_last = (atomicAdd(ticket, 1u) == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (top3_out) block_top3<T, 256>(cand_v, 3 * static_cast<int64_t>(gridDim.x), top3_out, cand_i);
-    if (threadIdx.x == 0) {
-        if (draws_next) gen[0] += 1u;
-        *ticket = 0u;
-    }
+        select_group<T>(t, blockIdx.x, lane, np, C, f_cur, flags, fbits, skip3, cand_v, cand_i, draws_next, gen, D,
+                        k0, k1, inst);
+}
+
+// One workgroup: the leaders from the 3 candidates of each of the ngroups
+// groups (top3_out), and/or the advance of the generation counter.
+template <typename T>
+__global__ __launch_bounds__(256) void finish_tail_kernel(const T *__restrict__ cand_v,
+                                                          const int32_t *__restrict__ cand_i, int64_t ngroups,
+                                                          int32_t *__restrict__ top3_out, uint32_t *__restrict__ gen,
+                                                          int advance)
+{
+    if (top3_out) block_top3<T, 256>(cand_v, 3 * ngroups, top3_out, cand_i);
+    if (advance && threadIdx.x == 0) gen[0] += 1u;
 }
 
 qpm_status launch_finish(const double *part, int gy, int64_t ld, int64_t np, const double *C, void *f_cur, bool f64,
                          uint32_t *flags, uint32_t *fbits, const int32_t *skip3, int32_t *top3_out, void *cand,
-                         int4 *draws_next, uint32_t *gen, int64_t D, uint64_t seed, uint32_t inst, uint32_t *ticket,
-                         hipStream_t s)
+                         int4 *draws_next, uint32_t *gen, int64_t D, uint64_t seed, uint32_t inst, hipStream_t s)
 {
     const unsigned blocks = static_cast<unsigned>((np + 63) / 64);
     QPM_REQUIRE(top3_out == nullptr || cand != nullptr, QPM_EINVAL, "leader candidates need a buffer");
     const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
+    const int advance = draws_next != nullptr;
     // cand: 3 values per workgroup (T) followed by 3 slots per workgroup (int32)
     if (f64) {
-        double *cv = static_cast<double *>(cand);
+        double *cv = top3_out ? static_cast<double *>(cand) : nullptr;
         int32_t *ci = cv ? reinterpret_cast<int32_t *>(cv + 3 * static_cast<size_t>(blocks)) : nullptr;
         finish_kernel<double><<<blocks, 256, 0, s>>>(part, gy, ld, np, C, static_cast<double *>(f_cur), flags, fbits,
-                                                     skip3, top3_out, cv, ci, draws_next, gen, D, k0, k1, inst,
-                                                     ticket);
+                                                     skip3, cv, ci, draws_next, gen, D, k0, k1, inst);
+        if (top3_out || advance) finish_tail_kernel<double><<<1, 256, 0, s>>>(cv, ci, blocks, top3_out, gen, advance);
     } else {
-        float *cv = static_cast<float *>(cand);
+        float *cv = top3_out ? static_cast<float *>(cand) : nullptr;
         int32_t *ci = cv ? reinterpret_cast<int32_t *>(cv + 3 * static_cast<size_t>(blocks)) : nullptr;
         finish_kernel<float><<<blocks, 256, 0, s>>>(part, gy, ld, np, C, static_cast<float *>(f_cur), flags, fbits,
-                                                    skip3, top3_out, cv, ci, draws_next, gen, D, k0, k1, inst,
-                                                    ticket);
+                                                    skip3, cv, ci, draws_next, gen, D, k0, k1, inst);
+        if (top3_out || advance) finish_tail_kernel<float><<<1, 256, 0, s>>>(cv, ci, blocks, top3_out, gen, advance);
     }
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;

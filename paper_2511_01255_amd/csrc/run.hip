@@ -36,7 +36,6 @@ struct qpm_run_s {
     uint32_t *gen = nullptr;
     float *a_tab = nullptr;
     int4 *draws = nullptr;
-    uint32_t *ticket = nullptr;
     double *fws = nullptr;
     FitPlan plan;
     int de_ipw = 0;     // 0 = chosen from np
@@ -86,7 +85,6 @@ static void release(qpm_run_s *r)
     (void)hipFree(r->a_tab);
     (void)hipFree(r->fws);
     (void)hipFree(r->draws);
-    (void)hipFree(r->ticket);
     (void)hipFree(r->pol);
     (void)hipFree(r->pol_S);
     (void)hipFree(r->pol_f);
@@ -123,13 +121,13 @@ static qpm_status enqueue_generation(qpm_run_s *r, hipEvent_t *ev = nullptr)
     QPM_STEP(QPM_K_FIT_DE, launch_fitness_partials(*r->d, p, r->tbits, c.np, r->ld, r->plan, r->fws, r->st))
     QPM_STEP(QPM_K_FINISH_DE, launch_finish(r->fws, gy, r->ld, c.np, C, r->f_cur, r->f64(), r->flags, r->fbits,
                                             nullptr, r->leaders, r->cand, nullptr, r->gen, r->D, c.seed, c.inst,
-                                            r->ticket, r->st))
+                                            r->st))
     QPM_STEP(QPM_K_GWO, launch_gwo(pv, r->leaders, r->a_tab, 0.0f, c.seed, r->gen, 0u, c.inst, c.gwo_variant,
                                    r->tbits, r->ld, r->st))
     QPM_STEP(QPM_K_FIT_GWO, launch_fitness_partials(*r->d, p, r->tbits, c.np, r->ld, r->plan, r->fws, r->st))
     QPM_STEP(QPM_K_FINISH_GWO, launch_finish(r->fws, gy, r->ld, c.np, C, r->f_cur, r->f64(), r->flags, r->fbits,
                                              r->leaders, nullptr, nullptr, r->draws, r->gen, r->D, c.seed, c.inst,
-                                             r->ticket, r->st))
+                                             r->st))
 #undef QPM_STEP
     return mark(QPM_K_COUNT);
 }
@@ -341,7 +339,6 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     if (e == hipSuccess) e = hipMalloc(&r->gen, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&r->a_tab, sizeof(float) * c.generations);
     if (e == hipSuccess) e = hipMalloc(&r->draws, sizeof(int4) * c.np);
-    if (e == hipSuccess) e = hipMalloc(&r->ticket, sizeof(uint32_t));
     if (e != hipSuccess) {
         set_error("run allocation failed: %s", hipGetErrorString(e));
         release(r);
@@ -361,7 +358,6 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     if (e == hipSuccess) e = hipMemsetAsync(r->flags, 0, sizeof(uint32_t) * c.np, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->fbits, 0, sizeof(uint32_t) * 2 * ((c.np + 63) / 64), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->gen, 0, sizeof(uint32_t), r->st);
-    if (e == hipSuccess) e = hipMemsetAsync(r->ticket, 0, sizeof(uint32_t), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->tbits, 0, sizeof(uint32_t) * r->W * r->ld, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->buf[1], 0, gene_bytes, r->st);
     if (e == hipSuccess) e = hipStreamSynchronize(r->st);  // a.data() must outlive the copy
