@@ -410,6 +410,13 @@ qpm_status qpm_batch_eval_fitness_table(qpm_batch b, qpm_prec p, const uint32_t 
 qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, int32_t tune, qpm_stream s,
                                 qpm_batch_run_handle *out);
 qpm_status qpm_batch_run_advance(qpm_batch_run_handle r, int64_t generations);
+/* Launch shape of the batched DE step: individuals_per_wave in {1, 2, 4}
+ * (gene chunks of 256 / individuals_per_wave) and passes in {1, 2, 4}
+ * groups of individuals per workgroup; replaces the tuner's or default
+ * choice (synchronises the run's stream and re-captures its graph). The
+ * shape changes the speed only, never the trajectory. */
+qpm_status qpm_batch_run_set_de_shape(qpm_batch_run_handle r, int32_t individuals_per_wave,
+                                      int32_t passes);
 qpm_status qpm_batch_run_set_timing(qpm_batch_run_handle r, int32_t enable);
 qpm_status qpm_batch_run_timing(qpm_batch_run_handle r, double *ms, int64_t *generations,
                                 int32_t reset);

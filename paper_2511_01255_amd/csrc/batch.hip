@@ -260,12 +260,12 @@ __global__ __launch_bounds__(256) void batch_init_kernel(int64_t np, const InstD
 }
 
 // DE: tiles (instance, chunk of CW = 256 / IPW genes) dealt round-robin to
-// the XCDs (workgroup id mod 8); a workgroup covers 4 IPW consecutive
-// individuals of one tile.
-// Each row's buffer flag comes from the instance's packed flags (np / 32
-// words, np <= 4096), copied to LDS first, instead of a dependent global
-// load after the draw.
-template <int IPW>
+// the XCDs (workgroup id mod 8); a workgroup makes R passes over groups of
+// 4 IPW consecutive individuals of one tile, loading the rows of pass r + 1
+// before storing the trials of pass r. Each row's buffer flag comes from
+// the instance's packed flags (np / 32 words, np <= 4096), copied to LDS
+// first, instead of a dependent global load after the draw.
+template <int IPW, int R>
 __global__ __launch_bounds__(256) void batch_de_kernel(BatchPop bp, const InstDesc *__restrict__ inst,
                                                        const Tile *__restrict__ tiles, int ntiles, int groups,
                                                        const int4 *__restrict__ draws, float F, uint32_t cr_max,
@@ -277,6 +277,8 @@ __global__ __launch_bounds__(256) void batch_de_kernel(BatchPop bp, const InstDe
     constexpr int CW = 4 * LPI;
     constexpr int WPC = CW / 32;
     constexpr int IPG = 4 * IPW;
+    constexpr int IPB = R * IPG;
+    static_assert(IPB * WPC <= 256, "one bit word per thread at the end");
     const uint32_t blk = blockIdx.x;
     const int xcd = static_cast<int>(blk & 7u);
     const int k = static_cast<int>(blk >> 3);
@@ -289,41 +291,61 @@ __global__ __launch_bounds__(256) void batch_de_kernel(BatchPop bp, const InstDe
     const int t = threadIdx.x;
     const int local = t / LPI, li = t % LPI;
     const int64_t np = bp.np, D = id.n;
-    const int64_t i = static_cast<int64_t>(gi) * IPG + local;
+    const int64_t i0 = static_cast<int64_t>(gi) * IPB + local;
     const int64_t j0 = static_cast<int64_t>(tl.chunk) * CW + 4 * li;
-    const bool active = i < np && j0 < D;
     const uint32_t g = gen[0];
     const uint32_t instb = inst0 + static_cast<uint32_t>(tl.inst);
-    __shared__ uint32_t wsh[IPG][WPC];
+    __shared__ uint32_t wsh[IPB][WPC];
     __shared__ uint32_t sfb[128];
-    const int4 dr = draws[static_cast<int64_t>(tl.inst) * np + (i < np ? i : np - 1)];
+    int4 dr[R];
+    bool act[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = i0 + r * IPG;
+        act[r] = i < np && j0 < D;
+        dr[r] = draws[static_cast<int64_t>(tl.inst) * np + (i < np ? i : np - 1)];
+    }
     const int fw = static_cast<int>((np + 31) / 32);
     if (t < fw) sfb[t] = fbits[static_cast<int64_t>(tl.inst) * fw + t];
     __syncthreads();
-    auto src = [&](int64_t r) -> const float * {
-        const bool second = ((sfb[r >> 5] >> (r & 31)) & 1u) != 0u;
-        return (second ? pv.x1 : pv.x0) + r * pv.ldx;
+    auto second = [&](int64_t r) -> bool { return ((sfb[r >> 5] >> (r & 31)) & 1u) != 0u; };
+    auto src = [&](int64_t r) -> const float * { return (second(r) ? pv.x1 : pv.x0) + r * pv.ldx; };
+    float4 cur[4], nxt[4];
+    auto load = [&](int r, float4 *v) {
+        if (act[r]) {
+            const int64_t i = i0 + r * IPG;
+            v[0] = *reinterpret_cast<const float4 *>(src(i) + j0);
+            v[1] = *reinterpret_cast<const float4 *>(src(dr[r].x) + j0);
+            v[2] = *reinterpret_cast<const float4 *>(src(dr[r].y) + j0);
+            v[3] = *reinterpret_cast<const float4 *>(src(dr[r].z) + j0);
+        }
     };
-    uint32_t nib = 0;
-    if (active) {
-        const float4 xv = *reinterpret_cast<const float4 *>(src(i) + j0);
-        const float4 a = *reinterpret_cast<const float4 *>(src(dr.x) + j0);
-        const float4 bq = *reinterpret_cast<const float4 *>(src(dr.y) + j0);
-        const float4 cq = *reinterpret_cast<const float4 *>(src(dr.z) + j0);
-        const float4 uv = de_quad(xv, a, bq, cq, j0, dr.w, static_cast<uint32_t>(i), g, instb, k0, k1, F, cr_max);
-        const bool second = ((sfb[i >> 5] >> (i & 31)) & 1u) != 0u;
-        store_quad_nt((second ? pv.out0 : pv.out1) + i * pv.ldx, j0, D, uv);
-        nib = quad_nibble(uv, j0, D);
+    load(0, cur);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (r + 1 < R) load(r + 1, nxt);
+        uint32_t nib = 0;
+        if (act[r]) {
+            const int64_t i = i0 + r * IPG;
+            const float4 uv = de_quad(cur[0], cur[1], cur[2], cur[3], j0, dr[r].w, static_cast<uint32_t>(i), g,
+                                      instb, k0, k1, F, cr_max);
+            store_quad_nt((second(i) ? pv.out0 : pv.out1) + i * pv.ldx, j0, D, uv);
+            nib = quad_nibble(uv, j0, D);
+        }
+        uint32_t w = nib << (4 * (t & 7));
+        w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 1));
+        w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 2));
+        w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 4));
+        if ((t & 7) == 0) wsh[r * IPG + local][li >> 3] = w;
+        if (r + 1 < R) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) cur[m] = nxt[m];
+        }
     }
-    uint32_t w = nib << (4 * (t & 7));
-    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 1));
-    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 2));
-    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 4));
-    if ((t & 7) == 0) wsh[local][li >> 3] = w;
     __syncthreads();
-    if (t < IPG * WPC) {
-        const int wd = t / IPG, ii = t % IPG;
-        const int64_t row = static_cast<int64_t>(gi) * IPG + ii;
+    if (t < IPB * WPC) {
+        const int wd = t / IPB, ii = t % IPB;
+        const int64_t row = static_cast<int64_t>(gi) * IPB + ii;
         const int64_t wg = static_cast<int64_t>(tl.chunk) * WPC + wd;
         if (row < np && wg * 32 < D) bits[(id.wofs + wg) * ld + row] = wsh[ii][wd];
     }
@@ -756,8 +778,9 @@ struct qpm_batch_run_s {
     InstDesc *inst = nullptr;  // instance table with xofs scaled by np
     Tile *gtiles = nullptr;    // (instance, 1024-gene chunk)
     int n_gtiles = 0;
-    Tile *dtiles = nullptr;    // (instance, DE chunk)
-    int n_dtiles = 0, de_ipw = 1, de_groups = 1;
+    Tile *dtiles[3] = {nullptr, nullptr, nullptr};  // (instance, DE chunk) for 1, 2, 4 individuals per wave
+    int n_dtiles[3] = {0, 0, 0};
+    int de_ipw = 1, de_passes = 1;
     BatchFitPlan fplan;
     FitPlanDev fdev;
     hipGraph_t graph = nullptr;
@@ -792,7 +815,7 @@ static void release_batch_run(qpm_batch_run_s *r)
     (void)hipFree(r->a_tab);
     (void)hipFree(r->inst);
     (void)hipFree(r->gtiles);
-    (void)hipFree(r->dtiles);
+    for (auto *t : r->dtiles) (void)hipFree(t);
     if (r->st && r->fdev.segs) {
         free_fit_plan(r->fdev, r->st);
         (void)hipStreamSynchronize(r->st);
@@ -803,23 +826,29 @@ static void release_batch_run(qpm_batch_run_s *r)
     delete r;
 }
 
-static qpm_status launch_batch_de(qpm_batch_run_s *r)
+static qpm_status launch_batch_de(qpm_batch_run_s *r, int ipw, int passes)
 {
     const qpm_run_config &c = r->cfg;
     const uint32_t k0 = static_cast<uint32_t>(c.seed), k1 = static_cast<uint32_t>(c.seed >> 32);
-    const int64_t blocks = 8 * ((r->n_dtiles + 7) / 8) * static_cast<int64_t>(r->de_groups);
+    const int64_t groups = (c.np + 4 * ipw * passes - 1) / (4 * ipw * passes);
+    const Tile *tiles = ipw == 1 ? r->dtiles[0] : (ipw == 2 ? r->dtiles[1] : r->dtiles[2]);
+    const int ntiles = ipw == 1 ? r->n_dtiles[0] : (ipw == 2 ? r->n_dtiles[1] : r->n_dtiles[2]);
+    const int64_t blocks = 8 * ((ntiles + 7) / 8) * groups;
+    QPM_REQUIRE(blocks < (int64_t(1) << 31), QPM_ERANGE, "batch too large for one DE launch");
     const unsigned nb = static_cast<unsigned>(blocks);
     const BatchPop bp = r->pop();
-#define QPM_BDE(IPW)                                                                                          \
-    batch_de_kernel<IPW><<<nb, 256, 0, r->st>>>(bp, r->inst, r->dtiles, r->n_dtiles, r->de_groups, r->draws, \
-                                                c.F, cr_threshold(c.CR), k0, k1, r->gen, c.inst, r->bits, r->ld,  \
-                                                r->fbits)
-    if (r->de_ipw == 1)
-        QPM_BDE(1);
-    else if (r->de_ipw == 2)
-        QPM_BDE(2);
-    else
-        QPM_BDE(4);
+    const int gr = static_cast<int>(groups);
+#define QPM_BDE(I, P)                                                                                       \
+    batch_de_kernel<I, P><<<nb, 256, 0, r->st>>>(bp, r->inst, tiles, ntiles, gr, r->draws, c.F,             \
+                                                 cr_threshold(c.CR), k0, k1, r->gen, c.inst, r->bits, r->ld, \
+                                                 r->fbits)
+    if (ipw == 1) {
+        if (passes == 1) { QPM_BDE(1, 1); } else if (passes == 2) { QPM_BDE(1, 2); } else { QPM_BDE(1, 4); }
+    } else if (ipw == 2) {
+        if (passes == 1) { QPM_BDE(2, 1); } else if (passes == 2) { QPM_BDE(2, 2); } else { QPM_BDE(2, 4); }
+    } else {
+        if (passes == 1) { QPM_BDE(4, 1); } else if (passes == 2) { QPM_BDE(4, 2); } else { QPM_BDE(4, 4); }
+    }
 #undef QPM_BDE
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
@@ -849,7 +878,7 @@ static qpm_status batch_generation(qpm_batch_run_s *r, hipEvent_t *ev = nullptr)
 #define QPM_STEP(k, call)                    \
     if ((st = mark(k)) != QPM_OK) return st; \
     if ((st = (call)) != QPM_OK) return st;
-    QPM_STEP(QPM_K_DE, launch_batch_de(r))
+    QPM_STEP(QPM_K_DE, launch_batch_de(r, r->de_ipw, r->de_passes))
     QPM_STEP(QPM_K_FIT_DE, launch_batch_fit(*r->bt, p, r->bits, c.np, r->ld, r->fplan, r->fdev.segs, r->fdev.part,
                                             r->st))
     QPM_STEP(QPM_K_FINISH_DE, launch_batch_finish(2, *r->bt, p, r->fdev, r->ld, c.np, r->f_cur, r->flags, r->leaders,
@@ -920,6 +949,70 @@ static qpm_status tune_fitness(qpm_batch_run_s *r)
     return QPM_OK;
 }
 
+// one generation captured into r->graph / r->exec
+static qpm_status capture_batch_generation(qpm_batch_run_s *r)
+{
+    hipError_t e = hipStreamBeginCapture(r->st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        set_error("hipStreamBeginCapture failed: %s", hipGetErrorString(e));
+        return QPM_EHIP;
+    }
+    qpm_status st = batch_generation(r);
+    e = hipStreamEndCapture(r->st, &r->graph);
+    if (st == QPM_OK && e != hipSuccess) {
+        set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        st = QPM_EHIP;
+    }
+    if (st == QPM_OK && hipGraphInstantiate(&r->exec, r->graph, nullptr, nullptr, 0) != hipSuccess) {
+        set_error("hipGraphInstantiate failed");
+        st = QPM_EHIP;
+    }
+    return st;
+}
+
+// time the batched DE for every (individuals per wave, passes) shape on the
+// initial population and keep the fastest (the shape never changes results)
+static qpm_status tune_de(qpm_batch_run_s *r)
+{
+    const qpm_run_config &c = r->cfg;
+    const std::string key = tune_key("batchde", r->bt->total_words, c.np, 0, r->bt->n_inst);
+    int ipw = 0, passes = 0;
+    if (!tune_lookup(key, &ipw, &passes)) {
+        hipEvent_t e0, e1;
+        QPM_TRY_HIP(hipEventCreate(&e0));
+        QPM_TRY_HIP(hipEventCreate(&e1));
+        float best = 1e30f;
+        qpm_status st = QPM_OK;
+        for (int cand : {1, 2, 4})
+            for (int pc : {1, 2, 4}) {
+                st = launch_batch_de(r, cand, pc);  // warm-up
+                float ms = 1e30f;
+                for (int rep = 0; rep < 3 && st == QPM_OK; ++rep) {
+                    QPM_TRY_HIP(hipEventRecord(e0, r->st));
+                    st = launch_batch_de(r, cand, pc);
+                    QPM_TRY_HIP(hipEventRecord(e1, r->st));
+                    QPM_TRY_HIP(hipEventSynchronize(e1));
+                    float t = 0.0f;
+                    QPM_TRY_HIP(hipEventElapsedTime(&t, e0, e1));
+                    ms = std::min(ms, t);
+                }
+                if (st != QPM_OK) break;
+                if (ms < best) {
+                    best = ms;
+                    ipw = cand;
+                    passes = pc;
+                }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != QPM_OK) return st;
+        tune_store(key, ipw, passes);
+    }
+    r->de_ipw = ipw;
+    r->de_passes = passes;
+    return QPM_OK;
+}
+
 QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, int32_t tune, qpm_stream sv,
                                         qpm_batch_run_handle *out)
 {
@@ -950,15 +1043,17 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
         xofs += c.np * d.ldx;
     }
     const size_t gene_bytes = sizeof(float) * static_cast<size_t>(xofs);
-    // tiles
-    std::vector<Tile> gt, dt;
+    // tiles: GWO / init chunks of 1024 genes; DE chunks of 256 / ipw genes
+    // for ipw = 1, 2, 4 (the shape is chosen by the default or the tuner)
+    std::vector<Tile> gt, dt[3];
     const int64_t row_bytes = 2 * 1024 * 1024 / c.np;
     r->de_ipw = row_bytes >= 1024 ? 1 : (row_bytes >= 512 ? 2 : 4);
-    const int64_t cw = 256 / r->de_ipw;
-    r->de_groups = static_cast<int>((c.np + 4 * r->de_ipw - 1) / (4 * r->de_ipw));
     for (int32_t i = 0; i < b->n_inst; ++i) {
         for (int64_t ch = 0; ch * 1024 < h[i].n; ++ch) gt.push_back(Tile{i, static_cast<int>(ch)});
-        for (int64_t ch = 0; ch * cw < h[i].n; ++ch) dt.push_back(Tile{i, static_cast<int>(ch)});
+        for (int v = 0; v < 3; ++v) {
+            const int64_t cw = 256 >> v;
+            for (int64_t ch = 0; ch * cw < h[i].n; ++ch) dt[v].push_back(Tile{i, static_cast<int>(ch)});
+        }
     }
     if (gt.size() > 65535) {  // the GWO and init grids put these chunks on gridDim.y
         set_error("too many 1024-gene chunks over the batch (%zu > 65535)", gt.size());
@@ -966,7 +1061,7 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
         return QPM_ERANGE;
     }
     r->n_gtiles = static_cast<int>(gt.size());
-    r->n_dtiles = static_cast<int>(dt.size());
+    for (int v = 0; v < 3; ++v) r->n_dtiles[v] = static_cast<int>(dt[v].size());
     hipError_t e = hipStreamCreateWithFlags(&r->st, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&r->buf[0], gene_bytes);
     if (e == hipSuccess) e = hipMalloc(&r->buf[1], gene_bytes);
@@ -981,7 +1076,8 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
     if (e == hipSuccess) e = hipMalloc(&r->a_tab, sizeof(float) * c.generations);
     if (e == hipSuccess) e = hipMalloc(&r->inst, sizeof(InstDesc) * n_inst);
     if (e == hipSuccess) e = hipMalloc(&r->gtiles, sizeof(Tile) * gt.size());
-    if (e == hipSuccess) e = hipMalloc(&r->dtiles, sizeof(Tile) * dt.size());
+    for (int v = 0; v < 3; ++v)
+        if (e == hipSuccess) e = hipMalloc(&r->dtiles[v], sizeof(Tile) * dt[v].size());
     if (e != hipSuccess) {
         set_error("batched run allocation failed: %s", hipGetErrorString(e));
         release_batch_run(r);
@@ -999,8 +1095,10 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
     if (e == hipSuccess) e = hipMemcpyAsync(r->inst, h.data(), sizeof(InstDesc) * n_inst, hipMemcpyHostToDevice, r->st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(r->gtiles, gt.data(), sizeof(Tile) * gt.size(), hipMemcpyHostToDevice, r->st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(r->dtiles, dt.data(), sizeof(Tile) * dt.size(), hipMemcpyHostToDevice, r->st);
+    for (int v = 0; v < 3; ++v)
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(r->dtiles[v], dt[v].data(), sizeof(Tile) * dt[v].size(), hipMemcpyHostToDevice,
+                               r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->flags, 0, sizeof(uint32_t) * n_inst * c.np, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->fbits, 0, sizeof(uint32_t) * n_inst * ((c.np + 31) / 32), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->gen, 0, sizeof(uint32_t), r->st);
@@ -1043,29 +1141,36 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
     if (st == QPM_OK)
         st = launch_batch_finish(1, *b, p, r->fdev, r->ld, c.np, r->f_cur, r->flags, r->leaders, r->draws, r->gen,
                                  c.seed, c.inst, r->ticket, r->st);
-    if (st == QPM_OK && c.use_graph) {
-        e = hipStreamBeginCapture(r->st, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) {
-            set_error("hipStreamBeginCapture failed: %s", hipGetErrorString(e));
-            st = QPM_EHIP;
-        } else {
-            st = batch_generation(r);
-            hipError_t e2 = hipStreamEndCapture(r->st, &r->graph);
-            if (st == QPM_OK && e2 != hipSuccess) {
-                set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e2));
-                st = QPM_EHIP;
-            }
-            if (st == QPM_OK && hipGraphInstantiate(&r->exec, r->graph, nullptr, nullptr, 0) != hipSuccess) {
-                set_error("hipGraphInstantiate failed");
-                st = QPM_EHIP;
-            }
-        }
-    }
+    // the DE shape: the trial launches of the tuner write only the other
+    // gene buffer and the bit rows, which the first generation overwrites
+    if (st == QPM_OK && tune) st = tune_de(r);
+    if (st == QPM_OK && c.use_graph) st = capture_batch_generation(r);
     if (st != QPM_OK) {
         release_batch_run(r);
         return st;
     }
     *out = r;
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_batch_run_set_de_shape(qpm_batch_run_handle r, int32_t individuals_per_wave, int32_t passes)
+{
+    clear_error();
+    QPM_REQUIRE(r != nullptr, QPM_EINVAL, "run is NULL");
+    QPM_REQUIRE(individuals_per_wave == 1 || individuals_per_wave == 2 || individuals_per_wave == 4, QPM_EINVAL,
+                "individuals_per_wave must be 1, 2 or 4 (got %d)", (int)individuals_per_wave);
+    QPM_REQUIRE(passes == 1 || passes == 2 || passes == 4, QPM_EINVAL, "passes must be 1, 2 or 4 (got %d)",
+                (int)passes);
+    QPM_TRY_HIP(hipStreamSynchronize(r->st));
+    r->de_ipw = individuals_per_wave;
+    r->de_passes = passes;
+    if (r->exec) {
+        (void)hipGraphExecDestroy(r->exec);
+        (void)hipGraphDestroy(r->graph);
+        r->exec = nullptr;
+        r->graph = nullptr;
+        return capture_batch_generation(r);
+    }
     return QPM_OK;
 }
 

@@ -83,6 +83,7 @@ _SIGS = {
     "qpm_batch_run_create": (_I32, [_P, C.POINTER(RunConfig), _I32, _P, C.POINTER(_P)]),
     "qpm_batch_run_advance": (_I32, [_P, _I64]),
     "qpm_batch_run_set_timing": (_I32, [_P, _I32]),
+    "qpm_batch_run_set_de_shape": (_I32, [_P, _I32, _I32]),
     "qpm_batch_run_timing": (_I32, [_P, _P, _P, _I32]),
     "qpm_batch_run_read": (_I32, [_P, _I32, _P, _I64, _P, _P, _P]),
     "qpm_batch_run_destroy": (_I32, [_P]),
@@ -492,6 +493,9 @@ class BatchRun:
 
     def set_timing(self, enable=True):
         _check(lib().qpm_batch_run_set_timing(self._h, 1 if enable else 0))
+
+    def set_de_shape(self, individuals_per_wave, passes):
+        _check(lib().qpm_batch_run_set_de_shape(self._h, individuals_per_wave, passes))
 
     def timing(self, reset=False):
         ms = (C.c_double * len(STEP_NAMES))()

@@ -107,6 +107,32 @@ def test_batch_run_tuned_and_graph_agree(q):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("graph", [1, 0])
+def test_batch_run_every_de_shape_same_trajectory(q, orc, graph):
+    # the DE launch shape (individuals per wave x passes) moves no gene: every
+    # shape gives the oracle's FP64 trajectory; np = 37 leaves ragged groups
+    # and N = 1007 / 2049 ragged gene chunks for every chunk width
+    specs = _small_batch()[1:]
+    npop, G, inst0 = 37, 5, 2
+    B = q.precompute_phases_batched([s[0] for s in specs], [s[1] for s in specs], [s[2] for s in specs])
+    want = [orc.Design(z, k1, k2).hwsda_run(npop, G, 0.5, 0.9, 11, inst=inst0 + b)[0]
+            for b, (z, k1, k2) in enumerate(specs)]
+    R = q.BatchRun(B, npop, G, seed=11, inst=inst0, prec=q.PREC_F64, tune=0, use_graph=graph)
+    with pytest.raises(q.QpmError):
+        R.set_de_shape(3, 1)
+    with pytest.raises(q.QpmError):
+        R.set_de_shape(1, 8)
+    R.destroy()
+    for ipw in (1, 2, 4):
+        for passes in (1, 2, 4):
+            R = q.BatchRun(B, npop, G, seed=11, inst=inst0, prec=q.PREC_F64, tune=0, use_graph=graph)
+            R.set_de_shape(ipw, passes)
+            R.advance(G)
+            for b in range(len(specs)):
+                assert np.array_equal(R.read(b)[0].cpu().numpy(), want[b]), (ipw, passes, b)
+            R.destroy()
+
+
 def test_batch_uneven_designs_full_recipe_fitness(q, orc):
     # 64 instances: N ~ U[1000, 50000], width U[1.5, 3] um, dk1 = 2pi/U[18,21],
     # dk2 = 2pi/U[6.2,7]; NP = 256. The initial population's fitness in every
