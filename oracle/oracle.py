@@ -57,6 +57,9 @@ def lib():
             "orc_top3": (None, [_P, _I64, _P]),
             "orc_a_schedule": (_F, [_I64, _I64]),
             "orc_hwsda_run": (_INT, [_P, _I64, _I64, _F, _F, _U64, _U32, _INT, _P, _P, _P]),
+            "orc_hwsda_run_ctl": (_INT, [_P, _I64, _I64, _F, _F, _U64, _U32, _INT, _INT, _P, _P, _P, _P]),
+            "orc_a_control": (_F, [_INT, _I64, _I64]),
+            "orc_adaptive_F": (_F, [_P, _I64, _I64, _I64]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -144,14 +147,24 @@ class Design:
         lib().orc_relax(self._h, _ptr(theta), B, _ptr(S), _ptr(f), _ptr(g))
         return S[0::2] + 1j * S[1::2], f, g
 
-    def hwsda_run(self, np_, G, F, CR, seed, inst=0, variant=0, trace=True):
+    def hwsda_run(self, np_, G, F, CR, seed, inst=0, variant=0, trace=True, control=None):
+        """control None: the plain entry point (textbook parameters);
+        0, 1, 2: the parameter control, returning also (G, 2) float32 rows
+        (F_g, a_g)."""
         x = np.zeros((np_, self.n), dtype=np.float32)
         f = np.zeros(np_)
         tr = np.zeros(G) if trace else None
-        rc = lib().orc_hwsda_run(self._h, np_, G, F, CR, seed, inst, variant, _ptr(x), _ptr(f), _ptr(tr))
+        if control is None:
+            rc = lib().orc_hwsda_run(self._h, np_, G, F, CR, seed, inst, variant, _ptr(x), _ptr(f), _ptr(tr))
+            if rc != 0:
+                raise ValueError("invalid run arguments")
+            return x, f, tr
+        par = np.zeros((G, 2), dtype=np.float32)
+        rc = lib().orc_hwsda_run_ctl(self._h, np_, G, F, CR, seed, inst, variant, control, _ptr(x), _ptr(f),
+                                     _ptr(tr), _ptr(par))
         if rc != 0:
             raise ValueError("invalid run arguments")
-        return x, f, tr
+        return x, f, tr, par
 
 
 def fitness_quad(z, dk1, dk2, d):
@@ -211,3 +224,12 @@ def top3(f):
 
 def a_schedule(g, G):
     return lib().orc_a_schedule(g, G)
+
+
+def a_control(control, g, G):
+    return lib().orc_a_control(control, g, G)
+
+
+def adaptive_F(f, g, G):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return lib().orc_adaptive_F(_ptr(f), f.size, g, G)

@@ -634,6 +634,70 @@ void orc_top3(const double *f, int64_t np, int32_t *out)
 /* a decreases linearly from 2 towards 0 over the run */
 float orc_a_schedule(int64_t g, int64_t G) { return (float)(2.0 * (1.0 - (double)g / (double)G)); }
 
+/* ------------------------------------------------------------------ */
+/* parameter control (Sec. 3.1.1; the parameter settings of Sec. 4)     */
+/* ------------------------------------------------------------------ */
+
+/* The GWO coefficient a_g of generation g under each control:
+ *   0  the textbook schedule above, a from 2 towards 0 (Sec. 2.2.2); F is
+ *      the caller's constant;
+ *   1  F = a, starting at 0.1 and falling to 0.01 over the run (Sec. 4,
+ *      parameter settings). The paper gives no decay law; linear in g / G
+ *      is this oracle's reading;
+ *   2  a as in 1, F adaptive (orc_adaptive_F). */
+float orc_a_control(int control, int64_t g, int64_t G)
+{
+    if (control == 0) return orc_a_schedule(g, G);
+    double t = (double)g / (double)G;
+    return (float)(0.1 * (1.0 - t) + 0.01 * t);
+}
+
+/* The adaptive DE scale factor of Sec. 3.1.1, kept in [0.01, 0.1], from
+ * the fitness of the population that enters generation g:
+ *   s     = std(f) / mean(f)          relative spread (population std),
+ *   kappa = (max f - mean f) / max f  how far the mean trails the best
+ *                                     (small once the population has
+ *                                     converged: the convergence measure),
+ *   range = max f - min f             (f in um^2).
+ * Low diversity, s < 0.1 or kappa < 0.1: F is raised by the exploration
+ * factor 1.2. Else too much spread or a narrow range, s > 0.5 or
+ * range < 10^3: F is lowered by the exploitation factor 0.8. Else the
+ * factor is 1. The factor scales the decay law of the intermediate state,
+ *   base(g) = 0.1 (cos(pi g / (2G)) + 1) / 2 (1 - 0.2 (g / G)^2),
+ * the paper's cosine decay times a quadratic coefficient falling from 1.0
+ * to 0.8, scaled so that F starts at the top of the interval; the product
+ * is clamped to [0.01, 0.1] and rounded to float once. Readings (the paper
+ * names the quantities but not these values): the definitions of s and
+ * kappa, the threshold 0.5 on s, the factors 1.2 and 0.8, the scaling by
+ * 0.1, and that the factor applies to base(g) rather than to the previous
+ * F. */
+float orc_adaptive_F(const double *f, int64_t np, int64_t g, int64_t G)
+{
+    double sum = 0.0, mx = f[0], mn = f[0];
+    for (int64_t i = 0; i < np; ++i) {
+        sum += f[i];
+        if (f[i] > mx) mx = f[i];
+        if (f[i] < mn) mn = f[i];
+    }
+    double mean = sum / (double)np;
+    double ss = 0.0;
+    for (int64_t i = 0; i < np; ++i) ss += (f[i] - mean) * (f[i] - mean);
+    double sd = sqrt(ss / (double)np);
+    double s = mean > 0.0 ? sd / mean : 0.0;
+    double kappa = mx > 0.0 ? (mx - mean) / mx : 0.0;
+    double m = 1.0;
+    if (s < 0.1 || kappa < 0.1)
+        m = 1.2;
+    else if (s > 0.5 || mx - mn < 1e3)
+        m = 0.8;
+    double t = (double)g / (double)G;
+    double base = 0.1 * (0.5 * (cos(0.5 * M_PI * t) + 1.0)) * (1.0 - 0.2 * t * t);
+    double F = base * m;
+    if (F < 0.01) F = 0.01;
+    if (F > 0.1) F = 0.1;
+    return (float)F;
+}
+
 static void fitness_of_genes(const orc_design *d, const float *x, int64_t np, int8_t *scratch, double *f)
 {
     orc_sign_map(x, np * d->n, scratch);
@@ -641,16 +705,21 @@ static void fitness_of_genes(const orc_design *d, const float *x, int64_t np, in
 }
 
 /* The whole optimiser. x_out: np x n final genes, f_out: np final fitness,
- * trace (may be NULL): best fitness after each generation.
- * Per generation g: DE trials, evaluation, greedy selection (strict >);
- * leaders from the sorted fitness; GWO candidates for the other wolves,
- * evaluation, greedy selection again. */
-int orc_hwsda_run(const void *h, int64_t np, int64_t G, float F, float CR, uint64_t seed,
-                  uint32_t inst, int variant, float *x_out, double *f_out, double *trace)
+ * trace (may be NULL): best fitness after each generation; params (may be
+ * NULL): F_g and a_g of each generation (2 G floats).
+ * Per generation g: F_g and a_g from the control (orc_a_control;
+ * orc_adaptive_F on the current fitness under control 2), DE trials,
+ * evaluation, greedy selection (strict >); leaders from the sorted
+ * fitness; GWO candidates for the other wolves, evaluation, greedy
+ * selection again. CR stays fixed (step 6 of Sec. 3.2 updates "F, CR and
+ * others"; the paper gives a rule for F only). */
+int orc_hwsda_run_ctl(const void *h, int64_t np, int64_t G, float F, float CR, uint64_t seed,
+                      uint32_t inst, int variant, int control, float *x_out, double *f_out,
+                      double *trace, float *params)
 {
     const orc_design *d = h;
     const int64_t D = d->n;
-    if (np < 4 || G < 1) return -1;
+    if (np < 4 || G < 1 || control < 0 || control > 2) return -1;
     float *x = x_out;
     float *u = malloc(sizeof(float) * np * D);
     int8_t *sg = malloc((size_t)(np * D));
@@ -659,7 +728,13 @@ int orc_hwsda_run(const void *h, int64_t np, int64_t G, float F, float CR, uint6
     orc_init_pop(np, D, seed, inst, x);
     fitness_of_genes(d, x, np, sg, f);
     for (int64_t g = 0; g < G; ++g) {
-        orc_de_step(x, np, D, F, CR, seed, (uint32_t)g, inst, u, NULL);
+        const float a_g = orc_a_control(control, g, G);
+        const float F_g = control == 0 ? F : (control == 1 ? a_g : orc_adaptive_F(f, np, g, G));
+        if (params) {
+            params[2 * g] = F_g;
+            params[2 * g + 1] = a_g;
+        }
+        orc_de_step(x, np, D, F_g, CR, seed, (uint32_t)g, inst, u, NULL);
         fitness_of_genes(d, u, np, sg, fu);
         for (int64_t i = 0; i < np; ++i)
             if (fu[i] > f[i]) {
@@ -668,7 +743,7 @@ int orc_hwsda_run(const void *h, int64_t np, int64_t G, float F, float CR, uint6
             }
         int32_t L[3];
         orc_top3(f, np, L);
-        orc_gwo_step(x, np, D, L, orc_a_schedule(g, G), seed, (uint32_t)g, inst, variant, u);
+        orc_gwo_step(x, np, D, L, a_g, seed, (uint32_t)g, inst, variant, u);
         fitness_of_genes(d, u, np, sg, fu);
         for (int64_t i = 0; i < np; ++i) {
             if (i == L[0] || i == L[1] || i == L[2]) continue;
@@ -688,4 +763,11 @@ int orc_hwsda_run(const void *h, int64_t np, int64_t G, float F, float CR, uint6
     free(sg);
     free(fu);
     return 0;
+}
+
+/* The optimiser with the textbook parameters (control 0). */
+int orc_hwsda_run(const void *h, int64_t np, int64_t G, float F, float CR, uint64_t seed,
+                  uint32_t inst, int variant, float *x_out, double *f_out, double *trace)
+{
+    return orc_hwsda_run_ctl(h, np, G, F, CR, seed, inst, variant, 0, x_out, f_out, trace, NULL);
 }

@@ -479,3 +479,95 @@ def test_hwsda_ties_keep_the_target(orc):
     x, f, _ = D.hwsda_run(6, 5, 0.5, 0.9, seed=4)
     assert np.array_equal(x, orc.init_pop(6, 1, seed=4))
     assert np.all(f == f[0])
+
+
+# ---- parameter control (Sec. 3.1.1; parameter settings of Sec. 4) ----------
+
+def test_a_control_paper_schedule(orc):
+    # control 1: F = a starts at 0.1 and falls to 0.01 (linear reading);
+    # control 0 is the textbook schedule
+    G = 1000
+    a = np.array([orc.a_control(1, g, G) for g in range(G)])
+    assert a[0] == np.float32(0.1)
+    assert a[500] == np.float32(0.055)
+    assert abs(a[-1] - (0.01 + 0.09 / G)) < 1e-8
+    assert np.all(np.diff(a) < 0)
+    assert all(orc.a_control(0, g, G) == orc.a_schedule(g, G) for g in (0, 1, 499, 999))
+    assert orc.a_control(2, 7, G) == orc.a_control(1, 7, G)
+
+
+def _branch_F(orc, f, G=2):
+    # F at g = 0 (decay law = 0.1 exactly) and at g = G / 2, where
+    # cos(pi / 4) = sqrt(2) / 2 and the quadratic coefficient is 0.95
+    mid = 0.1 * (np.sqrt(2.0) / 2 + 1.0) / 2 * 0.95
+    return orc.adaptive_F(np.asarray(f, float), 0, G), orc.adaptive_F(np.asarray(f, float), G // 2, G), mid
+
+
+def test_adaptive_F_branches(orc):
+    # low spread (s = 0): exploration factor 1.2, clamped at the top
+    F0, Fm, mid = _branch_F(orc, [5e4, 5e4, 5e4, 5e4])
+    assert F0 == np.float32(0.1) and Fm == np.float32(1.2 * mid)
+    # kappa = (10000 - 9500) / 10000 = 0.05 < 0.1 while s = 1500 / 9500 > 0.1
+    F0, Fm, mid = _branch_F(orc, [1e4] * 9 + [5e3])
+    assert Fm == np.float32(1.2 * mid)
+    # large spread: s = 1732 / 1000 > 0.5, kappa = 0.75 -> factor 0.8
+    F0, Fm, mid = _branch_F(orc, [0.0, 0.0, 0.0, 4000.0])
+    assert F0 == np.float32(0.08) and Fm == np.float32(0.8 * mid)
+    # narrow range: s = 70.7 / 500, kappa = 1 / 6, range 200 < 10^3 -> 0.8
+    F0, Fm, mid = _branch_F(orc, [400.0, 500.0, 600.0, 500.0])
+    assert F0 == np.float32(0.08) and Fm == np.float32(0.8 * mid)
+    # intermediate: s = 0.1414, kappa = 1 / 6, range 4000 -> the decay law
+    F0, Fm, mid = _branch_F(orc, [8e3, 1e4, 1.2e4, 1e4])
+    assert F0 == np.float32(0.1) and Fm == np.float32(mid)
+    # low spread wins over a narrow range (the first test decides)
+    F0, Fm, mid = _branch_F(orc, [500.0, 501.0, 502.0, 503.0])
+    assert Fm == np.float32(1.2 * mid)
+
+
+def test_adaptive_F_invariants(orc):
+    # F stays in [0.01, 0.1]; the decay law falls from 0.1 to 0.04, so the
+    # intermediate branch is monotone in g; scaling f by a power of two
+    # changes neither s nor kappa
+    rng = np.random.default_rng(5)
+    G = 64
+    for _ in range(20):
+        f = rng.exponential(1e5, size=int(rng.integers(4, 300)))
+        Fs = np.array([orc.adaptive_F(f, g, G) for g in range(G)])
+        assert np.all((Fs >= np.float32(0.01)) & (Fs <= np.float32(0.1)))
+    f = [8e3, 1e4, 1.2e4, 1e4]
+    Fs = np.array([orc.adaptive_F(np.asarray(f), g, 1000) for g in range(0, 1000, 37)])
+    assert np.all(np.diff(Fs) <= 0) and Fs[-1] > np.float32(0.04)
+    f = rng.exponential(1e5, size=100)
+    assert all(orc.adaptive_F(f, g, G) == orc.adaptive_F(4.0 * f, g, G) for g in range(0, G, 5))
+
+
+@pytest.mark.parametrize("control", [0, 1, 2])
+def test_hwsda_control_consistent_with_steps(orc, control):
+    # two generations of the run equal the steps chained by hand, with F_g
+    # and a_g from the control and, under control 2, F_g from the fitness
+    # of the population that enters generation g
+    n, np_, G = 40, 8, 2
+    D = orc.Design(inputs.uniform_boundaries(n), DK1, DK2)
+    x1, f1, _, par = D.hwsda_run(np_, G, 0.5, 0.9, seed=3, control=control)
+    x = orc.init_pop(np_, n, seed=3)
+    _, f = D.fitness(orc.sign_map(x))
+    for g in range(G):
+        a = orc.a_control(control, g, G)
+        F = 0.5 if control == 0 else (a if control == 1 else orc.adaptive_F(f, g, G))
+        assert par[g, 0] == np.float32(F) and par[g, 1] == np.float32(a)
+        u, _ = orc.de_step(x, F, 0.9, seed=3, g=g)
+        _, fu = D.fitness(orc.sign_map(u))
+        acc = fu > f
+        x[acc] = u[acc]
+        f[acc] = fu[acc]
+        L = orc.top3(f)
+        y = orc.gwo_step(x, L, a, seed=3, g=g)
+        _, fy = D.fitness(orc.sign_map(y))
+        acc = fy > f
+        acc[L] = False
+        x[acc] = y[acc]
+        f[acc] = fy[acc]
+    assert np.array_equal(x, x1) and np.array_equal(f, f1)
+    if control == 0:
+        x0, f0, _ = D.hwsda_run(np_, G, 0.5, 0.9, seed=3)
+        assert np.array_equal(x0, x1)
