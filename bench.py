@@ -257,6 +257,24 @@ def main():
         }
         log("[bench] NP=1024 run: %.1f generations/s" % (1.0 / t3))
 
+        # the same run under the paper's parameter control: F = a from 0.1 to
+        # 0.01, and the adaptive F (one extra one-workgroup statistics kernel
+        # per generation)
+        ctl = {}
+        for name, control in (("decay", qpm.CONTROL_DECAY), ("adaptive", qpm.CONTROL_ADAPTIVE)):
+            Rc = qpm.Run(design, 1024, 5000, CR=CR, seed=0, prec=qpm.PREC_F32, tune=1, control=control)
+            Rc.advance(20)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Rc.advance(400)
+            torch.cuda.synchronize()
+            tc = (time.perf_counter() - t0) / 400
+            Fs = [Rc.params(g)[0] for g in (0, 100, 420)]
+            Rc.destroy()
+            ctl[name] = {"generations_per_s": 1.0 / tc, "F_at_generations_0_100_420": Fs}
+        out["hwsda_np1024_parameter_control"] = ctl
+        log("[bench] NP=1024 parameter control: %s" % ctl)
+
         # batched uneven designs: 64 instances, N ~ U[1000, 50000], width
         # U[1.5, 3] um, dk1 = 2 pi / U[18, 21], dk2 = 2 pi / U[6.2, 7], NP = 256
         specs = inputs.batched_designs(64, seed=1)

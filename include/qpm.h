@@ -263,7 +263,33 @@ typedef struct {
     int32_t tune;        /* 1 = time candidate launch shapes of the fitness
                             and DE kernels at creation and keep the fastest
                             (cached per problem size; QPM_TUNE_CACHE file) */
+    int32_t control;     /* qpm_control: how F_g and a_g are set */
 } qpm_run_config;
+
+/*
+ * Parameter control (paper Sec. 3.1.1 and the parameter settings of
+ * Sec. 4), with t = g / G evaluated in double and rounded to float once:
+ *   QPM_CONTROL_FIXED     F_g = cfg->F, a_g = 2 (1 - t) (Sec. 2.2.2);
+ *   QPM_CONTROL_DECAY     F_g = a_g = 0.1 (1 - t) + 0.01 t: F and a start at
+ *                         0.1 and fall to 0.01 (the paper gives no decay
+ *                         law; linear is this library's reading);
+ *   QPM_CONTROL_ADAPTIVE  a_g as in DECAY; F_g in [0.01, 0.1] from the
+ *                         fitness of the population entering generation g:
+ *                         s = std f / mean f (population std),
+ *                         kappa = (max f - mean f) / max f,
+ *                         range = max f - min f (um^2); factor m = 1.2 if
+ *                         s < 0.1 or kappa < 0.1 (low diversity: explore),
+ *                         else 0.8 if s > 0.5 or range < 1e3 (exploit),
+ *                         else 1; F_g = clamp(m base(g), 0.01, 0.1) with
+ *                         base(g) = 0.1 (cos(pi t / 2) + 1) / 2 (1 - 0.2 t^2),
+ *                         the cosine decay times the quadratic coefficient
+ *                         from 1.0 to 0.8 (thresholds 0.5, factors, the
+ *                         scale 0.1 and the definitions of s and kappa are
+ *                         readings: the paper gives no values for them).
+ * CR stays cfg->CR under every control. Runs of batched designs support
+ * QPM_CONTROL_FIXED only (QPM_ENOTSUP otherwise).
+ */
+typedef enum { QPM_CONTROL_FIXED = 0, QPM_CONTROL_DECAY = 1, QPM_CONTROL_ADAPTIVE = 2 } qpm_control;
 
 typedef struct {
     double best_fitness;  /* f of the best individual */
@@ -276,12 +302,14 @@ typedef struct {
 /*
  * qpm_run_create -- allocate a run and perform step 1 (initialise, evaluate,
  * pick leaders). One generation g (steps 2-6 of paper Sec. 3.2) is then:
- * DE trials (qpm_de_step), evaluation, greedy one-to-one selection (a
- * trial replaces its target only when strictly better), leaders alpha,
- * beta, delta = the three best by (f descending, slot ascending), GWO
- * candidates for every other wolf with a_g = (float)(2 (1 - g / G)),
- * evaluation, greedy selection again (leaders excluded). The run owns its
- * own stream; s is the stream the caller's later reads are ordered with.
+ * DE trials (qpm_de_step) with F_g, evaluation, greedy one-to-one
+ * selection (a trial replaces its target only when strictly better),
+ * leaders alpha, beta, delta = the three best by (f descending, slot
+ * ascending), GWO candidates for every other wolf with a_g, evaluation,
+ * greedy selection again (leaders excluded); F_g and a_g per cfg->control
+ * (qpm_control). The run owns its own stream; s is the stream the caller's
+ * later reads are ordered with. Errors: QPM_EINVAL for an out-of-range
+ * field (np, G, F, CR, prec, gwo_variant, inst, fit_kernel, control).
  */
 qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_stream s,
                           qpm_run_handle *out);
@@ -304,6 +332,13 @@ qpm_status qpm_run_read(qpm_run_handle r, float *x, int64_t ldx, void *fitness, 
  * be NULL), best_bits (device, W words, may be NULL), stats (host, may be
  * NULL). Synchronous. */
 qpm_status qpm_run_best(qpm_run_handle r, float *best_x, uint32_t *best_bits, qpm_run_stats *stats);
+
+/* F_g and a_g (host outputs, either may be NULL) of generation g, for
+ * 0 <= g <= the generations completed (g < G): the values that generation
+ * uses or used. Under QPM_CONTROL_ADAPTIVE, F_g exists once the population
+ * entering g is known, so g past the completed count is QPM_EINVAL, as is
+ * g >= G. Synchronous. */
+qpm_status qpm_run_params(qpm_run_handle r, int64_t g, float *F, float *a);
 
 /*
  * qpm_run_load -- replace the current population with caller genes x

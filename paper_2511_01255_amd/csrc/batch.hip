@@ -1026,6 +1026,7 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
     QPM_REQUIRE(c.CR >= 0.0f && c.CR <= 1.0f, QPM_EINVAL, "CR must be in [0, 1]");
     QPM_REQUIRE(c.prec == QPM_PREC_F32 || c.prec == QPM_PREC_F64, QPM_EINVAL, "unknown precision %d", c.prec);
     QPM_REQUIRE(c.gwo_variant == 0 || c.gwo_variant == 1, QPM_EINVAL, "gwo_variant must be 0 or 1");
+    QPM_REQUIRE(c.control == QPM_CONTROL_FIXED, QPM_ENOTSUP, "batched runs use the fixed parameter control only");
     QPM_REQUIRE(static_cast<int64_t>(c.inst) + b->n_inst <= (int64_t(1) << 24), QPM_EINVAL,
                 "inst + n_inst must be <= 2^24");
     qpm_status st = check_device();

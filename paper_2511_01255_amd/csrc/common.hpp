@@ -86,9 +86,10 @@ size_t fitness_partials_bytes(const FitPlan &plan, int64_t ld);
 qpm_status launch_fitness_partials(const Design &d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
                                    const FitPlan &plan, double *part, hipStream_t s);
 // Finish one evaluation of a run: combine the triples of genome i into f,
-// select (f > f_cur[i] replaces, leaders in skip3 excluded), then in the
-// last workgroup: top3_out <- leaders (when non-null); with draws_next the
-// DE draws of generation gen + 1 are written and gen is advanced.
+// select (f > f_cur[i] replaces, leaders in skip3 excluded), then in a
+// one-workgroup kernel: top3_out <- leaders (when non-null); with
+// draws_next the DE draws of generation gen + 1 are written and gen is
+// advanced.
 // fbits (optional): packed copy of flags, 2 ceil(np / 64) words; cand:
 // scratch of finish_cand_bytes(np) for the leader candidates (needed with
 // top3_out)
@@ -100,6 +101,11 @@ inline size_t finish_cand_bytes(int64_t np)
 {
     return static_cast<size_t>((np + 63) / 64) * 3 * (sizeof(double) + sizeof(int32_t));
 }
+// Adaptive F of the generation in the device counter g = gen[0] (nothing
+// when g >= G): F_tab[g] from the statistics of f (np floats or doubles)
+// and the decay law F_base[g]
+qpm_status launch_adapt_F(const void *f, bool f64, int64_t np, const uint32_t *gen, int64_t G, const double *F_base,
+                          float *F_tab, hipStream_t s);
 
 // ---------------------------------------------------------------- evolution kernels
 
@@ -133,7 +139,8 @@ inline uint32_t cr_threshold(float CR)
 // packed copy of pv.flags (bit i % 32 of word i / 32)
 qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const uint32_t *gen_dev,
                      uint32_t gen, uint32_t inst, uint32_t *bits, int64_t ld, int4 *draws, bool compute_draws,
-                     hipStream_t s, int ipw = 0, int passes = 1, const uint32_t *fbits = nullptr);
+                     hipStream_t s, int ipw = 0, int passes = 1, const uint32_t *fbits = nullptr,
+                     const float *F_tab = nullptr);
 // segmented plan with an explicit shape
 FitPlan plan_fitness_shape(const Design &d, int waves, int wpw);
 // table plan: gw genome groups of 64 per workgroup, wpw words per wave

@@ -76,7 +76,8 @@ __global__ __launch_bounds__(256) void de_draws_kernel(int64_t np, int64_t D, ui
 // Otherwise the flags (if any) are read from global memory.
 template <int IPW, int R, bool PACKED>
 __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restrict__ draws,
-                                                 const uint32_t *__restrict__ fbits, float F, uint32_t cr_max,
+                                                 const uint32_t *__restrict__ fbits, float F,
+                                                 const float *__restrict__ F_tab, uint32_t cr_max,
                                                  uint32_t k0, uint32_t k1, const uint32_t *__restrict__ gen_dev,
                                                  uint32_t gen_c, uint32_t inst, uint32_t *__restrict__ bits,
                                                  int64_t ld, int groups, int chunks)
@@ -100,6 +101,7 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
     const int64_t i0 = static_cast<int64_t>(gi) * IPB + local;
     const int64_t j0 = static_cast<int64_t>(c) * CW + 4 * li;
     const uint32_t g = gen_dev ? gen_dev[0] : gen_c;
+    const float Fg = F_tab ? F_tab[g] : F;  // a run's per-generation F
     __shared__ uint32_t wsh[IPB][WPC];
     extern __shared__ uint32_t sfb[];  // PACKED: (np + 31) / 32 flag words
     int4 dr[R];
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
         if (act[r]) {
             const int64_t i = i0 + r * IPG;
             const float4 uv = de_quad(cur[0], cur[1], cur[2], cur[3], j0, dr[r].w, static_cast<uint32_t>(i), g, inst,
-                                      k0, k1, F, cr_max);
+                                      k0, k1, Fg, cr_max);
             float *dst;
             if constexpr (PACKED)
                 dst = pv.out0 + packed_row(i, 1u);
@@ -302,8 +304,9 @@ qpm_status launch_init(int64_t np, int64_t D, int64_t ldx, uint64_t seed, uint32
 
 qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const uint32_t *gen_dev, uint32_t gen,
                      uint32_t inst, uint32_t *bits, int64_t ld, int4 *draws, bool compute_draws, hipStream_t s,
-                     int ipw_req, int passes, const uint32_t *fbits)
+                     int ipw_req, int passes, const uint32_t *fbits, const float *F_tab)
 {
+    QPM_REQUIRE(F_tab == nullptr || gen_dev != nullptr, QPM_EINVAL, "an F table needs the device generation");
     // the packed-flag path: one allocation for both buffers, flags staged
     // in LDS (at most 65536 individuals, 8 KB), 24-bit row arithmetic
     const bool packed = fbits != nullptr && pv.np <= 65536 && pv.ldx < (int64_t(1) << 24) &&
@@ -328,11 +331,11 @@ qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const 
     const unsigned nb = static_cast<unsigned>(blocks);
 #define QPM_DE(I, P)                                                                                            \
     if (packed)                                                                                                 \
-        de_kernel<I, P, true><<<nb, 256, lds, s>>>(pv, draws, fbits, F, cr_max, k0, k1, gen_dev, gen, inst, bits, \
-                                                   ld, gr, ch);                                                 \
+        de_kernel<I, P, true><<<nb, 256, lds, s>>>(pv, draws, fbits, F, F_tab, cr_max, k0, k1, gen_dev, gen,     \
+                                                   inst, bits, ld, gr, ch);                                     \
     else                                                                                                        \
-        de_kernel<I, P, false><<<nb, 256, 0, s>>>(pv, draws, nullptr, F, cr_max, k0, k1, gen_dev, gen, inst, bits, \
-                                                  ld, gr, ch);
+        de_kernel<I, P, false><<<nb, 256, 0, s>>>(pv, draws, nullptr, F, F_tab, cr_max, k0, k1, gen_dev, gen,    \
+                                                  inst, bits, ld, gr, ch);
     if (ipw == 1) {
         if (R == 1) { QPM_DE(1, 1) } else if (R == 2) { QPM_DE(1, 2) } else { QPM_DE(1, 4) }
     } else if (ipw == 2) {

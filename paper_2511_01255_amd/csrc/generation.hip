@@ -96,6 +96,89 @@ __global__ __launch_bounds__(256) void finish_tail_kernel(const T *__restrict__ 
     if (advance && threadIdx.x == 0) gen[0] += 1u;
 }
 
+// Sum, maximum and minimum over the 1024 threads of the workgroup in a
+// fixed order (butterfly within each wave, then the 16 wave results in
+// order by every thread), so the result does not depend on timing.
+__device__ __forceinline__ void block_sum_max_min(double &s, double &mx, double &mn, double *sh)
+{
+    for (int o = 1; o < 64; o <<= 1) {
+        s += __shfl_xor(s, o);
+        mx = fmax(mx, __shfl_xor(mx, o));
+        mn = fmin(mn, __shfl_xor(mn, o));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[3 * w] = s;
+        sh[3 * w + 1] = mx;
+        sh[3 * w + 2] = mn;
+    }
+    __syncthreads();
+    s = sh[0];
+    mx = sh[1];
+    mn = sh[2];
+    for (int k = 1; k < 16; ++k) {
+        s += sh[3 * k];
+        mx = fmax(mx, sh[3 * k + 1]);
+        mn = fmin(mn, sh[3 * k + 2]);
+    }
+    __syncthreads();
+}
+
+// The adaptive scale factor of paper Sec. 3.1.1 for generation g from the
+// fitness of the population entering it: relative spread s = std / mean,
+// kappa = (max - mean) / max (how far the mean trails the best), range =
+// max - min. Low diversity (s < 0.1 or kappa < 0.1) raises F by 1.2; too
+// much spread or a narrow range (s > 0.5 or range < 1e3) lowers it by 0.8;
+// the factor scales the decay law F_base[g] and the result is kept in
+// [0.01, 0.1]. Two passes (mean, then squared deviations) in FP64.
+template <typename T>
+__global__ __launch_bounds__(1024) void adapt_F_kernel(const T *__restrict__ f, int64_t np,
+                                                       const uint32_t *__restrict__ gen, int64_t G,
+                                                       const double *__restrict__ F_base, float *__restrict__ F_tab)
+{
+    __shared__ double sh[48];
+    const int64_t g = gen[0];
+    if (g >= G) return;
+    double s = 0.0, mx = -INFINITY, mn = INFINITY;
+    for (int64_t i = threadIdx.x; i < np; i += 1024) {
+        const double v = static_cast<double>(f[i]);
+        s += v;
+        mx = fmax(mx, v);
+        mn = fmin(mn, v);
+    }
+    block_sum_max_min(s, mx, mn, sh);
+    const double mean = s / static_cast<double>(np);
+    double ss = 0.0, d0 = 0.0, d1 = 0.0;
+    for (int64_t i = threadIdx.x; i < np; i += 1024) {
+        const double d = static_cast<double>(f[i]) - mean;
+        ss += d * d;
+    }
+    block_sum_max_min(ss, d0, d1, sh);
+    if (threadIdx.x == 0) {
+        const double sd = sqrt(ss / static_cast<double>(np));
+        const double rel = mean > 0.0 ? sd / mean : 0.0;
+        const double kappa = mx > 0.0 ? (mx - mean) / mx : 0.0;
+        double m = 1.0;
+        if (rel < 0.1 || kappa < 0.1)
+            m = 1.2;
+        else if (rel > 0.5 || mx - mn < 1e3)
+            m = 0.8;
+        const double F = fmin(fmax(F_base[g] * m, 0.01), 0.1);
+        F_tab[g] = static_cast<float>(F);
+    }
+}
+
+qpm_status launch_adapt_F(const void *f, bool f64, int64_t np, const uint32_t *gen, int64_t G, const double *F_base,
+                          float *F_tab, hipStream_t s)
+{
+    if (f64)
+        adapt_F_kernel<double><<<1, 1024, 0, s>>>(static_cast<const double *>(f), np, gen, G, F_base, F_tab);
+    else
+        adapt_F_kernel<float><<<1, 1024, 0, s>>>(static_cast<const float *>(f), np, gen, G, F_base, F_tab);
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
+}
+
 qpm_status launch_finish(const double *part, int gy, int64_t ld, int64_t np, const double *C, void *f_cur, bool f64,
                          uint32_t *flags, uint32_t *fbits, const int32_t *skip3, int32_t *top3_out, void *cand,
                          int4 *draws_next, uint32_t *gen, int64_t D, uint64_t seed, uint32_t inst, hipStream_t s)

@@ -4,10 +4,12 @@
 // that holds the current row (selection flips a flag instead of copying a
 // row); fitness of the current rows; one bit buffer reused for the DE
 // trials and the GWO candidates; the leaders; a device generation counter
-// and a table of a_g. One generation is a fixed sequence of launches that
+// and tables of a_g and F_g (the adaptive control writes F_g on the device
+// once the population entering generation g is known). One generation is a fixed sequence of launches that
 // reads g from the counter, so it is captured once into a HIP graph and
 // replayed G times with no host work or synchronisation in between.
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -35,6 +37,8 @@ struct qpm_run_s {
     int32_t *best = nullptr;
     uint32_t *gen = nullptr;
     float *a_tab = nullptr;
+    float *F_tab = nullptr;     // F_g per generation
+    double *F_base = nullptr;   // decay law of the adaptive control
     int4 *draws = nullptr;
     double *fws = nullptr;
     FitPlan plan;
@@ -61,6 +65,7 @@ struct qpm_run_s {
     double *pol_edges = nullptr;  // relaxation edges of the 3 rows (both precisions' sizes)
 
     bool f64() const { return cfg.prec == QPM_PREC_F64; }
+    bool adaptive() const { return cfg.control == QPM_CONTROL_ADAPTIVE; }
     PopView view() const { return PopView{buf[0], buf[1], flags, buf[0], buf[1], cfg.np, D, ldx}; }
 };
 
@@ -83,6 +88,8 @@ static void release(qpm_run_s *r)
     (void)hipFree(r->best);
     (void)hipFree(r->gen);
     (void)hipFree(r->a_tab);
+    (void)hipFree(r->F_tab);
+    (void)hipFree(r->F_base);
     (void)hipFree(r->fws);
     (void)hipFree(r->draws);
     (void)hipFree(r->pol);
@@ -117,7 +124,7 @@ static qpm_status enqueue_generation(qpm_run_s *r, hipEvent_t *ev = nullptr)
     const int gy = r->plan.kind == QPM_FIT_PER_GENOME ? 1 : r->plan.gy;
     const double *C = r->d->Cdev;
     QPM_STEP(QPM_K_DE, launch_de(pv, c.F, c.CR, c.seed, r->gen, 0u, c.inst, r->tbits, r->ld, r->draws, false, r->st,
-                                 r->de_ipw, r->de_passes, r->fbits))
+                                 r->de_ipw, r->de_passes, r->fbits, r->F_tab))
     QPM_STEP(QPM_K_FIT_DE, launch_fitness_partials(*r->d, p, r->tbits, c.np, r->ld, r->plan, r->fws, r->st))
     QPM_STEP(QPM_K_FINISH_DE, launch_finish(r->fws, gy, r->ld, c.np, C, r->f_cur, r->f64(), r->flags, r->fbits,
                                             nullptr, r->leaders, r->cand, nullptr, r->gen, r->D, c.seed, c.inst,
@@ -128,6 +135,10 @@ static qpm_status enqueue_generation(qpm_run_s *r, hipEvent_t *ev = nullptr)
     QPM_STEP(QPM_K_FINISH_GWO, launch_finish(r->fws, gy, r->ld, c.np, C, r->f_cur, r->f64(), r->flags, r->fbits,
                                              r->leaders, nullptr, nullptr, r->draws, r->gen, r->D, c.seed, c.inst,
                                              r->st))
+    if (r->adaptive()) {  // F of the next generation (timed with the finish)
+        st = launch_adapt_F(r->f_cur, r->f64(), c.np, r->gen, c.generations, r->F_base, r->F_tab, r->st);
+        if (st != QPM_OK) return st;
+    }
 #undef QPM_STEP
     return mark(QPM_K_COUNT);
 }
@@ -310,6 +321,9 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
                 QPM_EINVAL, "unknown fitness kernel %d", c.fit_kernel);
     QPM_REQUIRE(!(c.fit_kernel == QPM_FIT_PER_GENOME && c.prec != QPM_PREC_F64), QPM_EINVAL,
                 "the per-genome kernel computes in FP64 only");
+    QPM_REQUIRE(c.control == QPM_CONTROL_FIXED || c.control == QPM_CONTROL_DECAY ||
+                    c.control == QPM_CONTROL_ADAPTIVE,
+                QPM_EINVAL, "unknown parameter control %d", c.control);
     qpm_status st = check_device();
     if (st != QPM_OK) return st;
 
@@ -338,16 +352,31 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     if (e == hipSuccess) e = hipMalloc(&r->best, sizeof(int32_t) * 3);
     if (e == hipSuccess) e = hipMalloc(&r->gen, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&r->a_tab, sizeof(float) * c.generations);
+    if (e == hipSuccess) e = hipMalloc(&r->F_tab, sizeof(float) * c.generations);
+    if (e == hipSuccess && r->adaptive()) e = hipMalloc(&r->F_base, sizeof(double) * c.generations);
     if (e == hipSuccess) e = hipMalloc(&r->draws, sizeof(int4) * c.np);
     if (e != hipSuccess) {
         set_error("run allocation failed: %s", hipGetErrorString(e));
         release(r);
         return e == hipErrorOutOfMemory ? QPM_ENOMEM : QPM_EHIP;
     }
-    // a_g = 2 (1 - g / G): linear from 2 towards 0, evaluated in double
-    std::vector<float> a(c.generations);
-    for (int64_t g = 0; g < c.generations; ++g)
-        a[g] = static_cast<float>(2.0 * (1.0 - static_cast<double>(g) / static_cast<double>(c.generations)));
+    // a_g and F_g per control, evaluated in double with t = g / G:
+    // fixed: a_g = 2 (1 - t) and F_g = F; decay: F_g = a_g = 0.1 (1 - t) +
+    // 0.01 t; adaptive: a_g as in decay, F_g written on the device from the
+    // decay law base(g) = 0.1 (cos(pi t / 2) + 1) / 2 (1 - 0.2 t^2)
+    std::vector<float> a(c.generations), F(c.generations);
+    std::vector<double> base(r->adaptive() ? c.generations : 0);
+    for (int64_t g = 0; g < c.generations; ++g) {
+        const double t = static_cast<double>(g) / static_cast<double>(c.generations);
+        if (c.control == QPM_CONTROL_FIXED) {
+            a[g] = static_cast<float>(2.0 * (1.0 - t));
+            F[g] = c.F;
+        } else {
+            a[g] = static_cast<float>(0.1 * (1.0 - t) + 0.01 * t);
+            F[g] = a[g];
+        }
+        if (r->adaptive()) base[g] = 0.1 * (0.5 * (std::cos(0.5 * M_PI * t) + 1.0)) * (1.0 - 0.2 * t * t);
+    }
 
     hipEvent_t ev = nullptr;
     e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
@@ -355,12 +384,16 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     if (e == hipSuccess) e = hipStreamWaitEvent(r->st, ev, 0);
     if (e == hipSuccess)
         e = hipMemcpyAsync(r->a_tab, a.data(), sizeof(float) * c.generations, hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(r->F_tab, F.data(), sizeof(float) * c.generations, hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess && r->adaptive())
+        e = hipMemcpyAsync(r->F_base, base.data(), sizeof(double) * c.generations, hipMemcpyHostToDevice, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->flags, 0, sizeof(uint32_t) * c.np, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->fbits, 0, sizeof(uint32_t) * 2 * ((c.np + 63) / 64), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->gen, 0, sizeof(uint32_t), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->tbits, 0, sizeof(uint32_t) * r->W * r->ld, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->buf[1], 0, gene_bytes, r->st);
-    if (e == hipSuccess) e = hipStreamSynchronize(r->st);  // a.data() must outlive the copy
+    if (e == hipSuccess) e = hipStreamSynchronize(r->st);  // the host tables must outlive the copies
     if (ev) (void)hipEventDestroy(ev);
     if (e != hipSuccess) {
         set_error("run set-up failed: %s", hipGetErrorString(e));
@@ -385,6 +418,8 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     if (st == QPM_OK) st = launch_fitness(*d, p, r->tbits, c.np, r->ld, r->f_cur, r->plan, r->fws, r->st);
     if (st == QPM_OK) st = launch_top3(r->f_cur, c.np, r->f64(), r->leaders, r->st);
     if (st == QPM_OK) st = launch_draws(c.np, r->D, c.seed, r->gen, c.inst, r->draws, r->st);
+    if (st == QPM_OK && r->adaptive())
+        st = launch_adapt_F(r->f_cur, r->f64(), c.np, r->gen, c.generations, r->F_base, r->F_tab, r->st);
     if (st == QPM_OK && c.use_graph) {
         st = capture_generations(r, 1, &r->graph, &r->exec);
         if (st == QPM_OK && c.generations >= 2 * kGraphGens)
@@ -473,7 +508,26 @@ QPM_API qpm_status qpm_run_load(qpm_run_handle r, const float *x, int64_t ldx)
                             r->st);
     if (st == QPM_OK) st = launch_top3(r->f_cur, c.np, r->f64(), r->leaders, r->st);
     if (st == QPM_OK) st = launch_draws(c.np, r->D, c.seed, r->gen, c.inst, r->draws, r->st);
+    if (st == QPM_OK && r->adaptive())  // F of the coming generation from the loaded population
+        st = launch_adapt_F(r->f_cur, r->f64(), c.np, r->gen, c.generations, r->F_base, r->F_tab, r->st);
     return st;
+}
+
+QPM_API qpm_status qpm_run_params(qpm_run_handle r, int64_t g, float *F, float *a)
+{
+    clear_error();
+    QPM_REQUIRE(r != nullptr, QPM_EINVAL, "run is NULL");
+    QPM_REQUIRE(g >= 0 && g < r->cfg.generations, QPM_EINVAL, "generation %lld outside [0, G)", (long long)g);
+    QPM_REQUIRE(!r->adaptive() || g <= r->done, QPM_EINVAL,
+                "the adaptive F of generation %lld is not known yet (%lld completed)", (long long)g,
+                (long long)r->done);
+    float v[2] = {0.0f, 0.0f};
+    QPM_TRY_HIP(hipMemcpyAsync(&v[0], r->F_tab + g, sizeof(float), hipMemcpyDeviceToHost, r->st));
+    QPM_TRY_HIP(hipMemcpyAsync(&v[1], r->a_tab + g, sizeof(float), hipMemcpyDeviceToHost, r->st));
+    QPM_TRY_HIP(hipStreamSynchronize(r->st));
+    if (F) *F = v[0];
+    if (a) *a = v[1];
+    return QPM_OK;
 }
 
 QPM_API qpm_status qpm_run_read(qpm_run_handle r, float *x, int64_t ldx, void *fitness, int32_t *leaders,
@@ -585,6 +639,8 @@ QPM_API qpm_status qpm_run_polish(qpm_run_handle r, int32_t steps, float eta, in
         QPM_TRY_HIP(hipMemsetAsync(r->pol_acc, 0, sizeof(uint32_t), r->st));
         st = launch_polish_accept(y, D, ldx, r->pol_fc, r->f64(), r->leaders, pv, r->f_cur, r->pol_acc, r->st);
     }
+    if (st == QPM_OK && r->adaptive())  // the population entering the next generation changed
+        st = launch_adapt_F(r->f_cur, r->f64(), c.np, r->gen, c.generations, r->F_base, r->F_tab, r->st);
     if (st != QPM_OK) return st;
     uint32_t acc = 0;
     QPM_TRY_HIP(hipMemcpyAsync(&acc, r->pol_acc, sizeof(acc), hipMemcpyDeviceToHost, r->st));

@@ -17,6 +17,9 @@ FIT_AUTO = 0
 FIT_SEGMENTED = 1
 FIT_PER_GENOME = 2
 FIT_TABLE = 3
+CONTROL_FIXED = 0     # F constant, a from 2 to 0
+CONTROL_DECAY = 1     # F = a from 0.1 to 0.01
+CONTROL_ADAPTIVE = 2  # adaptive F in [0.01, 0.1], a from 0.1 to 0.01
 # timing slots of one generation (QPM_K_*)
 STEP_NAMES = ["de", "fitness_de", "finish_de", "gwo", "fitness_gwo", "finish_gwo"]
 
@@ -38,7 +41,7 @@ class QpmError(RuntimeError):
 class RunConfig(C.Structure):
     _fields_ = [("np", _I64), ("generations", _I64), ("F", _F), ("CR", _F), ("seed", _U64),
                 ("inst", _U32), ("prec", _I32), ("gwo_variant", _I32), ("use_graph", _I32),
-                ("fit_kernel", _I32), ("tune", _I32)]
+                ("fit_kernel", _I32), ("tune", _I32), ("control", _I32)]
 
 
 class RunStats(C.Structure):
@@ -69,6 +72,7 @@ _SIGS = {
     "qpm_run_advance": (_I32, [_P, _I64]),
     "qpm_run_read": (_I32, [_P, _P, _I64, _P, _P, _P]),
     "qpm_run_best": (_I32, [_P, _P, _P, C.POINTER(RunStats)]),
+    "qpm_run_params": (_I32, [_P, _I64, _P, _P]),
     "qpm_run_destroy": (_I32, [_P]),
     "qpm_run_load": (_I32, [_P, _P, _I64]),
     "qpm_run_polish": (_I32, [_P, _I32, _F, _P]),
@@ -315,18 +319,20 @@ def relax(theta, design, prec=PREC_F32):
 
 
 def _config(np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0, use_graph=1,
-            fit_kernel=FIT_AUTO, tune=0):
+            fit_kernel=FIT_AUTO, tune=0, control=0):
     return RunConfig(np=np_, generations=generations, F=F, CR=CR, seed=seed, inst=inst, prec=prec,
-                     gwo_variant=gwo_variant, use_graph=use_graph, fit_kernel=fit_kernel, tune=tune)
+                     gwo_variant=gwo_variant, use_graph=use_graph, fit_kernel=fit_kernel, tune=tune,
+                     control=control)
 
 
 class Run:
     """A whole optimisation on the device (run_create / advance / read / best)."""
 
     def __init__(self, design, np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0,
-                 use_graph=1, fit_kernel=FIT_AUTO, tune=0, stream=None):
+                 use_graph=1, fit_kernel=FIT_AUTO, tune=0, control=CONTROL_FIXED, stream=None):
         self.design = design
-        self.cfg = _config(np_, generations, F, CR, seed, inst, prec, gwo_variant, use_graph, fit_kernel, tune)
+        self.cfg = _config(np_, generations, F, CR, seed, inst, prec, gwo_variant, use_graph, fit_kernel, tune,
+                           control)
         self.D = design.n
         h = C.c_void_p()
         _check(lib().qpm_run_create(design.handle, C.byref(self.cfg), _stream(stream), C.byref(h)))
@@ -356,6 +362,13 @@ class Run:
     def load(self, x):
         """x: float32 CUDA tensor (np, >= D) -> becomes the population."""
         _check(lib().qpm_run_load(self._h, _ptr(x), x.shape[1]))
+
+    def params(self, g):
+        """(F_g, a_g) of generation g."""
+        F = C.c_float()
+        a = C.c_float()
+        _check(lib().qpm_run_params(self._h, g, C.byref(F), C.byref(a)))
+        return F.value, a.value
 
     def polish(self, steps=20, eta=0.05):
         """Gradient polish of the three leaders; returns how many improved."""

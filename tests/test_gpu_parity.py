@@ -281,6 +281,62 @@ def test_run_fp64_trajectory_edge_cases(q, orc, case):
     R.destroy()
 
 
+@pytest.mark.parametrize("control", [1, 2])
+@pytest.mark.parametrize("graph", [1, 0])
+def test_run_parameter_control_fp64_equals_oracle(q, orc, control, graph):
+    # F = a from 0.1 to 0.01, and the adaptive F (its three branches all
+    # occur in this run: 0.8 early, 1, then 1.2): every generation's F_g and
+    # a_g and the final genes equal the oracle's; G = 25 replays the
+    # 8-generation graph and the single one
+    n, npop, G = 300, 64, 25
+    z = inputs.uniform_boundaries(n, 2.0)
+    D = q.precompute_phases(z, DK1, DK2)
+    xo, fo, _, par = orc.Design(z, DK1, DK2).hwsda_run(npop, G, 0.5, 0.9, 5, control=control)
+    R = q.Run(D, npop, G, seed=5, prec=1, control=control, use_graph=graph)
+    assert R.params(0) == (par[0, 0], par[0, 1])
+    if control == 2:
+        with pytest.raises(q.QpmError):
+            R.params(1)  # not known before generation 0 has run
+    R.advance(G)
+    x, f, _, _ = R.read()
+    assert np.array_equal(x.cpu().numpy(), xo)
+    assert np.max(np.abs(f.cpu().numpy() - fo) / fo) <= 1e-12
+    got = np.array([R.params(g) for g in range(G)], dtype=np.float32)
+    assert np.array_equal(got, par)
+    with pytest.raises(q.QpmError):
+        R.params(G)
+    R.destroy()
+
+
+def test_run_adaptive_F_fp32_from_its_own_population(q, orc):
+    # FP32 fitness: the F of each generation is the rule applied to the
+    # float fitness of the population that enters it; a load and a polish
+    # recompute it from the changed population
+    n, npop, G = 700, 100, 12
+    D = q.precompute_phases(inputs.uniform_boundaries(n, 2.0), DK1, DK2)
+    R = q.Run(D, npop, G, seed=8, prec=0, control=2)
+    for g in range(G - 2):
+        f = R.read()[1].double().cpu().numpy()
+        assert R.params(g)[0] == orc.adaptive_F(f, g, G), g
+        R.advance(1)
+    import torch
+    xs = torch.from_numpy(inputs.random_signs(npop, n, seed=3).astype(np.float32) * 0.5)
+    R.load(xs.cuda())
+    f = R.read()[1].double().cpu().numpy()
+    assert R.params(G - 2)[0] == orc.adaptive_F(f, G - 2, G)
+    R.polish(5, 0.05)
+    f = R.read()[1].double().cpu().numpy()
+    assert R.params(G - 2)[0] == orc.adaptive_F(f, G - 2, G)
+    R.advance(2)
+    R.destroy()
+
+
+def test_run_rejects_unknown_control(q):
+    D = q.precompute_phases(inputs.uniform_boundaries(10, 2.0), DK1, DK2)
+    with pytest.raises(q.QpmError):
+        q.Run(D, 8, 2, control=3)
+
+
 def test_run_graph_and_eager_agree(q):
     n, npop, G = 300, 20, 15
     D = q.precompute_phases(inputs.uniform_boundaries(n, 2.0), DK1, DK2)
