@@ -59,6 +59,9 @@ def lib():
             "orc_hwsda_run": (_INT, [_P, _I64, _I64, _F, _F, _U64, _U32, _INT, _P, _P, _P]),
             "orc_hwsda_run_ctl": (_INT, [_P, _I64, _I64, _F, _F, _U64, _U32, _INT, _INT, _P, _P, _P, _P]),
             "orc_a_control": (_F, [_INT, _I64, _I64]),
+            "orc_multi_objective": (_INT, [_P, _INT, _INT, _D, _D, _P, _I64, _P, _P]),
+            "orc_hwsda_run_obj": (_INT, [_P, _INT, _INT, _D, _D, _I64, _I64, _F, _F, _U64, _U32, _INT, _INT, _P,
+                                         _P, _P, _P]),
             "orc_adaptive_F": (_F, [_P, _I64, _I64, _I64]),
         }
         for name, (res, args) in sig.items():
@@ -162,6 +165,41 @@ class Design:
         par = np.zeros((G, 2), dtype=np.float32)
         rc = lib().orc_hwsda_run_ctl(self._h, np_, G, F, CR, seed, inst, variant, control, _ptr(x), _ptr(f),
                                      _ptr(tr), _ptr(par))
+        if rc != 0:
+            raise ValueError("invalid run arguments")
+        return x, f, tr, par
+
+
+class Objective:
+    """The multi-wavelength objective over K oracle designs that share
+    their boundaries: kind 0 = SHG, 1 = THG (f = -h, maximised)."""
+
+    def __init__(self, designs, kind, G0, beta):
+        self.designs = list(designs)  # keeps the designs alive
+        self.K = len(self.designs)
+        self.n = self.designs[0].n
+        self.kind, self.G0, self.beta = int(kind), float(G0), float(beta)
+        self._arr = (C.c_void_p * self.K)(*[d._h for d in self.designs])
+
+    def __call__(self, d):
+        """d: (np, n) of +-1 -> (G (np, K), f (np,))."""
+        d = np.ascontiguousarray(d, dtype=np.int8).reshape(-1, self.n)
+        npop = d.shape[0]
+        G = np.zeros((npop, self.K))
+        f = np.zeros(npop)
+        rc = lib().orc_multi_objective(self._arr, self.K, self.kind, self.G0, self.beta, _ptr(d), npop, _ptr(G),
+                                       _ptr(f))
+        if rc != 0:
+            raise ValueError("designs differ in their boundaries, or bad arguments")
+        return G, f
+
+    def hwsda_run(self, np_, G, F, CR, seed, inst=0, variant=0, control=0):
+        x = np.zeros((np_, self.n), dtype=np.float32)
+        f = np.zeros(np_)
+        tr = np.zeros(G)
+        par = np.zeros((G, 2), dtype=np.float32)
+        rc = lib().orc_hwsda_run_obj(self._arr, self.K, self.kind, self.G0, self.beta, np_, G, F, CR, seed, inst,
+                                     variant, control, _ptr(x), _ptr(f), _ptr(tr), _ptr(par))
         if rc != 0:
             raise ValueError("invalid run arguments")
         return x, f, tr, par

@@ -698,10 +698,83 @@ float orc_adaptive_F(const double *f, int64_t np, int64_t g, int64_t G)
     return (float)F;
 }
 
-static void fitness_of_genes(const orc_design *d, const float *x, int64_t np, int8_t *scratch, double *f)
+/* ------------------------------------------------------------------ */
+/* multi-wavelength objective (the multi-wavelength SHG and coupled THG  */
+/* designs of the paper's last section)                                 */
+/* ------------------------------------------------------------------ */
+
+/* K designs on the same boundaries z, one per wavelength (its dk1, dk2),
+ * L = z_N - z_0. Per genome and wavelength k:
+ *   SHG (kind 0): G_k = |int d(z) e^{-i dk1_k z} dz| / L
+ *                     = |sum_n d_n a_n^(k)| / L, the single-integral
+ *                 coupling of second-harmonic generation;
+ *   THG (kind 1): G_k = |S_k| / L^2, the coupled double integral of
+ *                 Sec. 2.1 with the k-th (dk1, dk2).
+ * The paper's objective h = sum_k |G0 - G_k| + beta (max_k G_k - min_k G_k)
+ * is minimised; the optimiser maximises f = -h. Normalising G by L (SHG)
+ * and L^2 (THG) makes G dimensionless (at most 1), so G0 and beta are too:
+ * a reading, the paper does not state its scale.
+ * dd: np x n int8; G (may be NULL): np x K; f: np. Returns -1 when the
+ * designs differ in their boundaries or an argument is out of range. */
+static int multi_valid(const void *const *designs, int K, int kind)
 {
-    orc_sign_map(x, np * d->n, scratch);
-    orc_fitness(d, scratch, np, NULL, f);
+    if (K < 1 || (kind != 0 && kind != 1)) return 0;
+    const orc_design *d0 = designs[0];
+    for (int k = 1; k < K; ++k) {
+        const orc_design *dk = designs[k];
+        if (dk->n != d0->n) return 0;
+        for (int64_t i = 0; i <= d0->n; ++i)
+            if (dk->z[i] != d0->z[i]) return 0;
+    }
+    return 1;
+}
+
+int orc_multi_objective(const void *const *designs, int K, int kind, double G0, double beta, const int8_t *dd,
+                        int64_t np, double *G, double *f)
+{
+    if (!multi_valid(designs, K, kind)) return -1;
+    const orc_design *d0 = designs[0];
+    const int64_t n = d0->n;
+    const ld L = d0->z[n] - d0->z[0];
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t g = 0; g < np; ++g) {
+        const int8_t *dg = dd + g * n;
+        ld sum = 0.0L, gmax = 0.0L, gmin = 0.0L;
+        for (int k = 0; k < K; ++k) {
+            const orc_design *dk = designs[k];
+            cld P = 0.0L, Q = 0.0L;
+            for (int64_t m = 0; m < n; ++m) {
+                ld s = (ld)dg[m];
+                Q += s * dk->b[m] * P;
+                P += s * dk->a[m];
+            }
+            ld Gk = kind == 0 ? cabsl(P) / L : cabsl(Q + dk->C) / (L * L);
+            if (G) G[g * K + k] = (double)Gk;
+            sum += fabsl((ld)G0 - Gk);
+            if (k == 0 || Gk > gmax) gmax = Gk;
+            if (k == 0 || Gk < gmin) gmin = Gk;
+        }
+        f[g] = (double)(-(sum + (ld)beta * (gmax - gmin)));
+    }
+    return 0;
+}
+
+/* the fitness the optimiser maximises: |d_eff|^2 of one design, or the
+ * negated multi-wavelength objective */
+typedef struct {
+    const orc_design *d;       /* single design (K == 0) */
+    const void *const *ds;     /* K designs */
+    int K, kind;
+    double G0, beta;
+} orc_target;
+
+static void fitness_of_genes(const orc_target *t, int64_t D, const float *x, int64_t np, int8_t *scratch, double *f)
+{
+    orc_sign_map(x, np * D, scratch);
+    if (t->K == 0)
+        orc_fitness(t->d, scratch, np, NULL, f);
+    else
+        orc_multi_objective(t->ds, t->K, t->kind, t->G0, t->beta, scratch, np, NULL, f);
 }
 
 /* The whole optimiser. x_out: np x n final genes, f_out: np final fitness,
@@ -713,12 +786,10 @@ static void fitness_of_genes(const orc_design *d, const float *x, int64_t np, in
  * fitness; GWO candidates for the other wolves, evaluation, greedy
  * selection again. CR stays fixed (step 6 of Sec. 3.2 updates "F, CR and
  * others"; the paper gives a rule for F only). */
-int orc_hwsda_run_ctl(const void *h, int64_t np, int64_t G, float F, float CR, uint64_t seed,
-                      uint32_t inst, int variant, int control, float *x_out, double *f_out,
-                      double *trace, float *params)
+static int hwsda_loop(const orc_target *t, int64_t D, int64_t np, int64_t G, float F, float CR, uint64_t seed,
+                      uint32_t inst, int variant, int control, float *x_out, double *f_out, double *trace,
+                      float *params)
 {
-    const orc_design *d = h;
-    const int64_t D = d->n;
     if (np < 4 || G < 1 || control < 0 || control > 2) return -1;
     float *x = x_out;
     float *u = malloc(sizeof(float) * np * D);
@@ -726,7 +797,7 @@ int orc_hwsda_run_ctl(const void *h, int64_t np, int64_t G, float F, float CR, u
     double *f = f_out;
     double *fu = malloc(sizeof(double) * np);
     orc_init_pop(np, D, seed, inst, x);
-    fitness_of_genes(d, x, np, sg, f);
+    fitness_of_genes(t, D, x, np, sg, f);
     for (int64_t g = 0; g < G; ++g) {
         const float a_g = orc_a_control(control, g, G);
         const float F_g = control == 0 ? F : (control == 1 ? a_g : orc_adaptive_F(f, np, g, G));
@@ -735,7 +806,7 @@ int orc_hwsda_run_ctl(const void *h, int64_t np, int64_t G, float F, float CR, u
             params[2 * g + 1] = a_g;
         }
         orc_de_step(x, np, D, F_g, CR, seed, (uint32_t)g, inst, u, NULL);
-        fitness_of_genes(d, u, np, sg, fu);
+        fitness_of_genes(t, D, u, np, sg, fu);
         for (int64_t i = 0; i < np; ++i)
             if (fu[i] > f[i]) {
                 memcpy(x + i * D, u + i * D, sizeof(float) * D);
@@ -744,7 +815,7 @@ int orc_hwsda_run_ctl(const void *h, int64_t np, int64_t G, float F, float CR, u
         int32_t L[3];
         orc_top3(f, np, L);
         orc_gwo_step(x, np, D, L, a_g, seed, (uint32_t)g, inst, variant, u);
-        fitness_of_genes(d, u, np, sg, fu);
+        fitness_of_genes(t, D, u, np, sg, fu);
         for (int64_t i = 0; i < np; ++i) {
             if (i == L[0] || i == L[1] || i == L[2]) continue;
             if (fu[i] > f[i]) {
@@ -763,6 +834,28 @@ int orc_hwsda_run_ctl(const void *h, int64_t np, int64_t G, float F, float CR, u
     free(sg);
     free(fu);
     return 0;
+}
+
+int orc_hwsda_run_ctl(const void *h, int64_t np, int64_t G, float F, float CR, uint64_t seed,
+                      uint32_t inst, int variant, int control, float *x_out, double *f_out,
+                      double *trace, float *params)
+{
+    const orc_target t = {h, NULL, 0, 0, 0.0, 0.0};
+    return hwsda_loop(&t, ((const orc_design *)h)->n, np, G, F, CR, seed, inst, variant, control, x_out, f_out,
+                      trace, params);
+}
+
+/* The optimiser on the multi-wavelength objective (f = -h of
+ * orc_multi_objective); controls 0 and 1 (the adaptive rule's thresholds
+ * are stated for |d_eff|^2). */
+int orc_hwsda_run_obj(const void *const *designs, int K, int kind, double G0, double beta, int64_t np, int64_t G,
+                      float F, float CR, uint64_t seed, uint32_t inst, int variant, int control, float *x_out,
+                      double *f_out, double *trace, float *params)
+{
+    if (!multi_valid(designs, K, kind) || control == 2) return -1;
+    const orc_target t = {NULL, designs, K, kind, G0, beta};
+    const int64_t D = ((const orc_design *)designs[0])->n;
+    return hwsda_loop(&t, D, np, G, F, CR, seed, inst, variant, control, x_out, f_out, trace, params);
 }
 
 /* The optimiser with the textbook parameters (control 0). */

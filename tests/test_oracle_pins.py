@@ -571,3 +571,96 @@ def test_hwsda_control_consistent_with_steps(orc, control):
     if control == 0:
         x0, f0, _ = D.hwsda_run(np_, G, 0.5, 0.9, seed=3)
         assert np.array_equal(x0, x1)
+
+
+# ---- multi-wavelength objective (the paper's multi-wavelength designs) -----
+
+def test_multi_objective_shg_closed_forms(orc):
+    # N uniform domains of width w: first-order QPM (dk = pi / w, alternating
+    # signs) gives G = |sum d a| / L = 2 / pi; all +1 gives |sinc(dk L / 2)|
+    n, w = 64, 2.0
+    z = inputs.uniform_boundaries(n, w)
+    L = n * w
+    dks = [np.pi / w, 0.013]
+    O = orc.Objective([orc.Design(z, dk, 0.7) for dk in dks], 0, 1.0, 0.0)
+    alt = np.where(np.arange(n) % 2 == 0, 1, -1)[None].astype(np.int8)
+    ones = np.ones((1, n), np.int8)
+    G, _ = O(np.concatenate([alt, -alt, ones]))
+    assert abs(G[0, 0] - 2 / np.pi) < 1e-13 and abs(G[1, 0] - 2 / np.pi) < 1e-13
+    for k, dk in enumerate(dks):
+        x = dk * L / 2
+        assert abs(G[2, k] - abs(np.sin(x) / x)) < 1e-13
+
+
+def test_multi_objective_value(orc):
+    # h = sum |G0 - G_k| + beta (max G - min G) from closed-form G of the
+    # all +1 genome; G0 = 0.5 sits between the two G, so the absolute value
+    # matters; f = -h
+    n, w = 50, 2.0
+    z = inputs.uniform_boundaries(n, w)
+    L = n * w
+    dks = [0.001, 0.05, 0.2]
+    G0, beta = 0.5, 3.0
+    O = orc.Objective([orc.Design(z, dk, 0.3) for dk in dks], 0, G0, beta)
+    Gc = np.array([abs(np.sin(dk * L / 2) / (dk * L / 2)) for dk in dks])
+    assert Gc[0] > G0 > Gc[1]
+    want = -(np.abs(G0 - Gc).sum() + beta * (Gc.max() - Gc.min()))
+    G, f = O(np.ones((1, n), np.int8))
+    assert np.max(np.abs(G[0] - Gc)) < 1e-13 and abs(f[0] - want) < 1e-12
+
+
+def test_multi_objective_thg_is_the_normalised_d_eff(orc):
+    # THG: G_k = |S_k| / L^2 with S_k the pinned coupled integral of each
+    # design; the sign flip d -> -d leaves every G unchanged (SHG and THG)
+    n = 300
+    z = inputs.jittered_boundaries(n, 2.0, 0.3, seed=5)
+    L = z[-1] - z[0]
+    Ds = [orc.Design(z, k1, k2) for k1, k2 in ((DK1, DK2), (0.31, 0.97), (0.335, 0.93))]
+    d = inputs.random_signs(20, n, seed=2)
+    G, f = orc.Objective(Ds, 1, 1.0, 0.5)(d)
+    for k, D in enumerate(Ds):
+        S, _ = D.fitness(d)
+        assert np.max(np.abs(G[:, k] - np.abs(S) / L**2) / np.abs(S / L**2)) < 1e-13
+    for kind in (0, 1):
+        O = orc.Objective(Ds, kind, 1.0, 0.5)
+        assert np.array_equal(O(d)[0], O(-d)[0])
+    with pytest.raises(ValueError):
+        orc.Objective([Ds[0], orc.Design(inputs.uniform_boundaries(n, 2.0), DK1, DK2)], 1, 1.0, 0.0)(d)
+
+
+def test_multi_objective_run_reduces_to_the_single_design_run(orc):
+    # K = 1, THG, G0 = 1, beta = 0: f = |S| / L^2 - 1 orders genomes as |S|^2
+    # does, so the optimiser takes the single-design run's every decision
+    n, np_, G = 120, 16, 6
+    z = inputs.uniform_boundaries(n, 2.0)
+    D = orc.Design(z, DK1, DK2)
+    x1, _, _ = D.hwsda_run(np_, G, 0.5, 0.9, 4)
+    x2, f2, _, _ = orc.Objective([D], 1, 1.0, 0.0).hwsda_run(np_, G, 0.5, 0.9, 4)
+    assert np.array_equal(x1, x2) and np.all(f2 < 0)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_multi_objective_run_consistent_with_steps(orc, kind):
+    n, np_, G = 40, 8, 2
+    z = inputs.uniform_boundaries(n, 2.0)
+    O = orc.Objective([orc.Design(z, k1, k2) for k1, k2 in ((DK1, DK2), (0.2, 0.8))], kind, 0.8, 0.5)
+    x1, f1, _, par = O.hwsda_run(np_, G, 0.5, 0.9, seed=3, control=1)
+    x = orc.init_pop(np_, n, seed=3)
+    f = O(orc.sign_map(x))[1]
+    for g in range(G):
+        a = orc.a_control(1, g, G)
+        u, _ = orc.de_step(x, a, 0.9, seed=3, g=g)
+        fu = O(orc.sign_map(u))[1]
+        acc = fu > f
+        x[acc] = u[acc]
+        f[acc] = fu[acc]
+        L = orc.top3(f)
+        y = orc.gwo_step(x, L, a, seed=3, g=g)
+        fy = O(orc.sign_map(y))[1]
+        acc = fy > f
+        acc[L] = False
+        x[acc] = y[acc]
+        f[acc] = fy[acc]
+    assert np.array_equal(x, x1) and np.array_equal(f, f1)
+    with pytest.raises(ValueError):
+        O.hwsda_run(np_, G, 0.5, 0.9, seed=3, control=2)
