@@ -76,6 +76,7 @@ typedef struct qpm_design_s *qpm_design; /* owns the device phase tables */
 typedef struct qpm_run_s *qpm_run_handle;
 typedef struct qpm_batch_s *qpm_batch;   /* many designs, concatenated tables */
 typedef struct qpm_batch_run_s *qpm_batch_run_handle;
+typedef struct qpm_objective_s *qpm_objective; /* K designs, one objective */
 
 /* Status text for a code, and the calling thread's last error message. */
 const char *qpm_status_string(qpm_status s);
@@ -248,6 +249,40 @@ qpm_status qpm_relax_backward(qpm_design d, qpm_prec p, const float *theta, int6
                               const double *S, const double *edges, const float *grad_f,
                               float *grad_theta, int64_t ldg, qpm_stream s);
 
+/*
+ * Multi-wavelength objective (the paper's multi-wavelength second- and
+ * coupled third-harmonic designs, its last section). K designs made by
+ * qpm_precompute_phases from the same boundaries z, one per wavelength
+ * (its dk1, dk2); L = z_N - z_0. Per genome and design k:
+ *   QPM_OBJ_SHG  G_k = |sum_n d_n a_n| / L, the single-integral coupling of
+ *                second-harmonic generation with the design's dk1 (dk2 is
+ *                not used);
+ *   QPM_OBJ_THG  G_k = |d_eff,k| / L^2, the coupled double integral of
+ *                Sec. 2.1 with the design's (dk1, dk2).
+ * The paper minimises h = sum_k |G0 - G_k| + beta (max_k G_k - min_k G_k);
+ * fitness = -h is maximised. G is normalised (at most 1) so that G0 and
+ * beta are dimensionless (a reading: the paper does not give its scale).
+ * One bit stream serves all K designs: each bit word is loaded once and
+ * looked up in the K designs' sign-pattern tables.
+ */
+typedef enum { QPM_OBJ_SHG = 0, QPM_OBJ_THG = 1 } qpm_objective_kind;
+
+/* designs: host array of K (1..8) designs that share their boundaries
+ * (checked: N, z_0, z_N and a hash of z), on the current device; the
+ * objective refers to them, so they must outlive it (and any run on it).
+ * G0, beta: finite. Errors: QPM_EINVAL (NULL, K out of range, unknown
+ * kind, boundaries differ, non-finite G0 or beta). */
+qpm_status qpm_objective_create(const qpm_design *designs, int32_t K, int32_t kind, double G0, double beta,
+                                qpm_objective *out);
+qpm_status qpm_objective_free(qpm_objective o); /* NULL accepted */
+
+/* fitness = -h per genome (device, np floats for QPM_PREC_F32 or doubles
+ * for QPM_PREC_F64) and, when G is not NULL, G_k of genome i at
+ * G[k * ldG + i] (device doubles, ldG >= np). bits: as qpm_eval_fitness.
+ * Errors: as qpm_eval_fitness, and QPM_EINVAL for ldG < np. */
+qpm_status qpm_eval_objective(qpm_objective o, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                              void *fitness, double *G, int64_t ldG, qpm_stream s);
+
 /* Configuration of a whole optimisation (paper Sec. 3.2, steps 1-7). */
 typedef struct {
     int64_t np;          /* population size, >= 4 */
@@ -313,6 +348,14 @@ typedef struct {
  */
 qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_stream s,
                           qpm_run_handle *out);
+
+/* A run whose fitness is the multi-wavelength objective o (fitness = -h;
+ * cfg->fit_kernel is ignored, the DE shape is still tuned with cfg->tune).
+ * o and its designs must outlive the run. Controls FIXED and DECAY (the
+ * adaptive rule's thresholds are stated for |d_eff|^2: QPM_EINVAL);
+ * qpm_run_polish is QPM_ENOTSUP on such a run. */
+qpm_status qpm_run_create_objective(qpm_objective o, const qpm_run_config *cfg, qpm_stream s,
+                                    qpm_run_handle *out);
 
 /* Advance a run by `generations` (asynchronous on the run's stream; the
  * total may not exceed cfg->generations). */

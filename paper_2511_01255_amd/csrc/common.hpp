@@ -57,6 +57,8 @@ struct Design {
     double2 *tab64 = nullptr; // [8 W][A, B, Q][16 sign patterns] per 4-domain block
     float2 *tab32 = nullptr;  // the same rounded to float
     int device = 0;
+    double z0 = 0, zN = 0;    // first and last boundary
+    uint64_t zhash = 0;       // FNV-1a of the boundary bytes (designs sharing z)
 };
 
 // sign-pattern tables of the 8 W blocks of 4 domains (from ph64)
@@ -106,6 +108,48 @@ inline size_t finish_cand_bytes(int64_t np)
 // and the decay law F_base[g]
 qpm_status launch_adapt_F(const void *f, bool f64, int64_t np, const uint32_t *gen, int64_t G, const double *F_base,
                           float *F_tab, hipStream_t s);
+
+// ---------------------------------------------------------------- multi-wavelength objective
+
+constexpr int kMaxObjectiveDesigns = 8;
+
+// per-design table pointers and C, passed by value to the kernels
+struct ObjTabs {
+    const float2 *t32[kMaxObjectiveDesigns];
+    const double2 *t64[kMaxObjectiveDesigns];
+    double C[kMaxObjectiveDesigns][2];
+};
+
+// K designs on one set of boundaries; G_k = |A_k| / L (SHG) or
+// |S_k| / L^2 (THG), fitness = -(sum |G0 - G_k| + beta (max G - min G))
+struct Objective {
+    const Design *d[kMaxObjectiveDesigns] = {};
+    int K = 0;
+    int kind = QPM_OBJ_SHG;
+    double G0 = 1.0, beta = 0.0;
+    double scale = 1.0;  // 1 / L or 1 / L^2
+    int64_t n = 0, words = 0;
+    ObjTabs tabs{};
+};
+
+struct ObjPlan {
+    int wpw = 1;  // bit words per segment wave (4 segment waves per workgroup)
+    int gy = 1;   // workgroup segments along the domain axis
+};
+
+ObjPlan plan_objective(const Objective &o, qpm_prec p);
+// segment partials of every design: K x gy x (6 or 2) x ld doubles
+size_t objective_partials_bytes(const Objective &o, const ObjPlan &pl, int64_t ld);
+qpm_status launch_objective_partials(const Objective &o, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                                     const ObjPlan &pl, double *part, hipStream_t s);
+// fitness (np floats or doubles) and optionally G ([K][ldG] doubles)
+qpm_status launch_objective_values(const Objective &o, const ObjPlan &pl, const double *part, int64_t ld, int64_t np,
+                                   void *fitness, bool f64, double *G, int64_t ldG, hipStream_t s);
+// the run's finish step on the objective (as launch_finish)
+qpm_status launch_objective_finish(const Objective &o, const ObjPlan &pl, const double *part, int64_t ld, int64_t np,
+                                   void *f_cur, bool f64, uint32_t *flags, uint32_t *fbits, const int32_t *skip3,
+                                   int32_t *top3_out, void *cand, int4 *draws_next, uint32_t *gen, int64_t D,
+                                   uint64_t seed, uint32_t inst, hipStream_t s);
 
 // ---------------------------------------------------------------- evolution kernels
 
@@ -185,3 +229,4 @@ void tune_store(const std::string &key, int v0, int v1);
 
 // The opaque handle types of the ABI are the library's structures.
 struct qpm_design_s : public qpm::Design {};
+struct qpm_objective_s : public qpm::Objective {};

@@ -267,6 +267,14 @@ QPM_API qpm_status qpm_precompute_phases(const double *z, int64_t n, double dk1,
     d->words = words_for(n);
     d->dk1 = dk1;
     d->dk2 = dk2;
+    d->z0 = z[0];
+    d->zN = z[n];
+    {
+        uint64_t h = 1469598103934665603ull;  // FNV-1a, 64 bit
+        const unsigned char *bytes = reinterpret_cast<const unsigned char *>(z);
+        for (size_t k = 0; k < sizeof(double) * static_cast<size_t>(n + 1); ++k) h = (h ^ bytes[k]) * 1099511628211ull;
+        d->zhash = h;
+    }
     QPM_TRY_HIP(hipGetDevice(&d->device));
     const int64_t npad = d->words * 32;
     double *zdev = nullptr;

@@ -23,6 +23,8 @@ using namespace qpm;
 
 struct qpm_run_s {
     const Design *d = nullptr;
+    const Objective *obj = nullptr;  // multi-wavelength objective instead of |d_eff|^2
+    ObjPlan oplan;
     qpm_run_config cfg{};
     hipStream_t st = nullptr;
     int64_t D = 0, ldx = 0, ld = 0, W = 0;
@@ -106,13 +108,47 @@ static void release(qpm_run_s *r)
     delete r;
 }
 
+// segment partials of the run's fitness for the genomes in tbits
+static qpm_status eval_partials(qpm_run_s *r)
+{
+    const qpm_run_config &c = r->cfg;
+    const qpm_prec p = static_cast<qpm_prec>(c.prec);
+    if (r->obj) return launch_objective_partials(*r->obj, p, r->tbits, c.np, r->ld, r->oplan, r->fws, r->st);
+    return launch_fitness_partials(*r->d, p, r->tbits, c.np, r->ld, r->plan, r->fws, r->st);
+}
+
+// combine + selection (+ leaders or the next generation's draws and advance)
+static qpm_status eval_finish(qpm_run_s *r, const int32_t *skip3, int32_t *top3_out, void *cand, int4 *draws_next)
+{
+    const qpm_run_config &c = r->cfg;
+    if (r->obj)
+        return launch_objective_finish(*r->obj, r->oplan, r->fws, r->ld, c.np, r->f_cur, r->f64(), r->flags,
+                                       r->fbits, skip3, top3_out, cand, draws_next, r->gen, r->D, c.seed, c.inst,
+                                       r->st);
+    const int gy = r->plan.kind == QPM_FIT_PER_GENOME ? 1 : r->plan.gy;
+    return launch_finish(r->fws, gy, r->ld, c.np, r->d->Cdev, r->f_cur, r->f64(), r->flags, r->fbits, skip3,
+                         top3_out, cand, draws_next, r->gen, r->D, c.seed, c.inst, r->st);
+}
+
+// the fitness of the genomes in tbits into f_cur (no selection)
+static qpm_status eval_values(qpm_run_s *r)
+{
+    const qpm_run_config &c = r->cfg;
+    const qpm_prec p = static_cast<qpm_prec>(c.prec);
+    if (r->obj) {
+        qpm_status st = launch_objective_partials(*r->obj, p, r->tbits, c.np, r->ld, r->oplan, r->fws, r->st);
+        if (st != QPM_OK) return st;
+        return launch_objective_values(*r->obj, r->oplan, r->fws, r->ld, c.np, r->f_cur, r->f64(), nullptr, 0, r->st);
+    }
+    return launch_fitness(*r->d, p, r->tbits, c.np, r->ld, r->f_cur, r->plan, r->fws, r->st);
+}
+
 // steps 2-6 for the generation held in the device counter; with `ev`, an
 // event is recorded before each step and after the last
 static qpm_status enqueue_generation(qpm_run_s *r, hipEvent_t *ev = nullptr)
 {
     const qpm_run_config &c = r->cfg;
     const PopView pv = r->view();
-    const qpm_prec p = static_cast<qpm_prec>(c.prec);
     auto mark = [&](int k) -> qpm_status {
         if (ev) QPM_TRY_HIP(hipEventRecord(ev[k], r->st));
         return QPM_OK;
@@ -121,20 +157,14 @@ static qpm_status enqueue_generation(qpm_run_s *r, hipEvent_t *ev = nullptr)
 #define QPM_STEP(k, call)                         \
     if ((st = mark(k)) != QPM_OK) return st;      \
     if ((st = (call)) != QPM_OK) return st;
-    const int gy = r->plan.kind == QPM_FIT_PER_GENOME ? 1 : r->plan.gy;
-    const double *C = r->d->Cdev;
     QPM_STEP(QPM_K_DE, launch_de(pv, c.F, c.CR, c.seed, r->gen, 0u, c.inst, r->tbits, r->ld, r->draws, false, r->st,
                                  r->de_ipw, r->de_passes, r->fbits, r->F_tab))
-    QPM_STEP(QPM_K_FIT_DE, launch_fitness_partials(*r->d, p, r->tbits, c.np, r->ld, r->plan, r->fws, r->st))
-    QPM_STEP(QPM_K_FINISH_DE, launch_finish(r->fws, gy, r->ld, c.np, C, r->f_cur, r->f64(), r->flags, r->fbits,
-                                            nullptr, r->leaders, r->cand, nullptr, r->gen, r->D, c.seed, c.inst,
-                                            r->st))
+    QPM_STEP(QPM_K_FIT_DE, eval_partials(r))
+    QPM_STEP(QPM_K_FINISH_DE, eval_finish(r, nullptr, r->leaders, r->cand, nullptr))
     QPM_STEP(QPM_K_GWO, launch_gwo(pv, r->leaders, r->a_tab, 0.0f, c.seed, r->gen, 0u, c.inst, c.gwo_variant,
                                    r->tbits, r->ld, r->st))
-    QPM_STEP(QPM_K_FIT_GWO, launch_fitness_partials(*r->d, p, r->tbits, c.np, r->ld, r->plan, r->fws, r->st))
-    QPM_STEP(QPM_K_FINISH_GWO, launch_finish(r->fws, gy, r->ld, c.np, C, r->f_cur, r->f64(), r->flags, r->fbits,
-                                             r->leaders, nullptr, nullptr, r->draws, r->gen, r->D, c.seed, c.inst,
-                                             r->st))
+    QPM_STEP(QPM_K_FIT_GWO, eval_partials(r))
+    QPM_STEP(QPM_K_FINISH_GWO, eval_finish(r, r->leaders, nullptr, nullptr, r->draws))
     if (r->adaptive()) {  // F of the next generation (timed with the finish)
         st = launch_adapt_F(r->f_cur, r->f64(), c.np, r->gen, c.generations, r->F_base, r->F_tab, r->st);
         if (st != QPM_OK) return st;
@@ -201,7 +231,9 @@ static qpm_status tune_run(qpm_run_s *r)
         return st;
     };
     qpm_status st = QPM_OK;
-    if (r->plan.kind == QPM_FIT_SEGMENTED) {
+    if (r->obj) {
+        // the objective kernel has one shape per kind and precision
+    } else if (r->plan.kind == QPM_FIT_SEGMENTED) {
         const std::string key = tune_key("fit", r->d->words, c.np, c.prec, 1);
         int waves = 0, wpw = 0;
         if (!tune_lookup(key, &waves, &wpw)) {
@@ -302,9 +334,9 @@ static qpm_status tune_run(qpm_run_s *r)
     return QPM_OK;
 }
 
-QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_stream sv, qpm_run_handle *out)
+static qpm_status create_run(const Design *d, const Objective *obj, const qpm_run_config *cfg, qpm_stream sv,
+                             qpm_run_handle *out)
 {
-    clear_error();
     QPM_REQUIRE(d && cfg && out, QPM_EINVAL, "design, cfg and out must not be NULL");
     const qpm_run_config c = *cfg;
     QPM_REQUIRE(c.np >= 4 && c.np <= (int64_t(1) << 24), QPM_EINVAL, "np must be in [4, 2^24] (got %lld)",
@@ -329,12 +361,14 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
 
     auto *r = new qpm_run_s();
     r->d = d;
+    r->obj = obj;
     r->cfg = c;
     r->D = d->n;
     r->ldx = ((r->D + 63) / 64) * 64;
     r->ld = ((c.np + 63) / 64) * 64;
     r->W = d->words;
     r->plan = plan_fitness(*d, static_cast<qpm_prec>(c.prec), c.np, c.fit_kernel);
+    if (obj) r->oplan = plan_objective(*obj, static_cast<qpm_prec>(c.prec));
     const size_t es = r->f64() ? sizeof(double) : sizeof(float);
     const size_t gene_bytes = sizeof(float) * static_cast<size_t>(c.np) * static_cast<size_t>(r->ldx);
     hipError_t e = hipStreamCreateWithFlags(&r->st, hipStreamNonBlocking);
@@ -402,20 +436,20 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     }
     // step 1: initialise, evaluate, leaders (after tuning on the initial
     // population, which the tuner's trial launches overwrite)
-    const qpm_prec p = static_cast<qpm_prec>(c.prec);
     st = launch_init(c.np, r->D, r->ldx, c.seed, c.inst, r->buf[0], r->tbits, r->ld, r->st);
     if (st == QPM_OK && c.tune) {
         st = tune_run(r);
         if (st == QPM_OK) st = launch_init(c.np, r->D, r->ldx, c.seed, c.inst, r->buf[0], r->tbits, r->ld, r->st);
     }
     if (st == QPM_OK) {
-        e = hipMalloc(&r->fws, fitness_partials_bytes(r->plan, r->ld));
+        e = hipMalloc(&r->fws, obj ? objective_partials_bytes(*obj, r->oplan, r->ld)
+                                   : fitness_partials_bytes(r->plan, r->ld));
         if (e != hipSuccess) {
             set_error("run allocation failed: %s", hipGetErrorString(e));
             st = e == hipErrorOutOfMemory ? QPM_ENOMEM : QPM_EHIP;
         }
     }
-    if (st == QPM_OK) st = launch_fitness(*d, p, r->tbits, c.np, r->ld, r->f_cur, r->plan, r->fws, r->st);
+    if (st == QPM_OK) st = eval_values(r);
     if (st == QPM_OK) st = launch_top3(r->f_cur, c.np, r->f64(), r->leaders, r->st);
     if (st == QPM_OK) st = launch_draws(c.np, r->D, c.seed, r->gen, c.inst, r->draws, r->st);
     if (st == QPM_OK && r->adaptive())
@@ -431,6 +465,22 @@ QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_s
     }
     *out = r;
     return QPM_OK;
+}
+
+QPM_API qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_stream sv, qpm_run_handle *out)
+{
+    clear_error();
+    return create_run(d, nullptr, cfg, sv, out);
+}
+
+QPM_API qpm_status qpm_run_create_objective(qpm_objective o, const qpm_run_config *cfg, qpm_stream sv,
+                                            qpm_run_handle *out)
+{
+    clear_error();
+    QPM_REQUIRE(o != nullptr && cfg != nullptr, QPM_EINVAL, "objective and cfg must not be NULL");
+    QPM_REQUIRE(cfg->control != QPM_CONTROL_ADAPTIVE, QPM_EINVAL,
+                "the adaptive control is defined for the |d_eff|^2 fitness, not for the objective");
+    return create_run(o->d[0], o, cfg, sv, out);
 }
 
 QPM_API qpm_status qpm_run_advance(qpm_run_handle r, int64_t generations)
@@ -503,9 +553,7 @@ QPM_API qpm_status qpm_run_load(qpm_run_handle r, const float *x, int64_t ldx)
     QPM_TRY_HIP(hipMemsetAsync(r->flags, 0, sizeof(uint32_t) * c.np, r->st));
     QPM_TRY_HIP(hipMemsetAsync(r->fbits, 0, sizeof(uint32_t) * 2 * ((c.np + 63) / 64), r->st));
     qpm_status st = launch_pack_pop(r->buf[0], c.np, r->D, r->ldx, r->tbits, r->ld, r->st);
-    if (st == QPM_OK)
-        st = launch_fitness(*r->d, static_cast<qpm_prec>(c.prec), r->tbits, c.np, r->ld, r->f_cur, r->plan, r->fws,
-                            r->st);
+    if (st == QPM_OK) st = eval_values(r);
     if (st == QPM_OK) st = launch_top3(r->f_cur, c.np, r->f64(), r->leaders, r->st);
     if (st == QPM_OK) st = launch_draws(c.np, r->D, c.seed, r->gen, c.inst, r->draws, r->st);
     if (st == QPM_OK && r->adaptive())  // F of the coming generation from the loaded population
@@ -594,6 +642,7 @@ QPM_API qpm_status qpm_run_polish(qpm_run_handle r, int32_t steps, float eta, in
     QPM_REQUIRE(r != nullptr, QPM_EINVAL, "run is NULL");
     QPM_REQUIRE(steps >= 0 && steps <= 100000, QPM_EINVAL, "steps must be in [0, 1e5] (got %d)", (int)steps);
     QPM_REQUIRE(eta >= 0.0f && eta <= 1e6f, QPM_EINVAL, "eta must be finite and >= 0");
+    QPM_REQUIRE(r->obj == nullptr, QPM_ENOTSUP, "polish relaxes |d_eff|^2, not the multi-wavelength objective");
     const qpm_run_config &c = r->cfg;
     const qpm_prec p = static_cast<qpm_prec>(c.prec);
     const int64_t ldx = r->ldx, D = r->D;

@@ -20,6 +20,8 @@ FIT_TABLE = 3
 CONTROL_FIXED = 0     # F constant, a from 2 to 0
 CONTROL_DECAY = 1     # F = a from 0.1 to 0.01
 CONTROL_ADAPTIVE = 2  # adaptive F in [0.01, 0.1], a from 0.1 to 0.01
+OBJ_SHG = 0  # multi-wavelength objective over |sum d a| / L
+OBJ_THG = 1  # multi-wavelength objective over |d_eff| / L^2
 # timing slots of one generation (QPM_K_*)
 STEP_NAMES = ["de", "fitness_de", "finish_de", "gwo", "fitness_gwo", "finish_gwo"]
 
@@ -73,6 +75,10 @@ _SIGS = {
     "qpm_run_read": (_I32, [_P, _P, _I64, _P, _P, _P]),
     "qpm_run_best": (_I32, [_P, _P, _P, C.POINTER(RunStats)]),
     "qpm_run_params": (_I32, [_P, _I64, _P, _P]),
+    "qpm_objective_create": (_I32, [_P, _I32, _I32, _D, _D, C.POINTER(_P)]),
+    "qpm_objective_free": (_I32, [_P]),
+    "qpm_eval_objective": (_I32, [_P, _I32, _P, _I64, _I64, _P, _P, _I64, _P]),
+    "qpm_run_create_objective": (_I32, [_P, _P, _P, C.POINTER(_P)]),
     "qpm_run_destroy": (_I32, [_P]),
     "qpm_run_load": (_I32, [_P, _P, _I64]),
     "qpm_run_polish": (_I32, [_P, _I32, _F, _P]),
@@ -190,6 +196,43 @@ def eval_fitness(design, bits, np_, prec=PREC_F32, kernel=FIT_AUTO, out=None, st
     _check(lib().qpm_eval_fitness(design.handle, prec, _ptr(bits), np_, bits.shape[1], _ptr(out), kernel,
                                   _stream(stream)))
     return out
+
+
+class Objective:
+    """The multi-wavelength objective over K designs that share their
+    boundaries (kind OBJ_SHG or OBJ_THG); fitness = -h."""
+
+    def __init__(self, designs, kind, G0=1.0, beta=0.0):
+        self.designs = list(designs)  # the objective refers to their tables
+        self.K = len(self.designs)
+        self.n = self.designs[0].n
+        self.kind = kind
+        arr = (C.c_void_p * self.K)(*[d.handle for d in self.designs])
+        h = C.c_void_p()
+        _check(lib().qpm_objective_create(arr, self.K, kind, G0, beta, C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.qpm_objective_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.free()
+
+
+def eval_objective(obj, bits, np_, prec=PREC_F32, with_G=False, stream=None):
+    """bits: int32 CUDA tensor (W, ld) -> fitness (np_,) [, G (K, np_) float64]."""
+    import torch
+    f = torch.empty(np_, dtype=torch.float64 if prec == PREC_F64 else torch.float32, device=bits.device)
+    G = torch.empty((obj.K, np_), dtype=torch.float64, device=bits.device) if with_G else None
+    _check(lib().qpm_eval_objective(obj.handle, prec, _ptr(bits), np_, bits.shape[1], _ptr(f), _ptr(G), np_,
+                                    _stream(stream)))
+    return (f, G) if with_G else f
 
 
 def eval_fitness_shape(design, bits, np_, prec, waves_per_group, words_per_wave, out=None, stream=None):
@@ -326,7 +369,8 @@ def _config(np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_
 
 
 class Run:
-    """A whole optimisation on the device (run_create / advance / read / best)."""
+    """A whole optimisation on the device (run_create / advance / read / best).
+    `design` is a Design (fitness |d_eff|^2) or an Objective (fitness -h)."""
 
     def __init__(self, design, np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0,
                  use_graph=1, fit_kernel=FIT_AUTO, tune=0, control=CONTROL_FIXED, stream=None):
@@ -335,7 +379,8 @@ class Run:
                            control)
         self.D = design.n
         h = C.c_void_p()
-        _check(lib().qpm_run_create(design.handle, C.byref(self.cfg), _stream(stream), C.byref(h)))
+        create = lib().qpm_run_create_objective if isinstance(design, Objective) else lib().qpm_run_create
+        _check(create(design.handle, C.byref(self.cfg), _stream(stream), C.byref(h)))
         self._h = h
 
     def advance(self, generations=1):

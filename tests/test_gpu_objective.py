@@ -1,0 +1,125 @@
+"""The multi-wavelength objective (SHG |sum d a| / L and coupled THG
+|d_eff| / L^2 per wavelength, fitness -(sum |G0 - G_k| + beta (max - min)))
+and the run on it, against the CPU oracle through the C ABI."""
+import numpy as np
+import pytest
+
+from paper_2511_01255_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DK1, DK2 = inputs.DK1, inputs.DK2
+# (dk1, dk2) per wavelength: the workload pair and nearby mismatches
+DKS = [(DK1, DK2), (0.31, 0.97), (0.335, 0.93), (0.30, 1.00), (0.29, 0.90), (0.345, 0.99), (0.325, 0.94),
+       (0.315, 0.96)]
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2511_01255_amd import qpm
+    qpm.lib()
+    return qpm
+
+
+def _bits(d):
+    import torch
+    return torch.from_numpy(inputs.pack_bits(d).view(np.int32)).cuda()
+
+
+def _pair(q, orc, z, K, kind, G0, beta):
+    gd = [q.precompute_phases(z, k1, k2) for k1, k2 in DKS[:K]]
+    od = [orc.Design(z, k1, k2) for k1, k2 in DKS[:K]]
+    return q.Objective(gd, kind, G0, beta), orc.Objective(od, kind, G0, beta)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("case", [(1007, 130, 3), (1, 5, 2), (33, 64, 1), (3001, 70, 8)],
+                         ids=lambda c: "n%d_np%d_K%d" % c)
+def test_objective_matches_oracle(q, orc, case, kind, prec):
+    n, npop, K = case
+    z = inputs.jittered_boundaries(n, 2.0, 0.3, seed=n)
+    G0, beta = 0.6, 1.5
+    O, Oo = _pair(q, orc, z, K, kind, G0, beta)
+    d = np.concatenate([inputs.random_signs(npop - npop // 4, n, seed=K),
+                        inputs.periodic_signs(npop // 4, n, 2.0, 19.5, seed=K)])
+    f, G = q.eval_objective(O, _bits(d), npop, prec, with_G=True)
+    Go, fo = Oo(d)
+    G = G.cpu().numpy().T
+    f = f.double().cpu().numpy()
+    tol = 1e-12 if prec == 1 else 1e-5
+    # normwise per design (G near 0 has no relative accuracy in FP32 sums)
+    scale = np.maximum(np.max(np.abs(Go), axis=0, keepdims=True), 1e-300)
+    assert np.max(np.abs(G - Go) / scale) <= tol
+    assert np.max(np.abs(f - fo)) <= tol * max(1.0, np.max(np.abs(fo)))
+
+
+def test_objective_rejects_bad_designs(q):
+    z = inputs.uniform_boundaries(100, 2.0)
+    a = q.precompute_phases(z, DK1, DK2)
+    b = q.precompute_phases(inputs.jittered_boundaries(100, 2.0, 0.2, seed=1), DK1, DK2)
+    with pytest.raises(q.QpmError):
+        q.Objective([a, b], q.OBJ_SHG)
+    with pytest.raises(q.QpmError):
+        q.Objective([a] * 9, q.OBJ_SHG)
+    with pytest.raises(q.QpmError):
+        q.Objective([a], 2)
+    with pytest.raises(q.QpmError):
+        q.Objective([a], q.OBJ_THG, float("nan"), 0.0)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("control,graph", [(0, 1), (1, 0), (1, 1)])
+def test_objective_run_fp64_equals_oracle(q, orc, kind, control, graph):
+    # every decision of the run on the objective is the oracle's (FP64);
+    # G = 20 replays the 8-generation graph twice and single generations
+    n, npop, G, K = 300, 40, 20, 3
+    z = inputs.uniform_boundaries(n, 2.0)
+    O, Oo = _pair(q, orc, z, K, kind, 0.7, 2.0)
+    xo, fo, _, par = Oo.hwsda_run(npop, G, 0.5, 0.9, 6, control=control)
+    R = q.Run(O, npop, G, seed=6, prec=1, control=control, use_graph=graph)
+    R.advance(G)
+    x, f, _, _ = R.read()
+    assert np.array_equal(x.cpu().numpy(), xo)
+    assert np.max(np.abs(f.cpu().numpy() - fo)) <= 1e-12 * max(1.0, np.max(np.abs(fo)))
+    assert np.array_equal(np.array([R.params(g) for g in range(G)], dtype=np.float32), par)
+    with pytest.raises(q.QpmError):
+        R.polish(3, 0.05)
+    R.destroy()
+
+
+def test_objective_run_fp32_selects_on_its_objective(q, orc):
+    # FP32: after the run, every stored fitness is the oracle's objective of
+    # the stored genes (within FP32 tolerance) and the best never decreased
+    n, npop, G, K = 1500, 96, 10, 4
+    z = inputs.uniform_boundaries(n, 2.0)
+    O, Oo = _pair(q, orc, z, K, 1, 0.5, 1.0)
+    R = q.Run(O, npop, G, seed=2, prec=0, control=1)
+    best = []
+    for g in range(G):
+        R.advance(1)
+        x, f, _, _ = R.read()
+        best.append(float(f.max()))
+    _, fo = Oo(orc.sign_map(x.cpu().numpy()))
+    assert np.max(np.abs(f.double().cpu().numpy() - fo)) <= 1e-5 * max(1.0, np.max(np.abs(fo)))
+    assert np.all(np.diff(best) >= 0)
+    R.destroy()
+
+
+def test_objective_run_reduces_to_the_single_design_run(q):
+    # K = 1, THG, G0 = 1, beta = 0 orders genomes as |d_eff|^2 does: the run
+    # on the objective takes the single-design run's decisions
+    n, npop, G = 500, 32, 10
+    z = inputs.uniform_boundaries(n, 2.0)
+    D = q.precompute_phases(z, DK1, DK2)
+    R1 = q.Run(D, npop, G, seed=3, prec=1)
+    R1.advance(G)
+    R2 = q.Run(q.Objective([D], q.OBJ_THG, 1.0, 0.0), npop, G, seed=3, prec=1)
+    R2.advance(G)
+    assert np.array_equal(R1.read()[0].cpu().numpy(), R2.read()[0].cpu().numpy())
+    with pytest.raises(q.QpmError):
+        q.Run(q.Objective([D], q.OBJ_THG), npop, G, control=2)
+    R1.destroy()
+    R2.destroy()
