@@ -283,6 +283,16 @@ qpm_status qpm_objective_free(qpm_objective o); /* NULL accepted */
 qpm_status qpm_eval_objective(qpm_objective o, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
                               void *fitness, double *G, int64_t ldG, qpm_stream s);
 
+/* qpm_eval_objective with an explicit launch shape: a workgroup is 64
+ * genomes x 4 segment waves of words_per_wave bit words each, in [1, 5]
+ * (FP32) or [1, 2] (FP64); the default picks it from N and np. Results
+ * equal qpm_eval_objective's up to the summation order. Errors: as
+ * qpm_eval_objective, QPM_EINVAL for words_per_wave out of range,
+ * QPM_ERANGE when the words need more than 65535 workgroup segments. */
+qpm_status qpm_eval_objective_shape(qpm_objective o, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                                    void *fitness, double *G, int64_t ldG, int32_t words_per_wave,
+                                    qpm_stream s);
+
 /* Configuration of a whole optimisation (paper Sec. 3.2, steps 1-7). */
 typedef struct {
     int64_t np;          /* population size, >= 4 */

@@ -137,7 +137,8 @@ struct ObjPlan {
     int gy = 1;   // workgroup segments along the domain axis
 };
 
-ObjPlan plan_objective(const Objective &o, qpm_prec p);
+ObjPlan plan_objective(const Objective &o, qpm_prec p, int64_t np);
+ObjPlan plan_objective_shape(const Objective &o, int wpw);
 // segment partials of every design: K x gy x (6 or 2) x ld doubles
 size_t objective_partials_bytes(const Objective &o, const ObjPlan &pl, int64_t ld);
 qpm_status launch_objective_partials(const Objective &o, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,

@@ -255,16 +255,25 @@ __global__ __launch_bounds__(256) void obj_finish_kernel(ObjTabs tabs, int K, do
                         k1, inst);
 }
 
-ObjPlan plan_objective(const Objective &o, qpm_prec p)
+ObjPlan plan_objective_shape(const Objective &o, int wpw)
 {
-    // THG: 4 words per wave in FP32 (48 KB of tables), 2 in FP64 (48 KB);
-    // SHG (a third of the table): the register limit of the word cache
-    const bool f32 = p == QPM_PREC_F32;
     ObjPlan pl;
-    pl.wpw = o.kind == QPM_OBJ_THG ? (f32 ? 4 : 2) : table_max_wpw(f32);
-    while (pl.wpw < table_max_wpw(f32) && (o.words + 4 * pl.wpw - 1) / (4 * pl.wpw) > 65535) ++pl.wpw;
+    pl.wpw = wpw;
     pl.gy = static_cast<int>((o.words + 4 * pl.wpw - 1) / (4 * pl.wpw));
     return pl;
+}
+
+ObjPlan plan_objective(const Objective &o, qpm_prec p, int64_t np)
+{
+    // the most words per wave (fewest partials) that still gives about
+    // 2048 workgroups (8 per CU, so staging and walking overlap across
+    // workgroups), at most the register limit of the word cache
+    const bool f32 = p == QPM_PREC_F32;
+    const int64_t groups = (np + 63) / 64;
+    int wpw = table_max_wpw(f32);
+    while (wpw > 1 && groups * ((o.words + 4 * wpw - 1) / (4 * wpw)) < 2048) --wpw;
+    while (wpw < table_max_wpw(f32) && (o.words + 4 * wpw - 1) / (4 * wpw) > 65535) ++wpw;
+    return plan_objective_shape(o, wpw);
 }
 
 size_t objective_partials_bytes(const Objective &o, const ObjPlan &pl, int64_t ld)
@@ -392,10 +401,12 @@ QPM_API qpm_status qpm_objective_free(qpm_objective o)
     return QPM_OK;
 }
 
-QPM_API qpm_status qpm_eval_objective(qpm_objective o, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
-                                      void *fitness, double *G, int64_t ldG, qpm_stream sv)
+static qpm_status eval_with_plan(qpm_objective o, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                                 void *fitness, double *G, int64_t ldG, const ObjPlan &pl, hipStream_t s);
+
+static qpm_status check_objective_args(qpm_objective o, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                                       void *fitness, double *G, int64_t ldG)
 {
-    clear_error();
     QPM_REQUIRE(o && bits && fitness, QPM_EINVAL, "objective, bits and fitness must not be NULL");
     QPM_REQUIRE(p == QPM_PREC_F32 || p == QPM_PREC_F64, QPM_EINVAL, "unknown precision %d", (int)p);
     QPM_REQUIRE(np >= 1, QPM_EINVAL, "np must be >= 1 (got %lld)", (long long)np);
@@ -405,8 +416,37 @@ QPM_API qpm_status qpm_eval_objective(qpm_objective o, qpm_prec p, const uint32_
     QPM_REQUIRE(G == nullptr || ldG >= np, QPM_EINVAL, "ldG (%lld) must be >= np (%lld)", (long long)ldG,
                 (long long)np);
     QPM_REQUIRE(np <= (int64_t(1) << 31) && o->words * ld <= (int64_t(1) << 40), QPM_ERANGE, "population too large");
+    return QPM_OK;
+}
+
+QPM_API qpm_status qpm_eval_objective(qpm_objective o, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                                      void *fitness, double *G, int64_t ldG, qpm_stream sv)
+{
+    clear_error();
+    qpm_status st = check_objective_args(o, p, bits, np, ld, fitness, G, ldG);
+    if (st != QPM_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(sv);
-    const ObjPlan pl = plan_objective(*o, p);
+    const ObjPlan pl = plan_objective(*o, p, np);
+    return eval_with_plan(o, p, bits, np, ld, fitness, G, ldG, pl, s);
+}
+
+QPM_API qpm_status qpm_eval_objective_shape(qpm_objective o, qpm_prec p, const uint32_t *bits, int64_t np,
+                                            int64_t ld, void *fitness, double *G, int64_t ldG, int32_t wpw,
+                                            qpm_stream sv)
+{
+    clear_error();
+    qpm_status st = check_objective_args(o, p, bits, np, ld, fitness, G, ldG);
+    if (st != QPM_OK) return st;
+    QPM_REQUIRE(wpw >= 1 && wpw <= table_max_wpw(p == QPM_PREC_F32), QPM_EINVAL,
+                "words_per_wave must be in [1, %d] (got %d)", table_max_wpw(p == QPM_PREC_F32), (int)wpw);
+    const ObjPlan pl = plan_objective_shape(*o, wpw);
+    QPM_REQUIRE(pl.gy <= 65535, QPM_ERANGE, "too many workgroup segments (%d)", pl.gy);
+    return eval_with_plan(o, p, bits, np, ld, fitness, G, ldG, pl, static_cast<hipStream_t>(sv));
+}
+
+static qpm_status eval_with_plan(qpm_objective o, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
+                                 void *fitness, double *G, int64_t ldG, const ObjPlan &pl, hipStream_t s)
+{
     double *part = nullptr;
     QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&part), objective_partials_bytes(*o, pl, ld), s));
     qpm_status st = launch_objective_partials(*o, p, bits, np, ld, pl, part, s);

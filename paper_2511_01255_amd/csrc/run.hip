@@ -232,7 +232,43 @@ static qpm_status tune_run(qpm_run_s *r)
     };
     qpm_status st = QPM_OK;
     if (r->obj) {
-        // the objective kernel has one shape per kind and precision
+        // words per wave of the objective kernel (partials + values)
+        const Objective &o = *r->obj;
+        const std::string key = tune_key(o.kind == QPM_OBJ_THG ? "objthg" : "objshg", o.words * 16 + o.K, c.np,
+                                         c.prec, 1);
+        int wpw = 0, unused = 0;
+        if (!tune_lookup(key, &wpw, &unused)) {
+            std::vector<ObjPlan> cands;
+            for (int w = 1; w <= table_max_wpw(p == QPM_PREC_F32); ++w) {
+                const ObjPlan pl = plan_objective_shape(o, w);
+                if (pl.gy <= 65535) cands.push_back(pl);
+            }
+            size_t maxb = 0;
+            for (const auto &pl : cands) maxb = std::max(maxb, objective_partials_bytes(o, pl, r->ld));
+            double *part = nullptr;
+            QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&part), maxb, r->st));
+            float best = 1e30f;
+            for (const auto &pl : cands) {
+                float ms = 0.0f;
+                st = time_min(
+                    [&]() {
+                        qpm_status s2 = launch_objective_partials(o, p, r->tbits, c.np, r->ld, pl, part, r->st);
+                        if (s2 != QPM_OK) return s2;
+                        return launch_objective_values(o, pl, part, r->ld, c.np, r->f_new, r->f64(), nullptr, 0,
+                                                       r->st);
+                    },
+                    &ms);
+                if (st != QPM_OK) break;
+                if (ms < best) {
+                    best = ms;
+                    wpw = pl.wpw;
+                }
+            }
+            (void)hipFreeAsync(part, r->st);
+            if (st != QPM_OK) return st;
+            tune_store(key, wpw, 0);
+        }
+        r->oplan = plan_objective_shape(o, wpw);
     } else if (r->plan.kind == QPM_FIT_SEGMENTED) {
         const std::string key = tune_key("fit", r->d->words, c.np, c.prec, 1);
         int waves = 0, wpw = 0;
@@ -368,7 +404,7 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
     r->ld = ((c.np + 63) / 64) * 64;
     r->W = d->words;
     r->plan = plan_fitness(*d, static_cast<qpm_prec>(c.prec), c.np, c.fit_kernel);
-    if (obj) r->oplan = plan_objective(*obj, static_cast<qpm_prec>(c.prec));
+    if (obj) r->oplan = plan_objective(*obj, static_cast<qpm_prec>(c.prec), c.np);
     const size_t es = r->f64() ? sizeof(double) : sizeof(float);
     const size_t gene_bytes = sizeof(float) * static_cast<size_t>(c.np) * static_cast<size_t>(r->ldx);
     hipError_t e = hipStreamCreateWithFlags(&r->st, hipStreamNonBlocking);

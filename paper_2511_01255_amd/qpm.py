@@ -78,6 +78,7 @@ _SIGS = {
     "qpm_objective_create": (_I32, [_P, _I32, _I32, _D, _D, C.POINTER(_P)]),
     "qpm_objective_free": (_I32, [_P]),
     "qpm_eval_objective": (_I32, [_P, _I32, _P, _I64, _I64, _P, _P, _I64, _P]),
+    "qpm_eval_objective_shape": (_I32, [_P, _I32, _P, _I64, _I64, _P, _P, _I64, _I32, _P]),
     "qpm_run_create_objective": (_I32, [_P, _P, _P, C.POINTER(_P)]),
     "qpm_run_destroy": (_I32, [_P]),
     "qpm_run_load": (_I32, [_P, _P, _I64]),
@@ -225,13 +226,17 @@ class Objective:
         self.free()
 
 
-def eval_objective(obj, bits, np_, prec=PREC_F32, with_G=False, stream=None):
+def eval_objective(obj, bits, np_, prec=PREC_F32, with_G=False, words_per_wave=None, stream=None):
     """bits: int32 CUDA tensor (W, ld) -> fitness (np_,) [, G (K, np_) float64]."""
     import torch
     f = torch.empty(np_, dtype=torch.float64 if prec == PREC_F64 else torch.float32, device=bits.device)
     G = torch.empty((obj.K, np_), dtype=torch.float64, device=bits.device) if with_G else None
-    _check(lib().qpm_eval_objective(obj.handle, prec, _ptr(bits), np_, bits.shape[1], _ptr(f), _ptr(G), np_,
-                                    _stream(stream)))
+    if words_per_wave is None:
+        _check(lib().qpm_eval_objective(obj.handle, prec, _ptr(bits), np_, bits.shape[1], _ptr(f), _ptr(G), np_,
+                                        _stream(stream)))
+    else:
+        _check(lib().qpm_eval_objective_shape(obj.handle, prec, _ptr(bits), np_, bits.shape[1], _ptr(f), _ptr(G),
+                                              np_, words_per_wave, _stream(stream)))
     return (f, G) if with_G else f
 
 

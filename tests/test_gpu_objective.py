@@ -56,6 +56,41 @@ def test_objective_matches_oracle(q, orc, case, kind, prec):
     assert np.max(np.abs(f - fo)) <= tol * max(1.0, np.max(np.abs(fo)))
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_objective_every_launch_shape(q, orc, kind, prec):
+    # the tuner may pick any words-per-wave: each meets the tolerance; 1537
+    # domains = 49 words leave ragged segments for every shape
+    n, npop, K = 1537, 100, 3
+    z = inputs.jittered_boundaries(n, 2.0, 0.3, seed=9)
+    O, Oo = _pair(q, orc, z, K, kind, 0.5, 1.0)
+    d = inputs.random_signs(npop, n, seed=5)
+    Go, fo = Oo(d)
+    bits = _bits(d)
+    tol = 1e-12 if prec == 1 else 1e-5
+    for wpw in range(1, (5 if prec == 0 else 2) + 1):
+        f, G = q.eval_objective(O, bits, npop, prec, with_G=True, words_per_wave=wpw)
+        G = G.cpu().numpy().T
+        assert np.max(np.abs(G - Go) / np.max(np.abs(Go), axis=0, keepdims=True)) <= tol, wpw
+        assert np.max(np.abs(f.double().cpu().numpy() - fo)) <= tol * max(1.0, np.max(np.abs(fo))), wpw
+    with pytest.raises(q.QpmError):
+        q.eval_objective(O, bits, npop, prec, words_per_wave=(6 if prec == 0 else 3))
+
+
+def test_objective_run_tuned_equals_untuned_fp64(q):
+    n, npop, G = 2000, 64, 6
+    z = inputs.uniform_boundaries(n, 2.0)
+    gd = [q.precompute_phases(z, k1, k2) for k1, k2 in DKS[:3]]
+    O = q.Objective(gd, q.OBJ_THG, 0.8, 1.0)
+    xs = []
+    for tune in (0, 1):
+        R = q.Run(O, npop, G, seed=1, prec=1, tune=tune)
+        R.advance(G)
+        xs.append(R.read()[0].cpu().numpy())
+        R.destroy()
+    assert np.array_equal(xs[0], xs[1])
+
+
 def test_objective_rejects_bad_designs(q):
     z = inputs.uniform_boundaries(100, 2.0)
     a = q.precompute_phases(z, DK1, DK2)
