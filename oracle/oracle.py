@@ -55,6 +55,9 @@ def lib():
             "orc_de_step": (None, [_P, _I64, _I64, _F, _F, _U64, _U32, _U32, _P, _P]),
             "orc_gwo_step": (None, [_P, _I64, _I64, _P, _F, _U64, _U32, _U32, _INT, _P]),
             "orc_top3": (None, [_P, _I64, _P]),
+            "orc_top4": (None, [_P, _I64, _P]),
+            "orc_dgwo_params": (None, [_I64, _I64, _P]),
+            "orc_dgwo_step": (None, [_P, _I64, _I64, _P, _P, _U64, _U32, _U32, _P]),
             "orc_a_schedule": (_F, [_I64, _I64]),
             "orc_hwsda_run": (_INT, [_P, _I64, _I64, _F, _F, _U64, _U32, _INT, _P, _P, _P]),
             "orc_hwsda_run_ctl": (_INT, [_P, _I64, _I64, _F, _F, _U64, _U32, _INT, _INT, _P, _P, _P, _P]),
@@ -250,6 +253,29 @@ def gwo_step(x, leaders, a, seed, g, inst=0, variant=0):
     L = np.ascontiguousarray(leaders, dtype=np.int32)
     y = np.zeros_like(x)
     lib().orc_gwo_step(_ptr(x), np_, D, _ptr(L), a, seed, g, inst, variant, _ptr(y))
+    return y
+
+
+def top4(f):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros(4, dtype=np.int32)
+    lib().orc_top4(_ptr(f), f.size, _ptr(out))
+    return out
+
+
+def dgwo_params(g, G):
+    par = np.zeros(4, dtype=np.float32)
+    lib().orc_dgwo_params(g, G, _ptr(par))
+    return par
+
+
+def dgwo_step(x, leaders4, par, seed, g, inst=0):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    np_, D = x.shape
+    L = np.ascontiguousarray(leaders4, dtype=np.int32)
+    pr = np.ascontiguousarray(par, dtype=np.float32)
+    y = np.zeros_like(x)
+    lib().orc_dgwo_step(_ptr(x), np_, D, _ptr(L), _ptr(pr), seed, g, inst, _ptr(y))
     return y
 
 

@@ -462,7 +462,7 @@ void orc_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out)
 }
 
 /* stream tags (counter word 3, low byte); high 24 bits = instance */
-enum { TAG_INIT = 1, TAG_DE_IDX = 2, TAG_DE_CR = 3, TAG_GWO = 4 };
+enum { TAG_INIT = 1, TAG_DE_IDX = 2, TAG_DE_CR = 3, TAG_GWO = 4, TAG_DGWO = 5 };
 
 static uint32_t draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t inst,
                      uint32_t tag, int lane)
@@ -606,6 +606,75 @@ void orc_gwo_step(const float *x, int64_t np, int64_t D, const int32_t *leaders,
 }
 
 /* ------------------------------------------------------------------ */
+/* improved discrete grey-wolf step (Sec. 3.1.2)                        */
+/* ------------------------------------------------------------------ */
+
+/* PARITY UNPINNED against the paper: Sec. 3.1.2 describes the discrete
+ * variant in words only (four leaders, +-1 states, a transition
+ * probability from the leaders' state counts, a perturbation that is
+ * strong early and a small flip probability late, a dispersion parameter,
+ * social learning at a falling rate) and gives no formula or rate. The
+ * rule below is this oracle's reading; its tests pin the implementation to
+ * the rule (special cases, frequencies), not the rule to the paper.
+ *
+ * Generation parameters, t = g / G in double, each rounded to float once:
+ *   par[0] = t
+ *   par[1] = 1 - 2 eps, eps = 0.1 (1 - t) + 0.01 t    (perturbation)
+ *   par[2] = eps
+ *   par[3] = lambda = 0.2 (1 - t)                      (social learning) */
+void orc_dgwo_params(int64_t g, int64_t G, float *par)
+{
+    double t = (double)g / (double)G;
+    float eps = (float)(0.1 * (1.0 - t) + 0.01 * t);
+    par[0] = (float)t;
+    par[1] = (float)(1.0 - 2.0 * (double)eps);
+    par[2] = eps;
+    par[3] = (float)(0.2 * (1.0 - t));
+}
+
+/* One step. L4: the four best (alpha, beta, delta, then the fourth); the
+ * first three keep their rows, every other wolf (the fourth included)
+ * gets new +-1 genes. For gene j of wolf i, with one Philox word w
+ * (tag DGWO, word j % 4 of counter j / 4):
+ *   n     = how many of the four leaders hold state +1 (gene >= 0) at j;
+ *   dist  = n / 4                  (the leaders' state distribution),
+ *   maj   = 1, 0 or 1/2 as n > 2, n < 2 or n = 2  (the dominant state),
+ *   p     = fmaf(t, maj - dist, dist)   (distribution early, majority late),
+ *   p'    = fmaf(1 - 2 eps, p, eps)     (perturbation towards 1/2),
+ *   social learning when (w >> 16 & 0x3FFF) 2^-14 < lambda: the state of
+ *   leader w >> 30; otherwise +1 when (w & 0xFFFF) 2^-16 < p', else -1.
+ * All of it in binary32. */
+void orc_dgwo_step(const float *x, int64_t np, int64_t D, const int32_t *L4, const float *par, uint64_t seed,
+                   uint32_t g, uint32_t inst, float *y)
+{
+    const float t = par[0], c1 = par[1], eps = par[2], lam = par[3];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < np; ++i) {
+        int keep = (i == L4[0] || i == L4[1] || i == L4[2]);
+        for (int64_t j = 0; j < D; ++j) {
+            if (keep) {
+                y[i * D + j] = x[i * D + j];
+                continue;
+            }
+            int plus[4], n = 0;
+            for (int k = 0; k < 4; ++k) {
+                plus[k] = !(x[(int64_t)L4[k] * D + j] < 0.0f);
+                n += plus[k];
+            }
+            uint32_t w = draw(seed, (uint32_t)(j >> 2), (uint32_t)i, g, inst, TAG_DGWO, (int)(j & 3));
+            float dist = (float)n * 0.25f;
+            float maj = n > 2 ? 1.0f : (n < 2 ? 0.0f : 0.5f);
+            float p = fmaf(t, maj - dist, dist);
+            float p2 = fmaf(c1, p, eps);
+            float us = (float)((w >> 16) & 0x3FFFu) * 0x1p-14f;
+            float up = (float)(w & 0xFFFFu) * 0x1p-16f;
+            int state = us < lam ? plus[w >> 30] : (up < p2);
+            y[i * D + j] = state ? 1.0f : -1.0f;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* leaders and the HWSDA loop (paper Sec. 3.2)                          */
 /* ------------------------------------------------------------------ */
 
@@ -621,15 +690,20 @@ static int cmp_desc(const void *pa, const void *pb)
 
 /* Step 3: sort all fitness values, best first (ties: lower index first),
  * and take the first three as alpha, beta, delta. */
-void orc_top3(const double *f, int64_t np, int32_t *out)
+static void topk(const double *f, int64_t np, int k, int32_t *out)
 {
     int64_t *ord = malloc(sizeof(int64_t) * np);
     for (int64_t i = 0; i < np; ++i) ord[i] = i;
     g_sort_f = f;
     qsort(ord, np, sizeof(int64_t), cmp_desc);
-    for (int k = 0; k < 3; ++k) out[k] = (int32_t)ord[k];
+    for (int m = 0; m < k; ++m) out[m] = (int32_t)ord[m];
     free(ord);
 }
+
+void orc_top3(const double *f, int64_t np, int32_t *out) { topk(f, np, 3, out); }
+
+/* the four best (Sec. 3.1.2: a fourth leader joins alpha, beta, delta) */
+void orc_top4(const double *f, int64_t np, int32_t *out) { topk(f, np, 4, out); }
 
 /* a decreases linearly from 2 towards 0 over the run */
 float orc_a_schedule(int64_t g, int64_t G) { return (float)(2.0 * (1.0 - (double)g / (double)G)); }
@@ -783,14 +857,15 @@ static void fitness_of_genes(const orc_target *t, int64_t D, const float *x, int
  * Per generation g: F_g and a_g from the control (orc_a_control;
  * orc_adaptive_F on the current fitness under control 2), DE trials,
  * evaluation, greedy selection (strict >); leaders from the sorted
- * fitness; GWO candidates for the other wolves, evaluation, greedy
- * selection again. CR stays fixed (step 6 of Sec. 3.2 updates "F, CR and
+ * fitness; GWO candidates for the other wolves (variants 0 and 1), or the
+ * discrete four-leader step (variant 2, orc_dgwo_step, guided by the four
+ * best), evaluation, greedy selection again (alpha, beta, delta kept). CR stays fixed (step 6 of Sec. 3.2 updates "F, CR and
  * others"; the paper gives a rule for F only). */
 static int hwsda_loop(const orc_target *t, int64_t D, int64_t np, int64_t G, float F, float CR, uint64_t seed,
                       uint32_t inst, int variant, int control, float *x_out, double *f_out, double *trace,
                       float *params)
 {
-    if (np < 4 || G < 1 || control < 0 || control > 2) return -1;
+    if (np < 4 || G < 1 || control < 0 || control > 2 || variant < 0 || variant > 2) return -1;
     float *x = x_out;
     float *u = malloc(sizeof(float) * np * D);
     int8_t *sg = malloc((size_t)(np * D));
@@ -812,9 +887,16 @@ static int hwsda_loop(const orc_target *t, int64_t D, int64_t np, int64_t G, flo
                 memcpy(x + i * D, u + i * D, sizeof(float) * D);
                 f[i] = fu[i];
             }
-        int32_t L[3];
-        orc_top3(f, np, L);
-        orc_gwo_step(x, np, D, L, a_g, seed, (uint32_t)g, inst, variant, u);
+        int32_t L[4];
+        if (variant == 2) {
+            float par[4];
+            orc_top4(f, np, L);
+            orc_dgwo_params(g, G, par);
+            orc_dgwo_step(x, np, D, L, par, seed, (uint32_t)g, inst, u);
+        } else {
+            orc_top3(f, np, L);
+            orc_gwo_step(x, np, D, L, a_g, seed, (uint32_t)g, inst, variant, u);
+        }
         fitness_of_genes(t, D, u, np, sg, fu);
         for (int64_t i = 0; i < np; ++i) {
             if (i == L[0] || i == L[1] || i == L[2]) continue;

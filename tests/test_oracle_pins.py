@@ -664,3 +664,98 @@ def test_multi_objective_run_consistent_with_steps(orc, kind):
     assert np.array_equal(x, x1) and np.array_equal(f, f1)
     with pytest.raises(ValueError):
         O.hwsda_run(np_, G, 0.5, 0.9, seed=3, control=2)
+
+
+# ---- improved discrete four-leader GWO (Sec. 3.1.2; parity unpinned) -------
+# The paper gives this variant in words only; these tests pin the oracle to
+# its stated reading (special cases and frequencies), not to the paper.
+
+def _dgwo_case(D=24000):
+    # rows 0-3 are the leaders; at gene j, n(j) = j % 5 of them hold +1
+    x = np.full((8, D), -0.5, np.float32)
+    n = np.arange(D) % 5
+    for k in range(4):
+        x[k, n > k] = 0.5
+    x[4:] = np.random.default_rng(0).uniform(-1, 1, (4, D)).astype(np.float32)
+    return x, n
+
+
+def test_dgwo_params(orc):
+    p0, pm = orc.dgwo_params(0, 10), orc.dgwo_params(5, 10)
+    assert p0.tolist() == [0.0, np.float32(0.8), np.float32(0.1), np.float32(0.2)]
+    assert pm[0] == np.float32(0.5) and pm[2] == np.float32(0.055) and pm[3] == np.float32(0.1)
+    assert pm[1] == np.float32(1.0 - 2.0 * float(np.float32(0.055)))
+
+
+def test_dgwo_leaders_kept_and_states_pm1(orc):
+    x, n = _dgwo_case(4000)
+    L4 = np.array([2, 0, 3, 1], np.int32)
+    y = orc.dgwo_step(x, L4, orc.dgwo_params(3, 10), seed=1, g=3)
+    assert np.array_equal(y[[2, 0, 3]], x[[2, 0, 3]])
+    assert set(np.unique(y[[1, 4, 5, 6, 7]])) <= {-1.0, 1.0}
+
+
+def _freq(y, n, cls):
+    rows = y[4:, n == cls]
+    return (rows > 0).mean(), rows.size
+
+
+def test_dgwo_majority_distribution_and_perturbation(orc):
+    x, n = _dgwo_case()
+    L4 = np.arange(4, dtype=np.int32)
+    # late, no perturbation, no social learning: the dominant state
+    y = orc.dgwo_step(x, L4, np.array([1, 1, 0, 0], np.float32), seed=2, g=1)
+    for c, want in ((0, 0.0), (1, 0.0), (3, 1.0), (4, 1.0)):
+        assert _freq(y, n, c)[0] == want
+    fr, m = _freq(y, n, 2)
+    assert abs(fr - 0.5) < 4 * np.sqrt(0.25 / m)
+    # early: the leaders' state distribution, P(+1) = n / 4
+    y = orc.dgwo_step(x, L4, np.array([0, 1, 0, 0], np.float32), seed=3, g=1)
+    for c in range(5):
+        fr, m = _freq(y, n, c)
+        p = c / 4
+        assert abs(fr - p) <= 4 * np.sqrt(p * (1 - p) / m)  # exact at p = 0 and 1
+    # perturbation eps = 0.1 around the majority: P(+1) = 0.1 or 0.9
+    y = orc.dgwo_step(x, L4, np.array([1, 0.8, 0.1, 0], np.float32), seed=4, g=1)
+    for c, p in ((0, 0.1), (1, 0.1), (3, 0.9), (4, 0.9)):
+        fr, m = _freq(y, n, c)
+        assert abs(fr - p) < 4 * np.sqrt(p * (1 - p) / m)
+
+
+def test_dgwo_social_learning(orc):
+    # lambda = 1: every gene copies a leader drawn uniformly: unanimous
+    # leaders are copied exactly, otherwise P(+1) = n / 4
+    x, n = _dgwo_case()
+    L4 = np.arange(4, dtype=np.int32)
+    y = orc.dgwo_step(x, L4, np.array([1, 1, 0, 1], np.float32), seed=5, g=2)
+    assert _freq(y, n, 0)[0] == 0.0 and _freq(y, n, 4)[0] == 1.0
+    for c in (1, 2, 3):
+        fr, m = _freq(y, n, c)
+        assert abs(fr - c / 4) < 4 * np.sqrt((c / 4) * (1 - c / 4) / m)
+
+
+def test_top4(orc):
+    f = np.array([1.0, 5.0, 5.0, 3.0, 5.0, 0.0, 3.0])
+    assert orc.top4(f).tolist() == [1, 2, 4, 3]
+
+
+def test_hwsda_discrete_variant_consistent_with_steps(orc):
+    n, np_, G = 40, 8, 2
+    D = orc.Design(inputs.uniform_boundaries(n), DK1, DK2)
+    x1, f1, _ = D.hwsda_run(np_, G, 0.5, 0.9, seed=3, variant=2)
+    x = orc.init_pop(np_, n, seed=3)
+    _, f = D.fitness(orc.sign_map(x))
+    for g in range(G):
+        u, _ = orc.de_step(x, 0.5, 0.9, seed=3, g=g)
+        _, fu = D.fitness(orc.sign_map(u))
+        acc = fu > f
+        x[acc] = u[acc]
+        f[acc] = fu[acc]
+        L4 = orc.top4(f)
+        y = orc.dgwo_step(x, L4, orc.dgwo_params(g, G), seed=3, g=g)
+        _, fy = D.fitness(orc.sign_map(y))
+        acc = fy > f
+        acc[L4[:3]] = False
+        x[acc] = y[acc]
+        f[acc] = fy[acc]
+    assert np.array_equal(x, x1) and np.array_equal(f, f1)
