@@ -204,6 +204,30 @@ qpm_status qpm_de_step_shape(const float *x, int64_t np, int64_t D, int64_t ldx,
  * Leader rows of y and y_bits are left untouched. a = 0 or
  * 2^-100 <= a <= 1e30 (the parameter runs from 2 down to 0).
  */
+/*
+ * qpm_dgwo_step -- the improved discrete four-leader grey-wolf step of paper
+ * Sec. 3.1.2. The paper describes it in words only (four leaders, +-1
+ * states, a transition probability from the leaders' state counts, strong
+ * perturbation early and a small flip probability late, social learning
+ * at a falling rate); this is the library's reading of it, with no rate
+ * taken from the paper. For gene j of a non-leader i, with one Philox word
+ * w (counter (j / 4, i, g, inst << 8 | 5), word j % 4) and
+ * params = {t, 1 - 2 eps, eps, lambda} (a run uses t = g / G,
+ * eps = 0.1 (1 - t) + 0.01 t, lambda = 0.2 (1 - t), each rounded to float):
+ *   n = number of the 4 leaders with gene >= 0 at j; dist = n / 4;
+ *   maj = 1, 0 or 1/2 for n > 2, n < 2, n = 2;
+ *   p = fmaf(t, maj - dist, dist); p' = fmaf(1 - 2 eps, p, eps);
+ *   y = the state of leader w >> 30 when (w >> 16 & 0x3FFF) 2^-14 < lambda
+ *   (social learning), else +1 when (w & 0xFFFF) 2^-16 < p', else -1.
+ * leaders: device int32[4], distinct, in [0, np): alpha, beta, delta (their
+ * rows of y and y_bits are left untouched) and the fourth; the call copies
+ * them to the host to validate them (it synchronises s). params: host.
+ * Errors: as qpm_gwo_step, and QPM_EINVAL for non-finite params.
+ */
+qpm_status qpm_dgwo_step(const float *x, int64_t np, int64_t D, int64_t ldx, const int32_t *leaders,
+                         const float *params, uint64_t seed, uint32_t generation, uint32_t inst, float *y,
+                         uint32_t *y_bits, int64_t ld, qpm_stream s);
+
 qpm_status qpm_gwo_step(const float *x, int64_t np, int64_t D, int64_t ldx,
                         const int32_t *leaders, float a, uint64_t seed, uint32_t generation,
                         uint32_t inst, int32_t variant, float *y, uint32_t *y_bits, int64_t ld,
@@ -302,7 +326,10 @@ typedef struct {
     uint64_t seed;       /* Philox key */
     uint32_t inst;       /* instance number in the Philox counter */
     int32_t prec;        /* qpm_prec of the fitness kernel */
-    int32_t gwo_variant; /* 0 = weighted as printed, 1 = plain mean */
+    int32_t gwo_variant; /* 0 = weighted as printed, 1 = plain mean,
+                            2 = discrete four-leader step (qpm_dgwo_step;
+                            a_g unused; the fourth leader is the best
+                            genome after alpha, beta, delta) */
     int32_t use_graph;   /* 1 = replay one captured generation */
     int32_t fit_kernel;  /* qpm_fit_kernel of the evaluations */
     int32_t tune;        /* 1 = time candidate launch shapes of the fitness

@@ -1025,7 +1025,8 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
     QPM_REQUIRE(c.F >= 0.0f && c.F <= 2.0f, QPM_EINVAL, "F must be in [0, 2]");
     QPM_REQUIRE(c.CR >= 0.0f && c.CR <= 1.0f, QPM_EINVAL, "CR must be in [0, 1]");
     QPM_REQUIRE(c.prec == QPM_PREC_F32 || c.prec == QPM_PREC_F64, QPM_EINVAL, "unknown precision %d", c.prec);
-    QPM_REQUIRE(c.gwo_variant == 0 || c.gwo_variant == 1, QPM_EINVAL, "gwo_variant must be 0 or 1");
+    QPM_REQUIRE(c.gwo_variant == 0 || c.gwo_variant == 1, c.gwo_variant == 2 ? QPM_ENOTSUP : QPM_EINVAL,
+                "batched runs take gwo_variant 0 or 1 (got %d)", (int)c.gwo_variant);
     QPM_REQUIRE(c.control == QPM_CONTROL_FIXED, QPM_ENOTSUP, "batched runs use the fixed parameter control only");
     QPM_REQUIRE(static_cast<int64_t>(c.inst) + b->n_inst <= (int64_t(1) << 24), QPM_EINVAL,
                 "inst + n_inst must be <= 2^24");

@@ -200,6 +200,13 @@ qpm_status launch_draws(int64_t np, int64_t D, uint64_t seed, const uint32_t *ge
 qpm_status launch_gwo(const PopView &pv, const int32_t *leaders, const float *a_tab, float a,
                       uint64_t seed, const uint32_t *gen_dev, uint32_t gen, uint32_t inst,
                       int variant, uint32_t *bits, int64_t ld, hipStream_t s);
+// the improved discrete four-leader step (leaders: 4 slots, the first three
+// kept; par_tab[g] or par = {t, 1 - 2 eps, eps, lambda})
+qpm_status launch_dgwo(const PopView &pv, const int32_t *leaders, const float4 *par_tab, float4 par,
+                       uint64_t seed, const uint32_t *gen_dev, uint32_t gen, uint32_t inst, uint32_t *bits,
+                       int64_t ld, hipStream_t s);
+// leaders[3] = the best of f other than leaders[0..2]
+qpm_status launch_fourth(const void *f, int64_t np, bool f64, int32_t *leaders, hipStream_t s);
 // the three best of f[0..np) (f descending, slot ascending) into out3;
 // T = float or double by `f64`
 qpm_status launch_top3(const void *f, int64_t np, bool f64, int32_t *out3, hipStream_t s);

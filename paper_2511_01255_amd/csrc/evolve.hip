@@ -225,6 +225,82 @@ __global__ __launch_bounds__(256) void gwo_kernel(PopView pv, const int32_t *__r
     store_word(nib, q, valid, bits, ld, i);
 }
 
+// Improved discrete four-leader step (dgwo_quad), same grid as gwo_kernel.
+// The new genes depend on the leaders' genes only, so the wolf's own row is
+// not read. leaders: alpha, beta, delta (kept), then the fourth.
+__global__ __launch_bounds__(256) void dgwo_kernel(PopView pv, const int32_t *__restrict__ leaders,
+                                                   const float4 *__restrict__ par_tab, float4 par_c, uint32_t k0,
+                                                   uint32_t k1, const uint32_t *__restrict__ gen_dev, uint32_t gen_c,
+                                                   uint32_t inst, uint32_t *__restrict__ bits, int64_t ld,
+                                                   int64_t per_xcd)
+{
+    const int64_t np = pv.np, D = pv.D;
+    const int64_t i = static_cast<int64_t>(blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
+    if (i >= np) return;
+    const int64_t L0 = leaders[0], L1 = leaders[1], L2 = leaders[2], L3 = leaders[3];
+    if (i == L0 || i == L1 || i == L2) return;
+    if (L0 < 0 || L0 >= np || L1 < 0 || L1 >= np || L2 < 0 || L2 >= np || L3 < 0 || L3 >= np) return;
+    const uint32_t g = gen_dev ? gen_dev[0] : gen_c;
+    const float4 par = par_tab ? par_tab[g] : par_c;
+    const int64_t q = static_cast<int64_t>(blockIdx.y) * 256 + threadIdx.x;
+    const int64_t j0 = 4 * q;
+    const bool valid = j0 < D;
+    uint32_t nib = 0;
+    if (valid) {
+        const float4 X0 = *reinterpret_cast<const float4 *>(row_of(pv, L0) + j0);
+        const float4 X1 = *reinterpret_cast<const float4 *>(row_of(pv, L1) + j0);
+        const float4 X2 = *reinterpret_cast<const float4 *>(row_of(pv, L2) + j0);
+        const float4 X3 = *reinterpret_cast<const float4 *>(row_of(pv, L3) + j0);
+        const float4 yv4 = dgwo_quad(X0, X1, X2, X3, static_cast<uint32_t>(q), static_cast<uint32_t>(i), g, inst, k0,
+                                     k1, par);
+        store_quad_nt(out_row_of(pv, i), j0, D, yv4);
+        nib = quad_nibble(yv4, j0, D);
+    }
+    store_word(nib, q, valid, bits, ld, i);
+}
+
+// The fourth leader: the best genome (f descending, slot ascending) other
+// than leaders[0..2], into leaders[3]. One workgroup; the order is total,
+// so the result does not depend on the reduction order.
+template <typename T>
+__global__ __launch_bounds__(1024) void fourth_kernel(const T *__restrict__ f, int64_t np, int32_t *__restrict__ leaders)
+{
+    __shared__ T sv[16];
+    __shared__ int si[16];
+    const int64_t L0 = leaders[0], L1 = leaders[1], L2 = leaders[2];
+    T bv = static_cast<T>(-INFINITY);
+    int bi = INT_MAX;
+    for (int64_t k = threadIdx.x; k < np; k += 1024) {
+        if (k == L0 || k == L1 || k == L2) continue;
+        const T v = f[k];
+        if (v > bv || (v == bv && static_cast<int>(k) < bi)) {
+            bv = v;
+            bi = static_cast<int>(k);
+        }
+    }
+    for (int o = 1; o < 64; o <<= 1) {
+        const T ov = __shfl_xor(bv, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+        }
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sv[threadIdx.x >> 6] = bv;
+        si[threadIdx.x >> 6] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 16; ++w)
+            if (sv[w] > bv || (sv[w] == bv && si[w] < bi)) {
+                bv = sv[w];
+                bi = si[w];
+            }
+        leaders[3] = bi;
+    }
+}
+
 // ------------------------------------------------------------ top-3
 
 template <typename T>
@@ -344,6 +420,30 @@ qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const 
         if (R == 1) { QPM_DE(4, 1) } else if (R == 2) { QPM_DE(4, 2) } else { QPM_DE(4, 4) }
     }
 #undef QPM_DE
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
+}
+
+qpm_status launch_dgwo(const PopView &pv, const int32_t *leaders, const float4 *par_tab, float4 par,
+                       uint64_t seed, const uint32_t *gen_dev, uint32_t gen, uint32_t inst, uint32_t *bits,
+                       int64_t ld, hipStream_t s)
+{
+    const int64_t per_xcd = (pv.np + 7) / 8;
+    const qpm_status st = check_quad_grid(pv.D, 8 * per_xcd);
+    if (st != QPM_OK) return st;
+    const dim3 grid(static_cast<unsigned>(8 * per_xcd), quad_grid(pv.D, pv.np).y);
+    dgwo_kernel<<<grid, 256, 0, s>>>(pv, leaders, par_tab, par, static_cast<uint32_t>(seed),
+                                     static_cast<uint32_t>(seed >> 32), gen_dev, gen, inst, bits, ld, per_xcd);
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
+}
+
+qpm_status launch_fourth(const void *f, int64_t np, bool f64, int32_t *leaders, hipStream_t s)
+{
+    if (f64)
+        fourth_kernel<double><<<1, 1024, 0, s>>>(static_cast<const double *>(f), np, leaders);
+    else
+        fourth_kernel<float><<<1, 1024, 0, s>>>(static_cast<const float *>(f), np, leaders);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }
@@ -524,4 +624,35 @@ QPM_API qpm_status qpm_gwo_step(const float *x, int64_t np, int64_t D, int64_t l
     QPM_REQUIRE(L[0] != L[1] && L[0] != L[2] && L[1] != L[2], QPM_EINVAL, "leaders must be distinct");
     const PopView pv{x, x, nullptr, y, y, np, D, ldx};
     return launch_gwo(pv, leaders, nullptr, a, seed, nullptr, generation, inst, variant, y_bits, ld, s);
+}
+
+QPM_API qpm_status qpm_dgwo_step(const float *x, int64_t np, int64_t D, int64_t ldx, const int32_t *leaders,
+                                 const float *params, uint64_t seed, uint32_t generation, uint32_t inst, float *y,
+                                 uint32_t *y_bits, int64_t ld, qpm_stream sv)
+{
+    clear_error();
+    qpm_status st = check_rows(x, np, D, ldx, "x");
+    if (st != QPM_OK) return st;
+    st = check_rows(y, np, D, ldx, "y");
+    if (st != QPM_OK) return st;
+    st = check_bits(y_bits, np, ld);
+    if (st != QPM_OK) return st;
+    QPM_REQUIRE(leaders != nullptr && params != nullptr, QPM_EINVAL, "leaders and params must not be NULL");
+    QPM_REQUIRE(np >= 4, QPM_EINVAL, "the four-leader step needs np >= 4 (got %lld)", (long long)np);
+    QPM_REQUIRE(inst < (1u << 24), QPM_EINVAL, "inst must be < 2^24");
+    for (int k = 0; k < 4; ++k)
+        QPM_REQUIRE(std::isfinite(params[k]), QPM_EINVAL, "params[%d] is not finite", k);
+    const size_t bytes = sizeof(float) * static_cast<size_t>(np) * static_cast<size_t>(ldx);
+    QPM_REQUIRE(!overlaps(x, bytes, y, bytes), QPM_EINVAL, "x and y must not overlap");
+    hipStream_t s = static_cast<hipStream_t>(sv);
+    int32_t L[4];
+    QPM_TRY_HIP(hipMemcpyAsync(L, leaders, sizeof(L), hipMemcpyDeviceToHost, s));
+    QPM_TRY_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < 4; ++k)
+        QPM_REQUIRE(L[k] >= 0 && L[k] < np, QPM_EINVAL, "leader %d (%d) is outside [0, np)", k, (int)L[k]);
+    for (int a = 0; a < 4; ++a)
+        for (int b = a + 1; b < 4; ++b) QPM_REQUIRE(L[a] != L[b], QPM_EINVAL, "leaders must be distinct");
+    const PopView pv{x, x, nullptr, y, y, np, D, ldx};
+    const float4 par = make_float4(params[0], params[1], params[2], params[3]);
+    return launch_dgwo(pv, leaders, nullptr, par, seed, nullptr, generation, inst, y_bits, ld, s);
 }

@@ -166,4 +166,43 @@ __device__ __forceinline__ float4 gwo_quad(float4 xv, float4 X0, float4 X1, floa
     return make_float4(ys[0], ys[1], ys[2], ys[3]);
 }
 
+// Improved discrete four-leader step (paper Sec. 3.1.2, as read here: the
+// paper gives no formula) for the 4 genes of quad q of wolf i: one Philox
+// word per gene (counter (q, i, g, inst << 8 | 5), word e); X0..X3 the
+// leaders' genes (state +1 when >= 0); par = {t, 1 - 2 eps, eps, lambda}.
+//   n = leaders in state +1; dist = n / 4; maj = 1, 0, 1/2 for n > 2, < 2, = 2;
+//   p = fmaf(t, maj - dist, dist); p' = fmaf(1 - 2 eps, p, eps);
+//   social learning when (w >> 16 & 0x3FFF) 2^-14 < lambda: the state of
+//   leader w >> 30; else +1 when (w & 0xFFFF) 2^-16 < p', else -1.
+__device__ __forceinline__ float4 dgwo_quad(float4 X0, float4 X1, float4 X2, float4 X3, uint32_t q, uint32_t i,
+                                            uint32_t g, uint32_t inst, uint32_t k0, uint32_t k1, float4 par)
+{
+    const U4 w4 = philox10(q, i, g, (inst << 8) | kTagDgwo, k0, k1);
+    const uint32_t ws[4] = {w4.x, w4.y, w4.z, w4.w};
+    const float Xs[4][4] = {{X0.x, X0.y, X0.z, X0.w}, {X1.x, X1.y, X1.z, X1.w}, {X2.x, X2.y, X2.z, X2.w},
+                            {X3.x, X3.y, X3.z, X3.w}};
+    float ys[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const uint32_t w = ws[e];
+        uint32_t plus = 0;  // bit k: leader k in state +1
+        int n = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t pk = Xs[k][e] < 0.0f ? 0u : 1u;
+            plus |= pk << k;
+            n += static_cast<int>(pk);
+        }
+        const float dist = static_cast<float>(n) * 0.25f;
+        const float maj = n > 2 ? 1.0f : (n < 2 ? 0.0f : 0.5f);
+        const float p = fmaf(par.x, maj - dist, dist);
+        const float p2 = fmaf(par.y, p, par.z);
+        const float us = static_cast<float>((w >> 16) & 0x3FFFu) * 0x1p-14f;
+        const float up = static_cast<float>(w & 0xFFFFu) * 0x1p-16f;
+        const bool st = us < par.w ? ((plus >> (w >> 30)) & 1u) != 0u : up < p2;
+        ys[e] = st ? 1.0f : -1.0f;
+    }
+    return make_float4(ys[0], ys[1], ys[2], ys[3]);
+}
+
 }  // namespace qpm

@@ -14,7 +14,7 @@
 
 namespace qpm {
 
-enum : uint32_t { kTagInit = 1, kTagDeIdx = 2, kTagDeCr = 3, kTagGwo = 4 };
+enum : uint32_t { kTagInit = 1, kTagDeIdx = 2, kTagDeCr = 3, kTagGwo = 4, kTagDgwo = 5 };
 
 struct U4 {
     uint32_t x, y, z, w;

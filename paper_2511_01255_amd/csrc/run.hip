@@ -40,6 +40,7 @@ struct qpm_run_s {
     uint32_t *gen = nullptr;
     float *a_tab = nullptr;
     float *F_tab = nullptr;     // F_g per generation
+    float4 *dg_tab = nullptr;   // discrete four-leader step: {t, 1 - 2 eps, eps, lambda} per generation
     double *F_base = nullptr;   // decay law of the adaptive control
     int4 *draws = nullptr;
     double *fws = nullptr;
@@ -91,6 +92,7 @@ static void release(qpm_run_s *r)
     (void)hipFree(r->gen);
     (void)hipFree(r->a_tab);
     (void)hipFree(r->F_tab);
+    (void)hipFree(r->dg_tab);
     (void)hipFree(r->F_base);
     (void)hipFree(r->fws);
     (void)hipFree(r->draws);
@@ -161,8 +163,15 @@ static qpm_status enqueue_generation(qpm_run_s *r, hipEvent_t *ev = nullptr)
                                  r->de_ipw, r->de_passes, r->fbits, r->F_tab))
     QPM_STEP(QPM_K_FIT_DE, eval_partials(r))
     QPM_STEP(QPM_K_FINISH_DE, eval_finish(r, nullptr, r->leaders, r->cand, nullptr))
-    QPM_STEP(QPM_K_GWO, launch_gwo(pv, r->leaders, r->a_tab, 0.0f, c.seed, r->gen, 0u, c.inst, c.gwo_variant,
-                                   r->tbits, r->ld, r->st))
+    if (c.gwo_variant == 2) {
+        // the fourth leader (after DE selection), then the discrete step
+        QPM_STEP(QPM_K_GWO, launch_fourth(r->f_cur, c.np, r->f64(), r->leaders, r->st))
+        st = launch_dgwo(pv, r->leaders, r->dg_tab, float4{}, c.seed, r->gen, 0u, c.inst, r->tbits, r->ld, r->st);
+        if (st != QPM_OK) return st;
+    } else {
+        QPM_STEP(QPM_K_GWO, launch_gwo(pv, r->leaders, r->a_tab, 0.0f, c.seed, r->gen, 0u, c.inst, c.gwo_variant,
+                                       r->tbits, r->ld, r->st))
+    }
     QPM_STEP(QPM_K_FIT_GWO, eval_partials(r))
     QPM_STEP(QPM_K_FINISH_GWO, eval_finish(r, r->leaders, nullptr, nullptr, r->draws))
     if (r->adaptive()) {  // F of the next generation (timed with the finish)
@@ -382,7 +391,7 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
     QPM_REQUIRE(c.F >= 0.0f && c.F <= 2.0f, QPM_EINVAL, "F must be in [0, 2] (got %g)", (double)c.F);
     QPM_REQUIRE(c.CR >= 0.0f && c.CR <= 1.0f, QPM_EINVAL, "CR must be in [0, 1] (got %g)", (double)c.CR);
     QPM_REQUIRE(c.prec == QPM_PREC_F32 || c.prec == QPM_PREC_F64, QPM_EINVAL, "unknown precision %d", c.prec);
-    QPM_REQUIRE(c.gwo_variant == 0 || c.gwo_variant == 1, QPM_EINVAL, "gwo_variant must be 0 or 1");
+    QPM_REQUIRE(c.gwo_variant >= 0 && c.gwo_variant <= 2, QPM_EINVAL, "gwo_variant must be 0, 1 or 2");
     QPM_REQUIRE(c.inst < (1u << 24), QPM_EINVAL, "inst must be < 2^24");
     QPM_REQUIRE(c.fit_kernel == QPM_FIT_AUTO || c.fit_kernel == QPM_FIT_SEGMENTED ||
                     c.fit_kernel == QPM_FIT_PER_GENOME || c.fit_kernel == QPM_FIT_TABLE,
@@ -418,12 +427,13 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
     if (e == hipSuccess) e = hipMalloc(&r->f_cur, es * c.np);
     if (e == hipSuccess) e = hipMalloc(&r->f_new, es * c.np);
     if (e == hipSuccess) e = hipMalloc(&r->tbits, sizeof(uint32_t) * r->W * r->ld);
-    if (e == hipSuccess) e = hipMalloc(&r->leaders, sizeof(int32_t) * 3);
+    if (e == hipSuccess) e = hipMalloc(&r->leaders, sizeof(int32_t) * 4);  // the fourth for variant 2
     if (e == hipSuccess) e = hipMalloc(&r->best, sizeof(int32_t) * 3);
     if (e == hipSuccess) e = hipMalloc(&r->gen, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&r->a_tab, sizeof(float) * c.generations);
     if (e == hipSuccess) e = hipMalloc(&r->F_tab, sizeof(float) * c.generations);
     if (e == hipSuccess && r->adaptive()) e = hipMalloc(&r->F_base, sizeof(double) * c.generations);
+    if (e == hipSuccess && c.gwo_variant == 2) e = hipMalloc(&r->dg_tab, sizeof(float4) * c.generations);
     if (e == hipSuccess) e = hipMalloc(&r->draws, sizeof(int4) * c.np);
     if (e != hipSuccess) {
         set_error("run allocation failed: %s", hipGetErrorString(e));
@@ -436,6 +446,9 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
     // decay law base(g) = 0.1 (cos(pi t / 2) + 1) / 2 (1 - 0.2 t^2)
     std::vector<float> a(c.generations), F(c.generations);
     std::vector<double> base(r->adaptive() ? c.generations : 0);
+    // discrete four-leader step: t, 1 - 2 eps, eps = 0.1 (1 - t) + 0.01 t,
+    // lambda = 0.2 (1 - t), each rounded to float once
+    std::vector<float4> dg(c.gwo_variant == 2 ? c.generations : 0);
     for (int64_t g = 0; g < c.generations; ++g) {
         const double t = static_cast<double>(g) / static_cast<double>(c.generations);
         if (c.control == QPM_CONTROL_FIXED) {
@@ -446,6 +459,11 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
             F[g] = a[g];
         }
         if (r->adaptive()) base[g] = 0.1 * (0.5 * (std::cos(0.5 * M_PI * t) + 1.0)) * (1.0 - 0.2 * t * t);
+        if (c.gwo_variant == 2) {
+            const float eps = static_cast<float>(0.1 * (1.0 - t) + 0.01 * t);
+            dg[g] = make_float4(static_cast<float>(t), static_cast<float>(1.0 - 2.0 * static_cast<double>(eps)), eps,
+                                static_cast<float>(0.2 * (1.0 - t)));
+        }
     }
 
     hipEvent_t ev = nullptr;
@@ -458,6 +476,8 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
         e = hipMemcpyAsync(r->F_tab, F.data(), sizeof(float) * c.generations, hipMemcpyHostToDevice, r->st);
     if (e == hipSuccess && r->adaptive())
         e = hipMemcpyAsync(r->F_base, base.data(), sizeof(double) * c.generations, hipMemcpyHostToDevice, r->st);
+    if (e == hipSuccess && c.gwo_variant == 2)
+        e = hipMemcpyAsync(r->dg_tab, dg.data(), sizeof(float4) * c.generations, hipMemcpyHostToDevice, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->flags, 0, sizeof(uint32_t) * c.np, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->fbits, 0, sizeof(uint32_t) * 2 * ((c.np + 63) / 64), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->gen, 0, sizeof(uint32_t), r->st);

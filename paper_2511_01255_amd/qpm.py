@@ -67,6 +67,7 @@ _SIGS = {
     "qpm_de_step": (_I32, [_P, _I64, _I64, _I64, _F, _F, _U64, _U32, _U32, _P, _P, _I64, _P]),
     "qpm_de_step_shape": (_I32, [_P, _I64, _I64, _I64, _F, _F, _U64, _U32, _U32, _P, _P, _I64, _I32, _I32, _P]),
     "qpm_gwo_step": (_I32, [_P, _I64, _I64, _I64, _P, _F, _U64, _U32, _U32, _I32, _P, _P, _I64, _P]),
+    "qpm_dgwo_step": (_I32, [_P, _I64, _I64, _I64, _P, _P, _U64, _U32, _U32, _P, _P, _I64, _P]),
     "qpm_relax_forward": (_I32, [_P, _I32, _P, _I64, _I64, _P, _P, _P, _P]),
     "qpm_relax_edges_size": (_I32, [_P, _I32, _I64, _P]),
     "qpm_relax_backward": (_I32, [_P, _I32, _P, _I64, _I64, _P, _P, _P, _P, _I64, _P]),
@@ -298,6 +299,21 @@ def gwo_step(x, D, leaders, a, seed, generation, inst=0, variant=0, stream=None)
     yb = torch.zeros((words(D), ld), dtype=torch.int32, device=x.device)
     _check(lib().qpm_gwo_step(_ptr(x), np_, D, ldx, _ptr(leaders), a, seed, generation, inst, variant, _ptr(y),
                               _ptr(yb), ld, _stream(stream)))
+    return y, yb
+
+
+def dgwo_step(x, D, leaders, params, seed, generation, inst=0, stream=None):
+    """The discrete four-leader step. x: float32 CUDA tensor (np, ldx);
+    leaders: int32 CUDA tensor (4,); params: 4 floats (t, 1 - 2 eps, eps,
+    lambda). Returns (y, y_bits) like gwo_step."""
+    import torch
+    np_, ldx = x.shape
+    ld = ld_for(np_)
+    y = x.clone()
+    yb = torch.zeros((words(D), ld), dtype=torch.int32, device=x.device)
+    par = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().qpm_dgwo_step(_ptr(x), np_, D, ldx, _ptr(leaders), par.ctypes.data, seed, generation, inst,
+                               _ptr(y), _ptr(yb), ld, _stream(stream)))
     return y, yb
 
 

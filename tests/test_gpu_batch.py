@@ -91,6 +91,13 @@ def test_batch_run_fp64_equals_oracle_runs(q, orc):
     R.destroy()
 
 
+def test_batch_run_rejects_unsupported_options(q):
+    specs = _small_batch()[1:3]
+    B = q.precompute_phases_batched([s[0] for s in specs], [s[1] for s in specs], [s[2] for s in specs])
+    with pytest.raises(q.QpmError):
+        q.BatchRun(B, 16, 4, gwo_variant=2)
+
+
 def test_batch_run_tuned_and_graph_agree(q):
     specs = _small_batch()
     npop, G = 40, 6

@@ -229,6 +229,42 @@ def test_gwo_step_matches_oracle(q, orc, np_, D, variant):
         assert np.array_equal(got, orc.sign_map(yo)[keep])
 
 
+@pytest.mark.parametrize("np_,D", [(37, 203), (4, 5), (300, 1001), (1024, 10000)])
+def test_dgwo_step_matches_oracle(q, orc, np_, D):
+    # the discrete four-leader step (the library's reading of Sec. 3.1.2):
+    # genes and bits bit-exact for early, middle and late parameters
+    import torch
+    x, _ = q.init_population(np_, D, seed=7)
+    rng = np.random.default_rng(np_ * 3 + D)
+    L = rng.choice(np_, size=4, replace=False).astype(np.int32)
+    Ld = torch.from_numpy(L).cuda()
+    for g, G in ((0, 50), (25, 50), (49, 50)):
+        par = orc.dgwo_params(g, G)
+        y, yb = q.dgwo_step(x, D, Ld, par, seed=9, generation=g, inst=2)
+        yo = orc.dgwo_step(_host(x, D), L, par, seed=9, g=g, inst=2)
+        assert np.array_equal(_host(y, D), yo)
+        keep = np.setdiff1d(np.arange(np_), L[:3])
+        got = inputs.unpack_bits(yb.cpu().numpy(), np_, D)[keep]
+        assert np.array_equal(got, orc.sign_map(yo)[keep])
+    for bad in ([0, 1, 2, 2], [0, 1, 2, np_]):
+        with pytest.raises(q.QpmError):
+            q.dgwo_step(x, D, torch.tensor(bad, dtype=torch.int32).cuda(), par, 9, 0)
+
+
+@pytest.mark.parametrize("graph", [1, 0])
+def test_run_discrete_gwo_fp64_equals_oracle(q, orc, graph):
+    n, npop, G = 400, 48, 20
+    z = inputs.jittered_boundaries(n, 2.0, 0.25, seed=4)
+    D = q.precompute_phases(z, DK1, DK2)
+    xo, fo, _ = orc.Design(z, DK1, DK2).hwsda_run(npop, G, 0.5, 0.9, 12, inst=1, variant=2)
+    R = q.Run(D, npop, G, seed=12, inst=1, prec=1, gwo_variant=2, use_graph=graph)
+    R.advance(G)
+    x, f, _, _ = R.read()
+    assert np.array_equal(x.cpu().numpy(), xo)
+    assert np.max(np.abs(f.cpu().numpy() - fo) / fo) <= 1e-12
+    R.destroy()
+
+
 def test_gwo_rejects_invalid_leaders(q):
     import torch
     x, _ = q.init_population(8, 16, seed=1)
