@@ -258,11 +258,13 @@ def main():
         log("[bench] NP=1024 run: %.1f generations/s" % (1.0 / t3))
 
         # the same run under the paper's parameter control: F = a from 0.1 to
-        # 0.01, and the adaptive F (one extra one-workgroup statistics kernel
-        # per generation)
+        # 0.01, the adaptive F (one extra one-workgroup statistics kernel per
+        # generation), and the adaptive F with the discrete four-leader GWO
         ctl = {}
-        for name, control in (("decay", qpm.CONTROL_DECAY), ("adaptive", qpm.CONTROL_ADAPTIVE)):
-            Rc = qpm.Run(design, 1024, 5000, CR=CR, seed=0, prec=qpm.PREC_F32, tune=1, control=control)
+        for name, control, variant in (("decay", qpm.CONTROL_DECAY, 0), ("adaptive", qpm.CONTROL_ADAPTIVE, 0),
+                                       ("adaptive_discrete_gwo", qpm.CONTROL_ADAPTIVE, 2)):
+            Rc = qpm.Run(design, 1024, 5000, CR=CR, seed=0, prec=qpm.PREC_F32, tune=1, control=control,
+                         gwo_variant=variant)
             Rc.advance(20)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
