@@ -38,7 +38,11 @@
  *                      S = sum_n d_n b_n P_{n-1} + sum_n c_n   (d_n^2 = 1).
  *
  * Optimiser (paper Sec. 2.2.1 DE, Sec. 2.2.2 GWO, Sec. 3.2 HWSDA steps):
- * see the comments at each function. Random numbers come from
+ * see the comments at each function.
+ *
+ * Parity unpinned: orc_dgwo_step, the improved discrete four-leader GWO of
+ * Sec. 3.1.2, which the paper gives in prose only; it implements a stated
+ * reading and its tests pin the reading, not the paper. Random numbers come from
  * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
  * easy as 1, 2, 3", SC'11), implemented here from that definition.
  */
