@@ -336,7 +336,21 @@ typedef struct {
                             and DE kernels at creation and keep the fastest
                             (cached per problem size; QPM_TUNE_CACHE file) */
     int32_t control;     /* qpm_control: how F_g and a_g are set */
+    int32_t trials;      /* qpm_trials: where the DE trial genes go */
 } qpm_run_config;
+
+/*
+ * Trial storage of a run's DE step (results are identical; speed differs):
+ *   QPM_TRIALS_AUTO      ACCEPTED when the two gene buffers exceed 256 MB
+ *                        (the last-level cache) and np <= 65536, else STORE;
+ *   QPM_TRIALS_STORE     every trial's genes are written, selection keeps
+ *                        or drops them;
+ *   QPM_TRIALS_ACCEPTED  the DE step writes the trials' bits only; after
+ *                        the selection, the accepted trials' genes are
+ *                        computed again from the same draws and written
+ *                        (np <= 65536, else QPM_EINVAL).
+ */
+typedef enum { QPM_TRIALS_AUTO = 0, QPM_TRIALS_STORE = 1, QPM_TRIALS_ACCEPTED = 2 } qpm_trials;
 
 /*
  * Parameter control (paper Sec. 3.1.1 and the parameter settings of

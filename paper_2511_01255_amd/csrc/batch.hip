@@ -1028,6 +1028,7 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
     QPM_REQUIRE(c.gwo_variant == 0 || c.gwo_variant == 1, c.gwo_variant == 2 ? QPM_ENOTSUP : QPM_EINVAL,
                 "batched runs take gwo_variant 0 or 1 (got %d)", (int)c.gwo_variant);
     QPM_REQUIRE(c.control == QPM_CONTROL_FIXED, QPM_ENOTSUP, "batched runs use the fixed parameter control only");
+    QPM_REQUIRE(c.trials != QPM_TRIALS_ACCEPTED, QPM_ENOTSUP, "batched runs store every trial");
     QPM_REQUIRE(static_cast<int64_t>(c.inst) + b->n_inst <= (int64_t(1) << 24), QPM_EINVAL,
                 "inst + n_inst must be <= 2^24");
     qpm_status st = check_device();

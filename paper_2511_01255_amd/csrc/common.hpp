@@ -95,10 +95,18 @@ qpm_status launch_fitness_partials(const Design &d, qpm_prec p, const uint32_t *
 // fbits (optional): packed copy of flags, 2 ceil(np / 64) words; cand:
 // scratch of finish_cand_bytes(np) for the leader candidates (needed with
 // top3_out)
+// Selection outputs of a run without stored trials (all optional, together):
+// the accepted slots appended to acc_list at *acc_cnt, and the packed flags
+// from before the selection in fbits_prev.
+struct AcceptOut {
+    int32_t *list = nullptr;
+    uint32_t *cnt = nullptr;
+    uint32_t *fbits_prev = nullptr;
+};
 qpm_status launch_finish(const double *part, int gy, int64_t ld, int64_t np, const double *C, void *f_cur,
                          bool f64, uint32_t *flags, uint32_t *fbits, const int32_t *skip3, int32_t *top3_out,
                          void *cand, int4 *draws_next, uint32_t *gen, int64_t D, uint64_t seed, uint32_t inst,
-                         hipStream_t s);
+                         hipStream_t s, AcceptOut acc = AcceptOut{});
 inline size_t finish_cand_bytes(int64_t np)
 {
     return static_cast<size_t>((np + 63) / 64) * 3 * (sizeof(double) + sizeof(int32_t));
@@ -150,7 +158,7 @@ qpm_status launch_objective_values(const Objective &o, const ObjPlan &pl, const 
 qpm_status launch_objective_finish(const Objective &o, const ObjPlan &pl, const double *part, int64_t ld, int64_t np,
                                    void *f_cur, bool f64, uint32_t *flags, uint32_t *fbits, const int32_t *skip3,
                                    int32_t *top3_out, void *cand, int4 *draws_next, uint32_t *gen, int64_t D,
-                                   uint64_t seed, uint32_t inst, hipStream_t s);
+                                   uint64_t seed, uint32_t inst, hipStream_t s, AcceptOut acc = AcceptOut{});
 
 // ---------------------------------------------------------------- evolution kernels
 
@@ -185,7 +193,14 @@ inline uint32_t cr_threshold(float CR)
 qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const uint32_t *gen_dev,
                      uint32_t gen, uint32_t inst, uint32_t *bits, int64_t ld, int4 *draws, bool compute_draws,
                      hipStream_t s, int ipw = 0, int passes = 1, const uint32_t *fbits = nullptr,
-                     const float *F_tab = nullptr);
+                     const float *F_tab = nullptr, bool store_genes = true, uint32_t *reset_cnt = nullptr);
+// store_genes = false: the DE kernel writes the trials' bits only (and
+// zeroes reset_cnt); launch_materialize then writes the genes of the
+// accepted trials listed by the finish step (list, *cnt), reading the
+// population before the selection through its packed flags fb_old
+qpm_status launch_materialize(const PopView &pv, const int4 *draws, const uint32_t *fb_old, float F,
+                              const float *F_tab, float CR, uint64_t seed, const uint32_t *gen, uint32_t inst,
+                              const int32_t *list, const uint32_t *cnt, hipStream_t s);
 // segmented plan with an explicit shape
 FitPlan plan_fitness_shape(const Design &d, int waves, int wpw);
 // table plan: gw genome groups of 64 per workgroup, wpw words per wave

@@ -80,7 +80,8 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
                                                  const float *__restrict__ F_tab, uint32_t cr_max,
                                                  uint32_t k0, uint32_t k1, const uint32_t *__restrict__ gen_dev,
                                                  uint32_t gen_c, uint32_t inst, uint32_t *__restrict__ bits,
-                                                 int64_t ld, int groups, int chunks)
+                                                 int64_t ld, int groups, int chunks, int store_genes,
+                                                 uint32_t *__restrict__ reset_cnt)
 {
     constexpr int LPI = 64 / IPW;  // lanes per individual
     constexpr int CW = 4 * LPI;    // genes per chunk
@@ -102,6 +103,9 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
     const int64_t j0 = static_cast<int64_t>(c) * CW + 4 * li;
     const uint32_t g = gen_dev ? gen_dev[0] : gen_c;
     const float Fg = F_tab ? F_tab[g] : F;  // a run's per-generation F
+    // a run without stored trials: the list counter of the accepted trials
+    // starts at 0 for this generation (the finish step appends to it)
+    if (reset_cnt != nullptr && b == 0 && threadIdx.x == 0) reset_cnt[0] = 0u;
     __shared__ uint32_t wsh[IPB][WPC];
     extern __shared__ uint32_t sfb[];  // PACKED: (np + 31) / 32 flag words
     int4 dr[R];
@@ -153,12 +157,14 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
             const int64_t i = i0 + r * IPG;
             const float4 uv = de_quad(cur[0], cur[1], cur[2], cur[3], j0, dr[r].w, static_cast<uint32_t>(i), g, inst,
                                       k0, k1, Fg, cr_max);
-            float *dst;
-            if constexpr (PACKED)
-                dst = pv.out0 + packed_row(i, 1u);
-            else
-                dst = (second(i) ? pv.out0 : pv.out1) + i * pv.ldx;
-            store_quad_nt(dst, j0, D, uv);
+            if (store_genes) {
+                float *dst;
+                if constexpr (PACKED)
+                    dst = pv.out0 + packed_row(i, 1u);
+                else
+                    dst = (second(i) ? pv.out0 : pv.out1) + i * pv.ldx;
+                store_quad_nt(dst, j0, D, uv);
+            }
             nib = quad_nibble(uv, j0, D);
         }
         // merge the nibbles of 8 neighbouring lanes (32 genes) into one word
@@ -181,6 +187,73 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
         const int64_t wg = static_cast<int64_t>(c) * WPC + wd;
         if (row < np && wg * 32 < D) bits[wg * ld + row] = wsh[ii][wd];
     }
+}
+
+// The accepted trials of a run whose DE step stored only their bits: the
+// trial genes of every individual in list[0 .. cnt) are computed again,
+// exactly as the DE kernel computed them (same draws, words and de_quad),
+// from the population before the selection (fb_old: its packed flags), and
+// written to the buffer that the selection made current. A work item is
+// (chunk of 256 genes, listed individual) for one wave. Chunk c belongs to
+// XCD c mod 8 (workgroup x runs on XCD x mod 8), and each XCD walks its
+// items chunk by chunk, so the waves running together on an XCD read the
+// same chunk of many rows and donor rows shared between accepted trials
+// come from its L2. The grid is fixed; every wave loops until its XCD's
+// items run out.
+__global__ __launch_bounds__(256) void materialize_kernel(PopView pv, const int4 *__restrict__ draws,
+                                                          const uint32_t *__restrict__ fb_old, float F,
+                                                          const float *__restrict__ F_tab, uint32_t cr_max,
+                                                          uint32_t k0, uint32_t k1, const uint32_t *__restrict__ gen,
+                                                          uint32_t inst, const int32_t *__restrict__ list,
+                                                          const uint32_t *__restrict__ cnt)
+{
+    extern __shared__ uint32_t sfb[];  // (np + 31) / 32 old flag words
+    const int64_t np = pv.np, D = pv.D;
+    for (int k = threadIdx.x; k < static_cast<int>((np + 31) / 32); k += 256) sfb[k] = fb_old[k];
+    __syncthreads();
+    const uint32_t g = gen[0];
+    const float Fg = F_tab ? F_tab[g] : F;
+    const int64_t n_acc = min(static_cast<int64_t>(cnt[0]), np);
+    const int64_t chunks = (D + 255) / 256;
+    const int xcd = static_cast<int>(blockIdx.x & 7u);
+    const int64_t wg_per_xcd = gridDim.x / 8;  // the grid is a multiple of 8
+    const int64_t my_chunks = chunks > xcd ? (chunks - xcd + 7) / 8 : 0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t np32 = static_cast<uint32_t>(np), ldx24 = static_cast<uint32_t>(pv.ldx) & 0xFFFFFFu;
+    auto row = [&](int64_t r, uint32_t flip) -> const float * {
+        const uint32_t rr = static_cast<uint32_t>(r);
+        const uint32_t b = ((sfb[rr >> 5] >> (rr & 31u)) & 1u) ^ flip;
+        return pv.x0 + static_cast<uint64_t>((rr + b * np32) & 0xFFFFFFu) * ldx24;
+    };
+    for (int64_t it = static_cast<int64_t>(blockIdx.x >> 3) * 4 + wave; it < n_acc * my_chunks;
+         it += wg_per_xcd * 4) {
+        const int64_t c = xcd + 8 * (it / n_acc);
+        const int64_t i = list[it % n_acc];
+        const int64_t j0 = c * 256 + 4 * lane;
+        if (i < 0 || i >= np || j0 >= D) continue;
+        const int4 dr = draws[i];
+        const float4 xv = *reinterpret_cast<const float4 *>(row(i, 0u) + j0);
+        const float4 a = *reinterpret_cast<const float4 *>(row(dr.x, 0u) + j0);
+        const float4 bq = *reinterpret_cast<const float4 *>(row(dr.y, 0u) + j0);
+        const float4 cq = *reinterpret_cast<const float4 *>(row(dr.z, 0u) + j0);
+        const float4 uv = de_quad(xv, a, bq, cq, j0, dr.w, static_cast<uint32_t>(i), g, inst, k0, k1, Fg, cr_max);
+        store_quad_nt(const_cast<float *>(row(i, 1u)), j0, D, uv);
+    }
+}
+
+qpm_status launch_materialize(const PopView &pv, const int4 *draws, const uint32_t *fb_old, float F,
+                              const float *F_tab, float CR, uint64_t seed, const uint32_t *gen, uint32_t inst,
+                              const int32_t *list, const uint32_t *cnt, hipStream_t s)
+{
+    QPM_REQUIRE(pv.np <= 65536 && pv.ldx < (int64_t(1) << 24) && pv.x1 == pv.x0 + pv.np * pv.ldx &&
+                    pv.out0 == pv.x0 && pv.out1 == pv.x1,
+                QPM_EINVAL, "materialising trials needs one allocation for both gene buffers");
+    const size_t lds = sizeof(uint32_t) * static_cast<size_t>((pv.np + 31) / 32);
+    materialize_kernel<<<2048, 256, lds, s>>>(pv, draws, fb_old, F, F_tab, cr_threshold(CR),
+                                              static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), gen,
+                                              inst, list, cnt);
+    QPM_TRY_HIP(hipGetLastError());
+    return QPM_OK;
 }
 
 // ------------------------------------------------------------ grey-wolf update
@@ -380,9 +453,11 @@ qpm_status launch_init(int64_t np, int64_t D, int64_t ldx, uint64_t seed, uint32
 
 qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const uint32_t *gen_dev, uint32_t gen,
                      uint32_t inst, uint32_t *bits, int64_t ld, int4 *draws, bool compute_draws, hipStream_t s,
-                     int ipw_req, int passes, const uint32_t *fbits, const float *F_tab)
+                     int ipw_req, int passes, const uint32_t *fbits, const float *F_tab, bool store_genes,
+                     uint32_t *reset_cnt)
 {
     QPM_REQUIRE(F_tab == nullptr || gen_dev != nullptr, QPM_EINVAL, "an F table needs the device generation");
+    QPM_REQUIRE(store_genes || fbits != nullptr, QPM_EINVAL, "trials that are not stored need the packed flags");
     // the packed-flag path: one allocation for both buffers, flags staged
     // in LDS (at most 65536 individuals, 8 KB), 24-bit row arithmetic
     const bool packed = fbits != nullptr && pv.np <= 65536 && pv.ldx < (int64_t(1) << 24) &&
@@ -408,10 +483,10 @@ qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const 
 #define QPM_DE(I, P)                                                                                            \
     if (packed)                                                                                                 \
         de_kernel<I, P, true><<<nb, 256, lds, s>>>(pv, draws, fbits, F, F_tab, cr_max, k0, k1, gen_dev, gen,     \
-                                                   inst, bits, ld, gr, ch);                                     \
+                                                   inst, bits, ld, gr, ch, store_genes ? 1 : 0, reset_cnt);     \
     else                                                                                                        \
         de_kernel<I, P, false><<<nb, 256, 0, s>>>(pv, draws, nullptr, F, F_tab, cr_max, k0, k1, gen_dev, gen,    \
-                                                  inst, bits, ld, gr, ch);
+                                                  inst, bits, ld, gr, ch, store_genes ? 1 : 0, reset_cnt);
     if (ipw == 1) {
         if (R == 1) { QPM_DE(1, 1) } else if (R == 2) { QPM_DE(1, 2) } else { QPM_DE(1, 4) }
     } else if (ipw == 2) {

@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void obj_finish_kernel(ObjTabs tabs, int K, do
                                                          const int32_t *__restrict__ skip3, T *__restrict__ cand_v,
                                                          int32_t *__restrict__ cand_i, int4 *__restrict__ draws_next,
                                                          const uint32_t *__restrict__ gen, int64_t D, uint32_t k0,
-                                                         uint32_t k1, uint32_t inst)
+                                                         uint32_t k1, uint32_t inst, AcceptOut acc)
 {
     __shared__ double sh[6 * 4 * 64];
     const int lane = threadIdx.x & 63;
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(256) void obj_finish_kernel(ObjTabs tabs, int K, do
     const double v = obj_value<THG>(tabs, K, scale, G0, beta, part, gy, ld, i, i < np, nullptr, 0, sh);
     if (threadIdx.x < 64)
         select_group<T>(v, blockIdx.x, lane, np, f_cur, flags, fbits, skip3, cand_v, cand_i, draws_next, gen, D, k0,
-                        k1, inst);
+                        k1, inst, acc);
 }
 
 ObjPlan plan_objective_shape(const Objective &o, int wpw)
@@ -326,7 +326,7 @@ qpm_status launch_objective_values(const Objective &o, const ObjPlan &pl, const 
 qpm_status launch_objective_finish(const Objective &o, const ObjPlan &pl, const double *part, int64_t ld, int64_t np,
                                    void *f_cur, bool f64, uint32_t *flags, uint32_t *fbits, const int32_t *skip3,
                                    int32_t *top3_out, void *cand, int4 *draws_next, uint32_t *gen, int64_t D,
-                                   uint64_t seed, uint32_t inst, hipStream_t s)
+                                   uint64_t seed, uint32_t inst, hipStream_t s, AcceptOut acc)
 {
     const unsigned blocks = static_cast<unsigned>((np + 63) / 64);
     QPM_REQUIRE(top3_out == nullptr || cand != nullptr, QPM_EINVAL, "leader candidates need a buffer");
@@ -340,7 +340,7 @@ qpm_status launch_objective_finish(const Objective &o, const ObjPlan &pl, const 
         int32_t *ci = cv ? reinterpret_cast<int32_t *>(cv + 3 * static_cast<size_t>(blocks)) : nullptr;          \
         obj_finish_kernel<T, H><<<blocks, 256, 0, s>>>(o.tabs, o.K, o.scale, o.G0, o.beta, part, pl.gy, ld, np,  \
                                                        static_cast<T *>(f_cur), flags, fbits, skip3, cv, ci,     \
-                                                       draws_next, gen, D, k0, k1, inst);                         \
+                                                       draws_next, gen, D, k0, k1, inst, acc);                    \
         if (top3_out || advance) finish_tail_kernel<T><<<1, 256, 0, s>>>(cv, ci, blocks, top3_out, gen, advance); \
     }
     if (f64) {

@@ -44,6 +44,13 @@ struct qpm_run_s {
     double *F_base = nullptr;   // decay law of the adaptive control
     int4 *draws = nullptr;
     double *fws = nullptr;
+    // trials not stored by the DE step: the accepted ones are listed by the
+    // finish step and materialised afterwards (the DE step then writes bits
+    // only, and the rejected majority costs no gene writes)
+    bool lazy = false;
+    int32_t *acc_list = nullptr;   // np slots
+    uint32_t *acc_cnt = nullptr;
+    uint32_t *fbits_prev = nullptr;  // packed flags before the selection
     FitPlan plan;
     int de_ipw = 0;     // 0 = chosen from np
     int de_passes = 1;  // groups of individuals per DE workgroup
@@ -96,6 +103,9 @@ static void release(qpm_run_s *r)
     (void)hipFree(r->F_base);
     (void)hipFree(r->fws);
     (void)hipFree(r->draws);
+    (void)hipFree(r->acc_list);
+    (void)hipFree(r->acc_cnt);
+    (void)hipFree(r->fbits_prev);
     (void)hipFree(r->pol);
     (void)hipFree(r->pol_S);
     (void)hipFree(r->pol_f);
@@ -120,16 +130,17 @@ static qpm_status eval_partials(qpm_run_s *r)
 }
 
 // combine + selection (+ leaders or the next generation's draws and advance)
-static qpm_status eval_finish(qpm_run_s *r, const int32_t *skip3, int32_t *top3_out, void *cand, int4 *draws_next)
+static qpm_status eval_finish(qpm_run_s *r, const int32_t *skip3, int32_t *top3_out, void *cand, int4 *draws_next,
+                              AcceptOut acc = AcceptOut{})
 {
     const qpm_run_config &c = r->cfg;
     if (r->obj)
         return launch_objective_finish(*r->obj, r->oplan, r->fws, r->ld, c.np, r->f_cur, r->f64(), r->flags,
                                        r->fbits, skip3, top3_out, cand, draws_next, r->gen, r->D, c.seed, c.inst,
-                                       r->st);
+                                       r->st, acc);
     const int gy = r->plan.kind == QPM_FIT_PER_GENOME ? 1 : r->plan.gy;
     return launch_finish(r->fws, gy, r->ld, c.np, r->d->Cdev, r->f_cur, r->f64(), r->flags, r->fbits, skip3,
-                         top3_out, cand, draws_next, r->gen, r->D, c.seed, c.inst, r->st);
+                         top3_out, cand, draws_next, r->gen, r->D, c.seed, c.inst, r->st, acc);
 }
 
 // the fitness of the genomes in tbits into f_cur (no selection)
@@ -160,9 +171,16 @@ static qpm_status enqueue_generation(qpm_run_s *r, hipEvent_t *ev = nullptr)
     if ((st = mark(k)) != QPM_OK) return st;      \
     if ((st = (call)) != QPM_OK) return st;
     QPM_STEP(QPM_K_DE, launch_de(pv, c.F, c.CR, c.seed, r->gen, 0u, c.inst, r->tbits, r->ld, r->draws, false, r->st,
-                                 r->de_ipw, r->de_passes, r->fbits, r->F_tab))
+                                 r->de_ipw, r->de_passes, r->fbits, r->F_tab, !r->lazy,
+                                 r->lazy ? r->acc_cnt : nullptr))
     QPM_STEP(QPM_K_FIT_DE, eval_partials(r))
-    QPM_STEP(QPM_K_FINISH_DE, eval_finish(r, nullptr, r->leaders, r->cand, nullptr))
+    QPM_STEP(QPM_K_FINISH_DE, eval_finish(r, nullptr, r->leaders, r->cand, nullptr,
+                                          r->lazy ? AcceptOut{r->acc_list, r->acc_cnt, r->fbits_prev} : AcceptOut{}))
+    if (r->lazy) {  // the accepted trials' genes (timed with the finish)
+        st = launch_materialize(pv, r->draws, r->fbits_prev, c.F, r->F_tab, c.CR, c.seed, r->gen, c.inst,
+                                r->acc_list, r->acc_cnt, r->st);
+        if (st != QPM_OK) return st;
+    }
     if (c.gwo_variant == 2) {
         // the fourth leader (after DE selection), then the discrete step
         QPM_STEP(QPM_K_GWO, launch_fourth(r->f_cur, c.np, r->f64(), r->leaders, r->st))
@@ -359,7 +377,7 @@ static qpm_status tune_run(qpm_run_s *r)
                     float ms = 0.0f;
                     st = time_min([&]() {
                         return launch_de(pv, c.F, c.CR, c.seed, r->gen, 0u, c.inst, r->tbits, r->ld, r->draws, false,
-                                         r->st, cand, np_, r->fbits);
+                                         r->st, cand, np_, r->fbits, nullptr, !r->lazy, nullptr);
                     },
                                &ms);
                     if (st != QPM_OK) return st;
@@ -401,6 +419,8 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
     QPM_REQUIRE(c.control == QPM_CONTROL_FIXED || c.control == QPM_CONTROL_DECAY ||
                     c.control == QPM_CONTROL_ADAPTIVE,
                 QPM_EINVAL, "unknown parameter control %d", c.control);
+    QPM_REQUIRE(c.trials == QPM_TRIALS_AUTO || c.trials == QPM_TRIALS_STORE || c.trials == QPM_TRIALS_ACCEPTED,
+                QPM_EINVAL, "unknown trial storage %d", c.trials);
     qpm_status st = check_device();
     if (st != QPM_OK) return st;
 
@@ -412,6 +432,21 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
     r->ldx = ((r->D + 63) / 64) * 64;
     r->ld = ((c.np + 63) / 64) * 64;
     r->W = d->words;
+    // trials are materialised only for the accepted ones when the two gene
+    // buffers exceed the 256 MB last-level cache (MALL): then every stored
+    // trial costs HBM write bandwidth, while recomputing an accepted one
+    // reads four rows; a smaller population absorbs the trial writes in
+    // the MALL and stores them all (measured: N = 10^4, NP = 4096 gains
+    // about 6 % per generation, NP = 1024 would lose about 3 %)
+    const bool lazy_ok = c.np <= 65536 && r->ldx < (int64_t(1) << 24);
+    if (c.trials == QPM_TRIALS_ACCEPTED && !lazy_ok) {
+        set_error("materialising accepted trials needs np <= 65536");
+        release(r);
+        return QPM_EINVAL;
+    }
+    r->lazy = c.trials == QPM_TRIALS_ACCEPTED ||
+              (c.trials == QPM_TRIALS_AUTO && lazy_ok &&
+               2 * static_cast<int64_t>(sizeof(float)) * c.np * r->ldx > (int64_t(256) << 20));
     r->plan = plan_fitness(*d, static_cast<qpm_prec>(c.prec), c.np, c.fit_kernel);
     if (obj) r->oplan = plan_objective(*obj, static_cast<qpm_prec>(c.prec), c.np);
     const size_t es = r->f64() ? sizeof(double) : sizeof(float);
@@ -435,6 +470,9 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
     if (e == hipSuccess && r->adaptive()) e = hipMalloc(&r->F_base, sizeof(double) * c.generations);
     if (e == hipSuccess && c.gwo_variant == 2) e = hipMalloc(&r->dg_tab, sizeof(float4) * c.generations);
     if (e == hipSuccess) e = hipMalloc(&r->draws, sizeof(int4) * c.np);
+    if (e == hipSuccess && r->lazy) e = hipMalloc(&r->acc_list, sizeof(int32_t) * c.np);
+    if (e == hipSuccess && r->lazy) e = hipMalloc(&r->acc_cnt, sizeof(uint32_t));
+    if (e == hipSuccess && r->lazy) e = hipMalloc(&r->fbits_prev, sizeof(uint32_t) * 2 * ((c.np + 63) / 64));
     if (e != hipSuccess) {
         set_error("run allocation failed: %s", hipGetErrorString(e));
         release(r);
@@ -481,6 +519,7 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
     if (e == hipSuccess) e = hipMemsetAsync(r->flags, 0, sizeof(uint32_t) * c.np, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->fbits, 0, sizeof(uint32_t) * 2 * ((c.np + 63) / 64), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->gen, 0, sizeof(uint32_t), r->st);
+    if (e == hipSuccess && r->lazy) e = hipMemsetAsync(r->acc_cnt, 0, sizeof(uint32_t), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->tbits, 0, sizeof(uint32_t) * r->W * r->ld, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->buf[1], 0, gene_bytes, r->st);
     if (e == hipSuccess) e = hipStreamSynchronize(r->st);  // the host tables must outlive the copies

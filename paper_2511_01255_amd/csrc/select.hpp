@@ -13,26 +13,30 @@ namespace qpm {
 // Selection for the 64 genomes of group grp (i = 64 grp + lane), from their
 // fitness `value` (rounded to T here); called by one whole wave. Writes
 // f_cur, flags, the group's two packed flag words, the DE draws of
-// generation gen + 1 (with draws_next) and the group's three best (with
-// cand_v).
+// generation gen + 1 (with draws_next), the group's three best (with
+// cand_v) and, with acc.list, the accepted slots (appended in any order)
+// and the packed flags from before the selection.
 template <typename T>
 __device__ __forceinline__ void select_group(double value, int64_t grp, int lane, int64_t np, T *__restrict__ f_cur,
                                              uint32_t *__restrict__ flags, uint32_t *__restrict__ fbits,
                                              const int32_t *__restrict__ skip3, T *__restrict__ cand_v,
                                              int32_t *__restrict__ cand_i, int4 *__restrict__ draws_next,
                                              const uint32_t *__restrict__ gen, int64_t D, uint32_t k0, uint32_t k1,
-                                             uint32_t inst)
+                                             uint32_t inst, AcceptOut acc = AcceptOut{})
 {
     const int64_t i = grp * 64 + lane;
     const bool valid = i < np;
-    uint32_t fl = 0;
+    uint32_t fl = 0, fl_old = 0;
+    bool accepted = false;
     T fv = static_cast<T>(-INFINITY);
     if (valid) {
         const T v = static_cast<T>(value);
         const bool skip = skip3 != nullptr && (i == skip3[0] || i == skip3[1] || i == skip3[2]);
         fl = flags[i];
+        fl_old = fl;
         fv = f_cur[i];
         if (!skip && v > fv) {
+            accepted = true;
             fv = v;
             f_cur[i] = v;
             fl ^= 1u;
@@ -44,6 +48,19 @@ __device__ __forceinline__ void select_group(double value, int64_t grp, int lane
     if (fbits != nullptr && lane == 0) {
         fbits[2 * grp] = static_cast<uint32_t>(m);
         fbits[2 * grp + 1] = static_cast<uint32_t>(m >> 32);
+    }
+    if (acc.list != nullptr) {
+        const uint64_t mo = __ballot(fl_old != 0u);
+        const uint64_t am = __ballot(accepted);
+        if (lane == 0) {
+            acc.fbits_prev[2 * grp] = static_cast<uint32_t>(mo);
+            acc.fbits_prev[2 * grp + 1] = static_cast<uint32_t>(mo >> 32);
+        }
+        uint32_t base = 0;
+        if (lane == 0 && am != 0) base = atomicAdd(acc.cnt, static_cast<uint32_t>(__popcll(am)));
+        base = static_cast<uint32_t>(__shfl(static_cast<int>(base), 0));
+        if (accepted)
+            acc.list[base + static_cast<uint32_t>(__popcll(am & ((uint64_t(1) << lane) - 1)))] = static_cast<int32_t>(i);
     }
     if (cand_v) {
         Top3<T> tp = top3_empty<T>();

@@ -20,6 +20,9 @@ FIT_TABLE = 3
 CONTROL_FIXED = 0     # F constant, a from 2 to 0
 CONTROL_DECAY = 1     # F = a from 0.1 to 0.01
 CONTROL_ADAPTIVE = 2  # adaptive F in [0.01, 0.1], a from 0.1 to 0.01
+TRIALS_AUTO = 0      # accepted-only trial genes when the population exceeds 256 MB
+TRIALS_STORE = 1     # every DE trial's genes written
+TRIALS_ACCEPTED = 2  # bits only, accepted trials recomputed after selection
 OBJ_SHG = 0  # multi-wavelength objective over |sum d a| / L
 OBJ_THG = 1  # multi-wavelength objective over |d_eff| / L^2
 # timing slots of one generation (QPM_K_*)
@@ -43,7 +46,7 @@ class QpmError(RuntimeError):
 class RunConfig(C.Structure):
     _fields_ = [("np", _I64), ("generations", _I64), ("F", _F), ("CR", _F), ("seed", _U64),
                 ("inst", _U32), ("prec", _I32), ("gwo_variant", _I32), ("use_graph", _I32),
-                ("fit_kernel", _I32), ("tune", _I32), ("control", _I32)]
+                ("fit_kernel", _I32), ("tune", _I32), ("control", _I32), ("trials", _I32)]
 
 
 class RunStats(C.Structure):
@@ -383,10 +386,10 @@ def relax(theta, design, prec=PREC_F32):
 
 
 def _config(np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0, use_graph=1,
-            fit_kernel=FIT_AUTO, tune=0, control=0):
+            fit_kernel=FIT_AUTO, tune=0, control=0, trials=0):
     return RunConfig(np=np_, generations=generations, F=F, CR=CR, seed=seed, inst=inst, prec=prec,
                      gwo_variant=gwo_variant, use_graph=use_graph, fit_kernel=fit_kernel, tune=tune,
-                     control=control)
+                     control=control, trials=trials)
 
 
 class Run:
@@ -394,10 +397,11 @@ class Run:
     `design` is a Design (fitness |d_eff|^2) or an Objective (fitness -h)."""
 
     def __init__(self, design, np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0,
-                 use_graph=1, fit_kernel=FIT_AUTO, tune=0, control=CONTROL_FIXED, stream=None):
+                 use_graph=1, fit_kernel=FIT_AUTO, tune=0, control=CONTROL_FIXED, trials=TRIALS_AUTO,
+                 stream=None):
         self.design = design
         self.cfg = _config(np_, generations, F, CR, seed, inst, prec, gwo_variant, use_graph, fit_kernel, tune,
-                           control)
+                           control, trials)
         self.D = design.n
         h = C.c_void_p()
         create = lib().qpm_run_create_objective if isinstance(design, Objective) else lib().qpm_run_create

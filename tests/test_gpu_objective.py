@@ -114,7 +114,8 @@ def test_objective_run_fp64_equals_oracle(q, orc, kind, control, graph):
     z = inputs.uniform_boundaries(n, 2.0)
     O, Oo = _pair(q, orc, z, K, kind, 0.7, 2.0)
     xo, fo, _, par = Oo.hwsda_run(npop, G, 0.5, 0.9, 6, control=control)
-    R = q.Run(O, npop, G, seed=6, prec=1, control=control, use_graph=graph)
+    R = q.Run(O, npop, G, seed=6, prec=1, control=control, use_graph=graph,
+              trials=q.TRIALS_ACCEPTED if kind == 1 else q.TRIALS_AUTO)
     R.advance(G)
     x, f, _, _ = R.read()
     assert np.array_equal(x.cpu().numpy(), xo)

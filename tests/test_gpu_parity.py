@@ -373,6 +373,33 @@ def test_run_rejects_unknown_control(q):
         q.Run(D, 8, 2, control=3)
 
 
+@pytest.mark.parametrize("case", [
+    # (N, NP, G, GWO variant, control, graph)
+    (300, 64, 20, 0, 0, 1),
+    (1007, 130, 12, 1, 1, 0),
+    (2049, 37, 10, 0, 2, 1),
+    (500, 48, 10, 2, 1, 1),
+    (1, 4, 6, 0, 0, 1),
+], ids=lambda c: "n%d_np%d_g%d_v%d_c%d_graph%d" % c)
+def test_run_accepted_trials_fp64_equals_oracle(q, orc, case):
+    # the DE step storing bits only, accepted trials recomputed after the
+    # selection: the oracle's trajectory, as with every trial stored
+    n, npop, G, variant, control, graph = case
+    z = inputs.jittered_boundaries(n, 2.0, 0.25, seed=n + 1)
+    D = q.precompute_phases(z, DK1, DK2)
+    xo, fo, _, _ = orc.Design(z, DK1, DK2).hwsda_run(npop, G, 0.5, 0.9, 21, variant=variant, control=control)
+    for trials in (q.TRIALS_ACCEPTED, q.TRIALS_STORE):
+        R = q.Run(D, npop, G, seed=21, prec=1, gwo_variant=variant, control=control, use_graph=graph,
+                  trials=trials)
+        R.advance(G)
+        x, f, _, _ = R.read()
+        assert np.array_equal(x.cpu().numpy(), xo), trials
+        assert np.max(np.abs(f.cpu().numpy() - fo) / np.maximum(fo, 1e-300)) <= 1e-12
+        R.destroy()
+    with pytest.raises(q.QpmError):
+        q.Run(D, npop, G, trials=3)
+
+
 def test_run_graph_and_eager_agree(q):
     n, npop, G = 300, 20, 15
     D = q.precompute_phases(inputs.uniform_boundaries(n, 2.0), DK1, DK2)
