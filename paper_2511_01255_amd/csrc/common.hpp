@@ -85,8 +85,10 @@ qpm_status launch_fitness(const Design &d, qpm_prec p, const uint32_t *bits, int
 // the segment triples only (6 x max(gy, 1) x ld doubles), for the fused
 // finish step of a run
 size_t fitness_partials_bytes(const FitPlan &plan, int64_t ld);
+// advance (optional): the run's generation counter, incremented once by the
+// kernel (which does not read it)
 qpm_status launch_fitness_partials(const Design &d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
-                                   const FitPlan &plan, double *part, hipStream_t s);
+                                   const FitPlan &plan, double *part, hipStream_t s, uint32_t *advance = nullptr);
 // Finish one evaluation of a run: combine the triples of genome i into f,
 // select (f > f_cur[i] replaces, leaders in skip3 excluded), then in a
 // one-workgroup kernel: top3_out <- leaders (when non-null); with
@@ -103,10 +105,19 @@ struct AcceptOut {
     uint32_t *cnt = nullptr;
     uint32_t *fbits_prev = nullptr;
 };
+// How a finish step ends (defaults: as described at launch_finish):
+// gen_advanced: the counter was already advanced by the evaluation kernel,
+// so the next draws are for gen[0] itself and no tail advances it;
+// defer_leaders: the candidates are left in `cand` for launch_materialize
+// to merge into top3_out (no tail kernel).
+struct FinishMode {
+    bool gen_advanced = false;
+    bool defer_leaders = false;
+};
 qpm_status launch_finish(const double *part, int gy, int64_t ld, int64_t np, const double *C, void *f_cur,
                          bool f64, uint32_t *flags, uint32_t *fbits, const int32_t *skip3, int32_t *top3_out,
                          void *cand, int4 *draws_next, uint32_t *gen, int64_t D, uint64_t seed, uint32_t inst,
-                         hipStream_t s, AcceptOut acc = AcceptOut{});
+                         hipStream_t s, AcceptOut acc = AcceptOut{}, FinishMode mode = FinishMode{});
 inline size_t finish_cand_bytes(int64_t np)
 {
     return static_cast<size_t>((np + 63) / 64) * 3 * (sizeof(double) + sizeof(int32_t));
@@ -150,7 +161,7 @@ ObjPlan plan_objective_shape(const Objective &o, int wpw);
 // segment partials of every design: K x gy x (6 or 2) x ld doubles
 size_t objective_partials_bytes(const Objective &o, const ObjPlan &pl, int64_t ld);
 qpm_status launch_objective_partials(const Objective &o, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
-                                     const ObjPlan &pl, double *part, hipStream_t s);
+                                     const ObjPlan &pl, double *part, hipStream_t s, uint32_t *advance = nullptr);
 // fitness (np floats or doubles) and optionally G ([K][ldG] doubles)
 qpm_status launch_objective_values(const Objective &o, const ObjPlan &pl, const double *part, int64_t ld, int64_t np,
                                    void *fitness, bool f64, double *G, int64_t ldG, hipStream_t s);
@@ -158,7 +169,8 @@ qpm_status launch_objective_values(const Objective &o, const ObjPlan &pl, const 
 qpm_status launch_objective_finish(const Objective &o, const ObjPlan &pl, const double *part, int64_t ld, int64_t np,
                                    void *f_cur, bool f64, uint32_t *flags, uint32_t *fbits, const int32_t *skip3,
                                    int32_t *top3_out, void *cand, int4 *draws_next, uint32_t *gen, int64_t D,
-                                   uint64_t seed, uint32_t inst, hipStream_t s, AcceptOut acc = AcceptOut{});
+                                   uint64_t seed, uint32_t inst, hipStream_t s, AcceptOut acc = AcceptOut{},
+                                   FinishMode mode = FinishMode{});
 
 // ---------------------------------------------------------------- evolution kernels
 
@@ -198,9 +210,12 @@ qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const 
 // zeroes reset_cnt); launch_materialize then writes the genes of the
 // accepted trials listed by the finish step (list, *cnt), reading the
 // population before the selection through its packed flags fb_old
+// (with top3_out: its first workgroup also merges the finish step's leader
+// candidates, cand from a finish with defer_leaders, of ngroups groups)
 qpm_status launch_materialize(const PopView &pv, const int4 *draws, const uint32_t *fb_old, float F,
                               const float *F_tab, float CR, uint64_t seed, const uint32_t *gen, uint32_t inst,
-                              const int32_t *list, const uint32_t *cnt, hipStream_t s);
+                              const int32_t *list, const uint32_t *cnt, hipStream_t s, const void *cand = nullptr,
+                              int64_t ngroups = 0, bool f64 = false, int32_t *top3_out = nullptr);
 // segmented plan with an explicit shape
 FitPlan plan_fitness_shape(const Design &d, int waves, int wpw);
 // table plan: gw genome groups of 64 per workgroup, wpw words per wave

@@ -199,15 +199,29 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
 // items chunk by chunk, so the waves running together on an XCD read the
 // same chunk of many rows and donor rows shared between accepted trials
 // come from its L2. The grid is fixed; every wave loops until its XCD's
-// items run out.
+// items run out. With top3_out, workgroup 0 first merges the finish step's
+// leader candidates (3 per group of 64) into the leaders, which saves the
+// finish step a one-workgroup kernel (the grey-wolf step after this kernel
+// reads them).
 __global__ __launch_bounds__(256) void materialize_kernel(PopView pv, const int4 *__restrict__ draws,
                                                           const uint32_t *__restrict__ fb_old, float F,
                                                           const float *__restrict__ F_tab, uint32_t cr_max,
                                                           uint32_t k0, uint32_t k1, const uint32_t *__restrict__ gen,
                                                           uint32_t inst, const int32_t *__restrict__ list,
-                                                          const uint32_t *__restrict__ cnt)
+                                                          const uint32_t *__restrict__ cnt, const void *cand,
+                                                          int64_t ngroups, int cand_f64, int32_t *top3_out)
 {
     extern __shared__ uint32_t sfb[];  // (np + 31) / 32 old flag words
+    if (top3_out != nullptr && blockIdx.x == 0) {
+        // cand: 3 values per group (T) followed by 3 slots per group
+        if (cand_f64) {
+            const double *cv = static_cast<const double *>(cand);
+            block_top3<double, 256>(cv, 3 * ngroups, top3_out, reinterpret_cast<const int32_t *>(cv + 3 * ngroups));
+        } else {
+            const float *cv = static_cast<const float *>(cand);
+            block_top3<float, 256>(cv, 3 * ngroups, top3_out, reinterpret_cast<const int32_t *>(cv + 3 * ngroups));
+        }
+    }
     const int64_t np = pv.np, D = pv.D;
     for (int k = threadIdx.x; k < static_cast<int>((np + 31) / 32); k += 256) sfb[k] = fb_old[k];
     __syncthreads();
@@ -243,15 +257,17 @@ __global__ __launch_bounds__(256) void materialize_kernel(PopView pv, const int4
 
 qpm_status launch_materialize(const PopView &pv, const int4 *draws, const uint32_t *fb_old, float F,
                               const float *F_tab, float CR, uint64_t seed, const uint32_t *gen, uint32_t inst,
-                              const int32_t *list, const uint32_t *cnt, hipStream_t s)
+                              const int32_t *list, const uint32_t *cnt, hipStream_t s, const void *cand,
+                              int64_t ngroups, bool f64, int32_t *top3_out)
 {
+    QPM_REQUIRE(top3_out == nullptr || cand != nullptr, QPM_EINVAL, "merging leaders needs the candidates");
     QPM_REQUIRE(pv.np <= 65536 && pv.ldx < (int64_t(1) << 24) && pv.x1 == pv.x0 + pv.np * pv.ldx &&
                     pv.out0 == pv.x0 && pv.out1 == pv.x1,
                 QPM_EINVAL, "materialising trials needs one allocation for both gene buffers");
     const size_t lds = sizeof(uint32_t) * static_cast<size_t>((pv.np + 31) / 32);
     materialize_kernel<<<2048, 256, lds, s>>>(pv, draws, fb_old, F, F_tab, cr_threshold(CR),
                                               static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32), gen,
-                                              inst, list, cnt);
+                                              inst, list, cnt, cand, ngroups, f64 ? 1 : 0, top3_out);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }

@@ -25,8 +25,9 @@ __global__ __launch_bounds__(WAVES * 64) void fit_seg_kernel(const uint32_t *__r
                                                              const float4 *__restrict__ ph32, int wpw, int64_t np,
                                                              double *__restrict__ part,
                                                              const double *__restrict__ C, void *__restrict__ fit,
-                                                             int direct, int out_f64)
+                                                             int direct, int out_f64, uint32_t *__restrict__ advance)
 {
+    if (advance != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) advance[0] += 1u;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + lane;
@@ -92,8 +93,9 @@ __global__ __launch_bounds__(256) void fit_combine_kernel(const double *__restri
 __global__ __launch_bounds__(128) void fit_per_genome_kernel(const uint32_t *__restrict__ bits, int64_t ld, int W,
                                                              const double4 *__restrict__ ph64, int64_t np,
                                                              const double *__restrict__ C, double *__restrict__ fit,
-                                                             double *__restrict__ part)
+                                                             double *__restrict__ part, uint32_t *__restrict__ advance)
 {
+    if (advance != nullptr && blockIdx.x == 0 && threadIdx.x == 0) advance[0] += 1u;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * 128 + threadIdx.x;
     if (i >= np) return;
     double ar = 0, ai = 0, qr = 0, qi = 0;
@@ -143,9 +145,13 @@ __global__ __launch_bounds__(GW * 256) void fit_tab_kernel(const uint32_t *__res
                                                            const double2 *__restrict__ tab64,
                                                            const float2 *__restrict__ tab32, int wpw, int64_t np,
                                                            double *__restrict__ part, const double *__restrict__ C,
-                                                           void *__restrict__ fit, int direct, int out_f64)
+                                                           void *__restrict__ fit, int direct, int out_f64,
+                                                           uint32_t *__restrict__ advance)
 {
     extern __shared__ __align__(16) unsigned char lds[];
+    // a run's generation advance, taken here because this kernel does not
+    // read the counter (the finish step after it reads the new value)
+    if (advance != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) advance[0] += 1u;
     const int wbase = static_cast<int>(blockIdx.y) * 4 * wpw;
     const int64_t i = (static_cast<int64_t>(blockIdx.x) * GW + (threadIdx.x >> 8)) * 64 + (threadIdx.x & 63);
     Tri t;
@@ -173,7 +179,8 @@ size_t table_lds_bytes(int64_t W, bool f32, int gw, int wpw)
 
 template <bool F32>
 static void launch_tab(const Design &d, const FitPlan &pl, const uint32_t *bits, int64_t np, int64_t ld,
-                       double *part, void *fit, int out_f64, bool direct_ok, hipStream_t s)
+                       double *part, void *fit, int out_f64, bool direct_ok, hipStream_t s,
+                       uint32_t *advance = nullptr)
 {
     const int gw = pl.waves;
     const dim3 grid(static_cast<unsigned>((np + 64 * gw - 1) / (64 * gw)), static_cast<unsigned>(pl.gy));
@@ -183,7 +190,7 @@ static void launch_tab(const Design &d, const FitPlan &pl, const uint32_t *bits,
 #define QPM_TAB_CASE(G)                                                                                       \
     case G:                                                                                                   \
         fit_tab_kernel<F32, G><<<grid, dim3(G * 256), lds, s>>>(bits, ld, W, d.tab64, d.tab32, pl.wpw, np, part, \
-                                                                d.Cdev, fit, direct, out_f64);               \
+                                                                d.Cdev, fit, direct, out_f64, advance);      \
         break;
     switch (gw) {
         QPM_TAB_CASE(1)
@@ -196,7 +203,8 @@ static void launch_tab(const Design &d, const FitPlan &pl, const uint32_t *bits,
 
 template <bool F32>
 static void launch_seg(const Design &d, const FitPlan &pl, const uint32_t *bits, int64_t np, int64_t ld,
-                       double *part, void *fit, int out_f64, bool direct_ok, hipStream_t s)
+                       double *part, void *fit, int out_f64, bool direct_ok, hipStream_t s,
+                       uint32_t *advance = nullptr)
 {
     const dim3 grid(static_cast<unsigned>((np + 63) / 64), static_cast<unsigned>(pl.gy));
     const int direct = direct_ok && pl.gy == 1;
@@ -204,7 +212,7 @@ static void launch_seg(const Design &d, const FitPlan &pl, const uint32_t *bits,
 #define QPM_SEG_CASE(NW)                                                                                       \
     case NW:                                                                                                   \
         fit_seg_kernel<F32, NW><<<grid, dim3(NW * 64), 0, s>>>(bits, ld, W, d.ph64, d.ph32, pl.wpw, np, part, \
-                                                              d.Cdev, fit, direct, out_f64);                  \
+                                                              d.Cdev, fit, direct, out_f64, advance);         \
         break;
     switch (pl.waves) {
         QPM_SEG_CASE(1)
@@ -290,7 +298,7 @@ qpm_status launch_fitness(const Design &d, qpm_prec p, const uint32_t *bits, int
     if (pl.kind == QPM_FIT_PER_GENOME) {
         const unsigned blocks = static_cast<unsigned>((np + 127) / 128);
         fit_per_genome_kernel<<<blocks, 128, 0, s>>>(bits, ld, static_cast<int>(d.words), d.ph64, np, d.Cdev,
-                                                     static_cast<double *>(fit), nullptr);
+                                                     static_cast<double *>(fit), nullptr, nullptr);
     } else {
         if (pl.kind == QPM_FIT_TABLE) {
             if (p == QPM_PREC_F32)
@@ -312,21 +320,21 @@ qpm_status launch_fitness(const Design &d, qpm_prec p, const uint32_t *bits, int
 }
 
 qpm_status launch_fitness_partials(const Design &d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
-                                   const FitPlan &pl, double *part, hipStream_t s)
+                                   const FitPlan &pl, double *part, hipStream_t s, uint32_t *advance)
 {
     if (pl.kind == QPM_FIT_PER_GENOME) {
         const unsigned blocks = static_cast<unsigned>((np + 127) / 128);
         fit_per_genome_kernel<<<blocks, 128, 0, s>>>(bits, ld, static_cast<int>(d.words), d.ph64, np, d.Cdev,
-                                                     nullptr, part);
+                                                     nullptr, part, advance);
     } else if (pl.kind == QPM_FIT_TABLE) {
         if (p == QPM_PREC_F32)
-            launch_tab<true>(d, pl, bits, np, ld, part, nullptr, 0, false, s);
+            launch_tab<true>(d, pl, bits, np, ld, part, nullptr, 0, false, s, advance);
         else
-            launch_tab<false>(d, pl, bits, np, ld, part, nullptr, 1, false, s);
+            launch_tab<false>(d, pl, bits, np, ld, part, nullptr, 1, false, s, advance);
     } else if (p == QPM_PREC_F32) {
-        launch_seg<true>(d, pl, bits, np, ld, part, nullptr, 0, false, s);
+        launch_seg<true>(d, pl, bits, np, ld, part, nullptr, 0, false, s, advance);
     } else {
-        launch_seg<false>(d, pl, bits, np, ld, part, nullptr, 1, false, s);
+        launch_seg<false>(d, pl, bits, np, ld, part, nullptr, 1, false, s, advance);
     }
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;

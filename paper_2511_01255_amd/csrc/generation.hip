@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ 
                                                      const int32_t *__restrict__ skip3, T *__restrict__ cand_v,
                                                      int32_t *__restrict__ cand_i, int4 *__restrict__ draws_next,
                                                      const uint32_t *__restrict__ gen, int64_t D, uint32_t k0,
-                                                     uint32_t k1, uint32_t inst, AcceptOut acc)
+                                                     uint32_t k1, uint32_t inst, AcceptOut acc, uint32_t next_off)
 {
     const int lane = threadIdx.x & 63;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + lane;
@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ 
     if (threadIdx.x < 64) {
         const double sr = t.qr + C[0], si = t.qi + C[1];
         select_group<T>(fma(sr, sr, si * si), blockIdx.x, lane, np, f_cur, flags, fbits, skip3, cand_v, cand_i,
-                        draws_next, gen, D, k0, k1, inst, acc);
+                        draws_next, gen, D, k0, k1, inst, acc, next_off);
     }
 }
 
@@ -125,27 +125,30 @@ qpm_status launch_adapt_F(const void *f, bool f64, int64_t np, const uint32_t *g
 qpm_status launch_finish(const double *part, int gy, int64_t ld, int64_t np, const double *C, void *f_cur, bool f64,
                          uint32_t *flags, uint32_t *fbits, const int32_t *skip3, int32_t *top3_out, void *cand,
                          int4 *draws_next, uint32_t *gen, int64_t D, uint64_t seed, uint32_t inst, hipStream_t s,
-                         AcceptOut acc)
+                         AcceptOut acc, FinishMode mode)
 {
     QPM_REQUIRE((acc.list == nullptr) == (acc.cnt == nullptr) && (acc.list == nullptr) == (acc.fbits_prev == nullptr),
                 QPM_EINVAL, "the accepted list, its counter and the previous flags go together");
     const unsigned blocks = static_cast<unsigned>((np + 63) / 64);
     QPM_REQUIRE(top3_out == nullptr || cand != nullptr, QPM_EINVAL, "leader candidates need a buffer");
     const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
-    const int advance = draws_next != nullptr;
+    const int advance = draws_next != nullptr && !mode.gen_advanced;
+    const uint32_t next_off = mode.gen_advanced ? 0u : 1u;
+    const bool tail = (top3_out != nullptr && !mode.defer_leaders) || advance;
+    int32_t *tail_top3 = mode.defer_leaders ? nullptr : top3_out;
     // cand: 3 values per workgroup (T) followed by 3 slots per workgroup (int32)
     if (f64) {
         double *cv = top3_out ? static_cast<double *>(cand) : nullptr;
         int32_t *ci = cv ? reinterpret_cast<int32_t *>(cv + 3 * static_cast<size_t>(blocks)) : nullptr;
         finish_kernel<double><<<blocks, 256, 0, s>>>(part, gy, ld, np, C, static_cast<double *>(f_cur), flags, fbits,
-                                                     skip3, cv, ci, draws_next, gen, D, k0, k1, inst, acc);
-        if (top3_out || advance) finish_tail_kernel<double><<<1, 256, 0, s>>>(cv, ci, blocks, top3_out, gen, advance);
+                                                     skip3, cv, ci, draws_next, gen, D, k0, k1, inst, acc, next_off);
+        if (tail) finish_tail_kernel<double><<<1, 256, 0, s>>>(cv, ci, blocks, tail_top3, gen, advance);
     } else {
         float *cv = top3_out ? static_cast<float *>(cand) : nullptr;
         int32_t *ci = cv ? reinterpret_cast<int32_t *>(cv + 3 * static_cast<size_t>(blocks)) : nullptr;
         finish_kernel<float><<<blocks, 256, 0, s>>>(part, gy, ld, np, C, static_cast<float *>(f_cur), flags, fbits,
-                                                    skip3, cv, ci, draws_next, gen, D, k0, k1, inst, acc);
-        if (top3_out || advance) finish_tail_kernel<float><<<1, 256, 0, s>>>(cv, ci, blocks, top3_out, gen, advance);
+                                                    skip3, cv, ci, draws_next, gen, D, k0, k1, inst, acc, next_off);
+        if (tail) finish_tail_kernel<float><<<1, 256, 0, s>>>(cv, ci, blocks, tail_top3, gen, advance);
     }
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;

@@ -48,8 +48,9 @@ size_t obj_lds_bytes(int wpw)
 template <bool F32, bool THG>
 __global__ __launch_bounds__(256) void obj_partials_kernel(ObjTabs tabs, int K, const uint32_t *__restrict__ bits,
                                                            int64_t ld, int W, int wpw, int gy, int64_t np,
-                                                           double *__restrict__ part)
+                                                           double *__restrict__ part, uint32_t *__restrict__ advance)
 {
+    if (advance != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) advance[0] += 1u;
     constexpr int R = ObjShape<THG>::R;
     constexpr int NC = ObjShape<THG>::NC;
     constexpr int ES = F32 ? 8 : 16;        // bytes per table entry (complex)
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(256) void obj_finish_kernel(ObjTabs tabs, int K, do
                                                          const int32_t *__restrict__ skip3, T *__restrict__ cand_v,
                                                          int32_t *__restrict__ cand_i, int4 *__restrict__ draws_next,
                                                          const uint32_t *__restrict__ gen, int64_t D, uint32_t k0,
-                                                         uint32_t k1, uint32_t inst, AcceptOut acc)
+                                                         uint32_t k1, uint32_t inst, AcceptOut acc, uint32_t next_off)
 {
     __shared__ double sh[6 * 4 * 64];
     const int lane = threadIdx.x & 63;
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(256) void obj_finish_kernel(ObjTabs tabs, int K, do
     const double v = obj_value<THG>(tabs, K, scale, G0, beta, part, gy, ld, i, i < np, nullptr, 0, sh);
     if (threadIdx.x < 64)
         select_group<T>(v, blockIdx.x, lane, np, f_cur, flags, fbits, skip3, cand_v, cand_i, draws_next, gen, D, k0,
-                        k1, inst, acc);
+                        k1, inst, acc, next_off);
 }
 
 ObjPlan plan_objective_shape(const Objective &o, int wpw)
@@ -283,7 +284,7 @@ size_t objective_partials_bytes(const Objective &o, const ObjPlan &pl, int64_t l
 }
 
 qpm_status launch_objective_partials(const Objective &o, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
-                                     const ObjPlan &pl, double *part, hipStream_t s)
+                                     const ObjPlan &pl, double *part, hipStream_t s, uint32_t *advance)
 {
     QPM_REQUIRE(pl.gy <= 65535, QPM_ERANGE, "too many workgroup segments (%d)", pl.gy);
     const dim3 grid(static_cast<unsigned>((np + 63) / 64), static_cast<unsigned>(pl.gy));
@@ -291,16 +292,17 @@ qpm_status launch_objective_partials(const Objective &o, qpm_prec p, const uint3
     const bool f32 = p == QPM_PREC_F32, thg = o.kind == QPM_OBJ_THG;
     if (f32 && thg)
         obj_partials_kernel<true, true><<<grid, 256, obj_lds_bytes<true, true>(pl.wpw), s>>>(o.tabs, o.K, bits, ld, W,
-                                                                                          pl.wpw, pl.gy, np, part);
+                                                                                          pl.wpw, pl.gy, np, part,
+                                                                                          advance);
     else if (f32)
         obj_partials_kernel<true, false><<<grid, 256, obj_lds_bytes<true, false>(pl.wpw), s>>>(
-            o.tabs, o.K, bits, ld, W, pl.wpw, pl.gy, np, part);
+            o.tabs, o.K, bits, ld, W, pl.wpw, pl.gy, np, part, advance);
     else if (thg)
         obj_partials_kernel<false, true><<<grid, 256, obj_lds_bytes<false, true>(pl.wpw), s>>>(
-            o.tabs, o.K, bits, ld, W, pl.wpw, pl.gy, np, part);
+            o.tabs, o.K, bits, ld, W, pl.wpw, pl.gy, np, part, advance);
     else
         obj_partials_kernel<false, false><<<grid, 256, obj_lds_bytes<false, false>(pl.wpw), s>>>(
-            o.tabs, o.K, bits, ld, W, pl.wpw, pl.gy, np, part);
+            o.tabs, o.K, bits, ld, W, pl.wpw, pl.gy, np, part, advance);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }
@@ -326,12 +328,15 @@ qpm_status launch_objective_values(const Objective &o, const ObjPlan &pl, const 
 qpm_status launch_objective_finish(const Objective &o, const ObjPlan &pl, const double *part, int64_t ld, int64_t np,
                                    void *f_cur, bool f64, uint32_t *flags, uint32_t *fbits, const int32_t *skip3,
                                    int32_t *top3_out, void *cand, int4 *draws_next, uint32_t *gen, int64_t D,
-                                   uint64_t seed, uint32_t inst, hipStream_t s, AcceptOut acc)
+                                   uint64_t seed, uint32_t inst, hipStream_t s, AcceptOut acc, FinishMode mode)
 {
     const unsigned blocks = static_cast<unsigned>((np + 63) / 64);
     QPM_REQUIRE(top3_out == nullptr || cand != nullptr, QPM_EINVAL, "leader candidates need a buffer");
     const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
-    const int advance = draws_next != nullptr;
+    const int advance = draws_next != nullptr && !mode.gen_advanced;
+    const uint32_t next_off = mode.gen_advanced ? 0u : 1u;
+    const bool tail = (top3_out != nullptr && !mode.defer_leaders) || advance;
+    int32_t *tail_top3 = mode.defer_leaders ? nullptr : top3_out;
     const bool thg = o.kind == QPM_OBJ_THG;
     // cand: 3 values per workgroup (T) followed by 3 slots per workgroup
 #define QPM_OF(T, H)                                                                                              \
@@ -340,8 +345,8 @@ qpm_status launch_objective_finish(const Objective &o, const ObjPlan &pl, const 
         int32_t *ci = cv ? reinterpret_cast<int32_t *>(cv + 3 * static_cast<size_t>(blocks)) : nullptr;          \
         obj_finish_kernel<T, H><<<blocks, 256, 0, s>>>(o.tabs, o.K, o.scale, o.G0, o.beta, part, pl.gy, ld, np,  \
                                                        static_cast<T *>(f_cur), flags, fbits, skip3, cv, ci,     \
-                                                       draws_next, gen, D, k0, k1, inst, acc);                    \
-        if (top3_out || advance) finish_tail_kernel<T><<<1, 256, 0, s>>>(cv, ci, blocks, top3_out, gen, advance); \
+                                                       draws_next, gen, D, k0, k1, inst, acc, next_off);          \
+        if (tail) finish_tail_kernel<T><<<1, 256, 0, s>>>(cv, ci, blocks, tail_top3, gen, advance);               \
     }
     if (f64) {
         if (thg) QPM_OF(double, true) else QPM_OF(double, false)

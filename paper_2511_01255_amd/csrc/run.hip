@@ -120,27 +120,29 @@ static void release(qpm_run_s *r)
     delete r;
 }
 
-// segment partials of the run's fitness for the genomes in tbits
-static qpm_status eval_partials(qpm_run_s *r)
+// segment partials of the run's fitness for the genomes in tbits; with
+// `advance` the kernel also advances the generation counter
+static qpm_status eval_partials(qpm_run_s *r, uint32_t *advance = nullptr)
 {
     const qpm_run_config &c = r->cfg;
     const qpm_prec p = static_cast<qpm_prec>(c.prec);
-    if (r->obj) return launch_objective_partials(*r->obj, p, r->tbits, c.np, r->ld, r->oplan, r->fws, r->st);
-    return launch_fitness_partials(*r->d, p, r->tbits, c.np, r->ld, r->plan, r->fws, r->st);
+    if (r->obj)
+        return launch_objective_partials(*r->obj, p, r->tbits, c.np, r->ld, r->oplan, r->fws, r->st, advance);
+    return launch_fitness_partials(*r->d, p, r->tbits, c.np, r->ld, r->plan, r->fws, r->st, advance);
 }
 
 // combine + selection (+ leaders or the next generation's draws and advance)
 static qpm_status eval_finish(qpm_run_s *r, const int32_t *skip3, int32_t *top3_out, void *cand, int4 *draws_next,
-                              AcceptOut acc = AcceptOut{})
+                              AcceptOut acc = AcceptOut{}, FinishMode mode = FinishMode{})
 {
     const qpm_run_config &c = r->cfg;
     if (r->obj)
         return launch_objective_finish(*r->obj, r->oplan, r->fws, r->ld, c.np, r->f_cur, r->f64(), r->flags,
                                        r->fbits, skip3, top3_out, cand, draws_next, r->gen, r->D, c.seed, c.inst,
-                                       r->st, acc);
+                                       r->st, acc, mode);
     const int gy = r->plan.kind == QPM_FIT_PER_GENOME ? 1 : r->plan.gy;
     return launch_finish(r->fws, gy, r->ld, c.np, r->d->Cdev, r->f_cur, r->f64(), r->flags, r->fbits, skip3,
-                         top3_out, cand, draws_next, r->gen, r->D, c.seed, c.inst, r->st, acc);
+                         top3_out, cand, draws_next, r->gen, r->D, c.seed, c.inst, r->st, acc, mode);
 }
 
 // the fitness of the genomes in tbits into f_cur (no selection)
@@ -174,11 +176,14 @@ static qpm_status enqueue_generation(qpm_run_s *r, hipEvent_t *ev = nullptr)
                                  r->de_ipw, r->de_passes, r->fbits, r->F_tab, !r->lazy,
                                  r->lazy ? r->acc_cnt : nullptr))
     QPM_STEP(QPM_K_FIT_DE, eval_partials(r))
+    // with accepted-only trials the materialise kernel also merges the
+    // leader candidates (no separate one-workgroup kernel)
     QPM_STEP(QPM_K_FINISH_DE, eval_finish(r, nullptr, r->leaders, r->cand, nullptr,
-                                          r->lazy ? AcceptOut{r->acc_list, r->acc_cnt, r->fbits_prev} : AcceptOut{}))
+                                          r->lazy ? AcceptOut{r->acc_list, r->acc_cnt, r->fbits_prev} : AcceptOut{},
+                                          FinishMode{false, r->lazy}))
     if (r->lazy) {  // the accepted trials' genes (timed with the finish)
         st = launch_materialize(pv, r->draws, r->fbits_prev, c.F, r->F_tab, c.CR, c.seed, r->gen, c.inst,
-                                r->acc_list, r->acc_cnt, r->st);
+                                r->acc_list, r->acc_cnt, r->st, r->cand, (c.np + 63) / 64, r->f64(), r->leaders);
         if (st != QPM_OK) return st;
     }
     if (c.gwo_variant == 2) {
@@ -190,8 +195,11 @@ static qpm_status enqueue_generation(qpm_run_s *r, hipEvent_t *ev = nullptr)
         QPM_STEP(QPM_K_GWO, launch_gwo(pv, r->leaders, r->a_tab, 0.0f, c.seed, r->gen, 0u, c.inst, c.gwo_variant,
                                        r->tbits, r->ld, r->st))
     }
-    QPM_STEP(QPM_K_FIT_GWO, eval_partials(r))
-    QPM_STEP(QPM_K_FINISH_GWO, eval_finish(r, r->leaders, nullptr, nullptr, r->draws))
+    // the evaluation kernel advances the generation counter (it does not
+    // read it), so the finish step needs no one-workgroup kernel after it
+    QPM_STEP(QPM_K_FIT_GWO, eval_partials(r, r->gen))
+    QPM_STEP(QPM_K_FINISH_GWO, eval_finish(r, r->leaders, nullptr, nullptr, r->draws, AcceptOut{},
+                                           FinishMode{true, false}))
     if (r->adaptive()) {  // F of the next generation (timed with the finish)
         st = launch_adapt_F(r->f_cur, r->f64(), c.np, r->gen, c.generations, r->F_base, r->F_tab, r->st);
         if (st != QPM_OK) return st;

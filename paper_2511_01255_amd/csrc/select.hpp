@@ -13,7 +13,8 @@ namespace qpm {
 // Selection for the 64 genomes of group grp (i = 64 grp + lane), from their
 // fitness `value` (rounded to T here); called by one whole wave. Writes
 // f_cur, flags, the group's two packed flag words, the DE draws of
-// generation gen + 1 (with draws_next), the group's three best (with
+// generation gen + next_off (with draws_next; next_off = 0 when the
+// counter was already advanced), the group's three best (with
 // cand_v) and, with acc.list, the accepted slots (appended in any order)
 // and the packed flags from before the selection.
 template <typename T>
@@ -22,7 +23,7 @@ __device__ __forceinline__ void select_group(double value, int64_t grp, int lane
                                              const int32_t *__restrict__ skip3, T *__restrict__ cand_v,
                                              int32_t *__restrict__ cand_i, int4 *__restrict__ draws_next,
                                              const uint32_t *__restrict__ gen, int64_t D, uint32_t k0, uint32_t k1,
-                                             uint32_t inst, AcceptOut acc = AcceptOut{})
+                                             uint32_t inst, AcceptOut acc = AcceptOut{}, uint32_t next_off = 1u)
 {
     const int64_t i = grp * 64 + lane;
     const bool valid = i < np;
@@ -42,7 +43,7 @@ __device__ __forceinline__ void select_group(double value, int64_t grp, int lane
             fl ^= 1u;
             flags[i] = fl;
         }
-        if (draws_next) draws_next[i] = de_draw(i, np, D, gen[0] + 1u, inst, k0, k1);
+        if (draws_next) draws_next[i] = de_draw(i, np, D, gen[0] + next_off, inst, k0, k1);
     }
     const uint64_t m = __ballot(fl != 0u);
     if (fbits != nullptr && lane == 0) {
