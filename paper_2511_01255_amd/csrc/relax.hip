@@ -124,6 +124,72 @@ __device__ __forceinline__ void load_theta(float (&th)[M], const float *__restri
     }
 }
 
+// Lane value of lane l - OFF in the lane's row of 16 lanes (row_shr, CTRL
+// 0x110 + OFF), or of the last lane of the previous row (row_bcast:15, CTRL
+// 0x142, rows 1 and 3) or of lane 31 (row_bcast:31, CTRL 0x143, rows 2 and
+// 3); undefined where there is none (no lane reads those). DPP moves: no
+// LDS traffic, unlike a shuffle.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_from(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, ROWS, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, ROWS, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// one level of the ordered tree: the lanes that `take` prepend the triple
+// of the lanes before them (u <- o (+) u)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void tree_level(RTri &u, bool take)
+{
+    RTri o{dpp_from<CTRL, ROWS>(u.ar), dpp_from<CTRL, ROWS>(u.ai), dpp_from<CTRL, ROWS>(u.br),
+           dpp_from<CTRL, ROWS>(u.bi), dpp_from<CTRL, ROWS>(u.qr), dpp_from<CTRL, ROWS>(u.qi),
+           dpp_from<CTRL, ROWS>(u.gr), dpp_from<CTRL, ROWS>(u.gi)};
+    if (take) {
+        rtri_append(o, u);
+        u = o;
+    }
+}
+
+// The 64 chunk triples of a wave combined in order into lane 63: pairs of
+// neighbours, then groups of 4, 8, 16, 32 and 64 lanes, each the left group
+// followed by the right one.
+__device__ __forceinline__ void wave_fold_rtri(RTri &u, int lane)
+{
+    tree_level<0x111, 0xF>(u, (lane & 1) == 1);
+    tree_level<0x112, 0xF>(u, (lane & 3) == 3);
+    tree_level<0x114, 0xF>(u, (lane & 7) == 7);
+    tree_level<0x118, 0xF>(u, (lane & 15) == 15);
+    tree_level<0x142, 0xA>(u, (lane & 31) == 31);
+    tree_level<0x143, 0xC>(u, lane == 63);
+}
+
+// Inclusive prefix sums of four values over the 64 lanes of a wave with DPP
+// moves: within rows of 16 lanes (shifts 1, 2, 4, 8), then the last lane of
+// row 0 / 2 into rows 1 / 3, then lane 31 into rows 2 and 3.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void scan_step(double &a, double &b, double &c, double &d, bool take)
+{
+    const double oa = dpp_from<CTRL, ROWS>(a), ob = dpp_from<CTRL, ROWS>(b);
+    const double oc = dpp_from<CTRL, ROWS>(c), od = dpp_from<CTRL, ROWS>(d);
+    if (take) {
+        a += oa;
+        b += ob;
+        c += oc;
+        d += od;
+    }
+}
+
+__device__ __forceinline__ void wave_scan4(double &a, double &b, double &c, double &d, int lane)
+{
+    scan_step<0x111, 0xF>(a, b, c, d, (lane & 15) >= 1);
+    scan_step<0x112, 0xF>(a, b, c, d, (lane & 15) >= 2);
+    scan_step<0x114, 0xF>(a, b, c, d, (lane & 15) >= 4);
+    scan_step<0x118, 0xF>(a, b, c, d, (lane & 15) >= 8);
+    scan_step<0x142, 0xA>(a, b, c, d, (lane & 16) != 0);
+    scan_step<0x143, 0xC>(a, b, c, d, lane >= 32);
+}
+
 // Segment partials: part[(seg * 8 + c) * ldb + row], c = A.re, A.im,
 // B.re, B.im, Q.re, Q.im, Dg.re, Dg.im (doubles).
 template <typename T, int M, int R, bool VEC>
@@ -161,13 +227,8 @@ __global__ __launch_bounds__(256) void relax_fwd_kernel(const float *__restrict_
             gi = fma(d2, c.ci[e], gi);
         }
         RTri u{ar, ai, br, bi, qr, qi, gr, gi};
-        // ordered tree over the wave: lane l (l % 2 off == 0) appends lane l + off
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const RTri o = rtri_shfl_down(u, off);
-            if ((lane & (2 * off - 1)) == 0) rtri_append(u, o);
-        }
-        if (lane == 0) sh[wave] = u;
+        wave_fold_rtri(u, lane);
+        if (lane == 63) sh[wave] = u;
         __syncthreads();
         if (t == 0) {
             RTri s0 = sh[0];
@@ -291,34 +352,22 @@ __global__ __launch_bounds__(256) void relax_bwd_kernel(const float *__restrict_
             blr = fma(d[e], c.br[e], blr);
             bli = fma(d[e], c.bi[e], bli);
         }
-        // inclusive scans over the wave: A forward, B backward
-        double par = alr, pai = ali, sbr = blr, sbi = bli;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const double ur = __shfl_up(par, off), ui = __shfl_up(pai, off);
-            const double vr = __shfl_down(sbr, off), vi = __shfl_down(sbi, off);
-            if (lane >= off) {
-                par += ur;
-                pai += ui;
-            }
-            if (lane + off < 64) {
-                sbr += vr;
-                sbi += vi;
-            }
-        }
+        // inclusive prefix scans of A and B over the wave (DPP moves); B
+        // after a lane's chunk is the wave's total less that prefix
+        double par = alr, pai = ali, pbr = blr, pbi = bli;
+        wave_scan4(par, pai, pbr, pbi, lane);
+        const double tbr = __shfl(pbr, 63), tbi = __shfl(pbi, 63);
         if (lane == 63) {
             swa[wave][0] = par;
             swa[wave][1] = pai;
-        }
-        if (lane == 0) {
-            swb[wave][0] = sbr;
-            swb[wave][1] = sbi;
+            swb[wave][0] = tbr;
+            swb[wave][1] = tbi;
         }
         __syncthreads();
         const double *e = edges + static_cast<int64_t>(seg) * 4 * lde + row;
         // A before this lane's chunk, B after it
         double Pr = e[0] + (par - alr), Pi = e[lde] + (pai - ali);
-        double Rr = e[2 * lde] + (sbr - blr), Ri = e[3 * lde] + (sbi - bli);
+        double Rr = e[2 * lde] + (tbr - pbr), Ri = e[3 * lde] + (tbi - pbi);
         for (int w = 0; w < wave; ++w) {
             Pr += swa[w][0];
             Pi += swa[w][1];
