@@ -351,6 +351,7 @@ typedef struct {
  *                        (np <= 65536, else QPM_EINVAL).
  */
 typedef enum { QPM_TRIALS_AUTO = 0, QPM_TRIALS_STORE = 1, QPM_TRIALS_ACCEPTED = 2 } qpm_trials;
+/* (Runs of batched designs take STORE for AUTO and accept ACCEPTED too.) */
 
 /*
  * Parameter control (paper Sec. 3.1.1 and the parameter settings of

@@ -552,9 +552,10 @@ class BatchRun:
     """One HWSDA run per instance of a Batch, advanced together."""
 
     def __init__(self, batch, np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0,
-                 use_graph=1, tune=1, stream=None):
+                 use_graph=1, tune=1, trials=TRIALS_AUTO, stream=None):
         self.batch = batch
-        self.cfg = _config(np_, generations, F, CR, seed, inst, prec, gwo_variant, use_graph, FIT_AUTO)
+        self.cfg = _config(np_, generations, F, CR, seed, inst, prec, gwo_variant, use_graph, FIT_AUTO,
+                           trials=trials)
         h = C.c_void_p()
         _check(lib().qpm_batch_run_create(batch.handle, C.byref(self.cfg), 1 if tune else 0, _stream(stream),
                                           C.byref(h)))

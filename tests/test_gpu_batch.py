@@ -75,13 +75,15 @@ def test_batch_table_fitness_every_shape(q, orc, prec, groups):
             assert err <= (1e-12 if prec == 1 else 1e-5), (wpw, k, err)
 
 
-def test_batch_run_fp64_equals_oracle_runs(q, orc):
+@pytest.mark.parametrize("trials", [1, 2])
+def test_batch_run_fp64_equals_oracle_runs(q, orc, trials):
     # every instance follows the single-design run with instance number
-    # inst0 + b: same trajectory as the oracle's run, bit for bit
+    # inst0 + b: same trajectory as the oracle's run, bit for bit, with every
+    # trial stored (1) or the accepted ones recomputed after selection (2)
     specs = _small_batch()[1:]  # N >= 33
     npop, G, inst0 = 24, 12, 5
     B = q.precompute_phases_batched([s[0] for s in specs], [s[1] for s in specs], [s[2] for s in specs])
-    R = q.BatchRun(B, npop, G, seed=3, inst=inst0, prec=q.PREC_F64, tune=0)
+    R = q.BatchRun(B, npop, G, seed=3, inst=inst0, prec=q.PREC_F64, tune=0, trials=trials)
     R.advance(G)
     for b, (z, k1, k2) in enumerate(specs):
         x, f, L, _ = R.read(b)
@@ -114,8 +116,8 @@ def test_batch_run_tuned_and_graph_agree(q):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("graph", [1, 0])
-def test_batch_run_every_de_shape_same_trajectory(q, orc, graph):
+@pytest.mark.parametrize("graph,trials", [(1, 1), (0, 1), (1, 2)])
+def test_batch_run_every_de_shape_same_trajectory(q, orc, graph, trials):
     # the DE launch shape (individuals per wave x passes) moves no gene: every
     # shape gives the oracle's FP64 trajectory; np = 37 leaves ragged groups
     # and N = 1007 / 2049 ragged gene chunks for every chunk width
@@ -132,7 +134,8 @@ def test_batch_run_every_de_shape_same_trajectory(q, orc, graph):
     R.destroy()
     for ipw in (1, 2, 4):
         for passes in (1, 2, 4):
-            R = q.BatchRun(B, npop, G, seed=11, inst=inst0, prec=q.PREC_F64, tune=0, use_graph=graph)
+            R = q.BatchRun(B, npop, G, seed=11, inst=inst0, prec=q.PREC_F64, tune=0, use_graph=graph,
+                           trials=trials)
             R.set_de_shape(ipw, passes)
             R.advance(G)
             for b in range(len(specs)):
