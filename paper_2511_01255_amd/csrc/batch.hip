@@ -1150,11 +1150,10 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
             for (int64_t ch = 0; ch * cw < h[i].n; ++ch) dt[v].push_back(Tile{i, static_cast<int>(ch)});
         }
     }
-    // accepted-only trials on request only: with populations of 256 the
-    // acceptance stays near the break-even of 20 % (20 B per gene to
-    // recompute an accepted trial against 4 B per gene of stored trials),
-    // and the 64-design workload measured 2.13 ms per generation with them
-    // against 2.03 ms storing every trial
+    // accepted-only trials on request only: recomputing an accepted trial
+    // reads 20 B per gene against 4 B per gene for storing every trial, so
+    // they pay below about 20 % acceptance; the 64-design workload (NP =
+    // 256) measured 2.13 ms per generation with them against 2.03 ms
     r->lazy = c.trials == QPM_TRIALS_ACCEPTED;
     if (n_inst * c.np >= (int64_t(1) << 31)) {  // list entries are int32 instance * np + slot
         if (c.trials == QPM_TRIALS_ACCEPTED) {
