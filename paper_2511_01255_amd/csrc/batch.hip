@@ -57,8 +57,9 @@ __global__ __launch_bounds__(WAVES * 64) void batch_fit_kernel(const uint32_t *_
                                                                const float4 *__restrict__ ph32, int wpw,
                                                                const InstDesc *__restrict__ inst,
                                                                const FitSeg *__restrict__ tab,
-                                                               double *__restrict__ part)
+                                                               double *__restrict__ part, uint32_t *__restrict__ advance)
 {
+    if (advance != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) advance[0] += 1u;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const FitSeg fs = tab[blockIdx.y];
@@ -114,9 +115,12 @@ __global__ __launch_bounds__(GW * 256) void batch_fit_tab_kernel(const uint32_t 
                                                                  const float2 *__restrict__ tab32, int wpw,
                                                                  int64_t np, const InstDesc *__restrict__ inst,
                                                                  const FitSeg *__restrict__ tab,
-                                                                 double *__restrict__ part)
+                                                                 double *__restrict__ part,
+                                                                 uint32_t *__restrict__ advance)
 {
     extern __shared__ __align__(16) unsigned char lds[];
+    // a run's generation advance (this kernel does not read the counter)
+    if (advance != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) advance[0] += 1u;
     const FitSeg fs = tab[blockIdx.y];
     const InstDesc id = inst[fs.inst];
     const int64_t i = (static_cast<int64_t>(blockIdx.x) * GW + (threadIdx.x >> 8)) * 64 + (threadIdx.x & 63);
@@ -133,20 +137,24 @@ __global__ __launch_bounds__(GW * 256) void batch_fit_tab_kernel(const uint32_t 
     o[5 * ld] = t.qi;
 }
 
-// One workgroup per instance: combine the instance's slots into f, then
+// One workgroup of 1024 threads per instance: four threads per genome fold
+// a quarter of the instance's slots each (in order), the first folds the
+// four quarters in order, then
 //   mode 0 (evaluation only): f_out[b][i] = f;
 //   mode 1 (initial): f_cur = f, leaders, DE draws of generation gen;
 //   mode 2 (after DE): select, leaders;
-//   mode 3 (after GWO): select with the leaders excluded, DE draws of
-//     generation gen + 1; the last workgroup advances gen.
+//   mode 3 (after GWO): select with the leaders excluded, DE draws of the
+//     next generation (gen, which the evaluation kernel before this one
+//     advanced: it does not read the counter, so no cross-workgroup
+//     ordering is needed here).
 template <typename T>
-__global__ __launch_bounds__(256) void batch_finish_kernel(int mode, const double *__restrict__ part,
+__global__ __launch_bounds__(1024) void batch_finish_kernel(int mode, const double *__restrict__ part,
                                                            const int *__restrict__ slot_ofs, int64_t ld, int64_t np,
                                                            const InstDesc *__restrict__ inst, T *__restrict__ f_cur,
                                                            uint32_t *__restrict__ flags, int32_t *__restrict__ leaders,
                                                            int4 *__restrict__ draws, uint32_t *__restrict__ gen,
                                                            uint32_t k0, uint32_t k1, uint32_t inst0,
-                                                           uint32_t *__restrict__ ticket, uint32_t *__restrict__ fbits,
+                                                           uint32_t *__restrict__ fbits,
                                                            AcceptOut acc)
 {
     const int b = blockIdx.x;
@@ -163,23 +171,40 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(int mode, const doubl
         L2 = Lb[2];
     }
     const int64_t fw = (np + 31) / 32;  // packed flag words per instance
+    const int quarter = static_cast<int>(threadIdx.x >> 8);
+    const int q0 = s0 + (s1 - s0) * quarter / 4, q1 = s0 + (s1 - s0) * (quarter + 1) / 4;
+    __shared__ double sq[3][6][256];
     for (int64_t base = 0; base < np; base += 256) {
-        const int64_t i = base + threadIdx.x;
+        const int64_t i = base + (threadIdx.x & 255);
         const bool valid = i < np;
+        Tri t{0, 0, 0, 0, 0, 0};
+        if (valid && q0 < q1) {
+            const double *p = part + static_cast<int64_t>(q0) * 6 * ld + i;
+            t = Tri{p[0], p[ld], p[2 * ld], p[3 * ld], p[4 * ld], p[5 * ld]};
+            for (int sg = q0 + 1; sg < q1; ++sg) {
+                const double *q = part + static_cast<int64_t>(sg) * 6 * ld + i;
+                tri_append(t, Tri{q[0], q[ld], q[2 * ld], q[3 * ld], q[4 * ld], q[5 * ld]});
+            }
+        }
+        if (quarter > 0) {
+            sq[quarter - 1][0][threadIdx.x & 255] = t.ar;
+            sq[quarter - 1][1][threadIdx.x & 255] = t.ai;
+            sq[quarter - 1][2][threadIdx.x & 255] = t.br;
+            sq[quarter - 1][3][threadIdx.x & 255] = t.bi;
+            sq[quarter - 1][4][threadIdx.x & 255] = t.qr;
+            sq[quarter - 1][5][threadIdx.x & 255] = t.qi;
+        }
+        __syncthreads();
         uint32_t fl = 0, fl_old = 0;
         bool accepted = false;
-        if (valid) {
-        const double *p = part + static_cast<int64_t>(s0) * 6 * ld + i;
-        double ar = p[0], ai = p[ld], qr = p[4 * ld], qi = p[5 * ld];
-        for (int sg = s0 + 1; sg < s1; ++sg) {
-            const double *q = part + static_cast<int64_t>(sg) * 6 * ld + i;
-            const double vr = q[2 * ld], vi = q[3 * ld];
-            qr = fma(ar, vr, fma(-ai, vi, qr + q[4 * ld]));
-            qi = fma(ar, vi, fma(ai, vr, qi + q[5 * ld]));
-            ar += q[0];
-            ai += q[ld];
+        if (quarter == 0 && valid) {
+        for (int u = 0; u < 3; ++u) {
+            const int lo = s0 + (s1 - s0) * (u + 1) / 4, hi = s0 + (s1 - s0) * (u + 2) / 4;
+            if (lo < hi)
+                tri_append(t, Tri{sq[u][0][threadIdx.x], sq[u][1][threadIdx.x], sq[u][2][threadIdx.x],
+                                  sq[u][3][threadIdx.x], sq[u][4][threadIdx.x], sq[u][5][threadIdx.x]});
         }
-        const double sr = qr + id.C[0], si = qi + id.C[1];
+        const double sr = t.qr + id.C[0], si = t.qi + id.C[1];
         const T v = static_cast<T>(fma(sr, sr, si * si));
         if (mode <= 1) {
             fb[i] = v;
@@ -194,12 +219,11 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(int mode, const doubl
                 flb[i] = fl;
             }
         }
-        if (mode == 1 || mode == 3)
-            draws[static_cast<int64_t>(b) * np + i] =
-                de_draw(i, np, id.n, mode == 3 ? g + 1u : g, inst0 + static_cast<uint32_t>(b), k0, k1);
+        if (mode == 1 || mode == 3)  // mode 3: the evaluation kernel already advanced gen
+            draws[static_cast<int64_t>(b) * np + i] = de_draw(i, np, id.n, g, inst0 + static_cast<uint32_t>(b), k0, k1);
         }
         // the packed copy of this wave's 64 flags (words (base + 64 w) / 32 and + 1)
-        if (mode >= 2 && fbits) {
+        if (quarter == 0 && mode >= 2 && fbits) {
             const uint64_t m = __ballot(fl != 0u);
             const int64_t w0 = (base + 64 * (threadIdx.x >> 6)) / 32;
             if ((threadIdx.x & 63) == 0) {
@@ -209,7 +233,7 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(int mode, const doubl
         }
         // accepted trials listed (as instance * np + slot) for
         // batch_materialize_kernel, with the flags from before the selection
-        if (mode == 2 && acc.list != nullptr) {
+        if (quarter == 0 && mode == 2 && acc.list != nullptr) {
             const int lane = threadIdx.x & 63;
             const uint64_t mo = __ballot(fl_old != 0u);
             const uint64_t am = __ballot(accepted);
@@ -225,21 +249,11 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(int mode, const doubl
                 acc.list[basec + static_cast<uint32_t>(__popcll(am & ((uint64_t(1) << lane) - 1)))] =
                     static_cast<int32_t>(static_cast<int64_t>(b) * np + i);
         }
+        __syncthreads();  // sq is refilled for the next 256 genomes
     }
     if (mode == 1 || mode == 2) {
         __syncthreads();
-        block_top3<T, 256>(fb, np, Lb);
-    }
-    if (mode == 3) {
-        __shared__ int s_last;
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) s_last = (atomicAdd(ticket, 1u) == gridDim.x - 1) ? 1 : 0;
-        __syncthreads();
-        if (s_last && threadIdx.x == 0) {
-            gen[0] += 1u;
-            *ticket = 0u;
-        }
+        block_top3<T, 1024>(fb, np, Lb);
     }
 }
 
@@ -665,7 +679,8 @@ QPM_API qpm_status qpm_batch_info(qpm_batch b, int32_t *n_inst, int64_t *n_domai
 // ---------------------------------------------------------------- batched fitness
 
 static qpm_status launch_batch_fit(const qpm_batch_s &bt, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
-                                   const BatchFitPlan &pl, const FitSeg *segs_dev, double *part, hipStream_t s)
+                                   const BatchFitPlan &pl, const FitSeg *segs_dev, double *part, hipStream_t s,
+                                   uint32_t *advance = nullptr)
 {
     if (pl.gw > 0) {
         const dim3 grid(static_cast<unsigned>((np + 64 * pl.gw - 1) / (64 * pl.gw)),
@@ -675,10 +690,10 @@ static qpm_status launch_batch_fit(const qpm_batch_s &bt, qpm_prec p, const uint
     case G:                                                                                                        \
         if (p == QPM_PREC_F32)                                                                                     \
             batch_fit_tab_kernel<true, G><<<grid, G * 256, lds, s>>>(bits, ld, bt.tab64, bt.tab32, pl.wpw, np, bt.dev, \
-                                                                    segs_dev, part);                               \
+                                                                    segs_dev, part, advance);                      \
         else                                                                                                       \
             batch_fit_tab_kernel<false, G><<<grid, G * 256, lds, s>>>(bits, ld, bt.tab64, bt.tab32, pl.wpw, np,      \
-                                                                     bt.dev, segs_dev, part);                      \
+                                                                     bt.dev, segs_dev, part, advance);             \
         break;
         switch (pl.gw) {
             QPM_BT_CASE(1)
@@ -695,10 +710,10 @@ static qpm_status launch_batch_fit(const qpm_batch_s &bt, qpm_prec p, const uint
     case NW:                                                                                                      \
         if (p == QPM_PREC_F32)                                                                                    \
             batch_fit_kernel<true, NW><<<grid, NW * 64, 0, s>>>(bits, ld, bt.ph64, bt.ph32, pl.wpw, bt.dev,       \
-                                                                segs_dev, part);                                  \
+                                                                segs_dev, part, advance);                         \
         else                                                                                                      \
             batch_fit_kernel<false, NW><<<grid, NW * 64, 0, s>>>(bits, ld, bt.ph64, bt.ph32, pl.wpw, bt.dev,      \
-                                                                 segs_dev, part);                                 \
+                                                                 segs_dev, part, advance);                        \
         break;
     switch (pl.waves) {
         QPM_BF_CASE(4)
@@ -752,18 +767,18 @@ static void free_fit_plan(FitPlanDev &d, hipStream_t s)
 
 static qpm_status launch_batch_finish(int mode, const qpm_batch_s &bt, qpm_prec p, const FitPlanDev &fp, int64_t ld,
                                       int64_t np, void *f, uint32_t *flags, int32_t *leaders, int4 *draws,
-                                      uint32_t *gen, uint64_t seed, uint32_t inst0, uint32_t *ticket, hipStream_t s,
+                                      uint32_t *gen, uint64_t seed, uint32_t inst0, hipStream_t s,
                                       uint32_t *fbits = nullptr, AcceptOut acc = AcceptOut{})
 {
     const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
     if (p == QPM_PREC_F64)
-        batch_finish_kernel<double><<<bt.n_inst, 256, 0, s>>>(mode, fp.part, fp.slot_ofs, ld, np, bt.dev,
+        batch_finish_kernel<double><<<bt.n_inst, 1024, 0, s>>>(mode, fp.part, fp.slot_ofs, ld, np, bt.dev,
                                                              static_cast<double *>(f), flags, leaders, draws, gen, k0,
-                                                             k1, inst0, ticket, fbits, acc);
+                                                             k1, inst0, fbits, acc);
     else
-        batch_finish_kernel<float><<<bt.n_inst, 256, 0, s>>>(mode, fp.part, fp.slot_ofs, ld, np, bt.dev,
+        batch_finish_kernel<float><<<bt.n_inst, 1024, 0, s>>>(mode, fp.part, fp.slot_ofs, ld, np, bt.dev,
                                                             static_cast<float *>(f), flags, leaders, draws, gen, k0,
-                                                            k1, inst0, ticket, fbits, acc);
+                                                            k1, inst0, fbits, acc);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }
@@ -825,7 +840,7 @@ static qpm_status batch_eval_plan(qpm_batch b, qpm_prec p, const uint32_t *bits,
     if (st != QPM_OK) return st;
     st = launch_batch_fit(*b, p, bits, np, ld, pl, fp.segs, fp.part, s);
     if (st == QPM_OK)
-        st = launch_batch_finish(0, *b, p, fp, ld, np, fitness, nullptr, nullptr, nullptr, nullptr, 0, 0, nullptr, s);
+        st = launch_batch_finish(0, *b, p, fp, ld, np, fitness, nullptr, nullptr, nullptr, nullptr, 0, 0, s);
     free_fit_plan(fp, s);
     return st;
 }
@@ -845,7 +860,6 @@ struct qpm_batch_run_s {
     int32_t *leaders = nullptr;
     int4 *draws = nullptr;
     uint32_t *gen = nullptr;
-    uint32_t *ticket = nullptr;
     float *a_tab = nullptr;
     InstDesc *inst = nullptr;  // instance table with xofs scaled by np
     Tile *gtiles = nullptr;    // (instance, 1024-gene chunk)
@@ -893,7 +907,6 @@ static void release_batch_run(qpm_batch_run_s *r)
     (void)hipFree(r->acc_cnt);
     (void)hipFree(r->fbits_prev);
     (void)hipFree(r->gen);
-    (void)hipFree(r->ticket);
     (void)hipFree(r->a_tab);
     (void)hipFree(r->inst);
     (void)hipFree(r->gtiles);
@@ -964,7 +977,7 @@ static qpm_status batch_generation(qpm_batch_run_s *r, hipEvent_t *ev = nullptr)
     QPM_STEP(QPM_K_FIT_DE, launch_batch_fit(*r->bt, p, r->bits, c.np, r->ld, r->fplan, r->fdev.segs, r->fdev.part,
                                             r->st))
     QPM_STEP(QPM_K_FINISH_DE, launch_batch_finish(2, *r->bt, p, r->fdev, r->ld, c.np, r->f_cur, r->flags, r->leaders,
-                                                  r->draws, r->gen, c.seed, c.inst, r->ticket, r->st, r->fbits,
+                                                  r->draws, r->gen, c.seed, c.inst, r->st, r->fbits,
                                                   r->lazy ? AcceptOut{r->acc_list, r->acc_cnt, r->fbits_prev}
                                                           : AcceptOut{}))
     if (r->lazy) {  // the accepted trials' genes (timed with the finish)
@@ -976,9 +989,9 @@ static qpm_status batch_generation(qpm_batch_run_s *r, hipEvent_t *ev = nullptr)
     }
     QPM_STEP(QPM_K_GWO, launch_batch_gwo(r))
     QPM_STEP(QPM_K_FIT_GWO, launch_batch_fit(*r->bt, p, r->bits, c.np, r->ld, r->fplan, r->fdev.segs, r->fdev.part,
-                                             r->st))
+                                             r->st, r->gen))
     QPM_STEP(QPM_K_FINISH_GWO, launch_batch_finish(3, *r->bt, p, r->fdev, r->ld, c.np, r->f_cur, r->flags,
-                                                   r->leaders, r->draws, r->gen, c.seed, c.inst, r->ticket, r->st,
+                                                   r->leaders, r->draws, r->gen, c.seed, c.inst, r->st,
                                                    r->fbits))
 #undef QPM_STEP
     return mark(QPM_K_COUNT);
@@ -1184,7 +1197,6 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
     if (e == hipSuccess && r->lazy) e = hipMalloc(&r->acc_cnt, sizeof(uint32_t));
     if (e == hipSuccess && r->lazy) e = hipMalloc(&r->fbits_prev, sizeof(uint32_t) * n_inst * ((c.np + 31) / 32));
     if (e == hipSuccess) e = hipMalloc(&r->gen, sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc(&r->ticket, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&r->a_tab, sizeof(float) * c.generations);
     if (e == hipSuccess) e = hipMalloc(&r->inst, sizeof(InstDesc) * n_inst);
     if (e == hipSuccess) e = hipMalloc(&r->gtiles, sizeof(Tile) * gt.size());
@@ -1214,7 +1226,6 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
     if (e == hipSuccess) e = hipMemsetAsync(r->flags, 0, sizeof(uint32_t) * n_inst * c.np, r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->fbits, 0, sizeof(uint32_t) * n_inst * ((c.np + 31) / 32), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->gen, 0, sizeof(uint32_t), r->st);
-    if (e == hipSuccess) e = hipMemsetAsync(r->ticket, 0, sizeof(uint32_t), r->st);
     if (e == hipSuccess && r->lazy) e = hipMemsetAsync(r->acc_cnt, 0, sizeof(uint32_t), r->st);
     if (e == hipSuccess) e = hipMemsetAsync(r->bits, 0, sizeof(uint32_t) * b->total_words * r->ld, r->st);
     if (e == hipSuccess) e = hipStreamSynchronize(r->st);
@@ -1253,7 +1264,7 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
     if (st == QPM_OK) st = launch_batch_fit(*b, p, r->bits, c.np, r->ld, r->fplan, r->fdev.segs, r->fdev.part, r->st);
     if (st == QPM_OK)
         st = launch_batch_finish(1, *b, p, r->fdev, r->ld, c.np, r->f_cur, r->flags, r->leaders, r->draws, r->gen,
-                                 c.seed, c.inst, r->ticket, r->st);
+                                 c.seed, c.inst, r->st);
     // the DE shape: the trial launches of the tuner write only the other
     // gene buffer and the bit rows, which the first generation overwrites
     if (st == QPM_OK && tune) st = tune_de(r);
