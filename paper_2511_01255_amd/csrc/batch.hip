@@ -439,11 +439,12 @@ __global__ __launch_bounds__(256) void batch_materialize_kernel(BatchPop bp, con
 
 // GWO: grid x = 8 ceil(np / 8) (individuals in contiguous ranges per XCD,
 // as in the single-design kernel), y = tile (instance, 1024-gene chunk)
+template <int VARIANT>
 __global__ __launch_bounds__(256) void batch_gwo_kernel(BatchPop bp, const InstDesc *__restrict__ inst,
                                                         const Tile *__restrict__ tiles,
                                                         const int32_t *__restrict__ leaders,
                                                         const float *__restrict__ a_tab, uint32_t k0, uint32_t k1,
-                                                        const uint32_t *__restrict__ gen, uint32_t inst0, int variant,
+                                                        const uint32_t *__restrict__ gen, uint32_t inst0,
                                                         uint32_t *__restrict__ bits, int64_t ld, int64_t per_xcd)
 {
     const int64_t np = bp.np;
@@ -468,8 +469,8 @@ __global__ __launch_bounds__(256) void batch_gwo_kernel(BatchPop bp, const InstD
         const float4 X0 = *reinterpret_cast<const float4 *>(row_of(pv, L0) + j0);
         const float4 X1 = *reinterpret_cast<const float4 *>(row_of(pv, L1) + j0);
         const float4 X2 = *reinterpret_cast<const float4 *>(row_of(pv, L2) + j0);
-        const float4 yv = gwo_quad(xv, X0, X1, X2, static_cast<uint32_t>(q), static_cast<uint32_t>(i), g,
-                                   inst0 + static_cast<uint32_t>(tl.inst), k0, k1, a, two_a, variant);
+        const float4 yv = gwo_quad<VARIANT>(xv, X0, X1, X2, static_cast<uint32_t>(q), static_cast<uint32_t>(i), g,
+                                            inst0 + static_cast<uint32_t>(tl.inst), k0, k1, a, two_a);
         store_quad_nt(out_row_of(pv, i), j0, D, yv);
         nib = quad_nibble(yv, j0, D);
     }
@@ -954,9 +955,14 @@ static qpm_status launch_batch_gwo(qpm_batch_run_s *r)
     const qpm_run_config &c = r->cfg;
     const int64_t per_xcd = (c.np + 7) / 8;
     const dim3 grid(static_cast<unsigned>(8 * per_xcd), static_cast<unsigned>(r->n_gtiles));
-    batch_gwo_kernel<<<grid, 256, 0, r->st>>>(r->pop(), r->inst, r->gtiles, r->leaders, r->a_tab,
-                                             static_cast<uint32_t>(c.seed), static_cast<uint32_t>(c.seed >> 32),
-                                             r->gen, c.inst, c.gwo_variant, r->bits, r->ld, per_xcd);
+    if (c.gwo_variant == 1)
+        batch_gwo_kernel<1><<<grid, 256, 0, r->st>>>(r->pop(), r->inst, r->gtiles, r->leaders, r->a_tab,
+                                                    static_cast<uint32_t>(c.seed), static_cast<uint32_t>(c.seed >> 32),
+                                                    r->gen, c.inst, r->bits, r->ld, per_xcd);
+    else
+        batch_gwo_kernel<0><<<grid, 256, 0, r->st>>>(r->pop(), r->inst, r->gtiles, r->leaders, r->a_tab,
+                                                    static_cast<uint32_t>(c.seed), static_cast<uint32_t>(c.seed >> 32),
+                                                    r->gen, c.inst, r->bits, r->ld, per_xcd);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }

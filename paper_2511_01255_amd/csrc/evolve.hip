@@ -279,11 +279,11 @@ qpm_status launch_materialize(const PopView &pv, const int4 *draws, const uint32
 // (x mod 8) ceil(np / 8) + x / 8. Each XCD thus owns a contiguous range of
 // individuals and the 32-bit bit words of neighbouring individuals, which
 // share cache lines, are written from one L2 instead of eight.
+template <int VARIANT>
 __global__ __launch_bounds__(256) void gwo_kernel(PopView pv, const int32_t *__restrict__ leaders,
                                                   const float *__restrict__ a_tab, float a_c, uint32_t k0, uint32_t k1,
                                                   const uint32_t *__restrict__ gen_dev, uint32_t gen_c, uint32_t inst,
-                                                  int variant, uint32_t *__restrict__ bits, int64_t ld,
-                                                  int64_t per_xcd)
+                                                  uint32_t *__restrict__ bits, int64_t ld, int64_t per_xcd)
 {
     const int64_t np = pv.np, D = pv.D;
     const int64_t i = static_cast<int64_t>(blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
@@ -306,8 +306,8 @@ __global__ __launch_bounds__(256) void gwo_kernel(PopView pv, const int32_t *__r
         const float4 X0 = *reinterpret_cast<const float4 *>(row_of(pv, L0) + j0);
         const float4 X1 = *reinterpret_cast<const float4 *>(row_of(pv, L1) + j0);
         const float4 X2 = *reinterpret_cast<const float4 *>(row_of(pv, L2) + j0);
-        const float4 yv4 = gwo_quad(xv, X0, X1, X2, static_cast<uint32_t>(q), static_cast<uint32_t>(i), g, inst, k0,
-                                    k1, a, two_a, variant);
+        const float4 yv4 = gwo_quad<VARIANT>(xv, X0, X1, X2, static_cast<uint32_t>(q), static_cast<uint32_t>(i), g,
+                                             inst, k0, k1, a, two_a);
         store_quad_nt(out_row_of(pv, i), j0, D, yv4);
         nib = quad_nibble(yv4, j0, D);
     }
@@ -547,8 +547,12 @@ qpm_status launch_gwo(const PopView &pv, const int32_t *leaders, const float *a_
     const qpm_status st = check_quad_grid(pv.D, 8 * per_xcd);
     if (st != QPM_OK) return st;
     const dim3 grid(static_cast<unsigned>(8 * per_xcd), quad_grid(pv.D, pv.np).y);
-    gwo_kernel<<<grid, 256, 0, s>>>(pv, leaders, a_tab, a, static_cast<uint32_t>(seed),
-                                    static_cast<uint32_t>(seed >> 32), gen_dev, gen, inst, variant, bits, ld, per_xcd);
+    if (variant == 1)
+        gwo_kernel<1><<<grid, 256, 0, s>>>(pv, leaders, a_tab, a, static_cast<uint32_t>(seed),
+                                           static_cast<uint32_t>(seed >> 32), gen_dev, gen, inst, bits, ld, per_xcd);
+    else
+        gwo_kernel<0><<<grid, 256, 0, s>>>(pv, leaders, a_tab, a, static_cast<uint32_t>(seed),
+                                           static_cast<uint32_t>(seed >> 32), gen_dev, gen, inst, bits, ld, per_xcd);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }

@@ -122,9 +122,9 @@ __device__ __forceinline__ float4 de_quad(float4 xv, float4 a, float4 b, float4 
 // r1 = lo16 2^-16 and C = 2 r2 = hi16 2^-15; A = fmaf(2a, r1, -a),
 // D_k = |fmaf(C, X_k, -x)|, Y_k = fmaf(-A, D_k, X_k); then the weighted
 // combination (variant 0) or the mean (variant 1), divided by 3, clamped.
+template <int VARIANT>
 __device__ __forceinline__ float4 gwo_quad(float4 xv, float4 X0, float4 X1, float4 X2, uint32_t q, uint32_t i,
-                                           uint32_t g, uint32_t inst, uint32_t k0, uint32_t k1, float a, float two_a,
-                                           int variant)
+                                           uint32_t g, uint32_t inst, uint32_t k0, uint32_t k1, float a, float two_a)
 {
     const uint32_t c3 = (inst << 8) | kTagGwo;
     const uint32_t cq = 3u * q;
@@ -151,7 +151,7 @@ __device__ __forceinline__ float4 gwo_quad(float4 xv, float4 X0, float4 X1, floa
             Y[k] = fmaf(-A, Dk, Xs[k][e]);
         }
         float yv;
-        if (variant == 1) {
+        if constexpr (VARIANT == 1) {
             yv = div3((Y[0] + Y[1]) + Y[2]);
         } else {
             const float s = (fabsf(Y[0]) + fabsf(Y[1])) + fabsf(Y[2]);
