@@ -292,7 +292,7 @@ __global__ __launch_bounds__(256) void batch_init_kernel(int64_t np, const InstD
         store_quad(x + id.xofs + i * id.ldx, j0, id.n, v);
         nib = quad_nibble(v, j0, id.n);
     }
-    store_word(nib, q, valid, bits + id.wofs * ld, ld, i);
+    store_word(nib, q, id.n, bits + id.wofs * ld, ld, i);
 }
 
 // DE: tiles (instance, chunk of CW = 256 / IPW genes) dealt round-robin to
@@ -370,11 +370,8 @@ __global__ __launch_bounds__(256) void batch_de_kernel(BatchPop bp, const InstDe
             if (store_genes) store_quad_nt((second(i) ? pv.out0 : pv.out1) + i * pv.ldx, j0, D, uv);
             nib = quad_nibble(uv, j0, D);
         }
-        uint32_t w = nib << (4 * (t & 7));
-        w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 1));
-        w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 2));
-        w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 4));
-        if ((t & 7) == 0) wsh[r * IPG + local][li >> 3] = w;
+        const uint32_t w = or8_into_last(nib << (4 * (t & 7)));
+        if ((t & 7) == 7) wsh[r * IPG + local][li >> 3] = w;
         if (r + 1 < R) {
 #pragma unroll
             for (int m = 0; m < 4; ++m) cur[m] = nxt[m];
@@ -474,7 +471,7 @@ __global__ __launch_bounds__(256) void batch_gwo_kernel(BatchPop bp, const InstD
         store_quad_nt(out_row_of(pv, i), j0, D, yv);
         nib = quad_nibble(yv, j0, D);
     }
-    store_word(nib, q, valid, bits + id.wofs * ld, ld, i);
+    store_word(nib, q, id.n, bits + id.wofs * ld, ld, i);
 }
 
 // rows of instance b's current population -> dense out[np][ldo]

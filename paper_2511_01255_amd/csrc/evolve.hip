@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void init_kernel(int64_t D, int64_t ldx, uint3
         store_quad(x + i * ldx, j0, D, v);
         nib = quad_nibble(v, j0, D);
     }
-    store_word(nib, q, valid, bits, ld, i);
+    store_word(nib, q, D, bits, ld, i);
 }
 
 // ------------------------------------------------------------ DE rand/1 + binomial crossover
@@ -168,11 +168,8 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
             nib = quad_nibble(uv, j0, D);
         }
         // merge the nibbles of 8 neighbouring lanes (32 genes) into one word
-        uint32_t w = nib << (4 * (t & 7));
-        w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 1));
-        w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 2));
-        w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 4));
-        if ((t & 7) == 0) wsh[r * IPG + local][li >> 3] = w;
+        const uint32_t w = or8_into_last(nib << (4 * (t & 7)));
+        if ((t & 7) == 7) wsh[r * IPG + local][li >> 3] = w;
         if (r + 1 < R) {
 #pragma unroll
             for (int m = 0; m < 4; ++m) cur[m] = nxt[m];
@@ -311,7 +308,7 @@ __global__ __launch_bounds__(256) void gwo_kernel(PopView pv, const int32_t *__r
         store_quad_nt(out_row_of(pv, i), j0, D, yv4);
         nib = quad_nibble(yv4, j0, D);
     }
-    store_word(nib, q, valid, bits, ld, i);
+    store_word(nib, q, D, bits, ld, i);
 }
 
 // Improved discrete four-leader step (dgwo_quad), same grid as gwo_kernel.
@@ -345,7 +342,7 @@ __global__ __launch_bounds__(256) void dgwo_kernel(PopView pv, const int32_t *__
         store_quad_nt(out_row_of(pv, i), j0, D, yv4);
         nib = quad_nibble(yv4, j0, D);
     }
-    store_word(nib, q, valid, bits, ld, i);
+    store_word(nib, q, D, bits, ld, i);
 }
 
 // The fourth leader: the best genome (f descending, slot ascending) other
@@ -419,7 +416,7 @@ __global__ __launch_bounds__(256) void pack_pop_kernel(const float *__restrict__
     const bool valid = j0 < D;
     uint32_t nib = 0;
     if (valid) nib = quad_nibble(*reinterpret_cast<const float4 *>(x + i * ldx + j0), j0, D);
-    store_word(nib, q, valid, bits, ld, i);
+    store_word(nib, q, D, bits, ld, i);
 }
 
 __global__ __launch_bounds__(256) void pack_row_kernel(const float *__restrict__ x, int64_t D,

@@ -78,17 +78,23 @@ __device__ __forceinline__ uint32_t quad_nibble(float4 v, int64_t j0, int64_t D)
     return n;
 }
 
-// Merge the nibbles of 8 neighbouring lanes (gene quads 8w .. 8w+7) into
-// word w and store it from the first lane of the group. Every lane of the
-// wave must call this (it shuffles).
-__device__ __forceinline__ void store_word(uint32_t nib, int64_t q, bool valid, uint32_t *bits, int64_t ld,
-                                           int64_t i)
+// OR of the values of lanes l - 7 .. l, valid in lanes l = 7 (mod 8): three
+// DPP row shifts (1, 2, 4) within the 16-lane row, no LDS traffic.
+__device__ __forceinline__ uint32_t or8_into_last(uint32_t w)
 {
-    uint32_t w = nib << (4 * (threadIdx.x & 7));
-    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 1));
-    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 2));
-    w |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 4));
-    if (valid && (threadIdx.x & 7) == 0) bits[(q >> 3) * ld + i] = w;
+    w |= static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(w), 0x111, 0xF, 0xF, true));
+    w |= static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(w), 0x112, 0xF, 0xF, true));
+    w |= static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(w), 0x114, 0xF, 0xF, true));
+    return w;
+}
+
+// Merge the nibbles of 8 neighbouring lanes (gene quads 8w .. 8w+7) into
+// word w and store it from the last lane of the group when the word holds
+// genes (4 (8w) < D). Every lane of the wave must call this.
+__device__ __forceinline__ void store_word(uint32_t nib, int64_t q, int64_t D, uint32_t *bits, int64_t ld, int64_t i)
+{
+    const uint32_t w = or8_into_last(nib << (4 * (threadIdx.x & 7)));
+    if ((threadIdx.x & 7) == 7 && 4 * (q & ~int64_t(7)) < D) bits[(q >> 3) * ld + i] = w;
 }
 
 // DE for genes j0..j0+3 of individual i: v = clamp(fmaf(F, b - c, a)),
