@@ -124,3 +124,49 @@ def test_run_rejects_bad_config(L):
         assert L.qpm_run_create(fake, C.byref(cfg), None, C.byref(h)) == -1
     assert h.value is None
     assert L.qpm_run_advance(None, 1) == -1
+
+
+def test_run_rejects_unknown_control_and_trial_storage(L):
+    from paper_2511_01255_amd import qpm
+    fake = C.c_void_p(0x10000)
+    h = C.c_void_p()
+    for kw in [dict(control=3), dict(control=-1), dict(trials=3), dict(trials=-1)]:
+        cfg = qpm._config(8, 5, **kw)
+        assert L.qpm_run_create(fake, C.byref(cfg), None, C.byref(h)) == -1
+        assert ("control" in _err(L)) or ("trial" in _err(L))
+    # the adaptive control is not offered on a multi-wavelength objective
+    cfg = qpm._config(8, 5, control=2)
+    assert L.qpm_run_create_objective(fake, C.byref(cfg), None, C.byref(h)) == -1
+    assert "adaptive" in _err(L)
+    assert h.value is None
+
+
+def test_discrete_gwo_and_objective_reject_bad_arguments(L):
+    x = C.c_void_p(0x10000)
+    y = C.c_void_p(0x20000)
+    b = C.c_void_p(0x30000)
+    lead = C.c_void_p(0x40000)
+    par = C.cast((C.c_float * 4)(0.5, 0.8, 0.1, 0.1), C.c_void_p)
+    bad = C.cast((C.c_float * 4)(0.5, float("nan"), 0.1, 0.1), C.c_void_p)
+    assert L.qpm_dgwo_step(x, 3, 10, 12, lead, par, 0, 0, 0, y, b, 64, None) == -1
+    assert L.qpm_dgwo_step(x, 8, 10, 12, None, par, 0, 0, 0, y, b, 64, None) == -1
+    assert L.qpm_dgwo_step(x, 8, 10, 12, lead, None, 0, 0, 0, y, b, 64, None) == -1
+    assert L.qpm_dgwo_step(x, 8, 10, 12, lead, bad, 0, 0, 0, y, b, 64, None) == -1 and "finite" in _err(L)
+    h = C.c_void_p()
+    designs = (C.c_void_p * 9)(*([0x10000] * 9))
+    assert L.qpm_objective_create(None, 1, 0, 1.0, 0.0, C.byref(h)) == -1
+    assert L.qpm_objective_create(designs, 0, 0, 1.0, 0.0, C.byref(h)) == -1
+    assert L.qpm_objective_create(designs, 9, 0, 1.0, 0.0, C.byref(h)) == -1 and "K must be" in _err(L)
+    assert L.qpm_objective_create(designs, 2, 2, 1.0, 0.0, C.byref(h)) == -1 and "kind" in _err(L)
+    assert L.qpm_objective_create(designs, 2, 1, float("inf"), 0.0, C.byref(h)) == -1
+    assert h.value is None
+    assert L.qpm_eval_objective(None, 0, b, 4, 64, y, None, 0, None) == -1
+    assert L.qpm_objective_free(None) == 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
