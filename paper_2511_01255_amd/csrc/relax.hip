@@ -42,8 +42,20 @@ static RelaxPlan plan_relax(int64_t n, int64_t B, bool f32)
 
 template <typename T>
 __device__ __forceinline__ T tanh_t(T x);
+// FP32: tanh x = 1 - 2 / (1 + e^{2x}) from the hardware exp2 and
+// reciprocal (a few ulp; exact +-1 once e^{2x} overflows or underflows),
+// and x (1 - x^2 / 3) for |x| < 2^-6, where the first form loses relative
+// accuracy (the next term, 2 x^5 / 15, is below 1e-8 relative there). The
+// FP32 path's tolerance (1e-5) is far above either error.
 template <>
-__device__ __forceinline__ float tanh_t<float>(float x) { return tanhf(x); }
+__device__ __forceinline__ float tanh_t<float>(float x)
+{
+    const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // 2 log2(e) x
+    const float big = fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
+    const float x2 = x * x;
+    const float small = fmaf(-x2 * (1.0f / 3.0f), x, x);
+    return fabsf(x) < 0.015625f ? small : big;
+}
 template <>
 __device__ __forceinline__ double tanh_t<double>(double x) { return tanh(x); }
 
