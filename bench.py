@@ -111,7 +111,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--prec", choices=["f32", "f64"], default="f32")
-    ap.add_argument("--cpu-generations", type=int, default=30,
+    ap.add_argument("--cpu-generations", type=int, default=40,
                     help="generations of the CPU oracle sample (0 = skip)")
     ap.add_argument("--no-extras", action="store_true", help="only the timed generations")
     ap.add_argument("--calib-copy", action="store_true",
@@ -337,6 +337,40 @@ def main():
         out["relaxation"] = rel
         log("[bench] relaxation fwd+adjoint: %s" % rel)
 
+        # gradient polish of the leaders inside a run (N = 10^4, NP = 1024,
+        # FP32): 20 relaxation steps every 100 generations for 500
+        # generations; leaders replaced (exact +-1 fitness strictly higher)
+        Rq = qpm.Run(design, 1024, 500, F=F, CR=CR, seed=0, prec=qpm.PREC_F32, tune=1)
+        acc_total, t_pol = 0, 0.0
+        for _ in range(5):
+            Rq.advance(100)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            acc_total += Rq.polish(20, 0.05)
+            t_pol += time.perf_counter() - t0
+        Rq.destroy()
+        out["polish_in_run"] = {"N": N_DOMAINS, "NP": 1024, "generations": 500, "polish_every": 100,
+                                "steps": 20, "leaders_replaced": acc_total, "of_leaders_tried": 15,
+                                "ms_per_polish": t_pol * 1e3 / 5}
+        log("[bench] polish in run: %s" % out["polish_in_run"])
+
+        # the plain FP64 HWSDA configuration: N = 256 x 2 um, NP = 32,
+        # G = 200 (seed 0); the whole run on the GPU in FP64 and in FP32 (a
+        # latency-bound size: one graph launch per 8 generations)
+        zp = inputs.uniform_boundaries(256, 2.0)
+        Dp = qpm.precompute_phases(zp, inputs.DK1, inputs.DK2)
+        plain = {}
+        for name, p_ in (("gpu_f64", qpm.PREC_F64), ("gpu_f32", qpm.PREC_F32)):
+            Rp1 = qpm.Run(Dp, 32, 200, F=F, CR=CR, seed=0, prec=p_)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Rp1.advance(200)
+            torch.cuda.synchronize()
+            plain[name] = {"generations_per_s": 200 / (time.perf_counter() - t0)}
+            Rp1.destroy()
+        out["plain_fp64_n256_np32_g200"] = plain
+        log("[bench] plain N=256 NP=32 G=200: %s" % plain)
+
     if not args.no_extras:
         # a run shaped like the paper's timing table (N = 6600 domains of
         # 0.1 um, L = 660 um, NP = 5000, G = 1000), with this workload's dk:
@@ -434,6 +468,14 @@ def main():
             "sample": "%d HWSDA generations of the same workload (plus the initial evaluation) with the "
                       "long-double CPU oracle, %.1f s" % (G, tc),
         }
+        if not args.no_extras:
+            # the oracle on the plain FP64 configuration (N = 256, NP = 32,
+            # G = 200), beside the GPU runs of it above
+            Op = orc.Design(inputs.uniform_boundaries(256, 2.0), inputs.DK1, inputs.DK2)
+            t0 = time.perf_counter()
+            Op.hwsda_run(32, 200, F, CR, 0)
+            out["oracle_plain_fp64_n256_np32_g200"] = {
+                "generations_per_s": 200 / (time.perf_counter() - t0), "cores": orc.num_threads()}
     print(json.dumps(out), flush=True)
 
 
