@@ -105,6 +105,16 @@ def measured_traffic(step):
 
 
 
+def host_cpu():
+    """The host's CPU model and logical CPU count, from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            names = [l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")]
+        return "%s (%d logical CPUs)" % (names[0], len(names)) if names else None
+    except OSError:
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +250,38 @@ def main():
             log("[bench] %s: %.1f generations/s, fitness pass %.1f us" % (name, st / dt2, t_fit * 1e6))
         out["generations_per_s_by_fitness"] = alt
         out["fitness_pass_in_run"] = fitk
+
+        # the fitness entry point alone on the benchmark population: K = 200
+        # back-to-back calls between HIP events on the current stream (median
+        # of 5 repetitions), and one call after an idle device (median of 20)
+        thr = {}
+        for name, p_, k_, K_ in (("f32_table", qpm.PREC_F32, qpm.FIT_TABLE, 200),
+                                 ("f64_table", qpm.PREC_F64, qpm.FIT_TABLE, 200),
+                                 ("f64_per_genome", qpm.PREC_F64, qpm.FIT_PER_GENOME, 20)):
+            fo = qpm.eval_fitness(design, bits, NP, p_, kernel=k_)
+            reps, lat = [], []
+            for _ in range(5):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(K_):
+                    qpm.eval_fitness(design, bits, NP, p_, kernel=k_, out=fo)
+                e1.record()
+                e1.synchronize()
+                reps.append(e0.elapsed_time(e1) / K_)
+            for _ in range(20):
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                qpm.eval_fitness(design, bits, NP, p_, kernel=k_, out=fo)
+                e1.record()
+                e1.synchronize()
+                lat.append(e0.elapsed_time(e1))
+            t_pass = float(np.median(reps)) * 1e-3
+            rate = NP * N_DOMAINS / t_pass
+            thr[name] = {"passes": K_, "us_per_pass": t_pass * 1e6, "domain_evals_per_s": rate,
+                         "single_call_us": float(np.median(lat)) * 1e3}
+            log("[bench] fitness alone %s: %.2f us per pass, %.3g domain evaluations/s" % (name, t_pass * 1e6, rate))
+        out["fitness_throughput_np4096_n10000"] = thr
 
     if not args.no_extras:
         # full HWSDA at NP = 1024 on the same design (G = 5000 schedule,
@@ -467,6 +509,7 @@ def main():
             "kind": "oracle",
             "sample": "%d HWSDA generations of the same workload (plus the initial evaluation) with the "
                       "long-double CPU oracle, %.1f s" % (G, tc),
+            "host_cpu": host_cpu(),
         }
         if not args.no_extras:
             # the oracle on the plain FP64 configuration (N = 256, NP = 32,
@@ -476,6 +519,27 @@ def main():
             Op.hwsda_run(32, 200, F, CR, 0)
             out["oracle_plain_fp64_n256_np32_g200"] = {
                 "generations_per_s": 200 / (time.perf_counter() - t0), "cores": orc.num_threads()}
+            # one fitness pass of the benchmark population on the oracle, on
+            # all host threads and on one (median of 3 each; the plain run
+            # above on one thread too)
+            dsign = orc.sign_map(mag * d.astype(np.float32))
+            one = {}
+            for nt in (orc.num_threads(), 1):
+                orc.set_num_threads(nt)
+                ts = []
+                for _ in range(3):
+                    t0 = time.perf_counter()
+                    O.fitness(dsign)
+                    ts.append(time.perf_counter() - t0)
+                one[nt] = NP * N_DOMAINS / float(np.median(ts))
+            t0 = time.perf_counter()
+            Op.hwsda_run(32, 200, F, CR, 0)
+            plain1 = 200 / (time.perf_counter() - t0)
+            orc.set_num_threads(max(one))
+            out["oracle_fitness_pass_np4096_n10000"] = {
+                "domain_evals_per_s_all_threads": one[max(one)], "threads": max(one),
+                "domain_evals_per_s_one_thread": one[1]}
+            out["oracle_plain_fp64_n256_np32_g200"]["generations_per_s_one_thread"] = plain1
     print(json.dumps(out), flush=True)
 
 

@@ -36,6 +36,14 @@
  *     64-bit seed; the counter is (c0, individual, generation,
  *     instance << 8 | stream tag), so every draw depends only on its
  *     coordinates, never on launch shape.
+ *   - Scratch: the evaluation entry points on a design or an objective
+ *     (fitness, objective, relaxation) keep their device scratch with that
+ *     handle between calls, one buffer per stream handle for up to 4
+ *     streams, freed with the handle. Successive
+ *     uses of a buffer are ordered by its stream, and one host lock per
+ *     handle covers a call's enqueueing, so calls from several streams and
+ *     threads are safe. Calls under stream capture, or on a fifth stream,
+ *     take scratch from the stream-ordered allocator of s instead.
  */
 #ifndef QPM_H
 #define QPM_H
@@ -117,7 +125,7 @@ qpm_status qpm_design_read_phases(qpm_design d, double *a, double *b, double *c)
  * bits: device, population-major words (layout above), W x ld uint32.
  * fitness: device, np floats (QPM_PREC_F32) or doubles (QPM_PREC_F64).
  * kernel: a qpm_fit_kernel; QPM_FIT_PER_GENOME needs QPM_PREC_F64.
- * Temporary device memory is taken from the stream-ordered allocator of s.
+ * Device scratch: the segment partials (see Conventions, Scratch).
  * Errors: QPM_EINVAL (np < 1, ld < np or not a multiple of 64, NULL
  * pointer, unknown precision or kernel), QPM_ENOMEM, QPM_EHIP.
  */
@@ -244,8 +252,8 @@ qpm_status qpm_gwo_step(const float *x, int64_t np, int64_t D, int64_t ldx,
  * receive the per-segment prefix and suffix sums the adjoint needs, so that
  * qpm_relax_backward given them skips recomputing the forward pass.
  * prec selects FP32 (per-lane chunks in FP32, everything across lanes and
- * segments in FP64) or FP64. Temporary device memory comes from the
- * stream-ordered allocator of s.
+ * segments in FP64) or FP64. Device scratch: the segment partials (see
+ * Conventions, Scratch).
  * Errors: QPM_EINVAL (NULL design or theta, both outputs NULL, B outside
  * [1, 2^24], ldt < N, unknown precision), QPM_ERANGE, QPM_EHIP.
  */

@@ -37,6 +37,7 @@ def lib():
         L = C.CDLL(path)
         sig = {
             "orc_num_threads": (_INT, []),
+            "orc_set_num_threads": (None, [_INT]),
             "orc_gl_rule": (None, [_INT, _P, _P]),
             "orc_G": (None, [_D, _D, _D, _P]),
             "orc_G_quad": (None, [_D, _D, _D, _P]),
@@ -77,6 +78,11 @@ def lib():
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    """Threads of the oracle's parallel loops from now on (timing only)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def gl_rule(n):

@@ -87,6 +87,17 @@ int orc_num_threads(void)
 #endif
 }
 
+/* threads of the parallel regions that follow (n >= 1); timing only, the
+   results do not depend on it */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* Gauss-Legendre rule on [-1, 1] (Newton iteration on P_n)            */
 /* ------------------------------------------------------------------ */

@@ -43,6 +43,41 @@ qpm_status check_device();
 inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 inline int64_t words_for(int64_t n) { return (n + 31) / 32; }
 
+// ---------------------------------------------------------------- scratch
+
+// Device scratch of an entry point (segment partials and the like) kept
+// with a design or objective between calls instead of being allocated on
+// every call. One buffer per stream, for up to kScratchSlots streams, found
+// by the stream handle: work on one stream runs in order, so successive uses
+// of a buffer never overlap, and the host lock is held from the lookup
+// until the call's work has been enqueued, so threads sharing a stream do
+// not interleave their launches. Calls under stream capture, or on more
+// streams than there are slots, take their scratch from the stream-ordered
+// allocator of their stream instead.
+constexpr int kScratchSlots = 4;
+struct ScratchCache;
+ScratchCache *scratch_cache_create();
+// synchronises the device (when a buffer exists), then frees the buffers
+void scratch_cache_destroy(ScratchCache *c);
+
+class ScratchLease {
+public:
+    ScratchLease(ScratchCache *c, hipStream_t s) : c_(c), s_(s) {}
+    ~ScratchLease() { (void)end(); }
+    ScratchLease(const ScratchLease &) = delete;
+    ScratchLease &operator=(const ScratchLease &) = delete;
+    // *p: at least `bytes` of device memory for work enqueued on s until end()
+    qpm_status begin(size_t bytes, void **p);
+    // after the work that uses the memory has been enqueued on s
+    qpm_status end();
+
+private:
+    ScratchCache *c_;
+    hipStream_t s_;
+    void *owned_ = nullptr;
+    bool locked_ = false;
+};
+
 // ---------------------------------------------------------------- design
 
 struct Design {
@@ -59,6 +94,7 @@ struct Design {
     int device = 0;
     double z0 = 0, zN = 0;    // first and last boundary
     uint64_t zhash = 0;       // FNV-1a of the boundary bytes (designs sharing z)
+    ScratchCache *scratch = nullptr;  // per-call scratch of the entry points on this design
 };
 
 // sign-pattern tables of the 8 W blocks of 4 domains (from ph64)
@@ -149,6 +185,7 @@ struct Objective {
     double scale = 1.0;  // 1 / L or 1 / L^2
     int64_t n = 0, words = 0;
     ObjTabs tabs{};
+    ScratchCache *scratch = nullptr;  // per-call scratch of the evaluation entry points
 };
 
 struct ObjPlan {

@@ -361,18 +361,13 @@ static qpm_status check_fitness_args(qpm_design d, qpm_prec p, const uint32_t *b
 static qpm_status run_plan(qpm_design d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld, void *fitness,
                            const FitPlan &pl, hipStream_t s)
 {
-    const size_t wsb = fitness_workspace_bytes(pl, ld);
-    double *ws = nullptr;
-    if (wsb) QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&ws), wsb, s));
-    qpm_status st = launch_fitness(*d, p, bits, np, ld, fitness, pl, ws, s);
-    if (ws) {
-        hipError_t e = hipFreeAsync(ws, s);
-        if (st == QPM_OK && e != hipSuccess) {
-            set_error("hipFreeAsync failed: %s", hipGetErrorString(e));
-            st = QPM_EHIP;
-        }
-    }
-    return st;
+    ScratchLease lease(d->scratch, s);
+    void *ws = nullptr;
+    qpm_status st = lease.begin(fitness_workspace_bytes(pl, ld), &ws);
+    if (st != QPM_OK) return st;
+    st = launch_fitness(*d, p, bits, np, ld, fitness, pl, static_cast<double *>(ws), s);
+    const qpm_status se = lease.end();
+    return st != QPM_OK ? st : se;
 }
 
 QPM_API qpm_status qpm_eval_fitness(qpm_design d, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,

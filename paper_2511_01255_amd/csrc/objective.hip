@@ -395,6 +395,7 @@ QPM_API qpm_status qpm_objective_create(const qpm_design *designs, int32_t K, in
         o->tabs.C[k][0] = designs[k]->C[0];
         o->tabs.C[k][1] = designs[k]->C[1];
     }
+    o->scratch = scratch_cache_create();
     *out = o;
     return QPM_OK;
 }
@@ -402,6 +403,7 @@ QPM_API qpm_status qpm_objective_create(const qpm_design *designs, int32_t K, in
 QPM_API qpm_status qpm_objective_free(qpm_objective o)
 {
     clear_error();
+    if (o) scratch_cache_destroy(o->scratch);
     delete o;
     return QPM_OK;
 }
@@ -452,10 +454,13 @@ QPM_API qpm_status qpm_eval_objective_shape(qpm_objective o, qpm_prec p, const u
 static qpm_status eval_with_plan(qpm_objective o, qpm_prec p, const uint32_t *bits, int64_t np, int64_t ld,
                                  void *fitness, double *G, int64_t ldG, const ObjPlan &pl, hipStream_t s)
 {
-    double *part = nullptr;
-    QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&part), objective_partials_bytes(*o, pl, ld), s));
-    qpm_status st = launch_objective_partials(*o, p, bits, np, ld, pl, part, s);
+    ScratchLease lease(o->scratch, s);
+    void *ws = nullptr;
+    qpm_status st = lease.begin(objective_partials_bytes(*o, pl, ld), &ws);
+    if (st != QPM_OK) return st;
+    double *part = static_cast<double *>(ws);
+    st = launch_objective_partials(*o, p, bits, np, ld, pl, part, s);
     if (st == QPM_OK) st = launch_objective_values(*o, pl, part, ld, np, fitness, p == QPM_PREC_F64, G, ldG, s);
-    (void)hipFreeAsync(part, s);
-    return st;
+    const qpm_status se = lease.end();
+    return st != QPM_OK ? st : se;
 }

@@ -238,6 +238,7 @@ static void free_design(Design *d)
     (void)hipFree(d->Cdev);
     (void)hipFree(d->tab64);
     (void)hipFree(d->tab32);
+    scratch_cache_destroy(d->scratch);
     delete static_cast<qpm_design_s *>(d);
 }
 
@@ -305,6 +306,8 @@ QPM_API qpm_status qpm_precompute_phases(const double *z, int64_t n, double dk1,
         set_error("phase precompute failed: %s", hipGetErrorString(e));
         return QPM_EHIP;
     }
+    // the per-call scratch cache (without it every call allocates its own)
+    d->scratch = scratch_cache_create();
     *out = d;
     return QPM_OK;
 }

@@ -598,12 +598,15 @@ QPM_API qpm_status qpm_relax_forward(qpm_design d, qpm_prec p, const float *thet
     QPM_REQUIRE(((B + pl.R - 1) / pl.R) * pl.nseg < (int64_t(1) << 31), QPM_ERANGE,
                 "batch x segments too large for one launch");
     const int64_t ldb = ((B + 63) / 64) * 64;
-    double *part = nullptr;
-    QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&part), sizeof(double) * 8 * pl.nseg * ldb, s));
+    ScratchLease lease(d->scratch, s);
+    void *ws = nullptr;
+    st = lease.begin(sizeof(double) * 8 * pl.nseg * ldb, &ws);
+    if (st != QPM_OK) return st;
+    double *part = static_cast<double *>(ws);
     st = relax_partials(*d, p, theta, B, ldt, pl, ldb, part, s);
     if (st == QPM_OK) st = launch_combine(part, pl.nseg, ldb, B, S, f, edges, B, s);
-    (void)hipFreeAsync(part, s);
-    return st;
+    const qpm_status se = lease.end();
+    return st != QPM_OK ? st : se;
 }
 
 QPM_API qpm_status qpm_relax_backward(qpm_design d, qpm_prec p, const float *theta, int64_t B, int64_t ldt,
@@ -620,13 +623,16 @@ QPM_API qpm_status qpm_relax_backward(qpm_design d, qpm_prec p, const float *the
     const RelaxPlan pl = plan_relax(d->n, B, p == QPM_PREC_F32);
     QPM_REQUIRE(((B + pl.R - 1) / pl.R) * pl.nseg < (int64_t(1) << 31), QPM_ERANGE,
                 "batch x segments too large for one launch");
-    double *work = nullptr;
+    ScratchLease lease(d->scratch, s);
     const double *e = edges;
     int64_t lde = B;
     if (!edges) {
         // no saved edges: recompute the segment partials and their edges
         const int64_t ldb = ((B + 63) / 64) * 64;
-        QPM_TRY_HIP(hipMallocAsync(reinterpret_cast<void **>(&work), sizeof(double) * 12 * pl.nseg * ldb, s));
+        void *ws = nullptr;
+        st = lease.begin(sizeof(double) * 12 * pl.nseg * ldb, &ws);
+        if (st != QPM_OK) return st;
+        double *work = static_cast<double *>(ws);
         double *ework = work + static_cast<int64_t>(8) * pl.nseg * ldb;
         st = relax_partials(*d, p, theta, B, ldt, pl, ldb, work, s);
         if (st == QPM_OK) st = launch_combine(work, pl.nseg, ldb, B, nullptr, nullptr, ework, ldb, s);
@@ -646,6 +652,6 @@ QPM_API qpm_status qpm_relax_backward(qpm_design d, qpm_prec p, const float *the
             st = QPM_EHIP;
         }
     }
-    if (work) (void)hipFreeAsync(work, s);
-    return st;
+    const qpm_status se = lease.end();
+    return st != QPM_OK ? st : se;
 }

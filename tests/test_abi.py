@@ -39,6 +39,24 @@ def test_every_declared_symbol_is_exported(L):
         assert hasattr(L, n), n
 
 
+def test_hip_symbol_versions_are_in_the_loaded_runtime():
+    # the library runs inside a process whose HIP runtime is the one torch
+    # ships: every versioned HIP symbol it needs must exist in that runtime
+    import shutil
+    import subprocess
+
+    import torch
+    from paper_2511_01255_amd import qpm
+    rt = os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so")
+    if not (os.path.exists(rt) and shutil.which("nm") and shutil.which("objdump")):
+        pytest.skip("no torch HIP runtime or binutils here")
+    need = set(re.findall(r"@(hip_[0-9.]+)", subprocess.run(
+        ["nm", "-D", "--undefined-only", qpm.LIB_PATH], capture_output=True, text=True, check=True).stdout))
+    have = set(re.findall(r"\b(hip_[0-9.]+)\b", subprocess.run(
+        ["objdump", "-T", rt], capture_output=True, text=True, check=True).stdout))
+    assert need and need <= have, sorted(need - have)
+
+
 def test_status_strings(L):
     for code in range(0, -6, -1):
         assert L.qpm_status_string(code)
