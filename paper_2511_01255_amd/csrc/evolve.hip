@@ -108,21 +108,15 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
     if (reset_cnt != nullptr && b == 0 && threadIdx.x == 0) reset_cnt[0] = 0u;
     __shared__ uint32_t wsh[IPB][WPC];
     extern __shared__ uint32_t sfb[];  // PACKED: (np + 31) / 32 flag words
-    int4 dr[R];
+    // PACKED: per individual of the workgroup, the float offsets from x0 of
+    // its target row, its three donor rows and its output row, and jrand,
+    // worked out once by one lane instead of by every lane of every pass
+    __shared__ uint64_t soff[PACKED ? IPB : 1][5];
+    __shared__ int sjr[PACKED ? IPB : 1];
+    int4 dr[PACKED ? 1 : R];
     bool act[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t i = i0 + r * IPG;
-        act[r] = i < np && j0 < D;
-        // unconditional (clamped) load: no branch, so no wait before the
-        // flag staging below
-        dr[r] = draws[i < np ? i : np - 1];
-    }
-    // the draws' loads are in flight while the flags are staged
-    if constexpr (PACKED) {
-        for (int k = t; k < static_cast<int>((np + 31) / 32); k += 256) sfb[k] = fbits[k];
-        __syncthreads();
-    }
+    for (int r = 0; r < R; ++r) act[r] = i0 + r * IPG < np && j0 < D;
     const uint32_t np32 = static_cast<uint32_t>(np), ldx24 = static_cast<uint32_t>(pv.ldx) & 0xFFFFFFu;
     // PACKED: float offset of row r of buffer (flag of r) ^ flip from x0
     auto packed_row = [&](int64_t r, uint32_t flip) -> uint64_t {
@@ -131,21 +125,46 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
         const uint32_t row = (rr + b * np32) & 0xFFFFFFu;
         return static_cast<uint64_t>(row) * ldx24;
     };
+    if constexpr (PACKED) {
+        // lane t < IPB loads the draws of individual gi IPB + t; the load is
+        // in flight while the flags are staged
+        const int64_t ip = static_cast<int64_t>(gi) * IPB + t;
+        int4 d4 = make_int4(0, 0, 0, 0);
+        if (t < IPB) d4 = draws[ip < np ? ip : np - 1];
+        for (int k = t; k < static_cast<int>((np + 31) / 32); k += 256) sfb[k] = fbits[k];
+        __syncthreads();
+        if (t < IPB && ip < np) {
+            soff[t][0] = packed_row(ip, 0u);
+            soff[t][1] = packed_row(d4.x, 0u);
+            soff[t][2] = packed_row(d4.y, 0u);
+            soff[t][3] = packed_row(d4.z, 0u);
+            soff[t][4] = packed_row(ip, 1u);
+            sjr[t] = d4.w;
+        }
+        __syncthreads();
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t i = i0 + r * IPG;
+            dr[r] = draws[i < np ? i : np - 1];
+        }
+    }
     auto second = [&](int64_t r) -> bool { return pv.flags != nullptr && pv.flags[r] != 0u; };
-    auto src = [&](int64_t r) -> const float * {
-        if constexpr (PACKED)
-            return pv.x0 + packed_row(r, 0u);
-        else
-            return (second(r) ? pv.x1 : pv.x0) + r * pv.ldx;
-    };
+    auto src = [&](int64_t r) -> const float * { return (second(r) ? pv.x1 : pv.x0) + r * pv.ldx; };
     float4 cur[4], nxt[4];
     auto load = [&](int r, float4 *v) {
         if (act[r]) {
-            const int64_t i = i0 + r * IPG;
-            v[0] = *reinterpret_cast<const float4 *>(src(i) + j0);
-            v[1] = *reinterpret_cast<const float4 *>(src(dr[r].x) + j0);
-            v[2] = *reinterpret_cast<const float4 *>(src(dr[r].y) + j0);
-            v[3] = *reinterpret_cast<const float4 *>(src(dr[r].z) + j0);
+            if constexpr (PACKED) {
+                const uint64_t *o = soff[r * IPG + local];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) v[m] = *reinterpret_cast<const float4 *>(pv.x0 + o[m] + j0);
+            } else {
+                const int64_t i = i0 + r * IPG;
+                v[0] = *reinterpret_cast<const float4 *>(src(i) + j0);
+                v[1] = *reinterpret_cast<const float4 *>(src(dr[r].x) + j0);
+                v[2] = *reinterpret_cast<const float4 *>(src(dr[r].y) + j0);
+                v[3] = *reinterpret_cast<const float4 *>(src(dr[r].z) + j0);
+            }
         }
     };
     load(0, cur);
@@ -155,12 +174,17 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
         uint32_t nib = 0;
         if (act[r]) {
             const int64_t i = i0 + r * IPG;
-            const float4 uv = de_quad(cur[0], cur[1], cur[2], cur[3], j0, dr[r].w, static_cast<uint32_t>(i), g, inst,
-                                      k0, k1, Fg, cr_max);
+            int jrand;
+            if constexpr (PACKED)
+                jrand = sjr[r * IPG + local];
+            else
+                jrand = dr[r].w;
+            const float4 uv = de_quad(cur[0], cur[1], cur[2], cur[3], j0, jrand, static_cast<uint32_t>(i), g, inst, k0,
+                                      k1, Fg, cr_max);
             if (store_genes) {
                 float *dst;
                 if constexpr (PACKED)
-                    dst = pv.out0 + packed_row(i, 1u);
+                    dst = pv.out0 + soff[r * IPG + local][4];
                 else
                     dst = (second(i) ? pv.out0 : pv.out1) + i * pv.ldx;
                 store_quad_nt(dst, j0, D, uv);
