@@ -248,30 +248,44 @@ __global__ __launch_bounds__(256) void materialize_kernel(PopView pv, const int4
     __syncthreads();
     const uint32_t g = gen[0];
     const float Fg = F_tab ? F_tab[g] : F;
-    const int64_t n_acc = min(static_cast<int64_t>(cnt[0]), np);
-    const int64_t chunks = (D + 255) / 256;
-    const int xcd = static_cast<int>(blockIdx.x & 7u);
-    const int64_t wg_per_xcd = gridDim.x / 8;  // the grid is a multiple of 8
-    const int64_t my_chunks = chunks > xcd ? (chunks - xcd + 7) / 8 : 0;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // np <= 65536 and D < 2^24 (checked by the launcher), so the item
+    // counts fit 32 bits
+    const uint32_t n_acc = static_cast<uint32_t>(min(static_cast<int64_t>(cnt[0]), np));
+    const uint32_t chunks = static_cast<uint32_t>((D + 255) / 256);
+    const uint32_t xcd = blockIdx.x & 7u;
+    const uint32_t stride = (gridDim.x / 8) * 4;  // the waves of one XCD (the grid is a multiple of 8)
+    const uint32_t my_chunks = chunks > xcd ? (chunks - xcd + 7) / 8 : 0;
+    const int lane = threadIdx.x & 63;
+    // the wave index is the same in all lanes: the item walk below is
+    // scalar, and so are an item's individual, draws and row offsets
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t np32 = static_cast<uint32_t>(np), ldx24 = static_cast<uint32_t>(pv.ldx) & 0xFFFFFFu;
-    auto row = [&](int64_t r, uint32_t flip) -> const float * {
-        const uint32_t rr = static_cast<uint32_t>(r);
-        const uint32_t b = ((sfb[rr >> 5] >> (rr & 31u)) & 1u) ^ flip;
+    auto row = [&](uint32_t rr, uint32_t flip) -> const float * {
+        const uint32_t b = __builtin_amdgcn_readfirstlane((sfb[rr >> 5] >> (rr & 31u)) & 1u) ^ flip;
         return pv.x0 + static_cast<uint64_t>((rr + b * np32) & 0xFFFFFFu) * ldx24;
     };
-    for (int64_t it = static_cast<int64_t>(blockIdx.x >> 3) * 4 + wave; it < n_acc * my_chunks;
-         it += wg_per_xcd * 4) {
-        const int64_t c = xcd + 8 * (it / n_acc);
-        const int64_t i = list[it % n_acc];
-        const int64_t j0 = c * 256 + 4 * lane;
-        if (i < 0 || i >= np || j0 >= D) continue;
+    if (n_acc == 0 || my_chunks == 0) return;
+    // item it = (chunk slot cq, list entry ir) with it = cq n_acc + ir,
+    // stepped by `stride` without a division
+    uint32_t it = (blockIdx.x >> 3) * 4 + wave;
+    uint32_t cq = it / n_acc, ir = it - cq * n_acc;
+    const uint32_t sq = stride / n_acc, sr = stride - sq * n_acc;
+    for (; cq < my_chunks; cq += sq, ir += sr) {
+        if (ir >= n_acc) {
+            ir -= n_acc;
+            ++cq;
+            if (cq >= my_chunks) break;
+        }
+        const int64_t j0 = static_cast<int64_t>(xcd + 8 * cq) * 256 + 4 * lane;
+        const int32_t iv = list[ir];
+        if (iv < 0 || iv >= np || j0 >= D) continue;
+        const uint32_t i = static_cast<uint32_t>(iv);
         const int4 dr = draws[i];
         const float4 xv = *reinterpret_cast<const float4 *>(row(i, 0u) + j0);
-        const float4 a = *reinterpret_cast<const float4 *>(row(dr.x, 0u) + j0);
-        const float4 bq = *reinterpret_cast<const float4 *>(row(dr.y, 0u) + j0);
-        const float4 cq = *reinterpret_cast<const float4 *>(row(dr.z, 0u) + j0);
-        const float4 uv = de_quad(xv, a, bq, cq, j0, dr.w, static_cast<uint32_t>(i), g, inst, k0, k1, Fg, cr_max);
+        const float4 a = *reinterpret_cast<const float4 *>(row(static_cast<uint32_t>(dr.x), 0u) + j0);
+        const float4 bq = *reinterpret_cast<const float4 *>(row(static_cast<uint32_t>(dr.y), 0u) + j0);
+        const float4 cv = *reinterpret_cast<const float4 *>(row(static_cast<uint32_t>(dr.z), 0u) + j0);
+        const float4 uv = de_quad(xv, a, bq, cv, j0, dr.w, i, g, inst, k0, k1, Fg, cr_max);
         store_quad_nt(const_cast<float *>(row(i, 1u)), j0, D, uv);
     }
 }
