@@ -335,27 +335,38 @@ __global__ __launch_bounds__(256) void batch_de_kernel(BatchPop bp, const InstDe
     const uint32_t instb = inst0 + static_cast<uint32_t>(tl.inst);
     __shared__ uint32_t wsh[IPB][WPC];
     __shared__ uint32_t sfb[128];
-    int4 dr[R];
+    // per individual of the workgroup: its target row, three donor rows and
+    // output row, and jrand, worked out once by one lane (lane t < IPB
+    // takes individual gi IPB + t) instead of by every lane of every pass
+    __shared__ const float *srow[IPB][4];
+    __shared__ float *sout[IPB];
+    __shared__ int sjr[IPB];
     bool act[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t i = i0 + r * IPG;
-        act[r] = i < np && j0 < D;
-        dr[r] = draws[static_cast<int64_t>(tl.inst) * np + (i < np ? i : np - 1)];
-    }
+    for (int r = 0; r < R; ++r) act[r] = i0 + r * IPG < np && j0 < D;
+    const int64_t ip = static_cast<int64_t>(gi) * IPB + t;
+    int4 d4 = make_int4(0, 0, 0, 0);
+    if (t < IPB) d4 = draws[static_cast<int64_t>(tl.inst) * np + (ip < np ? ip : np - 1)];
     const int fw = static_cast<int>((np + 31) / 32);
     if (t < fw) sfb[t] = fbits[static_cast<int64_t>(tl.inst) * fw + t];
     __syncthreads();
     auto second = [&](int64_t r) -> bool { return ((sfb[r >> 5] >> (r & 31)) & 1u) != 0u; };
     auto src = [&](int64_t r) -> const float * { return (second(r) ? pv.x1 : pv.x0) + r * pv.ldx; };
+    if (t < IPB && ip < np) {
+        srow[t][0] = src(ip);
+        srow[t][1] = src(d4.x);
+        srow[t][2] = src(d4.y);
+        srow[t][3] = src(d4.z);
+        sout[t] = (second(ip) ? pv.out0 : pv.out1) + ip * pv.ldx;
+        sjr[t] = d4.w;
+    }
+    __syncthreads();
     float4 cur[4], nxt[4];
     auto load = [&](int r, float4 *v) {
         if (act[r]) {
-            const int64_t i = i0 + r * IPG;
-            v[0] = *reinterpret_cast<const float4 *>(src(i) + j0);
-            v[1] = *reinterpret_cast<const float4 *>(src(dr[r].x) + j0);
-            v[2] = *reinterpret_cast<const float4 *>(src(dr[r].y) + j0);
-            v[3] = *reinterpret_cast<const float4 *>(src(dr[r].z) + j0);
+            const float *const *rw = srow[r * IPG + local];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) v[m] = *reinterpret_cast<const float4 *>(rw[m] + j0);
         }
     };
     load(0, cur);
@@ -365,9 +376,9 @@ __global__ __launch_bounds__(256) void batch_de_kernel(BatchPop bp, const InstDe
         uint32_t nib = 0;
         if (act[r]) {
             const int64_t i = i0 + r * IPG;
-            const float4 uv = de_quad(cur[0], cur[1], cur[2], cur[3], j0, dr[r].w, static_cast<uint32_t>(i), g,
-                                      instb, k0, k1, F, cr_max);
-            if (store_genes) store_quad_nt((second(i) ? pv.out0 : pv.out1) + i * pv.ldx, j0, D, uv);
+            const float4 uv = de_quad(cur[0], cur[1], cur[2], cur[3], j0, sjr[r * IPG + local], static_cast<uint32_t>(i),
+                                      g, instb, k0, k1, F, cr_max);
+            if (store_genes) store_quad_nt(sout[r * IPG + local], j0, D, uv);
             nib = quad_nibble(uv, j0, D);
         }
         const uint32_t w = or8_into_last(nib << (4 * (t & 7)));
