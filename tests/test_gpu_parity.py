@@ -448,39 +448,68 @@ def _replay_generation(orc, O, x_pre, g, G, F, CR, seed, L_gpu, tol, variant=0):
     return admissible, near_de
 
 
+def _lockstep_generation(orc, O, R, g, G, F, CR, seed):
+    """Advance R by one generation and check every row of the new state
+    against the oracle's replay from the old one; returns the number of
+    near-tie decisions taken the other way."""
+    npop = R.cfg.np
+    x_pre = R.read()[0].cpu().numpy()
+    R.advance(1)
+    x_post, _, L_gpu, _ = R.read()
+    x_post = x_post.cpu().numpy()
+    adm, near_de = _replay_generation(orc, O, x_pre, g, G, F, CR, seed, L_gpu, TOL[0])
+    Ls = set(L_gpu)
+    adoptions = 0
+    for i in range(npop):
+        ok = False
+        for b2, y, acc, near_g, is_alt in adm:
+            if is_alt and not near_de[i]:
+                continue
+            if i in Ls:
+                cands = [(b2[i], False)]
+            else:
+                cands = [(y[i] if acc[i] else b2[i], False), (b2[i] if acc[i] else y[i], True)]
+            for row, flip in cands:
+                if flip and not near_g[i]:
+                    continue
+                if np.array_equal(row, x_post[i]):
+                    ok = True
+                    adoptions += int(is_alt) + int(flip)
+                    break
+            if ok:
+                break
+        assert ok, "generation %d row %d matches no admissible outcome" % (g, i)
+    return adoptions
+
+
 def test_run_fp32_lockstep(q, orc):
     n, npop, G, F, CR, seed = 1500, 96, 25, 0.5, 0.9, 2
     z = inputs.uniform_boundaries(n, 2.0)
     D = q.precompute_phases(z, DK1, DK2)
     O = orc.Design(z, DK1, DK2)
     R = q.Run(D, npop, G, F=F, CR=CR, seed=seed, prec=0)
-    adoptions = 0
-    for g in range(G):
-        x_pre = R.read()[0].cpu().numpy()
-        R.advance(1)
-        x_post, _, L_gpu, _ = R.read()
-        x_post = x_post.cpu().numpy()
-        adm, near_de = _replay_generation(orc, O, x_pre, g, G, F, CR, seed, L_gpu, TOL[0])
-        for i in range(npop):
-            ok = False
-            for b2, y, acc, near_g, is_alt in adm:
-                if is_alt and not near_de[i]:
-                    continue
-                if i in L_gpu:
-                    cands = [(b2[i], False)]
-                else:
-                    cands = [(y[i] if acc[i] else b2[i], False), (b2[i] if acc[i] else y[i], True)]
-                for row, flip in cands:
-                    if flip and not near_g[i]:
-                        continue
-                    if np.array_equal(row, x_post[i]):
-                        ok = True
-                        adoptions += int(is_alt) + int(flip)
-                        break
-                if ok:
-                    break
-            assert ok, "generation %d row %d matches no admissible outcome" % (g, i)
+    adoptions = sum(_lockstep_generation(orc, O, R, g, G, F, CR, seed) for g in range(G))
     print("FP32 lockstep: %d generations, %d adopted near-tie decisions" % (G, adoptions))
+    R.destroy()
+
+
+def test_full_size_generation_lockstep(q, orc):
+    # the benchmark workload in the benchmark's launch configuration: N =
+    # 10^4 x 2 um, NP = 4096 (4064 iid + 32 periodic genomes with random
+    # magnitudes), FP32 table fitness, tuned shapes, graph replay, trials
+    # kept for the accepted only (chosen at this size); two generations,
+    # every row of each checked against the oracle's replay
+    import torch
+    n, npop, G, F, CR, seed = 10000, 4096, 8, 0.5, 0.9, 0
+    z = inputs.uniform_boundaries(n, 2.0)
+    d = inputs.fitness_population(npop, n, 2.0, 32, seed=1)
+    mag = np.random.default_rng(2).uniform(1e-3, 1.0, size=d.shape).astype(np.float32)
+    D = q.precompute_phases(z, DK1, DK2)
+    O = orc.Design(z, DK1, DK2)
+    R = q.Run(D, npop, G, F=F, CR=CR, seed=seed, prec=0, tune=1)
+    R.load(torch.from_numpy(np.ascontiguousarray(mag * d.astype(np.float32))).cuda())
+    adoptions = sum(_lockstep_generation(orc, O, R, g, G, F, CR, seed) for g in range(2))
+    print("full-size lockstep: 2 generations, %d adopted near-tie decisions" % adoptions)
     R.destroy()
 
 
