@@ -165,5 +165,17 @@ def test_batch_uneven_designs_full_recipe_fitness(q, orc):
         # the initial genes are the oracle's initial population of instance b
         xo = orc.init_pop(npop, len(z) - 1, seed=0, inst=int(b))
         assert np.array_equal(x.cpu().numpy()[pick], xo[pick])
+    best0 = [float(R.read(b)[1].max()) for b in range(64)]
     R.advance(2)
+    # after two generations: every stored fitness is the oracle's fitness of
+    # the stored genes (sampled), and no instance's best decreased
+    for b in range(64):
+        assert float(R.read(b)[1].max()) >= best0[b]
+    for b in rng.choice(64, size=6, replace=False):
+        z, k1, k2 = specs[b]
+        x, f, _, _ = R.read(int(b))
+        pick = rng.choice(npop, size=8, replace=False)
+        _, fo = orc.Design(z, k1, k2).fitness(orc.sign_map(x.cpu().numpy()[pick]))
+        err = np.max(np.abs(f.cpu().numpy()[pick] - fo) / np.maximum(fo, 1e-2 * np.median(fo)))
+        assert err <= 1e-5, (b, err)
     R.destroy()
