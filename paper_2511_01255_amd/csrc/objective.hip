@@ -98,9 +98,20 @@ __global__ __launch_bounds__(256) void obj_partials_kernel(ObjTabs tabs, int K, 
             const uint32_t word = live ? wv[k] : 0u;
             if constexpr (F32) {
                 const float2 *tb = reinterpret_cast<const float2 *>(lds) + wr * 8 * R * 16;
-                float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f, qr = 0.f, qi = 0.f;
+                // the word's first block starts the sums (as appending it to
+                // zeros, up to the sign of a zero, which |.| does not see)
+                const uint32_t p0 = word & 15u;
+                const float2 A0 = tb[p0];
+                float ar = A0.x, ai = A0.y, br = 0.f, bi = 0.f, qr = 0.f, qi = 0.f;
+                if constexpr (THG) {
+                    const float2 B0 = tb[16 + p0], Q0 = tb[32 + p0];
+                    br = B0.x;
+                    bi = B0.y;
+                    qr = Q0.x;
+                    qi = Q0.y;
+                }
 #pragma unroll
-                for (int h = 0; h < 8; ++h) {
+                for (int h = 1; h < 8; ++h) {
                     const uint32_t pt = (word >> (4 * h)) & 15u;
                     const float2 A = tb[(h * R) * 16 + pt];
                     if constexpr (THG) {

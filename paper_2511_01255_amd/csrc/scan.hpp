@@ -213,9 +213,14 @@ __device__ __forceinline__ bool tab_segment(Tri &t, const uint32_t *__restrict__
         const uint32_t word = live ? wv[k] : 0u;
         if constexpr (F32) {
             const float2 *tb = reinterpret_cast<const float2 *>(lds) + wr * 8 * 48;
-            float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f, qr = 0.f, qi = 0.f;
+            // the word's first block starts the sums (the same values as
+            // appending it to zeros, up to the sign of a zero, which |S|^2
+            // does not see); the pattern of block h is bits 4h..4h+3
+            const uint32_t p0 = word & 15u;
+            const float2 A0 = tb[p0], B0 = tb[16 + p0], Q0 = tb[32 + p0];
+            float ar = A0.x, ai = A0.y, br = B0.x, bi = B0.y, qr = Q0.x, qi = Q0.y;
 #pragma unroll
-            for (int h = 0; h < 8; ++h) {
+            for (int h = 1; h < 8; ++h) {
                 const uint32_t pt = (word >> (4 * h)) & 15u;
                 const float2 A = tb[h * 48 + pt], B = tb[h * 48 + 16 + pt], Q = tb[h * 48 + 32 + pt];
                 qr = fmaf(-ai, B.y, fmaf(ar, B.x, qr + Q.x));
