@@ -524,6 +524,18 @@ def test_adaptive_F_branches(orc):
     assert Fm == np.float32(1.2 * mid)
 
 
+def test_adaptive_F_spread_is_the_population_std(orc):
+    # s = std / mean with the population standard deviation: f = 10^5 (1 +
+    # 0.095 z) with z of mean 0 and population variance 1 gives s = 0.095
+    # (< 0.1: factor 1.2), while the sample deviation would give 0.1097
+    # (factor 1); kappa = 0.141 and range 21940 leave the spread to decide
+    z = np.array([1.5, -0.5, -0.5, -0.5]) / np.sqrt(0.75)
+    f = 1e5 * (1.0 + 0.095 * z)
+    t = 0.5
+    mid = 0.1 * (np.cos(0.5 * np.pi * t) + 1.0) / 2.0 * (1.0 - 0.2 * t * t)
+    assert orc.adaptive_F(f, 50, 100) == np.float32(1.2 * mid)
+
+
 def test_adaptive_F_invariants(orc):
     # F stays in [0.01, 0.1]; the decay law falls from 0.1 to 0.04, so the
     # intermediate branch is monotone in g; scaling f by a power of two
@@ -693,6 +705,17 @@ def test_dgwo_leaders_kept_and_states_pm1(orc):
     y = orc.dgwo_step(x, L4, orc.dgwo_params(3, 10), seed=1, g=3)
     assert np.array_equal(y[[2, 0, 3]], x[[2, 0, 3]])
     assert set(np.unique(y[[1, 4, 5, 6, 7]])) <= {-1.0, 1.0}
+
+
+def test_dgwo_zero_gene_is_state_plus(orc):
+    # a leader gene of 0.0 or -0.0 is in state +1 (d = -1 only for x < 0):
+    # with all four leaders at zero, t = 0, no perturbation and no social
+    # learning, p' = n / 4 = 1 and every new gene is +1
+    x = np.zeros((8, 64), np.float32)
+    x[1] = -0.0
+    x[2, ::2] = -0.0
+    y = orc.dgwo_step(x, np.arange(4, dtype=np.int32), np.array([0, 1, 0, 0], np.float32), seed=6, g=0)
+    assert np.all(y[3:] == 1.0)
 
 
 def _freq(y, n, cls):
