@@ -543,3 +543,50 @@ def test_run_tuned_equals_untuned_fp64(q):
         R.destroy()
     assert np.array_equal(outs[0][0], outs[1][0])
     assert np.max(np.abs(outs[0][1] - outs[1][1]) / outs[0][1]) <= 1e-13
+
+
+# ------------------------------------------------------------------ random shapes
+
+def _random_shapes(seed, count, n_max, np_max, np_min=1):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.integers(1, n_max + 1))
+        npop = int(rng.integers(np_min, np_max + 1))
+        out.append((n, npop, int(rng.integers(0, 1 << 30))))
+    return out
+
+
+@pytest.mark.parametrize("n,npop,s", _random_shapes(101, 12, 4000, 700), ids=lambda v: str(v))
+def test_random_shapes_fitness_every_kernel(q, orc, n, npop, s):
+    # seeded random sizes (ragged words, populations, jittered widths):
+    # every kernel and precision within its tolerance of the oracle
+    z = inputs.jittered_boundaries(n, 2.0, 0.3, seed=s % 1000)
+    d = inputs.random_signs(npop, n, seed=s)
+    D = q.precompute_phases(z, DK1, DK2)
+    _, fo = orc.Design(z, DK1, DK2).fitness(d)
+    bits = _bits(d)
+    for prec, kernel in ((0, q.FIT_TABLE), (1, q.FIT_TABLE), (0, q.FIT_SEGMENTED), (1, q.FIT_SEGMENTED),
+                         (1, q.FIT_PER_GENOME)):
+        f = q.eval_fitness(D, bits, npop, prec=prec, kernel=kernel).double().cpu().numpy()
+        assert _rel_err(f, fo).max() <= TOL[prec], (prec, kernel)
+
+
+@pytest.mark.parametrize("D,np_,s", _random_shapes(202, 10, 3000, 300, np_min=4), ids=lambda v: str(v))
+def test_random_shapes_de_and_gwo_bit_exact(q, orc, D, np_, s):
+    import torch
+    x, _ = q.init_population(np_, D, seed=s % 97)
+    xh = _host(x, D)
+    g = s % 50
+    u, ub = q.de_step(x, D, 0.5, 0.9, seed=s, generation=g, inst=s % 5)
+    uo, _ = orc.de_step(xh, 0.5, 0.9, seed=s, g=g, inst=s % 5)
+    assert np.array_equal(_host(u, D), uo)
+    assert np.array_equal(inputs.unpack_bits(ub.cpu().numpy(), np_, D), orc.sign_map(uo))
+    L = np.random.default_rng(s).choice(np_, size=3, replace=False).astype(np.int32)
+    a = float(np.float32(2.0 * (1.0 - g / 50.0)))
+    for variant in (0, 1):
+        y, yb = q.gwo_step(x, D, torch.from_numpy(L).cuda(), a, seed=s, generation=g, inst=s % 5, variant=variant)
+        yo = orc.gwo_step(xh, L, a, seed=s, g=g, inst=s % 5, variant=variant)
+        assert np.array_equal(_host(y, D), yo)
+        keep = np.setdiff1d(np.arange(np_), L)
+        assert np.array_equal(inputs.unpack_bits(yb.cpu().numpy(), np_, D)[keep], orc.sign_map(yo)[keep])
