@@ -159,3 +159,26 @@ def test_objective_run_reduces_to_the_single_design_run(q):
         q.Run(q.Objective([D], q.OBJ_THG), npop, G, control=2)
     R1.destroy()
     R2.destroy()
+
+
+def _random_cases(seed, count):
+    rng = np.random.default_rng(seed)
+    return [(int(rng.integers(1, 3000)), int(rng.integers(1, 400)), int(rng.integers(1, 9)), int(rng.integers(0, 2)),
+             int(rng.integers(0, 1 << 30))) for _ in range(count)]
+
+
+@pytest.mark.parametrize("n,npop,K,kind,s", _random_cases(303, 10), ids=lambda v: str(v))
+def test_objective_random_shapes(q, orc, n, npop, K, kind, s):
+    # seeded random sizes, wavelength counts and kinds, both precisions
+    z = inputs.jittered_boundaries(n, 2.0, 0.3, seed=s % 1000)
+    G0, beta = 0.3 + (s % 7) / 10.0, (s % 5) / 2.0
+    O, Oo = _pair(q, orc, z, K, kind, G0, beta)
+    d = inputs.random_signs(npop, n, seed=s)
+    Go, fo = Oo(d)
+    bits = _bits(d)
+    for prec, tol in ((1, 1e-12), (0, 1e-5)):
+        f, G = q.eval_objective(O, bits, npop, prec, with_G=True)
+        G = G.cpu().numpy().T
+        scale = np.maximum(np.max(np.abs(Go), axis=0, keepdims=True), 1e-300)
+        assert np.max(np.abs(G - Go) / scale) <= tol
+        assert np.max(np.abs(f.double().cpu().numpy() - fo)) <= tol * max(1.0, np.max(np.abs(fo)))
