@@ -46,9 +46,10 @@ F, CR, SEED = 0.5, 0.9, 0
 # Philox4x32-10 at 0.75 calls per gene x 10 rounds x (2 v_mad_u64_u32 +
 # 2 three-input xors) = 30; per leader two 16-bit conversions, A (1 FMA),
 # C X_k (multiply + FMA), Y_k (1 FMA) = 6, x 3 = 18; the combination: |Y|
-# sum (2), numerator (3), the IEEE division sequence (9), x / 3 (4), zero
-# test (2), clamp (1), sign bit (1) = 22.
-GWO_INSTR_PER_GENE = 30 + 18 + 22
+# sum (2), numerator (3), the division's short form for weights in range
+# (reciprocal and 7 FMA / multiply), x / 3 (3), range test (1), clamp (1),
+# sign bit (1) = 19.
+GWO_INSTR_PER_GENE = 30 + 18 + 19
 
 
 def algorithmic_work(step, npop, n):

@@ -41,6 +41,34 @@ __device__ __forceinline__ float div3(float x)
     return copysignf(fmaf(r, c, q0), x);
 }
 
+// div3 for x != 0: the same three steps without the sign restore (checked
+// against IEEE division for every nonzero finite binary32 input)
+__device__ __forceinline__ float div3_nonzero(float x)
+{
+    const float c = 0x1.555556p-2f;
+    const float q0 = x * c;
+    const float r = fmaf(-q0, 3.0f, x);
+    return fmaf(r, c, q0);
+}
+
+// n / d correctly rounded for d in [2^-60, 2^60] and |n| in [2^-60, 2^60]:
+// the IEEE single-precision division sequence (reciprocal, one Newton step,
+// quotient, two FMA remainder corrections) without its scaling and fix-up
+// steps, which leave every operand and result unchanged in this range (no
+// operand or quotient near the subnormal or overflow range, exponent gap
+// far below 96, no special value), so the result is that of n / d.
+__device__ __forceinline__ float div_in_range(float n, float d)
+{
+    const float r = __builtin_amdgcn_rcpf(d);
+    const float e = fmaf(-d, r, 1.0f);
+    const float r1 = fmaf(e, r, r);
+    const float q = n * r1;
+    const float rem = fmaf(-d, q, n);
+    const float q1 = fmaf(rem, r1, q);
+    const float rem2 = fmaf(-d, q1, n);
+    return fmaf(rem2, r1, q1);
+}
+
 __device__ __forceinline__ void store_quad(float *dst, int64_t j0, int64_t D, float4 v)
 {
     if (j0 + 3 < D) {
@@ -141,7 +169,7 @@ __device__ __forceinline__ float4 gwo_quad(float4 xv, float4 X0, float4 X1, floa
     const uint32_t wrd[12] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w, wc.x, wc.y, wc.z, wc.w};
     const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
     const float Xs[3][4] = {{X0.x, X0.y, X0.z, X0.w}, {X1.x, X1.y, X1.z, X1.w}, {X2.x, X2.y, X2.z, X2.w}};
-    float ys[4];
+    float ys[4], ss[4], ns[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         float Y[3];
@@ -156,18 +184,33 @@ __device__ __forceinline__ float4 gwo_quad(float4 xv, float4 X0, float4 X1, floa
             const float Dk = fabsf(fmaf(Cc, Xs[k][e], -xs[e]));
             Y[k] = fmaf(-A, Dk, Xs[k][e]);
         }
-        float yv;
         if constexpr (VARIANT == 1) {
-            yv = div3((Y[0] + Y[1]) + Y[2]);
+            ys[e] = clamp1(div3((Y[0] + Y[1]) + Y[2]));
         } else {
-            const float s = (fabsf(Y[0]) + fabsf(Y[1])) + fabsf(Y[2]);
-            const float num = fmaf(fabsf(Y[2]), Y[2], fmaf(fabsf(Y[1]), Y[1], fabsf(Y[0]) * Y[0]));
-            // evaluated unconditionally (no divergent branch); the 0/0 of
-            // s == 0 is selected away
-            const float qv = div3(num / s);
-            yv = (s == 0.0f) ? 0.0f : qv;
+            ss[e] = (fabsf(Y[0]) + fabsf(Y[1])) + fabsf(Y[2]);
+            ns[e] = fmaf(fabsf(Y[2]), Y[2], fmaf(fabsf(Y[1]), Y[1], fabsf(Y[0]) * Y[0]));
         }
-        ys[e] = clamp1(yv);
+    }
+    if constexpr (VARIANT == 0) {
+        // |Y| <= 7, so s <= 21 and |num| <= 147: when every s and |num| of
+        // the wave's quads is >= 2^-60, the division takes its short form
+        // and, the quotient being nonzero, x / 3 needs no sign restore and
+        // s == 0 cannot occur. Otherwise (tiny or zero weights) the full
+        // IEEE division and the s == 0 case.
+        const float lo = fminf(fminf(fminf(ss[0], fabsf(ns[0])), fminf(ss[1], fabsf(ns[1]))),
+                               fminf(fminf(ss[2], fabsf(ns[2])), fminf(ss[3], fabsf(ns[3]))));
+        if (__all(lo >= 0x1p-60f)) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ys[e] = clamp1(div3_nonzero(div_in_range(ns[e], ss[e])));
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                // evaluated unconditionally (no divergent branch); the 0/0
+                // of s == 0 is selected away
+                const float qv = div3(ns[e] / ss[e]);
+                ys[e] = clamp1(ss[e] == 0.0f ? 0.0f : qv);
+            }
+        }
     }
     return make_float4(ys[0], ys[1], ys[2], ys[3]);
 }
