@@ -298,12 +298,25 @@ def main():
         R3.advance(20)
         ms3, ng3 = R3.timing()
         R3.destroy()
+        # the whole 5000-generation run from a fresh initial population
+        # (creation, tuning and initial evaluation outside the clock)
+        R4 = qpm.Run(design, 1024, 5000, F=F, CR=CR, seed=0, prec=qpm.PREC_F32, tune=1)
+        f_init = float(R4.read()[1].max())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R4.advance(5000)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter() - t0
+        f_end = float(R4.read()[1].max())
+        R4.destroy()
         out["hwsda_np1024"] = {
             "generations_per_s": 1.0 / t3, "ms_per_generation": t3 * 1e3,
             "domain_evals_per_s": (2 * 1024 - 3) * N_DOMAINS / t3,
             "kernel_ms": {k: v / ng3 for k, v in ms3.items()},
+            "full_run_5000_generations_seconds": t4,
+            "best_fitness_initial_and_final": [f_init, f_end],
         }
-        log("[bench] NP=1024 run: %.1f generations/s" % (1.0 / t3))
+        log("[bench] NP=1024 run: %.1f generations/s; 5000 generations in %.3f s" % (1.0 / t3, t4))
 
         # the same run under the paper's parameter control: F = a from 0.1 to
         # 0.01, the adaptive F (one extra one-workgroup statistics kernel per
@@ -341,6 +354,14 @@ def main():
         BR.advance(3)
         bms, bng = BR.timing()
         BR.destroy()
+        # the whole 500-generation batched run
+        BR = qpm.BatchRun(B, 256, 500, F=F, CR=CR, seed=SEED, prec=prec, tune=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        BR.advance(500)
+        torch.cuda.synchronize()
+        tb500 = time.perf_counter() - t0
+        BR.destroy()
         del B
         t_bfit = 0.5 * (bms["fitness_de"] + bms["fitness_gwo"]) / bng * 1e-3
         brate = 256 * total_n / t_bfit
@@ -349,6 +370,7 @@ def main():
             "ms_per_generation": tb * 1e3, "generations_per_s": 1.0 / tb,
             "domain_evals_per_s": (2 * 256 - 3) * total_n / tb,
             "kernel_ms": {k: v / bng for k, v in bms.items()},
+            "full_run_500_generations_seconds": tb500,
             # one batched FP32 table-fitness pass: 10 algorithmic flops per
             # domain evaluation against the packed and the non-packed peak
             "fitness_pass": {"us": t_bfit * 1e6, "domain_evals_per_s": brate, "alg_tflops": 10 * brate / 1e12,
