@@ -1,7 +1,8 @@
 /* Exhaustive check of the division-free x / 3 used by the grey-wolf kernel:
  * for every finite binary32 x, copysign(fma(fma(-q0, 3, x), c, q0), x) with
- * q0 = x * c and c = RN(1/3) equals the IEEE quotient x / 3 bit for bit.
- * Prints the number of mismatches. */
+ * q0 = x * c and c = RN(1/3) equals the IEEE quotient x / 3 bit for bit,
+ * and so does fma(fma(-q0, 3, x), c, q0) without the copysign for every
+ * x != 0. Prints the number of mismatches. */
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -21,10 +22,13 @@ int main(void)
         float q0 = x * c;
         float r = fmaf(-q0, 3.0f, x);
         float q = copysignf(fmaf(r, c, q0), x);
-        uint32_t a, d;
+        float q2 = fmaf(r, c, q0);
+        uint32_t a, d, d2;
         memcpy(&a, &ref, 4);
         memcpy(&d, &q, 4);
+        memcpy(&d2, &q2, 4);
         if (a != d) ++bad;
+        if (x != 0.0f && a != d2) ++bad;
     }
     printf("%llu\n", bad);
     return 0;
