@@ -224,7 +224,18 @@ def main():
     roof["kernel_ms"] = per[dom]
     out["roofline"] = roof
 
-    if not args.no_extras:
+    def guarded(name, fn):
+        # an extra measurement that fails is reported and leaves the
+        # headline line intact
+        try:
+            fn()
+        except Exception as e:
+            import traceback
+            traceback.print_exc()
+            log("[bench] %s failed: %r" % (name, e))
+            out.setdefault("errors", {})[name] = repr(e)
+
+    def _extra_fitness_kernels():
         # the same generation with each fitness kernel and precision:
         # generations/s (graph replay) and the evaluation step's kernel time
         # inside the run (HIP events around the step, eager launches)
@@ -285,6 +296,9 @@ def main():
         out["fitness_throughput_np4096_n10000"] = thr
 
     if not args.no_extras:
+        guarded('fitness kernels', _extra_fitness_kernels)
+
+    def _extra_runs():
         # full HWSDA at NP = 1024 on the same design (G = 5000 schedule,
         # seed 0, FP32 fitness): generations/s and the per-kernel split
         R3 = qpm.Run(design, 1024, 5000, F=F, CR=CR, seed=0, prec=qpm.PREC_F32, tune=1)
@@ -437,6 +451,9 @@ def main():
         log("[bench] plain N=256 NP=32 G=200: %s" % plain)
 
     if not args.no_extras:
+        guarded('runs and workloads', _extra_runs)
+
+    def _extra_paper_and_objectives():
         # a run shaped like the paper's timing table (N = 6600 domains of
         # 0.1 um, L = 660 um, NP = 5000, G = 1000), with this workload's dk:
         # seconds for the whole run, next to the paper's RTX 4070 figure
@@ -488,7 +505,10 @@ def main():
         out["multi_wavelength_objective"] = multi
         log("[bench] multi-wavelength objective: %s" % multi)
 
-    if args.cpu_generations > 0:
+    if not args.no_extras:
+        guarded('paper-shaped run and objectives', _extra_paper_and_objectives)
+
+    def _cpu_leg():
         import oracle as orc
         # fitness error of the GPU kernels against the oracle on the
         # benchmark population (max relative error per genome class)
@@ -563,6 +583,9 @@ def main():
                 "domain_evals_per_s_all_threads": one[max(one)], "threads": max(one),
                 "domain_evals_per_s_one_thread": one[1]}
             out["oracle_plain_fp64_n256_np32_g200"]["generations_per_s_one_thread"] = plain1
+
+    if args.cpu_generations > 0:
+        guarded('cpu leg', _cpu_leg)
     print(json.dumps(out), flush=True)
 
 
