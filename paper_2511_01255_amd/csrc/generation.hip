@@ -27,7 +27,8 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ 
                                                      const int32_t *__restrict__ skip3, T *__restrict__ cand_v,
                                                      int32_t *__restrict__ cand_i, int4 *__restrict__ draws_next,
                                                      const uint32_t *__restrict__ gen, int64_t D, uint32_t k0,
-                                                     uint32_t k1, uint32_t inst, AcceptOut acc, uint32_t next_off)
+                                                     uint32_t k1, uint32_t inst, AcceptOut acc, uint32_t next_off,
+                                                     int32_t *__restrict__ top3_direct)
 {
     const int lane = threadIdx.x & 63;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + lane;
@@ -36,6 +37,12 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ 
         const double sr = t.qr + C[0], si = t.qi + C[1];
         select_group<T>(fma(sr, sr, si * si), blockIdx.x, lane, np, f_cur, flags, fbits, skip3, cand_v, cand_i,
                         draws_next, gen, D, k0, k1, inst, acc, next_off);
+    }
+    // a one-workgroup population (np <= 64): the leaders from its own three
+    // candidates, as the tail kernel would take them, without that launch
+    if (top3_direct != nullptr) {
+        __syncthreads();
+        block_top3<T, 256>(cand_v, 3, top3_direct, cand_i);
     }
 }
 
@@ -134,20 +141,24 @@ qpm_status launch_finish(const double *part, int gy, int64_t ld, int64_t np, con
     const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
     const int advance = draws_next != nullptr && !mode.gen_advanced;
     const uint32_t next_off = mode.gen_advanced ? 0u : 1u;
-    const bool tail = (top3_out != nullptr && !mode.defer_leaders) || advance;
-    int32_t *tail_top3 = mode.defer_leaders ? nullptr : top3_out;
+    // one workgroup: it merges its own candidates into the leaders
+    int32_t *direct = blocks == 1 && !mode.defer_leaders ? top3_out : nullptr;
+    const bool tail = (top3_out != nullptr && !mode.defer_leaders && direct == nullptr) || advance;
+    int32_t *tail_top3 = mode.defer_leaders || direct != nullptr ? nullptr : top3_out;
     // cand: 3 values per workgroup (T) followed by 3 slots per workgroup (int32)
     if (f64) {
         double *cv = top3_out ? static_cast<double *>(cand) : nullptr;
         int32_t *ci = cv ? reinterpret_cast<int32_t *>(cv + 3 * static_cast<size_t>(blocks)) : nullptr;
         finish_kernel<double><<<blocks, 256, 0, s>>>(part, gy, ld, np, C, static_cast<double *>(f_cur), flags, fbits,
-                                                     skip3, cv, ci, draws_next, gen, D, k0, k1, inst, acc, next_off);
+                                                     skip3, cv, ci, draws_next, gen, D, k0, k1, inst, acc, next_off,
+                                                     direct);
         if (tail) finish_tail_kernel<double><<<1, 256, 0, s>>>(cv, ci, blocks, tail_top3, gen, advance);
     } else {
         float *cv = top3_out ? static_cast<float *>(cand) : nullptr;
         int32_t *ci = cv ? reinterpret_cast<int32_t *>(cv + 3 * static_cast<size_t>(blocks)) : nullptr;
         finish_kernel<float><<<blocks, 256, 0, s>>>(part, gy, ld, np, C, static_cast<float *>(f_cur), flags, fbits,
-                                                    skip3, cv, ci, draws_next, gen, D, k0, k1, inst, acc, next_off);
+                                                    skip3, cv, ci, draws_next, gen, D, k0, k1, inst, acc, next_off,
+                                                    direct);
         if (tail) finish_tail_kernel<float><<<1, 256, 0, s>>>(cv, ci, blocks, tail_top3, gen, advance);
     }
     QPM_TRY_HIP(hipGetLastError());
