@@ -349,8 +349,8 @@ typedef struct {
 
 /*
  * Trial storage of a run's DE step (results are identical; speed differs):
- *   QPM_TRIALS_AUTO      ACCEPTED when the two gene buffers exceed 256 MB
- *                        (the last-level cache) and np <= 65536, else STORE;
+ *   QPM_TRIALS_AUTO      ACCEPTED when the two gene buffers exceed 64 MB
+ *                        and np <= 65536, else STORE;
  *   QPM_TRIALS_STORE     every trial's genes are written, selection keeps
  *                        or drops them;
  *   QPM_TRIALS_ACCEPTED  the DE step writes the trials' bits only; after

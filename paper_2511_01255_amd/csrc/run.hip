@@ -441,11 +441,13 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
     r->ld = ((c.np + 63) / 64) * 64;
     r->W = d->words;
     // trials are materialised only for the accepted ones when the two gene
-    // buffers exceed the 256 MB last-level cache (MALL): then every stored
-    // trial costs HBM write bandwidth, while recomputing an accepted one
-    // reads four rows; a smaller population absorbs the trial writes in
-    // the MALL and stores them all (measured: N = 10^4, NP = 4096 gains
-    // about 6 % per generation, NP = 1024 would lose about 3 %)
+    // buffers are large: every stored trial costs write bandwidth (HBM once
+    // the population spills the 256 MB last-level cache), while
+    // recomputing an accepted one
+    // reads four rows; below about 64 MB of population (both buffers) the
+    // stored trials cost less (measured, whole runs: 82-329 MB populations
+    // gain 4-6 % with accepted-only trials, 16-33 MB ones lose 2-6 %, 41 MB
+    // is even)
     const bool lazy_ok = c.np <= 65536 && r->ldx < (int64_t(1) << 24);
     if (c.trials == QPM_TRIALS_ACCEPTED && !lazy_ok) {
         set_error("materialising accepted trials needs np <= 65536");
@@ -454,7 +456,7 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
     }
     r->lazy = c.trials == QPM_TRIALS_ACCEPTED ||
               (c.trials == QPM_TRIALS_AUTO && lazy_ok &&
-               2 * static_cast<int64_t>(sizeof(float)) * c.np * r->ldx > (int64_t(256) << 20));
+               2 * static_cast<int64_t>(sizeof(float)) * c.np * r->ldx > (int64_t(64) << 20));
     r->plan = plan_fitness(*d, static_cast<qpm_prec>(c.prec), c.np, c.fit_kernel);
     if (obj) r->oplan = plan_objective(*obj, static_cast<qpm_prec>(c.prec), c.np);
     const size_t es = r->f64() ? sizeof(double) : sizeof(float);
