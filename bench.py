@@ -379,19 +379,23 @@ def main():
         del B
         t_bfit = 0.5 * (bms["fitness_de"] + bms["fitness_gwo"]) / bng * 1e-3
         brate = 256 * total_n / t_bfit
+        tavg = tb500 / 500
         out["batched_designs"] = {
             "instances": 64, "np": 256, "total_domains": total_n,
-            "ms_per_generation": tb * 1e3, "generations_per_s": 1.0 / tb,
-            "domain_evals_per_s": (2 * 256 - 3) * total_n / tb,
-            "kernel_ms": {k: v / bng for k, v in bms.items()},
+            # the whole 500-generation run (its average generation), and
+            # generations 2-11 alone (early: most trials accepted)
+            "ms_per_generation": tavg * 1e3, "generations_per_s": 1.0 / tavg,
+            "domain_evals_per_s": (2 * 256 - 3) * total_n / tavg,
             "full_run_500_generations_seconds": tb500,
+            "ms_per_generation_generations_2_to_11": tb * 1e3,
+            "kernel_ms_generations_12_to_14": {k: v / bng for k, v in bms.items()},
             # one batched FP32 table-fitness pass: 10 algorithmic flops per
             # domain evaluation against the packed and the non-packed peak
             "fitness_pass": {"us": t_bfit * 1e6, "domain_evals_per_s": brate, "alg_tflops": 10 * brate / 1e12,
                              "alg_frac_of_vector_peak": 10 * brate / 1e12 / PEAK_FP32_TFLOPS,
                              "alg_frac_of_nonpacked_fp32_peak": 10 * brate / 1e12 / PEAK_FP32_NONPACKED_TFLOPS},
         }
-        log("[bench] batched designs: %.2f ms/generation" % (tb * 1e3))
+        log("[bench] batched designs: %.2f ms/generation over 500 generations (%.2f early)" % (tavg * 1e3, tb * 1e3))
         # relaxation forward + adjoint: batch 256, N = 50,000 x 2 um
         zr = inputs.uniform_boundaries(50000, 2.0)
         Dr = qpm.precompute_phases(zr, inputs.DK1, inputs.DK2)

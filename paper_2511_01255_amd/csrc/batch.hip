@@ -1177,12 +1177,18 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
             for (int64_t ch = 0; ch * cw < h[i].n; ++ch) dt[v].push_back(Tile{i, static_cast<int>(ch)});
         }
     }
-    // accepted-only trials on request only: recomputing an accepted trial
-    // reads 20 B per gene against 4 B per gene for storing every trial, so
-    // they pay below about 20 % acceptance; the 64-design workload (NP =
-    // 256) measured 2.13 ms per generation with them against 2.03 ms
-    r->lazy = c.trials == QPM_TRIALS_ACCEPTED;
-    if (n_inst * c.np >= (int64_t(1) << 31)) {  // list entries are int32 instance * np + slot
+    // accepted-only trials: recomputing an accepted trial reads 20 B per
+    // gene against 4 B per gene for storing every trial, so they pay below
+    // about 20 % acceptance and for large populations; chosen automatically,
+    // as for single runs, above 64 MB for both gene buffers (the 64-design
+    // workload, NP = 256, 1.7 GB: a whole 500-generation run 0.909 s against
+    // 0.946 s storing every trial)
+    int64_t total_n = 0;
+    for (const auto &d : h) total_n += d.n;
+    r->lazy = c.trials == QPM_TRIALS_ACCEPTED ||
+              (c.trials == QPM_TRIALS_AUTO && 2 * static_cast<int64_t>(sizeof(float)) * c.np * total_n >
+                                                  (int64_t(64) << 20));
+    if (r->lazy && n_inst * c.np >= (int64_t(1) << 31)) {  // list entries are int32 instance * np + slot
         if (c.trials == QPM_TRIALS_ACCEPTED) {
             set_error("accepted-only trials need n_inst * np < 2^31");
             release_batch_run(r);
