@@ -165,3 +165,27 @@ def test_run_polish_of_leaders(q, prec):
         results.append((x1, f1, acc))
         R.destroy()
     assert np.array_equal(results[0][0], results[1][0]) and results[0][2] == results[1][2]
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_run_polish_then_continue_same_for_both_trial_storages(q, orc, prec):
+    # a polish changes leader rows (and so the buffer flags the DE step
+    # reads); the run that continues afterwards must take the same decisions
+    # whether it stores every trial or only the accepted ones, and every
+    # stored fitness must be the oracle's fitness of the stored genes
+    n, npop = 1500, 96
+    z = inputs.uniform_boundaries(n, 2.0)
+    D = q.precompute_phases(z, DK1, DK2)
+    out = []
+    for trials in (q.TRIALS_STORE, q.TRIALS_ACCEPTED):
+        R = q.Run(D, npop, 12, seed=5, prec=prec, trials=trials)
+        R.advance(4)
+        R.polish(20, 0.05)
+        R.advance(5)
+        x, f, L, _ = R.read()
+        out.append((x.cpu().numpy(), f.double().cpu().numpy(), L))
+        R.destroy()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1]) and out[0][2] == out[1][2]
+    _, fo = orc.Design(z, DK1, DK2).fitness(orc.sign_map(out[0][0]))
+    tol = 1e-12 if prec == 1 else 1e-5
+    assert np.max(np.abs(out[0][1] - fo) / np.maximum(fo, 1e-2 * np.median(fo))) <= tol
