@@ -67,6 +67,10 @@ def lib():
             "orc_hwsda_run_obj": (_INT, [_P, _INT, _INT, _D, _D, _I64, _I64, _F, _F, _U64, _U32, _INT, _INT, _P,
                                          _P, _P, _P]),
             "orc_adaptive_F": (_F, [_P, _I64, _I64, _I64]),
+            "orc_run_algo": (_INT, [_P, _I64, _I64, _F, _F, _U64, _U32, _INT, _INT, _INT, _P, _P, _P, _P]),
+            "orc_run_obj_algo": (_INT, [_P, _INT, _INT, _D, _D, _I64, _I64, _F, _F, _U64, _U32, _INT, _INT, _INT,
+                                        _P, _P, _P, _P]),
+            "orc_polish": (None, [_P, _P, _I64, _P, _INT, _D, _P, _P, _P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -159,6 +163,32 @@ class Design:
         lib().orc_relax(self._h, _ptr(theta), B, _ptr(S), _ptr(f), _ptr(g))
         return S[0::2] + 1j * S[1::2], f, g
 
+    def run_algo(self, np_, G, F, CR, seed, algo, inst=0, variant=0, control=0):
+        """The loop with algo 0 (HWSDA), 1 (DE alone) or 2 (GWO alone) ->
+        (x, f, best trace, (G, 2) float32 rows (F_g, a_g))."""
+        x = np.zeros((np_, self.n), dtype=np.float32)
+        f = np.zeros(np_)
+        tr = np.zeros(G)
+        par = np.zeros((G, 2), dtype=np.float32)
+        rc = lib().orc_run_algo(self._h, np_, G, F, CR, seed, inst, variant, control, algo, _ptr(x), _ptr(f),
+                                _ptr(tr), _ptr(par))
+        if rc != 0:
+            raise ValueError("invalid run arguments")
+        return x, f, tr, par
+
+    def polish(self, x, f0, steps=20, eta=0.05):
+        """Gradient polish of gene rows x (rows, n) float32 whose exact
+        fitness is f0 -> (theta (rows, n) float64, f1 (rows,), accept
+        (rows,) bool)."""
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, self.n)
+        rows = x.shape[0]
+        f0 = np.ascontiguousarray(f0, dtype=np.float64).reshape(rows)
+        th = np.zeros((rows, self.n))
+        f1 = np.zeros(rows)
+        acc = np.zeros(rows, dtype=np.int32)
+        lib().orc_polish(self._h, _ptr(x), rows, _ptr(f0), int(steps), float(eta), _ptr(th), _ptr(f1), _ptr(acc))
+        return th, f1, acc.astype(bool)
+
     def hwsda_run(self, np_, G, F, CR, seed, inst=0, variant=0, trace=True, control=None):
         """control None: the plain entry point (textbook parameters);
         0, 1, 2: the parameter control, returning also (G, 2) float32 rows
@@ -202,13 +232,13 @@ class Objective:
             raise ValueError("designs differ in their boundaries, or bad arguments")
         return G, f
 
-    def hwsda_run(self, np_, G, F, CR, seed, inst=0, variant=0, control=0):
+    def hwsda_run(self, np_, G, F, CR, seed, inst=0, variant=0, control=0, algo=0):
         x = np.zeros((np_, self.n), dtype=np.float32)
         f = np.zeros(np_)
         tr = np.zeros(G)
         par = np.zeros((G, 2), dtype=np.float32)
-        rc = lib().orc_hwsda_run_obj(self._arr, self.K, self.kind, self.G0, self.beta, np_, G, F, CR, seed, inst,
-                                     variant, control, _ptr(x), _ptr(f), _ptr(tr), _ptr(par))
+        rc = lib().orc_run_obj_algo(self._arr, self.K, self.kind, self.G0, self.beta, np_, G, F, CR, seed, inst,
+                                    variant, control, algo, _ptr(x), _ptr(f), _ptr(tr), _ptr(par))
         if rc != 0:
             raise ValueError("invalid run arguments")
         return x, f, tr, par

@@ -40,9 +40,21 @@
  * Optimiser (paper Sec. 2.2.1 DE, Sec. 2.2.2 GWO, Sec. 3.2 HWSDA steps):
  * see the comments at each function.
  *
- * Parity unpinned: orc_dgwo_step, the improved discrete four-leader GWO of
- * Sec. 3.1.2, which the paper gives in prose only; it implements a stated
- * reading and its tests pin the reading, not the paper. Random numbers come from
+ * Parity unpinned (against the paper):
+ *   orc_dgwo_step, the improved discrete four-leader GWO of Sec. 3.1.2,
+ *   which the paper gives in prose only; it implements a stated reading and
+ *   its tests pin the reading, not the paper.
+ *   orc_adaptive_F, the adaptive F of Sec. 3.1.1: the paper names its
+ *   inputs (standard deviation, fitness range, convergence rate, progress),
+ *   the range threshold 10^3, the convergence threshold 0.1, the cosine law
+ *   and a quadratic coefficient from 1.0 to 0.8, but not the spread
+ *   threshold 0.5, the factors 1.2 and 0.8, the scaling of the cosine law by
+ *   0.1, or how s (std / mean) and kappa ((max - mean) / max) are defined;
+ *   those are this oracle's readings, pinned by their own branches only.
+ *   orc_polish, the gradient polish, is not in the paper at all: its tests
+ *   pin mathematical properties of the stated rule (first-order ascent, the
+ *   step length, the projection, strict acceptance), not a published
+ *   result. Random numbers come from
  * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
  * easy as 1, 2, 3", SC'11), implemented here from that definition.
  */
@@ -447,6 +459,49 @@ void orc_relax(const void *h, const double *theta, int64_t B, double *S, double 
 void orc_relax_f_at(const void *h, const double *theta, int64_t B, double *f)
 {
     orc_relax(h, theta, B, NULL, f, NULL);
+}
+
+/* Gradient polish of a few rows through the relaxation (not in the paper; a
+ * use of the relaxation above to refine +-1 designs): each row of genes x
+ * (binary32, rows x n) starts theta = x, so tanh(theta) has the signs of the
+ * row's +-1 design. Then `steps` steps of normalised gradient ascent on the
+ * relaxed fitness,
+ *   g = df/dtheta (orc_relax),  m = max_k |g_k|,  theta += eta g / m
+ * (no step when m = 0), so every step moves theta by exactly eta in the
+ * largest coordinate. The result is projected back to a gene row
+ * y = clamp(theta, -1, 1) (same signs as theta) and scored by the exact +-1
+ * fitness of its signs (d = -1 exactly when y < 0), f1; the row is
+ * accepted when f1 > f0 (strictly), f0 being the exact fitness the caller
+ * holds for the row. theta in double; outputs: theta_out (rows x n, the
+ * final theta, may be NULL), f1 (rows), accept (rows: 1 or 0). */
+void orc_polish(const void *h, const float *x, int64_t rows, const double *f0, int steps, double eta,
+                double *theta_out, double *f1, int32_t *accept)
+{
+    const orc_design *d = h;
+    const int64_t n = d->n;
+    double *th = malloc(sizeof(double) * rows * n);
+    double *g = malloc(sizeof(double) * rows * n);
+    int8_t *sg = malloc((size_t)(rows * n));
+    for (int64_t k = 0; k < rows * n; ++k) th[k] = (double)x[k];
+    for (int st = 0; st < steps; ++st) {
+        orc_relax(h, th, rows, NULL, NULL, g);
+        for (int64_t r = 0; r < rows; ++r) {
+            double m = 0.0;
+            for (int64_t k = 0; k < n; ++k) m = fmax(m, fabs(g[r * n + k]));
+            if (m == 0.0) continue;
+            for (int64_t k = 0; k < n; ++k) th[r * n + k] += eta * g[r * n + k] / m;
+        }
+    }
+    for (int64_t k = 0; k < rows * n; ++k) {
+        const double y = fmin(fmax(th[k], -1.0), 1.0);
+        sg[k] = y < 0.0 ? -1 : 1;
+    }
+    orc_fitness(h, sg, rows, NULL, f1);
+    for (int64_t r = 0; r < rows; ++r) accept[r] = f1[r] > f0[r] ? 1 : 0;
+    if (theta_out) memcpy(theta_out, th, sizeof(double) * rows * n);
+    free(th);
+    free(g);
+    free(sg);
 }
 
 /* ------------------------------------------------------------------ */
@@ -869,18 +924,28 @@ static void fitness_of_genes(const orc_target *t, int64_t D, const float *x, int
 /* The whole optimiser. x_out: np x n final genes, f_out: np final fitness,
  * trace (may be NULL): best fitness after each generation; params (may be
  * NULL): F_g and a_g of each generation (2 G floats).
- * Per generation g: F_g and a_g from the control (orc_a_control;
- * orc_adaptive_F on the current fitness under control 2), DE trials,
- * evaluation, greedy selection (strict >); leaders from the sorted
- * fitness; GWO candidates for the other wolves (variants 0 and 1), or the
- * discrete four-leader step (variant 2, orc_dgwo_step, guided by the four
- * best), evaluation, greedy selection again (alpha, beta, delta kept). CR stays fixed (step 6 of Sec. 3.2 updates "F, CR and
- * others"; the paper gives a rule for F only). */
+ * Per generation g of HWSDA (algo 0, Sec. 3.2): F_g and a_g from the
+ * control (orc_a_control; orc_adaptive_F on the current fitness under
+ * control 2), DE trials, evaluation, greedy selection (strict >); leaders
+ * from the sorted fitness; GWO candidates for the other wolves (variants 0
+ * and 1), or the discrete four-leader step (variant 2, orc_dgwo_step,
+ * guided by the four best), evaluation, greedy selection again (alpha,
+ * beta, delta kept). CR stays fixed (step 6 of Sec. 3.2 updates "F, CR and
+ * others"; the paper gives a rule for F only).
+ * The two optimisers HWSDA is compared with (Tables 3-7):
+ *   algo 1, DE alone (Sec. 2.2.1): per generation only the DE trials,
+ *           their evaluation and the greedy selection;
+ *   algo 2, GWO alone (Sec. 2.2.2): per generation the leaders from the
+ *           sorted fitness, the omega wolves move to their GWO candidates
+ *           unconditionally (the basic GWO has no greedy selection; it is
+ *           DE's operator, which HWSDA adds back as its step 5), alpha,
+ *           beta and delta keep their positions, evaluation. */
 static int hwsda_loop(const orc_target *t, int64_t D, int64_t np, int64_t G, float F, float CR, uint64_t seed,
-                      uint32_t inst, int variant, int control, float *x_out, double *f_out, double *trace,
+                      uint32_t inst, int variant, int control, int algo, float *x_out, double *f_out, double *trace,
                       float *params)
 {
-    if (np < 4 || G < 1 || control < 0 || control > 2 || variant < 0 || variant > 2) return -1;
+    if (np < 4 || G < 1 || control < 0 || control > 2 || variant < 0 || variant > 2 || algo < 0 || algo > 2)
+        return -1;
     float *x = x_out;
     float *u = malloc(sizeof(float) * np * D);
     int8_t *sg = malloc((size_t)(np * D));
@@ -895,29 +960,33 @@ static int hwsda_loop(const orc_target *t, int64_t D, int64_t np, int64_t G, flo
             params[2 * g] = F_g;
             params[2 * g + 1] = a_g;
         }
-        orc_de_step(x, np, D, F_g, CR, seed, (uint32_t)g, inst, u, NULL);
-        fitness_of_genes(t, D, u, np, sg, fu);
-        for (int64_t i = 0; i < np; ++i)
-            if (fu[i] > f[i]) {
-                memcpy(x + i * D, u + i * D, sizeof(float) * D);
-                f[i] = fu[i];
-            }
-        int32_t L[4];
-        if (variant == 2) {
-            float par[4];
-            orc_top4(f, np, L);
-            orc_dgwo_params(g, G, par);
-            orc_dgwo_step(x, np, D, L, par, seed, (uint32_t)g, inst, u);
-        } else {
-            orc_top3(f, np, L);
-            orc_gwo_step(x, np, D, L, a_g, seed, (uint32_t)g, inst, variant, u);
+        if (algo != 2) {
+            orc_de_step(x, np, D, F_g, CR, seed, (uint32_t)g, inst, u, NULL);
+            fitness_of_genes(t, D, u, np, sg, fu);
+            for (int64_t i = 0; i < np; ++i)
+                if (fu[i] > f[i]) {
+                    memcpy(x + i * D, u + i * D, sizeof(float) * D);
+                    f[i] = fu[i];
+                }
         }
-        fitness_of_genes(t, D, u, np, sg, fu);
-        for (int64_t i = 0; i < np; ++i) {
-            if (i == L[0] || i == L[1] || i == L[2]) continue;
-            if (fu[i] > f[i]) {
-                memcpy(x + i * D, u + i * D, sizeof(float) * D);
-                f[i] = fu[i];
+        if (algo != 1) {
+            int32_t L[4];
+            if (variant == 2) {
+                float par[4];
+                orc_top4(f, np, L);
+                orc_dgwo_params(g, G, par);
+                orc_dgwo_step(x, np, D, L, par, seed, (uint32_t)g, inst, u);
+            } else {
+                orc_top3(f, np, L);
+                orc_gwo_step(x, np, D, L, a_g, seed, (uint32_t)g, inst, variant, u);
+            }
+            fitness_of_genes(t, D, u, np, sg, fu);
+            for (int64_t i = 0; i < np; ++i) {
+                if (i == L[0] || i == L[1] || i == L[2]) continue;
+                if (algo == 2 || fu[i] > f[i]) {
+                    memcpy(x + i * D, u + i * D, sizeof(float) * D);
+                    f[i] = fu[i];
+                }
             }
         }
         if (trace) {
@@ -938,21 +1007,40 @@ int orc_hwsda_run_ctl(const void *h, int64_t np, int64_t G, float F, float CR, u
                       double *trace, float *params)
 {
     const orc_target t = {h, NULL, 0, 0, 0.0, 0.0};
-    return hwsda_loop(&t, ((const orc_design *)h)->n, np, G, F, CR, seed, inst, variant, control, x_out, f_out,
+    return hwsda_loop(&t, ((const orc_design *)h)->n, np, G, F, CR, seed, inst, variant, control, 0, x_out, f_out,
                       trace, params);
 }
 
-/* The optimiser on the multi-wavelength objective (f = -h of
- * orc_multi_objective); controls 0 and 1 (the adaptive rule's thresholds
- * are stated for |d_eff|^2). */
-int orc_hwsda_run_obj(const void *const *designs, int K, int kind, double G0, double beta, int64_t np, int64_t G,
-                      float F, float CR, uint64_t seed, uint32_t inst, int variant, int control, float *x_out,
-                      double *f_out, double *trace, float *params)
+/* The loop with the optimiser chosen by algo: 0 HWSDA, 1 DE alone, 2 GWO
+ * alone (see hwsda_loop). */
+int orc_run_algo(const void *h, int64_t np, int64_t G, float F, float CR, uint64_t seed, uint32_t inst, int variant,
+                 int control, int algo, float *x_out, double *f_out, double *trace, float *params)
+{
+    const orc_target t = {h, NULL, 0, 0, 0.0, 0.0};
+    return hwsda_loop(&t, ((const orc_design *)h)->n, np, G, F, CR, seed, inst, variant, control, algo, x_out,
+                      f_out, trace, params);
+}
+
+/* The optimiser chosen by algo (as orc_run_algo) on the multi-wavelength
+ * objective (f = -h of orc_multi_objective); controls 0 and 1 (the
+ * adaptive rule's thresholds are stated for |d_eff|^2). */
+int orc_run_obj_algo(const void *const *designs, int K, int kind, double G0, double beta, int64_t np, int64_t G,
+                     float F, float CR, uint64_t seed, uint32_t inst, int variant, int control, int algo,
+                     float *x_out, double *f_out, double *trace, float *params)
 {
     if (!multi_valid(designs, K, kind) || control == 2) return -1;
     const orc_target t = {NULL, designs, K, kind, G0, beta};
     const int64_t D = ((const orc_design *)designs[0])->n;
-    return hwsda_loop(&t, D, np, G, F, CR, seed, inst, variant, control, x_out, f_out, trace, params);
+    return hwsda_loop(&t, D, np, G, F, CR, seed, inst, variant, control, algo, x_out, f_out, trace, params);
+}
+
+/* HWSDA on the multi-wavelength objective. */
+int orc_hwsda_run_obj(const void *const *designs, int K, int kind, double G0, double beta, int64_t np, int64_t G,
+                      float F, float CR, uint64_t seed, uint32_t inst, int variant, int control, float *x_out,
+                      double *f_out, double *trace, float *params)
+{
+    return orc_run_obj_algo(designs, K, kind, G0, beta, np, G, F, CR, seed, inst, variant, control, 0, x_out, f_out,
+                            trace, params);
 }
 
 /* The optimiser with the textbook parameters (control 0). */
