@@ -207,9 +207,10 @@ qpm_status qpm_de_step_shape(const float *x, int64_t np, int64_t D, int64_t ldx,
  * sum is 0); variant 1: y = (Y_1 + Y_2 + Y_3) / 3; clamped to [-1, 1].
  * Philox words: for gene quad q = j / 4 and t = 3 (j % 4) + k, counter
  * (3 q + t / 4, i, g, inst << 8 | 4), word t % 4.
- * leaders: device int32[3] (alpha, beta, delta), distinct, in [0, np); the
- * call copies them to the host to validate them, so it synchronises s.
- * Leader rows of y and y_bits are left untouched. a = 0 or
+ * leaders: host int32[3] (alpha, beta, delta), distinct, in [0, np),
+ * validated before the launch and passed by value (the call enqueues on s
+ * and returns without synchronising). Leader rows of y and y_bits are left
+ * untouched. a = 0 or
  * 2^-100 <= a <= 1e30 (the parameter runs from 2 down to 0).
  */
 /*
@@ -227,9 +228,9 @@ qpm_status qpm_de_step_shape(const float *x, int64_t np, int64_t D, int64_t ldx,
  *   p = fmaf(t, maj - dist, dist); p' = fmaf(1 - 2 eps, p, eps);
  *   y = the state of leader w >> 30 when (w >> 16 & 0x3FFF) 2^-14 < lambda
  *   (social learning), else +1 when (w & 0xFFFF) 2^-16 < p', else -1.
- * leaders: device int32[4], distinct, in [0, np): alpha, beta, delta (their
- * rows of y and y_bits are left untouched) and the fourth; the call copies
- * them to the host to validate them (it synchronises s). params: host.
+ * leaders: host int32[4], distinct, in [0, np): alpha, beta, delta (their
+ * rows of y and y_bits are left untouched) and the fourth; validated before
+ * the launch and passed by value (no synchronisation). params: host.
  * Errors: as qpm_gwo_step, and QPM_EINVAL for non-finite params.
  */
 qpm_status qpm_dgwo_step(const float *x, int64_t np, int64_t D, int64_t ldx, const int32_t *leaders,
@@ -345,7 +346,27 @@ typedef struct {
                             (cached per problem size; QPM_TUNE_CACHE file) */
     int32_t control;     /* qpm_control: how F_g and a_g are set */
     int32_t trials;      /* qpm_trials: where the DE trial genes go */
+    int32_t algo;        /* qpm_algo: HWSDA, or one of its two parts alone */
 } qpm_run_config;
+
+/*
+ * The optimiser a run applies each generation. HWSDA is the hybrid of paper
+ * Sec. 3.2; the other two are the optimisers it is compared with in the
+ * tables of Sec. 4 (each alone, on the same fitness and random streams):
+ *   QPM_ALGO_HWSDA  DE trials + greedy selection, leaders, grey-wolf
+ *                   candidates + greedy selection (leaders kept);
+ *   QPM_ALGO_DE     DE rand/1 alone (Sec. 2.2.1): trials, evaluation,
+ *                   greedy selection; the leaders reported are the three
+ *                   best after the selection;
+ *   QPM_ALGO_GWO    the grey-wolf optimiser alone (Sec. 2.2.2): alpha,
+ *                   beta, delta = the three best of the current population,
+ *                   every other wolf moves to its candidate unconditionally
+ *                   (the basic method has no greedy selection), evaluation;
+ *                   gwo_variant applies as in HWSDA, F is unused.
+ * DE and GWO runs store every trial (QPM_TRIALS_AUTO means STORE;
+ * QPM_TRIALS_ACCEPTED is QPM_EINVAL). Batched runs take QPM_ALGO_HWSDA only.
+ */
+typedef enum { QPM_ALGO_HWSDA = 0, QPM_ALGO_DE = 1, QPM_ALGO_GWO = 2 } qpm_algo;
 
 /*
  * Trial storage of a run's DE step (results are identical; speed differs):
@@ -402,9 +423,11 @@ typedef struct {
  * leaders alpha, beta, delta = the three best by (f descending, slot
  * ascending), GWO candidates for every other wolf with a_g, evaluation,
  * greedy selection again (leaders excluded); F_g and a_g per cfg->control
- * (qpm_control). The run owns its own stream; s is the stream the caller's
+ * (qpm_control). cfg->algo selects HWSDA or one of its parts alone
+ * (qpm_algo). The run owns its own stream; s is the stream the caller's
  * later reads are ordered with. Errors: QPM_EINVAL for an out-of-range
- * field (np, G, F, CR, prec, gwo_variant, inst, fit_kernel, control).
+ * field (np, G, F, CR, prec, gwo_variant, inst, fit_kernel, control,
+ * trials, algo).
  */
 qpm_status qpm_run_create(qpm_design d, const qpm_run_config *cfg, qpm_stream s,
                           qpm_run_handle *out);

@@ -145,10 +145,12 @@ struct AcceptOut {
 // gen_advanced: the counter was already advanced by the evaluation kernel,
 // so the next draws are for gen[0] itself and no tail advances it;
 // defer_leaders: the candidates are left in `cand` for launch_materialize
-// to merge into top3_out (no tail kernel).
+// to merge into top3_out (no tail kernel); replace_all: every genome
+// outside skip3 takes its new value (no greedy selection).
 struct FinishMode {
     bool gen_advanced = false;
     bool defer_leaders = false;
+    bool replace_all = false;
 };
 qpm_status launch_finish(const double *part, int gy, int64_t ld, int64_t np, const double *C, void *f_cur,
                          bool f64, uint32_t *flags, uint32_t *fbits, const int32_t *skip3, int32_t *top3_out,
@@ -264,14 +266,16 @@ size_t table_lds_bytes(int64_t W, bool f32, int gw, int wpw);
 // DE draws of generation *gen_dev for every individual
 qpm_status launch_draws(int64_t np, int64_t D, uint64_t seed, const uint32_t *gen_dev, uint32_t inst, int4 *draws,
                         hipStream_t s);
+// leaders: device int32[3], or nullptr and the three by value in lead_c
 qpm_status launch_gwo(const PopView &pv, const int32_t *leaders, const float *a_tab, float a,
                       uint64_t seed, const uint32_t *gen_dev, uint32_t gen, uint32_t inst,
-                      int variant, uint32_t *bits, int64_t ld, hipStream_t s);
+                      int variant, uint32_t *bits, int64_t ld, hipStream_t s, int4 lead_c = int4{});
 // the improved discrete four-leader step (leaders: 4 slots, the first three
-// kept; par_tab[g] or par = {t, 1 - 2 eps, eps, lambda})
+// kept, on the device or by value in lead_c; par_tab[g] or
+// par = {t, 1 - 2 eps, eps, lambda})
 qpm_status launch_dgwo(const PopView &pv, const int32_t *leaders, const float4 *par_tab, float4 par,
                        uint64_t seed, const uint32_t *gen_dev, uint32_t gen, uint32_t inst, uint32_t *bits,
-                       int64_t ld, hipStream_t s);
+                       int64_t ld, hipStream_t s, int4 lead_c = int4{});
 // leaders[3] = the best of f other than leaders[0..2]
 qpm_status launch_fourth(const void *f, int64_t np, bool f64, int32_t *leaders, hipStream_t s);
 // the three best of f[0..np) (f descending, slot ascending) into out3;

@@ -315,7 +315,7 @@ qpm_status launch_materialize(const PopView &pv, const int4 *draws, const uint32
 // individuals and the 32-bit bit words of neighbouring individuals, which
 // share cache lines, are written from one L2 instead of eight.
 template <int VARIANT>
-__global__ __launch_bounds__(256) void gwo_kernel(PopView pv, const int32_t *__restrict__ leaders,
+__global__ __launch_bounds__(256) void gwo_kernel(PopView pv, const int32_t *__restrict__ leaders, int4 lead_c,
                                                   const float *__restrict__ a_tab, float a_c, uint32_t k0, uint32_t k1,
                                                   const uint32_t *__restrict__ gen_dev, uint32_t gen_c, uint32_t inst,
                                                   uint32_t *__restrict__ bits, int64_t ld, int64_t per_xcd)
@@ -323,7 +323,9 @@ __global__ __launch_bounds__(256) void gwo_kernel(PopView pv, const int32_t *__r
     const int64_t np = pv.np, D = pv.D;
     const int64_t i = static_cast<int64_t>(blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
     if (i >= np) return;
-    const int64_t L0 = leaders[0], L1 = leaders[1], L2 = leaders[2];
+    // leaders from the device (runs) or by value (the entry point)
+    const int64_t L0 = leaders ? leaders[0] : lead_c.x, L1 = leaders ? leaders[1] : lead_c.y,
+                  L2 = leaders ? leaders[2] : lead_c.z;
     // leaders keep their positions; indices outside the population make
     // the launch a no-op instead of an out-of-bounds read
     if (i == L0 || i == L1 || i == L2) return;
@@ -352,7 +354,7 @@ __global__ __launch_bounds__(256) void gwo_kernel(PopView pv, const int32_t *__r
 // Improved discrete four-leader step (dgwo_quad), same grid as gwo_kernel.
 // The new genes depend on the leaders' genes only, so the wolf's own row is
 // not read. leaders: alpha, beta, delta (kept), then the fourth.
-__global__ __launch_bounds__(256) void dgwo_kernel(PopView pv, const int32_t *__restrict__ leaders,
+__global__ __launch_bounds__(256) void dgwo_kernel(PopView pv, const int32_t *__restrict__ leaders, int4 lead_c,
                                                    const float4 *__restrict__ par_tab, float4 par_c, uint32_t k0,
                                                    uint32_t k1, const uint32_t *__restrict__ gen_dev, uint32_t gen_c,
                                                    uint32_t inst, uint32_t *__restrict__ bits, int64_t ld,
@@ -361,7 +363,8 @@ __global__ __launch_bounds__(256) void dgwo_kernel(PopView pv, const int32_t *__
     const int64_t np = pv.np, D = pv.D;
     const int64_t i = static_cast<int64_t>(blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
     if (i >= np) return;
-    const int64_t L0 = leaders[0], L1 = leaders[1], L2 = leaders[2], L3 = leaders[3];
+    const int64_t L0 = leaders ? leaders[0] : lead_c.x, L1 = leaders ? leaders[1] : lead_c.y,
+                  L2 = leaders ? leaders[2] : lead_c.z, L3 = leaders ? leaders[3] : lead_c.w;
     if (i == L0 || i == L1 || i == L2) return;
     if (L0 < 0 || L0 >= np || L1 < 0 || L1 >= np || L2 < 0 || L2 >= np || L3 < 0 || L3 >= np) return;
     const uint32_t g = gen_dev ? gen_dev[0] : gen_c;
@@ -552,13 +555,13 @@ qpm_status launch_de(const PopView &pv, float F, float CR, uint64_t seed, const 
 
 qpm_status launch_dgwo(const PopView &pv, const int32_t *leaders, const float4 *par_tab, float4 par,
                        uint64_t seed, const uint32_t *gen_dev, uint32_t gen, uint32_t inst, uint32_t *bits,
-                       int64_t ld, hipStream_t s)
+                       int64_t ld, hipStream_t s, int4 lead_c)
 {
     const int64_t per_xcd = (pv.np + 7) / 8;
     const qpm_status st = check_quad_grid(pv.D, 8 * per_xcd);
     if (st != QPM_OK) return st;
     const dim3 grid(static_cast<unsigned>(8 * per_xcd), quad_grid(pv.D, pv.np).y);
-    dgwo_kernel<<<grid, 256, 0, s>>>(pv, leaders, par_tab, par, static_cast<uint32_t>(seed),
+    dgwo_kernel<<<grid, 256, 0, s>>>(pv, leaders, lead_c, par_tab, par, static_cast<uint32_t>(seed),
                                      static_cast<uint32_t>(seed >> 32), gen_dev, gen, inst, bits, ld, per_xcd);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
@@ -576,17 +579,17 @@ qpm_status launch_fourth(const void *f, int64_t np, bool f64, int32_t *leaders, 
 
 qpm_status launch_gwo(const PopView &pv, const int32_t *leaders, const float *a_tab, float a, uint64_t seed,
                       const uint32_t *gen_dev, uint32_t gen, uint32_t inst, int variant, uint32_t *bits, int64_t ld,
-                      hipStream_t s)
+                      hipStream_t s, int4 lead_c)
 {
     const int64_t per_xcd = (pv.np + 7) / 8;
     const qpm_status st = check_quad_grid(pv.D, 8 * per_xcd);
     if (st != QPM_OK) return st;
     const dim3 grid(static_cast<unsigned>(8 * per_xcd), quad_grid(pv.D, pv.np).y);
     if (variant == 1)
-        gwo_kernel<1><<<grid, 256, 0, s>>>(pv, leaders, a_tab, a, static_cast<uint32_t>(seed),
+        gwo_kernel<1><<<grid, 256, 0, s>>>(pv, leaders, lead_c, a_tab, a, static_cast<uint32_t>(seed),
                                            static_cast<uint32_t>(seed >> 32), gen_dev, gen, inst, bits, ld, per_xcd);
     else
-        gwo_kernel<0><<<grid, 256, 0, s>>>(pv, leaders, a_tab, a, static_cast<uint32_t>(seed),
+        gwo_kernel<0><<<grid, 256, 0, s>>>(pv, leaders, lead_c, a_tab, a, static_cast<uint32_t>(seed),
                                            static_cast<uint32_t>(seed >> 32), gen_dev, gen, inst, bits, ld, per_xcd);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
@@ -746,14 +749,13 @@ QPM_API qpm_status qpm_gwo_step(const float *x, int64_t np, int64_t D, int64_t l
     const size_t bytes = sizeof(float) * static_cast<size_t>(np) * static_cast<size_t>(ldx);
     QPM_REQUIRE(!overlaps(x, bytes, y, bytes), QPM_EINVAL, "x and y must not overlap");
     hipStream_t s = static_cast<hipStream_t>(sv);
-    int32_t L[3];
-    QPM_TRY_HIP(hipMemcpyAsync(L, leaders, sizeof(L), hipMemcpyDeviceToHost, s));
-    QPM_TRY_HIP(hipStreamSynchronize(s));
+    const int32_t *L = leaders;  // host memory: validated here, passed by value
     for (int k = 0; k < 3; ++k)
         QPM_REQUIRE(L[k] >= 0 && L[k] < np, QPM_EINVAL, "leader %d (%d) is outside [0, np)", k, (int)L[k]);
     QPM_REQUIRE(L[0] != L[1] && L[0] != L[2] && L[1] != L[2], QPM_EINVAL, "leaders must be distinct");
     const PopView pv{x, x, nullptr, y, y, np, D, ldx};
-    return launch_gwo(pv, leaders, nullptr, a, seed, nullptr, generation, inst, variant, y_bits, ld, s);
+    return launch_gwo(pv, nullptr, nullptr, a, seed, nullptr, generation, inst, variant, y_bits, ld, s,
+                      make_int4(L[0], L[1], L[2], 0));
 }
 
 QPM_API qpm_status qpm_dgwo_step(const float *x, int64_t np, int64_t D, int64_t ldx, const int32_t *leaders,
@@ -775,14 +777,13 @@ QPM_API qpm_status qpm_dgwo_step(const float *x, int64_t np, int64_t D, int64_t 
     const size_t bytes = sizeof(float) * static_cast<size_t>(np) * static_cast<size_t>(ldx);
     QPM_REQUIRE(!overlaps(x, bytes, y, bytes), QPM_EINVAL, "x and y must not overlap");
     hipStream_t s = static_cast<hipStream_t>(sv);
-    int32_t L[4];
-    QPM_TRY_HIP(hipMemcpyAsync(L, leaders, sizeof(L), hipMemcpyDeviceToHost, s));
-    QPM_TRY_HIP(hipStreamSynchronize(s));
+    const int32_t *L = leaders;  // host memory: validated here, passed by value
     for (int k = 0; k < 4; ++k)
         QPM_REQUIRE(L[k] >= 0 && L[k] < np, QPM_EINVAL, "leader %d (%d) is outside [0, np)", k, (int)L[k]);
     for (int a = 0; a < 4; ++a)
         for (int b = a + 1; b < 4; ++b) QPM_REQUIRE(L[a] != L[b], QPM_EINVAL, "leaders must be distinct");
     const PopView pv{x, x, nullptr, y, y, np, D, ldx};
     const float4 par = make_float4(params[0], params[1], params[2], params[3]);
-    return launch_dgwo(pv, leaders, nullptr, par, seed, nullptr, generation, inst, y_bits, ld, s);
+    return launch_dgwo(pv, nullptr, nullptr, par, seed, nullptr, generation, inst, y_bits, ld, s,
+                       make_int4(L[0], L[1], L[2], L[3]));
 }

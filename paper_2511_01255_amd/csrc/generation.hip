@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ 
                                                      int32_t *__restrict__ cand_i, int4 *__restrict__ draws_next,
                                                      const uint32_t *__restrict__ gen, int64_t D, uint32_t k0,
                                                      uint32_t k1, uint32_t inst, AcceptOut acc, uint32_t next_off,
-                                                     int32_t *__restrict__ top3_direct)
+                                                     int32_t *__restrict__ top3_direct, int replace_all)
 {
     const int lane = threadIdx.x & 63;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + lane;
@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *__restrict__ 
     if (threadIdx.x < 64) {
         const double sr = t.qr + C[0], si = t.qi + C[1];
         select_group<T>(fma(sr, sr, si * si), blockIdx.x, lane, np, f_cur, flags, fbits, skip3, cand_v, cand_i,
-                        draws_next, gen, D, k0, k1, inst, acc, next_off);
+                        draws_next, gen, D, k0, k1, inst, acc, next_off, replace_all != 0);
     }
     // a one-workgroup population (np <= 64): the leaders from its own three
     // candidates, as the tail kernel would take them, without that launch
@@ -151,14 +151,14 @@ qpm_status launch_finish(const double *part, int gy, int64_t ld, int64_t np, con
         int32_t *ci = cv ? reinterpret_cast<int32_t *>(cv + 3 * static_cast<size_t>(blocks)) : nullptr;
         finish_kernel<double><<<blocks, 256, 0, s>>>(part, gy, ld, np, C, static_cast<double *>(f_cur), flags, fbits,
                                                      skip3, cv, ci, draws_next, gen, D, k0, k1, inst, acc, next_off,
-                                                     direct);
+                                                     direct, mode.replace_all ? 1 : 0);
         if (tail) finish_tail_kernel<double><<<1, 256, 0, s>>>(cv, ci, blocks, tail_top3, gen, advance);
     } else {
         float *cv = top3_out ? static_cast<float *>(cand) : nullptr;
         int32_t *ci = cv ? reinterpret_cast<int32_t *>(cv + 3 * static_cast<size_t>(blocks)) : nullptr;
         finish_kernel<float><<<blocks, 256, 0, s>>>(part, gy, ld, np, C, static_cast<float *>(f_cur), flags, fbits,
                                                     skip3, cv, ci, draws_next, gen, D, k0, k1, inst, acc, next_off,
-                                                    direct);
+                                                    direct, mode.replace_all ? 1 : 0);
         if (tail) finish_tail_kernel<float><<<1, 256, 0, s>>>(cv, ci, blocks, tail_top3, gen, advance);
     }
     QPM_TRY_HIP(hipGetLastError());

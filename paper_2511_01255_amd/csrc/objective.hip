@@ -256,7 +256,8 @@ __global__ __launch_bounds__(256) void obj_finish_kernel(ObjTabs tabs, int K, do
                                                          const int32_t *__restrict__ skip3, T *__restrict__ cand_v,
                                                          int32_t *__restrict__ cand_i, int4 *__restrict__ draws_next,
                                                          const uint32_t *__restrict__ gen, int64_t D, uint32_t k0,
-                                                         uint32_t k1, uint32_t inst, AcceptOut acc, uint32_t next_off)
+                                                         uint32_t k1, uint32_t inst, AcceptOut acc, uint32_t next_off,
+                                                         int replace_all)
 {
     __shared__ double sh[6 * 4 * 64];
     const int lane = threadIdx.x & 63;
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(256) void obj_finish_kernel(ObjTabs tabs, int K, do
     const double v = obj_value<THG>(tabs, K, scale, G0, beta, part, gy, ld, i, i < np, nullptr, 0, sh);
     if (threadIdx.x < 64)
         select_group<T>(v, blockIdx.x, lane, np, f_cur, flags, fbits, skip3, cand_v, cand_i, draws_next, gen, D, k0,
-                        k1, inst, acc, next_off);
+                        k1, inst, acc, next_off, replace_all != 0);
 }
 
 ObjPlan plan_objective_shape(const Objective &o, int wpw)
@@ -356,7 +357,8 @@ qpm_status launch_objective_finish(const Objective &o, const ObjPlan &pl, const 
         int32_t *ci = cv ? reinterpret_cast<int32_t *>(cv + 3 * static_cast<size_t>(blocks)) : nullptr;          \
         obj_finish_kernel<T, H><<<blocks, 256, 0, s>>>(o.tabs, o.K, o.scale, o.G0, o.beta, part, pl.gy, ld, np,  \
                                                        static_cast<T *>(f_cur), flags, fbits, skip3, cv, ci,     \
-                                                       draws_next, gen, D, k0, k1, inst, acc, next_off);          \
+                                                       draws_next, gen, D, k0, k1, inst, acc, next_off,          \
+                                                       mode.replace_all ? 1 : 0);                                 \
         if (tail) finish_tail_kernel<T><<<1, 256, 0, s>>>(cv, ci, blocks, tail_top3, gen, advance);               \
     }
     if (f64) {

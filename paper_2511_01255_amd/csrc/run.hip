@@ -172,6 +172,48 @@ static qpm_status enqueue_generation(qpm_run_s *r, hipEvent_t *ev = nullptr)
 #define QPM_STEP(k, call)                         \
     if ((st = mark(k)) != QPM_OK) return st;      \
     if ((st = (call)) != QPM_OK) return st;
+    if (c.algo == QPM_ALGO_DE) {
+        // DE alone: trials, evaluation (which advances the counter), greedy
+        // selection with the next generation's draws, and the three best
+        // after it as the reported leaders
+        QPM_STEP(QPM_K_DE, launch_de(pv, c.F, c.CR, c.seed, r->gen, 0u, c.inst, r->tbits, r->ld, r->draws, false,
+                                     r->st, r->de_ipw, r->de_passes, r->fbits, r->F_tab, true, nullptr))
+        QPM_STEP(QPM_K_FIT_DE, eval_partials(r, r->gen))
+        QPM_STEP(QPM_K_FINISH_DE, eval_finish(r, nullptr, r->leaders, r->cand, r->draws, AcceptOut{},
+                                              FinishMode{true, false, false}))
+        if (r->adaptive()) {
+            st = launch_adapt_F(r->f_cur, r->f64(), c.np, r->gen, c.generations, r->F_base, r->F_tab, r->st);
+            if (st != QPM_OK) return st;
+        }
+        for (int k = QPM_K_GWO; k <= QPM_K_FINISH_GWO; ++k)
+            if ((st = mark(k)) != QPM_OK) return st;
+        return mark(QPM_K_COUNT);
+    }
+    if (c.algo == QPM_ALGO_GWO) {
+        // GWO alone: the leaders are the three best of the population
+        // entering the generation (from initialisation, or from the previous
+        // generation's finish); every other wolf moves to its candidate
+        for (int k = QPM_K_DE; k <= QPM_K_FINISH_DE; ++k)
+            if ((st = mark(k)) != QPM_OK) return st;
+        if (c.gwo_variant == 2) {
+            QPM_STEP(QPM_K_GWO, launch_fourth(r->f_cur, c.np, r->f64(), r->leaders, r->st))
+            st = launch_dgwo(pv, r->leaders, r->dg_tab, float4{}, c.seed, r->gen, 0u, c.inst, r->tbits, r->ld,
+                             r->st);
+            if (st != QPM_OK) return st;
+        } else {
+            QPM_STEP(QPM_K_GWO, launch_gwo(pv, r->leaders, r->a_tab, 0.0f, c.seed, r->gen, 0u, c.inst,
+                                           c.gwo_variant, r->tbits, r->ld, r->st))
+        }
+        QPM_STEP(QPM_K_FIT_GWO, eval_partials(r, r->gen))
+        // leaders kept; the next leaders from the moved population
+        QPM_STEP(QPM_K_FINISH_GWO, eval_finish(r, r->leaders, r->leaders, r->cand, nullptr, AcceptOut{},
+                                               FinishMode{true, false, true}))
+        if (r->adaptive()) {
+            st = launch_adapt_F(r->f_cur, r->f64(), c.np, r->gen, c.generations, r->F_base, r->F_tab, r->st);
+            if (st != QPM_OK) return st;
+        }
+        return mark(QPM_K_COUNT);
+    }
     QPM_STEP(QPM_K_DE, launch_de(pv, c.F, c.CR, c.seed, r->gen, 0u, c.inst, r->tbits, r->ld, r->draws, false, r->st,
                                  r->de_ipw, r->de_passes, r->fbits, r->F_tab, !r->lazy,
                                  r->lazy ? r->acc_cnt : nullptr))
@@ -429,6 +471,10 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
                 QPM_EINVAL, "unknown parameter control %d", c.control);
     QPM_REQUIRE(c.trials == QPM_TRIALS_AUTO || c.trials == QPM_TRIALS_STORE || c.trials == QPM_TRIALS_ACCEPTED,
                 QPM_EINVAL, "unknown trial storage %d", c.trials);
+    QPM_REQUIRE(c.algo == QPM_ALGO_HWSDA || c.algo == QPM_ALGO_DE || c.algo == QPM_ALGO_GWO, QPM_EINVAL,
+                "unknown algorithm %d", c.algo);
+    QPM_REQUIRE(c.algo == QPM_ALGO_HWSDA || c.trials != QPM_TRIALS_ACCEPTED, QPM_EINVAL,
+                "accepted-only trials are a mode of the hybrid run; DE and GWO runs store every trial");
     qpm_status st = check_device();
     if (st != QPM_OK) return st;
 
@@ -455,7 +501,7 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
         return QPM_EINVAL;
     }
     r->lazy = c.trials == QPM_TRIALS_ACCEPTED ||
-              (c.trials == QPM_TRIALS_AUTO && lazy_ok &&
+              (c.trials == QPM_TRIALS_AUTO && c.algo == QPM_ALGO_HWSDA && lazy_ok &&
                2 * static_cast<int64_t>(sizeof(float)) * c.np * r->ldx > (int64_t(64) << 20));
     r->plan = plan_fitness(*d, static_cast<qpm_prec>(c.prec), c.np, c.fit_kernel);
     if (obj) r->oplan = plan_objective(*obj, static_cast<qpm_prec>(c.prec), c.np);
@@ -735,7 +781,11 @@ QPM_API qpm_status qpm_run_best(qpm_run_handle r, float *best_x, uint32_t *best_
         stats->best_fitness = bf;
         stats->best_index = bi[0];
         stats->generations = r->done;
-        stats->fitness_evals = r->cfg.np + r->done * (2 * r->cfg.np - 3);
+        // evaluations per generation: trials and candidates (HWSDA), trials
+        // (DE), candidates of the omega wolves (GWO)
+        const int64_t np = r->cfg.np;
+        const int64_t per_gen = r->cfg.algo == QPM_ALGO_DE ? np : (r->cfg.algo == QPM_ALGO_GWO ? np - 3 : 2 * np - 3);
+        stats->fitness_evals = np + r->done * per_gen;
         stats->domain_evals = static_cast<double>(stats->fitness_evals) * static_cast<double>(r->D);
     }
     return QPM_OK;
@@ -795,6 +845,9 @@ QPM_API qpm_status qpm_run_polish(qpm_run_handle r, int32_t steps, float eta, in
     }
     if (st == QPM_OK && r->adaptive())  // the population entering the next generation changed
         st = launch_adapt_F(r->f_cur, r->f64(), c.np, r->gen, c.generations, r->F_base, r->F_tab, r->st);
+    // a GWO run's next generation is led by the three best of the polished
+    // population (a polished leader may now rank differently)
+    if (st == QPM_OK && c.algo == QPM_ALGO_GWO) st = launch_top3(r->f_cur, c.np, r->f64(), r->leaders, r->st);
     if (st != QPM_OK) return st;
     uint32_t acc = 0;
     QPM_TRY_HIP(hipMemcpyAsync(&acc, r->pol_acc, sizeof(acc), hipMemcpyDeviceToHost, r->st));

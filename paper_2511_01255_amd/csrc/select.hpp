@@ -16,14 +16,17 @@ namespace qpm {
 // generation gen + next_off (with draws_next; next_off = 0 when the
 // counter was already advanced), the group's three best (with
 // cand_v) and, with acc.list, the accepted slots (appended in any order)
-// and the packed flags from before the selection.
+// and the packed flags from before the selection. With replace_all every
+// genome outside skip3 takes its new value whatever its fitness (the move
+// of the basic grey-wolf optimiser, which has no greedy selection).
 template <typename T>
 __device__ __forceinline__ void select_group(double value, int64_t grp, int lane, int64_t np, T *__restrict__ f_cur,
                                              uint32_t *__restrict__ flags, uint32_t *__restrict__ fbits,
                                              const int32_t *__restrict__ skip3, T *__restrict__ cand_v,
                                              int32_t *__restrict__ cand_i, int4 *__restrict__ draws_next,
                                              const uint32_t *__restrict__ gen, int64_t D, uint32_t k0, uint32_t k1,
-                                             uint32_t inst, AcceptOut acc = AcceptOut{}, uint32_t next_off = 1u)
+                                             uint32_t inst, AcceptOut acc = AcceptOut{}, uint32_t next_off = 1u,
+                                             bool replace_all = false)
 {
     const int64_t i = grp * 64 + lane;
     const bool valid = i < np;
@@ -36,7 +39,7 @@ __device__ __forceinline__ void select_group(double value, int64_t grp, int lane
         fl = flags[i];
         fl_old = fl;
         fv = f_cur[i];
-        if (!skip && v > fv) {
+        if (!skip && (replace_all || v > fv)) {
             accepted = true;
             fv = v;
             f_cur[i] = v;

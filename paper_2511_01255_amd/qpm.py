@@ -20,9 +20,12 @@ FIT_TABLE = 3
 CONTROL_FIXED = 0     # F constant, a from 2 to 0
 CONTROL_DECAY = 1     # F = a from 0.1 to 0.01
 CONTROL_ADAPTIVE = 2  # adaptive F in [0.01, 0.1], a from 0.1 to 0.01
-TRIALS_AUTO = 0      # accepted-only trial genes when the population exceeds 256 MB
+TRIALS_AUTO = 0      # accepted-only trial genes when the population exceeds 64 MB
 TRIALS_STORE = 1     # every DE trial's genes written
 TRIALS_ACCEPTED = 2  # bits only, accepted trials recomputed after selection
+ALGO_HWSDA = 0  # the hybrid: DE + selection, leaders, GWO + selection
+ALGO_DE = 1     # DE rand/1 alone
+ALGO_GWO = 2    # the grey-wolf optimiser alone (omega wolves always move)
 OBJ_SHG = 0  # multi-wavelength objective over |sum d a| / L
 OBJ_THG = 1  # multi-wavelength objective over |d_eff| / L^2
 # timing slots of one generation (QPM_K_*)
@@ -46,7 +49,8 @@ class QpmError(RuntimeError):
 class RunConfig(C.Structure):
     _fields_ = [("np", _I64), ("generations", _I64), ("F", _F), ("CR", _F), ("seed", _U64),
                 ("inst", _U32), ("prec", _I32), ("gwo_variant", _I32), ("use_graph", _I32),
-                ("fit_kernel", _I32), ("tune", _I32), ("control", _I32), ("trials", _I32)]
+                ("fit_kernel", _I32), ("tune", _I32), ("control", _I32), ("trials", _I32),
+                ("algo", _I32)]
 
 
 class RunStats(C.Structure):
@@ -291,8 +295,19 @@ def de_step(x, D, F, CR, seed, generation, inst=0, stream=None, shape=None):
     return u, ub
 
 
+def _host_leaders(leaders, k):
+    """Leader slots (a sequence, numpy array or tensor on any device) as a
+    host int32 array of k entries."""
+    if hasattr(leaders, "detach"):
+        leaders = leaders.detach().cpu().numpy()
+    L = np.ascontiguousarray(np.asarray(leaders).reshape(-1), dtype=np.int32)
+    if L.size != k:
+        raise ValueError("%d leader slots expected, got %d" % (k, L.size))
+    return L
+
+
 def gwo_step(x, D, leaders, a, seed, generation, inst=0, variant=0, stream=None):
-    """x: float32 CUDA tensor (np, ldx); leaders: int32 CUDA tensor (3,).
+    """x: float32 CUDA tensor (np, ldx); leaders: 3 slots (host values).
     Returns (y, y_bits); leader rows of y are a copy of x, their bit
     columns are left 0."""
     import torch
@@ -300,14 +315,15 @@ def gwo_step(x, D, leaders, a, seed, generation, inst=0, variant=0, stream=None)
     ld = ld_for(np_)
     y = x.clone()
     yb = torch.zeros((words(D), ld), dtype=torch.int32, device=x.device)
-    _check(lib().qpm_gwo_step(_ptr(x), np_, D, ldx, _ptr(leaders), a, seed, generation, inst, variant, _ptr(y),
+    L = _host_leaders(leaders, 3)
+    _check(lib().qpm_gwo_step(_ptr(x), np_, D, ldx, L.ctypes.data, a, seed, generation, inst, variant, _ptr(y),
                               _ptr(yb), ld, _stream(stream)))
     return y, yb
 
 
 def dgwo_step(x, D, leaders, params, seed, generation, inst=0, stream=None):
     """The discrete four-leader step. x: float32 CUDA tensor (np, ldx);
-    leaders: int32 CUDA tensor (4,); params: 4 floats (t, 1 - 2 eps, eps,
+    leaders: 4 slots (host values); params: 4 floats (t, 1 - 2 eps, eps,
     lambda). Returns (y, y_bits) like gwo_step."""
     import torch
     np_, ldx = x.shape
@@ -315,7 +331,8 @@ def dgwo_step(x, D, leaders, params, seed, generation, inst=0, stream=None):
     y = x.clone()
     yb = torch.zeros((words(D), ld), dtype=torch.int32, device=x.device)
     par = np.ascontiguousarray(params, dtype=np.float32)
-    _check(lib().qpm_dgwo_step(_ptr(x), np_, D, ldx, _ptr(leaders), par.ctypes.data, seed, generation, inst,
+    L = _host_leaders(leaders, 4)
+    _check(lib().qpm_dgwo_step(_ptr(x), np_, D, ldx, L.ctypes.data, par.ctypes.data, seed, generation, inst,
                                _ptr(y), _ptr(yb), ld, _stream(stream)))
     return y, yb
 
@@ -386,10 +403,10 @@ def relax(theta, design, prec=PREC_F32):
 
 
 def _config(np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0, use_graph=1,
-            fit_kernel=FIT_AUTO, tune=0, control=0, trials=0):
+            fit_kernel=FIT_AUTO, tune=0, control=0, trials=0, algo=ALGO_HWSDA):
     return RunConfig(np=np_, generations=generations, F=F, CR=CR, seed=seed, inst=inst, prec=prec,
                      gwo_variant=gwo_variant, use_graph=use_graph, fit_kernel=fit_kernel, tune=tune,
-                     control=control, trials=trials)
+                     control=control, trials=trials, algo=algo)
 
 
 class Run:
@@ -398,10 +415,10 @@ class Run:
 
     def __init__(self, design, np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0,
                  use_graph=1, fit_kernel=FIT_AUTO, tune=0, control=CONTROL_FIXED, trials=TRIALS_AUTO,
-                 stream=None):
+                 algo=ALGO_HWSDA, stream=None):
         self.design = design
         self.cfg = _config(np_, generations, F, CR, seed, inst, prec, gwo_variant, use_graph, fit_kernel, tune,
-                           control, trials)
+                           control, trials, algo)
         self.D = design.n
         h = C.c_void_p()
         create = lib().qpm_run_create_objective if isinstance(design, Objective) else lib().qpm_run_create
@@ -469,9 +486,12 @@ class Run:
 
 
 def run(design, np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0, use_graph=1,
-        fit_kernel=FIT_AUTO, stream=None, device="cuda"):
+        fit_kernel=FIT_AUTO, tune=0, control=CONTROL_FIXED, trials=TRIALS_AUTO, algo=ALGO_HWSDA, stream=None,
+        device="cuda"):
+    """The one-shot run (qpm_run) -> (best genes (D,), best bits (W,), RunStats)."""
     import torch
-    cfg = _config(np_, generations, F, CR, seed, inst, prec, gwo_variant, use_graph, fit_kernel)
+    cfg = _config(np_, generations, F, CR, seed, inst, prec, gwo_variant, use_graph, fit_kernel, tune, control,
+                  trials, algo)
     bx = torch.empty(design.n, dtype=torch.float32, device=device)
     bb = torch.empty(words(design.n), dtype=torch.int32, device=device)
     st = RunStats()

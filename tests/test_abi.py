@@ -121,14 +121,19 @@ def test_de_and_gwo_reject_bad_arguments(L):
     assert de_shape(1, 3) == -1 and "passes" in _err(L)
     assert de_shape(2, 2) == -1 and "np >= 4" in _err(L)  # a valid shape goes on to the usual checks
 
-    def gwo(np_=8, D=10, ldx=12, a=1.0, variant=0, leaders=C.c_void_p(0x40000000)):
-        return L.qpm_gwo_step(x, np_, D, ldx, leaders, C.c_float(a), 0, 0, 0, variant, u, b, 64, None)
+    def gwo(np_=8, D=10, ldx=12, a=1.0, variant=0, leaders=(0, 1, 2)):
+        lead = None if leaders is None else C.cast((C.c_int32 * 3)(*leaders), C.c_void_p)
+        return L.qpm_gwo_step(x, np_, D, ldx, lead, C.c_float(a), 0, 0, 0, variant, u, b, 64, None)
 
     assert gwo(np_=3) == -1
     assert gwo(a=-1.0) == -1
     assert gwo(a=1e-35) == -1 and "2^-100" in _err(L)
     assert gwo(variant=2) == -1
     assert gwo(leaders=None) == -1
+    # the leaders are host values, checked before any launch
+    assert gwo(leaders=(0, 1, 8)) == -1 and "outside" in _err(L)
+    assert gwo(leaders=(-1, 1, 2)) == -1 and "outside" in _err(L)
+    assert gwo(leaders=(3, 1, 3)) == -1 and "distinct" in _err(L)
 
 
 def test_run_rejects_bad_config(L):
@@ -152,6 +157,17 @@ def test_run_rejects_unknown_control_and_trial_storage(L):
         cfg = qpm._config(8, 5, **kw)
         assert L.qpm_run_create(fake, C.byref(cfg), None, C.byref(h)) == -1
         assert ("control" in _err(L)) or ("trial" in _err(L))
+    # unknown optimiser; the accepted-only trial storage belongs to the hybrid
+    for kw, word in [(dict(algo=3), "algorithm"), (dict(algo=-1), "algorithm"),
+                     (dict(algo=1, trials=2), "accepted-only"), (dict(algo=2, trials=2), "accepted-only")]:
+        cfg = qpm._config(8, 5, **kw)
+        assert L.qpm_run_create(fake, C.byref(cfg), None, C.byref(h)) == -1
+        assert word in _err(L)
+    # batched runs apply the hybrid only: DE or GWO alone is not supported there
+    for algo in (1, 2):
+        cfg = qpm._config(8, 5, algo=algo)
+        assert L.qpm_batch_run_create(fake, C.byref(cfg), 0, None, C.byref(h)) == -5
+        assert "hybrid" in _err(L)
     # the adaptive control is not offered on a multi-wavelength objective
     cfg = qpm._config(8, 5, control=2)
     assert L.qpm_run_create_objective(fake, C.byref(cfg), None, C.byref(h)) == -1
@@ -163,13 +179,17 @@ def test_discrete_gwo_and_objective_reject_bad_arguments(L):
     x = C.c_void_p(0x10000)
     y = C.c_void_p(0x20000)
     b = C.c_void_p(0x30000)
-    lead = C.c_void_p(0x40000)
+    lead = C.cast((C.c_int32 * 4)(0, 1, 2, 3), C.c_void_p)
     par = C.cast((C.c_float * 4)(0.5, 0.8, 0.1, 0.1), C.c_void_p)
     bad = C.cast((C.c_float * 4)(0.5, float("nan"), 0.1, 0.1), C.c_void_p)
     assert L.qpm_dgwo_step(x, 3, 10, 12, lead, par, 0, 0, 0, y, b, 64, None) == -1
     assert L.qpm_dgwo_step(x, 8, 10, 12, None, par, 0, 0, 0, y, b, 64, None) == -1
     assert L.qpm_dgwo_step(x, 8, 10, 12, lead, None, 0, 0, 0, y, b, 64, None) == -1
     assert L.qpm_dgwo_step(x, 8, 10, 12, lead, bad, 0, 0, 0, y, b, 64, None) == -1 and "finite" in _err(L)
+    for bad_lead in ((0, 1, 2, 8), (0, 1, 2, 2)):
+        bl = C.cast((C.c_int32 * 4)(*bad_lead), C.c_void_p)
+        assert L.qpm_dgwo_step(x, 8, 10, 12, bl, par, 0, 0, 0, y, b, 64, None) == -1
+        assert "outside" in _err(L) or "distinct" in _err(L)
     h = C.c_void_p()
     designs = (C.c_void_p * 9)(*([0x10000] * 9))
     assert L.qpm_objective_create(None, 1, 0, 1.0, 0.0, C.byref(h)) == -1
