@@ -76,7 +76,7 @@ __global__ __launch_bounds__(WAVES * 64) void batch_fit_kernel(const uint32_t *_
             if (wd + 1 < w1) next = bp[static_cast<int64_t>(wd + 1) * ld];
             const int64_t dom = (id.wofs + wd) * 32;
             if constexpr (F32)
-                scan_word_f32<32>(t, word, ph32 + dom);
+                scan_word_f32(t, word, ph64 + dom, ph32 + dom);
             else
                 scan_word_f64(t, word, ph64 + dom);
         }
@@ -112,7 +112,8 @@ __global__ __launch_bounds__(WAVES * 64) void batch_fit_kernel(const uint32_t *_
 template <bool F32, int GW>
 __global__ __launch_bounds__(GW * 256) void batch_fit_tab_kernel(const uint32_t *__restrict__ bits, int64_t ld,
                                                                  const double2 *__restrict__ tab64,
-                                                                 const float2 *__restrict__ tab32, int wpw,
+                                                                 const int2 *__restrict__ tabq,
+                                                                 const double *__restrict__ wsc, int wpw,
                                                                  int64_t np, const InstDesc *__restrict__ inst,
                                                                  const FitSeg *__restrict__ tab,
                                                                  double *__restrict__ part,
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(GW * 256) void batch_fit_tab_kernel(const uint32_t 
     const int64_t i = (static_cast<int64_t>(blockIdx.x) * GW + (threadIdx.x >> 8)) * 64 + (threadIdx.x & 63);
     Tri t;
     if (!tab_segment<F32, GW>(t, bits + id.wofs * ld, ld, static_cast<int>(id.words), fs.w0,
-                              tab64 + id.wofs * 8 * 48, tab32 + id.wofs * 8 * 48, wpw, np, lds))
+                              tab64 + id.wofs * 8 * 48, tabq + id.wofs * 8 * 48, wsc + id.wofs, wpw, np, lds))
         return;
     double *o = part + static_cast<int64_t>(fs.slot) * 6 * ld + i;
     o[0] = t.ar;
@@ -565,7 +566,8 @@ struct qpm_batch_s {
     double2 *c64 = nullptr;
     double *Cdev = nullptr;
     double2 *tab64 = nullptr;  // sign-pattern tables, [8 total_words][3][16]
-    float2 *tab32 = nullptr;
+    int2 *tabq = nullptr;      // their fixed-point form at the word scales
+    double *wsc = nullptr;     // [total_words] word scales (word_scales per instance)
 };
 
 static void free_batch(qpm_batch_s *b)
@@ -577,7 +579,8 @@ static void free_batch(qpm_batch_s *b)
     (void)hipFree(b->c64);
     (void)hipFree(b->Cdev);
     (void)hipFree(b->tab64);
-    (void)hipFree(b->tab32);
+    (void)hipFree(b->tabq);
+    (void)hipFree(b->wsc);
     delete b;
 }
 
@@ -600,6 +603,8 @@ QPM_API qpm_status qpm_precompute_phases_batched(const double *z, const int64_t 
             QPM_REQUIRE(std::isfinite(z[k]), QPM_EINVAL, "instance %d: z[%lld] not finite", (int)b, (long long)k);
         for (int64_t k = offsets[b]; k + 1 < offsets[b + 1]; ++k)
             QPM_REQUIRE(z[k + 1] > z[k], QPM_EINVAL, "instance %d: z must be strictly increasing", (int)b);
+        QPM_REQUIRE(z[offsets[b + 1] - 1] - z[offsets[b]] <= 1e100, QPM_EINVAL,
+                    "instance %d: the crystal length must be at most 1e100", (int)b);
         words += words_for(n);
         genes += ((n + 63) / 64) * 64;
     }
@@ -629,7 +634,11 @@ QPM_API qpm_status qpm_precompute_phases_batched(const double *z, const int64_t 
     if (e == hipSuccess) e = hipMalloc(&bt->c64, sizeof(double2) * 32 * words);
     if (e == hipSuccess) e = hipMalloc(&bt->Cdev, sizeof(double) * 2 * n_inst);
     if (e == hipSuccess) e = hipMalloc(&bt->tab64, sizeof(double2) * 48 * 8 * words);
-    if (e == hipSuccess) e = hipMalloc(&bt->tab32, sizeof(float2) * 48 * 8 * words);
+    if (e == hipSuccess) e = hipMalloc(&bt->tabq, sizeof(int2) * 48 * 8 * words);
+    if (e == hipSuccess) e = hipMalloc(&bt->wsc, sizeof(double) * words);
+    std::vector<double> wsc(words);
+    for (int32_t b = 0; b < n_inst; ++b) word_scales(z + offsets[b], bt->host[b].n, wsc.data() + bt->host[b].wofs);
+    if (e == hipSuccess) e = hipMemcpyAsync(bt->wsc, wsc.data(), sizeof(double) * words, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMalloc(&bt->dev, sizeof(InstDesc) * n_inst);
     if (e == hipSuccess) e = hipMalloc(&zdev, sizeof(double) * offsets[n_inst]);
     if (e == hipSuccess) e = hipMemcpyAsync(zdev, z, sizeof(double) * offsets[n_inst], hipMemcpyHostToDevice, s);
@@ -639,7 +648,7 @@ QPM_API qpm_status qpm_precompute_phases_batched(const double *z, const int64_t 
                           bt->c64 + 32 * d.wofs, bt->Cdev + 2 * b, s) != QPM_OK)
             e = hipErrorLaunchFailure;
     }
-    if (e == hipSuccess && launch_pattern_tables(bt->ph64, words, bt->tab64, bt->tab32, s) != QPM_OK)
+    if (e == hipSuccess && launch_pattern_tables(bt->ph64, words, bt->wsc, bt->tab64, bt->tabq, s) != QPM_OK)
         e = hipErrorLaunchFailure;
     std::vector<double> C(2 * n_inst);
     if (e == hipSuccess) e = hipMemcpyAsync(C.data(), bt->Cdev, sizeof(double) * 2 * n_inst, hipMemcpyDeviceToHost, s);
@@ -698,10 +707,11 @@ static qpm_status launch_batch_fit(const qpm_batch_s &bt, qpm_prec p, const uint
 #define QPM_BT_CASE(G)                                                                                             \
     case G:                                                                                                        \
         if (p == QPM_PREC_F32)                                                                                     \
-            batch_fit_tab_kernel<true, G><<<grid, G * 256, lds, s>>>(bits, ld, bt.tab64, bt.tab32, pl.wpw, np, bt.dev, \
+            batch_fit_tab_kernel<true, G><<<grid, G * 256, lds, s>>>(bits, ld, bt.tab64, bt.tabq, bt.wsc, pl.wpw, np,   \
+                                                                     bt.dev,                                      \
                                                                     segs_dev, part, advance);                      \
         else                                                                                                       \
-            batch_fit_tab_kernel<false, G><<<grid, G * 256, lds, s>>>(bits, ld, bt.tab64, bt.tab32, pl.wpw, np,      \
+            batch_fit_tab_kernel<false, G><<<grid, G * 256, lds, s>>>(bits, ld, bt.tab64, bt.tabq, bt.wsc, pl.wpw, np, \
                                                                      bt.dev, segs_dev, part, advance);             \
         break;
         switch (pl.gw) {

@@ -90,15 +90,25 @@ struct Design {
     double2 *c64 = nullptr;   // [n] diagonal terms c_n
     double *Cdev = nullptr;   // [2] C on the device
     double2 *tab64 = nullptr; // [8 W][A, B, Q][16 sign patterns] per 4-domain block
-    float2 *tab32 = nullptr;  // the same rounded to float
+    int2 *tabq = nullptr;     // the same for the FP32 kernels: A and B as fixed-point
+                              // integers at the word's scale, Q as float bits (word_tab_q)
+    double *wsc = nullptr;    // [W] the word scales 2^-e_w of tabq (word_scales)
     int device = 0;
     double z0 = 0, zN = 0;    // first and last boundary
     uint64_t zhash = 0;       // FNV-1a of the boundary bytes (designs sharing z)
     ScratchCache *scratch = nullptr;  // per-call scratch of the entry points on this design
 };
 
-// sign-pattern tables of the 8 W blocks of 4 domains (from ph64)
-qpm_status launch_pattern_tables(const double4 *ph64, int64_t words, double2 *tab64, float2 *tab32, hipStream_t s);
+// Word scales of the fixed-point tables: for word w, sc[w] = 2^-e with e
+// the largest integer such that M 2^e <= 2^31 - 64, M the sum of the word's
+// domain widths (every |A| and |B| of a stretch of the word is at most the
+// stretch's width sum, so the integer sums of a word stay below 2^31), with
+// e at most 60. Host arrays: z[0..n], sc[ceil(n / 32)].
+void word_scales(const double *z, int64_t n, double *sc);
+// sign-pattern tables of the 8 W blocks of 4 domains (from ph64): tab64 in
+// FP64, tabq in the fixed-point form at the scales wsc
+qpm_status launch_pattern_tables(const double4 *ph64, int64_t words, const double *wsc, double2 *tab64, int2 *tabq,
+                                 hipStream_t s);
 
 // per-domain tables of one design into caller buffers (npad = 32 W
 // entries of ph64 / ph32, n of c64) and C = sum c_n into Cdev[2]
@@ -172,7 +182,8 @@ constexpr int kMaxObjectiveDesigns = 8;
 
 // per-design table pointers and C, passed by value to the kernels
 struct ObjTabs {
-    const float2 *t32[kMaxObjectiveDesigns];
+    const int2 *tq[kMaxObjectiveDesigns];
+    const double *wsc[kMaxObjectiveDesigns];
     const double2 *t64[kMaxObjectiveDesigns];
     double C[kMaxObjectiveDesigns][2];
 };

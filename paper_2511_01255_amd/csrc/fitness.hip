@@ -42,7 +42,7 @@ __global__ __launch_bounds__(WAVES * 64) void fit_seg_kernel(const uint32_t *__r
             const uint32_t word = next;
             if (wd + 1 < w1) next = bp[static_cast<int64_t>(wd + 1) * ld];
             if constexpr (F32)
-                scan_word_f32<32>(t, word, ph32 + static_cast<int64_t>(wd) * 32);
+                scan_word_f32(t, word, ph64 + static_cast<int64_t>(wd) * 32, ph32 + static_cast<int64_t>(wd) * 32);
             else
                 scan_word_f64(t, word, ph64 + static_cast<int64_t>(wd) * 32);
         }
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(128) void fit_per_genome_kernel(const uint32_t *__r
 }
 
 // The table kernel: each 4-domain block contributes the precomputed triple
-// of its sign pattern (16 patterns per block, Design::tab32 / tab64), so a
+// of its sign pattern (16 patterns per block, Design::tabq / tab64), so a
 // domain evaluation costs a quarter of a pattern lookup plus one triple
 // append, instead of a complex multiply-add per domain:
 //   Q += A Bp + Qp,  A += Ap,  B += Bp   (complex; p = 4 bits of the word).
@@ -138,12 +138,14 @@ __global__ __launch_bounds__(128) void fit_per_genome_kernel(const uint32_t *__r
 // component row of 16 patterns is 128 bytes in FP32, so a wave's lookups
 // of one component hit distinct banks), each wave walks wpw words of its
 // segment, and the 4 segment triples of each genome are combined in LDS in
-// order. FP32: the lookups and sums of one word in binary32, each word's
-// triple folded into FP64; FP64: binary64 throughout.
+// order. FP32: the word's A and B summed exactly in fixed point, its Q in
+// binary32, each word's triple folded into FP64 (word_tab_q); FP64:
+// binary64 throughout.
 template <bool F32, int GW>
 __global__ __launch_bounds__(GW * 256) void fit_tab_kernel(const uint32_t *__restrict__ bits, int64_t ld, int W,
                                                            const double2 *__restrict__ tab64,
-                                                           const float2 *__restrict__ tab32, int wpw, int64_t np,
+                                                           const int2 *__restrict__ tabq,
+                                                           const double *__restrict__ wsc, int wpw, int64_t np,
                                                            double *__restrict__ part, const double *__restrict__ C,
                                                            void *__restrict__ fit, int direct, int out_f64,
                                                            uint32_t *__restrict__ advance)
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(GW * 256) void fit_tab_kernel(const uint32_t *__res
     const int wbase = static_cast<int>(blockIdx.y) * 4 * wpw;
     const int64_t i = (static_cast<int64_t>(blockIdx.x) * GW + (threadIdx.x >> 8)) * 64 + (threadIdx.x & 63);
     Tri t;
-    if (!tab_segment<F32, GW>(t, bits, ld, W, wbase, tab64, tab32, wpw, np, lds)) return;
+    if (!tab_segment<F32, GW>(t, bits, ld, W, wbase, tab64, tabq, wsc, wpw, np, lds)) return;
     if (direct) {
         store_fitness(fit, out_f64, i, t, C);
     } else {
@@ -189,7 +191,8 @@ static void launch_tab(const Design &d, const FitPlan &pl, const uint32_t *bits,
     const size_t lds = table_lds_bytes(d.words, F32, gw, pl.wpw);
 #define QPM_TAB_CASE(G)                                                                                       \
     case G:                                                                                                   \
-        fit_tab_kernel<F32, G><<<grid, dim3(G * 256), lds, s>>>(bits, ld, W, d.tab64, d.tab32, pl.wpw, np, part, \
+        fit_tab_kernel<F32, G><<<grid, dim3(G * 256), lds, s>>>(bits, ld, W, d.tab64, d.tabq, d.wsc, pl.wpw, np,  \
+                                                                part,                                         \
                                                                 d.Cdev, fit, direct, out_f64, advance);      \
         break;
     switch (gw) {

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void obj_partials_kernel(ObjTabs tabs, int K, 
     for (int kd = 0; kd < K; ++kd) {
         // design kd's table rows of words [wbase, wbase + nw) into LDS:
         // piece idx = ((word 8 + block) R + row) PPR + q
-        const unsigned char *src = F32 ? reinterpret_cast<const unsigned char *>(tabs.t32[kd])
+        const unsigned char *src = F32 ? reinterpret_cast<const unsigned char *>(tabs.tq[kd])
                                        : reinterpret_cast<const unsigned char *>(tabs.t64[kd]);
         for (int r0 = 0; r0 * 256 < n16; ++r0) {
             const int idx = r0 * 256 + static_cast<int>(threadIdx.x);
@@ -97,39 +97,8 @@ __global__ __launch_bounds__(256) void obj_partials_kernel(ObjTabs tabs, int K, 
             if (wr >= w1) break;
             const uint32_t word = live ? wv[k] : 0u;
             if constexpr (F32) {
-                const float2 *tb = reinterpret_cast<const float2 *>(lds) + wr * 8 * R * 16;
-                // the word's first block starts the sums (as appending it to
-                // zeros, up to the sign of a zero, which |.| does not see)
-                const uint32_t p0 = word & 15u;
-                const float2 A0 = tb[p0];
-                float ar = A0.x, ai = A0.y, br = 0.f, bi = 0.f, qr = 0.f, qi = 0.f;
-                if constexpr (THG) {
-                    const float2 B0 = tb[16 + p0], Q0 = tb[32 + p0];
-                    br = B0.x;
-                    bi = B0.y;
-                    qr = Q0.x;
-                    qi = Q0.y;
-                }
-#pragma unroll
-                for (int h = 1; h < 8; ++h) {
-                    const uint32_t pt = (word >> (4 * h)) & 15u;
-                    const float2 A = tb[(h * R) * 16 + pt];
-                    if constexpr (THG) {
-                        const float2 B = tb[(h * R + 1) * 16 + pt], Q = tb[(h * R + 2) * 16 + pt];
-                        qr = fmaf(-ai, B.y, fmaf(ar, B.x, qr + Q.x));
-                        qi = fmaf(ai, B.x, fmaf(ar, B.y, qi + Q.y));
-                        br += B.x;
-                        bi += B.y;
-                    }
-                    ar += A.x;
-                    ai += A.y;
-                }
-                if constexpr (THG)
-                    tri_append(t, Tri{ar, ai, br, bi, qr, qi});
-                else {
-                    t.ar += ar;
-                    t.ai += ai;
-                }
+                word_tab_q<R>(t, word, reinterpret_cast<const int2 *>(lds) + wr * 8 * R * 16,
+                              tabs.wsc[kd][wbase + wr]);
             } else {
                 const double2 *tb = reinterpret_cast<const double2 *>(lds) + wr * 8 * R * 16;
 #pragma unroll
@@ -403,7 +372,8 @@ QPM_API qpm_status qpm_objective_create(const qpm_design *designs, int32_t K, in
     o->words = d0->words;
     for (int k = 0; k < K; ++k) {
         o->d[k] = designs[k];
-        o->tabs.t32[k] = designs[k]->tab32;
+        o->tabs.tq[k] = designs[k]->tabq;
+        o->tabs.wsc[k] = designs[k]->wsc;
         o->tabs.t64[k] = designs[k]->tab64;
         o->tabs.C[k][0] = designs[k]->C[0];
         o->tabs.C[k][1] = designs[k]->C[1];

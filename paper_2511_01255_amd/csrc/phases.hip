@@ -177,9 +177,12 @@ __global__ __launch_bounds__(256) void sum_c_kernel(const double2 *__restrict__ 
 //   A = sum_k d_k a_k,  B = sum_k d_k b_k,  Q = sum_k d_k b_k sum_{m<k} d_m a_m,
 // in FP64 from the FP64 integrals (padding domains have a = b = 0). Layout
 // [q][A, B, Q][p], one complex value per entry, so the 16 patterns of one
-// component are one contiguous row.
+// component are one contiguous row. The fixed-point copy for the FP32
+// kernels holds A 2^e and B 2^e rounded to integers and Q 2^(2e) rounded to
+// float, e the scale exponent of the block's word (wsc = 2^-e).
 __global__ __launch_bounds__(256) void pattern_table_kernel(const double4 *__restrict__ ph64, int64_t nblocks,
-                                                            double2 *__restrict__ tab64, float2 *__restrict__ tab32)
+                                                            const double *__restrict__ wsc,
+                                                            double2 *__restrict__ tab64, int2 *__restrict__ tabq)
 {
     const int64_t tid = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (tid >= nblocks * 16) return;
@@ -200,19 +203,35 @@ __global__ __launch_bounds__(256) void pattern_table_kernel(const double4 *__res
     o[0] = make_double2(ar, ai);
     o[16] = make_double2(br, bi);
     o[32] = make_double2(qr, qi);
-    float2 *f = tab32 + q * 48 + p;
-    f[0] = make_float2(static_cast<float>(ar), static_cast<float>(ai));
-    f[16] = make_float2(static_cast<float>(br), static_cast<float>(bi));
-    f[32] = make_float2(static_cast<float>(qr), static_cast<float>(qi));
+    const double up = 1.0 / wsc[q >> 3];  // 2^e, exact
+    const double up2 = up * up;
+    int2 *f = tabq + q * 48 + p;
+    f[0] = make_int2(__double2int_rn(ar * up), __double2int_rn(ai * up));
+    f[16] = make_int2(__double2int_rn(br * up), __double2int_rn(bi * up));
+    f[32] = make_int2(__float_as_int(static_cast<float>(qr * up2)), __float_as_int(static_cast<float>(qi * up2)));
 }
 
-qpm_status launch_pattern_tables(const double4 *ph64, int64_t words, double2 *tab64, float2 *tab32, hipStream_t s)
+qpm_status launch_pattern_tables(const double4 *ph64, int64_t words, const double *wsc, double2 *tab64, int2 *tabq,
+                                 hipStream_t s)
 {
     const int64_t nblocks = words * 8;
-    pattern_table_kernel<<<static_cast<unsigned>((nblocks * 16 + 255) / 256), 256, 0, s>>>(ph64, nblocks, tab64,
-                                                                                           tab32);
+    pattern_table_kernel<<<static_cast<unsigned>((nblocks * 16 + 255) / 256), 256, 0, s>>>(ph64, nblocks, wsc, tab64,
+                                                                                           tabq);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
+}
+
+void word_scales(const double *z, int64_t n, double *sc)
+{
+    const double lim = 2147483648.0 - 64.0;  // 2^31 - 64
+    const int64_t W = words_for(n);
+    for (int64_t w = 0; w < W; ++w) {
+        const double M = z[std::min<int64_t>(32 * w + 32, n)] - z[32 * w];
+        int e = 30 - std::ilogb(M);  // M 2^e < 2^31
+        if (std::ldexp(M, e) > lim) --e;
+        e = std::min(e, 60);
+        sc[w] = std::ldexp(1.0, -e);
+    }
 }
 
 qpm_status launch_phases(const double *zdev, int64_t n, double dk1, double dk2, double4 *ph64, float4 *ph32,
@@ -237,7 +256,8 @@ static void free_design(Design *d)
     (void)hipFree(d->c64);
     (void)hipFree(d->Cdev);
     (void)hipFree(d->tab64);
-    (void)hipFree(d->tab32);
+    (void)hipFree(d->tabq);
+    (void)hipFree(d->wsc);
     scratch_cache_destroy(d->scratch);
     delete static_cast<qpm_design_s *>(d);
 }
@@ -259,6 +279,7 @@ QPM_API qpm_status qpm_precompute_phases(const double *z, int64_t n, double dk1,
     for (int64_t i = 0; i < n; ++i)
         QPM_REQUIRE(z[i + 1] > z[i], QPM_EINVAL, "z must be strictly increasing (z[%lld] >= z[%lld])",
                     (long long)i, (long long)(i + 1));
+    QPM_REQUIRE(z[n] - z[0] <= 1e100, QPM_EINVAL, "the crystal length z[n] - z[0] must be at most 1e100");
     qpm_status st = check_device();
     if (st != QPM_OK) return st;
 
@@ -285,7 +306,8 @@ QPM_API qpm_status qpm_precompute_phases(const double *z, int64_t n, double dk1,
     if (e == hipSuccess) e = hipMalloc(&d->c64, sizeof(double2) * n);
     if (e == hipSuccess) e = hipMalloc(&d->Cdev, sizeof(double) * 2);
     if (e == hipSuccess) e = hipMalloc(&d->tab64, sizeof(double2) * 48 * 8 * d->words);
-    if (e == hipSuccess) e = hipMalloc(&d->tab32, sizeof(float2) * 48 * 8 * d->words);
+    if (e == hipSuccess) e = hipMalloc(&d->tabq, sizeof(int2) * 48 * 8 * d->words);
+    if (e == hipSuccess) e = hipMalloc(&d->wsc, sizeof(double) * d->words);
     if (e == hipSuccess) e = hipMalloc(&zdev, sizeof(double) * (n + 1));
     if (e != hipSuccess) {
         (void)hipFree(zdev);
@@ -293,10 +315,13 @@ QPM_API qpm_status qpm_precompute_phases(const double *z, int64_t n, double dk1,
         set_error("device allocation for a design of %lld domains failed: %s", (long long)n, hipGetErrorString(e));
         return QPM_ENOMEM;
     }
+    std::vector<double> wsc(d->words);
+    word_scales(z, n, wsc.data());
     e = hipMemcpyAsync(zdev, z, sizeof(double) * (n + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d->wsc, wsc.data(), sizeof(double) * d->words, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && launch_phases(zdev, n, dk1, dk2, d->ph64, d->ph32, d->c64, d->Cdev, s) != QPM_OK)
         e = hipErrorLaunchFailure;
-    if (e == hipSuccess && launch_pattern_tables(d->ph64, d->words, d->tab64, d->tab32, s) != QPM_OK)
+    if (e == hipSuccess && launch_pattern_tables(d->ph64, d->words, d->wsc, d->tab64, d->tabq, s) != QPM_OK)
         e = hipErrorLaunchFailure;
     if (e == hipSuccess) e = hipMemcpyAsync(d->C, d->Cdev, sizeof(double) * 2, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -127,29 +127,77 @@ __device__ __forceinline__ void scan_word_f64(Tri &t, uint32_t word, const doubl
     }
 }
 
-// One word in FP32 blocks of BLK domains, each block folded into FP64.
-template <int BLK>
-__device__ __forceinline__ void scan_word_f32(Tri &t, uint32_t word, const float4 *__restrict__ p)
+// One word in the FP32 form of the per-domain walk: the word's sums A and B
+// in FP64 (they multiply, and are carried into, the long prefix of the
+// design, where FP32 rounding would accumulate coherently over periodic
+// sign patterns), its own Q in FP32 from a float copy of the running A and
+// the float b; the word's triple is folded into t in FP64.
+__device__ __forceinline__ void scan_word_f32(Tri &t, uint32_t word, const double4 *__restrict__ p64,
+                                              const float4 *__restrict__ p32)
 {
+    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+    float qr = 0.f, qi = 0.f;
 #pragma unroll
-    for (int h = 0; h < 32 / BLK; ++h) {
-        float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f, qr = 0.f, qi = 0.f;
+    for (int k = 0; k < 32; ++k) {
+        const double4 c = p64[k];
+        const float4 cf = p32[k];
+        const double sd = sign64(word, k);
+        const float s = sign32(word, k);
+        const float fr = static_cast<float>(ar), fi = static_cast<float>(ai);
+        const float tr = fmaf(cf.z, fr, -(cf.w * fi));
+        const float ti = fmaf(cf.z, fi, cf.w * fr);
+        qr = fmaf(s, tr, qr);
+        qi = fmaf(s, ti, qi);
+        ar = fma(sd, c.x, ar);
+        ai = fma(sd, c.y, ai);
+        br = fma(sd, c.z, br);
+        bi = fma(sd, c.w, bi);
+    }
+    tri_append(t, Tri{ar, ai, br, bi, qr, qi});
+}
+
+// One word of the FP32 table walk. tb: the word's 8 blocks x R table rows x
+// 16 patterns (row 0 A, then B and Q when R = 3): A and B are fixed-point
+// integers at the word's scale 2^e and Q holds the float bits of Q 2^(2e);
+// sc = 2^-e. A and B are summed exactly in 32-bit integers (the word scale
+// keeps every partial sum below 2^31), the word's Q in FP32 from float
+// copies of the running A and of B; the triple (only A when R = 1) is
+// scaled back exactly and folded into t in FP64.
+template <int R>
+__device__ __forceinline__ void word_tab_q(Tri &t, uint32_t word, const int2 *__restrict__ tb, double sc)
+{
+    const uint32_t p0 = word & 15u;
+    const int2 A0 = tb[p0];
+    int ar = A0.x, ai = A0.y;
+    if constexpr (R == 1) {
 #pragma unroll
-        for (int kk = 0; kk < BLK; ++kk) {
-            const int k = h * BLK + kk;
-            const float4 c = p[k];
-            const float s = sign32(word, k);
-            const float tr = fmaf(c.z, ar, -(c.w * ai));
-            const float ti = fmaf(c.z, ai, c.w * ar);
-            qr = fmaf(s, tr, qr);
-            qi = fmaf(s, ti, qi);
-            ar = fmaf(s, c.x, ar);
-            ai = fmaf(s, c.y, ai);
-            br = fmaf(s, c.z, br);
-            bi = fmaf(s, c.w, bi);
+        for (int h = 1; h < 8; ++h) {
+            const int2 A = tb[h * 16 + ((word >> (4 * h)) & 15u)];
+            ar += A.x;
+            ai += A.y;
         }
-        const Tri u{ar, ai, br, bi, qr, qi};
-        tri_append(t, u);
+        t.ar += static_cast<double>(ar) * sc;
+        t.ai += static_cast<double>(ai) * sc;
+    } else {
+        const int2 B0 = tb[16 + p0], Q0 = tb[32 + p0];
+        int br = B0.x, bi = B0.y;
+        float qr = __int_as_float(Q0.x), qi = __int_as_float(Q0.y);
+#pragma unroll
+        for (int h = 1; h < 8; ++h) {
+            const uint32_t pt = (word >> (4 * h)) & 15u;
+            const int2 A = tb[h * R * 16 + pt], B = tb[(h * R + 1) * 16 + pt], Q = tb[(h * R + 2) * 16 + pt];
+            const float fr = static_cast<float>(ar), fi = static_cast<float>(ai);
+            const float bx = static_cast<float>(B.x), by = static_cast<float>(B.y);
+            qr = fmaf(-fi, by, fmaf(fr, bx, qr + __int_as_float(Q.x)));
+            qi = fmaf(fi, bx, fmaf(fr, by, qi + __int_as_float(Q.y)));
+            ar += A.x;
+            ai += A.y;
+            br += B.x;
+            bi += B.y;
+        }
+        const double sc2 = sc * sc;
+        tri_append(t, Tri{static_cast<double>(ar) * sc, static_cast<double>(ai) * sc, static_cast<double>(br) * sc,
+                          static_cast<double>(bi) * sc, static_cast<double>(qr) * sc2, static_cast<double>(qi) * sc2});
     }
 }
 
@@ -161,11 +209,12 @@ __device__ __forceinline__ void scan_word_f32(Tri &t, uint32_t word, const float
 // genome are folded in order. Returns true (with the workgroup's triple in
 // t) in the first segment wave of each group for genomes i < np, where
 // i = (blockIdx.x GW + group) 64 + lane. Every lane of the workgroup must
-// call it (it synchronises the workgroup).
+// call it (it synchronises the workgroup). FP32 walks the fixed-point
+// tables tabq at the word scales wsc (word_tab_q), FP64 the tables tab64.
 template <bool F32, int GW>
 __device__ __forceinline__ bool tab_segment(Tri &t, const uint32_t *__restrict__ bits, int64_t ld, int W, int wbase,
-                                            const double2 *__restrict__ tab64, const float2 *__restrict__ tab32,
-                                            int wpw, int64_t np, unsigned char *lds)
+                                            const double2 *__restrict__ tab64, const int2 *__restrict__ tabq,
+                                            const double *__restrict__ wsc, int wpw, int64_t np, unsigned char *lds)
 {
     constexpr int SW = 4;
     constexpr int NT = GW * 256;
@@ -179,7 +228,7 @@ __device__ __forceinline__ bool tab_segment(Tri &t, const uint32_t *__restrict__
     // per lane per load, no registers, no wait between loads)
     {
         const int n16 = nw * 8 * 48 * (F32 ? 8 : 16) / 16;
-        const uint4 *src = F32 ? reinterpret_cast<const uint4 *>(tab32 + static_cast<int64_t>(wbase) * 8 * 48)
+        const uint4 *src = F32 ? reinterpret_cast<const uint4 *>(tabq + static_cast<int64_t>(wbase) * 8 * 48)
                                : reinterpret_cast<const uint4 *>(tab64 + static_cast<int64_t>(wbase) * 8 * 48);
         for (int k = 0; k * NT < n16; ++k) {
             const int idx = k * NT + static_cast<int>(threadIdx.x);
@@ -212,25 +261,7 @@ __device__ __forceinline__ bool tab_segment(Tri &t, const uint32_t *__restrict__
         if (wr >= w1) break;
         const uint32_t word = live ? wv[k] : 0u;
         if constexpr (F32) {
-            const float2 *tb = reinterpret_cast<const float2 *>(lds) + wr * 8 * 48;
-            // the word's first block starts the sums (the same values as
-            // appending it to zeros, up to the sign of a zero, which |S|^2
-            // does not see); the pattern of block h is bits 4h..4h+3
-            const uint32_t p0 = word & 15u;
-            const float2 A0 = tb[p0], B0 = tb[16 + p0], Q0 = tb[32 + p0];
-            float ar = A0.x, ai = A0.y, br = B0.x, bi = B0.y, qr = Q0.x, qi = Q0.y;
-#pragma unroll
-            for (int h = 1; h < 8; ++h) {
-                const uint32_t pt = (word >> (4 * h)) & 15u;
-                const float2 A = tb[h * 48 + pt], B = tb[h * 48 + 16 + pt], Q = tb[h * 48 + 32 + pt];
-                qr = fmaf(-ai, B.y, fmaf(ar, B.x, qr + Q.x));
-                qi = fmaf(ai, B.x, fmaf(ar, B.y, qi + Q.y));
-                ar += A.x;
-                ai += A.y;
-                br += B.x;
-                bi += B.y;
-            }
-            tri_append(t, Tri{ar, ai, br, bi, qr, qi});
+            word_tab_q<3>(t, word, reinterpret_cast<const int2 *>(lds) + wr * 8 * 48, wsc[wbase + wr]);
         } else {
             const double2 *tb = reinterpret_cast<const double2 *>(lds) + wr * 8 * 48;
 #pragma unroll

@@ -490,6 +490,29 @@ def test_run_fp32_lockstep(q, orc):
     R = q.Run(D, npop, G, F=F, CR=CR, seed=seed, prec=0)
     adoptions = sum(_lockstep_generation(orc, O, R, g, G, F, CR, seed) for g in range(G))
     print("FP32 lockstep: %d generations, %d adopted near-tie decisions" % (G, adoptions))
+    assert adoptions <= max(2, G * (2 * npop - 3) // 1000), adoptions
+    R.destroy()
+
+
+def test_hwsda_workload_lockstep_50_generations(q, orc):
+    # the full HWSDA workload (N = 10^4 x 2 um, NP = 1024, G = 5000,
+    # F = 0.5, CR = 0.9, a from 2 to 0, seed 0, FP32 fitness) in its
+    # benchmark launch configuration (tuned shapes, graph replay): the first
+    # 50 generations, every row of each against the oracle's replay. A
+    # decision may go the other way only on a near-tie (|f_u - f_x| within
+    # twice the FP32 tolerance); such adoptions must stay rare: at most one
+    # per 1000 of the 50 x (2 NP - 3) decisions.
+    n, npop, G, F, CR, seed = 10000, 1024, 5000, 0.5, 0.9, 0
+    z = inputs.uniform_boundaries(n, 2.0)
+    D = q.precompute_phases(z, DK1, DK2)
+    O = orc.Design(z, DK1, DK2)
+    R = q.Run(D, npop, G, F=F, CR=CR, seed=seed, prec=0, tune=1)
+    gens = 50
+    adoptions = sum(_lockstep_generation(orc, O, R, g, G, F, CR, seed) for g in range(gens))
+    decisions = gens * (2 * npop - 3)
+    print("HWSDA workload lockstep: %d generations, %d of %d decisions adopted near ties"
+          % (gens, adoptions, decisions))
+    assert adoptions <= decisions // 1000
     R.destroy()
 
 
@@ -510,6 +533,7 @@ def test_full_size_generation_lockstep(q, orc):
     R.load(torch.from_numpy(np.ascontiguousarray(mag * d.astype(np.float32))).cuda())
     adoptions = sum(_lockstep_generation(orc, O, R, g, G, F, CR, seed) for g in range(2))
     print("full-size lockstep: 2 generations, %d adopted near-tie decisions" % adoptions)
+    assert adoptions <= max(2, 2 * (2 * npop - 3) // 1000), adoptions
     R.destroy()
 
 
