@@ -180,9 +180,9 @@ size_t table_lds_bytes(int64_t W, bool f32, int gw, int wpw)
 }
 
 template <bool F32>
-static void launch_tab(const Design &d, const FitPlan &pl, const uint32_t *bits, int64_t np, int64_t ld,
-                       double *part, void *fit, int out_f64, bool direct_ok, hipStream_t s,
-                       uint32_t *advance = nullptr)
+static qpm_status launch_tab(const Design &d, const FitPlan &pl, const uint32_t *bits, int64_t np, int64_t ld,
+                             double *part, void *fit, int out_f64, bool direct_ok, hipStream_t s,
+                             uint32_t *advance = nullptr)
 {
     const int gw = pl.waves;
     const dim3 grid(static_cast<unsigned>((np + 64 * gw - 1) / (64 * gw)), static_cast<unsigned>(pl.gy));
@@ -199,15 +199,16 @@ static void launch_tab(const Design &d, const FitPlan &pl, const uint32_t *bits,
         QPM_TAB_CASE(1)
         QPM_TAB_CASE(2)
         QPM_TAB_CASE(4)
-    default: break;
+    default: QPM_REQUIRE(false, QPM_EINVAL, "unsupported genome groups per workgroup %d", gw);
     }
 #undef QPM_TAB_CASE
+    return QPM_OK;
 }
 
 template <bool F32>
-static void launch_seg(const Design &d, const FitPlan &pl, const uint32_t *bits, int64_t np, int64_t ld,
-                       double *part, void *fit, int out_f64, bool direct_ok, hipStream_t s,
-                       uint32_t *advance = nullptr)
+static qpm_status launch_seg(const Design &d, const FitPlan &pl, const uint32_t *bits, int64_t np, int64_t ld,
+                             double *part, void *fit, int out_f64, bool direct_ok, hipStream_t s,
+                             uint32_t *advance = nullptr)
 {
     const dim3 grid(static_cast<unsigned>((np + 63) / 64), static_cast<unsigned>(pl.gy));
     const int direct = direct_ok && pl.gy == 1;
@@ -223,9 +224,10 @@ static void launch_seg(const Design &d, const FitPlan &pl, const uint32_t *bits,
         QPM_SEG_CASE(4)
         QPM_SEG_CASE(8)
         QPM_SEG_CASE(16)
-    default: break;
+    default: QPM_REQUIRE(false, QPM_EINVAL, "unsupported waves per workgroup %d", pl.waves);
     }
 #undef QPM_SEG_CASE
+    return QPM_OK;
 }
 
 FitPlan plan_fitness_table(const Design &d, qpm_prec p, int gw, int wpw)
@@ -303,16 +305,14 @@ qpm_status launch_fitness(const Design &d, qpm_prec p, const uint32_t *bits, int
         fit_per_genome_kernel<<<blocks, 128, 0, s>>>(bits, ld, static_cast<int>(d.words), d.ph64, np, d.Cdev,
                                                      static_cast<double *>(fit), nullptr, nullptr);
     } else {
-        if (pl.kind == QPM_FIT_TABLE) {
-            if (p == QPM_PREC_F32)
-                launch_tab<true>(d, pl, bits, np, ld, part, fit, out_f64, true, s);
-            else
-                launch_tab<false>(d, pl, bits, np, ld, part, fit, out_f64, true, s);
-        } else if (p == QPM_PREC_F32) {
-            launch_seg<true>(d, pl, bits, np, ld, part, fit, out_f64, true, s);
-        } else {
-            launch_seg<false>(d, pl, bits, np, ld, part, fit, out_f64, true, s);
-        }
+        qpm_status st;
+        if (pl.kind == QPM_FIT_TABLE)
+            st = p == QPM_PREC_F32 ? launch_tab<true>(d, pl, bits, np, ld, part, fit, out_f64, true, s)
+                                   : launch_tab<false>(d, pl, bits, np, ld, part, fit, out_f64, true, s);
+        else
+            st = p == QPM_PREC_F32 ? launch_seg<true>(d, pl, bits, np, ld, part, fit, out_f64, true, s)
+                                   : launch_seg<false>(d, pl, bits, np, ld, part, fit, out_f64, true, s);
+        if (st != QPM_OK) return st;
         if (pl.gy > 1) {
             const unsigned blocks = static_cast<unsigned>((np + 63) / 64);
             fit_combine_kernel<<<blocks, 256, 0, s>>>(part, pl.gy, ld, np, d.Cdev, fit, out_f64);
@@ -329,15 +329,15 @@ qpm_status launch_fitness_partials(const Design &d, qpm_prec p, const uint32_t *
         const unsigned blocks = static_cast<unsigned>((np + 127) / 128);
         fit_per_genome_kernel<<<blocks, 128, 0, s>>>(bits, ld, static_cast<int>(d.words), d.ph64, np, d.Cdev,
                                                      nullptr, part, advance);
-    } else if (pl.kind == QPM_FIT_TABLE) {
-        if (p == QPM_PREC_F32)
-            launch_tab<true>(d, pl, bits, np, ld, part, nullptr, 0, false, s, advance);
-        else
-            launch_tab<false>(d, pl, bits, np, ld, part, nullptr, 1, false, s, advance);
-    } else if (p == QPM_PREC_F32) {
-        launch_seg<true>(d, pl, bits, np, ld, part, nullptr, 0, false, s, advance);
     } else {
-        launch_seg<false>(d, pl, bits, np, ld, part, nullptr, 1, false, s, advance);
+        qpm_status st;
+        if (pl.kind == QPM_FIT_TABLE)
+            st = p == QPM_PREC_F32 ? launch_tab<true>(d, pl, bits, np, ld, part, nullptr, 0, false, s, advance)
+                                   : launch_tab<false>(d, pl, bits, np, ld, part, nullptr, 1, false, s, advance);
+        else
+            st = p == QPM_PREC_F32 ? launch_seg<true>(d, pl, bits, np, ld, part, nullptr, 0, false, s, advance)
+                                   : launch_seg<false>(d, pl, bits, np, ld, part, nullptr, 1, false, s, advance);
+        if (st != QPM_OK) return st;
     }
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
