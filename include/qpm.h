@@ -133,6 +133,22 @@ qpm_status qpm_eval_fitness(qpm_design d, qpm_prec p, const uint32_t *bits, int6
                             int64_t ld, void *fitness, int32_t kernel, qpm_stream s);
 
 /*
+ * qpm_eval_fitness_noalloc -- qpm_eval_fitness for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): same arguments, launch plan and
+ * results (bit for bit), but the segment partials live in a fixed 16 MiB
+ * device array of the library, one per device, held until the process
+ * ends; the call allocates and frees nothing. Every call on a device shares
+ * that device's array, so calls that overlap on one device (other streams,
+ * other threads) race; the caller orders them. Errors: as qpm_eval_fitness,
+ * and QPM_ERANGE when the population needs more than 16 MiB of partials
+ * (6 doubles per genome column ld and workgroup segment; the 4096 x 10^4
+ * fitness workload needs 3.1 MB).
+ */
+qpm_status qpm_eval_fitness_noalloc(qpm_design d, qpm_prec p, const uint32_t *bits, int64_t np,
+                                    int64_t ld, void *fitness, int32_t kernel, qpm_stream s);
+
+/*
  * qpm_eval_fitness_shape -- qpm_eval_fitness with the segmented kernel's
  * launch shape given explicitly (for tuning): waves_per_group in
  * {1, 2, 4, 8, 16} waves of 64 genomes share one workgroup and scan

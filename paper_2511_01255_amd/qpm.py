@@ -68,6 +68,7 @@ _SIGS = {
     "qpm_design_info": (_I32, [_P, _P, _P]),
     "qpm_design_read_phases": (_I32, [_P, _P, _P, _P]),
     "qpm_eval_fitness": (_I32, [_P, _I32, _P, _I64, _I64, _P, _I32, _P]),
+    "qpm_eval_fitness_noalloc": (_I32, [_P, _I32, _P, _I64, _I64, _P, _I32, _P]),
     "qpm_eval_fitness_shape": (_I32, [_P, _I32, _P, _I64, _I64, _P, _I32, _I32, _P]),
     "qpm_eval_fitness_table_shape": (_I32, [_P, _I32, _P, _I64, _I64, _P, _I32, _I32, _P]),
     "qpm_init_population": (_I32, [_I64, _I64, _I64, _U64, _U32, _P, _P, _I64, _P]),
@@ -246,6 +247,17 @@ def eval_objective(obj, bits, np_, prec=PREC_F32, with_G=False, words_per_wave=N
         _check(lib().qpm_eval_objective_shape(obj.handle, prec, _ptr(bits), np_, bits.shape[1], _ptr(f), _ptr(G),
                                               np_, words_per_wave, _stream(stream)))
     return (f, G) if with_G else f
+
+
+def eval_fitness_noalloc(design, bits, np_, prec=PREC_F32, kernel=FIT_AUTO, out=None, stream=None):
+    """eval_fitness through qpm_eval_fitness_noalloc (no device allocation in
+    the library; out must be given by callers that cannot allocate)."""
+    import torch
+    if out is None:
+        out = torch.empty(np_, dtype=torch.float64 if prec == PREC_F64 else torch.float32, device=bits.device)
+    _check(lib().qpm_eval_fitness_noalloc(design.handle, prec, _ptr(bits), np_, bits.shape[1], _ptr(out), kernel,
+                                          _stream(stream)))
+    return out
 
 
 def eval_fitness_shape(design, bits, np_, prec, waves_per_group, words_per_wave, out=None, stream=None):
