@@ -35,35 +35,67 @@ METRIC = ("domain-evaluations/sec (NP×N per s) of |d_eff|^2; HWSDA generations/
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, GB/s
 PEAK_FP32_TFLOPS = 157.3     # vector FP32 (packed), TFLOP/s
 PEAK_FP64_TFLOPS = 78.6      # vector FP64, TFLOP/s
-PEAK_VALU_TOPS = 39.3        # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, lane-instructions/s (x1e12)
 # FP32 FMA without packed instructions (the library is built with packed
-# FP32 disabled): 39.3e12 lane-instructions/s x 2 flops
+# FP32 disabled): 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
 PEAK_FP32_NONPACKED_TFLOPS = 78.6
+# LDS: 256 CU x 128 B/clk x 2.4 GHz (64-bit reads; 128-bit reads were
+# measured at about twice that on this chip)
+PEAK_LDS_TBS = 78.6
 
 N_DOMAINS, NP, WIDTH = 10000, 4096, 2.0
 F, CR, SEED = 0.5, 0.9, 0
-# The grey-wolf update's minimal VALU work per gene, in lane-instructions:
-# Philox4x32-10 at 0.75 calls per gene x 10 rounds x (2 v_mad_u64_u32 +
-# 2 three-input xors) = 30; per leader two 16-bit conversions, A (1 FMA),
-# C X_k (multiply + FMA), Y_k (1 FMA) = 6, x 3 = 18; the combination: |Y|
-# sum (2), numerator (3), the division's short form for weights in range
-# (reciprocal and 7 FMA / multiply), x / 3 (3), range test (1), clamp (1),
-# sign bit (1) = 19.
-GWO_INSTR_PER_GENE = 30 + 18 + 19
 
 
-def algorithmic_work(step, npop, n):
-    """(bound, work per launch, unit) of one generation step; work is the
-    algorithmic bytes or operations of one launch."""
+def algorithmic_work(step, npop, n, lazy=True):
+    """Algorithmic work of one launch of a generation step, per unit of work
+    times the units one launch processes:
+      gwo      8 B of HBM per gene of the np - 3 moving wolves (gene read,
+               candidate written; leader rows are cache-resident) and about
+               25 FP32 flops per gene;
+      de       4 B of HBM per gene (target read) plus 1/8 B of trial bits,
+               and 4 B more for the trial genes when every trial is stored
+               (lazy = False; with accepted-only trials, the runs' choice
+               at this size, the accepted genes are written after the
+               selection, in the finish step); the three donor rows (12 B
+               per gene) are served from the last-level cache and counted
+               apart;
+      fitness  10 FP32 flops per domain evaluation (np N per pass) and 6 B
+               of LDS table reads per domain evaluation (one 24-byte
+               triple per 4-domain block); the bit words, 1/8 B each.
+    Returns a dict of {quantity: amount}."""
     genes = npop * n
-    bits = genes / 8.0
-    if step == "de":          # target + 3 donors read, trial written, trial bits
-        return "hbm", 20.0 * genes + bits, "B"
-    if step == "gwo":         # VALU lane-instructions of the non-leader genes
-        return "alu", GWO_INSTR_PER_GENE * (npop - 3) * n, "instr"
-    if step.startswith("fitness"):  # 10 flops per domain evaluation, bits read
-        return "alu", 10.0 * genes, "flop"
-    return "latency", 0.0, ""
+    if step == "gwo":
+        return {"hbm_bytes": 8.0 * (npop - 3) * n, "fp32_flops": 25.0 * (npop - 3) * n}
+    if step == "de":
+        return {"hbm_bytes": (4.125 if lazy else 8.125) * genes, "l2_bytes": 12.0 * genes}
+    if step.startswith("fitness"):
+        return {"fp32_flops": 10.0 * genes, "lds_bytes": 6.0 * genes, "hbm_bytes": genes / 8.0}
+    return {}
+
+
+def roofline_of(step, npop, n, seconds, f64=False):
+    """The roofline entry of one step from its algorithmic work and its
+    measured time per launch: the bound, achieved / peak and the fraction,
+    plus the other fractions of the same work."""
+    w = algorithmic_work(step, npop, n)
+    if not w or seconds <= 0:
+        return None
+    fl_peak = PEAK_FP64_TFLOPS if f64 else PEAK_FP32_TFLOPS
+    if step.startswith("fitness"):
+        ach = w["fp32_flops"] / seconds / 1e12
+        r = {"bound": "alu", "achieved": ach, "peak": fl_peak, "unit": "TFLOP/s", "frac": ach / fl_peak,
+             "frac_of_nonpacked_fp32": ach / PEAK_FP32_NONPACKED_TFLOPS,
+             "lds_tbs": w["lds_bytes"] / seconds / 1e12,
+             "lds_frac": w["lds_bytes"] / seconds / 1e12 / PEAK_LDS_TBS}
+    else:
+        ach = w["hbm_bytes"] / seconds / 1e9
+        r = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS}
+        if "fp32_flops" in w:
+            r["fp32_tflops"] = w["fp32_flops"] / seconds / 1e12
+            r["fp32_frac_of_nonpacked"] = r["fp32_tflops"] / PEAK_FP32_NONPACKED_TFLOPS
+        if "l2_bytes" in w:
+            r["l2_tbs_donor_reads"] = w["l2_bytes"] / seconds / 1e12
+    return r
 
 
 KERNEL_SOURCES = {  # the files a kernel's code comes from (traffic records are tied to them)
@@ -207,22 +239,16 @@ def main():
     R.destroy()
     per = {k: v / ng for k, v in ms.items()}
     out["kernel_ms"] = per
-    dom = max(per, key=per.get)
-    bound, work, wunit = algorithmic_work(dom, NP, N_DOMAINS)
-    t_dom = per[dom] * 1e-3
-    if bound == "hbm":
-        roof = {"bound": "hbm", "achieved": work / t_dom / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
-    elif wunit == "instr":
-        roof = {"bound": "alu", "achieved": work / t_dom / 1e12, "peak": PEAK_VALU_TOPS,
-                "unit": "T VALU lane-instructions/s"}
-    else:
-        peak = PEAK_FP64_TFLOPS if prec == qpm.PREC_F64 else PEAK_FP32_TFLOPS
-        roof = {"bound": "alu", "achieved": work / t_dom / 1e12, "peak": peak, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
+    # the dominant kernel among the steps with algorithmic work (the finish
+    # steps are latency-bound one-workgroup tails and combines)
+    dom = max((k for k in per if algorithmic_work(k, NP, N_DOMAINS)), key=per.get)
+    roof = roofline_of(dom, NP, N_DOMAINS, per[dom] * 1e-3, f64=prec == qpm.PREC_F64)
     roof["traffic"] = measured_traffic(dom)
     roof["kernel"] = dom
     roof["kernel_ms"] = per[dom]
     out["roofline"] = roof
+    out["kernel_rooflines"] = {k: roofline_of(k, NP, N_DOMAINS, v * 1e-3, f64=prec == qpm.PREC_F64)
+                               for k, v in per.items() if algorithmic_work(k, NP, N_DOMAINS)}
 
     def guarded(name, fn):
         # an extra measurement that fails is reported and leaves the
@@ -512,10 +538,137 @@ def main():
     if not args.no_extras:
         guarded('paper-shaped run and objectives', _extra_paper_and_objectives)
 
+    def _lockstep_errors(orc):
+        # the full HWSDA workload (N = 10^4, NP = 1024, G = 5000 schedule,
+        # seed 0, FP32 fitness, tuned shapes, graph replay): 50 generations,
+        # each replayed by the oracle from the GPU's state; a decision may go
+        # the other way only on a near-tie (|f_new - f_old| within twice the
+        # FP32 tolerance), counted as an adoption; rows matching no
+        # admissible outcome are counted as mismatches
+        npop, G, gens, tol = 1024, 5000, 50, 1e-5
+        O = orc.Design(z, inputs.DK1, inputs.DK2)
+        R = qpm.Run(design, npop, G, F=F, CR=CR, seed=SEED, prec=qpm.PREC_F32, tune=1)
+        adopted = mismatched = 0
+        for g in range(gens):
+            x0 = R.read()[0].cpu().numpy()
+            R.advance(1)
+            xg, _, Lg, _ = R.read()
+            xg = xg.cpu().numpy()
+            u, _ = orc.de_step(x0, F, CR, SEED, g)
+            _, fx = O.fitness(orc.sign_map(x0))
+            _, fu = O.fitness(orc.sign_map(u))
+            dec = fu > fx
+            near = np.abs(fu - fx) <= 2 * tol * np.maximum(fu, fx)
+            a = orc.a_schedule(g, G)
+            outcomes = []
+            for alt in (False, True):
+                base = np.where((dec != alt)[:, None], u, x0)
+                fb = np.where(dec != alt, fu, fx)
+                base[Lg] = np.where(dec[Lg][:, None], u[Lg], x0[Lg])
+                y = orc.gwo_step(base, np.array(Lg, np.int32), a, SEED, g)
+                _, fy = O.fitness(orc.sign_map(y))
+                acc = fy > fb
+                outcomes.append((alt, base, y, acc, np.abs(fy - fb) <= 2 * tol * np.maximum(fy, fb)))
+            for i in range(npop):
+                found = None
+                for alt, base, y, acc, ng in outcomes:
+                    if alt and not near[i]:
+                        continue
+                    cands = [(base[i], 0)] if i in Lg else [(y[i] if acc[i] else base[i], 0),
+                                                              (base[i] if acc[i] else y[i], 1)]
+                    for row, flip in cands:
+                        if flip and not ng[i]:
+                            continue
+                        if np.array_equal(row, xg[i]):
+                            found = int(alt) + flip
+                            break
+                    if found is not None:
+                        break
+                if found is None:
+                    mismatched += 1
+                else:
+                    adopted += found
+        R.destroy()
+        out.setdefault("errors_vs_oracle", {})["hwsda_np1024_lockstep"] = {
+            "generations": gens, "decisions": gens * (2 * npop - 3), "adopted_near_ties": adopted,
+            "rows_matching_no_outcome": mismatched}
+        log("[bench] lockstep: %d adoptions, %d mismatches" % (adopted, mismatched))
+
+    def _batched_errors(orc):
+        # the 64 batched designs (FP32 table kernel, one launch): per
+        # instance 8 first-order periodic seeds of the instance's own period
+        # and 24 iid genomes; the largest plain relative error per instance
+        specs = inputs.batched_designs(64, seed=1)
+        npb = 32
+        ldb = inputs.ld_for(npb)
+        ds, rows = [], []
+        for k, (zb, k1, k2) in enumerate(specs):
+            nb = len(zb) - 1
+            dd = np.concatenate([inputs.periodic_signs(8, nb, zb[1] - zb[0], 2 * np.pi / k1, seed=100 + k),
+                                 inputs.random_signs(24, nb, seed=200 + k)])
+            ds.append(dd)
+            rows.append(inputs.pack_bits(dd, ldb))
+        Bt = qpm.precompute_phases_batched([t[0] for t in specs], [t[1] for t in specs], [t[2] for t in specs])
+        bb = torch.from_numpy(np.concatenate(rows, axis=0).view(np.int32)).cuda()
+        fb = qpm.batch_eval_fitness(Bt, bb, npb, qpm.PREC_F32).double().cpu().numpy()
+        per_p, per_r = [], []
+        for k, (zb, k1, k2) in enumerate(specs):
+            _, fo_ = orc.Design(zb, k1, k2).fitness(ds[k])
+            rel = np.abs(fb[k] - fo_) / fo_
+            per_p.append(float(rel[:8].max()))
+            per_r.append(float(np.max(np.abs(fb[k][8:] - fo_[8:]) / np.maximum(fo_[8:], 1e-2 * np.median(fo_[8:])))))
+        del Bt
+        out.setdefault("errors_vs_oracle", {})["batched_64_designs_f32"] = {
+            "instances": 64, "genomes_per_instance": npb,
+            "periodic_max_rel_worst_instance": max(per_p), "periodic_max_rel_median_instance": float(np.median(per_p)),
+            "random_max_rel_floor1pct_median_worst_instance": max(per_r)}
+        log("[bench] batched errors: periodic worst %.3g" % max(per_p))
+
+    def _relax_errors(orc):
+        # the relaxation workload (batch 256, N = 5 x 10^4 x 2 um, theta ~
+        # N(0, 1)): f of 8 rows against the oracle; the gradient on 64
+        # sampled coordinates against the oracle's analytic gradient and its
+        # central differences (h = 1e-6), normwise over the sampled rows
+        Bn, nn = 256, 50000
+        zr = inputs.uniform_boundaries(nn, 2.0)
+        theta = inputs.relax_theta(Bn, nn, seed=5)
+        Dr = qpm.precompute_phases(zr, inputs.DK1, inputs.DK2)
+        Or = orc.Design(zr, inputs.DK1, inputs.DK2)
+        th = torch.from_numpy(theta).cuda()
+        rng = np.random.default_rng(17)
+        rows = rng.integers(0, Bn, 64)
+        cols = rng.integers(0, nn, 64)
+        h = 1e-6
+        fd = np.empty(64)
+        for k, (b, c) in enumerate(zip(rows, cols)):
+            tp = theta[b].astype(np.float64)
+            tm = tp.copy()
+            tp[c] += h
+            tm[c] -= h
+            fd[k] = np.diff(Or.relax(np.stack([tm, tp]), grad=False)[1])[0] / (2 * h)
+        ur = np.unique(rows)
+        _, _, go = Or.relax(theta[ur].astype(np.float64))
+        scale = float(np.max(np.abs(go)))
+        an = np.array([go[np.searchsorted(ur, b), c] for b, c in zip(rows, cols)])
+        fo8 = Or.relax(theta[:8].astype(np.float64), grad=False)[1]
+        res = {}
+        for name, p_ in (("f32", qpm.PREC_F32), ("f64", qpm.PREC_F64)):
+            f_, S_ = qpm.relax_forward(Dr, th, p_)
+            g_ = qpm.relax_backward(Dr, th, S_, torch.ones(Bn, device="cuda"), p_).cpu().numpy()
+            got = g_[rows, cols]
+            res[name] = {"f_max_rel": float(np.max(np.abs(f_[:8].double().cpu().numpy() - fo8) / fo8)),
+                         "grad_normwise_vs_analytic": float(np.max(np.abs(got - an)) / scale),
+                         "grad_normwise_vs_central_differences": float(np.max(np.abs(got - fd)) / scale)}
+        res["oracle_analytic_vs_central_differences"] = float(np.max(np.abs(an - fd)) / scale)
+        out.setdefault("errors_vs_oracle", {})["relaxation_256x50000"] = res
+        log("[bench] relaxation errors: %s" % res)
+
     def _cpu_leg():
         import oracle as orc
-        # fitness error of the GPU kernels against the oracle on the
-        # benchmark population (max relative error per genome class)
+        # errors against the oracle, per configuration: the fitness of the
+        # benchmark population (plain relative error per genome, and against
+        # max(f, 1e-2 median f)), the HWSDA workload in lockstep, the batched
+        # designs per instance, the relaxation's value and gradient
         Of = orc.Design(z, inputs.DK1, inputs.DK2)
         _, fo = Of.fitness(d)
         floor = 1e-2 * np.median(fo)
@@ -525,10 +678,17 @@ def main():
                              ("f64_table", qpm.PREC_F64, qpm.FIT_TABLE),
                              ("f64_segmented", qpm.PREC_F64, qpm.FIT_SEGMENTED)):
             fg = qpm.eval_fitness(design, bits, NP, prec=p_, kernel=k_).double().cpu().numpy()
-            rel = np.abs(fg - fo) / np.maximum(fo, floor)
-            errs[name] = {"random_max_rel": float(rel[:NP - 32].max()), "periodic_max_rel": float(rel[NP - 32:].max())}
+            rel = np.abs(fg - fo) / fo
+            relf = np.abs(fg - fo) / np.maximum(fo, floor)
+            errs[name] = {"random_max_rel": float(rel[:NP - 32].max()),
+                          "random_max_rel_floor1pct_median": float(relf[:NP - 32].max()),
+                          "periodic_max_rel": float(rel[NP - 32:].max())}
         out["fitness_error_vs_oracle"] = errs
         log("[bench] fitness error vs oracle: %s" % errs)
+        if not args.no_extras:
+            guarded("lockstep errors", lambda: _lockstep_errors(orc))
+            guarded("batched errors", lambda: _batched_errors(orc))
+            guarded("relaxation errors", lambda: _relax_errors(orc))
         log("[bench] CPU oracle: %d generations" % args.cpu_generations)
         O = orc.Design(z, inputs.DK1, inputs.DK2)
         x = (mag * d.astype(np.float32)).astype(np.float32)

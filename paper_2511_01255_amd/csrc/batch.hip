@@ -1030,7 +1030,8 @@ static qpm_status tune_fitness(qpm_batch_run_s *r)
     const std::string key = tune_key("batchtab", r->bt->total_words, c.np, c.prec, r->bt->n_inst);
     {
         int v0, v1;
-        if (tune_lookup(key, &v0, &v1)) {
+        const int maxw = table_max_wpw(p == QPM_PREC_F32);
+        if (tune_lookup(key, &v0, &v1, [&](int g, int w) { return (g == 1 || g == 2 || g == 4) && w >= 1 && w <= maxw; })) {
             r->fplan = make_tab_plan(r->bt->host, v0, v1);
             return QPM_OK;
         }
@@ -1105,7 +1106,8 @@ static qpm_status tune_de(qpm_batch_run_s *r)
     const qpm_run_config &c = r->cfg;
     const std::string key = tune_key("batchde", r->bt->total_words, c.np, 0, r->bt->n_inst);
     int ipw = 0, passes = 0;
-    if (!tune_lookup(key, &ipw, &passes)) {
+    const auto de_ok = [](int w, int pc) { return (w == 1 || w == 2 || w == 4) && (pc == 1 || pc == 2 || pc == 4); };
+    if (!tune_lookup(key, &ipw, &passes, de_ok)) {
         hipEvent_t e0, e1;
         QPM_TRY_HIP(hipEventCreate(&e0));
         QPM_TRY_HIP(hipEventCreate(&e1));

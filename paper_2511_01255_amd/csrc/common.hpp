@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cmath>
 #include <cstdint>
+#include <functional>
 #include <string>
 
 #include "qpm.h"
@@ -312,7 +313,9 @@ qpm_status launch_polish_accept(const float *y, int64_t n, int64_t ldy, const vo
 // ---------------------------------------------------------------- tuner cache
 
 std::string tune_key(const char *kind, int64_t a, int64_t b, int prec, int64_t c);
-bool tune_lookup(const std::string &key, int *v0, int *v1);
+// a cached shape, when present and accepted by `valid` (when given)
+bool tune_lookup(const std::string &key, int *v0, int *v1,
+                 const std::function<bool(int, int)> &valid = std::function<bool(int, int)>());
 void tune_store(const std::string &key, int v0, int v1);
 
 }  // namespace qpm

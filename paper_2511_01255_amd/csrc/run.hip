@@ -314,7 +314,9 @@ static qpm_status tune_run(qpm_run_s *r)
         const std::string key = tune_key(o.kind == QPM_OBJ_THG ? "objthg" : "objshg", o.words * 16 + o.K, c.np,
                                          c.prec, 1);
         int wpw = 0, unused = 0;
-        if (!tune_lookup(key, &wpw, &unused)) {
+        const int maxw = table_max_wpw(p == QPM_PREC_F32);
+        if (!tune_lookup(key, &wpw, &unused,
+                         [&](int w, int) { return w >= 1 && w <= maxw && plan_objective_shape(o, w).gy <= 65535; })) {
             std::vector<ObjPlan> cands;
             for (int w = 1; w <= table_max_wpw(p == QPM_PREC_F32); ++w) {
                 const ObjPlan pl = plan_objective_shape(o, w);
@@ -349,7 +351,11 @@ static qpm_status tune_run(qpm_run_s *r)
     } else if (r->plan.kind == QPM_FIT_SEGMENTED) {
         const std::string key = tune_key("fit", r->d->words, c.np, c.prec, 1);
         int waves = 0, wpw = 0;
-        if (!tune_lookup(key, &waves, &wpw)) {
+        const auto seg_ok = [&](int wv, int w) {
+            return (wv == 1 || wv == 2 || wv == 4 || wv == 8 || wv == 16) && w >= 1 &&
+                   plan_fitness_shape(*r->d, wv, w).gy <= 65535;
+        };
+        if (!tune_lookup(key, &waves, &wpw, seg_ok)) {
             const int w0 = r->plan.wpw;
             std::vector<FitPlan> cands;
             for (int wv : {4, 8, 16})
@@ -384,7 +390,11 @@ static qpm_status tune_run(qpm_run_s *r)
     } else if (r->plan.kind == QPM_FIT_TABLE) {
         const std::string key = tune_key("tab", r->d->words, c.np, c.prec, 1);
         int gw = 0, wpw = 0;
-        if (!tune_lookup(key, &gw, &wpw)) {
+        const auto tab_ok = [&](int g, int w) {
+            return (g == 1 || g == 2 || g == 4) && w >= 1 && w <= table_max_wpw(p == QPM_PREC_F32) &&
+                   plan_fitness_table(*r->d, p, g, w).gy <= 65535;
+        };
+        if (!tune_lookup(key, &gw, &wpw, tab_ok)) {
             std::vector<FitPlan> cands;
             for (int g : {1, 2, 4})
                 for (int w = 1; w <= table_max_wpw(p == QPM_PREC_F32); ++w) {
@@ -417,7 +427,8 @@ static qpm_status tune_run(qpm_run_s *r)
     {
         const std::string key = tune_key("de2", r->D, c.np, 0, 1);
         int ipw = 0, passes = 0;
-        if (!tune_lookup(key, &ipw, &passes)) {
+        const auto de_ok = [](int w, int pc) { return (w == 1 || w == 2 || w == 4) && (pc == 1 || pc == 2 || pc == 4); };
+        if (!tune_lookup(key, &ipw, &passes, de_ok)) {
             st = launch_draws(c.np, r->D, c.seed, r->gen, c.inst, r->draws, r->st);
             if (st != QPM_OK) return st;
             const PopView pv = r->view();

@@ -1,9 +1,13 @@
 // tune.hip -- the launch-shape cache of the tuner: a process-wide map from a
-// problem key (kind, size buckets, precision) to two integers, optionally
-// persisted in the text file named by QPM_TUNE_CACHE ("key v0 v1" lines,
-// appended as new shapes are measured).
+// problem key (table layout version, kind, size buckets, precision) to two
+// integers, optionally persisted in the text file named by QPM_TUNE_CACHE
+// ("key v0 v1" lines, appended as new shapes are measured; read when first
+// needed and again whenever the variable names another file). A cached shape
+// that the caller's check rejects (an old or edited file) counts as absent,
+// so the caller measures again.
 #include <cstdio>
 #include <cstdlib>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -14,7 +18,7 @@ namespace qpm {
 
 static std::mutex g_mu;
 static std::map<std::string, std::pair<int, int>> g_map;
-static bool g_loaded = false;
+static std::string g_loaded_path;  // the cache file read into g_map ("" = none yet)
 
 static int bucket(int64_t v)
 {
@@ -26,16 +30,19 @@ static int bucket(int64_t v)
 std::string tune_key(const char *kind, int64_t a, int64_t b, int prec, int64_t c)
 {
     char buf[160];
-    std::snprintf(buf, sizeof(buf), "gfx950/%s/a%d/b%d/p%d/c%d", kind, bucket(a), bucket(b), prec, bucket(c));
+    // the version names the kernels' table layout: shapes measured on another
+    // layout are not reused
+    std::snprintf(buf, sizeof(buf), "gfx950/v2/%s/a%d/b%d/p%d/c%d", kind, bucket(a), bucket(b), prec, bucket(c));
     return buf;
 }
 
+// reads the file named by QPM_TUNE_CACHE into the map when it names a file
+// not read yet (its entries replace the map's for the same keys)
 static void load_locked()
 {
-    if (g_loaded) return;
-    g_loaded = true;
     const char *path = std::getenv("QPM_TUNE_CACHE");
-    if (!path) return;
+    if (!path || g_loaded_path == path) return;
+    g_loaded_path = path;
     FILE *fh = std::fopen(path, "r");
     if (!fh) return;
     char key[160];
@@ -44,12 +51,16 @@ static void load_locked()
     std::fclose(fh);
 }
 
-bool tune_lookup(const std::string &key, int *v0, int *v1)
+bool tune_lookup(const std::string &key, int *v0, int *v1, const std::function<bool(int, int)> &valid)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     load_locked();
     auto it = g_map.find(key);
     if (it == g_map.end()) return false;
+    if (valid && !valid(it->second.first, it->second.second)) {
+        g_map.erase(it);
+        return false;
+    }
     *v0 = it->second.first;
     *v1 = it->second.second;
     return true;

@@ -6,6 +6,7 @@ whose f is near zero is not judged on cancellation alone. Genes, trial and
 candidate vectors and the +-1 bits are compared bit for bit.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -614,3 +615,39 @@ def test_random_shapes_de_and_gwo_bit_exact(q, orc, D, np_, s):
         assert np.array_equal(_host(y, D), yo)
         keep = np.setdiff1d(np.arange(np_), L)
         assert np.array_equal(inputs.unpack_bits(yb.cpu().numpy(), np_, D)[keep], orc.sign_map(yo)[keep])
+
+
+def test_tune_cache_with_invalid_shapes_retunes(q, tmp_path, monkeypatch):
+    # a tuner cache file (an old or edited one) holding shapes outside the
+    # kernels' limits for this run's keys: they are ignored and measured
+    # again, and the run's FP64 trajectory is the untuned one's. The library
+    # reads the file named by QPM_TUNE_CACHE whenever the name changes.
+    def bucket(v):
+        b = 0
+        while (1 << b) < v:
+            b += 1
+        return b
+
+    n, npop = 3001, 200
+    W = (n + 31) // 32
+    cache = tmp_path / "tune.txt"
+    lines = []
+    for kind, a, b, p, c in (("tab", W, npop, 1, 1), ("de2", n, npop, 0, 1)):
+        key = "gfx950/v2/%s/a%d/b%d/p%d/c%d" % (kind, bucket(a), bucket(b), p, bucket(c))
+        lines.append("%s 3 9" % key)
+    cache.write_text("\n".join(lines) + "\n")
+    monkeypatch.setenv("QPM_TUNE_CACHE", str(cache))
+    D = q.precompute_phases(inputs.uniform_boundaries(n, 2.0), DK1, DK2)
+    out = []
+    for tune in (1, 0):
+        R = q.Run(D, npop, 6, seed=9, prec=1, tune=tune)
+        R.advance(6)
+        out.append(R.read()[0].cpu().numpy())
+        R.destroy()
+    assert np.array_equal(out[0], out[1])
+    # the shapes measured again were appended, and are valid
+    new = cache.read_text().splitlines()[len(lines):]
+    assert len(new) == 2, new
+    for line in new:
+        _, v0, v1 = line.split()
+        assert int(v0) in (1, 2, 4) and int(v1) in (1, 2, 4)
