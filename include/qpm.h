@@ -363,6 +363,13 @@ typedef struct {
     int32_t control;     /* qpm_control: how F_g and a_g are set */
     int32_t trials;      /* qpm_trials: where the DE trial genes go */
     int32_t algo;        /* qpm_algo: HWSDA, or one of its two parts alone */
+    int32_t fused;       /* whole generations in one workgroup with the
+                            population in LDS: 0 = when the run allows it
+                            (FP64 fitness, table or automatic kernel, fixed
+                            or decaying control, gwo_variant 0 or 1, no
+                            objective, np <= 64 and the population within
+                            160 KB of LDS), 1 = required (QPM_ENOTSUP
+                            otherwise), -1 = never; same trajectory */
 } qpm_run_config;
 
 /*

@@ -23,7 +23,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqpm.so")
-SOURCES = ["api.hip", "phases.hip", "fitness.hip", "evolve.hip", "generation.hip", "objective.hip", "relax.hip", "batch.hip", "run.hip", "tune.hip", "noalloc.hip"]
+SOURCES = ["api.hip", "phases.hip", "fitness.hip", "evolve.hip", "generation.hip", "objective.hip", "relax.hip", "batch.hip", "run.hip", "tune.hip", "noalloc.hip", "fused.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -1160,6 +1160,8 @@ QPM_API qpm_status qpm_batch_run_create(qpm_batch b, const qpm_run_config *cfg, 
     QPM_REQUIRE(c.control == QPM_CONTROL_FIXED, QPM_ENOTSUP, "batched runs use the fixed parameter control only");
     QPM_REQUIRE(c.algo == QPM_ALGO_HWSDA, c.algo == QPM_ALGO_DE || c.algo == QPM_ALGO_GWO ? QPM_ENOTSUP : QPM_EINVAL,
                 "batched runs apply the hybrid optimiser only (algo %d)", (int)c.algo);
+    QPM_REQUIRE(c.fused == 0 || c.fused == -1, c.fused == 1 ? QPM_ENOTSUP : QPM_EINVAL,
+                "batched runs have no fused single-workgroup generations (fused %d)", (int)c.fused);
     QPM_REQUIRE(c.trials == QPM_TRIALS_AUTO || c.trials == QPM_TRIALS_STORE || c.trials == QPM_TRIALS_ACCEPTED,
                 QPM_EINVAL, "unknown trial storage %d", c.trials);
     QPM_REQUIRE(static_cast<int64_t>(c.inst) + b->n_inst <= (int64_t(1) << 24), QPM_EINVAL,

@@ -302,6 +302,36 @@ qpm_status launch_pack_pop(const float *x, int64_t np, int64_t D, int64_t ldx, u
 // sign bits of one gene row (D genes) -> W words
 qpm_status launch_pack_row(const float *x, int64_t D, uint32_t *bits, hipStream_t s);
 
+// ---------------------------------------------------------------- fused generations
+
+// Whole generations of a small population in one workgroup (fused.hip):
+// both gene buffers, the fitness, bits, draws and (when they fit) the FP64
+// tables in LDS. FP64 fitness, gwo_variant 0 or 1, any qpm_algo; F_g and a_g
+// from the run's tables.
+constexpr size_t kFusedMaxLds = 160 * 1024;
+struct FusedRun {
+    float *x0;
+    const float *x1;
+    uint32_t *flags, *fbits;
+    double *f_cur;
+    int32_t *leaders;
+    uint32_t *gen;
+    const float *a_tab, *F_tab;
+    const double2 *tab64;
+    const double *C;
+    int64_t np, D, ldx;
+    float CR;
+    uint64_t seed;
+    uint32_t inst;
+    int variant, algo;
+};
+// the population fits the kernel's LDS (np <= 64)
+bool fused_eligible(int64_t np, int64_t D);
+// gens generations from the run state (rows through flags, f, the counter);
+// writes back every row to x0 with its flag cleared, f, the leaders of the
+// last generation and the advanced counter
+qpm_status launch_fused_generations(const FusedRun &fr, int gens, hipStream_t s);
+
 // ---------------------------------------------------------------- polish
 
 qpm_status launch_polish_step(float *theta, const float *grad, int64_t rows, int64_t n, int64_t ld, float eta,

@@ -54,6 +54,7 @@ struct qpm_run_s {
     FitPlan plan;
     int de_ipw = 0;     // 0 = chosen from np
     int de_passes = 1;  // groups of individuals per DE workgroup
+    bool fused = false; // whole generations in one workgroup (fused.hip)
     hipGraph_t graph = nullptr;  // one generation
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph_k = nullptr;  // kGraphGens generations back to back
@@ -486,6 +487,14 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
                 "unknown algorithm %d", c.algo);
     QPM_REQUIRE(c.algo == QPM_ALGO_HWSDA || c.trials != QPM_TRIALS_ACCEPTED, QPM_EINVAL,
                 "accepted-only trials are a mode of the hybrid run; DE and GWO runs store every trial");
+    QPM_REQUIRE(c.fused >= -1 && c.fused <= 1, QPM_EINVAL, "fused must be -1, 0 or 1 (got %d)", (int)c.fused);
+    const bool fused_ok = obj == nullptr && c.prec == QPM_PREC_F64 &&
+                          (c.fit_kernel == QPM_FIT_AUTO || c.fit_kernel == QPM_FIT_TABLE) &&
+                          c.control != QPM_CONTROL_ADAPTIVE && (c.gwo_variant == 0 || c.gwo_variant == 1) &&
+                          fused_eligible(c.np, d->n);
+    QPM_REQUIRE(c.fused != 1 || fused_ok, QPM_ENOTSUP,
+                "fused generations need FP64 table fitness, a fixed or decaying control, gwo_variant 0 or 1, no "
+                "objective and a population that fits in LDS (np <= 64)");
     qpm_status st = check_device();
     if (st != QPM_OK) return st;
 
@@ -511,6 +520,7 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
         release(r);
         return QPM_EINVAL;
     }
+    r->fused = fused_ok && c.fused != -1;
     r->lazy = c.trials == QPM_TRIALS_ACCEPTED ||
               (c.trials == QPM_TRIALS_AUTO && c.algo == QPM_ALGO_HWSDA && lazy_ok &&
                2 * static_cast<int64_t>(sizeof(float)) * c.np * r->ldx > (int64_t(64) << 20));
@@ -616,7 +626,7 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
     if (st == QPM_OK) st = launch_draws(c.np, r->D, c.seed, r->gen, c.inst, r->draws, r->st);
     if (st == QPM_OK && r->adaptive())
         st = launch_adapt_F(r->f_cur, r->f64(), c.np, r->gen, c.generations, r->F_base, r->F_tab, r->st);
-    if (st == QPM_OK && c.use_graph) {
+    if (st == QPM_OK && c.use_graph && !r->fused) {
         st = capture_generations(r, 1, &r->graph, &r->exec);
         if (st == QPM_OK && c.generations >= 2 * kGraphGens)
             st = capture_generations(r, kGraphGens, &r->graph_k, &r->exec_k);
@@ -653,6 +663,22 @@ QPM_API qpm_status qpm_run_advance(qpm_run_handle r, int64_t generations)
                 "advancing %lld generations would pass the configured %lld (done %lld)", (long long)generations,
                 (long long)r->cfg.generations, (long long)r->done);
     int64_t g = 0;
+    if (!r->timing && r->fused && generations > 0) {
+        // whole generations in one workgroup, in launches of at most 1000
+        const qpm_run_config &c = r->cfg;
+        FusedRun fr{r->buf[0], r->buf[1], r->flags, r->fbits, static_cast<double *>(r->f_cur), r->leaders, r->gen,
+                    r->a_tab, r->F_tab, r->d->tab64, r->d->Cdev, c.np, r->D, r->ldx, c.CR, c.seed, c.inst,
+                    c.gwo_variant, c.algo};
+        for (; g < generations;) {
+            const int k = static_cast<int>(std::min<int64_t>(1000, generations - g));
+            qpm_status st = launch_fused_generations(fr, k, r->st);
+            if (st != QPM_OK) return st;
+            g += k;
+            r->done += k;
+        }
+        // the DE draws of the coming generation, for the multi-kernel path
+        return launch_draws(c.np, r->D, c.seed, r->gen, c.inst, r->draws, r->st);
+    }
     if (!r->timing && r->exec_k)
         for (; g + kGraphGens <= generations; g += kGraphGens) {
             QPM_TRY_HIP(hipGraphLaunch(r->exec_k, r->st));

@@ -50,7 +50,7 @@ class RunConfig(C.Structure):
     _fields_ = [("np", _I64), ("generations", _I64), ("F", _F), ("CR", _F), ("seed", _U64),
                 ("inst", _U32), ("prec", _I32), ("gwo_variant", _I32), ("use_graph", _I32),
                 ("fit_kernel", _I32), ("tune", _I32), ("control", _I32), ("trials", _I32),
-                ("algo", _I32)]
+                ("algo", _I32), ("fused", _I32)]
 
 
 class RunStats(C.Structure):
@@ -415,10 +415,10 @@ def relax(theta, design, prec=PREC_F32):
 
 
 def _config(np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0, use_graph=1,
-            fit_kernel=FIT_AUTO, tune=0, control=0, trials=0, algo=ALGO_HWSDA):
+            fit_kernel=FIT_AUTO, tune=0, control=0, trials=0, algo=ALGO_HWSDA, fused=0):
     return RunConfig(np=np_, generations=generations, F=F, CR=CR, seed=seed, inst=inst, prec=prec,
                      gwo_variant=gwo_variant, use_graph=use_graph, fit_kernel=fit_kernel, tune=tune,
-                     control=control, trials=trials, algo=algo)
+                     control=control, trials=trials, algo=algo, fused=fused)
 
 
 class Run:
@@ -427,10 +427,10 @@ class Run:
 
     def __init__(self, design, np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0,
                  use_graph=1, fit_kernel=FIT_AUTO, tune=0, control=CONTROL_FIXED, trials=TRIALS_AUTO,
-                 algo=ALGO_HWSDA, stream=None):
+                 algo=ALGO_HWSDA, fused=0, stream=None):
         self.design = design
         self.cfg = _config(np_, generations, F, CR, seed, inst, prec, gwo_variant, use_graph, fit_kernel, tune,
-                           control, trials, algo)
+                           control, trials, algo, fused)
         self.D = design.n
         h = C.c_void_p()
         create = lib().qpm_run_create_objective if isinstance(design, Objective) else lib().qpm_run_create
@@ -498,12 +498,12 @@ class Run:
 
 
 def run(design, np_, generations, F=0.5, CR=0.9, seed=0, inst=0, prec=PREC_F32, gwo_variant=0, use_graph=1,
-        fit_kernel=FIT_AUTO, tune=0, control=CONTROL_FIXED, trials=TRIALS_AUTO, algo=ALGO_HWSDA, stream=None,
-        device="cuda"):
+        fit_kernel=FIT_AUTO, tune=0, control=CONTROL_FIXED, trials=TRIALS_AUTO, algo=ALGO_HWSDA, fused=0,
+        stream=None, device="cuda"):
     """The one-shot run (qpm_run) -> (best genes (D,), best bits (W,), RunStats)."""
     import torch
     cfg = _config(np_, generations, F, CR, seed, inst, prec, gwo_variant, use_graph, fit_kernel, tune, control,
-                  trials, algo)
+                  trials, algo, fused)
     bx = torch.empty(design.n, dtype=torch.float32, device=device)
     bb = torch.empty(words(design.n), dtype=torch.int32, device=device)
     st = RunStats()
