@@ -268,9 +268,9 @@ qpm_status qpm_gwo_step(const float *x, int64_t np, int64_t D, int64_t ldx,
  * edges: NULL, or device doubles (qpm_relax_edges_size of them) that
  * receive the per-segment prefix and suffix sums the adjoint needs, so that
  * qpm_relax_backward given them skips recomputing the forward pass.
- * prec selects FP32 (per-lane chunks in FP32, everything across lanes and
- * segments in FP64) or FP64. Device scratch: the segment partials (see
- * Conventions, Scratch).
+ * prec selects how tanh is evaluated: FP32 (binary32, hardware exp2 and
+ * reciprocal) or FP64; the sums are FP64 in both. Device scratch: the
+ * segment partials (see Conventions, Scratch).
  * Errors: QPM_EINVAL (NULL design or theta, both outputs NULL, B outside
  * [1, 2^24], ldt < N, unknown precision), QPM_ERANGE, QPM_EHIP.
  */
@@ -278,8 +278,9 @@ qpm_status qpm_relax_forward(qpm_design d, qpm_prec p, const float *theta, int64
                              float *f, double *S, double *edges, qpm_stream s);
 
 /* Number of doubles of the edges buffer of qpm_relax_forward for a batch of
- * B rows in precision p (4 per row and segment of 2048 (FP32) or 1024
- * (FP64) domains). */
+ * B rows in precision p: per row, 4 per segment of 256 domains (the prefix A
+ * before the segment and the sum of B from it on) and 4 per sub-segment of
+ * 64 domains (its own sums A and B). */
 qpm_status qpm_relax_edges_size(qpm_design d, qpm_prec p, int64_t B, int64_t *count);
 
 /*

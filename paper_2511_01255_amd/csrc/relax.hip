@@ -7,37 +7,52 @@
 //   P_{k-1} = sum_{m<k} d_m a_m,  R_{k+1} = sum_{n>k} d_n b_n,
 //   df/dtheta_k = 2 Re(conj(S) dS/dd_k) (1 - d_k^2).
 //
-// Mapping: a workgroup of 256 lanes covers one segment of L = 256 M
-// consecutive domains for R consecutive rows; lane t owns the M domains
-// [seg L + t M, seg L + (t + 1) M), so the loads of theta and the stores of
-// the gradient are coalesced along the row, and it keeps its M domains'
-// coefficients in registers while it walks the R rows. A lane's chunk
-// reduces to (A, B, Q, Dg) = (sum d a, sum d b, sum_n d_n b_n (A before n),
-// sum c d^2); the 256 chunk triples of a segment combine in order (a
-// shuffle tree in each wave, then the 4 waves through LDS, in FP64), and
-// the segments of a row combine in order in a small per-row pass that also
-// forms, for the adjoint, the prefix A before and the suffix B after every
-// segment. The adjoint takes a lane's prefix of A and suffix of B from
-// ordered scans over the lanes and walks its chunk from them.
+// Mapping: a wave owns a tile of 64 consecutive rows x one sub-segment of 64
+// consecutive domains, lane = row; the 4 waves of a workgroup take the 4
+// consecutive sub-segments of one 256-domain segment. The rows' theta of a
+// 16-domain chunk is loaded coalesced (four lanes per row, 16 bytes each),
+// transposed through LDS, and each lane walks its row's domains in order;
+// the coefficients of a domain are the same for every lane (scalar loads).
+// A lane's sub-segment reduces to (A, B, Q, Dg) = (sum d a, sum d b,
+// sum_n d_n b_n (A before n), sum c d^2) with no exchange between lanes; the
+// workgroup folds its 4 sub-segments per row in order through LDS, the
+// segments of a row combine in order in a small per-row pass that also
+// forms, for the adjoint, the prefix A before and the sum of B from every
+// segment on, and the forward pass keeps each sub-segment's A and B. The
+// adjoint walks the same tiles from those edges and stores the gradient
+// back through LDS, coalesced. Precision: FP32 evaluates tanh in binary32
+// (hardware exp2 and reciprocal); the sums, products and the adjoint are
+// FP64 in both precisions (FP64 costs what FP32 does on this chip without
+// packed FP32 instructions).
 #include "common.hpp"
 
 namespace qpm {
 
 struct RelaxPlan {
-    int M;     // domains per lane
-    int R;     // rows per workgroup
-    int L;     // domains per segment (256 M)
-    int nseg;  // segments per row
+    int nseg;        // segments of kRelaxSeg domains per row
+    int nsub;        // sub-segments of kRelaxSub domains per row (4 nseg)
+    int64_t groups;  // row groups of 64
 };
+
+constexpr int kRelaxSub = 64;                 // domains per wave tile
+constexpr int kRelaxSeg = 4 * kRelaxSub;      // domains per workgroup (4 waves)
+constexpr int kRelaxChunk = 16;               // domains per transposed chunk
 
 static RelaxPlan plan_relax(int64_t n, int64_t B, bool f32)
 {
+    (void)f32;
     RelaxPlan p;
-    p.M = f32 ? 8 : 4;
-    p.R = B >= 64 ? 4 : 1;
-    p.L = 256 * p.M;
-    p.nseg = static_cast<int>((n + p.L - 1) / p.L);
+    p.nseg = static_cast<int>((n + kRelaxSeg - 1) / kRelaxSeg);
+    p.nsub = 4 * p.nseg;
+    p.groups = (B + 63) / 64;
     return p;
+}
+
+// doubles of the edges: per row, 4 per segment (A before it, B from it on)
+// and 4 per sub-segment (its own A and B)
+static int64_t relax_edges_count(const RelaxPlan &p, int64_t rows)
+{
+    return 4 * static_cast<int64_t>(p.nseg + p.nsub) * rows;
 }
 
 template <typename T>
@@ -83,194 +98,186 @@ __device__ __forceinline__ RTri rtri_shfl_down(const RTri &t, int off)
                 __shfl_down(t.qr, off), __shfl_down(t.qi, off), __shfl_down(t.gr, off), __shfl_down(t.gi, off)};
 }
 
-// coefficients of lane-owned domains (0 past n)
-template <typename T, int M>
-struct Coef {
-    T ar[M], ai[M], br[M], bi[M], cr[M], ci[M];
-};
-
-template <typename T, int M>
-__device__ __forceinline__ void load_coef(Coef<T, M> &c, int64_t k0, int64_t n, const double4 *__restrict__ ph64,
-                                          const float4 *__restrict__ ph32, const double2 *__restrict__ c64)
+// The loads of one 16-domain chunk [kc, kc + 16) of rows rg 64 .. + 63:
+// four instructions of 16 rows each, four lanes per row, 16 bytes per lane
+// (0 past n or B). Issued ahead of use: every chunk of a tile is in flight
+// before the first is consumed.
+template <bool VEC>
+__device__ __forceinline__ void load_chunk_regs(float4 (&v)[4], const float *__restrict__ theta, int64_t ldt,
+                                                int64_t B, int64_t n, int64_t rg, int64_t kc, int lane)
 {
 #pragma unroll
-    for (int e = 0; e < M; ++e) {
-        const int64_t k = k0 + e;
-        const bool in = k < n;
-        const int64_t kc = in ? k : 0;
-        if constexpr (sizeof(T) == 4) {
-            const float4 v = ph32[kc];
-            c.ar[e] = in ? v.x : 0.f;
-            c.ai[e] = in ? v.y : 0.f;
-            c.br[e] = in ? v.z : 0.f;
-            c.bi[e] = in ? v.w : 0.f;
-        } else {
-            const double4 v = ph64[kc];
-            c.ar[e] = in ? v.x : 0.0;
-            c.ai[e] = in ? v.y : 0.0;
-            c.br[e] = in ? v.z : 0.0;
-            c.bi[e] = in ? v.w : 0.0;
+    for (int step = 0; step < 4; ++step) {
+        const int rt = step * 16 + (lane >> 2), col = (lane & 3) * 4;
+        const int64_t row = rg * 64 + rt, k = kc + col;
+        float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (row < B) {
+            const float *src = theta + row * ldt + k;
+            if (VEC && k + 3 < n) {
+                q = *reinterpret_cast<const float4 *>(src);
+            } else {
+                if (k < n) q.x = src[0];
+                if (k + 1 < n) q.y = src[1];
+                if (k + 2 < n) q.z = src[2];
+                if (k + 3 < n) q.w = src[3];
+            }
         }
-        const double2 cc = c64[kc];
-        c.cr[e] = in ? static_cast<T>(cc.x) : T(0);
-        c.ci[e] = in ? static_cast<T>(cc.y) : T(0);
+        v[step] = q;
     }
 }
 
-// theta[row][k0 .. k0 + M) (0 past n); VEC: 16-byte aligned rows
-template <int M, bool VEC>
-__device__ __forceinline__ void load_theta(float (&th)[M], const float *__restrict__ rowp, int64_t k0, int64_t n)
+// The chunk's loaded values into the wave's LDS tile, row-major with a
+// padded stride (kRelaxST floats: the column reads of lane = row are free
+// of bank conflicts); ends with a workgroup barrier. Lane l then reads its
+// row's values at tile[l kRelaxST + e].
+constexpr int kRelaxST = kRelaxChunk + 1;
+__device__ __forceinline__ void stage_chunk(const float4 (&v)[4], float *tile, int lane)
 {
-    if (VEC && k0 + M <= n) {
 #pragma unroll
-        for (int e = 0; e < M; e += 4) {
-            const float4 v = *reinterpret_cast<const float4 *>(rowp + k0 + e);
-            th[e] = v.x;
-            th[e + 1] = v.y;
-            th[e + 2] = v.z;
-            th[e + 3] = v.w;
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < M; ++e) th[e] = k0 + e < n ? rowp[k0 + e] : 0.f;
+    for (int step = 0; step < 4; ++step) {
+        const int rt = step * 16 + (lane >> 2), col = (lane & 3) * 4;
+        float *t = tile + rt * kRelaxST + col;
+        t[0] = v[step].x;
+        t[1] = v[step].y;
+        t[2] = v[step].z;
+        t[3] = v[step].w;
     }
+    __syncthreads();
 }
 
-// Lane value of lane l - OFF in the lane's row of 16 lanes (row_shr, CTRL
-// 0x110 + OFF), or of the last lane of the previous row (row_bcast:15, CTRL
-// 0x142, rows 1 and 3) or of lane 31 (row_bcast:31, CTRL 0x143, rows 2 and
-// 3); undefined where there is none (no lane reads those). DPP moves: no
-// LDS traffic, unlike a shuffle.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_from(double v)
-{
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, ROWS, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, ROWS, 0xF, true);
-    return __hiloint2double(hi, lo);
-}
+// domains per step of the walks
+constexpr int kRelaxStep = 4;
 
-// one level of the ordered tree: the lanes that `take` prepend the triple
-// of the lanes before them (u <- o (+) u)
-template <int CTRL, int ROWS>
-__device__ __forceinline__ void tree_level(RTri &u, bool take)
+// The coefficients of the workgroup's segment [seg 256, seg 256 + 256) into
+// LDS: co[3 j] = (a.re, a.im), co[3 j + 1] = (b.re, b.im), co[3 j + 2] = c of
+// domain seg 256 + j (0 past n); read back as broadcasts (every lane the
+// same address). Ends with a workgroup barrier.
+__device__ __forceinline__ void stage_coef(double2 *co, const double4 *__restrict__ ph64,
+                                           const double2 *__restrict__ c64, int64_t seg, int64_t n)
 {
-    RTri o{dpp_from<CTRL, ROWS>(u.ar), dpp_from<CTRL, ROWS>(u.ai), dpp_from<CTRL, ROWS>(u.br),
-           dpp_from<CTRL, ROWS>(u.bi), dpp_from<CTRL, ROWS>(u.qr), dpp_from<CTRL, ROWS>(u.qi),
-           dpp_from<CTRL, ROWS>(u.gr), dpp_from<CTRL, ROWS>(u.gi)};
-    if (take) {
-        rtri_append(o, u);
-        u = o;
+    const int j = threadIdx.x;  // 256 threads, one domain each
+    const int64_t k = seg * kRelaxSeg + j;
+    double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
+    double2 c = make_double2(0.0, 0.0);
+    if (k < n) {
+        v = ph64[k];
+        c = c64[k];
     }
+    co[3 * j] = make_double2(v.x, v.y);
+    co[3 * j + 1] = make_double2(v.z, v.w);
+    co[3 * j + 2] = c;
+    __syncthreads();
 }
 
-// The 64 chunk triples of a wave combined in order into lane 63: pairs of
-// neighbours, then groups of 4, 8, 16, 32 and 64 lanes, each the left group
-// followed by the right one.
-__device__ __forceinline__ void wave_fold_rtri(RTri &u, int lane)
-{
-    tree_level<0x111, 0xF>(u, (lane & 1) == 1);
-    tree_level<0x112, 0xF>(u, (lane & 3) == 3);
-    tree_level<0x114, 0xF>(u, (lane & 7) == 7);
-    tree_level<0x118, 0xF>(u, (lane & 15) == 15);
-    tree_level<0x142, 0xA>(u, (lane & 31) == 31);
-    tree_level<0x143, 0xC>(u, lane == 63);
-}
-
-// Inclusive prefix sums of four values over the 64 lanes of a wave with DPP
-// moves: within rows of 16 lanes (shifts 1, 2, 4, 8), then the last lane of
-// row 0 / 2 into rows 1 / 3, then lane 31 into rows 2 and 3.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ void scan_step(double &a, double &b, double &c, double &d, bool take)
-{
-    const double oa = dpp_from<CTRL, ROWS>(a), ob = dpp_from<CTRL, ROWS>(b);
-    const double oc = dpp_from<CTRL, ROWS>(c), od = dpp_from<CTRL, ROWS>(d);
-    if (take) {
-        a += oa;
-        b += ob;
-        c += oc;
-        d += od;
-    }
-}
-
-__device__ __forceinline__ void wave_scan4(double &a, double &b, double &c, double &d, int lane)
-{
-    scan_step<0x111, 0xF>(a, b, c, d, (lane & 15) >= 1);
-    scan_step<0x112, 0xF>(a, b, c, d, (lane & 15) >= 2);
-    scan_step<0x114, 0xF>(a, b, c, d, (lane & 15) >= 4);
-    scan_step<0x118, 0xF>(a, b, c, d, (lane & 15) >= 8);
-    scan_step<0x142, 0xA>(a, b, c, d, (lane & 16) != 0);
-    scan_step<0x143, 0xC>(a, b, c, d, lane >= 32);
-}
-
-// Segment partials: part[(seg * 8 + c) * ldb + row], c = A.re, A.im,
-// B.re, B.im, Q.re, Q.im, Dg.re, Dg.im (doubles).
-template <typename T, int M, int R, bool VEC>
+// Segment partials: part[(row * nseg + seg) * 8 + c], c = A.re, A.im,
+// B.re, B.im, Q.re, Q.im, Dg.re, Dg.im (doubles, a row's segments
+// contiguous for the per-row combine); with sub, also each
+// sub-segment's A and B: sub[(ss * 4 + c) * lds + row], c = A.re, A.im,
+// B.re, B.im. Workgroup (seg, rg) = blockIdx.x / groups, % groups; wave w
+// walks sub-segment 4 seg + w of the rows rg 64 + lane.
+template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void relax_fwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
                                                         int64_t n, const double4 *__restrict__ ph64,
-                                                        const float4 *__restrict__ ph32,
-                                                        const double2 *__restrict__ c64, int nseg, int64_t ldb,
-                                                        double *__restrict__ part)
+                                                        const double2 *__restrict__ c64, int64_t groups,
+                                                        double *__restrict__ part, double *__restrict__ sub,
+                                                        int64_t lds)
 {
-    __shared__ RTri sh[4];
-    const int seg = static_cast<int>(blockIdx.x % static_cast<unsigned>(nseg));
-    const int64_t row0 = static_cast<int64_t>(blockIdx.x / static_cast<unsigned>(nseg)) * R;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int64_t k0 = static_cast<int64_t>(seg) * 256 * M + static_cast<int64_t>(t) * M;
-    Coef<T, M> c;
-    load_coef<T, M>(c, k0, n, ph64, ph32, c64);
-    for (int r = 0; r < R; ++r) {
-        const int64_t row = row0 + r;
-        if (row >= B) break;
-        float th[M];
-        load_theta<M, VEC>(th, theta + row * ldt, k0, n);
-        T ar = 0, ai = 0, br = 0, bi = 0, qr = 0, qi = 0, gr = 0, gi = 0;
+    __shared__ float tiles[4][64 * kRelaxST];
+    // the segment's coefficients, then (after the walk) the fold of the waves
+    __shared__ double2 co[3 * kRelaxSeg];
+    double(*fold)[8][64] = reinterpret_cast<double(*)[8][64]>(co);
+    // the wave index as a wave-uniform value: the segment and domain indices
+    // below stay scalar, so the coefficients are scalar loads
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t seg = blockIdx.x / groups, rg = blockIdx.x % groups;
+    const int64_t ss = 4 * seg + wave;
+    const int64_t row = rg * 64 + lane;
+    double ar = 0, ai = 0, br = 0, bi = 0, qr = 0, qi = 0, gr = 0, gi = 0;
+    constexpr int NCH = kRelaxSub / kRelaxChunk;
+    // the next chunk's loads are in flight while a chunk is worked on
+    float4 cur[4], nxt[4];
+    load_chunk_regs<VEC>(cur, theta, ldt, B, n, rg, ss * kRelaxSub, lane);
+    stage_coef(co, ph64, c64, seg, n);
+#pragma unroll 1
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int64_t kc = ss * kRelaxSub + ch * kRelaxChunk;
+        if (ch + 1 < NCH) load_chunk_regs<VEC>(nxt, theta, ldt, B, n, rg, kc + kRelaxChunk, lane);
+        float *tl = tiles[wave];
+        stage_chunk(cur, tl, lane);
 #pragma unroll
-        for (int e = 0; e < M; ++e) {
-            const T d = tanh_t<T>(static_cast<T>(th[e]));
-            const T yr = d * c.br[e], yi = d * c.bi[e];
-            qr = fma(yr, ar, fma(-yi, ai, qr));
-            qi = fma(yr, ai, fma(yi, ar, qi));
-            ar = fma(d, c.ar[e], ar);
-            ai = fma(d, c.ai[e], ai);
-            br += yr;
-            bi += yi;
-            const T d2 = d * d;
-            gr = fma(d2, c.cr[e], gr);
-            gi = fma(d2, c.ci[e], gi);
+        for (int m = 0; m < 4; ++m) cur[m] = nxt[m];
+#pragma unroll 1
+        for (int e0 = 0; e0 < kRelaxChunk; e0 += kRelaxStep) {
+#pragma unroll
+            for (int e1 = 0; e1 < kRelaxStep; ++e1) {
+                // past the row's end: d = 0 (no contribution), coefficients
+                // of the last domain (an address in range)
+                const int e = e0 + e1;
+                const int64_t k = kc + e;
+                const int jl = wave * kRelaxSub + ch * kRelaxChunk + e;  // domain within the segment
+                const double2 ca = co[3 * jl], cb = co[3 * jl + 1], cc = co[3 * jl + 2];
+                const double4 c = make_double4(ca.x, ca.y, cb.x, cb.y);
+                const float th = tl[lane * kRelaxST + e];
+                const double d = k < n ? static_cast<double>(tanh_t<T>(static_cast<T>(th))) : 0.0;
+                const double yr = d * c.z, yi = d * c.w;
+                qr = fma(yr, ar, fma(-yi, ai, qr));
+                qi = fma(yr, ai, fma(yi, ar, qi));
+                ar = fma(d, c.x, ar);
+                ai = fma(d, c.y, ai);
+                br += yr;
+                bi += yi;
+                const double d2 = d * d;
+                gr = fma(d2, cc.x, gr);
+                gi = fma(d2, cc.y, gi);
+            }
         }
-        RTri u{ar, ai, br, bi, qr, qi, gr, gi};
-        wave_fold_rtri(u, lane);
-        if (lane == 63) sh[wave] = u;
-        __syncthreads();
-        if (t == 0) {
-            RTri s0 = sh[0];
-            rtri_append(s0, sh[1]);
-            rtri_append(s0, sh[2]);
-            rtri_append(s0, sh[3]);
-            double *o = part + static_cast<int64_t>(seg) * 8 * ldb + row;
-            o[0] = s0.ar;
-            o[ldb] = s0.ai;
-            o[2 * ldb] = s0.br;
-            o[3 * ldb] = s0.bi;
-            o[4 * ldb] = s0.qr;
-            o[5 * ldb] = s0.qi;
-            o[6 * ldb] = s0.gr;
-            o[7 * ldb] = s0.gi;
-        }
-        __syncthreads();
+        __syncthreads();  // the tile is refilled by the next chunk
+    }
+    // (the last barrier also ends every wave's reads of co: fold reuses it)
+    if (sub != nullptr && row < B) {
+        double *o = sub + ss * 4 * lds + row;
+        o[0] = ar;
+        o[lds] = ai;
+        o[2 * lds] = br;
+        o[3 * lds] = bi;
+    }
+    // the 4 sub-segments of each row in order: waves 1-3 through LDS into
+    // wave 0
+    if (wave > 0) {
+        const double v[8] = {ar, ai, br, bi, qr, qi, gr, gi};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) fold[wave - 1][c][lane] = v[c];
+    }
+    __syncthreads();
+    if (wave == 0 && row < B) {
+        RTri t{ar, ai, br, bi, qr, qi, gr, gi};
+#pragma unroll
+        for (int w = 0; w < 3; ++w)
+            rtri_append(t, RTri{fold[w][0][lane], fold[w][1][lane], fold[w][2][lane], fold[w][3][lane],
+                                fold[w][4][lane], fold[w][5][lane], fold[w][6][lane], fold[w][7][lane]});
+        const int64_t nseg = gridDim.x / groups;
+        double *o = part + (row * nseg + seg) * 8;
+        o[0] = t.ar;
+        o[1] = t.ai;
+        o[2] = t.br;
+        o[3] = t.bi;
+        o[4] = t.qr;
+        o[5] = t.qi;
+        o[6] = t.gr;
+        o[7] = t.gi;
     }
 }
 
 // Per row (one wave): S = (combined Q) + sum Dg and f = |S|^2; with `edges`,
-// also the prefix A before and the suffix B after every segment:
-// edges[(seg * 4 + c) * lde + row], c = Apre.re, Apre.im, Bsuf.re, Bsuf.im.
+// also the prefix A before every segment and the sum of B from the
+// segment's start to the row's end: edges[(row * nseg + seg) * 4 + c],
+// c = Apre.re, Apre.im, Bfrom.re, Bfrom.im.
 // Lane l folds the segments [l m, (l + 1) m), m = ceil(nseg / 64), in
 // order; an ordered shuffle tree combines the lanes, and lane scans give
 // each lane's prefix of A and suffix of B for the edges.
-__global__ __launch_bounds__(256) void relax_combine_kernel(const double *__restrict__ part, int nseg, int64_t ldb,
-                                                            int64_t B, double *__restrict__ S,
-                                                            float *__restrict__ f, double *__restrict__ edges,
-                                                            int64_t lde)
+__global__ __launch_bounds__(256) void relax_combine_kernel(const double *__restrict__ part, int nseg, int64_t B,
+                                                            double *__restrict__ S, float *__restrict__ f,
+                                                            double *__restrict__ edges)
 {
     const int lane = threadIdx.x & 63;
     const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
@@ -279,8 +286,8 @@ __global__ __launch_bounds__(256) void relax_combine_kernel(const double *__rest
     const int s0 = min(nseg, lane * m), s1 = min(nseg, s0 + m);
     RTri t{0, 0, 0, 0, 0, 0, 0, 0};
     for (int sg = s0; sg < s1; ++sg) {
-        const double *p = part + static_cast<int64_t>(sg) * 8 * ldb + row;
-        rtri_append(t, RTri{p[0], p[ldb], p[2 * ldb], p[3 * ldb], p[4 * ldb], p[5 * ldb], p[6 * ldb], p[7 * ldb]});
+        const double *p = part + (row * nseg + sg) * 8;
+        rtri_append(t, RTri{p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7]});
     }
     if (edges) {
         double par = t.ar, pai = t.ai, sbr = t.br, sbi = t.bi;
@@ -299,21 +306,21 @@ __global__ __launch_bounds__(256) void relax_combine_kernel(const double *__rest
         }
         double ar = par - t.ar, ai = pai - t.ai;  // A before this lane's segments
         for (int sg = s0; sg < s1; ++sg) {
-            const double *p = part + static_cast<int64_t>(sg) * 8 * ldb + row;
-            double *e = edges + static_cast<int64_t>(sg) * 4 * lde + row;
+            const double *p = part + (row * nseg + sg) * 8;
+            double *e = edges + (row * nseg + sg) * 4;
             e[0] = ar;
-            e[lde] = ai;
+            e[1] = ai;
             ar += p[0];
-            ai += p[ldb];
+            ai += p[1];
         }
         double br = sbr - t.br, bi = sbi - t.bi;  // B after this lane's segments
         for (int sg = s1 - 1; sg >= s0; --sg) {
-            const double *p = part + static_cast<int64_t>(sg) * 8 * ldb + row;
-            double *e = edges + static_cast<int64_t>(sg) * 4 * lde + row;
-            e[2 * lde] = br;
-            e[3 * lde] = bi;
-            br += p[2 * ldb];
-            bi += p[3 * ldb];
+            const double *p = part + (row * nseg + sg) * 8;
+            double *e = edges + (row * nseg + sg) * 4;
+            br += p[2];
+            bi += p[3];
+            e[2] = br;
+            e[3] = bi;
         }
     }
 #pragma unroll
@@ -330,140 +337,147 @@ __global__ __launch_bounds__(256) void relax_combine_kernel(const double *__rest
     if (f) f[row] = static_cast<float>(fma(Sr, Sr, Si * Si));
 }
 
-// The adjoint over one segment for R rows: lane prefix of A and suffix of
-// B by ordered scans (FP64), then each lane walks its chunk.
-template <typename T, int M, int R, bool VEC>
+// The adjoint over the tiles of the forward pass: per lane (row), walking
+// its sub-segment's domains in order from P = A before the sub-segment and
+// R = B from the sub-segment on (the segment's edges, less the earlier
+// sub-segments of the segment),
+//   R_{k+1} = R - (B of the sub-segment up to k),  P_{k-1} = P + (A before k),
+//   grad_k = grad_f 2 Re(conj(S) (b_k P_{k-1} + a_k R_{k+1} + 2 c_k d_k)) (1 - d_k^2);
+// each chunk's gradients go back through the wave's LDS tile and are stored
+// coalesced (four lanes per row, 16 bytes each).
+template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void relax_bwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
                                                         int64_t n, const double4 *__restrict__ ph64,
-                                                        const float4 *__restrict__ ph32,
-                                                        const double2 *__restrict__ c64, int nseg,
-                                                        const double *__restrict__ edges, int64_t lde,
+                                                        const double2 *__restrict__ c64, int64_t groups,
+                                                        const double *__restrict__ edges,
+                                                        const double *__restrict__ sub, int64_t lde,
                                                         const double *__restrict__ S,
                                                         const float *__restrict__ grad_f,
                                                         float *__restrict__ grad_theta, int64_t ldg)
 {
-    __shared__ double swa[4][2], swb[4][2];
-    const int seg = static_cast<int>(blockIdx.x % static_cast<unsigned>(nseg));
-    const int64_t row0 = static_cast<int64_t>(blockIdx.x / static_cast<unsigned>(nseg)) * R;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int64_t k0 = static_cast<int64_t>(seg) * 256 * M + static_cast<int64_t>(t) * M;
-    Coef<T, M> c;
-    load_coef<T, M>(c, k0, n, ph64, ph32, c64);
-    for (int r = 0; r < R; ++r) {
-        const int64_t row = row0 + r;
-        if (row >= B) break;
-        float th[M];
-        load_theta<M, VEC>(th, theta + row * ldt, k0, n);
-        T d[M];
-        T alr = 0, ali = 0, blr = 0, bli = 0;
-#pragma unroll
-        for (int e = 0; e < M; ++e) {
-            d[e] = tanh_t<T>(static_cast<T>(th[e]));
-            alr = fma(d[e], c.ar[e], alr);
-            ali = fma(d[e], c.ai[e], ali);
-            blr = fma(d[e], c.br[e], blr);
-            bli = fma(d[e], c.bi[e], bli);
-        }
-        // inclusive prefix scans of A and B over the wave (DPP moves); B
-        // after a lane's chunk is the wave's total less that prefix
-        double par = alr, pai = ali, pbr = blr, pbi = bli;
-        wave_scan4(par, pai, pbr, pbi, lane);
-        const double tbr = __shfl(pbr, 63), tbi = __shfl(pbi, 63);
-        if (lane == 63) {
-            swa[wave][0] = par;
-            swa[wave][1] = pai;
-            swb[wave][0] = tbr;
-            swb[wave][1] = tbi;
-        }
-        __syncthreads();
-        const double *e = edges + static_cast<int64_t>(seg) * 4 * lde + row;
-        // A before this lane's chunk, B after it
-        double Pr = e[0] + (par - alr), Pi = e[lde] + (pai - ali);
-        double Rr = e[2 * lde] + (tbr - pbr), Ri = e[3 * lde] + (tbi - pbi);
+    __shared__ float tiles[4][64 * kRelaxST];
+    __shared__ double2 co[3 * kRelaxSeg];
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t seg = blockIdx.x / groups, rg = blockIdx.x % groups;
+    const int64_t ss = 4 * seg + wave;
+    const int64_t row = rg * 64 + lane;
+    const bool rv = row < B;
+    double pr = 0, pi = 0, rr = 0, ri = 0, Sr = 0, Si = 0, gs = 0;
+    if (rv) {
+        const int64_t nseg = gridDim.x / groups;
+        const double *e = edges + (row * nseg + seg) * 4;
+        pr = e[0];
+        pi = e[1];
+        rr = e[2];
+        ri = e[3];
         for (int w = 0; w < wave; ++w) {
-            Pr += swa[w][0];
-            Pi += swa[w][1];
+            const double *u = sub + (4 * seg + w) * 4 * lde + row;
+            pr += u[0];
+            pi += u[lde];
+            rr -= u[2 * lde];
+            ri -= u[3 * lde];
         }
-        for (int w = 3; w > wave; --w) {
-            Rr += swb[w][0];
-            Ri += swb[w][1];
+        Sr = S[2 * row];
+        Si = S[2 * row + 1];
+        gs = 2.0 * static_cast<double>(grad_f[row]);
+    }
+    float *tl = tiles[wave];
+    constexpr int NCH = kRelaxSub / kRelaxChunk;
+    // the next chunk's loads are in flight while a chunk is worked on
+    float4 cur[4], nxt[4];
+    load_chunk_regs<VEC>(cur, theta, ldt, B, n, rg, ss * kRelaxSub, lane);
+    stage_coef(co, ph64, c64, seg, n);
+#pragma unroll 1
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int64_t kc = ss * kRelaxSub + ch * kRelaxChunk;
+        if (ch + 1 < NCH) load_chunk_regs<VEC>(nxt, theta, ldt, B, n, rg, kc + kRelaxChunk, lane);
+        stage_chunk(cur, tl, lane);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) cur[m] = nxt[m];
+#pragma unroll 1
+        for (int e0 = 0; e0 < kRelaxChunk; e0 += kRelaxStep) {
+#pragma unroll
+            for (int e1 = 0; e1 < kRelaxStep; ++e1) {
+                // past the row's end: d = 0 (no contribution; the gradient
+                // there is not stored), coefficients of the last domain
+                const int e = e0 + e1;
+                const int64_t k = kc + e;
+                const int jl = wave * kRelaxSub + ch * kRelaxChunk + e;  // domain within the segment
+                const double2 ca = co[3 * jl], cb = co[3 * jl + 1], cc = co[3 * jl + 2];
+                const double4 c = make_double4(ca.x, ca.y, cb.x, cb.y);
+                float *slot = tl + lane * kRelaxST + e;  // theta in, the gradient out
+                const double d = k < n ? static_cast<double>(tanh_t<T>(static_cast<T>(*slot))) : 0.0;
+                // R_{k+1}: B from k + 1 on
+                rr = fma(-d, c.z, rr);
+                ri = fma(-d, c.w, ri);
+                const double two_d = d + d;
+                const double dsr =
+                    fma(c.z, pr, fma(-c.w, pi, fma(c.x, rr, fma(-c.y, ri, two_d * cc.x))));
+                const double dsi = fma(c.z, pi, fma(c.w, pr, fma(c.x, ri, fma(c.y, rr, two_d * cc.y))));
+                const double re = fma(Sr, dsr, Si * dsi);
+                *slot = static_cast<float>(gs * re * fma(-d, d, 1.0));
+                pr = fma(d, c.x, pr);
+                pi = fma(d, c.y, pi);
+            }
         }
         __syncthreads();
-        const T Sr = static_cast<T>(S[2 * row]), Si = static_cast<T>(S[2 * row + 1]);
-        const T gscale = static_cast<T>(2.0f * grad_f[row]);
-        // R_{k+1} = (B after the chunk) + (chunk B) - (chunk B up to k)
-        const T rr0 = static_cast<T>(Rr) + blr, ri0 = static_cast<T>(Ri) + bli;
-        T pr = static_cast<T>(Pr), pi = static_cast<T>(Pi), cbr = 0, cbi = 0;
-        float g[M];
+        // the chunk's gradients, coalesced
 #pragma unroll
-        for (int q = 0; q < M; ++q) {
-            const T dq = d[q];
-            cbr = fma(dq, c.br[q], cbr);
-            cbi = fma(dq, c.bi[q], cbi);
-            const T rr = rr0 - cbr, ri = ri0 - cbi;
-            // dS/dd = b P + a R + 2 c d
-            const T two_d = dq + dq;
-            const T dsr = fma(c.br[q], pr, fma(-c.bi[q], pi, fma(c.ar[q], rr, fma(-c.ai[q], ri, two_d * c.cr[q]))));
-            const T dsi = fma(c.br[q], pi, fma(c.bi[q], pr, fma(c.ar[q], ri, fma(c.ai[q], rr, two_d * c.ci[q]))));
-            const T re = fma(Sr, dsr, Si * dsi);
-            g[q] = static_cast<float>(gscale * re * (1 - dq * dq));
-            pr = fma(dq, c.ar[q], pr);
-            pi = fma(dq, c.ai[q], pi);
+        for (int step = 0; step < 4; ++step) {
+            const int rt = step * 16 + (lane >> 2), col = (lane & 3) * 4;
+            const int64_t r = rg * 64 + rt, k = kc + col;
+            if (r < B && k < n) {
+                float *dst = grad_theta + r * ldg + k;
+                const float *v = tl + rt * kRelaxST + col;
+                if (VEC && k + 3 < n) {
+                    *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (k + e < n) dst[e] = v[e];
+                }
+            }
         }
-        float *go = grad_theta + row * ldg;
-        if (VEC && k0 + M <= n) {
-#pragma unroll
-            for (int q = 0; q < M; q += 4)
-                *reinterpret_cast<float4 *>(go + k0 + q) = make_float4(g[q], g[q + 1], g[q + 2], g[q + 3]);
-        } else {
-#pragma unroll
-            for (int q = 0; q < M; ++q)
-                if (k0 + q < n) go[k0 + q] = g[q];
-        }
+        __syncthreads();
     }
 }
 
-template <typename T, int M>
+template <typename T>
 static void launch_relax_fwd(const Design &d, const RelaxPlan &pl, bool vec, const float *theta, int64_t B,
-                             int64_t ldt, int64_t ldb, double *part, hipStream_t s)
+                             int64_t ldt, double *part, double *sub, int64_t lds, hipStream_t s)
 {
-    const unsigned blocks = static_cast<unsigned>(((B + pl.R - 1) / pl.R) * pl.nseg);
-#define QPM_RF(RR, V)                                                                                          \
-    relax_fwd_kernel<T, M, RR, V><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.ph32, d.c64, pl.nseg, ldb, \
-                                                         part)
-    if (pl.R == 4) {
-        if (vec) QPM_RF(4, true); else QPM_RF(4, false);
-    } else {
-        if (vec) QPM_RF(1, true); else QPM_RF(1, false);
-    }
-#undef QPM_RF
+    const unsigned blocks = static_cast<unsigned>(static_cast<int64_t>(pl.nseg) * pl.groups);
+    if (vec)
+        relax_fwd_kernel<T, true><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.c64, pl.groups, part, sub, lds);
+    else
+        relax_fwd_kernel<T, false><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.c64, pl.groups, part, sub,
+                                                          lds);
 }
 
-template <typename T, int M>
+template <typename T>
 static void launch_relax_bwd(const Design &d, const RelaxPlan &pl, bool vec, const float *theta, int64_t B,
-                             int64_t ldt, const double *edges, int64_t lde, const double *S, const float *grad_f,
-                             float *grad_theta, int64_t ldg, hipStream_t s)
+                             int64_t ldt, const double *edges, const double *sub, int64_t lde, const double *S,
+                             const float *grad_f, float *grad_theta, int64_t ldg, hipStream_t s)
 {
-    const unsigned blocks = static_cast<unsigned>(((B + pl.R - 1) / pl.R) * pl.nseg);
-#define QPM_RB(RR, V)                                                                                              \
-    relax_bwd_kernel<T, M, RR, V><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.ph32, d.c64, pl.nseg, edges, \
-                                                         lde, S, grad_f, grad_theta, ldg)
-    if (pl.R == 4) {
-        if (vec) QPM_RB(4, true); else QPM_RB(4, false);
-    } else {
-        if (vec) QPM_RB(1, true); else QPM_RB(1, false);
-    }
-#undef QPM_RB
+    const unsigned blocks = static_cast<unsigned>(static_cast<int64_t>(pl.nseg) * pl.groups);
+    if (vec)
+        relax_bwd_kernel<T, true><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.c64, pl.groups, edges, sub, lde,
+                                                         S, grad_f, grad_theta, ldg);
+    else
+        relax_bwd_kernel<T, false><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.c64, pl.groups, edges, sub,
+                                                          lde, S, grad_f, grad_theta, ldg);
 }
 
+// segment partials part (8 nseg B doubles) and, with sub, the
+// sub-segments' A and B (4 nsub lds doubles)
 static qpm_status relax_partials(const Design &d, qpm_prec p, const float *theta, int64_t B, int64_t ldt,
-                                 const RelaxPlan &pl, int64_t ldb, double *part, hipStream_t s)
+                                 const RelaxPlan &pl, double *part, double *sub, int64_t lds, hipStream_t s)
 {
     const bool vec = (reinterpret_cast<uintptr_t>(theta) & 15u) == 0 && ldt % 4 == 0;
     if (p == QPM_PREC_F32)
-        launch_relax_fwd<float, 8>(d, pl, vec, theta, B, ldt, ldb, part, s);
+        launch_relax_fwd<float>(d, pl, vec, theta, B, ldt, part, sub, lds, s);
     else
-        launch_relax_fwd<double, 4>(d, pl, vec, theta, B, ldt, ldb, part, s);
+        launch_relax_fwd<double>(d, pl, vec, theta, B, ldt, part, sub, lds, s);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }
@@ -567,10 +581,10 @@ static qpm_status check_relax(qpm_design d, qpm_prec p, const float *theta, int6
     return QPM_OK;
 }
 
-static qpm_status launch_combine(const double *part, int nseg, int64_t ldb, int64_t B, double *S, float *f,
-                                 double *edges, int64_t lde, hipStream_t s)
+static qpm_status launch_combine(const double *part, int nseg, int64_t B, double *S, float *f, double *edges,
+                                 hipStream_t s)
 {
-    relax_combine_kernel<<<static_cast<unsigned>((B + 3) / 4), 256, 0, s>>>(part, nseg, ldb, B, S, f, edges, lde);
+    relax_combine_kernel<<<static_cast<unsigned>((B + 3) / 4), 256, 0, s>>>(part, nseg, B, S, f, edges);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }
@@ -582,7 +596,7 @@ QPM_API qpm_status qpm_relax_edges_size(qpm_design d, qpm_prec p, int64_t B, int
     QPM_REQUIRE(p == QPM_PREC_F32 || p == QPM_PREC_F64, QPM_EINVAL, "unknown precision %d", (int)p);
     QPM_REQUIRE(B >= 1 && B <= (int64_t(1) << 24), QPM_EINVAL, "batch must be in [1, 2^24] (got %lld)",
                 (long long)B);
-    *count = 4 * static_cast<int64_t>(plan_relax(d->n, B, p == QPM_PREC_F32).nseg) * B;
+    *count = relax_edges_count(plan_relax(d->n, B, p == QPM_PREC_F32), B);
     return QPM_OK;
 }
 
@@ -595,16 +609,17 @@ QPM_API qpm_status qpm_relax_forward(qpm_design d, qpm_prec p, const float *thet
     QPM_REQUIRE(f != nullptr || S != nullptr, QPM_EINVAL, "at least one of f and S must be given");
     hipStream_t s = static_cast<hipStream_t>(sv);
     const RelaxPlan pl = plan_relax(d->n, B, p == QPM_PREC_F32);
-    QPM_REQUIRE(((B + pl.R - 1) / pl.R) * pl.nseg < (int64_t(1) << 31), QPM_ERANGE,
+    QPM_REQUIRE(static_cast<int64_t>(pl.nseg) * pl.groups < (int64_t(1) << 31), QPM_ERANGE,
                 "batch x segments too large for one launch");
-    const int64_t ldb = ((B + 63) / 64) * 64;
     ScratchLease lease(d->scratch, s);
     void *ws = nullptr;
-    st = lease.begin(sizeof(double) * 8 * pl.nseg * ldb, &ws);
+    st = lease.begin(sizeof(double) * 8 * pl.nseg * B, &ws);
     if (st != QPM_OK) return st;
     double *part = static_cast<double *>(ws);
-    st = relax_partials(*d, p, theta, B, ldt, pl, ldb, part, s);
-    if (st == QPM_OK) st = launch_combine(part, pl.nseg, ldb, B, S, f, edges, B, s);
+    // edges: the segments' (A before, B from) then the sub-segments' (A, B)
+    double *sub = edges ? edges + 4 * static_cast<int64_t>(pl.nseg) * B : nullptr;
+    st = relax_partials(*d, p, theta, B, ldt, pl, part, sub, B, s);
+    if (st == QPM_OK) st = launch_combine(part, pl.nseg, B, S, f, edges, s);
     const qpm_status se = lease.end();
     return st != QPM_OK ? st : se;
 }
@@ -621,31 +636,32 @@ QPM_API qpm_status qpm_relax_backward(qpm_design d, qpm_prec p, const float *the
     QPM_REQUIRE(ldg >= d->n, QPM_EINVAL, "ldg (%lld) must be >= n_domains", (long long)ldg);
     hipStream_t s = static_cast<hipStream_t>(sv);
     const RelaxPlan pl = plan_relax(d->n, B, p == QPM_PREC_F32);
-    QPM_REQUIRE(((B + pl.R - 1) / pl.R) * pl.nseg < (int64_t(1) << 31), QPM_ERANGE,
+    QPM_REQUIRE(static_cast<int64_t>(pl.nseg) * pl.groups < (int64_t(1) << 31), QPM_ERANGE,
                 "batch x segments too large for one launch");
     ScratchLease lease(d->scratch, s);
     const double *e = edges;
-    int64_t lde = B;
+    const double *sub = edges ? edges + 4 * static_cast<int64_t>(pl.nseg) * B : nullptr;
+    const int64_t lde = B;
     if (!edges) {
         // no saved edges: recompute the segment partials and their edges
-        const int64_t ldb = ((B + 63) / 64) * 64;
         void *ws = nullptr;
-        st = lease.begin(sizeof(double) * 12 * pl.nseg * ldb, &ws);
+        st = lease.begin(sizeof(double) * (12 * static_cast<int64_t>(pl.nseg) + 4 * pl.nsub) * B, &ws);
         if (st != QPM_OK) return st;
         double *work = static_cast<double *>(ws);
-        double *ework = work + static_cast<int64_t>(8) * pl.nseg * ldb;
-        st = relax_partials(*d, p, theta, B, ldt, pl, ldb, work, s);
-        if (st == QPM_OK) st = launch_combine(work, pl.nseg, ldb, B, nullptr, nullptr, ework, ldb, s);
+        double *ework = work + static_cast<int64_t>(8) * pl.nseg * B;
+        double *swork = ework + static_cast<int64_t>(4) * pl.nseg * B;
+        st = relax_partials(*d, p, theta, B, ldt, pl, work, swork, B, s);
+        if (st == QPM_OK) st = launch_combine(work, pl.nseg, B, nullptr, nullptr, ework, s);
         e = ework;
-        lde = ldb;
+        sub = swork;
     }
     if (st == QPM_OK) {
         const bool vec = (reinterpret_cast<uintptr_t>(theta) & 15u) == 0 && ldt % 4 == 0 &&
                          (reinterpret_cast<uintptr_t>(grad_theta) & 15u) == 0 && ldg % 4 == 0;
         if (p == QPM_PREC_F32)
-            launch_relax_bwd<float, 8>(*d, pl, vec, theta, B, ldt, e, lde, S, grad_f, grad_theta, ldg, s);
+            launch_relax_bwd<float>(*d, pl, vec, theta, B, ldt, e, sub, lde, S, grad_f, grad_theta, ldg, s);
         else
-            launch_relax_bwd<double, 4>(*d, pl, vec, theta, B, ldt, e, lde, S, grad_f, grad_theta, ldg, s);
+            launch_relax_bwd<double>(*d, pl, vec, theta, B, ldt, e, sub, lde, S, grad_f, grad_theta, ldg, s);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) {
             set_error("relax adjoint launch failed: %s", hipGetErrorString(err));
