@@ -55,6 +55,18 @@ static int64_t relax_edges_count(const RelaxPlan &p, int64_t rows)
     return 4 * static_cast<int64_t>(p.nseg + p.nsub) * rows;
 }
 
+// The work item (seg groups + rg) of a workgroup. Workgroups go to the 8
+// XCDs in turn; each XCD takes a contiguous range of items (the row groups
+// of a segment, then the next segment), so a segment's coefficients are
+// fetched into one XCD's L2 rather than several. -1: past the last item.
+__device__ __forceinline__ int64_t relax_item(int64_t per_xcd, int64_t items)
+{
+    const int64_t it = static_cast<int64_t>(blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
+    return it < items ? it : -1;
+}
+
+static int64_t relax_per_xcd(const RelaxPlan &p) { return (static_cast<int64_t>(p.nseg) * p.groups + 7) / 8; }
+
 template <typename T>
 __device__ __forceinline__ T tanh_t(T x);
 // FP32: tanh x = 1 - 2 / (1 + e^{2x}) from the hardware exp2 and
@@ -173,14 +185,14 @@ __device__ __forceinline__ void stage_coef(double2 *co, const double4 *__restric
 // B.re, B.im, Q.re, Q.im, Dg.re, Dg.im (doubles, a row's segments
 // contiguous for the per-row combine); with sub, also each
 // sub-segment's A and B: sub[(ss * 4 + c) * lds + row], c = A.re, A.im,
-// B.re, B.im. Workgroup (seg, rg) = blockIdx.x / groups, % groups; wave w
+// B.re, B.im. Workgroup item (seg, rg) = item / groups, % groups; wave w
 // walks sub-segment 4 seg + w of the rows rg 64 + lane.
 template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void relax_fwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
                                                         int64_t n, const double4 *__restrict__ ph64,
-                                                        const double2 *__restrict__ c64, int64_t groups,
-                                                        double *__restrict__ part, double *__restrict__ sub,
-                                                        int64_t lds)
+                                                        const double2 *__restrict__ c64, int64_t groups, int nseg,
+                                                        int64_t per_xcd, double *__restrict__ part,
+                                                        double *__restrict__ sub, int64_t lds)
 {
     __shared__ float tiles[4][64 * kRelaxST];
     // the segment's coefficients, then (after the walk) the fold of the waves
@@ -189,7 +201,9 @@ __global__ __launch_bounds__(256) void relax_fwd_kernel(const float *__restrict_
     // the wave index as a wave-uniform value: the segment and domain indices
     // below stay scalar, so the coefficients are scalar loads
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t seg = blockIdx.x / groups, rg = blockIdx.x % groups;
+    const int64_t item = relax_item(per_xcd, nseg * groups);
+    if (item < 0) return;  // the whole workgroup
+    const int64_t seg = item / groups, rg = item % groups;
     const int64_t ss = 4 * seg + wave;
     const int64_t row = rg * 64 + lane;
     double ar = 0, ai = 0, br = 0, bi = 0, qr = 0, qi = 0, gr = 0, gi = 0;
@@ -210,15 +224,14 @@ __global__ __launch_bounds__(256) void relax_fwd_kernel(const float *__restrict_
         for (int e0 = 0; e0 < kRelaxChunk; e0 += kRelaxStep) {
 #pragma unroll
             for (int e1 = 0; e1 < kRelaxStep; ++e1) {
-                // past the row's end: d = 0 (no contribution), coefficients
-                // of the last domain (an address in range)
+                // past the row's end theta and the coefficients are 0, so
+                // d = tanh 0 = 0 and the domain adds nothing
                 const int e = e0 + e1;
-                const int64_t k = kc + e;
                 const int jl = wave * kRelaxSub + ch * kRelaxChunk + e;  // domain within the segment
                 const double2 ca = co[3 * jl], cb = co[3 * jl + 1], cc = co[3 * jl + 2];
                 const double4 c = make_double4(ca.x, ca.y, cb.x, cb.y);
                 const float th = tl[lane * kRelaxST + e];
-                const double d = k < n ? static_cast<double>(tanh_t<T>(static_cast<T>(th))) : 0.0;
+                const double d = static_cast<double>(tanh_t<T>(static_cast<T>(th)));
                 const double yr = d * c.z, yi = d * c.w;
                 qr = fma(yr, ar, fma(-yi, ai, qr));
                 qi = fma(yr, ai, fma(yi, ar, qi));
@@ -255,7 +268,6 @@ __global__ __launch_bounds__(256) void relax_fwd_kernel(const float *__restrict_
         for (int w = 0; w < 3; ++w)
             rtri_append(t, RTri{fold[w][0][lane], fold[w][1][lane], fold[w][2][lane], fold[w][3][lane],
                                 fold[w][4][lane], fold[w][5][lane], fold[w][6][lane], fold[w][7][lane]});
-        const int64_t nseg = gridDim.x / groups;
         double *o = part + (row * nseg + seg) * 8;
         o[0] = t.ar;
         o[1] = t.ai;
@@ -268,68 +280,171 @@ __global__ __launch_bounds__(256) void relax_fwd_kernel(const float *__restrict_
     }
 }
 
-// Per row (one wave): S = (combined Q) + sum Dg and f = |S|^2; with `edges`,
-// also the prefix A before every segment and the sum of B from the
-// segment's start to the row's end: edges[(row * nseg + seg) * 4 + c],
+// The partial triple of segment sg of a row (zero past the row's segments:
+// the identity of rtri_append).
+__device__ __forceinline__ RTri load_part(const double *__restrict__ pr, int sg, int nseg)
+{
+    if (sg >= nseg) return RTri{0, 0, 0, 0, 0, 0, 0, 0};
+    const double2 *p = reinterpret_cast<const double2 *>(pr + static_cast<int64_t>(sg) * 8);
+    const double2 a = p[0], b = p[1], q = p[2], g = p[3];
+    return RTri{a.x, a.y, b.x, b.y, q.x, q.y, g.x, g.y};
+}
+
+// DPP moves within 16-lane rows (double as two 32-bit moves): lane l reads
+// lane l + k (row_shl k) or l - k (row_shr k) of its own row; a lane whose
+// source lies outside its row reads 0.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int K>
+__device__ __forceinline__ double row_from_above(double v) { return dpp_d<0x100 + K>(v); }  // lane l + K
+template <int K>
+__device__ __forceinline__ double row_from_below(double v) { return dpp_d<0x110 + K>(v); }  // lane l - K
+
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+template <int K>
+__device__ __forceinline__ void rtri_tree_level(RTri &u, int lane)
+{
+    const RTri o{row_from_above<K>(u.ar), row_from_above<K>(u.ai), row_from_above<K>(u.br),
+                 row_from_above<K>(u.bi), row_from_above<K>(u.qr), row_from_above<K>(u.qi),
+                 row_from_above<K>(u.gr), row_from_above<K>(u.gi)};
+    if ((lane & (2 * K - 1)) == 0) rtri_append(u, o);
+}
+
+__device__ __forceinline__ RTri rtri_lane(const RTri &u, int l)
+{
+    return RTri{lane_value(u.ar, l), lane_value(u.ai, l), lane_value(u.br, l), lane_value(u.bi, l),
+                lane_value(u.qr, l), lane_value(u.qi, l), lane_value(u.gr, l), lane_value(u.gi, l)};
+}
+
+// inclusive scan of v within each 16-lane row
+__device__ __forceinline__ double row_scan(double v)
+{
+    v += row_from_below<1>(v);
+    v += row_from_below<2>(v);
+    v += row_from_below<4>(v);
+    v += row_from_below<8>(v);
+    return v;
+}
+
+// rounds of 64 segments whose loads are issued together
+constexpr int kCombineBatch = 4;
+
+// Per row (a workgroup of four waves): S = (combined Q) + sum Dg and
+// f = |S|^2; with `edges`, also the prefix A before every segment and the
+// sum of B from the segment on: edges[(row * nseg + seg) * 4 + c],
 // c = Apre.re, Apre.im, Bfrom.re, Bfrom.im.
-// Lane l folds the segments [l m, (l + 1) m), m = ceil(nseg / 64), in
-// order; an ordered shuffle tree combines the lanes, and lane scans give
-// each lane's prefix of A and suffix of B for the edges.
+// The row's segments go in rounds of 64, lane l taking segment 64 t + l (a
+// row's partials are contiguous, so a round's loads are coalesced), and
+// wave w takes a contiguous quarter of the rounds (the loads of up to four
+// rounds in flight together). A round folds in order: within each 16-lane
+// row by a DPP tree, then the four row heads; the waves' folds combine in
+// order through LDS. For the edges each wave rereads its A and B and scans
+// them (DPP within rows, then the rows' totals) from the A and B of the
+// waves before it: A before the segment, and B from it on as the row's B
+// less the B before the segment.
 __global__ __launch_bounds__(256) void relax_combine_kernel(const double *__restrict__ part, int nseg, int64_t B,
                                                             double *__restrict__ S, float *__restrict__ f,
                                                             double *__restrict__ edges)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    if (row >= B) return;  // a whole wave: no barriers below
-    const int m = (nseg + 63) / 64;
-    const int s0 = min(nseg, lane * m), s1 = min(nseg, s0 + m);
-    RTri t{0, 0, 0, 0, 0, 0, 0, 0};
-    for (int sg = s0; sg < s1; ++sg) {
-        const double *p = part + (row * nseg + sg) * 8;
-        rtri_append(t, RTri{p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7]});
+    __shared__ double folds[4][8];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t row = blockIdx.x;
+    if (row >= B) return;  // the whole workgroup (the grid is B workgroups)
+    const double *pr = part + row * nseg * 8;
+    const int rounds = (nseg + 63) / 64;
+    const int t_beg = wave * rounds / 4, t_end = (wave + 1) * rounds / 4;
+    RTri mine{0, 0, 0, 0, 0, 0, 0, 0};
+    for (int t0 = t_beg; t0 < t_end; t0 += kCombineBatch) {
+        RTri u[kCombineBatch];  // every round of the batch in flight at once
+#pragma unroll
+        for (int b = 0; b < kCombineBatch; ++b)
+            u[b] = t0 + b < t_end ? load_part(pr, 64 * (t0 + b) + lane, nseg) : RTri{0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int b = 0; b < kCombineBatch; ++b) {
+            if (t0 + b < t_end) {
+                rtri_tree_level<1>(u[b], lane);
+                rtri_tree_level<2>(u[b], lane);
+                rtri_tree_level<4>(u[b], lane);
+                rtri_tree_level<8>(u[b], lane);
+#pragma unroll
+                for (int h = 0; h < 64; h += 16) rtri_append(mine, rtri_lane(u[b], h));
+            }
+        }
+    }
+    if (lane == 0) {
+        const double v[8] = {mine.ar, mine.ai, mine.br, mine.bi, mine.qr, mine.qi, mine.gr, mine.gi};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) folds[wave][c] = v[c];
+    }
+    __syncthreads();
+    // the row's fold (the same order in every wave) and the A and B of the
+    // waves before this one
+    RTri tot{0, 0, 0, 0, 0, 0, 0, 0};
+    double carry[4] = {0, 0, 0, 0};  // A.re, A.im, B.re, B.im before the wave's next round
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const RTri tw{folds[w][0], folds[w][1], folds[w][2], folds[w][3],
+                      folds[w][4], folds[w][5], folds[w][6], folds[w][7]};
+        if (w < wave) {
+            carry[0] += tw.ar;
+            carry[1] += tw.ai;
+            carry[2] += tw.br;
+            carry[3] += tw.bi;
+        }
+        rtri_append(tot, tw);
     }
     if (edges) {
-        double par = t.ar, pai = t.ai, sbr = t.br, sbi = t.bi;
+        double *er = edges + row * nseg * 4;
+        const int rid = lane >> 4;
+        for (int t0 = t_beg; t0 < t_end; t0 += kCombineBatch) {
+            double4 vb[kCombineBatch];
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const double ur = __shfl_up(par, off), ui = __shfl_up(pai, off);
-            const double vr = __shfl_down(sbr, off), vi = __shfl_down(sbi, off);
-            if (lane >= off) {
-                par += ur;
-                pai += ui;
+            for (int b = 0; b < kCombineBatch; ++b) {
+                const int sg = 64 * (t0 + b) + lane;
+                vb[b] = make_double4(0.0, 0.0, 0.0, 0.0);
+                if (t0 + b < t_end && sg < nseg) {
+                    const double2 *p = reinterpret_cast<const double2 *>(pr + static_cast<int64_t>(sg) * 8);
+                    const double2 a = p[0], bb = p[1];
+                    vb[b] = make_double4(a.x, a.y, bb.x, bb.y);
+                }
             }
-            if (lane + off < 64) {
-                sbr += vr;
-                sbi += vi;
+#pragma unroll
+            for (int b = 0; b < kCombineBatch; ++b) {
+                if (t0 + b >= t_end) break;
+                const int sg = 64 * (t0 + b) + lane;
+                const double in[4] = {row_scan(vb[b].x), row_scan(vb[b].y), row_scan(vb[b].z), row_scan(vb[b].w)};
+                double ex[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    // the rows' totals; the sum of the rows before this lane's
+                    const double r0 = lane_value(in[c], 15), r1 = lane_value(in[c], 31),
+                                 r2 = lane_value(in[c], 47), r3 = lane_value(in[c], 63);
+                    const double before = rid == 0 ? 0.0 : rid == 1 ? r0 : rid == 2 ? r0 + r1 : (r0 + r1) + r2;
+                    ex[c] = (before + row_from_below<1>(in[c])) + carry[c];  // lane 16 k reads 0
+                    carry[c] += ((r0 + r1) + r2) + r3;
+                }
+                if (sg < nseg) {
+                    double *e = er + static_cast<int64_t>(sg) * 4;  // (only 8-byte aligned)
+                    e[0] = ex[0];
+                    e[1] = ex[1];
+                    e[2] = tot.br - ex[2];
+                    e[3] = tot.bi - ex[3];
+                }
             }
-        }
-        double ar = par - t.ar, ai = pai - t.ai;  // A before this lane's segments
-        for (int sg = s0; sg < s1; ++sg) {
-            const double *p = part + (row * nseg + sg) * 8;
-            double *e = edges + (row * nseg + sg) * 4;
-            e[0] = ar;
-            e[1] = ai;
-            ar += p[0];
-            ai += p[1];
-        }
-        double br = sbr - t.br, bi = sbi - t.bi;  // B after this lane's segments
-        for (int sg = s1 - 1; sg >= s0; --sg) {
-            const double *p = part + (row * nseg + sg) * 8;
-            double *e = edges + (row * nseg + sg) * 4;
-            br += p[2];
-            bi += p[3];
-            e[2] = br;
-            e[3] = bi;
         }
     }
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const RTri o = rtri_shfl_down(t, off);
-        if ((lane & (2 * off - 1)) == 0) rtri_append(t, o);
-    }
-    if (lane != 0) return;
-    const double Sr = t.qr + t.gr, Si = t.qi + t.gi;
+    if (threadIdx.x != 0) return;
+    const double Sr = tot.qr + tot.gr, Si = tot.qi + tot.gi;
     if (S) {
         S[2 * row] = Sr;
         S[2 * row + 1] = Si;
@@ -348,8 +463,8 @@ __global__ __launch_bounds__(256) void relax_combine_kernel(const double *__rest
 template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void relax_bwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
                                                         int64_t n, const double4 *__restrict__ ph64,
-                                                        const double2 *__restrict__ c64, int64_t groups,
-                                                        const double *__restrict__ edges,
+                                                        const double2 *__restrict__ c64, int64_t groups, int nseg,
+                                                        int64_t per_xcd, const double *__restrict__ edges,
                                                         const double *__restrict__ sub, int64_t lde,
                                                         const double *__restrict__ S,
                                                         const float *__restrict__ grad_f,
@@ -358,13 +473,14 @@ __global__ __launch_bounds__(256) void relax_bwd_kernel(const float *__restrict_
     __shared__ float tiles[4][64 * kRelaxST];
     __shared__ double2 co[3 * kRelaxSeg];
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t seg = blockIdx.x / groups, rg = blockIdx.x % groups;
+    const int64_t item = relax_item(per_xcd, nseg * groups);
+    if (item < 0) return;  // the whole workgroup
+    const int64_t seg = item / groups, rg = item % groups;
     const int64_t ss = 4 * seg + wave;
     const int64_t row = rg * 64 + lane;
     const bool rv = row < B;
     double pr = 0, pi = 0, rr = 0, ri = 0, Sr = 0, Si = 0, gs = 0;
     if (rv) {
-        const int64_t nseg = gridDim.x / groups;
         const double *e = edges + (row * nseg + seg) * 4;
         pr = e[0];
         pi = e[1];
@@ -398,15 +514,14 @@ __global__ __launch_bounds__(256) void relax_bwd_kernel(const float *__restrict_
         for (int e0 = 0; e0 < kRelaxChunk; e0 += kRelaxStep) {
 #pragma unroll
             for (int e1 = 0; e1 < kRelaxStep; ++e1) {
-                // past the row's end: d = 0 (no contribution; the gradient
-                // there is not stored), coefficients of the last domain
+                // past the row's end theta and the coefficients are 0: d = 0
+                // and the domain adds nothing (its gradient is not stored)
                 const int e = e0 + e1;
-                const int64_t k = kc + e;
                 const int jl = wave * kRelaxSub + ch * kRelaxChunk + e;  // domain within the segment
                 const double2 ca = co[3 * jl], cb = co[3 * jl + 1], cc = co[3 * jl + 2];
                 const double4 c = make_double4(ca.x, ca.y, cb.x, cb.y);
                 float *slot = tl + lane * kRelaxST + e;  // theta in, the gradient out
-                const double d = k < n ? static_cast<double>(tanh_t<T>(static_cast<T>(*slot))) : 0.0;
+                const double d = static_cast<double>(tanh_t<T>(static_cast<T>(*slot)));
                 // R_{k+1}: B from k + 1 on
                 rr = fma(-d, c.z, rr);
                 ri = fma(-d, c.w, ri);
@@ -446,12 +561,14 @@ template <typename T>
 static void launch_relax_fwd(const Design &d, const RelaxPlan &pl, bool vec, const float *theta, int64_t B,
                              int64_t ldt, double *part, double *sub, int64_t lds, hipStream_t s)
 {
-    const unsigned blocks = static_cast<unsigned>(static_cast<int64_t>(pl.nseg) * pl.groups);
+    const int64_t per_xcd = relax_per_xcd(pl);
+    const unsigned blocks = static_cast<unsigned>(8 * per_xcd);
     if (vec)
-        relax_fwd_kernel<T, true><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.c64, pl.groups, part, sub, lds);
+        relax_fwd_kernel<T, true><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.c64, pl.groups, pl.nseg,
+                                                         per_xcd, part, sub, lds);
     else
-        relax_fwd_kernel<T, false><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.c64, pl.groups, part, sub,
-                                                          lds);
+        relax_fwd_kernel<T, false><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.c64, pl.groups, pl.nseg,
+                                                          per_xcd, part, sub, lds);
 }
 
 template <typename T>
@@ -459,13 +576,14 @@ static void launch_relax_bwd(const Design &d, const RelaxPlan &pl, bool vec, con
                              int64_t ldt, const double *edges, const double *sub, int64_t lde, const double *S,
                              const float *grad_f, float *grad_theta, int64_t ldg, hipStream_t s)
 {
-    const unsigned blocks = static_cast<unsigned>(static_cast<int64_t>(pl.nseg) * pl.groups);
+    const int64_t per_xcd = relax_per_xcd(pl);
+    const unsigned blocks = static_cast<unsigned>(8 * per_xcd);
     if (vec)
-        relax_bwd_kernel<T, true><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.c64, pl.groups, edges, sub, lde,
-                                                         S, grad_f, grad_theta, ldg);
+        relax_bwd_kernel<T, true><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.c64, pl.groups, pl.nseg,
+                                                         per_xcd, edges, sub, lde, S, grad_f, grad_theta, ldg);
     else
-        relax_bwd_kernel<T, false><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.c64, pl.groups, edges, sub,
-                                                          lde, S, grad_f, grad_theta, ldg);
+        relax_bwd_kernel<T, false><<<blocks, 256, 0, s>>>(theta, ldt, B, d.n, d.ph64, d.c64, pl.groups, pl.nseg,
+                                                          per_xcd, edges, sub, lde, S, grad_f, grad_theta, ldg);
 }
 
 // segment partials part (8 nseg B doubles) and, with sub, the
@@ -584,7 +702,7 @@ static qpm_status check_relax(qpm_design d, qpm_prec p, const float *theta, int6
 static qpm_status launch_combine(const double *part, int nseg, int64_t B, double *S, float *f, double *edges,
                                  hipStream_t s)
 {
-    relax_combine_kernel<<<static_cast<unsigned>((B + 3) / 4), 256, 0, s>>>(part, nseg, B, S, f, edges);
+    relax_combine_kernel<<<static_cast<unsigned>(B), 256, 0, s>>>(part, nseg, B, S, f, edges);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }
@@ -609,7 +727,7 @@ QPM_API qpm_status qpm_relax_forward(qpm_design d, qpm_prec p, const float *thet
     QPM_REQUIRE(f != nullptr || S != nullptr, QPM_EINVAL, "at least one of f and S must be given");
     hipStream_t s = static_cast<hipStream_t>(sv);
     const RelaxPlan pl = plan_relax(d->n, B, p == QPM_PREC_F32);
-    QPM_REQUIRE(static_cast<int64_t>(pl.nseg) * pl.groups < (int64_t(1) << 31), QPM_ERANGE,
+    QPM_REQUIRE(static_cast<int64_t>(pl.nseg) * pl.groups < (int64_t(1) << 31) - 8, QPM_ERANGE,
                 "batch x segments too large for one launch");
     ScratchLease lease(d->scratch, s);
     void *ws = nullptr;
@@ -636,7 +754,7 @@ QPM_API qpm_status qpm_relax_backward(qpm_design d, qpm_prec p, const float *the
     QPM_REQUIRE(ldg >= d->n, QPM_EINVAL, "ldg (%lld) must be >= n_domains", (long long)ldg);
     hipStream_t s = static_cast<hipStream_t>(sv);
     const RelaxPlan pl = plan_relax(d->n, B, p == QPM_PREC_F32);
-    QPM_REQUIRE(static_cast<int64_t>(pl.nseg) * pl.groups < (int64_t(1) << 31), QPM_ERANGE,
+    QPM_REQUIRE(static_cast<int64_t>(pl.nseg) * pl.groups < (int64_t(1) << 31) - 8, QPM_ERANGE,
                 "batch x segments too large for one launch");
     ScratchLease lease(d->scratch, s);
     const double *e = edges;
