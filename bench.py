@@ -148,6 +148,37 @@ def host_cpu():
         return None
 
 
+def relaxation_timing(qpm, inputs, torch, reps):
+    """The relaxation workload (batch 256, N = 50,000 x 2 um, theta ~ N(0, 1)):
+    forward keeping the segment edges, then the adjoint from them (the
+    autograd path), reps times per precision between HIP events; ms per
+    forward + adjoint, domain evaluations/s and the HBM roofline at 12 B of
+    algorithmic traffic per domain (theta read by both passes, the gradient
+    written)."""
+    zr = inputs.uniform_boundaries(50000, 2.0)
+    Dr = qpm.precompute_phases(zr, inputs.DK1, inputs.DK2)
+    th = torch.from_numpy(inputs.relax_theta(256, 50000, seed=1)).cuda()
+    ones = torch.ones(256, device="cuda")
+    rel = {}
+    for name, p_ in (("f32", qpm.PREC_F32), ("f64", qpm.PREC_F64)):
+        f_, S_, E_ = qpm.relax_forward(Dr, th, p_, keep_edges=True)
+        qpm.relax_backward(Dr, th, S_, ones, p_, edges=E_)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            f_, S_, E_ = qpm.relax_forward(Dr, th, p_, keep_edges=True)
+            qpm.relax_backward(Dr, th, S_, ones, p_, edges=E_)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3 / reps
+        gbs = 12.0 * 256 * 50000 / t / 1e9
+        rel[name] = {"ms_forward_adjoint": t * 1e3, "domain_evals_per_s": 256 * 50000 / t,
+                     "hbm_gbs_at_12B_per_domain": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
+    Dr.free()
+    return rel
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +190,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the timed generations")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 512 MiB buffer three times (byte calibration of memory counters)")
+    ap.add_argument("--relaxation-only", type=int, default=0, metavar="REPS",
+                    help="time only the relaxation workload (REPS forward + adjoint per precision), print "
+                         "its record as one JSON line and exit (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -182,6 +216,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.relaxation_only > 0:
+        rel = relaxation_timing(qpm, inputs, torch, args.relaxation_only)
+        print(json.dumps({"workload": "relaxation: batch 256 x N = 50,000 x 2.0 um, forward keeping the "
+                                      "segment edges + adjoint", "relaxation": rel}), flush=True)
+        return
 
     z = inputs.uniform_boundaries(N_DOMAINS, WIDTH)
     d = inputs.fitness_population(NP, N_DOMAINS, WIDTH, 32, seed=1)
@@ -422,29 +462,8 @@ def main():
                              "alg_frac_of_nonpacked_fp32_peak": 10 * brate / 1e12 / PEAK_FP32_NONPACKED_TFLOPS},
         }
         log("[bench] batched designs: %.2f ms/generation over 500 generations (%.2f early)" % (tavg * 1e3, tb * 1e3))
-        # relaxation forward + adjoint: batch 256, N = 50,000 x 2 um
-        zr = inputs.uniform_boundaries(50000, 2.0)
-        Dr = qpm.precompute_phases(zr, inputs.DK1, inputs.DK2)
-        th = torch.from_numpy(inputs.relax_theta(256, 50000, seed=1)).cuda()
-        ones = torch.ones(256, device="cuda")
-        rel = {}
-        # forward keeping the segment edges, then the adjoint from them (the
-        # autograd path)
-        for name, p_ in (("f32", qpm.PREC_F32), ("f64", qpm.PREC_F64)):
-            f_, S_, E_ = qpm.relax_forward(Dr, th, p_, keep_edges=True)
-            qpm.relax_backward(Dr, th, S_, ones, p_, edges=E_)
-            stream = torch.cuda.current_stream()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(10):
-                f_, S_, E_ = qpm.relax_forward(Dr, th, p_, keep_edges=True)
-                qpm.relax_backward(Dr, th, S_, ones, p_, edges=E_)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            t = e0.elapsed_time(e1) * 1e-3 / 10
-            rel[name] = {"ms_forward_adjoint": t * 1e3, "domain_evals_per_s": 256 * 50000 / t}
-        out["relaxation"] = rel
-        log("[bench] relaxation fwd+adjoint: %s" % rel)
+        out["relaxation"] = relaxation_timing(qpm, inputs, torch, 10)
+        log("[bench] relaxation fwd+adjoint: %s" % out["relaxation"])
 
         # gradient polish of the leaders inside a run (N = 10^4, NP = 1024,
         # FP32): 20 relaxation steps every 100 generations for 500

@@ -584,10 +584,12 @@ qpm_status qpm_batch_eval_fitness_table(qpm_batch b, qpm_prec p, const uint32_t 
  * qpm_batch_run_create -- one HWSDA run per instance, all advanced together
  * (every instance follows the single-design generation of qpm_run_create
  * with Philox instance number cfg->inst + b). 4 <= cfg->np <= 4096; the
- * fitness kernel is the segmented one (cfg->fit_kernel is ignored). With
- * tune != 0 the fitness launch shape is chosen by timing candidates on the
- * initial population (kept per problem size for the process, and appended
- * to the file named by the QPM_TUNE_CACHE environment variable if set).
+ * fitness kernel is the batched sign-pattern table kernel of
+ * qpm_batch_eval_fitness_table (cfg->fit_kernel is ignored). With tune != 0
+ * its launch shape (genome groups per workgroup x words per wave) and the
+ * DE shape are chosen by timing candidates on the initial population (kept
+ * per problem size for the process, and appended to the file named by the
+ * QPM_TUNE_CACHE environment variable if set).
  * Errors: QPM_EINVAL (NULL arguments, parameters out of range),
  * QPM_ERANGE (more than 65535 fitness segments or 1024-gene chunks over
  * the batch), QPM_ENOMEM, QPM_EHIP, QPM_ENOTSUP (not a gfx950 device).
