@@ -26,7 +26,12 @@ def _t(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-CASES = [(3, 120, "jitter"), (70, 5003, "uniform"), (1, 1, "uniform"), (65, 37, "jitter")]
+# (B, N, widths): one ragged segment, ragged segments and rows, one domain,
+# fewer domains than a sub-segment; rows of more than 256 segments (the
+# combine's waves then take several rounds of 64 segments each: 5 rounds at
+# N = 7 x 10^4, 19 at N = 3 x 10^5)
+CASES = [(3, 120, "jitter"), (70, 5003, "uniform"), (1, 1, "uniform"), (65, 37, "jitter"),
+         (3, 70000, "uniform"), (2, 300001, "jitter")]
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "B%d_n%d_%s" % c)
@@ -96,7 +101,7 @@ def test_relax_gradient_vs_finite_differences_full_size(q, orc, prec):
 def test_relax_saved_edges_equal_recomputed(q, prec):
     # the adjoint from the forward call's saved edges is bit-identical to
     # the adjoint that recomputes them (ragged B and N, unaligned ldt)
-    for B, n, ldt in ((5, 4099, 4099), (67, 2048, 2052), (1, 3, 3)):
+    for B, n, ldt in ((5, 4099, 4099), (67, 2048, 2052), (1, 3, 3), (2, 300001, 300003)):
         D = q.precompute_phases(inputs.jittered_boundaries(n, 2.0, 0.3, seed=n), DK1, DK2)
         th = _t(np.pad(inputs.relax_theta(B, n, seed=B), ((0, 0), (0, ldt - n))))
         f1, S1, E = q.relax_forward(D, th, prec, keep_edges=True)
