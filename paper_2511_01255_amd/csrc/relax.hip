@@ -140,8 +140,10 @@ __device__ __forceinline__ void load_chunk_regs(float4 (&v)[4], const float *__r
 
 // The chunk's loaded values into the wave's LDS tile, row-major with a
 // padded stride (kRelaxST floats: the column reads of lane = row are free
-// of bank conflicts); ends with a workgroup barrier. Lane l then reads its
-// row's values at tile[l kRelaxST + e].
+// of bank conflicts). Lane l then reads its row's values at
+// tile[l kRelaxST + e]; only the wave that staged a tile reads it, so no
+// workgroup barrier is needed (a wave's LDS accesses complete in order) and
+// the waves of a workgroup run their chunks independently.
 constexpr int kRelaxST = kRelaxChunk + 1;
 __device__ __forceinline__ void stage_chunk(const float4 (&v)[4], float *tile, int lane)
 {
@@ -154,7 +156,8 @@ __device__ __forceinline__ void stage_chunk(const float4 (&v)[4], float *tile, i
         t[2] = v[step].z;
         t[3] = v[step].w;
     }
-    __syncthreads();
+    // (the wave reads only its own tile: its LDS accesses complete in order)
+    __builtin_amdgcn_wave_barrier();
 }
 
 // domains per step of the walks
@@ -162,8 +165,9 @@ constexpr int kRelaxStep = 4;
 
 // The coefficients of the workgroup's segment [seg 256, seg 256 + 256) into
 // LDS: co[3 j] = (a.re, a.im), co[3 j + 1] = (b.re, b.im), co[3 j + 2] = c of
-// domain seg 256 + j (0 past n); read back as broadcasts (every lane the
-// same address). Ends with a workgroup barrier.
+// domain seg 256 + j (0 past n), thread j staging domain j, so wave w
+// stages exactly the coefficients of its own sub-segment; read back as
+// broadcasts (every lane the same address).
 __device__ __forceinline__ void stage_coef(double2 *co, const double4 *__restrict__ ph64,
                                            const double2 *__restrict__ c64, int64_t seg, int64_t n)
 {
@@ -178,7 +182,8 @@ __device__ __forceinline__ void stage_coef(double2 *co, const double4 *__restric
     co[3 * j] = make_double2(v.x, v.y);
     co[3 * j + 1] = make_double2(v.z, v.w);
     co[3 * j + 2] = c;
-    __syncthreads();
+    // (each wave stages and reads only its own sub-segment's coefficients)
+    __builtin_amdgcn_wave_barrier();
 }
 
 // Segment partials: part[(row * nseg + seg) * 8 + c], c = A.re, A.im,
@@ -244,9 +249,8 @@ __global__ __launch_bounds__(256) void relax_fwd_kernel(const float *__restrict_
                 gi = fma(d2, cc.y, gi);
             }
         }
-        __syncthreads();  // the tile is refilled by the next chunk
+        __builtin_amdgcn_wave_barrier();  // the tile is refilled by the next chunk
     }
-    // (the last barrier also ends every wave's reads of co: fold reuses it)
     if (sub != nullptr && row < B) {
         double *o = sub + ss * 4 * lds + row;
         o[0] = ar;
@@ -255,7 +259,8 @@ __global__ __launch_bounds__(256) void relax_fwd_kernel(const float *__restrict_
         o[3 * lds] = bi;
     }
     // the 4 sub-segments of each row in order: waves 1-3 through LDS into
-    // wave 0
+    // wave 0 (fold reuses co: every wave must be done with it)
+    __syncthreads();
     if (wave > 0) {
         const double v[8] = {ar, ai, br, bi, qr, qi, gr, gi};
 #pragma unroll
@@ -535,8 +540,8 @@ __global__ __launch_bounds__(256) void relax_bwd_kernel(const float *__restrict_
                 pi = fma(d, c.y, pi);
             }
         }
-        __syncthreads();
-        // the chunk's gradients, coalesced
+        __builtin_amdgcn_wave_barrier();
+        // the chunk's gradients, coalesced (rows of this wave's tile)
 #pragma unroll
         for (int step = 0; step < 4; ++step) {
             const int rt = step * 16 + (lane >> 2), col = (lane & 3) * 4;
@@ -553,7 +558,7 @@ __global__ __launch_bounds__(256) void relax_bwd_kernel(const float *__restrict_
                 }
             }
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
