@@ -7,12 +7,14 @@
 //   P_{k-1} = sum_{m<k} d_m a_m,  R_{k+1} = sum_{n>k} d_n b_n,
 //   df/dtheta_k = 2 Re(conj(S) dS/dd_k) (1 - d_k^2).
 //
-// Mapping: a wave owns a tile of 64 consecutive rows x one sub-segment of 64
+// Mapping: a wave owns a tile of 64 consecutive rows x one sub-segment of 32
 // consecutive domains, lane = row; the 4 waves of a workgroup take the 4
-// consecutive sub-segments of one 256-domain segment. The rows' theta of a
-// 16-domain chunk is loaded coalesced (four lanes per row, 16 bytes each),
+// consecutive sub-segments of one 128-domain segment (short sub-segments:
+// about 6 waves per SIMD at 256 rows x 5 x 10^4 domains). The rows' theta of
+// a 16-domain chunk is loaded coalesced (four lanes per row, 16 bytes each),
 // transposed through LDS, and each lane walks its row's domains in order;
-// the coefficients of a domain are the same for every lane (scalar loads).
+// the coefficients of a domain are the same for every lane (LDS
+// broadcasts).
 // A lane's sub-segment reduces to (A, B, Q, Dg) = (sum d a, sum d b,
 // sum_n d_n b_n (A before n), sum c d^2) with no exchange between lanes; the
 // workgroup folds its 4 sub-segments per row in order through LDS, the
@@ -34,7 +36,7 @@ struct RelaxPlan {
     int64_t groups;  // row groups of 64
 };
 
-constexpr int kRelaxSub = 64;                 // domains per wave tile
+constexpr int kRelaxSub = 32;                 // domains per wave tile
 constexpr int kRelaxSeg = 4 * kRelaxSub;      // domains per workgroup (4 waves)
 constexpr int kRelaxChunk = 16;               // domains per transposed chunk
 
@@ -163,25 +165,29 @@ __device__ __forceinline__ void stage_chunk(const float4 (&v)[4], float *tile, i
 // domains per step of the walks
 constexpr int kRelaxStep = 4;
 
-// The coefficients of the workgroup's segment [seg 256, seg 256 + 256) into
-// LDS: co[3 j] = (a.re, a.im), co[3 j + 1] = (b.re, b.im), co[3 j + 2] = c of
-// domain seg 256 + j (0 past n), thread j staging domain j, so wave w
-// stages exactly the coefficients of its own sub-segment; read back as
-// broadcasts (every lane the same address).
+// The coefficients of the workgroup's segment [seg S, seg S + S) (S =
+// kRelaxSeg) into LDS: co[3 j] = (a.re, a.im), co[3 j + 1] = (b.re, b.im),
+// co[3 j + 2] = c of domain seg S + j (0 past n), staged by lane j % Sub of
+// wave j / Sub (Sub = kRelaxSub), so every wave stages exactly the
+// coefficients of its own sub-segment; read back as broadcasts (every lane
+// the same address).
 __device__ __forceinline__ void stage_coef(double2 *co, const double4 *__restrict__ ph64,
                                            const double2 *__restrict__ c64, int64_t seg, int64_t n)
 {
-    const int j = threadIdx.x;  // 256 threads, one domain each
-    const int64_t k = seg * kRelaxSeg + j;
-    double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
-    double2 c = make_double2(0.0, 0.0);
-    if (k < n) {
-        v = ph64[k];
-        c = c64[k];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l < kRelaxSub) {
+        const int j = w * kRelaxSub + l;  // lane l of wave w: domain l of the wave's sub-segment
+        const int64_t k = seg * kRelaxSeg + j;
+        double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
+        double2 c = make_double2(0.0, 0.0);
+        if (k < n) {
+            v = ph64[k];
+            c = c64[k];
+        }
+        co[3 * j] = make_double2(v.x, v.y);
+        co[3 * j + 1] = make_double2(v.z, v.w);
+        co[3 * j + 2] = c;
     }
-    co[3 * j] = make_double2(v.x, v.y);
-    co[3 * j + 1] = make_double2(v.z, v.w);
-    co[3 * j + 2] = c;
     // (each wave stages and reads only its own sub-segment's coefficients)
     __builtin_amdgcn_wave_barrier();
 }
@@ -193,16 +199,19 @@ __device__ __forceinline__ void stage_coef(double2 *co, const double4 *__restric
 // B.re, B.im. Workgroup item (seg, rg) = item / groups, % groups; wave w
 // walks sub-segment 4 seg + w of the rows rg 64 + lane.
 template <typename T, bool VEC>
-__global__ __launch_bounds__(256) void relax_fwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1))) void
+relax_fwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
                                                         int64_t n, const double4 *__restrict__ ph64,
                                                         const double2 *__restrict__ c64, int64_t groups, int nseg,
                                                         int64_t per_xcd, double *__restrict__ part,
                                                         double *__restrict__ sub, int64_t lds)
 {
     __shared__ float tiles[4][64 * kRelaxST];
-    // the segment's coefficients, then (after the walk) the fold of the waves
+    // the segment's coefficients
     __shared__ double2 co[3 * kRelaxSeg];
-    double(*fold)[8][64] = reinterpret_cast<double(*)[8][64]>(co);
+    // after the walk, the fold of the waves (in the tiles)
+    double(*fold)[8][64] = reinterpret_cast<double(*)[8][64]>(&tiles[0][0]);
+    static_assert(sizeof(tiles) >= 3 * 8 * 64 * sizeof(double), "the fold reuses the tiles");
     // the wave index as a wave-uniform value: the segment and domain indices
     // below stay scalar, so the coefficients are scalar loads
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -213,18 +222,17 @@ __global__ __launch_bounds__(256) void relax_fwd_kernel(const float *__restrict_
     const int64_t row = rg * 64 + lane;
     double ar = 0, ai = 0, br = 0, bi = 0, qr = 0, qi = 0, gr = 0, gi = 0;
     constexpr int NCH = kRelaxSub / kRelaxChunk;
-    // the next chunk's loads are in flight while a chunk is worked on
-    float4 cur[4], nxt[4];
-    load_chunk_regs<VEC>(cur, theta, ldt, B, n, rg, ss * kRelaxSub, lane);
+    // a chunk is staged, then the next chunk's loads go out into the same
+    // registers while the chunk is walked
+    float4 buf[4];
+    load_chunk_regs<VEC>(buf, theta, ldt, B, n, rg, ss * kRelaxSub, lane);
     stage_coef(co, ph64, c64, seg, n);
 #pragma unroll 1
     for (int ch = 0; ch < NCH; ++ch) {
         const int64_t kc = ss * kRelaxSub + ch * kRelaxChunk;
-        if (ch + 1 < NCH) load_chunk_regs<VEC>(nxt, theta, ldt, B, n, rg, kc + kRelaxChunk, lane);
         float *tl = tiles[wave];
-        stage_chunk(cur, tl, lane);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) cur[m] = nxt[m];
+        stage_chunk(buf, tl, lane);
+        if (ch + 1 < NCH) load_chunk_regs<VEC>(buf, theta, ldt, B, n, rg, kc + kRelaxChunk, lane);
 #pragma unroll 1
         for (int e0 = 0; e0 < kRelaxChunk; e0 += kRelaxStep) {
 #pragma unroll
@@ -259,7 +267,7 @@ __global__ __launch_bounds__(256) void relax_fwd_kernel(const float *__restrict_
         o[3 * lds] = bi;
     }
     // the 4 sub-segments of each row in order: waves 1-3 through LDS into
-    // wave 0 (fold reuses co: every wave must be done with it)
+    // wave 0 (fold reuses the tiles: every wave must be done with its own)
     __syncthreads();
     if (wave > 0) {
         const double v[8] = {ar, ai, br, bi, qr, qi, gr, gi};
@@ -343,31 +351,35 @@ __device__ __forceinline__ double row_scan(double v)
 
 // rounds of 64 segments whose loads are issued together
 constexpr int kCombineBatch = 4;
+// waves per row of the combine, each taking a contiguous share of the rounds
+constexpr int kCombineWaves = 8;
 
-// Per row (a workgroup of four waves): S = (combined Q) + sum Dg and
+// Per row (a workgroup of kCombineWaves waves): S = (combined Q) + sum Dg and
 // f = |S|^2; with `edges`, also the prefix A before every segment and the
 // sum of B from the segment on: edges[(row * nseg + seg) * 4 + c],
 // c = Apre.re, Apre.im, Bfrom.re, Bfrom.im.
 // The row's segments go in rounds of 64, lane l taking segment 64 t + l (a
 // row's partials are contiguous, so a round's loads are coalesced), and
-// wave w takes a contiguous quarter of the rounds (the loads of up to four
+// wave w takes a contiguous share of the rounds (the loads of up to four
 // rounds in flight together). A round folds in order: within each 16-lane
 // row by a DPP tree, then the four row heads; the waves' folds combine in
 // order through LDS. For the edges each wave rereads its A and B and scans
 // them (DPP within rows, then the rows' totals) from the A and B of the
 // waves before it: A before the segment, and B from it on as the row's B
 // less the B before the segment.
-__global__ __launch_bounds__(256) void relax_combine_kernel(const double *__restrict__ part, int nseg, int64_t B,
-                                                            double *__restrict__ S, float *__restrict__ f,
-                                                            double *__restrict__ edges)
+__global__ __launch_bounds__(64 * kCombineWaves) void relax_combine_kernel(const double *__restrict__ part,
+                                                                          int nseg, int64_t B,
+                                                                          double *__restrict__ S,
+                                                                          float *__restrict__ f,
+                                                                          double *__restrict__ edges)
 {
-    __shared__ double folds[4][8];
+    __shared__ double folds[kCombineWaves][8];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t row = blockIdx.x;
     if (row >= B) return;  // the whole workgroup (the grid is B workgroups)
     const double *pr = part + row * nseg * 8;
     const int rounds = (nseg + 63) / 64;
-    const int t_beg = wave * rounds / 4, t_end = (wave + 1) * rounds / 4;
+    const int t_beg = wave * rounds / kCombineWaves, t_end = (wave + 1) * rounds / kCombineWaves;
     RTri mine{0, 0, 0, 0, 0, 0, 0, 0};
     for (int t0 = t_beg; t0 < t_end; t0 += kCombineBatch) {
         RTri u[kCombineBatch];  // every round of the batch in flight at once
@@ -397,7 +409,7 @@ __global__ __launch_bounds__(256) void relax_combine_kernel(const double *__rest
     RTri tot{0, 0, 0, 0, 0, 0, 0, 0};
     double carry[4] = {0, 0, 0, 0};  // A.re, A.im, B.re, B.im before the wave's next round
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < kCombineWaves; ++w) {
         const RTri tw{folds[w][0], folds[w][1], folds[w][2], folds[w][3],
                       folds[w][4], folds[w][5], folds[w][6], folds[w][7]};
         if (w < wave) {
@@ -504,17 +516,16 @@ __global__ __launch_bounds__(256) void relax_bwd_kernel(const float *__restrict_
     }
     float *tl = tiles[wave];
     constexpr int NCH = kRelaxSub / kRelaxChunk;
-    // the next chunk's loads are in flight while a chunk is worked on
-    float4 cur[4], nxt[4];
-    load_chunk_regs<VEC>(cur, theta, ldt, B, n, rg, ss * kRelaxSub, lane);
+    // a chunk is staged, then the next chunk's loads go out into the same
+    // registers while the chunk is walked
+    float4 buf[4];
+    load_chunk_regs<VEC>(buf, theta, ldt, B, n, rg, ss * kRelaxSub, lane);
     stage_coef(co, ph64, c64, seg, n);
 #pragma unroll 1
     for (int ch = 0; ch < NCH; ++ch) {
         const int64_t kc = ss * kRelaxSub + ch * kRelaxChunk;
-        if (ch + 1 < NCH) load_chunk_regs<VEC>(nxt, theta, ldt, B, n, rg, kc + kRelaxChunk, lane);
-        stage_chunk(cur, tl, lane);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) cur[m] = nxt[m];
+        stage_chunk(buf, tl, lane);
+        if (ch + 1 < NCH) load_chunk_regs<VEC>(buf, theta, ldt, B, n, rg, kc + kRelaxChunk, lane);
 #pragma unroll 1
         for (int e0 = 0; e0 < kRelaxChunk; e0 += kRelaxStep) {
 #pragma unroll
@@ -707,7 +718,7 @@ static qpm_status check_relax(qpm_design d, qpm_prec p, const float *theta, int6
 static qpm_status launch_combine(const double *part, int nseg, int64_t B, double *S, float *f, double *edges,
                                  hipStream_t s)
 {
-    relax_combine_kernel<<<static_cast<unsigned>(B), 256, 0, s>>>(part, nseg, B, S, f, edges);
+    relax_combine_kernel<<<static_cast<unsigned>(B), 64 * kCombineWaves, 0, s>>>(part, nseg, B, S, f, edges);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }
