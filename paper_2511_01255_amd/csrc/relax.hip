@@ -198,13 +198,15 @@ __device__ __forceinline__ void stage_coef(double2 *co, const double4 *__restric
 // sub-segment's A and B: sub[(ss * 4 + c) * lds + row], c = A.re, A.im,
 // B.re, B.im. Workgroup item (seg, rg) = item / groups, % groups; wave w
 // walks sub-segment 4 seg + w of the rows rg 64 + lane.
+// (FP32: at most about 80 VGPRs, so the 6 waves per SIMD the grid gives at
+// 256 rows x 5 x 10^4 domains fit; the FP64 tanh needs more registers)
 template <typename T, bool VEC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1))) void
 relax_fwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
-                                                        int64_t n, const double4 *__restrict__ ph64,
-                                                        const double2 *__restrict__ c64, int64_t groups, int nseg,
-                                                        int64_t per_xcd, double *__restrict__ part,
-                                                        double *__restrict__ sub, int64_t lds)
+                 int64_t n, const double4 *__restrict__ ph64,
+                 const double2 *__restrict__ c64, int64_t groups, int nseg,
+                 int64_t per_xcd, double *__restrict__ part,
+                 double *__restrict__ sub, int64_t lds)
 {
     __shared__ float tiles[4][64 * kRelaxST];
     // the segment's coefficients
@@ -477,15 +479,18 @@ __global__ __launch_bounds__(64 * kCombineWaves) void relax_combine_kernel(const
 //   grad_k = grad_f 2 Re(conj(S) (b_k P_{k-1} + a_k R_{k+1} + 2 c_k d_k)) (1 - d_k^2);
 // each chunk's gradients go back through the wave's LDS tile and are stored
 // coalesced (four lanes per row, 16 bytes each).
+// (no register cap: held to 6 waves per SIMD, the FP32 adjoint spills and
+// measured slower than at its natural 82 VGPRs)
 template <typename T, bool VEC>
-__global__ __launch_bounds__(256) void relax_bwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
-                                                        int64_t n, const double4 *__restrict__ ph64,
-                                                        const double2 *__restrict__ c64, int64_t groups, int nseg,
-                                                        int64_t per_xcd, const double *__restrict__ edges,
-                                                        const double *__restrict__ sub, int64_t lde,
-                                                        const double *__restrict__ S,
-                                                        const float *__restrict__ grad_f,
-                                                        float *__restrict__ grad_theta, int64_t ldg)
+__global__ __launch_bounds__(256) void
+relax_bwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
+                 int64_t n, const double4 *__restrict__ ph64,
+                 const double2 *__restrict__ c64, int64_t groups, int nseg,
+                 int64_t per_xcd, const double *__restrict__ edges,
+                 const double *__restrict__ sub, int64_t lde,
+                 const double *__restrict__ S,
+                 const float *__restrict__ grad_f,
+                 float *__restrict__ grad_theta, int64_t ldg)
 {
     __shared__ float tiles[4][64 * kRelaxST];
     __shared__ double2 co[3 * kRelaxSeg];
