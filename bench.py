@@ -646,6 +646,31 @@ def main():
             "random_max_rel_floor1pct_median_worst_instance": max(per_r)}
         log("[bench] batched errors: periodic worst %.3g" % max(per_p))
 
+    def _oracle_timings(orc):
+        # the oracle on the other run workloads, on all host threads, over a
+        # few generations (each time includes the initial evaluation, so the
+        # per-generation rates are slight underestimates): the full HWSDA
+        # workload (N = 10^4, NP = 1024) for 20 generations and the 64
+        # batched designs (NP = 256 each) for 2 generations, with the whole
+        # runs (5000 and 500 generations) extrapolated from them
+        res = {}
+        O3 = orc.Design(z, inputs.DK1, inputs.DK2)
+        t0 = time.perf_counter()
+        O3.hwsda_run(1024, 20, F, CR, 0)
+        t3 = time.perf_counter() - t0
+        res["hwsda_np1024_n10000"] = {"generations": 20, "seconds": t3, "generations_per_s": 20 / t3,
+                                      "run_5000_generations_seconds_extrapolated": 5000 * t3 / 20}
+        specs = inputs.batched_designs(64, seed=1)
+        t0 = time.perf_counter()
+        for k, (zb, k1, k2) in enumerate(specs):
+            orc.Design(zb, k1, k2).hwsda_run(256, 2, F, CR, 0, inst=k)
+        t4 = time.perf_counter() - t0
+        res["batched_64_designs_np256"] = {"generations": 2, "seconds": t4, "generations_per_s": 2 / t4,
+                                           "run_500_generations_seconds_extrapolated": 500 * t4 / 2}
+        res["threads"] = orc.num_threads()
+        out.setdefault("oracle_timings", {}).update(res)
+        log("[bench] oracle timings: %s" % res)
+
     def _relax_errors(orc):
         # the relaxation workload (batch 256, N = 5 x 10^4 x 2 um, theta ~
         # N(0, 1)): f of 8 rows against the oracle; the gradient on 64
@@ -662,14 +687,18 @@ def main():
         cols = rng.integers(0, nn, 64)
         h = 1e-6
         fd = np.empty(64)
+        t0 = time.perf_counter()
         for k, (b, c) in enumerate(zip(rows, cols)):
             tp = theta[b].astype(np.float64)
             tm = tp.copy()
             tp[c] += h
             tm[c] -= h
             fd[k] = np.diff(Or.relax(np.stack([tm, tp]), grad=False)[1])[0] / (2 * h)
+        t_fd = time.perf_counter() - t0
         ur = np.unique(rows)
+        t0 = time.perf_counter()
         _, _, go = Or.relax(theta[ur].astype(np.float64))
+        t_an = time.perf_counter() - t0
         scale = float(np.max(np.abs(go)))
         an = np.array([go[np.searchsorted(ur, b), c] for b, c in zip(rows, cols)])
         fo8 = Or.relax(theta[:8].astype(np.float64), grad=False)[1]
@@ -683,6 +712,10 @@ def main():
                          "grad_normwise_vs_central_differences": float(np.max(np.abs(got - fd)) / scale)}
         res["oracle_analytic_vs_central_differences"] = float(np.max(np.abs(an - fd)) / scale)
         out.setdefault("errors_vs_oracle", {})["relaxation_256x50000"] = res
+        out.setdefault("oracle_timings", {})["relaxation_256x50000"] = {
+            "fd_set_seconds": t_fd, "fd_evaluations": 128,
+            "analytic_forward_adjoint_rows": int(len(ur)), "analytic_seconds": t_an,
+            "analytic_domain_evals_per_s": len(ur) * nn / t_an, "threads": orc.num_threads()}
         log("[bench] relaxation errors: %s" % res)
 
     def _cpu_leg():
@@ -708,6 +741,7 @@ def main():
         out["fitness_error_vs_oracle"] = errs
         log("[bench] fitness error vs oracle: %s" % errs)
         if not args.no_extras:
+            guarded("oracle timings", lambda: _oracle_timings(orc))
             guarded("lockstep errors", lambda: _lockstep_errors(orc))
             guarded("batched errors", lambda: _batched_errors(orc))
             guarded("relaxation errors", lambda: _relax_errors(orc))
