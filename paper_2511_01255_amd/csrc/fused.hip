@@ -17,8 +17,11 @@
 // genome one 16-lane DPP row whose lanes walk consecutive 4-domain blocks
 // and fold their triples in order with row shifts; the leaders come from
 // each individual's rank, counted by its 16 lanes. The DE draws of the next
-// generation depend on its number only, so they are drawn during the
-// previous selection step by threads that take no part in it.
+// generation depend on its number only, so they are drawn during the last
+// evaluation of a generation by the highest threads (idle in the evaluation
+// when np <= 32). Each genome's selection is taken by the first lane of its
+// evaluation row right after the fold, so an evaluation and its selection
+// need one barrier.
 #include <algorithm>
 
 #include "common.hpp"
@@ -55,7 +58,7 @@ struct FusedArgs {
 // LDS layout (bytes), shared by the kernel and the launcher
 struct FusedLayout {
     int64_t D4, Q, Qpad;    // gene stride, quads, quads padded to whole words
-    size_t buf, fs, fn, fl, bw, dr, sl, tab, total;
+    size_t buf, fs, fl, bw, dr, sl, tab, total;
 };
 
 __host__ __device__ inline FusedLayout fused_layout(int64_t np, int64_t D, int W, bool tab_lds)
@@ -68,8 +71,6 @@ __host__ __device__ inline FusedLayout fused_layout(int64_t np, int64_t D, int W
     L.buf = o;
     o += 2 * static_cast<size_t>(np) * L.D4 * sizeof(float);
     L.fs = o;
-    o += static_cast<size_t>(np) * sizeof(double);
-    L.fn = o;
     o += static_cast<size_t>(np) * sizeof(double);
     L.dr = o;
     o += static_cast<size_t>(np) * sizeof(int4);
@@ -117,12 +118,22 @@ __device__ __forceinline__ double row_down(double v, int off)
     return __hiloint2double(rh, rl);
 }
 
+// How the evaluated genomes replace the current ones (paper Sec. 3.2 steps 4
+// and 5): SEL_GREEDY keeps a genome whose fitness is strictly higher;
+// SEL_GREEDY_OMEGA does so for every genome but the three leaders; SEL_MOVE
+// (the grey-wolf optimiser alone) moves every genome but the leaders.
+enum { SEL_GREEDY = 0, SEL_GREEDY_OMEGA = 1, SEL_MOVE = 2 };
+
+// The fitness of every genome of the bit words, then its selection, by the
+// genome's first lane once its triples are folded (no other thread reads
+// fs or fl meanwhile).
 template <bool TAB_LDS>
 __device__ __forceinline__ void fused_fitness(const FusedArgs &a, const FusedLayout &L, unsigned char *lds,
-                                              const double2 *__restrict__ tabs)
+                                              const double2 *__restrict__ tabs, int sel, int4 lead)
 {
     const uint32_t *bw = reinterpret_cast<const uint32_t *>(lds + L.bw);
-    double *fn = reinterpret_cast<double *>(lds + L.fn);
+    double *fs = reinterpret_cast<double *>(lds + L.fs);
+    uint32_t *fl = reinterpret_cast<uint32_t *>(lds + L.fl);
     constexpr int T = kFusedLanes;
     const int tid = static_cast<int>(threadIdx.x);
     const int64_t i = tid / T;
@@ -159,7 +170,13 @@ __device__ __forceinline__ void fused_fitness(const FusedArgs &a, const FusedLay
     }
     if (i < a.np && s == 0) {
         const double sr = t.qr + a.C[0], si = t.qi + a.C[1];
-        fn[i] = fma(sr, sr, si * si);
+        const double fnew = fma(sr, sr, si * si);
+        const bool leader = i == lead.x || i == lead.y || i == lead.z;
+        const bool take = sel == SEL_GREEDY ? fnew > fs[i] : (!leader && (sel == SEL_MOVE || fnew > fs[i]));
+        if (take) {
+            fs[i] = fnew;
+            fl[i] ^= 1u;
+        }
     }
 }
 
@@ -196,7 +213,6 @@ __global__ __launch_bounds__(kFusedThreads) void fused_gen_kernel(FusedArgs a)
     const FusedLayout L = fused_layout(a.np, a.D, a.W, TAB_LDS);
     float *xb = reinterpret_cast<float *>(lds + L.buf);  // [2][np][D4]
     double *fs = reinterpret_cast<double *>(lds + L.fs);
-    double *fn = reinterpret_cast<double *>(lds + L.fn);
     int4 *dr = reinterpret_cast<int4 *>(lds + L.dr);
     uint32_t *fl = reinterpret_cast<uint32_t *>(lds + L.fl);
     uint32_t *bw = reinterpret_cast<uint32_t *>(lds + L.bw);
@@ -266,15 +282,12 @@ __global__ __launch_bounds__(kFusedThreads) void fused_gen_kernel(FusedArgs a)
                 if ((tid & 7) == 7 && i < np) bw[i * a.W + (q >> 3)] = w;
             }
             __syncthreads();
-            fused_fitness<TAB_LDS>(a, L, lds, tabs);
-            __syncthreads();
-            if (tid < np && fn[tid] > fs[tid]) {
-                fs[tid] = fn[tid];
-                fl[tid] ^= 1u;
-            }
-            // DE alone: the draws of the next generation, by other threads
-            if (a.algo == QPM_ALGO_DE && tid >= 512 && tid - 512 < np)
-                dr[tid - 512] = de_draw(tid - 512, np, D, g + 1, a.inst, a.k0, a.k1);
+            // evaluation and greedy selection; DE alone: the draws of the
+            // next generation (read by its DE step only)
+            fused_fitness<TAB_LDS>(a, L, lds, tabs, SEL_GREEDY, make_int4(-1, -1, -1, -1));
+            if (a.algo == QPM_ALGO_DE && tid >= kFusedThreads - np)
+                dr[tid - (kFusedThreads - np)] =
+                    de_draw(tid - (kFusedThreads - np), np, D, g + 1, a.inst, a.k0, a.k1);
             __syncthreads();
         }
         // leaders: the three best (f descending, slot ascending)
@@ -302,17 +315,13 @@ __global__ __launch_bounds__(kFusedThreads) void fused_gen_kernel(FusedArgs a)
                 if ((tid & 7) == 7 && i < np) bw[i * a.W + (q >> 3)] = w;
             }
             __syncthreads();
-            fused_fitness<TAB_LDS>(a, L, lds, tabs);
-            __syncthreads();
-            if (tid < np && tid != L0 && tid != L1 && tid != L2 &&
-                (a.algo == QPM_ALGO_GWO || fn[tid] > fs[tid])) {
-                fs[tid] = fn[tid];
-                fl[tid] ^= 1u;
-            }
-            // the DE draws of the next generation (they depend on its number
-            // only), by threads that take no part in the selection
-            if (a.algo == QPM_ALGO_HWSDA && tid >= 512 && tid - 512 < np)
-                dr[tid - 512] = de_draw(tid - 512, np, D, g + 1, a.inst, a.k0, a.k1);
+            // evaluation and selection (leaders kept); the DE draws of the
+            // next generation (they depend on its number only)
+            fused_fitness<TAB_LDS>(a, L, lds, tabs, a.algo == QPM_ALGO_GWO ? SEL_MOVE : SEL_GREEDY_OMEGA,
+                                   make_int4(L0, L1, L2, -1));
+            if (a.algo == QPM_ALGO_HWSDA && tid >= kFusedThreads - np)
+                dr[tid - (kFusedThreads - np)] =
+                    de_draw(tid - (kFusedThreads - np), np, D, g + 1, a.inst, a.k0, a.k1);
             __syncthreads();
             // the leaders of the next generation (and those reported)
             if (a.algo == QPM_ALGO_GWO) fused_leaders(fs, np, sl);
