@@ -487,11 +487,11 @@ def main():
         # latency-bound size: one graph launch per 8 generations)
         zp = inputs.uniform_boundaries(256, 2.0)
         Dp = qpm.precompute_phases(zp, inputs.DK1, inputs.DK2)
-        # (FP64: whole generations in one workgroup with the population in
-        # LDS, and the multi-kernel graph path; FP32: the multi-kernel path)
+        # (whole generations in one workgroup with the population in LDS,
+        # and the multi-kernel graph path, in each precision)
         plain = {}
         for name, p_, fu in (("gpu_f64", qpm.PREC_F64, 0), ("gpu_f64_multikernel", qpm.PREC_F64, -1),
-                             ("gpu_f32", qpm.PREC_F32, 0)):
+                             ("gpu_f32", qpm.PREC_F32, 0), ("gpu_f32_multikernel", qpm.PREC_F32, -1)):
             # warm-up run (first launches of the path's kernels), then the
             # timed one
             Rw = qpm.Run(Dp, 32, 200, F=F, CR=CR, seed=0, prec=p_, fused=fu)

@@ -366,11 +366,15 @@ typedef struct {
     int32_t algo;        /* qpm_algo: HWSDA, or one of its two parts alone */
     int32_t fused;       /* whole generations in one workgroup with the
                             population in LDS: 0 = when the run allows it
-                            (FP64 fitness, table or automatic kernel, fixed
-                            or decaying control, gwo_variant 0 or 1, no
-                            objective, np <= 64 and the population within
-                            160 KB of LDS), 1 = required (QPM_ENOTSUP
-                            otherwise), -1 = never; same trajectory */
+                            (table or automatic kernel, fixed or decaying
+                            control, gwo_variant 0 or 1, no objective,
+                            np <= 64 and the population within 160 KB of
+                            LDS), 1 = required (QPM_ENOTSUP otherwise),
+                            -1 = never. FP64: the same trajectory as the
+                            multi-kernel path. FP32: the fitness is walked
+                            with the FP64 tables and rounded to binary32 (at
+                            least the FP32 path's accuracy), so a near tie
+                            may be decided otherwise than there */
 } qpm_run_config;
 
 /*

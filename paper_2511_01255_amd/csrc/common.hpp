@@ -313,7 +313,8 @@ struct FusedRun {
     float *x0;
     const float *x1;
     uint32_t *flags, *fbits;
-    double *f_cur;
+    void *f_cur;  // double, or float when f32
+    int f32;
     int32_t *leaders;
     uint32_t *gen;
     const float *a_tab, *F_tab;

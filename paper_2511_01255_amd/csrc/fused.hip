@@ -5,11 +5,14 @@
 // any number of generations with workgroup barriers between the steps.
 //
 // LDS holds both gene buffers (a per-row flag names the one holding the
-// current row, as in the multi-kernel path), the FP64 fitness, the trial /
-// candidate bits, the DE draws, the leaders and, when they fit, the
+// current row, as in the multi-kernel path), the fitness (as doubles), the
+// trial / candidate bits, the DE draws, the leaders and, when they fit, the
 // design's FP64 sign-pattern tables. The arithmetic of every step is the
 // multi-kernel path's (de_draw, de_quad, gwo_quad; the FP64 table walk),
-// so trials, candidates and decisions are those of the oracle.
+// so in FP64 trials, candidates and decisions are those of the oracle. An
+// FP32 run takes the same FP64 walk and rounds each fitness to binary32,
+// the precision its fitness is held and compared in (on one CU the FP64
+// walk costs what an FP32 one would).
 //
 // Thread mapping: the optimiser steps walk (individual, gene quad) pairs,
 // each individual padded to a whole number of 32-gene words, so eight
@@ -40,7 +43,8 @@ struct FusedArgs {
     const float *x1;        // run buffer 1
     uint32_t *flags;        // per-row buffer flags (cleared on exit)
     uint32_t *fbits;        // packed flags (cleared on exit), nfb words
-    double *f_cur;          // current fitness (read, written back)
+    void *f_cur;            // current fitness, double or float (read, written back)
+    int f32;                // the run's fitness is binary32
     int32_t *leaders;       // leaders of the last generation (written)
     uint32_t *gen;          // generation counter (advanced by gens)
     const float *a_tab;     // a_g
@@ -170,7 +174,9 @@ __device__ __forceinline__ void fused_fitness(const FusedArgs &a, const FusedLay
     }
     if (i < a.np && s == 0) {
         const double sr = t.qr + a.C[0], si = t.qi + a.C[1];
-        const double fnew = fma(sr, sr, si * si);
+        double fnew = fma(sr, sr, si * si);
+        // an FP32 run holds its fitness in binary32 (compared as such)
+        if (a.f32) fnew = static_cast<double>(static_cast<float>(fnew));
         const bool leader = i == lead.x || i == lead.y || i == lead.z;
         const bool take = sel == SEL_GREEDY ? fnew > fs[i] : (!leader && (sel == SEL_MOVE || fnew > fs[i]));
         if (take) {
@@ -239,7 +245,8 @@ __global__ __launch_bounds__(kFusedThreads) void fused_gen_kernel(FusedArgs a)
         *reinterpret_cast<float4 *>(row(r, 0) + 4 * q) = v;
     }
     for (int64_t r = tid; r < np; r += kFusedThreads) {
-        fs[r] = a.f_cur[r];
+        fs[r] = a.f32 ? static_cast<double>(static_cast<const float *>(a.f_cur)[r])
+                      : static_cast<const double *>(a.f_cur)[r];
         fl[r] = 0u;
     }
     if constexpr (TAB_LDS) {
@@ -342,7 +349,10 @@ __global__ __launch_bounds__(kFusedThreads) void fused_gen_kernel(FusedArgs a)
         }
     }
     for (int64_t r = tid; r < np; r += kFusedThreads) {
-        a.f_cur[r] = fs[r];
+        if (a.f32)
+            static_cast<float *>(a.f_cur)[r] = static_cast<float>(fs[r]);  // (exact: fs holds binary32 values)
+        else
+            static_cast<double *>(a.f_cur)[r] = fs[r];
         a.flags[r] = 0u;
     }
     for (int k = tid; k < a.nfb; k += kFusedThreads) a.fbits[k] = 0u;
@@ -369,6 +379,7 @@ qpm_status launch_fused_generations(const FusedRun &fr, int gens, hipStream_t s)
     a.flags = fr.flags;
     a.fbits = fr.fbits;
     a.f_cur = fr.f_cur;
+    a.f32 = fr.f32;
     a.leaders = fr.leaders;
     a.gen = fr.gen;
     a.a_tab = fr.a_tab;

@@ -488,12 +488,12 @@ static qpm_status create_run(const Design *d, const Objective *obj, const qpm_ru
     QPM_REQUIRE(c.algo == QPM_ALGO_HWSDA || c.trials != QPM_TRIALS_ACCEPTED, QPM_EINVAL,
                 "accepted-only trials are a mode of the hybrid run; DE and GWO runs store every trial");
     QPM_REQUIRE(c.fused >= -1 && c.fused <= 1, QPM_EINVAL, "fused must be -1, 0 or 1 (got %d)", (int)c.fused);
-    const bool fused_ok = obj == nullptr && c.prec == QPM_PREC_F64 &&
+    const bool fused_ok = obj == nullptr &&
                           (c.fit_kernel == QPM_FIT_AUTO || c.fit_kernel == QPM_FIT_TABLE) &&
                           c.control != QPM_CONTROL_ADAPTIVE && (c.gwo_variant == 0 || c.gwo_variant == 1) &&
                           fused_eligible(c.np, d->n);
     QPM_REQUIRE(c.fused != 1 || fused_ok, QPM_ENOTSUP,
-                "fused generations need FP64 table fitness, a fixed or decaying control, gwo_variant 0 or 1, no "
+                "fused generations need table fitness, a fixed or decaying control, gwo_variant 0 or 1, no "
                 "objective and a population that fits in LDS (np <= 64)");
     qpm_status st = check_device();
     if (st != QPM_OK) return st;
@@ -666,7 +666,7 @@ QPM_API qpm_status qpm_run_advance(qpm_run_handle r, int64_t generations)
     if (!r->timing && r->fused && generations > 0) {
         // whole generations in one workgroup, in launches of at most 1000
         const qpm_run_config &c = r->cfg;
-        FusedRun fr{r->buf[0], r->buf[1], r->flags, r->fbits, static_cast<double *>(r->f_cur), r->leaders, r->gen,
+        FusedRun fr{r->buf[0], r->buf[1], r->flags, r->fbits, r->f_cur, c.prec == QPM_PREC_F32, r->leaders, r->gen,
                     r->a_tab, r->F_tab, r->d->tab64, r->d->Cdev, c.np, r->D, r->ldx, c.CR, c.seed, c.inst,
                     c.gwo_variant, c.algo};
         for (; g < generations;) {

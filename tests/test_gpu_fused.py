@@ -88,10 +88,30 @@ def test_fused_alternates_with_multikernel_steps_and_polish(q, orc):
 
 def test_fused_required_but_not_possible(q):
     D = q.precompute_phases(inputs.uniform_boundaries(256, 2.0), DK1, DK2)
-    for kw in (dict(prec=0), dict(prec=1, control=2), dict(prec=1, gwo_variant=2), dict(prec=1, np_=65),
-               dict(prec=1, fit_kernel=1)):
+    for kw in (dict(prec=1, control=2), dict(prec=1, gwo_variant=2), dict(prec=1, np_=65),
+               dict(prec=1, fit_kernel=1), dict(prec=0, fit_kernel=1)):
         np_ = kw.pop("np_", 32)
         with pytest.raises(q.QpmError):
             q.Run(D, np_, 10, fused=1, **kw)
     with pytest.raises(q.QpmError):
         q.Run(D, 32, 10, prec=1, fused=2)
+
+
+@pytest.mark.parametrize("case", [(256, 32, 40, 3), (257, 17, 30, 5), (600, 24, 12, 7)],
+                         ids=lambda c: "n%d_np%d_g%d_s%d" % c)
+def test_fused_fp32_run_lockstep(q, orc, case):
+    # FP32 runs take the fused path too (the FP64 table walk, each fitness
+    # rounded to binary32): every row of every generation against the
+    # oracle's replay from the run's own state; a decision may go the other
+    # way only on a near tie, and such adoptions must stay rare
+    from test_gpu_parity import _lockstep_generation
+    n, npop, G, seed = case
+    F, CR = 0.5, 0.9
+    z = inputs.uniform_boundaries(n, 2.0)
+    D = q.precompute_phases(z, DK1, DK2)
+    O = orc.Design(z, DK1, DK2)
+    R = q.Run(D, npop, G, F=F, CR=CR, seed=seed, prec=0, fused=1)
+    adoptions = sum(_lockstep_generation(orc, O, R, g, G, F, CR, seed) for g in range(G))
+    print("fused FP32 lockstep: %d generations, %d adopted near-tie decisions" % (G, adoptions))
+    assert adoptions <= max(2, G * (2 * npop - 3) // 1000), adoptions
+    R.destroy()

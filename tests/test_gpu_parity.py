@@ -402,11 +402,12 @@ def test_run_accepted_trials_fp64_equals_oracle(q, orc, case):
 
 
 def test_run_graph_and_eager_agree(q):
+    # (the multi-kernel path: small populations would otherwise run fused)
     n, npop, G = 300, 20, 15
     D = q.precompute_phases(inputs.uniform_boundaries(n, 2.0), DK1, DK2)
     out = []
     for use_graph in (1, 0):
-        R = q.Run(D, npop, G, seed=4, prec=0, use_graph=use_graph)
+        R = q.Run(D, npop, G, seed=4, prec=0, use_graph=use_graph, fused=-1)
         R.advance(5)
         R.advance(G - 5)
         x, f, L, _ = R.read()
