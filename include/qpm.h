@@ -278,9 +278,10 @@ qpm_status qpm_relax_forward(qpm_design d, qpm_prec p, const float *theta, int64
                              float *f, double *S, double *edges, qpm_stream s);
 
 /* Number of doubles of the edges buffer of qpm_relax_forward for a batch of
- * B rows in precision p: per row, 4 per segment of 128 domains (the prefix A
- * before the segment and the sum of B from it on) and 4 per sub-segment of
- * 32 domains (its own sums A and B). */
+ * B rows in precision p: per row, 4 doubles per segment of 128 domains (the
+ * prefix A before the segment and the sum of B from it on) and 4 values per
+ * sub-segment of 32 domains (its own sums A and B: doubles for QPM_PREC_F64,
+ * floats, 2 doubles' worth, for QPM_PREC_F32). */
 qpm_status qpm_relax_edges_size(qpm_design d, qpm_prec p, int64_t B, int64_t *count);
 
 /*

@@ -50,11 +50,12 @@ static RelaxPlan plan_relax(int64_t n, int64_t B, bool f32)
     return p;
 }
 
-// doubles of the edges: per row, 4 per segment (A before it, B from it on)
-// and 4 per sub-segment (its own A and B)
-static int64_t relax_edges_count(const RelaxPlan &p, int64_t rows)
+// doubles of the edges: per row, 4 per segment (A before it, B from it on,
+// as doubles) and 4 values per sub-segment (its own A and B, in the
+// precision of the walk: binary32 for FP32, 2 doubles' worth)
+static int64_t relax_edges_count(const RelaxPlan &p, int64_t rows, bool f32)
 {
-    return 4 * static_cast<int64_t>(p.nseg + p.nsub) * rows;
+    return (4 * static_cast<int64_t>(p.nseg) + (f32 ? 2 : 4) * static_cast<int64_t>(p.nsub)) * rows;
 }
 
 // The work item (seg groups + rg) of a workgroup. Workgroups go to the 8
@@ -196,7 +197,9 @@ __device__ __forceinline__ void stage_coef(double2 *co, const double4 *__restric
 // B.re, B.im, Q.re, Q.im, Dg.re, Dg.im (doubles, a row's segments
 // contiguous for the per-row combine); with sub, also each
 // sub-segment's A and B: sub[(ss * 4 + c) * lds + row], c = A.re, A.im,
-// B.re, B.im. Workgroup item (seg, rg) = item / groups, % groups; wave w
+// B.re, B.im, in T (binary32 for FP32: the adjoint adds them to FP64
+// edges, so their rounding stays far below the FP32 tolerance and the
+// pass pair moves half the bytes for them). Workgroup item (seg, rg) = item / groups, % groups; wave w
 // walks sub-segment 4 seg + w of the rows rg 64 + lane.
 // (FP32: at most about 80 VGPRs, so the 6 waves per SIMD the grid gives at
 // 256 rows x 5 x 10^4 domains fit; the FP64 tanh needs more registers)
@@ -206,7 +209,7 @@ relax_fwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
                  int64_t n, const double4 *__restrict__ ph64,
                  const double2 *__restrict__ c64, int64_t groups, int nseg,
                  int64_t per_xcd, double *__restrict__ part,
-                 double *__restrict__ sub, int64_t lds)
+                 T *__restrict__ sub, int64_t lds)
 {
     __shared__ float tiles[4][64 * kRelaxST];
     // the segment's coefficients
@@ -262,11 +265,11 @@ relax_fwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
         __builtin_amdgcn_wave_barrier();  // the tile is refilled by the next chunk
     }
     if (sub != nullptr && row < B) {
-        double *o = sub + ss * 4 * lds + row;
-        o[0] = ar;
-        o[lds] = ai;
-        o[2 * lds] = br;
-        o[3 * lds] = bi;
+        T *o = sub + ss * 4 * lds + row;
+        o[0] = static_cast<T>(ar);
+        o[lds] = static_cast<T>(ai);
+        o[2 * lds] = static_cast<T>(br);
+        o[3 * lds] = static_cast<T>(bi);
     }
     // the 4 sub-segments of each row in order: waves 1-3 through LDS into
     // wave 0 (fold reuses the tiles: every wave must be done with its own)
@@ -487,7 +490,7 @@ relax_bwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
                  int64_t n, const double4 *__restrict__ ph64,
                  const double2 *__restrict__ c64, int64_t groups, int nseg,
                  int64_t per_xcd, const double *__restrict__ edges,
-                 const double *__restrict__ sub, int64_t lde,
+                 const T *__restrict__ sub, int64_t lde,
                  const double *__restrict__ S,
                  const float *__restrict__ grad_f,
                  float *__restrict__ grad_theta, int64_t ldg)
@@ -509,7 +512,7 @@ relax_bwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
         rr = e[2];
         ri = e[3];
         for (int w = 0; w < wave; ++w) {
-            const double *u = sub + (4 * seg + w) * 4 * lde + row;
+            const T *u = sub + (4 * seg + w) * 4 * lde + row;
             pr += u[0];
             pi += u[lde];
             rr -= u[2 * lde];
@@ -580,7 +583,7 @@ relax_bwd_kernel(const float *__restrict__ theta, int64_t ldt, int64_t B,
 
 template <typename T>
 static void launch_relax_fwd(const Design &d, const RelaxPlan &pl, bool vec, const float *theta, int64_t B,
-                             int64_t ldt, double *part, double *sub, int64_t lds, hipStream_t s)
+                             int64_t ldt, double *part, T *sub, int64_t lds, hipStream_t s)
 {
     const int64_t per_xcd = relax_per_xcd(pl);
     const unsigned blocks = static_cast<unsigned>(8 * per_xcd);
@@ -594,7 +597,7 @@ static void launch_relax_fwd(const Design &d, const RelaxPlan &pl, bool vec, con
 
 template <typename T>
 static void launch_relax_bwd(const Design &d, const RelaxPlan &pl, bool vec, const float *theta, int64_t B,
-                             int64_t ldt, const double *edges, const double *sub, int64_t lde, const double *S,
+                             int64_t ldt, const double *edges, const T *sub, int64_t lde, const double *S,
                              const float *grad_f, float *grad_theta, int64_t ldg, hipStream_t s)
 {
     const int64_t per_xcd = relax_per_xcd(pl);
@@ -610,13 +613,13 @@ static void launch_relax_bwd(const Design &d, const RelaxPlan &pl, bool vec, con
 // segment partials part (8 nseg B doubles) and, with sub, the
 // sub-segments' A and B (4 nsub lds doubles)
 static qpm_status relax_partials(const Design &d, qpm_prec p, const float *theta, int64_t B, int64_t ldt,
-                                 const RelaxPlan &pl, double *part, double *sub, int64_t lds, hipStream_t s)
+                                 const RelaxPlan &pl, double *part, void *sub, int64_t lds, hipStream_t s)
 {
     const bool vec = (reinterpret_cast<uintptr_t>(theta) & 15u) == 0 && ldt % 4 == 0;
     if (p == QPM_PREC_F32)
-        launch_relax_fwd<float>(d, pl, vec, theta, B, ldt, part, sub, lds, s);
+        launch_relax_fwd<float>(d, pl, vec, theta, B, ldt, part, static_cast<float *>(sub), lds, s);
     else
-        launch_relax_fwd<double>(d, pl, vec, theta, B, ldt, part, sub, lds, s);
+        launch_relax_fwd<double>(d, pl, vec, theta, B, ldt, part, static_cast<double *>(sub), lds, s);
     QPM_TRY_HIP(hipGetLastError());
     return QPM_OK;
 }
@@ -735,7 +738,7 @@ QPM_API qpm_status qpm_relax_edges_size(qpm_design d, qpm_prec p, int64_t B, int
     QPM_REQUIRE(p == QPM_PREC_F32 || p == QPM_PREC_F64, QPM_EINVAL, "unknown precision %d", (int)p);
     QPM_REQUIRE(B >= 1 && B <= (int64_t(1) << 24), QPM_EINVAL, "batch must be in [1, 2^24] (got %lld)",
                 (long long)B);
-    *count = relax_edges_count(plan_relax(d->n, B, p == QPM_PREC_F32), B);
+    *count = relax_edges_count(plan_relax(d->n, B, p == QPM_PREC_F32), B, p == QPM_PREC_F32);
     return QPM_OK;
 }
 
@@ -756,7 +759,7 @@ QPM_API qpm_status qpm_relax_forward(qpm_design d, qpm_prec p, const float *thet
     if (st != QPM_OK) return st;
     double *part = static_cast<double *>(ws);
     // edges: the segments' (A before, B from) then the sub-segments' (A, B)
-    double *sub = edges ? edges + 4 * static_cast<int64_t>(pl.nseg) * B : nullptr;
+    void *sub = edges ? edges + 4 * static_cast<int64_t>(pl.nseg) * B : nullptr;
     st = relax_partials(*d, p, theta, B, ldt, pl, part, sub, B, s);
     if (st == QPM_OK) st = launch_combine(part, pl.nseg, B, S, f, edges, s);
     const qpm_status se = lease.end();
@@ -779,7 +782,7 @@ QPM_API qpm_status qpm_relax_backward(qpm_design d, qpm_prec p, const float *the
                 "batch x segments too large for one launch");
     ScratchLease lease(d->scratch, s);
     const double *e = edges;
-    const double *sub = edges ? edges + 4 * static_cast<int64_t>(pl.nseg) * B : nullptr;
+    const void *sub = edges ? edges + 4 * static_cast<int64_t>(pl.nseg) * B : nullptr;
     const int64_t lde = B;
     if (!edges) {
         // no saved edges: recompute the segment partials and their edges
@@ -798,9 +801,11 @@ QPM_API qpm_status qpm_relax_backward(qpm_design d, qpm_prec p, const float *the
         const bool vec = (reinterpret_cast<uintptr_t>(theta) & 15u) == 0 && ldt % 4 == 0 &&
                          (reinterpret_cast<uintptr_t>(grad_theta) & 15u) == 0 && ldg % 4 == 0;
         if (p == QPM_PREC_F32)
-            launch_relax_bwd<float>(*d, pl, vec, theta, B, ldt, e, sub, lde, S, grad_f, grad_theta, ldg, s);
+            launch_relax_bwd<float>(*d, pl, vec, theta, B, ldt, e, static_cast<const float *>(sub), lde, S, grad_f,
+                                    grad_theta, ldg, s);
         else
-            launch_relax_bwd<double>(*d, pl, vec, theta, B, ldt, e, sub, lde, S, grad_f, grad_theta, ldg, s);
+            launch_relax_bwd<double>(*d, pl, vec, theta, B, ldt, e, static_cast<const double *>(sub), lde, S, grad_f,
+                                     grad_theta, ldg, s);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) {
             set_error("relax adjoint launch failed: %s", hipGetErrorString(err));
