@@ -269,8 +269,9 @@ qpm_status qpm_gwo_step(const float *x, int64_t np, int64_t D, int64_t ldx,
  * receive the per-segment prefix and suffix sums the adjoint needs, so that
  * qpm_relax_backward given them skips recomputing the forward pass.
  * prec selects how tanh is evaluated: FP32 (binary32, hardware exp2 and
- * reciprocal) or FP64; the sums are FP64 in both. Device scratch: the
- * segment partials (see Conventions, Scratch).
+ * reciprocal) or FP64; the sums are FP64 in both (for FP32 the
+ * sub-segment sums kept in edges are stored rounded to binary32). Device
+ * scratch: the segment partials (see Conventions, Scratch).
  * Errors: QPM_EINVAL (NULL design or theta, both outputs NULL, B outside
  * [1, 2^24], ldt < N, unknown precision), QPM_ERANGE, QPM_EHIP.
  */
