@@ -362,7 +362,9 @@ __global__ __launch_bounds__(256) void batch_de_kernel(BatchPop bp, const InstDe
         sjr[t] = d4.w;
     }
     __syncthreads();
-    float4 cur[4], nxt[4];
+    // two row buffers used alternately by the unrolled passes (no register
+    // copy between passes)
+    float4 buf0[4], buf1[4];
     auto load = [&](int r, float4 *v) {
         if (act[r]) {
             const float *const *rw = srow[r * IPG + local];
@@ -370,10 +372,11 @@ __global__ __launch_bounds__(256) void batch_de_kernel(BatchPop bp, const InstDe
             for (int m = 0; m < 4; ++m) v[m] = *reinterpret_cast<const float4 *>(rw[m] + j0);
         }
     };
-    load(0, cur);
+    load(0, buf0);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        if (r + 1 < R) load(r + 1, nxt);
+        float4 *cur = (r & 1) ? buf1 : buf0;
+        if (r + 1 < R) load(r + 1, (r & 1) ? buf0 : buf1);
         uint32_t nib = 0;
         if (act[r]) {
             const int64_t i = i0 + r * IPG;
@@ -384,10 +387,6 @@ __global__ __launch_bounds__(256) void batch_de_kernel(BatchPop bp, const InstDe
         }
         const uint32_t w = or8_into_last(nib << (4 * (t & 7)));
         if ((t & 7) == 7) wsh[r * IPG + local][li >> 3] = w;
-        if (r + 1 < R) {
-#pragma unroll
-            for (int m = 0; m < 4; ++m) cur[m] = nxt[m];
-        }
     }
     __syncthreads();
     if (t < IPB * WPC) {

@@ -151,7 +151,10 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
     }
     auto second = [&](int64_t r) -> bool { return pv.flags != nullptr && pv.flags[r] != 0u; };
     auto src = [&](int64_t r) -> const float * { return (second(r) ? pv.x1 : pv.x0) + r * pv.ldx; };
-    float4 cur[4], nxt[4];
+    // two row buffers used alternately by the passes (the pass loop is
+    // unrolled, so each pass names its buffers statically and the next
+    // pass's rows load without a register copy)
+    float4 buf0[4], buf1[4];
     auto load = [&](int r, float4 *v) {
         if (act[r]) {
             if constexpr (PACKED) {
@@ -167,10 +170,11 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
             }
         }
     };
-    load(0, cur);
+    load(0, buf0);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        if (r + 1 < R) load(r + 1, nxt);
+        float4 *cur = (r & 1) ? buf1 : buf0;
+        if (r + 1 < R) load(r + 1, (r & 1) ? buf0 : buf1);
         uint32_t nib = 0;
         if (act[r]) {
             const int64_t i = i0 + r * IPG;
@@ -194,10 +198,6 @@ __global__ __launch_bounds__(256) void de_kernel(PopView pv, const int4 *__restr
         // merge the nibbles of 8 neighbouring lanes (32 genes) into one word
         const uint32_t w = or8_into_last(nib << (4 * (t & 7)));
         if ((t & 7) == 7) wsh[r * IPG + local][li >> 3] = w;
-        if (r + 1 < R) {
-#pragma unroll
-            for (int m = 0; m < 4; ++m) cur[m] = nxt[m];
-        }
     }
     __syncthreads();
     // the IPB consecutive individuals of this workgroup share each bit row:
